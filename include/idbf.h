@@ -1,0 +1,204 @@
+/*
+ * idbf.h -- C ABI of the MI355X (gfx950) interpolative decomposition butterfly
+ * factorization (IDBF) of Pang, Ho and Yang, arXiv:1809.10573.
+ *
+ * The library builds K ~= U^L ... U^h S^h V^h ... V^L (Section 2.4, eq. finishIDBF)
+ * for K(x, xi) = exp(2 pi i Phi(x, xi)) sampled entry by entry (Introduction),
+ * and applies it to blocks of vectors in O(N log N) per vector.
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers documented as "device" are HIP device pointers on the current
+ *    device; "host" pointers are ordinary process memory.  The caller owns
+ *    every buffer it passes; the library never retains one past the call,
+ *    except that a handle owns the factor memory it allocates.
+ *  - Complex arrays are interleaved (re, im): complex128 = 2 doubles,
+ *    complex64 = 2 floats.  Multi-vector arrays are (rows, nrhs) row-major,
+ *    right-hand sides fastest.
+ *  - Index arrays are int32 positions into X / Omega (0-based).
+ *  - No entry point aborts or throws.  Each returns an idbf_status; on failure
+ *    idbf_last_error() returns a thread-local message describing it, and
+ *    outputs are left unspecified (a failed idbf_construct sets *out = NULL
+ *    and frees everything it allocated).
+ *  - "stream" arguments are hipStream_t values (NULL: the null stream).
+ *    idbf_construct synchronizes that stream; the other compute calls are
+ *    asynchronous on it.
+ */
+#ifndef IDBF_H
+#define IDBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum idbf_status {
+  IDBF_OK = 0,
+  IDBF_EINVAL = 1,        /* invalid argument (sizes, pointers, tolerances) */
+  IDBF_ENOMEM = 2,        /* device allocation failed or exceeded opts.mem_cap_bytes */
+  IDBF_EHIP = 3,          /* a HIP runtime call failed */
+  IDBF_ERANK = 4,         /* an ID needed a rank above the supported maximum (32) */
+  IDBF_EUNSUPPORTED = 5   /* a candidate set above 64 or a sample set above 128 */
+} idbf_status;
+
+/* Phase functions (Example 1 and the DFT kernel):
+ *   IDBF_PHASE_DFT: Phi(x, xi) = -x * xi
+ *   IDBF_PHASE_FIO: Phi(x, xi) = x * xi + c(x) |xi|,
+ *                   c(x) = (c0 + a * sin(2 pi freq x)) / cdiv              */
+enum { IDBF_PHASE_DFT = 0, IDBF_PHASE_FIO = 1 };
+
+/* Apply precisions: complex128 arithmetic on FP64 factors, or complex64
+ * arithmetic on FP32 copies of the same FP64-constructed factors. */
+enum { IDBF_C128 = 0, IDBF_C64 = 1 };
+
+/* The two ID families of a level: U (row IDs) and V (column IDs). */
+enum { IDBF_SIDE_U = 0, IDBF_SIDE_V = 1 };
+
+typedef struct idbf_phase {
+  int32_t kind;   /* IDBF_PHASE_DFT or IDBF_PHASE_FIO */
+  int32_t reserved;
+  double c0, a, freq, cdiv;  /* c(x) parameters; ignored for the DFT; cdiv != 0 */
+} idbf_phase;
+
+typedef struct idbf_opts {
+  int32_t kmax;        /* rank parameter k of the (eps, k)-ID (Section 2.1); 0: k = min(s, c) */
+  int32_t oversample;  /* oversampling parameter t >= 1: s = min(t |cand|, |allowed|) samples */
+  int32_t reserved0, reserved1;
+  uint64_t mem_cap_bytes; /* cap on device memory a handle may allocate; 0: none */
+  void* stream;        /* hipStream_t used by idbf_construct */
+} idbf_opts;
+
+typedef struct idbf_handle_s* idbf_handle;
+
+/* Fill *o with the defaults: kmax 0, oversample 1 (the paper's t = 1),
+ * no memory cap, null stream.  NULL-safe. */
+void idbf_opts_default(idbf_opts* o);
+
+/*
+ * idbf_construct -- build the IDBF of K(X, Omega) (Sections 2.1-2.4).
+ *   phase  host; the phase function.
+ *   X      device, N doubles, ascending: row points x_i.
+ *   Omega  device, N doubles, ascending: column points xi_j.
+ *   N      power of two >= leaf; leaf power of two in [1, 64].
+ *   tol    ID tolerance eps of eq. acc, 0 <= tol < 1.
+ *   opts   host, nullable (defaults).
+ *   out    host; receives the handle (NULL on failure).
+ * Every interpolative decomposition runs in FP64 on the GPU: Mock-Chebyshev
+ * sample selection, entry sampling, column-pivoted Householder QR stopped at
+ * the eps-rank, and the interpolation solve T = R11^{-1} R12 (eq. R2).
+ * Levels run U_1, V_1, ..., U_H, V_H with H = floor(L/2), L = log2(N/leaf);
+ * then the middle factor's blocks are sampled.  Candidate sets must stay
+ * <= 64 points and sample sets <= 128 (else IDBF_EUNSUPPORTED); ranks <= 32
+ * (else IDBF_ERANK).  Synchronizes opts->stream.  The handle owns all factor
+ * memory (FP64 factors and an FP32 copy) until idbf_destroy.
+ */
+idbf_status idbf_construct(const idbf_phase* phase, const double* X, const double* Omega,
+                           int64_t N, double tol, int32_t leaf, const idbf_opts* opts,
+                           idbf_handle* out);
+
+/*
+ * idbf_apply -- y = U^L ... U^h S^h V^h ... V^L x (eq. finishIDBF).
+ *   x      device, (N, nrhs) complex of the given dtype; read only.
+ *   y      device, (N, nrhs) complex of the given dtype; fully overwritten;
+ *          must not overlap x.
+ *   nrhs   >= 0 (0 is a no-op).
+ *   dtype  IDBF_C128 (FP64 factors and arithmetic) or IDBF_C64 (FP32).
+ * Asynchronous on stream.  Intermediate vectors live in a workspace owned by
+ * the handle, grown (hipMalloc, which synchronizes) when nrhs exceeds what
+ * was used before; calls on one handle must not overlap in time.
+ */
+idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype,
+                       void* stream);
+
+/* Free a handle and everything it owns.  NULL-safe.  Synchronizes the device. */
+idbf_status idbf_destroy(idbf_handle h);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* idbf_last_error(void);
+
+typedef struct idbf_info {
+  int64_t N;
+  int32_t leaf, L, H, oversample;
+  double tol;
+  int64_t n_ids;          /* interpolative decompositions performed */
+  int64_t nnz_T;          /* complex entries of all T blocks */
+  int64_t nnz_S;          /* complex entries of the middle factor */
+  int64_t n_skel;         /* skeleton indices stored over all levels */
+  int32_t rank_min, rank_max;
+  int32_t cand_max, samples_max;
+  int64_t device_bytes;   /* device memory held by the handle */
+  double construct_ms;    /* host wall time of idbf_construct */
+} idbf_info;
+
+/* Summary of a handle (host *info). */
+idbf_status idbf_get_info(idbf_handle h, idbf_info* info);
+
+/*
+ * Inspection of one level's IDs, for verification.  side IDBF_SIDE_U or
+ * IDBF_SIDE_V, level t in [1, H].  IDs are numbered q = partner * 2^(L-t+1)
+ * + node, where node is the tree node at depth L-t+1 whose candidates the ID
+ * compresses and partner the node at depth t of the other tree.
+ *   idbf_batch_sizes: *n_ids, *n_skel (sum of ranks), *n_T (T entries stored).
+ *   idbf_batch_export (all host arrays, sized by idbf_batch_sizes):
+ *     rank[n_ids], cand_len[n_ids], mask[n_ids] (bit l set: candidate l is a
+ *     skeleton), skel[n_skel] (global indices, ascending within each ID,
+ *     IDs consecutive), T[2 * n_T] (complex128), T_off[n_ids] (entry offset
+ *     of each ID's T).  T of an ID with rank k and r = cand_len - k redundant
+ *     candidates is k x r; V IDs store it column-major (entry j*k + i), U IDs
+ *     row-major (entry i*r + j); rows follow ascending skeletons, columns
+ *     ascending redundant candidates.
+ */
+idbf_status idbf_batch_sizes(idbf_handle h, int32_t side, int32_t level, int64_t* n_ids,
+                             int64_t* n_skel, int64_t* n_T);
+idbf_status idbf_batch_export(idbf_handle h, int32_t side, int32_t level, int32_t* rank,
+                              int32_t* cand_len, uint64_t* mask, int32_t* skel, double* T,
+                              int64_t* T_off);
+
+/*
+ * Middle factor S (Section 2.4): for rows R and columns C' at depth
+ * d = L-H+1, block b = (C'' * 2^d + R) * 2^(d-H) + j holds
+ * K(skel of U_H ID (R, C''), skel of V_H ID (C', R >> (d-H))) with
+ * C' = C'' * 2^(d-H) + j, stored column-major.  When H = 0 there is one
+ * N x N block, K itself.  Host arrays: S[2 * n_entries], S_off[n_blocks].
+ */
+idbf_status idbf_middle_sizes(idbf_handle h, int64_t* n_blocks, int64_t* n_entries);
+idbf_status idbf_middle_export(idbf_handle h, double* S, int64_t* S_off);
+
+/*
+ * idbf_sample -- entry sampler: out[i * ncols + j] = K(X[rows[i]], Omega[cols[j]])
+ * as complex128 (Introduction: each entry in O(1) operations).  The phase is
+ * formed with an error-free product and reduced modulo 1 in FP64 before the
+ * exponential.  rows, cols, out: device; X, Omega: device.
+ */
+idbf_status idbf_sample(const idbf_phase* phase, const double* X, const double* Omega,
+                        const int32_t* rows, int64_t nrows, const int32_t* cols, int64_t ncols,
+                        double* out, void* stream);
+
+/*
+ * idbf_id_batch -- n_ids independent (tol, kmax)-IDs on explicit index sets
+ * (Section 2.1, Lemma 2.1, eqs. pivotedQR2, acc, R2), the kernel every level
+ * of idbf_construct runs.  ID q compresses candidates
+ * cand_idx[cand_beg[q] .. cand_beg[q] + cand_len[q]) (ascending global
+ * indices, <= 64) against allowed points allow_idx[allow_beg[q] .. + allow_len[q])
+ * (ascending).  side IDBF_SIDE_V: candidates are columns (Omega) and the ID
+ * is a column ID of K(samples, cand); IDBF_SIDE_U: candidates are rows (X)
+ * and it is a row ID of K(cand, samples).  s = min(oversample * cand_len,
+ * allow_len) <= 128 samples are picked by the Mock-Chebyshev rule.
+ * Outputs (device): rank[q]; mask[q]; skel[q * 64 + i] ascending skeleton
+ * global indices; T[(q * 1024 + e) * 2 ..] complex128 in the layout of
+ * idbf_batch_export.  Asynchronous on stream.
+ */
+idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double* Omega,
+                          int32_t side, int64_t n_ids, const int32_t* cand_idx,
+                          const int32_t* cand_beg, const int32_t* cand_len,
+                          const int32_t* allow_idx, const int32_t* allow_beg,
+                          const int32_t* allow_len, double tol, int32_t kmax,
+                          int32_t oversample, int32_t* rank, uint64_t* mask, int32_t* skel,
+                          double* T, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IDBF_H */

@@ -1,0 +1,46 @@
+"""CPU FP64 reference ("oracle") for the interpolative decomposition butterfly
+factorization (IDBF) of Pang, Ho and Yang, arXiv:1809.10573.
+
+THIS PACKAGE IS TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py`` may import it.  The product path
+(the HIP library and its Python binding) never imports, calls or links it, and
+it shares no code with that path: the two meet only through the seeded inputs
+of ``paper_1809_10573_amd/inputs.py``, which hold none of the method's arithmetic.
+
+Everything here is plain NumPy/SciPy in float64 / complex128, slow and written
+to be checked against the paper by eye:
+
+* ``kernel``   -- entries of K(x, xi) = exp(2 pi i Phi(x, xi)) (Introduction;
+                  Example 1), the dense O(N^2) matvec, and the closed forms
+                  (DFT, constant-c FIO) that pin it.
+* ``interp``   -- the interpolative decomposition by column-pivoted Householder
+                  QR of Lemma 2.1 and the epsilon-rank / truncated interpolation
+                  solve of Section 2.1 (eqs. pivotedQR2, acc, R2); row IDs as
+                  column IDs of the transpose.
+* ``sampling`` -- Mock-Chebyshev sample selection (Section 2.1).
+* ``idbf``     -- the level-by-level construction (LRCS, MSCS, recursive MSCS
+                  of Sections 2.2-2.4) and the factor-by-factor apply
+                  (eq. finishIDBF), plus ``densify`` for small N.
+
+Readings of the paper where it is silent, ambiguous or garbled are listed in
+the module docstrings where they apply.
+
+Parity status: every function is pinned by ``tests/test_oracle_*.py`` against
+closed forms, LAPACK, SVD bounds, brute force or exactness identities, except
+the Mock-Chebyshev rule itself (``sampling.mock_chebyshev``), whose parity is
+unpinned beyond hand-worked cases and the end-to-end error it produces.
+"""
+from .kernel import (PHASE_DFT, PHASE_FIO, amplitude_shift, phase_mod1, entries,
+                     matvec_rows, dense_matvec, dft_closed_form, fio_const_closed_form,
+                     relative_error)
+from .interp import PIVOT_TIE_REL, column_id, ColumnID
+from .sampling import chebyshev_fraction, mock_chebyshev
+from .idbf import Factors, build, apply, densify, tree_sizes, factor_matrices
+
+__all__ = [
+    "PHASE_DFT", "PHASE_FIO", "amplitude_shift", "phase_mod1", "entries",
+    "matvec_rows", "dense_matvec", "dft_closed_form", "fio_const_closed_form",
+    "relative_error", "PIVOT_TIE_REL", "column_id", "ColumnID",
+    "chebyshev_fraction", "mock_chebyshev", "Factors", "build", "apply",
+    "densify", "tree_sizes", "factor_matrices",
+]

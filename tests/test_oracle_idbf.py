@@ -1,0 +1,145 @@
+"""Pins of the oracle's IDBF construction and apply (Sections 2.2-2.4)."""
+import os
+from functools import reduce
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_10573_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _K(ph, N):
+    X, O = I.uniform_grid(N)
+    return oracle.entries(ph, X, O, np.arange(N), np.arange(N))
+
+
+@pytest.mark.parametrize("N,leaf,kind", [(16, 8, "dft"), (32, 2, "fio"), (64, 4, "fio"),
+                                         (128, 4, "fio"), (128, 2, "dft"), (256, 8, "fio"),
+                                         (256, 2, "fio")])
+def test_full_sampling_reproduces_K(N, leaf, kind):
+    # With every allowed point sampled, each ID is accurate to its tolerance on its
+    # whole block; at tol = 1e-13 the assembled factorization must equal K.
+    ph = I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 2.0)
+    X, O = I.uniform_grid(N)
+    F = oracle.build(ph, X, O, leaf, 1e-13, sample_all=True)
+    K = _K(ph, N)
+    err = np.linalg.norm(oracle.densify(F) - K, 2) / np.linalg.norm(K, 2)
+    assert err < 1e-11
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-8])
+def test_approximation_tracks_tolerance(tol):
+    N, leaf = 256, 4
+    ph = I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    F = oracle.build(ph, X, O, leaf, tol, sample_all=True)
+    K = _K(ph, N)
+    err = np.linalg.norm(oracle.densify(F) - K, 2) / np.linalg.norm(K, 2)
+    assert err < 100 * tol
+    assert F.nnz() < K.size
+
+
+def test_ranks_bounded_by_block_svd():
+    # every ID sees its whole block when sample_all is set, so its rank is bounded
+    # below by the block's singular values (stopping rule bound of the cID)
+    N, leaf, tol = 256, 8, 1e-6
+    ph = I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    F = oracle.build(ph, X, O, leaf, tol, sample_all=True)
+    L, H = F.L, F.H
+    checked = 0
+    for t in range(1, H + 1):
+        for (r, p), rec in F.U[t].items():
+            if t == 1:
+                allowed = np.arange(p * N // 2, (p + 1) * N // 2)
+            else:
+                sh = L - 2 * t + 2
+                allowed = np.concatenate([F.V[t - 1][(cc, r >> sh)].skel
+                                          for cc in range(p << sh, (p + 1) << sh)])
+            B = oracle.entries(ph, X, O, rec.cand, allowed).T
+            sv = np.linalg.svd(B, compute_uv=False)
+            assert len(rec.skel) >= np.count_nonzero(sv > np.sqrt(len(rec.cand)) * tol * sv[0])
+            checked += 1
+    assert checked == sum(len(F.U[t]) for t in F.U)
+
+
+def test_dft_n1024_leaf8_matches_fft():
+    # the DFT workload at N = 1024, leaf 8, tol 1e-10 against the FFT closed form
+    N = 1024
+    X, O = I.uniform_grid(N)
+    F = oracle.build(I.dft_phase(), X, O, 8, 1e-10)
+    assert (F.L, F.H) == (7, 3)
+    g = I.gaussian_vectors(N, None, seed=1)
+    err = oracle.relative_error(oracle.apply(F, g), oracle.dft_closed_form(g))
+    assert err < 1e-8
+
+
+def test_fio_leaf16_oversampling():
+    # leaf 16 with t = 1 under-samples the leaf-level IDs of this phase; t = 2 does not
+    N = 1024
+    ph = I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    g = I.gaussian_vectors(N, None, seed=2)
+    y = oracle.dense_matvec(ph, X, O, g)
+    F2 = oracle.build(ph, X, O, 16, 1e-6, oversample=2)
+    assert oracle.relative_error(oracle.apply(F2, g), y) < 1e-5
+
+
+def test_multiple_rhs_and_factor_product():
+    N, leaf = 128, 4
+    ph = I.fio_phase(0.5, 2.0)
+    X, O = I.uniform_grid(N)
+    F = oracle.build(ph, X, O, leaf, 1e-8)
+    G = I.gaussian_vectors(N, 5, seed=4)
+    Y = oracle.apply(F, G)
+    for j in range(5):
+        assert np.allclose(Y[:, j], oracle.apply(F, G[:, j]), rtol=0, atol=1e-13)
+    P = reduce(np.matmul, oracle.factor_matrices(F))
+    assert np.max(np.abs(P - oracle.densify(F))) < 1e-12
+
+
+def _golden_patterns():
+    pats = {}
+    with open(os.path.join(GOLDEN, "tikz_factor_patterns_m16.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, x0, y0, x1, y1 = line.split()
+            x0, y0, x1, y1 = map(int, (x0, y0, x1, y1))
+            M = pats.setdefault(name, np.zeros((32, 32), dtype=bool))
+            M[32 - max(y0, y1):32 - min(y0, y1), min(x0, x1):max(x0, x1)] = True
+    return pats
+
+
+def test_factor_patterns_match_paper_figures():
+    # 16 leaves of 2 points, rank-1 IDs: Figures exlfac and exsfac.
+    # Level 1 uses the figures' own order (q = partner * 16 + node).  At level 2 the
+    # figures order IDs by (outer row half, outer column half, inner half, node)
+    # while q orders them (outer, inner, other outer, node): bits 2 and 3 swap.
+    pats = _golden_patterns()
+    N, leaf = 32, 2
+    X, O = I.uniform_grid(N)
+    F = oracle.build(I.fio_phase(1.0, 1.0), X, O, leaf, 0.0, kmax=1)
+    assert (F.L, F.H) == (4, 2)
+    U1, U2, S, V2, V1 = oracle.factor_matrices(F)
+    nz = lambda M: np.abs(M) > 0
+    assert np.array_equal(nz(U1), pats["UL"])
+    assert np.array_equal(nz(V1), pats["VL"])
+    swap = np.array([(i & ~12) | ((i & 4) << 1) | ((i & 8) >> 1) for i in range(32)])
+    SL = U2 @ S @ V2
+    assert np.array_equal(nz(SL), pats["SL"])
+    assert np.array_equal(nz(U2[:, swap]), pats["UL1"])
+    assert np.array_equal(nz(S[swap][:, swap]), pats["SL1"])
+    assert np.array_equal(nz(V2[swap]), pats["VL1"])
+
+
+def test_bad_sizes_rejected():
+    with pytest.raises(ValueError):
+        oracle.tree_sizes(96, 8)
+    with pytest.raises(ValueError):
+        oracle.tree_sizes(64, 3)
+    with pytest.raises(ValueError):
+        oracle.tree_sizes(8, 16)

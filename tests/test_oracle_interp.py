@@ -1,0 +1,99 @@
+"""Pins of the oracle's interpolative decomposition (Lemma 2.1; eqs. pivotedQR2, acc, R2)."""
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+import oracle
+
+
+def _cgauss(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("s,c", [(24, 24), (40, 17), (12, 30), (64, 52)])
+def test_pivots_and_rdiag_match_lapack_geqp3(s, c):
+    rng = np.random.default_rng(s * 100 + c)
+    B = _cgauss(rng, s, c)
+    cid = oracle.column_id(B, tol=0.0)
+    _, R, P = sl.qr(B, pivoting=True, mode="economic")
+    k = min(s, c)
+    assert cid.rank == k
+    assert np.array_equal(cid.pivots, P[:k])
+    assert np.allclose(cid.rdiag, np.abs(np.diag(R))[:k], rtol=1e-12)
+
+
+@pytest.mark.parametrize("s,c,r", [(30, 20, 7), (20, 30, 11), (64, 64, 25)])
+def test_exact_low_rank_is_recovered(s, c, r):
+    rng = np.random.default_rng(r)
+    B = _cgauss(rng, s, r) @ _cgauss(rng, r, c)
+    cid = oracle.column_id(B, tol=1e-10)
+    assert cid.rank == r
+    err = np.linalg.norm(B[:, cid.red] - B[:, cid.skel] @ cid.T) / np.linalg.norm(B)
+    assert err < 1e-12
+
+
+def test_skeleton_columns_reproduced_exactly():
+    # V = [I T] Lambda^*: the skeleton columns of A_{:,q} V are A_{:,q} itself, bit for bit
+    rng = np.random.default_rng(1)
+    B = _cgauss(rng, 20, 15) @ np.diag(np.logspace(0, -12, 15)) @ _cgauss(rng, 15, 15)
+    cid = oracle.column_id(B, tol=1e-6)
+    V = np.zeros((cid.rank, B.shape[1]), dtype=np.complex128)
+    V[:, cid.skel] = np.eye(cid.rank)
+    V[:, cid.red] = cid.T
+    approx = B[:, cid.skel] @ V
+    assert np.array_equal(approx[:, cid.skel], B[:, cid.skel])
+    assert np.all(np.diff(cid.skel) > 0) and np.all(np.diff(cid.red) > 0)
+    assert sorted(np.concatenate([cid.skel, cid.red]).tolist()) == list(range(15))
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-6, 1e-10])
+def test_stopping_rule_bounds(tol):
+    # Stopping when every residual column norm is <= tol |R_00| gives
+    #   ||B_red - B_skel T||_F = ||R_22||_F <= sqrt(c - k) tol |R_00|   and
+    #   sigma_{k+1}(B) <= ||R_22||_2, |R_00| <= sigma_1  =>  k >= #{sigma_i > sqrt(c) tol sigma_1}.
+    rng = np.random.default_rng(42)
+    for trial in range(20):
+        s, c = rng.integers(8, 60, 2)
+        decay = np.logspace(0, rng.uniform(-14, -2), min(s, c))
+        B = (_cgauss(rng, s, len(decay)) * decay) @ _cgauss(rng, len(decay), c)
+        cid = oracle.column_id(B, tol=tol)
+        k = cid.rank
+        r00 = cid.rdiag[0]
+        resid = np.linalg.norm(B[:, cid.red] - B[:, cid.skel] @ cid.T)
+        assert resid <= np.sqrt(c - k) * tol * r00 * (1 + 1e-6) + 1e-13 * r00
+        sv = np.linalg.svd(B, compute_uv=False)
+        assert k >= np.count_nonzero(sv > np.sqrt(c) * tol * sv[0])
+        assert np.all(cid.rdiag > tol * r00)
+
+
+def test_tie_rule_prefers_smallest_index():
+    # every column has the same norm: the first pivot is the first column; a
+    # column permutation moves the pivot with it only through the index order
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(_cgauss(rng, 6, 6))
+    B = Q[:, :4] * 2.0                          # equal norms, orthogonal columns
+    cid = oracle.column_id(B, tol=0.0)
+    assert list(cid.pivots) == [0, 1, 2, 3]
+    cid2 = oracle.column_id(B[:, [2, 0, 3, 1]], tol=0.0)
+    assert list(cid2.pivots) == [0, 1, 2, 3]
+
+
+def test_zero_block_and_rank_cap():
+    z = oracle.column_id(np.zeros((5, 4)), tol=1e-6)
+    assert z.rank == 1 and list(z.skel) == [0] and np.all(z.T == 0)
+    rng = np.random.default_rng(9)
+    B = _cgauss(rng, 20, 20)
+    cap = oracle.column_id(B, tol=0.0, kmax=5)
+    assert cap.rank == 5 and cap.T.shape == (5, 15)
+
+
+def test_row_id_by_transpose():
+    # rID of A (Section 2.1): A ~= Lambda [I T]^T A_{q,:}, from the cID of A^T
+    rng = np.random.default_rng(8)
+    A = _cgauss(rng, 16, 6) @ _cgauss(rng, 6, 40)
+    cid = oracle.column_id(A.T, tol=1e-12)
+    U = np.zeros((16, cid.rank), dtype=np.complex128)
+    U[cid.skel] = np.eye(cid.rank)
+    U[cid.red] = cid.T.T
+    assert cid.rank == 6
+    assert np.linalg.norm(A - U @ A[cid.skel]) / np.linalg.norm(A) < 1e-12
