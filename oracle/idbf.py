@@ -67,6 +67,7 @@ class IDRecord:
     redpos: np.ndarray    # positions of the redundant candidates within cand
     T: np.ndarray         # (k, c-k): redundant ~= skeleton interpolation
     nsamples: int
+    rdiag: np.ndarray     # |R_jj| of the pivoted QR, j < k
 
 
 @dataclass
@@ -106,7 +107,7 @@ def tree_sizes(N: int, leaf: int) -> tuple[int, int]:
 def _interp(B, tol, kmax, cand):
     cid = column_id(B, tol, kmax)
     return IDRecord(cand=cand, skel=cand[cid.skel], skelpos=cid.skel, redpos=cid.red,
-                    T=cid.T, nsamples=B.shape[0])
+                    T=cid.T, nsamples=B.shape[0], rdiag=cid.rdiag)
 
 
 def _samples(coords_of_allowed, allowed, c, oversample, sample_all):

@@ -1,0 +1,249 @@
+"""ctypes binding of libidbf.so (the C ABI declared in include/idbf.h).
+
+Argument marshalling only: every step of construction and apply runs in the
+HIP kernels of the library.  Device buffers are torch tensors on a ROCm
+device; torch is used for memory and streams, nothing else.  The library is
+loaded on first use; if it is missing or fails to load, calls raise -- there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libidbf.so")
+
+OK, EINVAL, ENOMEM, EHIP, ERANK, EUNSUPPORTED = range(6)
+PHASE_DFT, PHASE_FIO = 0, 1
+C128, C64 = 0, 1
+SIDE_U, SIDE_V = 0, 1
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ERANK", 5: "EUNSUPPORTED"}
+
+# every symbol include/idbf.h declares
+EXPORTED = [
+    "idbf_opts_default", "idbf_construct", "idbf_apply", "idbf_destroy", "idbf_last_error",
+    "idbf_get_info", "idbf_batch_sizes", "idbf_batch_export", "idbf_middle_sizes",
+    "idbf_middle_export", "idbf_sample", "idbf_id_batch",
+]
+
+
+class IdbfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Phase_t(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("c0", C.c_double),
+                ("a", C.c_double), ("freq", C.c_double), ("cdiv", C.c_double)]
+
+
+class Opts_t(C.Structure):
+    _fields_ = [("kmax", C.c_int32), ("oversample", C.c_int32), ("reserved0", C.c_int32),
+                ("reserved1", C.c_int32), ("mem_cap_bytes", C.c_uint64), ("stream", C.c_void_p)]
+
+
+class Info_t(C.Structure):
+    _fields_ = [("N", C.c_int64), ("leaf", C.c_int32), ("L", C.c_int32), ("H", C.c_int32),
+                ("oversample", C.c_int32), ("tol", C.c_double), ("n_ids", C.c_int64),
+                ("nnz_T", C.c_int64), ("nnz_S", C.c_int64), ("n_skel", C.c_int64),
+                ("rank_min", C.c_int32), ("rank_max", C.c_int32), ("cand_max", C.c_int32),
+                ("samples_max", C.c_int32), ("device_bytes", C.c_int64), ("construct_ms", C.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libidbf.so once; raises if it is absent (build it with paper_1809_10573_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"IDBF HIP library not built: {path} is missing "
+                           "(run `python -m paper_1809_10573_amd.build`)")
+    lib = C.CDLL(path)
+    P, I32, I64, D, VP = C.POINTER, C.c_int32, C.c_int64, C.c_double, C.c_void_p
+    lib.idbf_opts_default.argtypes = [P(Opts_t)]
+    lib.idbf_opts_default.restype = None
+    lib.idbf_last_error.argtypes = []
+    lib.idbf_last_error.restype = C.c_char_p
+    lib.idbf_construct.argtypes = [P(Phase_t), VP, VP, I64, D, I32, P(Opts_t), P(VP)]
+    lib.idbf_apply.argtypes = [VP, VP, VP, I64, I32, VP]
+    lib.idbf_destroy.argtypes = [VP]
+    lib.idbf_get_info.argtypes = [VP, P(Info_t)]
+    lib.idbf_batch_sizes.argtypes = [VP, I32, I32, P(I64), P(I64), P(I64)]
+    lib.idbf_batch_export.argtypes = [VP, I32, I32, VP, VP, VP, VP, VP, VP]
+    lib.idbf_middle_sizes.argtypes = [VP, P(I64), P(I64)]
+    lib.idbf_middle_export.argtypes = [VP, VP, VP]
+    lib.idbf_sample.argtypes = [P(Phase_t), VP, VP, VP, I64, VP, I64, VP, VP]
+    lib.idbf_id_batch.argtypes = [P(Phase_t), VP, VP, I32, I64, VP, VP, VP, VP, VP, VP, D, I32, I32,
+                                  VP, VP, VP, VP, VP]
+    for name in EXPORTED:
+        if name not in ("idbf_opts_default", "idbf_last_error"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int) -> None:
+    if status != OK:
+        raise IdbfError(status, load().idbf_last_error().decode())
+
+
+def _phase(phase) -> Phase_t:
+    return Phase_t(int(phase.kind), 0, float(phase.c0), float(phase.a), float(phase.freq),
+                   float(phase.cdiv))
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else 0
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _dev_f64(a, device):
+    import torch
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.float64).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=device)
+
+
+def _dev_i32(a, device):
+    import torch
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.int32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.int32), device=device)
+
+
+@dataclass
+class Batch:
+    rank: np.ndarray
+    cand_len: np.ndarray
+    mask: np.ndarray
+    skel: np.ndarray
+    T: np.ndarray
+    T_off: np.ndarray
+
+
+class Factorization:
+    """A constructed IDBF living on the GPU (owns the C handle)."""
+
+    def __init__(self, handle: int, X, Omega):
+        self._h = C.c_void_p(handle)
+        self.X, self.Omega = X, Omega
+
+    def close(self) -> None:
+        if self._h:
+            _check(load().idbf_destroy(self._h))
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = Info_t()
+        _check(load().idbf_get_info(self._h, C.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in Info_t._fields_}
+
+    def apply(self, x, y=None, dtype: int | None = None, stream=None):
+        """y = K~ x for a (N,) or (N, nrhs) complex128/complex64 device tensor."""
+        import torch
+        if dtype is None:
+            dtype = C128 if x.dtype == torch.complex128 else C64
+        want = torch.complex128 if dtype == C128 else torch.complex64
+        if x.dtype != want or not x.is_contiguous():
+            raise ValueError(f"x must be a contiguous {want} tensor")
+        nrhs = 1 if x.dim() == 1 else x.shape[1]
+        if y is None:
+            y = torch.empty_like(x)
+        _check(load().idbf_apply(self._h, _ptr(x), _ptr(y), nrhs, dtype, _stream(stream)))
+        return y
+
+    def batch(self, side: int, level: int) -> Batch:
+        lib = load()
+        n, ns, nt = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib.idbf_batch_sizes(self._h, side, level, C.byref(n), C.byref(ns), C.byref(nt)))
+        rank = np.zeros(n.value, np.int32)
+        cand = np.zeros(n.value, np.int32)
+        mask = np.zeros(n.value, np.uint64)
+        skel = np.zeros(max(ns.value, 1), np.int32)
+        T = np.zeros(max(nt.value, 1), np.complex128)
+        toff = np.zeros(n.value, np.int64)
+        _check(lib.idbf_batch_export(self._h, side, level, rank.ctypes.data, cand.ctypes.data,
+                                     mask.ctypes.data, skel.ctypes.data, T.ctypes.data,
+                                     toff.ctypes.data))
+        return Batch(rank, cand, mask, skel[:ns.value], T[:nt.value], toff)
+
+    def middle(self) -> tuple[np.ndarray, np.ndarray]:
+        lib = load()
+        nb, ne = C.c_int64(), C.c_int64()
+        _check(lib.idbf_middle_sizes(self._h, C.byref(nb), C.byref(ne)))
+        S = np.zeros(max(ne.value, 1), np.complex128)
+        off = np.zeros(nb.value, np.int64)
+        _check(lib.idbf_middle_export(self._h, S.ctypes.data, off.ctypes.data))
+        return S[:ne.value], off
+
+
+def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample: int = 1,
+              mem_cap_bytes: int = 0, device="cuda", stream=None) -> Factorization:
+    """idbf_construct on device copies of X and Omega (float64, ascending)."""
+    lib = load()
+    Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
+    if Xd.numel() != Od.numel():
+        raise ValueError("X and Omega must have the same length")
+    opts = Opts_t()
+    lib.idbf_opts_default(C.byref(opts))
+    opts.kmax, opts.oversample, opts.mem_cap_bytes = kmax, oversample, mem_cap_bytes
+    opts.stream = _stream(stream)
+    ph = _phase(phase)
+    h = C.c_void_p()
+    _check(lib.idbf_construct(C.byref(ph), _ptr(Xd), _ptr(Od), Xd.numel(), float(tol), int(leaf),
+                              C.byref(opts), C.byref(h)))
+    return Factorization(h.value, Xd, Od)
+
+
+def sample(phase, X, Omega, rows, cols, device="cuda", stream=None):
+    """K(X[rows], Omega[cols]) as a complex128 device tensor (idbf_sample)."""
+    import torch
+    Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
+    r, c = _dev_i32(rows, device), _dev_i32(cols, device)
+    out = torch.empty((r.numel(), c.numel()), dtype=torch.complex128, device=device)
+    ph = _phase(phase)
+    _check(load().idbf_sample(C.byref(ph), _ptr(Xd), _ptr(Od), _ptr(r), r.numel(), _ptr(c),
+                              c.numel(), _ptr(out), _stream(stream)))
+    return out
+
+
+def id_batch(phase, X, Omega, side: int, cand_idx, cand_beg, cand_len, allow_idx, allow_beg,
+             allow_len, tol: float, kmax: int = 0, oversample: int = 1, device="cuda", stream=None):
+    """idbf_id_batch; returns host arrays (rank, mask, skel (n, 64), T (n, 1024))."""
+    import torch
+    Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
+    ci, cb, cl = (_dev_i32(a, device) for a in (cand_idx, cand_beg, cand_len))
+    ai, abg, al = (_dev_i32(a, device) for a in (allow_idx, allow_beg, allow_len))
+    n = cb.numel()
+    rank = torch.zeros(n, dtype=torch.int32, device=device)
+    mask = torch.zeros(n, dtype=torch.int64, device=device)
+    skel = torch.full((n, 64), -1, dtype=torch.int32, device=device)
+    T = torch.zeros((n, 1024), dtype=torch.complex128, device=device)
+    ph = _phase(phase)
+    _check(load().idbf_id_batch(C.byref(ph), _ptr(Xd), _ptr(Od), side, n, _ptr(ci), _ptr(cb),
+                                _ptr(cl), _ptr(ai), _ptr(abg), _ptr(al), float(tol), int(kmax),
+                                int(oversample), _ptr(rank), _ptr(mask), _ptr(skel), _ptr(T),
+                                _stream(stream)))
+    torch.cuda.synchronize()
+    return (rank.cpu().numpy(), mask.cpu().numpy().view(np.uint64), skel.cpu().numpy(),
+            T.cpu().numpy())

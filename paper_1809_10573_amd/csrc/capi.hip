@@ -1,0 +1,774 @@
+// C ABI of the IDBF library (include/idbf.h): argument checks, the level
+// schedule of the construction, factor memory, the apply stage sequence,
+// inspection and the stand-alone sampler / ID entry points.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace idbf {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+namespace {
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+  int l = 0;
+  while ((1ll << l) < v) ++l;
+  return l;
+}
+
+// Bump allocator over large hipMalloc chunks: the construction's many
+// per-level arrays cost a handful of driver allocations.
+struct Arena {
+  struct Chunk {
+    void* base;
+    size_t size;
+  };
+  std::vector<Chunk> chunks;
+  char* cur = nullptr;
+  size_t used = 0, cap = 0, total = 0, limit = 0, chunk_min = size_t(64) << 20;
+
+  idbf_status alloc(size_t bytes, void** out) {
+    bytes = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
+    if (cur && used + bytes <= cap) {
+      *out = cur + used;
+      used += bytes;
+      return IDBF_OK;
+    }
+    size_t sz = std::max(bytes, chunk_min);
+    if (limit && total + sz > limit) sz = bytes;
+    if (limit && total + sz > limit) {
+      set_error("device memory cap of %zu bytes exceeded (%zu held, %zu requested)", limit, total, bytes);
+      return IDBF_ENOMEM;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("hipMalloc(%zu) failed: %s", sz, hipGetErrorString(e));
+      return IDBF_ENOMEM;
+    }
+    chunks.push_back({p, sz});
+    total += sz;
+    cur = static_cast<char*>(p);
+    used = bytes;
+    cap = sz;
+    *out = p;
+    return IDBF_OK;
+  }
+  template <typename T>
+  idbf_status get(size_t n, T** out) {
+    void* p = nullptr;
+    idbf_status s = alloc(n * sizeof(T), &p);
+    *out = static_cast<T*>(p);
+    return s;
+  }
+  void release() {
+    for (auto& c : chunks) (void)hipFree(c.base);
+    chunks.clear();
+    cur = nullptr;
+    used = cap = total = 0;
+  }
+};
+
+struct Batch {
+  int side = 0, t = 0;
+  int64_t n = 0;
+  int32_t *cand_beg = nullptr, *cand_len = nullptr, *allow_beg = nullptr, *allow_len = nullptr;
+  int32_t *samples = nullptr, *rank = nullptr, *skel_off = nullptr, *skel_idx = nullptr;
+  int64_t *t_bound = nullptr, *T_off = nullptr;
+  uint64_t* mask = nullptr;
+  double2* T128 = nullptr;
+  float2* T64 = nullptr;
+  const int32_t* cand_arr = nullptr;
+  const int32_t* allow_arr = nullptr;
+  int64_t n_skel = 0, n_T = 0;
+  int rank_min = 0, rank_max = 0, cand_max = 0, s_max = 0;
+};
+
+PhaseDev to_dev(const idbf_phase& p) { return PhaseDev{p.kind, p.c0, p.a, p.freq, p.cdiv}; }
+
+idbf_status check_phase(const idbf_phase* phase) {
+  if (!phase) {
+    set_error("phase is NULL");
+    return IDBF_EINVAL;
+  }
+  if (phase->kind != IDBF_PHASE_DFT && phase->kind != IDBF_PHASE_FIO) {
+    set_error("unknown phase kind %d", phase->kind);
+    return IDBF_EINVAL;
+  }
+  if (phase->kind == IDBF_PHASE_FIO &&
+      (!(phase->cdiv != 0.0) || !std::isfinite(phase->cdiv) || !std::isfinite(phase->c0) ||
+       !std::isfinite(phase->a) || !std::isfinite(phase->freq))) {
+    set_error("FIO phase parameters must be finite with cdiv != 0");
+    return IDBF_EINVAL;
+  }
+  return IDBF_OK;
+}
+
+// finite and strictly ascending; result in *bad (device int) as a count of violations
+__global__ void check_points_kernel(const double* p, int64_t n, int32_t* bad) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = p[i];
+  bool ok = __builtin_isfinite(v);
+  if (i + 1 < n) ok = ok && (p[i + 1] > v);
+  if (!ok) atomicAdd(bad, 1);
+}
+
+}  // namespace
+}  // namespace idbf
+
+using namespace idbf;
+
+struct idbf_handle_s {
+  int64_t N = 0;
+  int leaf = 0, L = 0, H = 0, kmax = 0, oversample = 1;
+  double tol = 0.0;
+  PhaseDev ph{};
+  Arena arena;
+  int32_t* iota = nullptr;
+  int32_t* scratch = nullptr;  // skeleton lists before compaction (64 per ID)
+  int64_t* stats = nullptr;    // 8 int64 read back after each scan
+  int32_t* status = nullptr;
+  std::vector<Batch> U, V;
+  int64_t nblk = 0, nnz_S = 0;
+  int32_t *s_rbeg = nullptr, *s_rlen = nullptr, *s_cbeg = nullptr, *s_clen = nullptr;
+  int64_t *s_size = nullptr, *S_off = nullptr;
+  double2* S128 = nullptr;
+  float2* S64 = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int64_t max_skel = 0;
+  double construct_ms = 0.0;
+  hipStream_t stream = nullptr;
+
+  ~idbf_handle_s() {
+    if (ws) (void)hipFree(ws);
+    arena.release();
+  }
+};
+
+namespace {
+
+idbf_status read_stats(idbf_handle_s* h, int64_t* host, int n) {
+  IDBF_HIP_CHECK(hipMemcpyAsync(host, h->stats, n * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
+  IDBF_HIP_CHECK(hipStreamSynchronize(h->stream));
+  return IDBF_OK;
+}
+
+#define TRY(x)                          \
+  do {                                  \
+    idbf_status s_ = (x);               \
+    if (s_ != IDBF_OK) return s_;       \
+  } while (0)
+#define TRYHIP(x) IDBF_HIP_CHECK(x)
+
+idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int side, int t) {
+  Batch b;
+  b.side = side;
+  b.t = t;
+  b.n = int64_t(2) << h->L;
+  const int64_t n = b.n;
+  Arena& A = h->arena;
+  TRY(A.get(n, &b.cand_beg));
+  TRY(A.get(n, &b.cand_len));
+  TRY(A.get(n, &b.allow_beg));
+  TRY(A.get(n, &b.allow_len));
+  TRY(A.get(n, &b.samples));
+  TRY(A.get(n, &b.rank));
+  TRY(A.get(n + 1, &b.skel_off));
+  TRY(A.get(n, &b.t_bound));
+  TRY(A.get(n + 1, &b.T_off));
+  TRY(A.get(n, &b.mask));
+
+  const Batch* prev = nullptr;   // same side, level t-1
+  const Batch* other = nullptr;  // allowed points' batch
+  if (t > 1) prev = (side == IDBF_SIDE_U) ? &h->U[t - 2] : &h->V[t - 2];
+  if (side == IDBF_SIDE_U) {
+    if (t > 1) other = &h->V[t - 2];
+  } else {
+    other = &h->U[t - 1];
+  }
+  b.cand_arr = prev ? prev->skel_idx : h->iota;
+  b.allow_arr = other ? other->skel_idx : h->iota;
+
+  DescArgs d{};
+  d.side = side;
+  d.t = t;
+  d.L = h->L;
+  d.leaf = h->leaf;
+  d.N = h->N;
+  d.n_ids = n;
+  d.oversample = h->oversample;
+  d.kmax = h->kmax;
+  d.prev_skel_off = prev ? prev->skel_off : nullptr;
+  d.allow_skel_off = other ? other->skel_off : nullptr;
+  d.cand_beg = b.cand_beg;
+  d.cand_len = b.cand_len;
+  d.allow_beg = b.allow_beg;
+  d.allow_len = b.allow_len;
+  d.t_bound = b.t_bound;
+  d.samples = b.samples;
+  TRYHIP(launch_desc(d, h->stream));
+  TRYHIP(launch_scan_i64(b.t_bound, n, b.T_off, b.cand_len, h->stats, h->stream));
+  TRYHIP(launch_scan_i32(b.samples, n, b.skel_off, nullptr, h->stats + 4, h->stream));
+  int64_t st[8];
+  TRY(read_stats(h, st, 8));
+  b.n_T = st[0];
+  b.cand_max = (int)st[3];
+  b.s_max = (int)st[5];
+  if (b.cand_max > kMaxCand) {
+    set_error("level %d %c: a candidate set has %d points (max %d); ranks grew past %d", t,
+              side == IDBF_SIDE_U ? 'U' : 'V', b.cand_max, kMaxCand, kMaxCand / 2);
+    return IDBF_EUNSUPPORTED;
+  }
+  if (b.s_max > kMaxSamples) {
+    set_error("level %d %c: %d samples requested (max %d); lower the oversampling", t,
+              side == IDBF_SIDE_U ? 'U' : 'V', b.s_max, kMaxSamples);
+    return IDBF_EUNSUPPORTED;
+  }
+  const int waves = std::max(1, std::min(kMaxWaves, (b.s_max + kRowsPerWave - 1) / kRowsPerWave));
+  TRY(A.get(std::max<int64_t>(b.n_T, 1), &b.T128));
+  TRY(A.get(std::max<int64_t>(b.n_T, 1), &b.T64));
+
+  IdArgs ia{};
+  ia.ph = h->ph;
+  ia.X = X;
+  ia.Om = Om;
+  ia.side = side;
+  ia.n_ids = n;
+  ia.cand_idx = b.cand_arr;
+  ia.cand_beg = b.cand_beg;
+  ia.cand_len = b.cand_len;
+  ia.allow_idx = b.allow_arr;
+  ia.allow_beg = b.allow_beg;
+  ia.allow_len = b.allow_len;
+  ia.tol = h->tol;
+  ia.kmax = h->kmax;
+  ia.oversample = h->oversample;
+  ia.rank = b.rank;
+  ia.mask = b.mask;
+  ia.skel_out = h->scratch;
+  ia.T128 = b.T128;
+  ia.T64 = b.T64;
+  ia.T_off = b.T_off;
+  ia.status = h->status;
+  TRYHIP(launch_id_batch(ia, waves, h->stream));
+  TRYHIP(launch_scan_i32(b.rank, n, b.skel_off, nullptr, h->stats, h->stream));
+  TRYHIP(hipMemcpyAsync(h->stats + 6, h->status, sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+  TRY(read_stats(h, st, 8));
+  const int32_t status = (int32_t)(st[6] & 0xffffffff);
+  if (status & kErrRank) {
+    set_error("level %d %c: an ID needs rank > %d at tol %g", t, side == IDBF_SIDE_U ? 'U' : 'V', kMaxRank,
+              h->tol);
+    return IDBF_ERANK;
+  }
+  if (status & kErrSize) {
+    set_error("level %d %c: an ID exceeded the kernel's size limits", t, side == IDBF_SIDE_U ? 'U' : 'V');
+    return IDBF_EUNSUPPORTED;
+  }
+  b.n_skel = st[0];
+  b.rank_max = (int)st[1];
+  b.rank_min = (int)st[2];
+  TRY(A.get(std::max<int64_t>(b.n_skel, 1), &b.skel_idx));
+  TRYHIP(launch_compact_skel(h->scratch, b.rank, b.skel_off, n, b.skel_idx, h->stream));
+  h->max_skel = std::max(h->max_skel, b.n_skel);
+  if (side == IDBF_SIDE_U) h->U.push_back(b); else h->V.push_back(b);
+  return IDBF_OK;
+}
+
+idbf_status build_middle(idbf_handle_s* h, const double* X, const double* Om) {
+  Arena& A = h->arena;
+  int64_t st[8];
+  const int32_t* row_idx;
+  const int32_t* col_idx;
+  if (h->H == 0) {
+    h->nblk = 1;
+    TRY(A.get(1, &h->s_rbeg));
+    TRY(A.get(1, &h->s_rlen));
+    TRY(A.get(1, &h->s_cbeg));
+    TRY(A.get(1, &h->s_clen));
+    TRY(A.get(2, &h->S_off));
+    const int32_t zero = 0, nn = (int32_t)h->N;
+    const int64_t offs[2] = {0, h->N * h->N};
+    TRYHIP(hipMemcpyAsync(h->s_rbeg, &zero, 4, hipMemcpyHostToDevice, h->stream));
+    TRYHIP(hipMemcpyAsync(h->s_cbeg, &zero, 4, hipMemcpyHostToDevice, h->stream));
+    TRYHIP(hipMemcpyAsync(h->s_rlen, &nn, 4, hipMemcpyHostToDevice, h->stream));
+    TRYHIP(hipMemcpyAsync(h->s_clen, &nn, 4, hipMemcpyHostToDevice, h->stream));
+    TRYHIP(hipMemcpyAsync(h->S_off, offs, 16, hipMemcpyHostToDevice, h->stream));
+    TRYHIP(hipStreamSynchronize(h->stream));
+    h->nnz_S = h->N * h->N;
+    row_idx = col_idx = h->iota;
+  } else {
+    const int d = h->L - h->H + 1;
+    h->nblk = int64_t(1) << (2 * d);
+    TRY(A.get(h->nblk, &h->s_rbeg));
+    TRY(A.get(h->nblk, &h->s_rlen));
+    TRY(A.get(h->nblk, &h->s_cbeg));
+    TRY(A.get(h->nblk, &h->s_clen));
+    TRY(A.get(h->nblk, &h->s_size));
+    TRY(A.get(h->nblk + 1, &h->S_off));
+    MiddleDescArgs m{};
+    m.L = h->L;
+    m.H = h->H;
+    m.n_blocks = h->nblk;
+    m.u_off = h->U[h->H - 1].skel_off;
+    m.v_off = h->V[h->H - 1].skel_off;
+    m.rbeg = h->s_rbeg;
+    m.rlen = h->s_rlen;
+    m.cbeg = h->s_cbeg;
+    m.clen = h->s_clen;
+    m.size = h->s_size;
+    TRYHIP(launch_middle_desc(m, h->stream));
+    TRYHIP(launch_scan_i64(h->s_size, h->nblk, h->S_off, nullptr, h->stats, h->stream));
+    TRY(read_stats(h, st, 4));
+    h->nnz_S = st[0];
+    row_idx = h->U[h->H - 1].skel_idx;
+    col_idx = h->V[h->H - 1].skel_idx;
+  }
+  TRY(A.get(std::max<int64_t>(h->nnz_S, 1), &h->S128));
+  TRY(A.get(std::max<int64_t>(h->nnz_S, 1), &h->S64));
+  SampleBlocksArgs sb{};
+  sb.ph = h->ph;
+  sb.X = X;
+  sb.Om = Om;
+  sb.n_blocks = h->nblk;
+  sb.row_idx = row_idx;
+  sb.col_idx = col_idx;
+  sb.rbeg = h->s_rbeg;
+  sb.rlen = h->s_rlen;
+  sb.cbeg = h->s_cbeg;
+  sb.clen = h->s_clen;
+  sb.off = h->S_off;
+  sb.out128 = h->S128;
+  sb.out64 = h->S64;
+  TRYHIP(launch_sample_blocks(sb, h->stream));
+  return IDBF_OK;
+}
+
+idbf_status check_points(idbf_handle_s* h, const double* p, const char* name) {
+  TRYHIP(hipMemsetAsync(h->status, 0, sizeof(int32_t), h->stream));
+  hipLaunchKernelGGL(check_points_kernel, dim3((unsigned)((h->N + 255) / 256)), dim3(256), 0, h->stream, p, h->N,
+                     h->status);
+  TRYHIP(hipGetLastError());
+  int32_t bad = 0;
+  TRYHIP(hipMemcpyAsync(&bad, h->status, sizeof bad, hipMemcpyDeviceToHost, h->stream));
+  TRYHIP(hipStreamSynchronize(h->stream));
+  if (bad) {
+    set_error("%s must be finite and strictly ascending (%d violations)", name, bad);
+    return IDBF_EINVAL;
+  }
+  return IDBF_OK;
+}
+
+idbf_status construct_impl(idbf_handle_s* h, const double* X, const double* Om) {
+  Arena& A = h->arena;
+  TRY(A.get(8, &h->stats));
+  TRY(A.get(1, &h->status));
+  TRY(check_points(h, X, "X"));
+  TRY(check_points(h, Om, "Omega"));
+  TRYHIP(hipMemsetAsync(h->status, 0, sizeof(int32_t), h->stream));
+  TRY(A.get(h->N, &h->iota));
+  TRYHIP(launch_iota(h->iota, h->N, h->stream));
+  if (h->H > 0) TRY(A.get((int64_t(2) << h->L) * kMaxCand, &h->scratch));
+  for (int t = 1; t <= h->H; ++t) {
+    TRY(run_batch(h, X, Om, IDBF_SIDE_U, t));
+    TRY(run_batch(h, X, Om, IDBF_SIDE_V, t));
+  }
+  TRY(build_middle(h, X, Om));
+  TRYHIP(hipStreamSynchronize(h->stream));
+  return IDBF_OK;
+}
+
+const Batch* find_batch(const idbf_handle_s* h, int side, int level) {
+  if (level < 1 || level > h->H) return nullptr;
+  if (side == IDBF_SIDE_U) return &h->U[level - 1];
+  if (side == IDBF_SIDE_V) return &h->V[level - 1];
+  return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+void idbf_opts_default(idbf_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->oversample = 1;
+}
+
+const char* idbf_last_error(void) { return g_err; }
+
+idbf_status idbf_construct(const idbf_phase* phase, const double* X, const double* Omega, int64_t N, double tol,
+                           int32_t leaf, const idbf_opts* opts, idbf_handle* out) {
+  g_err[0] = 0;
+  if (!out) {
+    set_error("out is NULL");
+    return IDBF_EINVAL;
+  }
+  *out = nullptr;
+  TRY(check_phase(phase));
+  if (!X || !Omega) {
+    set_error("X and Omega must be device pointers");
+    return IDBF_EINVAL;
+  }
+  if (!is_pow2(leaf) || leaf > kMaxCand) {
+    set_error("leaf must be a power of two in [1, %d], got %d", kMaxCand, leaf);
+    return IDBF_EINVAL;
+  }
+  if (!is_pow2(N) || N < leaf || N > (int64_t(1) << 30)) {
+    set_error("N must be a power of two in [leaf, 2^30], got %lld", (long long)N);
+    return IDBF_EINVAL;
+  }
+  if (!(tol >= 0.0 && tol < 1.0)) {
+    set_error("tol must satisfy 0 <= tol < 1, got %g", tol);
+    return IDBF_EINVAL;
+  }
+  idbf_opts o;
+  idbf_opts_default(&o);
+  if (opts) o = *opts;
+  if (o.oversample < 1 || o.kmax < 0) {
+    set_error("opts: oversample must be >= 1 and kmax >= 0");
+    return IDBF_EINVAL;
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<idbf_handle_s> h(new (std::nothrow) idbf_handle_s());
+  if (!h) {
+    set_error("host allocation failed");
+    return IDBF_ENOMEM;
+  }
+  h->N = N;
+  h->leaf = leaf;
+  h->L = ilog2(N / leaf);
+  h->H = h->L / 2;
+  h->tol = tol;
+  h->kmax = o.kmax;
+  h->oversample = o.oversample;
+  h->ph = to_dev(*phase);
+  h->arena.limit = o.mem_cap_bytes;
+  h->arena.chunk_min = std::max<size_t>(size_t(64) << 20, size_t(N) * 2048);
+  if (o.mem_cap_bytes) h->arena.chunk_min = std::min<size_t>(h->arena.chunk_min, o.mem_cap_bytes);
+  h->stream = static_cast<hipStream_t>(o.stream);
+  idbf_status s = construct_impl(h.get(), X, Omega);
+  if (s != IDBF_OK) {
+    (void)hipStreamSynchronize(h->stream);
+    return s;  // the handle's destructor frees everything
+  }
+  h->construct_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = h.release();
+  return IDBF_OK;
+}
+
+idbf_status idbf_destroy(idbf_handle h) {
+  if (!h) return IDBF_OK;
+  (void)hipDeviceSynchronize();
+  delete h;
+  return IDBF_OK;
+}
+
+idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype, void* stream) {
+  g_err[0] = 0;
+  if (!h) {
+    set_error("handle is NULL");
+    return IDBF_EINVAL;
+  }
+  if (nrhs < 0 || (dtype != IDBF_C128 && dtype != IDBF_C64)) {
+    set_error("nrhs must be >= 0 and dtype IDBF_C128 or IDBF_C64");
+    return IDBF_EINVAL;
+  }
+  if (nrhs == 0) return IDBF_OK;
+  if (!x || !y || x == y) {
+    set_error("x and y must be distinct device pointers");
+    return IDBF_EINVAL;
+  }
+  const bool fp64 = dtype == IDBF_C128;
+  const size_t elem = fp64 ? 16 : 8;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t half = size_t(h->max_skel) * size_t(nrhs) * elem;
+  if (h->H > 0 && 2 * half > h->ws_bytes) {
+    if (h->ws) {
+      IDBF_HIP_CHECK(hipStreamSynchronize(st));
+      IDBF_HIP_CHECK(hipFree(h->ws));
+      h->ws = nullptr;
+      h->ws_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&h->ws, 2 * half);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      h->ws = nullptr;
+      set_error("apply workspace of %zu bytes: %s", 2 * half, hipGetErrorString(e));
+      return IDBF_ENOMEM;
+    }
+    h->ws_bytes = 2 * half;
+  }
+  char* buf[2] = {static_cast<char*>(h->ws), static_cast<char*>(h->ws) + half};
+  int cur = 0;
+  const void* in = x;
+  for (int t = 1; t <= h->H; ++t) {
+    const Batch& b = h->V[t - 1];
+    StageArgs a{};
+    a.n = b.n;
+    a.nrhs = nrhs;
+    a.cand_beg = b.cand_beg;
+    a.cand_len = b.cand_len;
+    a.rank = b.rank;
+    a.skel_off = b.skel_off;
+    a.mask = b.mask;
+    a.T_off = b.T_off;
+    a.T = fp64 ? (const void*)b.T128 : (const void*)b.T64;
+    a.in = in;
+    a.out = buf[cur];
+    IDBF_HIP_CHECK(launch_apply_v(a, fp64, st));
+    in = buf[cur];
+    cur ^= 1;
+  }
+  {
+    StageArgs a{};
+    a.n = (h->H == 0) ? 1 : h->U[h->H - 1].n;
+    a.nrhs = nrhs;
+    a.nsub = (h->H == 0) ? 1 : (1 << (h->L - 2 * h->H + 1));
+    a.rbeg = h->s_rbeg;
+    a.rlen = h->s_rlen;
+    a.cbeg = h->s_cbeg;
+    a.clen = h->s_clen;
+    a.T_off = h->S_off;
+    a.T = fp64 ? (const void*)h->S128 : (const void*)h->S64;
+    a.in = in;
+    a.out = (h->H == 0) ? y : buf[cur];
+    IDBF_HIP_CHECK(launch_apply_s(a, fp64, st));
+    in = a.out;
+    cur ^= 1;
+  }
+  for (int t = h->H; t >= 1; --t) {
+    const Batch& b = h->U[t - 1];
+    StageArgs a{};
+    a.n = int64_t(1) << h->L;  // units: one per (node, parent partner)
+    a.nn = 1 << (h->L - t + 1);
+    a.nrhs = nrhs;
+    a.cand_beg = b.cand_beg;
+    a.cand_len = b.cand_len;
+    a.rank = b.rank;
+    a.skel_off = b.skel_off;
+    a.mask = b.mask;
+    a.T_off = b.T_off;
+    a.T = fp64 ? (const void*)b.T128 : (const void*)b.T64;
+    a.in = in;
+    a.out = (t == 1) ? y : buf[cur];
+    IDBF_HIP_CHECK(launch_apply_u(a, fp64, st));
+    in = a.out;
+    cur ^= 1;
+  }
+  return IDBF_OK;
+}
+
+idbf_status idbf_get_info(idbf_handle h, idbf_info* info) {
+  if (!h || !info) {
+    set_error("handle and info must be non-NULL");
+    return IDBF_EINVAL;
+  }
+  std::memset(info, 0, sizeof *info);
+  info->N = h->N;
+  info->leaf = h->leaf;
+  info->L = h->L;
+  info->H = h->H;
+  info->oversample = h->oversample;
+  info->tol = h->tol;
+  info->nnz_S = h->nnz_S;
+  info->rank_min = 1 << 30;
+  for (const auto* side : {&h->U, &h->V}) {
+    for (const Batch& b : *side) {
+      info->n_ids += b.n;
+      info->nnz_T += b.n_T;
+      info->n_skel += b.n_skel;
+      info->rank_min = std::min(info->rank_min, b.rank_min);
+      info->rank_max = std::max(info->rank_max, b.rank_max);
+      info->cand_max = std::max(info->cand_max, b.cand_max);
+      info->samples_max = std::max(info->samples_max, b.s_max);
+    }
+  }
+  if (info->n_ids == 0) info->rank_min = 0;
+  info->device_bytes = (int64_t)(h->arena.total + h->ws_bytes);
+  info->construct_ms = h->construct_ms;
+  return IDBF_OK;
+}
+
+idbf_status idbf_batch_sizes(idbf_handle h, int32_t side, int32_t level, int64_t* n_ids, int64_t* n_skel,
+                             int64_t* n_T) {
+  if (!h) {
+    set_error("handle is NULL");
+    return IDBF_EINVAL;
+  }
+  const Batch* b = find_batch(h, side, level);
+  if (!b) {
+    set_error("no batch for side %d level %d (H = %d)", side, level, h->H);
+    return IDBF_EINVAL;
+  }
+  if (n_ids) *n_ids = b->n;
+  if (n_skel) *n_skel = b->n_skel;
+  if (n_T) *n_T = b->n_T;
+  return IDBF_OK;
+}
+
+idbf_status idbf_batch_export(idbf_handle h, int32_t side, int32_t level, int32_t* rank, int32_t* cand_len,
+                              uint64_t* mask, int32_t* skel, double* T, int64_t* T_off) {
+  if (!h) {
+    set_error("handle is NULL");
+    return IDBF_EINVAL;
+  }
+  const Batch* b = find_batch(h, side, level);
+  if (!b) {
+    set_error("no batch for side %d level %d (H = %d)", side, level, h->H);
+    return IDBF_EINVAL;
+  }
+  IDBF_HIP_CHECK(hipDeviceSynchronize());
+  if (rank) IDBF_HIP_CHECK(hipMemcpy(rank, b->rank, b->n * 4, hipMemcpyDeviceToHost));
+  if (cand_len) IDBF_HIP_CHECK(hipMemcpy(cand_len, b->cand_len, b->n * 4, hipMemcpyDeviceToHost));
+  if (mask) IDBF_HIP_CHECK(hipMemcpy(mask, b->mask, b->n * 8, hipMemcpyDeviceToHost));
+  if (skel) IDBF_HIP_CHECK(hipMemcpy(skel, b->skel_idx, b->n_skel * 4, hipMemcpyDeviceToHost));
+  if (T) IDBF_HIP_CHECK(hipMemcpy(T, b->T128, b->n_T * 16, hipMemcpyDeviceToHost));
+  if (T_off) IDBF_HIP_CHECK(hipMemcpy(T_off, b->T_off, b->n * 8, hipMemcpyDeviceToHost));
+  return IDBF_OK;
+}
+
+idbf_status idbf_middle_sizes(idbf_handle h, int64_t* n_blocks, int64_t* n_entries) {
+  if (!h) {
+    set_error("handle is NULL");
+    return IDBF_EINVAL;
+  }
+  if (n_blocks) *n_blocks = h->nblk;
+  if (n_entries) *n_entries = h->nnz_S;
+  return IDBF_OK;
+}
+
+idbf_status idbf_middle_export(idbf_handle h, double* S, int64_t* S_off) {
+  if (!h) {
+    set_error("handle is NULL");
+    return IDBF_EINVAL;
+  }
+  IDBF_HIP_CHECK(hipDeviceSynchronize());
+  if (S) IDBF_HIP_CHECK(hipMemcpy(S, h->S128, h->nnz_S * 16, hipMemcpyDeviceToHost));
+  if (S_off) IDBF_HIP_CHECK(hipMemcpy(S_off, h->S_off, h->nblk * 8, hipMemcpyDeviceToHost));
+  return IDBF_OK;
+}
+
+idbf_status idbf_sample(const idbf_phase* phase, const double* X, const double* Omega, const int32_t* rows,
+                        int64_t nrows, const int32_t* cols, int64_t ncols, double* out, void* stream) {
+  g_err[0] = 0;
+  TRY(check_phase(phase));
+  if (nrows < 0 || ncols < 0) {
+    set_error("nrows and ncols must be >= 0");
+    return IDBF_EINVAL;
+  }
+  if (nrows * ncols == 0) return IDBF_OK;
+  if (!X || !Omega || !rows || !cols || !out) {
+    set_error("sampler pointers must be non-NULL");
+    return IDBF_EINVAL;
+  }
+  IDBF_HIP_CHECK(launch_sample_dense(to_dev(*phase), X, Omega, rows, nrows, cols, ncols,
+                                     reinterpret_cast<double2*>(out), static_cast<hipStream_t>(stream)));
+  return IDBF_OK;
+}
+
+idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double* Omega, int32_t side,
+                          int64_t n_ids, const int32_t* cand_idx, const int32_t* cand_beg, const int32_t* cand_len,
+                          const int32_t* allow_idx, const int32_t* allow_beg, const int32_t* allow_len, double tol,
+                          int32_t kmax, int32_t oversample, int32_t* rank, uint64_t* mask, int32_t* skel, double* T,
+                          void* stream) {
+  g_err[0] = 0;
+  TRY(check_phase(phase));
+  if (side != IDBF_SIDE_U && side != IDBF_SIDE_V) {
+    set_error("side must be IDBF_SIDE_U or IDBF_SIDE_V");
+    return IDBF_EINVAL;
+  }
+  if (n_ids < 0 || oversample < 1 || kmax < 0 || !(tol >= 0.0 && tol < 1.0) || n_ids > INT32_MAX) {
+    set_error("invalid n_ids, oversample, kmax or tol");
+    return IDBF_EINVAL;
+  }
+  if (n_ids == 0) return IDBF_OK;
+  if (!X || !Omega || !cand_idx || !cand_beg || !cand_len || !allow_idx || !allow_beg || !allow_len || !rank ||
+      !mask || !skel || !T) {
+    set_error("id_batch pointers must be non-NULL");
+    return IDBF_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<int32_t> cl(n_ids), al(n_ids);
+  IDBF_HIP_CHECK(hipMemcpyAsync(cl.data(), cand_len, n_ids * 4, hipMemcpyDeviceToHost, st));
+  IDBF_HIP_CHECK(hipMemcpyAsync(al.data(), allow_len, n_ids * 4, hipMemcpyDeviceToHost, st));
+  IDBF_HIP_CHECK(hipStreamSynchronize(st));
+  int smax = 0;
+  for (int64_t q = 0; q < n_ids; ++q) {
+    if (cl[q] < 1 || cl[q] > kMaxCand || al[q] < 1) {
+      set_error("ID %lld: candidate count %d must be in [1, %d] and allowed count %d >= 1", (long long)q, cl[q],
+                kMaxCand, al[q]);
+      return IDBF_EINVAL;
+    }
+    smax = std::max<int>(smax, (int)std::min<int64_t>((int64_t)oversample * cl[q], al[q]));
+  }
+  if (smax > kMaxSamples) {
+    set_error("%d samples requested (max %d)", smax, kMaxSamples);
+    return IDBF_EUNSUPPORTED;
+  }
+  int32_t* status = nullptr;
+  IDBF_HIP_CHECK(hipMalloc(&status, sizeof(int32_t)));
+  IDBF_HIP_CHECK(hipMemsetAsync(status, 0, sizeof(int32_t), st));
+  IdArgs ia{};
+  ia.ph = to_dev(*phase);
+  ia.X = X;
+  ia.Om = Omega;
+  ia.side = side;
+  ia.n_ids = n_ids;
+  ia.cand_idx = cand_idx;
+  ia.cand_beg = cand_beg;
+  ia.cand_len = cand_len;
+  ia.allow_idx = allow_idx;
+  ia.allow_beg = allow_beg;
+  ia.allow_len = allow_len;
+  ia.tol = tol;
+  ia.kmax = kmax;
+  ia.oversample = oversample;
+  ia.rank = rank;
+  ia.mask = mask;
+  ia.skel_out = skel;
+  ia.T128 = reinterpret_cast<double2*>(T);
+  ia.T64 = nullptr;
+  ia.T_off = nullptr;
+  ia.status = status;
+  const int waves = std::max(1, std::min(kMaxWaves, (smax + kRowsPerWave - 1) / kRowsPerWave));
+  hipError_t e = launch_id_batch(ia, waves, st);
+  int32_t flag = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&flag, status, sizeof flag, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(status);
+  if (e != hipSuccess) {
+    set_error("id_batch: %s", hipGetErrorString(e));
+    return IDBF_EHIP;
+  }
+  if (flag & kErrRank) {
+    set_error("an ID needs rank > %d at tol %g", kMaxRank, tol);
+    return IDBF_ERANK;
+  }
+  if (flag & kErrSize) {
+    set_error("an ID exceeded the kernel's size limits");
+    return IDBF_EUNSUPPORTED;
+  }
+  return IDBF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Launchers of the IDBF HIP kernels (one translation unit per kernel family).
+#pragma once
+
+#include "common.hpp"
+
+namespace idbf {
+
+// Error bits a kernel may raise in its status word.
+enum : int32_t { kErrRank = 1, kErrSize = 2 };
+
+// ------------------------------------------------------------- batched ID
+struct IdArgs {
+  PhaseDev ph;
+  const double* X;
+  const double* Om;
+  int side;  // IDBF_SIDE_U: candidates are rows (row ID); IDBF_SIDE_V: columns (column ID)
+  int64_t n_ids;
+  const int32_t* cand_idx;
+  const int32_t* cand_beg;
+  const int32_t* cand_len;
+  const int32_t* allow_idx;
+  const int32_t* allow_beg;
+  const int32_t* allow_len;
+  double tol;
+  int kmax;
+  int oversample;
+  int32_t* rank;
+  uint64_t* mask;
+  int32_t* skel_out;     // kMaxCand entries per ID
+  double2* T128;
+  float2* T64;           // may be null
+  const int64_t* T_off;  // null: ID q writes at q * kSlot
+  int32_t* status;
+};
+// waves: 1..4 cooperating waves per ID (s <= 32 * waves)
+hipError_t launch_id_batch(const IdArgs& a, int waves, hipStream_t st);
+
+// ------------------------------------------------------------- level plumbing
+struct DescArgs {
+  int side, t, L, leaf;
+  int64_t N, n_ids;
+  int oversample, kmax;
+  const int32_t* prev_skel_off;   // same side, level t-1 (t > 1)
+  const int32_t* allow_skel_off;  // U: V_{t-1} (t > 1); V: U_t
+  int32_t* cand_beg;
+  int32_t* cand_len;
+  int32_t* allow_beg;
+  int32_t* allow_len;
+  int64_t* t_bound;               // upper bound of k (c - k) per ID
+  int32_t* samples;               // s = min(t c, |allowed|) per ID
+};
+hipError_t launch_desc(const DescArgs& a, hipStream_t st);
+
+// Exclusive scan of n values into off[0..n] (off[n] = total) plus the sum,
+// max and min of the values and the max of an optional second array, written
+// to stats[0..3].  One workgroup; fine for the <= 2^22 values of a level.
+hipError_t launch_scan_i64(const int64_t* v, int64_t n, int64_t* off, const int32_t* aux,
+                           int64_t* stats, hipStream_t st);
+hipError_t launch_scan_i32(const int32_t* v, int64_t n, int32_t* off, const int32_t* aux,
+                           int64_t* stats, hipStream_t st);
+
+hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t st);
+hipError_t launch_compact_skel(const int32_t* scratch, const int32_t* rank, const int32_t* off,
+                               int64_t n_ids, int32_t* out, hipStream_t st);
+
+// Middle factor: per block b rows skel_r[rbeg .. +rlen), cols skel_c[cbeg .. +clen).
+struct MiddleDescArgs {
+  int L, H;
+  int64_t n_blocks;
+  const int32_t* u_off;  // U_H skeleton offsets
+  const int32_t* v_off;  // V_H skeleton offsets
+  int32_t* rbeg;
+  int32_t* rlen;
+  int32_t* cbeg;
+  int32_t* clen;
+  int64_t* size;
+};
+hipError_t launch_middle_desc(const MiddleDescArgs& a, hipStream_t st);
+struct SampleBlocksArgs {
+  PhaseDev ph;
+  const double* X;
+  const double* Om;
+  int64_t n_blocks;
+  const int32_t* row_idx;
+  const int32_t* col_idx;
+  const int32_t* rbeg;
+  const int32_t* rlen;
+  const int32_t* cbeg;
+  const int32_t* clen;
+  const int64_t* off;
+  double2* out128;
+  float2* out64;  // may be null
+};
+// block b stored column-major at off[b]: entry (i, j) at off[b] + j * rlen[b] + i
+hipError_t launch_sample_blocks(const SampleBlocksArgs& a, hipStream_t st);
+
+// dense sampler: out[i * nc + j] = K(X[rows[i]], Om[cols[j]])
+hipError_t launch_sample_dense(const PhaseDev& ph, const double* X, const double* Om,
+                               const int32_t* rows, int64_t nr, const int32_t* cols, int64_t nc,
+                               double2* out, hipStream_t st);
+
+// ------------------------------------------------------------- apply
+struct StageArgs {
+  int64_t n;               // IDs (V stage) or units (U stage) or U_H IDs (S stage)
+  int nn;                  // U stage: nodes per partner row of the level (2^(L-t+1))
+  int64_t nrhs;
+  const int32_t* cand_beg;
+  const int32_t* cand_len;
+  const int32_t* rank;
+  const int32_t* skel_off;
+  const uint64_t* mask;
+  const int64_t* T_off;
+  const void* T;           // double2 or float2 entries
+  const void* in;
+  void* out;
+  // middle stage
+  int nsub;                // blocks per output: 2^(d-H) (1 when H = 0)
+  const int32_t* rbeg;
+  const int32_t* rlen;
+  const int32_t* cbeg;
+  const int32_t* clen;
+};
+hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st);
+hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st);
+hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st);
+
+}  // namespace idbf

@@ -1,0 +1,231 @@
+// Level plumbing of the construction (Sections 2.2-2.4): per-ID candidate and
+// allowed index segments, prefix scans that size the packed factor arrays,
+// skeleton compaction, and the middle factor's block list.
+//
+// IDs of level t are numbered q = partner * 2^(L-t+1) + node.  In that order
+//  - the candidates of a level-t ID (the merged skeletons of its node's two
+//    children for the same parent partner) are one contiguous segment of the
+//    level t-1 skeleton list of the same side, and
+//  - its allowed points (skeletons of the other side for every descendant at
+//    the right depth, with the partner the tree algebra fixes) are one
+//    contiguous segment of the other side's list,
+// so every ID reads two contiguous index segments.
+#include "kernels.hpp"
+
+namespace idbf {
+
+namespace {
+
+__global__ void desc_kernel(DescArgs A) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= A.n_ids) return;
+  const int t = A.t, L = A.L;
+  const int64_t nn = 1ll << (L - t + 1);
+  const int64_t node = q % nn, partner = q / nn;
+  int32_t cb, cl, ab, al;
+  if (t == 1) {
+    cb = (int32_t)(node * A.leaf);
+    cl = A.leaf;
+  } else {
+    // children 2 node, 2 node + 1 of the parent partner at level t-1
+    const int64_t qp = (partner >> 1) * (2 * nn) + 2 * node;
+    cb = A.prev_skel_off[qp];
+    cl = A.prev_skel_off[qp + 2] - cb;
+  }
+  if (A.side == IDBF_SIDE_U) {
+    if (t == 1) {
+      ab = (int32_t)(partner * (A.N / 2));
+      al = (int32_t)(A.N / 2);
+    } else {
+      // V_{t-1} IDs (C'' below partner at depth L-t+2, ancestor of node at depth t-1)
+      const int sh = L - 2 * t + 2;
+      const int64_t lo = (node >> sh) * (2 * nn) + (partner << sh);
+      ab = A.allow_skel_off[lo];
+      al = A.allow_skel_off[lo + (1ll << sh)] - ab;
+    }
+  } else {
+    // U_t IDs (R'' below partner at depth L-t+1, ancestor of node at depth t)
+    const int sh = L - 2 * t + 1;
+    const int64_t lo = (node >> sh) * nn + (partner << sh);
+    ab = A.allow_skel_off[lo];
+    al = A.allow_skel_off[lo + (1ll << sh)] - ab;
+  }
+  A.cand_beg[q] = cb;
+  A.cand_len[q] = cl;
+  A.allow_beg[q] = ab;
+  A.allow_len[q] = al;
+  const int64_t s = min((int64_t)A.oversample * cl, (int64_t)al);
+  int64_t kcap = min((int64_t)cl, s);
+  if (A.kmax > 0) kcap = min(kcap, (int64_t)A.kmax);
+  kcap = min(kcap, (int64_t)kMaxRank);
+  const int64_t half = cl / 2;
+  A.t_bound[q] = (kcap >= half) ? half * (cl - half) : kcap * (cl - kcap);
+  A.samples[q] = (int32_t)s;
+}
+
+template <typename V, typename O>
+__global__ __launch_bounds__(1024) void scan_kernel(const V* v, int64_t n, O* off, const int32_t* aux,
+                                                    int64_t* stats) {
+  __shared__ int64_t s_sum[1024];
+  __shared__ int64_t s_max[1024];
+  __shared__ int64_t s_min[1024];
+  __shared__ int64_t s_aux[1024];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t b = tid * chunk, e = min(n, b + chunk);
+  int64_t sum = 0, mx = INT64_MIN, mn = INT64_MAX, ax = INT64_MIN;
+  for (int64_t i = b; i < e; ++i) {
+    const int64_t x = (int64_t)v[i];
+    sum += x;
+    mx = max(mx, x);
+    mn = min(mn, x);
+    if (aux) ax = max(ax, (int64_t)aux[i]);
+  }
+  s_sum[tid] = sum;
+  s_max[tid] = mx;
+  s_min[tid] = mn;
+  s_aux[tid] = ax;
+  __syncthreads();
+  // inclusive Hillis-Steele scan of the chunk sums
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int64_t add = (tid >= d) ? s_sum[tid - d] : 0;
+    __syncthreads();
+    s_sum[tid] += add;
+    __syncthreads();
+  }
+  int64_t run = (tid == 0) ? 0 : s_sum[tid - 1];
+  for (int64_t i = b; i < e; ++i) {
+    off[i] = (O)run;
+    run += (int64_t)v[i];
+  }
+  if (tid == 1023) off[n] = (O)s_sum[1023];
+  for (int d = 512; d > 0; d >>= 1) {
+    if (tid < d) {
+      s_max[tid] = max(s_max[tid], s_max[tid + d]);
+      s_min[tid] = min(s_min[tid], s_min[tid + d]);
+      s_aux[tid] = max(s_aux[tid], s_aux[tid + d]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    stats[0] = s_sum[1023];
+    stats[1] = s_max[0];
+    stats[2] = s_min[0];
+    stats[3] = s_aux[0];
+  }
+}
+
+__global__ void iota_kernel(int32_t* p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+__global__ void compact_kernel(const int32_t* scratch, const int32_t* rank, const int32_t* off,
+                               int64_t n_ids, int32_t* out) {
+  const int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (q >= n_ids) return;
+  if (lane < rank[q]) out[off[q] + lane] = scratch[q * kMaxCand + lane];
+}
+
+__global__ void middle_desc_kernel(MiddleDescArgs A) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (b >= A.n_blocks) return;
+  const int H = A.H, d = A.L - A.H + 1, sh = d - H;
+  const int64_t nsub = 1ll << sh;
+  const int64_t qu = b / nsub, j = b % nsub;
+  const int64_t r = qu & ((1ll << d) - 1), cpart = qu >> d;   // U_H ID (node r, partner cpart)
+  const int64_t cnode = (cpart << sh) + j;                      // column node at depth d
+  const int64_t qv = (r >> sh) * (1ll << d) + cnode;            // V_H ID (node cnode, partner r >> sh)
+  const int32_t rb = A.u_off[qu], rl = A.u_off[qu + 1] - rb;
+  const int32_t cb = A.v_off[qv], cl = A.v_off[qv + 1] - cb;
+  A.rbeg[b] = rb;
+  A.rlen[b] = rl;
+  A.cbeg[b] = cb;
+  A.clen[b] = cl;
+  A.size[b] = (int64_t)rl * cl;
+}
+
+// One workgroup per block; lanes over rows, loop over columns.
+__global__ __launch_bounds__(256) void sample_blocks_kernel(SampleBlocksArgs A) {
+  const int64_t b = blockIdx.x;
+  const int rl = A.rlen[b], cl = A.clen[b];
+  const int32_t* ri = A.row_idx + A.rbeg[b];
+  const int32_t* ci = A.col_idx + A.cbeg[b];
+  const int64_t off = A.off[b];
+  const bool fio = (A.ph.kind == IDBF_PHASE_FIO);
+  for (int64_t e = threadIdx.x; e < (int64_t)rl * cl; e += blockDim.x) {
+    const int i = (int)(e % rl), jc = (int)(e / rl);
+    const double x = A.X[ri[i]];
+    const double cx = fio ? amplitude_shift(A.ph, x) : 0.0;
+    const double2 v = kernel_entry(A.ph, x, cx, A.Om[ci[jc]]);
+    A.out128[off + e] = v;
+    if (A.out64) A.out64[off + e] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+__global__ void sample_dense_kernel(PhaseDev ph, const double* X, const double* Om, const int32_t* rows,
+                                    int64_t nr, const int32_t* cols, int64_t nc, double2* out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= nr * nc) return;
+  const int64_t i = e / nc, j = e % nc;
+  const double x = X[rows[i]];
+  const double cx = (ph.kind == IDBF_PHASE_FIO) ? amplitude_shift(ph, x) : 0.0;
+  out[e] = kernel_entry(ph, x, cx, Om[cols[j]]);
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_desc(const DescArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(desc_kernel, dim3(blocks_for(a.n_ids, 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_i64(const int64_t* v, int64_t n, int64_t* off, const int32_t* aux, int64_t* stats,
+                           hipStream_t st) {
+  hipLaunchKernelGGL((scan_kernel<int64_t, int64_t>), dim3(1), dim3(1024), 0, st, v, n, off, aux, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_i32(const int32_t* v, int64_t n, int32_t* off, const int32_t* aux, int64_t* stats,
+                           hipStream_t st) {
+  hipLaunchKernelGGL((scan_kernel<int32_t, int32_t>), dim3(1), dim3(1024), 0, st, v, n, off, aux, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_skel(const int32_t* scratch, const int32_t* rank, const int32_t* off, int64_t n_ids,
+                               int32_t* out, hipStream_t st) {
+  if (n_ids <= 0) return hipSuccess;
+  hipLaunchKernelGGL(compact_kernel, dim3(blocks_for(n_ids, 4)), dim3(256), 0, st, scratch, rank, off, n_ids,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_middle_desc(const MiddleDescArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(middle_desc_kernel, dim3(blocks_for(a.n_blocks, 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_blocks(const SampleBlocksArgs& a, hipStream_t st) {
+  if (a.n_blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sample_blocks_kernel, dim3((unsigned)a.n_blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_dense(const PhaseDev& ph, const double* X, const double* Om, const int32_t* rows,
+                               int64_t nr, const int32_t* cols, int64_t nc, double2* out, hipStream_t st) {
+  if (nr * nc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sample_dense_kernel, dim3(blocks_for(nr * nc, 256)), dim3(256), 0, st, ph, X, Om, rows, nr,
+                     cols, nc, out);
+  return hipGetLastError();
+}
+
+}  // namespace idbf

@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every declared symbol; host-side
+argument checks answer without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1809_10573_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+pytestmark = pytest.mark.skipif(not os.path.exists(B.LIB_PATH), reason="library not built")
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "idbf.h")).read()
+    return sorted(set(re.findall(r"\b(idbf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = B.load()
+    names = _declared()
+    assert set(names) == set(B.EXPORTED)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_defaults_and_error_string():
+    lib = B.load()
+    o = B.Opts_t()
+    o.kmax, o.oversample = 7, 9
+    lib.idbf_opts_default(C.byref(o))
+    assert (o.kmax, o.oversample, o.mem_cap_bytes) == (0, 1, 0)
+    lib.idbf_opts_default(None)          # NULL-safe
+    assert isinstance(lib.idbf_last_error(), bytes)
+    assert lib.idbf_destroy(None) == B.OK
+
+
+def test_argument_errors_without_gpu():
+    lib = B.load()
+    ph = B.Phase_t(B.PHASE_DFT, 0, 0.0, 0.0, 0.0, 1.0)
+    h = C.c_void_p()
+    fake = C.c_void_p(16)  # never dereferenced: every call below fails its checks first
+    assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1e-6, 8, None, None) == B.EINVAL
+    assert lib.idbf_construct(C.byref(ph), fake, fake, 1000, 1e-6, 8, None, C.byref(h)) == B.EINVAL
+    assert b"power of two" in lib.idbf_last_error()
+    assert h.value is None
+    assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1e-6, 3, None, C.byref(h)) == B.EINVAL
+    assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1e-6, 128, None, C.byref(h)) == B.EINVAL
+    assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1.5, 8, None, C.byref(h)) == B.EINVAL
+    assert lib.idbf_construct(C.byref(ph), None, fake, 1024, 1e-6, 8, None, C.byref(h)) == B.EINVAL
+    bad = B.Phase_t(7, 0, 0.0, 0.0, 0.0, 1.0)
+    assert lib.idbf_construct(C.byref(bad), fake, fake, 1024, 1e-6, 8, None, C.byref(h)) == B.EINVAL
+    fio0 = B.Phase_t(B.PHASE_FIO, 0, 2.0, 1.0, 1.0, 0.0)
+    assert lib.idbf_construct(C.byref(fio0), fake, fake, 1024, 1e-6, 8, None, C.byref(h)) == B.EINVAL
+    o = B.Opts_t()
+    lib.idbf_opts_default(C.byref(o))
+    o.oversample = 0
+    assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1e-6, 8, C.byref(o), C.byref(h)) == B.EINVAL
+    assert lib.idbf_apply(None, fake, fake, 1, B.C128, None) == B.EINVAL
+    assert lib.idbf_get_info(None, None) == B.EINVAL
+    assert lib.idbf_batch_sizes(None, 0, 1, None, None, None) == B.EINVAL
+    assert lib.idbf_sample(C.byref(ph), fake, fake, fake, -1, fake, 3, fake, None) == B.EINVAL
+    assert lib.idbf_sample(C.byref(ph), fake, fake, fake, 0, fake, 3, fake, None) == B.OK
+    assert lib.idbf_id_batch(C.byref(ph), fake, fake, 5, 1, fake, fake, fake, fake, fake, fake, 1e-6, 0, 1,
+                             fake, fake, fake, fake, None) == B.EINVAL

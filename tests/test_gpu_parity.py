@@ -1,0 +1,248 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle.
+
+Tolerances are derived from the arithmetic:
+* entries: the phase is reduced modulo 1 exactly on both sides except for c(x)
+  itself (GPU sinpi vs host sin, a few ulps): |dK| <= 2 pi (|xi| * 8 ulp(1) * a/cdiv + 1e-15) + 1e-15;
+* T = R11^{-1} R12: perturbations of the sampled block are amplified by the
+  conditioning of R11, bounded by |R_00| / |R_kk|;
+* apply: products of O(log N) factors in FP64 (c128) or FP32 (c64).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_10573_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1809_10573_amd import binding as B  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _entry_tol(phase, N):
+    amp = 0.0 if phase.kind == I.PHASE_DFT else abs(phase.a) / abs(phase.cdiv)
+    return 2 * np.pi * ((N / 2) * 8 * 2.2e-16 * amp + 1e-15) + 1e-15
+
+
+# ------------------------------------------------------------------ sampler
+@pytest.mark.parametrize("kind,N", [("dft", 1024), ("fio", 1024), ("dft", 1 << 20), ("fio", 1 << 20)])
+def test_sampler_matches_oracle(kind, N):
+    ph = I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    rng = np.random.default_rng(N + len(kind))
+    rows = np.sort(rng.choice(N, 97, replace=False))
+    cols = np.sort(np.concatenate([rng.choice(N, 60, replace=False), [0, N // 2, N - 1]]))
+    cols = np.unique(cols)
+    got = B.sample(ph, X, O, rows, cols, device=DEV).cpu().numpy()
+    ref = oracle.entries(ph, X, O, rows, cols)
+    assert np.max(np.abs(got - ref)) <= _entry_tol(ph, N)
+
+
+def test_sampler_empty():
+    X, O = I.uniform_grid(64)
+    got = B.sample(I.dft_phase(), X, O, np.zeros(0, np.int32), np.arange(5), device=DEV)
+    assert got.shape == (0, 5)
+
+
+# ------------------------------------------------------------------ batched ID
+def _id_problem(rng, N, c, wc, na, wa):
+    """Candidates: c of a window of wc grid points; allowed: na of a window of wa
+    points elsewhere.  wc * wa / N bounds the block's time-frequency product, as
+    for the complementary blocks the construction meets."""
+    c0 = int(rng.integers(0, N - wc))
+    a0 = int(rng.integers(0, N - wa))
+    cand = np.sort(c0 + rng.choice(wc, c, replace=False))
+    allowed = np.sort(a0 + rng.choice(wa, na, replace=False))
+    return cand, allowed
+
+
+def _run_ids(ph, X, O, side, problems, tol, kmax, oversample):
+    cands = [p[0] for p in problems]
+    alloweds = [p[1] for p in problems]
+    cb = np.cumsum([0] + [len(x) for x in cands[:-1]])
+    ab = np.cumsum([0] + [len(x) for x in alloweds[:-1]])
+    return B.id_batch(ph, X, O, side, np.concatenate(cands), cb, [len(x) for x in cands],
+                      np.concatenate(alloweds), ab, [len(x) for x in alloweds], tol, kmax,
+                      oversample, device=DEV)
+
+
+@pytest.mark.parametrize("side", [B.SIDE_U, B.SIDE_V])
+@pytest.mark.parametrize("oversample,kmax", [(1, 0), (2, 0), (2, 7)])
+def test_id_batch_matches_oracle(side, oversample, kmax):
+    N = 4096
+    ph = I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    rng = np.random.default_rng(10 * side + oversample + kmax)
+    shapes = [(8, 8, 5, 5), (16, 16, 16, 16), (16, 16, 700, 2048), (24, 32, 30, 40),
+              (33, 40, 700, 800), (52, 64, 60, 64), (64, 128, 64, 100), (5, 5, 1, 1),
+              (40, 48, 128, 300), (17, 20, 1500, 1600), (1, 1, 50, 60), (12, 12, 12, 12),
+              (28, 28, 2000, 2048), (60, 64, 90, 90)]
+    problems = [_id_problem(rng, N, *sh) for sh in shapes]
+    tol = 1e-6
+    rank, mask, skel, T = _run_ids(ph, X, O, side, problems, tol, kmax, oversample)
+    allow_coord = X if side == B.SIDE_V else O
+    for q, (cand, allowed) in enumerate(problems):
+        s = min(oversample * len(cand), len(allowed))
+        samp = allowed[oracle.mock_chebyshev(allow_coord[allowed], s)]
+        Bm = (oracle.entries(ph, X, O, samp, cand) if side == B.SIDE_V
+              else oracle.entries(ph, X, O, cand, samp).T)
+        cid = oracle.column_id(Bm, tol, kmax)
+        k = cid.rank
+        assert rank[q] == k, (q, rank[q], k)
+        assert np.array_equal(skel[q, :k], cand[cid.skel]), q
+        bits = np.array([(int(mask[q]) >> l) & 1 for l in range(len(cand))], bool)
+        assert np.array_equal(np.nonzero(bits)[0], cid.skel)
+        r = len(cand) - k
+        flat = T[q, :k * r]
+        Tg = flat.reshape(r, k).T if side == B.SIDE_V else flat.reshape(k, r)
+        kappa = cid.rdiag[0] / cid.rdiag[-1]
+        scale = max(1.0, np.abs(cid.T).max()) if r else 1.0
+        assert np.max(np.abs(Tg - cid.T), initial=0.0) <= 1e-12 * kappa * scale, q
+
+
+def test_id_batch_rank_overflow_is_reported():
+    # 64 candidates spread over the whole grid against 64 spread allowed points:
+    # full rank, above the 32 the kernel holds -> IDBF_ERANK, not a wrong answer
+    N = 4096
+    X, O = I.uniform_grid(N)
+    rng = np.random.default_rng(3)
+    prob = (np.sort(rng.choice(N, 64, replace=False)), np.sort(rng.choice(N, 64, replace=False)))
+    with pytest.raises(B.IdbfError) as e:
+        _run_ids(I.dft_phase(), X, O, B.SIDE_V, [prob], 1e-6, 0, 1)
+    assert e.value.status == B.ERANK
+    rank, _, _, _ = _run_ids(I.dft_phase(), X, O, B.SIDE_V, [prob], 1e-6, 20, 1)
+    assert rank[0] == 20
+
+
+def test_id_batch_rejects_oversized():
+    N = 1024
+    X, O = I.uniform_grid(N)
+    with pytest.raises(B.IdbfError) as e:
+        B.id_batch(I.dft_phase(), X, O, B.SIDE_V, np.arange(65), [0], [65], np.arange(100), [0],
+                   [100], 1e-6, device=DEV)
+    assert e.value.status == B.EINVAL
+
+
+# ------------------------------------------------------------------ construction
+def _compare_construction(F, fac, ph, X, O):
+    """Level-by-level comparison of GPU factors with the oracle's.
+
+    Skeletons must agree exactly.  T = R11^{-1} R12 may differ by the sampled
+    entries' perturbation amplified by R11's conditioning: the bound used is
+    1e-12 * (|R_00| / |R_kk|) * max(1, max |T|)."""
+    L, H = F.L, F.H
+    mismatched = 0
+    for t in range(1, H + 1):
+        nn = 1 << (L - t + 1)
+        for side, recs in ((B.SIDE_U, F.U[t]), (B.SIDE_V, F.V[t])):
+            b = fac.batch(side, t)
+            offs = np.concatenate([[0], np.cumsum(b.rank)])
+            for q in range(len(b.rank)):
+                rec = recs[(q % nn, q // nn)]
+                k = len(rec.skel)
+                assert b.cand_len[q] == len(rec.cand)
+                gs = b.skel[offs[q]:offs[q + 1]]
+                if b.rank[q] != k or not np.array_equal(gs, rec.skel):
+                    mismatched += 1
+                    continue
+                r = len(rec.cand) - k
+                flat = b.T[b.T_off[q]:b.T_off[q] + k * r]
+                Tg = flat.reshape(r, k).T if side == B.SIDE_V else flat.reshape(k, r)
+                scale = max(1.0, np.abs(rec.T).max(initial=0.0))
+                kappa = rec.rdiag[0] / rec.rdiag[-1]
+                assert np.max(np.abs(Tg - rec.T), initial=0.0) <= 1e-12 * kappa * scale
+    return mismatched
+
+
+@pytest.mark.parametrize("N,leaf,kind,tol,os_", [
+    (1024, 8, "dft", 1e-10, 1),     # the DFT workload: L = 7 (odd), H = 3
+    (16, 8, "dft", 1e-10, 1),       # L = 1: no levels, S = K
+    (64, 16, "fio", 1e-6, 1),       # L = 2, H = 1
+    (256, 2, "fio", 1e-8, 1),       # L = 7 with leaf 2
+    (2048, 16, "fio", 1e-6, 2),     # the FIO workload's shape at a small N
+    (1024, 4, "fio", 1e-4, 1),
+])
+def test_construct_and_apply_match_oracle(N, leaf, kind, tol, os_):
+    ph = I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    F = oracle.build(ph, X, O, leaf, tol, oversample=os_)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=os_, device=DEV)
+    info = fac.info()
+    assert (info["L"], info["H"]) == (F.L, F.H)
+    assert _compare_construction(F, fac, ph, X, O) == 0
+    assert info["nnz_T"] + info["nnz_S"] >= F.nnz()
+    g = I.gaussian_vectors(N, None, seed=N)
+    y_or = oracle.apply(F, g)
+    x = torch.as_tensor(g, device=DEV)
+    y128 = fac.apply(x).cpu().numpy()
+    assert oracle.relative_error(y128, y_or) < 1e-12
+    y64 = fac.apply(x.to(torch.complex64)).cpu().numpy()
+    assert oracle.relative_error(y64, y_or) < 2e-6
+    # against the exact matvec
+    y_ex = (oracle.dft_closed_form(g) if kind == "dft" else oracle.dense_matvec(ph, X, O, g))
+    assert oracle.relative_error(y128, y_ex) < max(100 * tol, 1e-12)
+
+
+def test_apply_many_rhs_and_repeat():
+    N, leaf, tol = 2048, 16, 1e-6
+    ph = I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    F = oracle.build(ph, X, O, leaf, tol, oversample=2)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=2, device=DEV)
+    G = I.gaussian_vectors(N, 67, seed=5)          # a ragged right-hand-side count
+    Y_or = oracle.apply(F, G)
+    Gd = torch.as_tensor(G, device=DEV)
+    Y = fac.apply(Gd).cpu().numpy()
+    assert oracle.relative_error(Y, Y_or) < 1e-12
+    Y2 = fac.apply(Gd).cpu().numpy()
+    assert np.array_equal(Y, Y2)                    # deterministic: no atomics
+    Y64 = fac.apply(Gd.to(torch.complex64)).cpu().numpy()
+    assert oracle.relative_error(Y64, Y_or) < 2e-6
+    one = fac.apply(Gd[:, 3].contiguous()).cpu().numpy()
+    assert oracle.relative_error(one, Y_or[:, 3]) < 1e-12
+    empty = torch.zeros((N, 0), dtype=torch.complex128, device=DEV)
+    assert fac.apply(empty).shape == (N, 0)
+
+
+def test_construct_errors():
+    X, O = I.uniform_grid(64)
+    with pytest.raises(B.IdbfError) as e:
+        B.construct(I.dft_phase(), X, O, 1e-6, 3, device=DEV)
+    assert e.value.status == B.EINVAL
+    with pytest.raises(B.IdbfError) as e:
+        B.construct(I.dft_phase(), X[::-1].copy(), O, 1e-6, 4, device=DEV)
+    assert e.value.status == B.EINVAL
+    Xn = X.copy()
+    Xn[5] = np.nan
+    with pytest.raises(B.IdbfError) as e:
+        B.construct(I.dft_phase(), Xn, O, 1e-6, 4, device=DEV)
+    assert e.value.status == B.EINVAL
+    with pytest.raises(B.IdbfError) as e:
+        B.construct(I.fio_phase(1.0, 1.0), *I.uniform_grid(4096), 1e-6, 16, mem_cap_bytes=1 << 16,
+                    device=DEV)
+    assert e.value.status == B.ENOMEM
+
+
+# ------------------------------------------------------------------ full size
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_full_size_fio_sampled_rows(dtype):
+    """N = 2^20, leaf 16, tol 1e-6, t = 2 (the measured workload): 48 exact rows."""
+    N, leaf, tol = 1 << 20, 16, 1e-6
+    ph = I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=2, device=DEV)
+    info = fac.info()
+    assert info["H"] == 8 and info["rank_max"] <= 32
+    g = I.gaussian_vectors(N, None, seed=4)
+    x = torch.as_tensor(g, device=DEV)
+    if dtype == "c64":
+        x = x.to(torch.complex64)
+    y = fac.apply(x).cpu().numpy()
+    rows = np.sort(np.random.default_rng(4).choice(N, 48, replace=False))
+    ex = oracle.matvec_rows(ph, X, O, g, rows)
+    assert oracle.relative_error(y[rows], ex) < 1e-4
