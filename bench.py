@@ -1,0 +1,231 @@
+"""Benchmark of the IDBF hot path on one MI355X.
+
+One step = the whole hot path on the N = 2^20 FIO workload
+(Phi = x xi + c(x)|xi|, c(x) = (2 + sin 2 pi x)/8, leaf 16, tol 1e-6,
+oversampling t = 2): construction (FP64 IDs on the GPU), one 1-RHS apply in
+complex64 and one apply to 1024 right-hand sides in complex64, all inputs
+resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--nrhs 1024] [--no-cpu-baseline]
+
+value = algorithmic GB/s of the 1-RHS apply (factor entries + skeleton masks +
+x and y once), averaged over the timed steps; construct_ms and the many-RHS
+apply rate are reported beside it.  "roofline" is computed live from HIP events
+the library records around every launch, for the kernel that takes the largest
+share of a step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1809_10573_amd import inputs as I  # noqa: E402
+
+METRIC = "IDBF apply GB/s+GFLOP/s & construct ms, N=2^20, vs plain FP64 at rel.err 1e-6"
+HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK = 78.6e12
+FP32_MFMA_PEAK = 157.3e12
+
+WORKLOAD = dict(N=1 << 20, leaf=16, tol=1e-6, oversample=2, a=1.0, freq=1.0, c0=2.0, cdiv=8.0)
+
+
+def _cpu_baseline(timeout_s: int = 240) -> dict | None:
+    """The oracle, single-threaded, on a bounded sample of the same workload."""
+    code = r"""
+import json, os, sys, time
+sys.path.insert(0, %r)
+import numpy as np
+import oracle
+from paper_1809_10573_amd import inputs as I
+N, leaf, tol, t = 2048, 16, 1e-6, 2
+ph = I.fio_phase(1.0, 1.0)
+X, O = I.uniform_grid(N)
+t0 = time.perf_counter()
+F = oracle.build(ph, X, O, leaf, tol, oversample=t)
+tb = time.perf_counter() - t0
+g = I.gaussian_vectors(N, None, 4)
+reps = 5
+t0 = time.perf_counter()
+for _ in range(reps):
+    y = oracle.apply(F, g)
+ta = (time.perf_counter() - t0) / reps
+nnz = F.nnz()
+print(json.dumps(dict(N=N, nnz=nnz, build_s=tb, apply_s=ta, gbs=(nnz * 16 + 2 * N * 16) / ta / 1e9)))
+""" % ROOT
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    try:
+        res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                             timeout=timeout_s, env=env)
+    except subprocess.TimeoutExpired:
+        return None
+    if res.returncode != 0:
+        print(res.stderr[-2000:], file=sys.stderr)
+        return None
+    r = json.loads(res.stdout.strip().splitlines()[-1])
+    return {"value": r["gbs"], "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle FP64 apply of its own N={r['N']} factorization of the same FIO "
+                       f"kernel (leaf 16, tol 1e-6, t=2; {r['nnz']} stored entries, complex128), "
+                       f"1 thread; apply {r['apply_s'] * 1e3:.1f} ms, construction "
+                       f"{r['build_s']:.1f} s (N=2^20 would take hours)")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nrhs", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; the multi-GPU layout is described "
+              "in DESIGN.md and not run", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1809_10573_amd import binding as B
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    W = WORKLOAD
+    N = W["N"]
+    ph = I.fio_phase(W["a"], W["freq"], W["c0"], W["cdiv"])
+    Xh, Oh = I.uniform_grid(N)
+    X = torch.as_tensor(Xh, device=dev)
+    O = torch.as_tensor(Oh, device=dev)
+    x1 = torch.as_tensor(I.gaussian_vectors(N, None, 4), device=dev).to(torch.complex64)
+    y1 = torch.empty_like(x1)
+    nrhs = args.nrhs
+    gen = torch.Generator(device=dev).manual_seed(4)
+    # N(0,1) + i N(0,1) entries (complex randn has variance 1/2 per component)
+    XM = torch.randn(N, nrhs, dtype=torch.complex64, device=dev, generator=gen) * np.sqrt(2.0)
+    YM = torch.empty_like(XM)
+    stream = torch.cuda.current_stream()
+
+    def step(record):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac = B.construct(ph, X, O, W["tol"], W["leaf"], oversample=W["oversample"], profile=True,
+                          device=dev, stream=stream)
+        t_con = (time.perf_counter() - t0) * 1e3
+        fac.reserve(nrhs, B.C64)  # apply workspace, allocated outside the timed applies
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(stream)
+        fac.apply(x1, y1, stream=stream)
+        e[1].record(stream)
+        e[2].record(stream)
+        fac.apply(XM, YM, stream=stream)
+        e[3].record(stream)
+        torch.cuda.synchronize()
+        if record is not None:
+            record.append(dict(construct_ms=t_con, apply1_ms=e[0].elapsed_time(e[1]),
+                               applyn_ms=e[2].elapsed_time(e[3]), prof=fac.profile(reset=True),
+                               info=fac.info()))
+        return fac
+
+    for _ in range(args.warmup):
+        step(None)
+    recs: list = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fac = None
+    for _ in range(args.steps):
+        del fac
+        fac = step(recs)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    info = recs[-1]["info"]
+    elem = 8
+    bytes1 = (info["nnz_T"] + info["nnz_S"]) * elem + 8 * info["n_ids"] + 2 * N * elem
+    apply1_ms = float(np.mean([r["apply1_ms"] for r in recs]))
+    applyn_ms = float(np.mean([r["applyn_ms"] for r in recs]))
+    construct_ms = float(np.mean([r["construct_ms"] for r in recs]))
+    flops_n = 8.0 * (info["nnz_T"] + info["nnz_S"]) * nrhs
+    value = bytes1 / apply1_ms / 1e6
+
+    # per-kernel aggregates over the timed steps
+    agg: dict = {}
+    for r in recs:
+        for name, st in r["prof"].items():
+            a = agg.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0, flops=0.0))
+            for k in a:
+                a[k] += st[k]
+    dom_name = max(agg, key=lambda k: agg[k]["ms"])
+    dom = agg[dom_name]
+    if dom_name == "id_qr":
+        achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=FP64_VALU_PEAK / 1e12, unit="TFLOP/s")
+    elif dom_name.startswith("applyn"):
+        achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+        roof = dict(bound="mfma", achieved=achieved, peak=FP32_MFMA_PEAK / 1e12, unit="TFLOP/s")
+    else:
+        achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom_name
+    roof["launches_per_step"] = dom["launches"] / len(recs)
+
+    # accuracy (outside the timed region): complex64 apply vs the FP64 (complex128)
+    # apply of the same factors on 8 probe vectors, and the paper's epsilon^a on 256 rows
+    probes = torch.as_tensor(I.gaussian_vectors(N, 8, 5), device=dev)
+    y64 = fac.apply(probes.to(torch.complex64).contiguous()).to(torch.complex128)
+    y128 = fac.apply(probes)
+    rel64 = float(torch.linalg.norm(y64 - y128) / torch.linalg.norm(y128))
+    rows = np.sort(np.random.default_rng(0).choice(N, 256, replace=False))
+    ex = torch.zeros(256, dtype=torch.complex128, device=dev)
+    cols = torch.arange(N, dtype=torch.int32, device=dev)
+    rows_d = torch.as_tensor(rows, dtype=torch.int32, device=dev)
+    for c0 in range(0, N, 1 << 16):
+        K = B.sample(ph, X, O, rows_d, cols[c0:c0 + (1 << 16)], device=dev)
+        ex += K @ probes[c0:c0 + (1 << 16), 0]
+    eps_a = float(torch.linalg.norm(y128[rows, 0] - ex) / torch.linalg.norm(ex))
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 apply / f64 construct", "data": "synthetic",
+        "config": {"workload": "FIO exp(2 pi i (x xi + (2+sin 2 pi x)/8 |xi|)), uniform grid",
+                   "N": N, "leaf": W["leaf"], "tol": W["tol"], "oversample": W["oversample"],
+                   "nrhs": [1, nrhs]},
+        "construct_ms": construct_ms, "apply1_ms": apply1_ms, "applyn_ms": applyn_ms,
+        "applyn_gflops": flops_n / applyn_ms / 1e6,
+        "id_fp64_tflops": agg.get("id_qr", {}).get("flops", 0) / max(agg.get("id_qr", {}).get("ms", 1), 1e-9) / 1e9,
+        "rel_err_c64_vs_c128": rel64, "eps_a_256rows": eps_a,
+        "nnz": info["nnz_T"] + info["nnz_S"], "rank_max": info["rank_max"],
+        "kernels": {k: {"launches_per_step": v["launches"] / len(recs),
+                        "ms_per_step": v["ms"] / len(recs)} for k, v in sorted(agg.items())},
+        "roofline": roof,
+        "roofline_apply1": None,
+        "cpu_baseline": None,
+    }
+    # 1-RHS apply roofline: the three stage kernels of one 1-RHS apply
+    a1 = [fac.apply(x1, y1)]
+    torch.cuda.synchronize()
+    fac.profile(reset=True)
+    fac.apply(x1, y1)
+    p1 = fac.profile(reset=True)
+    tb = sum(v["bytes"] for k, v in p1.items() if k.startswith("apply"))
+    tm = sum(v["ms"] for k, v in p1.items() if k.startswith("apply"))
+    out["roofline_apply1"] = {"bound": "hbm", "achieved": tb / tm / 1e6, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": tb / tm / 1e6 / HBM_PEAK_GBS,
+                              "kernels": {k: v["ms"] for k, v in p1.items()}}
+    del a1
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

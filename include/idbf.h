@@ -61,10 +61,13 @@ typedef struct idbf_phase {
   double c0, a, freq, cdiv;  /* c(x) parameters; ignored for the DFT; cdiv != 0 */
 } idbf_phase;
 
+enum { IDBF_FLAG_PROFILE = 1 }; /* record per-launch device times (idbf_profile_read) */
+
 typedef struct idbf_opts {
   int32_t kmax;        /* rank parameter k of the (eps, k)-ID (Section 2.1); 0: k = min(s, c) */
   int32_t oversample;  /* oversampling parameter t >= 1: s = min(t |cand|, |allowed|) samples */
-  int32_t reserved0, reserved1;
+  int32_t flags;       /* IDBF_FLAG_* */
+  int32_t reserved1;
   uint64_t mem_cap_bytes; /* cap on device memory a handle may allocate; 0: none */
   void* stream;        /* hipStream_t used by idbf_construct */
 } idbf_opts;
@@ -72,7 +75,7 @@ typedef struct idbf_opts {
 typedef struct idbf_handle_s* idbf_handle;
 
 /* Fill *o with the defaults: kmax 0, oversample 1 (the paper's t = 1),
- * no memory cap, null stream.  NULL-safe. */
+ * no flags, no memory cap, null stream.  NULL-safe. */
 void idbf_opts_default(idbf_opts* o);
 
 /*
@@ -111,6 +114,11 @@ idbf_status idbf_construct(const idbf_phase* phase, const double* X, const doubl
 idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype,
                        void* stream);
 
+/* Grow the handle's apply workspace (hipMalloc) so that idbf_apply with up to
+ * nrhs right-hand sides of dtype allocates nothing.  Synchronizes the device
+ * if it allocates. */
+idbf_status idbf_reserve(idbf_handle h, int64_t nrhs, int32_t dtype);
+
 /* Free a handle and everything it owns.  NULL-safe.  Synchronizes the device. */
 idbf_status idbf_destroy(idbf_handle h);
 
@@ -122,17 +130,39 @@ typedef struct idbf_info {
   int32_t leaf, L, H, oversample;
   double tol;
   int64_t n_ids;          /* interpolative decompositions performed */
-  int64_t nnz_T;          /* complex entries of all T blocks */
-  int64_t nnz_S;          /* complex entries of the middle factor */
+  int64_t nnz_T;          /* complex entries of all T blocks (sum of k (c - k)) */
+  int64_t nnz_S;          /* complex entries of the middle factor (in use) */
   int64_t n_skel;         /* skeleton indices stored over all levels */
   int32_t rank_min, rank_max;
   int32_t cand_max, samples_max;
   int64_t device_bytes;   /* device memory held by the handle */
   double construct_ms;    /* host wall time of idbf_construct */
+  double id_flops;        /* FP64 flops of the IDs: sum 16 sum_{j<k} (s-j)(c-j) + 4 k^2 (c-k) */
+  int64_t sampled_entries;/* kernel entries sampled by the IDs: sum s c */
 } idbf_info;
 
 /* Summary of a handle (host *info). */
 idbf_status idbf_get_info(idbf_handle h, idbf_info* info);
+
+/* Per-kernel device time of a handle built with IDBF_FLAG_PROFILE: HIP events
+ * recorded around every launch of idbf_construct and idbf_apply on the stream
+ * the kernel runs on.  bytes / flops are the algorithmic work of those
+ * launches: factor entries streamed plus the vectors read or written once
+ * (apply), FP64 flops of the pivoted QR and solve (IDs). */
+typedef struct idbf_kernel_stat {
+  char name[24];
+  int32_t launches;
+  int32_t reserved;
+  double ms;      /* summed device time of the launches */
+  double bytes;   /* summed algorithmic bytes */
+  double flops;   /* summed algorithmic flops */
+} idbf_kernel_stat;
+
+/* Aggregate recorded launches by kernel name into out[0 .. *n) (host, at most
+ * max entries); reset != 0 discards the records afterwards.  Synchronizes
+ * with the recorded events.  IDBF_EINVAL if profiling is off. */
+idbf_status idbf_profile_read(idbf_handle h, idbf_kernel_stat* out, int32_t max, int32_t* n,
+                              int32_t reset);
 
 /*
  * Inspection of one level's IDs, for verification.  side IDBF_SIDE_U or
@@ -145,9 +175,10 @@ idbf_status idbf_get_info(idbf_handle h, idbf_info* info);
  *     skeleton), skel[n_skel] (global indices, ascending within each ID,
  *     IDs consecutive), T[2 * n_T] (complex128), T_off[n_ids] (entry offset
  *     of each ID's T).  T of an ID with rank k and r = cand_len - k redundant
- *     candidates is k x r; V IDs store it column-major (entry j*k + i), U IDs
- *     row-major (entry i*r + j); rows follow ascending skeletons, columns
- *     ascending redundant candidates.
+ *     candidates is k x r, stored from the even offset T_off[q]; V IDs store it
+ *     column-major (entry j*k + i), U IDs row-major (entry i*r + j); rows
+ *     follow ascending skeletons, columns ascending redundant candidates.
+ *     n_T counts the reserved entries (per-ID rank bounds, rounded even).
  */
 idbf_status idbf_batch_sizes(idbf_handle h, int32_t side, int32_t level, int64_t* n_ids,
                              int64_t* n_skel, int64_t* n_T);
@@ -159,8 +190,10 @@ idbf_status idbf_batch_export(idbf_handle h, int32_t side, int32_t level, int32_
  * Middle factor S (Section 2.4): for rows R and columns C' at depth
  * d = L-H+1, block b = (C'' * 2^d + R) * 2^(d-H) + j holds
  * K(skel of U_H ID (R, C''), skel of V_H ID (C', R >> (d-H))) with
- * C' = C'' * 2^(d-H) + j, stored column-major.  When H = 0 there is one
- * N x N block, K itself.  Host arrays: S[2 * n_entries], S_off[n_blocks].
+ * C' = C'' * 2^(d-H) + j, stored column-major from the even offset S_off[b].
+ * When H = 0 there is one N x N block, K itself.  n_entries counts the
+ * stored entries including the alignment padding.  Host arrays:
+ * S[2 * n_entries], S_off[n_blocks].
  */
 idbf_status idbf_middle_sizes(idbf_handle h, int64_t* n_blocks, int64_t* n_entries);
 idbf_status idbf_middle_export(idbf_handle h, double* S, int64_t* S_off);

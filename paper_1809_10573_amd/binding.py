@@ -27,8 +27,9 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ERANK", 5: "EU
 EXPORTED = [
     "idbf_opts_default", "idbf_construct", "idbf_apply", "idbf_destroy", "idbf_last_error",
     "idbf_get_info", "idbf_batch_sizes", "idbf_batch_export", "idbf_middle_sizes",
-    "idbf_middle_export", "idbf_sample", "idbf_id_batch",
+    "idbf_middle_export", "idbf_sample", "idbf_id_batch", "idbf_profile_read", "idbf_reserve",
 ]
+FLAG_PROFILE = 1
 
 
 class IdbfError(RuntimeError):
@@ -43,7 +44,7 @@ class Phase_t(C.Structure):
 
 
 class Opts_t(C.Structure):
-    _fields_ = [("kmax", C.c_int32), ("oversample", C.c_int32), ("reserved0", C.c_int32),
+    _fields_ = [("kmax", C.c_int32), ("oversample", C.c_int32), ("flags", C.c_int32),
                 ("reserved1", C.c_int32), ("mem_cap_bytes", C.c_uint64), ("stream", C.c_void_p)]
 
 
@@ -52,7 +53,13 @@ class Info_t(C.Structure):
                 ("oversample", C.c_int32), ("tol", C.c_double), ("n_ids", C.c_int64),
                 ("nnz_T", C.c_int64), ("nnz_S", C.c_int64), ("n_skel", C.c_int64),
                 ("rank_min", C.c_int32), ("rank_max", C.c_int32), ("cand_max", C.c_int32),
-                ("samples_max", C.c_int32), ("device_bytes", C.c_int64), ("construct_ms", C.c_double)]
+                ("samples_max", C.c_int32), ("device_bytes", C.c_int64), ("construct_ms", C.c_double),
+                ("id_flops", C.c_double), ("sampled_entries", C.c_int64)]
+
+
+class KernelStat_t(C.Structure):
+    _fields_ = [("name", C.c_char * 24), ("launches", C.c_int32), ("reserved", C.c_int32),
+                ("ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double)]
 
 
 _lib = None
@@ -83,6 +90,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_sample.argtypes = [P(Phase_t), VP, VP, VP, I64, VP, I64, VP, VP]
     lib.idbf_id_batch.argtypes = [P(Phase_t), VP, VP, I32, I64, VP, VP, VP, VP, VP, VP, D, I32, I32,
                                   VP, VP, VP, VP, VP]
+    lib.idbf_profile_read.argtypes = [VP, P(KernelStat_t), I32, P(I32), I32]
+    lib.idbf_reserve.argtypes = [VP, I64, I32]
     for name in EXPORTED:
         if name not in ("idbf_opts_default", "idbf_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -172,6 +181,10 @@ class Factorization:
         _check(load().idbf_apply(self._h, _ptr(x), _ptr(y), nrhs, dtype, _stream(stream)))
         return y
 
+    def reserve(self, nrhs: int, dtype: int = C64) -> None:
+        """Pre-allocate the apply workspace for up to nrhs right-hand sides."""
+        _check(load().idbf_reserve(self._h, int(nrhs), int(dtype)))
+
     def batch(self, side: int, level: int) -> Batch:
         lib = load()
         n, ns, nt = C.c_int64(), C.c_int64(), C.c_int64()
@@ -187,6 +200,15 @@ class Factorization:
                                      toff.ctypes.data))
         return Batch(rank, cand, mask, skel[:ns.value], T[:nt.value], toff)
 
+    def profile(self, reset: bool = True) -> dict:
+        """{kernel name: {launches, ms, bytes, flops}} since the last reset (IDBF_FLAG_PROFILE)."""
+        arr = (KernelStat_t * 64)()
+        n = C.c_int32()
+        _check(load().idbf_profile_read(self._h, arr, 64, C.byref(n), int(reset)))
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].ms,
+                                       "bytes": arr[i].bytes, "flops": arr[i].flops}
+                for i in range(n.value)}
+
     def middle(self) -> tuple[np.ndarray, np.ndarray]:
         lib = load()
         nb, ne = C.c_int64(), C.c_int64()
@@ -198,7 +220,8 @@ class Factorization:
 
 
 def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample: int = 1,
-              mem_cap_bytes: int = 0, device="cuda", stream=None) -> Factorization:
+              mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
+              stream=None) -> Factorization:
     """idbf_construct on device copies of X and Omega (float64, ascending)."""
     lib = load()
     Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
@@ -207,6 +230,7 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
     opts = Opts_t()
     lib.idbf_opts_default(C.byref(opts))
     opts.kmax, opts.oversample, opts.mem_cap_bytes = kmax, oversample, mem_cap_bytes
+    opts.flags = FLAG_PROFILE if profile else 0
     opts.stream = _stream(stream)
     ph = _phase(phase)
     h = C.c_void_p()

@@ -12,6 +12,8 @@
 // nrhs == 1: one wavefront per ID (unit), lane = candidate position.
 // nrhs > 1:  one workgroup per (ID, 64 right-hand sides); lanes over
 //            right-hand sides, so every load of z / w / x / y is coalesced.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace idbf {
@@ -21,64 +23,127 @@ namespace {
 constexpr int kIdsPerBlock = 4;  // wavefronts (IDs) per 256-thread workgroup
 
 // ---------------------------------------------------------------- 1 RHS
+// Each wavefront streams the factor block(s) of its ID (unit) with 16-byte
+// loads per lane, all issued before the first use, multiplies each entry by
+// the input it meets (from LDS) and writes the product to LDS; lanes then sum
+// the products of their output.  Block offsets are even, so every block
+// starts 16-byte aligned.
+
+template <typename C> struct Vec;
+template <> struct Vec<float2> { using type = float4; static constexpr int epl = 2; };
+template <> struct Vec<double2> { using type = double2; static constexpr int epl = 1; };
+
+template <typename C>
+__device__ __forceinline__ C vec_entry(const typename Vec<C>::type& v, int t);
+template <>
+__device__ __forceinline__ float2 vec_entry<float2>(const float4& v, int t) {
+  return t == 0 ? make_float2(v.x, v.y) : make_float2(v.z, v.w);
+}
+template <>
+__device__ __forceinline__ double2 vec_entry<double2>(const double2& v, int) { return v; }
+
+// Products P[e] = blk[e] * in[e / div] for e < n; NV vector loads per lane
+// cover the largest block (kSlot entries).
+template <typename C, int NV>
+__device__ __forceinline__ void stream_products(const C* blk, int n, int div, const C* in_lds, C* out_lds,
+                                                int lane) {
+  using V = typename Vec<C>::type;
+  constexpr int EPL = Vec<C>::epl;
+  const V* src = reinterpret_cast<const V*>(blk);
+  V buf[NV];
+  const int nv = (n + EPL - 1) / EPL;
+#pragma unroll
+  for (int m = 0; m < NV; ++m) {
+    const int v = lane + m * kWave;
+    if (m * kWave < nv && v < nv) buf[m] = src[v];
+  }
+  const float rdiv = 1.0f / (float)div;
+#pragma unroll
+  for (int m = 0; m < NV; ++m) {
+    const int v = lane + m * kWave;
+    if (m * kWave < nv && v < nv) {
+#pragma unroll
+      for (int t = 0; t < EPL; ++t) {
+        const int e = v * EPL + t;
+        if (e < n) {
+          const int j = (int)(((float)e + 0.5f) * rdiv);  // e / div, exact for e < 2^16
+          out_lds[e] = cfma(vec_entry<C>(buf[m], t), in_lds[j], czero(C{}));
+        }
+      }
+    }
+  }
+}
+
+template <typename C> constexpr int nv_for() { return kSlot * (int)sizeof(C) / (kWave * 16); }
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// V stage: z(ID) = u[skel] + T u[red]; T column-major (entry j*k + i).
+// Dynamic LDS: kIdsPerBlock * pmax products.
 template <typename C>
 __global__ __launch_bounds__(256) void apply_v1(StageArgs A) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   __shared__ C s_u[kIdsPerBlock][kWave];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t q = blockIdx.x * (int64_t)kIdsPerBlock + w;
-  const bool ok = q < A.n;
+  const int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + w;
+  if (q >= A.n) return;
+  C* s_p = reinterpret_cast<C*>(s_dyn) + (size_t)w * A.pmax;
   const C* in = static_cast<const C*>(A.in);
   C* out = static_cast<C*>(A.out);
-  const C* T = static_cast<const C*>(A.T);
-  int c = 0, k = 0, cb = 0;
-  uint64_t msk = 0;
-  if (ok) {
-    c = A.cand_len[q];
-    k = A.rank[q];
-    cb = A.cand_beg[q];
-    msk = A.mask[q];
-  }
+  const int c = A.cand_len[q], k = A.rank[q], cb = A.cand_beg[q];
+  const uint64_t msk = A.mask[q];
+  const int r = c - k;
   C u = czero(C{});
   if (lane < c) u = in[cb + lane];
   const int below = __popcll(msk & lanes_below(lane));
   const bool sk = (msk >> lane) & 1ull;
   if (lane < c && !sk) s_u[w][lane - below] = u;
-  __syncthreads();
+  wave_sync_lds();
+  stream_products<C, nv_for<C>()>(static_cast<const C*>(A.T) + A.T_off[q], k * r, k, s_u[w], s_p, lane);
+  wave_sync_lds();
   if (lane < c && sk) {
-    const int r = c - k;
-    const C* Tq = T + A.T_off[q] + below;
     C acc = u;
-    for (int j = 0; j < r; ++j) acc = cfma(Tq[(int64_t)j * k], s_u[w][j], acc);
+    for (int j = 0; j < r; ++j) acc = cadd(acc, s_p[j * k + below]);
     out[A.skel_off[q] + below] = acc;
   }
 }
 
+// U stage: one unit = the two IDs of one node with the two children of one
+// partner; they share the candidate segment, which the unit writes whole.
+// T row-major (entry i*r + j).
 template <typename C>
 __global__ __launch_bounds__(256) void apply_u1(StageArgs A) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   __shared__ C s_w[kIdsPerBlock][2][kMaxRank];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t unit = blockIdx.x * (int64_t)kIdsPerBlock + w;
-  const bool ok = unit < A.n;
+  const int64_t unit = blockIdx.x * (int64_t)(blockDim.x / kWave) + w;
+  if (unit >= A.n) return;
+  C* s_p = reinterpret_cast<C*>(s_dyn) + (size_t)w * 2 * A.pmax;
   const C* in = static_cast<const C*>(A.in);
   C* out = static_cast<C*>(A.out);
   const C* T = static_cast<const C*>(A.T);
-  int64_t qid[2] = {0, 0};
-  int kk[2] = {0, 0}, c = 0, cb = 0;
-  uint64_t mk[2] = {0, 0};
-  if (ok) {
-    const int64_t P = unit / A.nn, node = unit % A.nn;
-    qid[0] = 2 * P * A.nn + node;
-    qid[1] = qid[0] + A.nn;
-    c = A.cand_len[qid[0]];
-    cb = A.cand_beg[qid[0]];
+  const int64_t P = unit / A.nn, node = unit % A.nn;
+  const int64_t qid[2] = {2 * P * A.nn + node, 2 * P * A.nn + node + A.nn};
+  const int c = A.cand_len[qid[0]], cb = A.cand_beg[qid[0]];
+  int kk[2];
+  uint64_t mk[2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      kk[h] = A.rank[qid[h]];
-      mk[h] = A.mask[qid[h]];
-      if (lane < kk[h]) s_w[w][h][lane] = in[A.skel_off[qid[h]] + lane];
-    }
+  for (int h = 0; h < 2; ++h) {
+    kk[h] = A.rank[qid[h]];
+    mk[h] = A.mask[qid[h]];
+    if (lane < kk[h]) s_w[w][h][lane] = in[A.skel_off[qid[h]] + lane];
   }
-  __syncthreads();
+  wave_sync_lds();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int r = c - kk[h];
+    stream_products<C, nv_for<C>()>(T + A.T_off[qid[h]], kk[h] * r, r, s_w[w][h], s_p + h * A.pmax, lane);
+  }
+  wave_sync_lds();
   if (lane < c) {
     C acc = czero(C{});
 #pragma unroll
@@ -87,36 +152,86 @@ __global__ __launch_bounds__(256) void apply_u1(StageArgs A) {
       if ((mk[h] >> lane) & 1ull) {
         acc = cadd(acc, s_w[w][h][below]);
       } else {
-        const int k = kk[h], r = c - k, jr = lane - below;
-        const C* Tq = T + A.T_off[qid[h]] + jr;
-        for (int i = 0; i < k; ++i) acc = cfma(Tq[(int64_t)i * r], s_w[w][h][i], acc);
+        const int r = c - kk[h], jr = lane - below;
+        const C* p = s_p + h * A.pmax + jr;
+        for (int i = 0; i < kk[h]; ++i) acc = cadd(acc, p[i * r]);
       }
     }
     out[cb + lane] = acc;
   }
 }
 
+// Middle factor, one U_H ID per wavefront: the 2^(d-H) blocks S(R, C') are
+// consecutive, column-major, rows of the output.
 template <typename C>
 __global__ __launch_bounds__(256) void apply_s1(StageArgs A) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
+  __shared__ C s_z[kIdsPerBlock][4][kMaxRank];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t q = blockIdx.x * (int64_t)kIdsPerBlock + w;
+  const int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + w;
+  if (q >= A.n) return;
+  C* s_p = reinterpret_cast<C*>(s_dyn) + (size_t)w * A.nsub * A.pmax;
+  const C* in = static_cast<const C*>(A.in);
+  C* out = static_cast<C*>(A.out);
+  const C* S = static_cast<const C*>(A.T);
+  const int64_t b0 = q * A.nsub;
+  const int rl = A.rlen[b0], rb = A.rbeg[b0];
+  for (int jb = 0; jb < A.nsub; ++jb)
+    if (lane < A.clen[b0 + jb]) s_z[w][jb][lane] = in[A.cbeg[b0 + jb] + lane];
+  wave_sync_lds();
+  for (int jb = 0; jb < A.nsub; ++jb)
+    stream_products<C, nv_for<C>()>(S + A.T_off[b0 + jb], rl * A.clen[b0 + jb], rl, s_z[w][jb],
+                                    s_p + jb * A.pmax, lane);
+  wave_sync_lds();
+  if (lane < rl) {
+    C acc = czero(C{});
+    for (int jb = 0; jb < A.nsub; ++jb) {
+      const C* p = s_p + jb * A.pmax + lane;
+      for (int col = 0, cl = A.clen[b0 + jb]; col < cl; ++col) acc = cadd(acc, p[col * rl]);
+    }
+    out[rb + lane] = acc;
+  }
+}
+
+// Middle factor when its blocks are too large to stage: lanes over output rows,
+// eight independent column loads in flight per lane.
+template <typename C>
+__global__ __launch_bounds__(256) void apply_s1_direct(StageArgs A) {
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + w;
   if (q >= A.n) return;
   const C* in = static_cast<const C*>(A.in);
   C* out = static_cast<C*>(A.out);
   const C* S = static_cast<const C*>(A.T);
   const int64_t b0 = q * A.nsub;
   const int rl = A.rlen[b0], rb = A.rbeg[b0];
-  for (int i0 = 0; i0 < rl; i0 += kWave) {
-    const int i = i0 + lane;
-    if (i >= rl) break;
+  if (lane >= rl) return;
+  C acc = czero(C{});
+  for (int jb = 0; jb < A.nsub; ++jb) {
+    const int64_t b = b0 + jb;
+    const int cl = A.clen[b], cbg = A.cbeg[b];
+    const C* Sb = S + A.T_off[b] + lane;
+#pragma unroll 8
+    for (int col = 0; col < cl; ++col) acc = cfma(Sb[(int64_t)col * rl], in[cbg + col], acc);
+  }
+  out[rb + lane] = acc;
+}
+
+// The whole matrix when the tree has no levels (N <= 2 leaf): lanes over rows.
+template <typename C>
+__global__ __launch_bounds__(256) void apply_dense(StageArgs A) {
+  const C* in = static_cast<const C*>(A.in);
+  C* out = static_cast<C*>(A.out);
+  const C* S = static_cast<const C*>(A.T);
+  const int rl = A.rlen[0], cl = A.clen[0];
+  const int64_t nr = A.nrhs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)rl * nr;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / nr);
+    const int64_t rhs = e % nr;
     C acc = czero(C{});
-    for (int jb = 0; jb < A.nsub; ++jb) {
-      const int64_t b = b0 + jb;
-      const int cl = A.clen[b], cbg = A.cbeg[b];
-      const C* Sb = S + A.T_off[b] + i;
-      for (int col = 0; col < cl; ++col) acc = cfma(Sb[(int64_t)col * rl], in[cbg + col], acc);
-    }
-    out[rb + i] = acc;
+    for (int col = 0; col < cl; ++col) acc = cfma(S[(int64_t)col * rl + i], in[(int64_t)col * nr + rhs], acc);
+    out[(int64_t)i * nr + rhs] = acc;
   }
 }
 
@@ -207,7 +322,12 @@ __global__ __launch_bounds__(256) void apply_sn(StageArgs A) {
   }
 }
 
-inline unsigned grid1(int64_t n) { return (unsigned)((n + kIdsPerBlock - 1) / kIdsPerBlock); }
+inline unsigned grid1(int64_t n, int ipb = kIdsPerBlock) { return (unsigned)((n + ipb - 1) / ipb); }
+constexpr size_t kDynLds = size_t(48) << 10;  // dynamic LDS budget per workgroup
+// wavefronts (IDs) per workgroup so that per_id bytes of LDS each fit the budget
+inline int ids_per_block(size_t per_id) {
+  return (int)std::max<size_t>(1, std::min<size_t>(kIdsPerBlock, kDynLds / std::max<size_t>(per_id, 1)));
+}
 inline dim3 gridn(int64_t n, int64_t nrhs) {
   return dim3((unsigned)n, (unsigned)((nrhs + kRhsChunk - 1) / kRhsChunk));
 }
@@ -217,8 +337,10 @@ inline dim3 gridn(int64_t n, int64_t nrhs) {
 hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st) {
   if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
   if (a.nrhs == 1) {
-    if (fp64) hipLaunchKernelGGL(apply_v1<double2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(apply_v1<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
+    const size_t per = (size_t)a.pmax * (fp64 ? 16 : 8);
+    const int ipb = ids_per_block(per);
+    if (fp64) hipLaunchKernelGGL(apply_v1<double2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
+    else hipLaunchKernelGGL(apply_v1<float2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
   } else {
     if (fp64) hipLaunchKernelGGL(apply_vn<double2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);
     else hipLaunchKernelGGL(apply_vn<float2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);
@@ -229,8 +351,10 @@ hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st) {
 hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st) {
   if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
   if (a.nrhs == 1) {
-    if (fp64) hipLaunchKernelGGL(apply_u1<double2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(apply_u1<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
+    const size_t per = (size_t)2 * a.pmax * (fp64 ? 16 : 8);
+    const int ipb = ids_per_block(per);
+    if (fp64) hipLaunchKernelGGL(apply_u1<double2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
+    else hipLaunchKernelGGL(apply_u1<float2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
   } else {
     if (fp64) hipLaunchKernelGGL(apply_un<double2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);
     else hipLaunchKernelGGL(apply_un<float2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);
@@ -240,9 +364,20 @@ hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st) {
 
 hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st) {
   if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
-  if (a.nrhs == 1) {
-    if (fp64) hipLaunchKernelGGL(apply_s1<double2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(apply_s1<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
+  if (a.dense) {
+    const unsigned blocks = (unsigned)std::min<int64_t>((a.rlen_host * a.nrhs + 255) / 256, 65535);
+    if (fp64) hipLaunchKernelGGL(apply_dense<double2>, dim3(blocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(apply_dense<float2>, dim3(blocks), dim3(256), 0, st, a);
+  } else if (a.nrhs == 1) {
+    const size_t per = (size_t)a.nsub * a.pmax * (fp64 ? 16 : 8);
+    if (per <= kDynLds && a.nsub <= 4) {
+      const int ipb = ids_per_block(per);
+      if (fp64) hipLaunchKernelGGL(apply_s1<double2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
+      else hipLaunchKernelGGL(apply_s1<float2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
+    } else {
+      if (fp64) hipLaunchKernelGGL(apply_s1_direct<double2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
+      else hipLaunchKernelGGL(apply_s1_direct<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
+    }
   } else {
     if (fp64) hipLaunchKernelGGL(apply_sn<double2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);
     else hipLaunchKernelGGL(apply_sn<float2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);

@@ -92,14 +92,73 @@ struct Batch {
   int64_t n = 0;
   int32_t *cand_beg = nullptr, *cand_len = nullptr, *allow_beg = nullptr, *allow_len = nullptr;
   int32_t *samples = nullptr, *rank = nullptr, *skel_off = nullptr, *skel_idx = nullptr;
+  double* skel_coord = nullptr;  // X (U side) or Omega (V side) of each skeleton index
   int64_t *t_bound = nullptr, *T_off = nullptr;
   uint64_t* mask = nullptr;
   double2* T128 = nullptr;
   float2* T64 = nullptr;
   const int32_t* cand_arr = nullptr;
   const int32_t* allow_arr = nullptr;
-  int64_t n_skel = 0, n_T = 0;
+  const double* cand_coord = nullptr;
+  const double* allow_coord = nullptr;
+  int64_t n_skel = 0, n_T = 0;   // n_T: reserved T entries (per-ID bounds, rounded even)
+  int64_t nnz_T = 0;              // T entries in use: sum k (c - k)
+  int64_t tb_max = 0;             // largest per-ID T reservation
+  double flops = 0.0;             // FP64 flops of the batch's IDs
+  int64_t sampled = 0;            // kernel entries sampled
   int rank_min = 0, rank_max = 0, cand_max = 0, s_max = 0;
+};
+
+// HIP events around kernel launches, aggregated by name on request.
+struct Profiler {
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  bool on = false;
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+
+  hipEvent_t event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return e;
+  }
+  // returns a record index, or -1 when profiling is off
+  int begin(const char* name, hipStream_t st) {
+    if (!on) return -1;
+    Rec r{name, event(), event(), 0.0, 0.0};
+    if (!r.a || !r.b) return -1;
+    (void)hipEventRecord(r.a, st);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void end(int id, hipStream_t st, double bytes = 0.0, double flops = 0.0) {
+    if (id < 0) return;
+    (void)hipEventRecord(recs[id].b, st);
+    recs[id].bytes = bytes;
+    recs[id].flops = flops;
+  }
+  void clear() {
+    for (auto& r : recs) {
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    recs.clear();
+  }
+  ~Profiler() {
+    clear();
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
 };
 
 PhaseDev to_dev(const idbf_phase& p) { return PhaseDev{p.kind, p.c0, p.a, p.freq, p.cdiv}; }
@@ -145,10 +204,11 @@ struct idbf_handle_s {
   Arena arena;
   int32_t* iota = nullptr;
   int32_t* scratch = nullptr;  // skeleton lists before compaction (64 per ID)
+  int32_t* samp_pos = nullptr; // sample positions of the current level (128 per ID)
   int64_t* stats = nullptr;    // 8 int64 read back after each scan
   int32_t* status = nullptr;
   std::vector<Batch> U, V;
-  int64_t nblk = 0, nnz_S = 0;
+  int64_t nblk = 0, nnz_S = 0, nnz_S_res = 0, sblk_max = 0;
   int32_t *s_rbeg = nullptr, *s_rlen = nullptr, *s_cbeg = nullptr, *s_clen = nullptr;
   int64_t *s_size = nullptr, *S_off = nullptr;
   double2* S128 = nullptr;
@@ -158,6 +218,7 @@ struct idbf_handle_s {
   int64_t max_skel = 0;
   double construct_ms = 0.0;
   hipStream_t stream = nullptr;
+  Profiler prof;
 
   ~idbf_handle_s() {
     if (ws) (void)hipFree(ws);
@@ -208,6 +269,9 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   }
   b.cand_arr = prev ? prev->skel_idx : h->iota;
   b.allow_arr = other ? other->skel_idx : h->iota;
+  // on the first level the index arrays are the identity, so coordinates are X / Omega
+  b.cand_coord = prev ? prev->skel_coord : (side == IDBF_SIDE_U ? X : Om);
+  b.allow_coord = other ? other->skel_coord : (side == IDBF_SIDE_U ? Om : X);
 
   DescArgs d{};
   d.side = side;
@@ -226,12 +290,15 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   d.allow_len = b.allow_len;
   d.t_bound = b.t_bound;
   d.samples = b.samples;
+  int pr = h->prof.begin("level_desc", h->stream);
   TRYHIP(launch_desc(d, h->stream));
   TRYHIP(launch_scan_i64(b.t_bound, n, b.T_off, b.cand_len, h->stats, h->stream));
   TRYHIP(launch_scan_i32(b.samples, n, b.skel_off, nullptr, h->stats + 4, h->stream));
+  h->prof.end(pr, h->stream);
   int64_t st[8];
   TRY(read_stats(h, st, 8));
   b.n_T = st[0];
+  b.tb_max = st[1];
   b.cand_max = (int)st[3];
   b.s_max = (int)st[5];
   if (b.cand_max > kMaxCand) {
@@ -244,7 +311,6 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
               side == IDBF_SIDE_U ? 'U' : 'V', b.s_max, kMaxSamples);
     return IDBF_EUNSUPPORTED;
   }
-  const int waves = std::max(1, std::min(kMaxWaves, (b.s_max + kRowsPerWave - 1) / kRowsPerWave));
   TRY(A.get(std::max<int64_t>(b.n_T, 1), &b.T128));
   TRY(A.get(std::max<int64_t>(b.n_T, 1), &b.T64));
 
@@ -257,12 +323,16 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   ia.cand_idx = b.cand_arr;
   ia.cand_beg = b.cand_beg;
   ia.cand_len = b.cand_len;
+  ia.cand_coord = b.cand_coord;
   ia.allow_idx = b.allow_arr;
   ia.allow_beg = b.allow_beg;
   ia.allow_len = b.allow_len;
+  ia.allow_coord = b.allow_coord;
   ia.tol = h->tol;
   ia.kmax = h->kmax;
   ia.oversample = h->oversample;
+  ia.s_max = b.s_max;
+  ia.samp_pos = h->samp_pos;
   ia.rank = b.rank;
   ia.mask = b.mask;
   ia.skel_out = h->scratch;
@@ -270,11 +340,25 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   ia.T64 = b.T64;
   ia.T_off = b.T_off;
   ia.status = h->status;
-  TRYHIP(launch_id_batch(ia, waves, h->stream));
+  pr = h->prof.begin("id_select", h->stream);
+  TRYHIP(launch_select(ia, h->stream));
+  h->prof.end(pr, h->stream);
+  const int pq = h->prof.begin("id_qr", h->stream);
+  TRYHIP(launch_qr(ia, h->stream));
+  h->prof.end(pq, h->stream);
+  pr = h->prof.begin("level_scan", h->stream);
+  TRYHIP(hipMemsetAsync(h->stats + 4, 0, 3 * sizeof(int64_t), h->stream));
+  TRYHIP(launch_id_work(b.rank, b.cand_len, b.samples, n, reinterpret_cast<unsigned long long*>(h->stats + 4),
+                        h->stream));
   TRYHIP(launch_scan_i32(b.rank, n, b.skel_off, nullptr, h->stats, h->stream));
-  TRYHIP(hipMemcpyAsync(h->stats + 6, h->status, sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+  TRYHIP(hipMemcpyAsync(h->stats + 7, h->status, sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+  h->prof.end(pr, h->stream);
   TRY(read_stats(h, st, 8));
-  const int32_t status = (int32_t)(st[6] & 0xffffffff);
+  b.flops = (double)(unsigned long long)st[4];
+  b.nnz_T = st[5];
+  b.sampled = st[6];
+  if (pq >= 0) h->prof.recs[pq].flops = b.flops;
+  const int32_t status = (int32_t)(st[7] & 0xffffffff);
   if (status & kErrRank) {
     set_error("level %d %c: an ID needs rank > %d at tol %g", t, side == IDBF_SIDE_U ? 'U' : 'V', kMaxRank,
               h->tol);
@@ -288,7 +372,11 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   b.rank_max = (int)st[1];
   b.rank_min = (int)st[2];
   TRY(A.get(std::max<int64_t>(b.n_skel, 1), &b.skel_idx));
-  TRYHIP(launch_compact_skel(h->scratch, b.rank, b.skel_off, n, b.skel_idx, h->stream));
+  TRY(A.get(std::max<int64_t>(b.n_skel, 1), &b.skel_coord));
+  pr = h->prof.begin("level_compact", h->stream);
+  TRYHIP(launch_compact_skel(h->scratch, b.rank, b.skel_off, n, side == IDBF_SIDE_U ? X : Om, b.skel_idx,
+                             b.skel_coord, h->stream));
+  h->prof.end(pr, h->stream);
   h->max_skel = std::max(h->max_skel, b.n_skel);
   if (side == IDBF_SIDE_U) h->U.push_back(b); else h->V.push_back(b);
   return IDBF_OK;
@@ -307,14 +395,16 @@ idbf_status build_middle(idbf_handle_s* h, const double* X, const double* Om) {
     TRY(A.get(1, &h->s_clen));
     TRY(A.get(2, &h->S_off));
     const int32_t zero = 0, nn = (int32_t)h->N;
-    const int64_t offs[2] = {0, h->N * h->N};
+    h->nnz_S = h->N * h->N;
+    h->nnz_S_res = (h->nnz_S + 1) & ~int64_t(1);
+    h->sblk_max = h->nnz_S_res;
+    const int64_t offs[2] = {0, h->nnz_S_res};
     TRYHIP(hipMemcpyAsync(h->s_rbeg, &zero, 4, hipMemcpyHostToDevice, h->stream));
     TRYHIP(hipMemcpyAsync(h->s_cbeg, &zero, 4, hipMemcpyHostToDevice, h->stream));
     TRYHIP(hipMemcpyAsync(h->s_rlen, &nn, 4, hipMemcpyHostToDevice, h->stream));
     TRYHIP(hipMemcpyAsync(h->s_clen, &nn, 4, hipMemcpyHostToDevice, h->stream));
     TRYHIP(hipMemcpyAsync(h->S_off, offs, 16, hipMemcpyHostToDevice, h->stream));
     TRYHIP(hipStreamSynchronize(h->stream));
-    h->nnz_S = h->N * h->N;
     row_idx = col_idx = h->iota;
   } else {
     const int d = h->L - h->H + 1;
@@ -336,15 +426,19 @@ idbf_status build_middle(idbf_handle_s* h, const double* X, const double* Om) {
     m.cbeg = h->s_cbeg;
     m.clen = h->s_clen;
     m.size = h->s_size;
+    m.nnz = reinterpret_cast<unsigned long long*>(h->stats + 4);
+    TRYHIP(hipMemsetAsync(h->stats + 4, 0, sizeof(int64_t), h->stream));
     TRYHIP(launch_middle_desc(m, h->stream));
     TRYHIP(launch_scan_i64(h->s_size, h->nblk, h->S_off, nullptr, h->stats, h->stream));
-    TRY(read_stats(h, st, 4));
-    h->nnz_S = st[0];
+    TRY(read_stats(h, st, 5));
+    h->nnz_S_res = st[0];
+    h->sblk_max = st[1];
+    h->nnz_S = st[4];
     row_idx = h->U[h->H - 1].skel_idx;
     col_idx = h->V[h->H - 1].skel_idx;
   }
-  TRY(A.get(std::max<int64_t>(h->nnz_S, 1), &h->S128));
-  TRY(A.get(std::max<int64_t>(h->nnz_S, 1), &h->S64));
+  TRY(A.get(std::max<int64_t>(h->nnz_S_res, 1), &h->S128));
+  TRY(A.get(std::max<int64_t>(h->nnz_S_res, 1), &h->S64));
   SampleBlocksArgs sb{};
   sb.ph = h->ph;
   sb.X = X;
@@ -359,7 +453,9 @@ idbf_status build_middle(idbf_handle_s* h, const double* X, const double* Om) {
   sb.off = h->S_off;
   sb.out128 = h->S128;
   sb.out64 = h->S64;
+  const int pr = h->prof.begin("middle_sample", h->stream);
   TRYHIP(launch_sample_blocks(sb, h->stream));
+  h->prof.end(pr, h->stream);
   return IDBF_OK;
 }
 
@@ -387,13 +483,35 @@ idbf_status construct_impl(idbf_handle_s* h, const double* X, const double* Om) 
   TRYHIP(hipMemsetAsync(h->status, 0, sizeof(int32_t), h->stream));
   TRY(A.get(h->N, &h->iota));
   TRYHIP(launch_iota(h->iota, h->N, h->stream));
-  if (h->H > 0) TRY(A.get((int64_t(2) << h->L) * kMaxCand, &h->scratch));
+  if (h->H > 0) {
+    TRY(A.get((int64_t(2) << h->L) * kMaxCand, &h->scratch));
+    TRY(A.get((int64_t(2) << h->L) * kMaxSamples, &h->samp_pos));
+  }
   for (int t = 1; t <= h->H; ++t) {
     TRY(run_batch(h, X, Om, IDBF_SIDE_U, t));
     TRY(run_batch(h, X, Om, IDBF_SIDE_V, t));
   }
   TRY(build_middle(h, X, Om));
   TRYHIP(hipStreamSynchronize(h->stream));
+  return IDBF_OK;
+}
+
+idbf_status grow_workspace(idbf_handle_s* h, size_t bytes, hipStream_t st) {
+  if (h->H == 0 || bytes <= h->ws_bytes) return IDBF_OK;
+  if (h->ws) {
+    IDBF_HIP_CHECK(hipStreamSynchronize(st));
+    IDBF_HIP_CHECK(hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&h->ws, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    h->ws = nullptr;
+    set_error("apply workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+    return IDBF_ENOMEM;
+  }
+  h->ws_bytes = bytes;
   return IDBF_OK;
 }
 
@@ -466,6 +584,7 @@ idbf_status idbf_construct(const idbf_phase* phase, const double* X, const doubl
   h->arena.chunk_min = std::max<size_t>(size_t(64) << 20, size_t(N) * 2048);
   if (o.mem_cap_bytes) h->arena.chunk_min = std::min<size_t>(h->arena.chunk_min, o.mem_cap_bytes);
   h->stream = static_cast<hipStream_t>(o.stream);
+  h->prof.on = (o.flags & IDBF_FLAG_PROFILE) != 0;
   idbf_status s = construct_impl(h.get(), X, Omega);
   if (s != IDBF_OK) {
     (void)hipStreamSynchronize(h->stream);
@@ -502,22 +621,7 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
   const size_t elem = fp64 ? 16 : 8;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t half = size_t(h->max_skel) * size_t(nrhs) * elem;
-  if (h->H > 0 && 2 * half > h->ws_bytes) {
-    if (h->ws) {
-      IDBF_HIP_CHECK(hipStreamSynchronize(st));
-      IDBF_HIP_CHECK(hipFree(h->ws));
-      h->ws = nullptr;
-      h->ws_bytes = 0;
-    }
-    hipError_t e = hipMalloc(&h->ws, 2 * half);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      h->ws = nullptr;
-      set_error("apply workspace of %zu bytes: %s", 2 * half, hipGetErrorString(e));
-      return IDBF_ENOMEM;
-    }
-    h->ws_bytes = 2 * half;
-  }
+  TRY(grow_workspace(h, 2 * half, st));
   char* buf[2] = {static_cast<char*>(h->ws), static_cast<char*>(h->ws) + half};
   int cur = 0;
   const void* in = x;
@@ -533,9 +637,13 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     a.mask = b.mask;
     a.T_off = b.T_off;
     a.T = fp64 ? (const void*)b.T128 : (const void*)b.T64;
+    a.pmax = (int)b.tb_max;
     a.in = in;
     a.out = buf[cur];
+    const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
+    const int pr = h->prof.begin(nrhs == 1 ? "apply1_v" : "applyn_v", st);
     IDBF_HIP_CHECK(launch_apply_v(a, fp64, st));
+    h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T) * nrhs);
     in = buf[cur];
     cur ^= 1;
   }
@@ -550,9 +658,16 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     a.clen = h->s_clen;
     a.T_off = h->S_off;
     a.T = fp64 ? (const void*)h->S128 : (const void*)h->S64;
+    a.pmax = (int)h->sblk_max;
+    a.dense = (h->H == 0);
+    a.rlen_host = h->N;
     a.in = in;
     a.out = (h->H == 0) ? y : buf[cur];
+    double bytes = double(h->nnz_S) * elem;
+    if (h->H == 0) bytes += 2.0 * double(h->N) * nrhs * elem;
+    const int pr = h->prof.begin(nrhs == 1 ? "apply1_s" : "applyn_s", st);
     IDBF_HIP_CHECK(launch_apply_s(a, fp64, st));
+    h->prof.end(pr, st, bytes, 8.0 * double(h->nnz_S) * nrhs);
     in = a.out;
     cur ^= 1;
   }
@@ -569,13 +684,27 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     a.mask = b.mask;
     a.T_off = b.T_off;
     a.T = fp64 ? (const void*)b.T128 : (const void*)b.T64;
+    a.pmax = (int)b.tb_max;
     a.in = in;
     a.out = (t == 1) ? y : buf[cur];
+    const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
+    const int pr = h->prof.begin(nrhs == 1 ? "apply1_u" : "applyn_u", st);
     IDBF_HIP_CHECK(launch_apply_u(a, fp64, st));
+    h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T) * nrhs);
     in = a.out;
     cur ^= 1;
   }
   return IDBF_OK;
+}
+
+idbf_status idbf_reserve(idbf_handle h, int64_t nrhs, int32_t dtype) {
+  g_err[0] = 0;
+  if (!h || nrhs < 0 || (dtype != IDBF_C128 && dtype != IDBF_C64)) {
+    set_error("reserve: invalid handle, nrhs or dtype");
+    return IDBF_EINVAL;
+  }
+  const size_t elem = dtype == IDBF_C128 ? 16 : 8;
+  return grow_workspace(h, 2 * size_t(h->max_skel) * size_t(nrhs) * elem, h->stream);
 }
 
 idbf_status idbf_get_info(idbf_handle h, idbf_info* info) {
@@ -595,7 +724,9 @@ idbf_status idbf_get_info(idbf_handle h, idbf_info* info) {
   for (const auto* side : {&h->U, &h->V}) {
     for (const Batch& b : *side) {
       info->n_ids += b.n;
-      info->nnz_T += b.n_T;
+      info->nnz_T += b.nnz_T;
+      info->id_flops += b.flops;
+      info->sampled_entries += b.sampled;
       info->n_skel += b.n_skel;
       info->rank_min = std::min(info->rank_min, b.rank_min);
       info->rank_max = std::max(info->rank_max, b.rank_max);
@@ -606,6 +737,40 @@ idbf_status idbf_get_info(idbf_handle h, idbf_info* info) {
   if (info->n_ids == 0) info->rank_min = 0;
   info->device_bytes = (int64_t)(h->arena.total + h->ws_bytes);
   info->construct_ms = h->construct_ms;
+  return IDBF_OK;
+}
+
+idbf_status idbf_profile_read(idbf_handle h, idbf_kernel_stat* out, int32_t max, int32_t* n, int32_t reset) {
+  if (!h || !n || max < 0 || (max > 0 && !out)) {
+    set_error("profile_read: handle, n and out must be valid");
+    return IDBF_EINVAL;
+  }
+  if (!h->prof.on) {
+    set_error("profiling is off for this handle (construct with IDBF_FLAG_PROFILE)");
+    return IDBF_EINVAL;
+  }
+  std::vector<idbf_kernel_stat> agg;
+  for (auto& r : h->prof.recs) {
+    IDBF_HIP_CHECK(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    IDBF_HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
+    idbf_kernel_stat* e = nullptr;
+    for (auto& x : agg)
+      if (std::strncmp(x.name, r.name, sizeof x.name) == 0) e = &x;
+    if (!e) {
+      agg.push_back(idbf_kernel_stat{});
+      e = &agg.back();
+      std::snprintf(e->name, sizeof e->name, "%s", r.name);
+    }
+    e->launches += 1;
+    e->ms += ms;
+    e->bytes += r.bytes;
+    e->flops += r.flops;
+  }
+  const int m = std::min<int>(max, (int)agg.size());
+  for (int i = 0; i < m; ++i) out[i] = agg[i];
+  *n = m;
+  if (reset) h->prof.clear();
   return IDBF_OK;
 }
 
@@ -653,7 +818,7 @@ idbf_status idbf_middle_sizes(idbf_handle h, int64_t* n_blocks, int64_t* n_entri
     return IDBF_EINVAL;
   }
   if (n_blocks) *n_blocks = h->nblk;
-  if (n_entries) *n_entries = h->nnz_S;
+  if (n_entries) *n_entries = h->nnz_S_res;
   return IDBF_OK;
 }
 
@@ -663,7 +828,7 @@ idbf_status idbf_middle_export(idbf_handle h, double* S, int64_t* S_off) {
     return IDBF_EINVAL;
   }
   IDBF_HIP_CHECK(hipDeviceSynchronize());
-  if (S) IDBF_HIP_CHECK(hipMemcpy(S, h->S128, h->nnz_S * 16, hipMemcpyDeviceToHost));
+  if (S) IDBF_HIP_CHECK(hipMemcpy(S, h->S128, h->nnz_S_res * 16, hipMemcpyDeviceToHost));
   if (S_off) IDBF_HIP_CHECK(hipMemcpy(S_off, h->S_off, h->nblk * 8, hipMemcpyDeviceToHost));
   return IDBF_OK;
 }
@@ -726,7 +891,14 @@ idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double
     return IDBF_EUNSUPPORTED;
   }
   int32_t* status = nullptr;
+  int32_t* samp_pos = nullptr;
   IDBF_HIP_CHECK(hipMalloc(&status, sizeof(int32_t)));
+  if (hipMalloc(&samp_pos, size_t(n_ids) * kMaxSamples * sizeof(int32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(status);
+    set_error("id_batch: no memory for %lld sample lists", (long long)n_ids);
+    return IDBF_ENOMEM;
+  }
   IDBF_HIP_CHECK(hipMemsetAsync(status, 0, sizeof(int32_t), st));
   IdArgs ia{};
   ia.ph = to_dev(*phase);
@@ -743,6 +915,8 @@ idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double
   ia.tol = tol;
   ia.kmax = kmax;
   ia.oversample = oversample;
+  ia.s_max = smax;
+  ia.samp_pos = samp_pos;
   ia.rank = rank;
   ia.mask = mask;
   ia.skel_out = skel;
@@ -750,12 +924,12 @@ idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double
   ia.T64 = nullptr;
   ia.T_off = nullptr;
   ia.status = status;
-  const int waves = std::max(1, std::min(kMaxWaves, (smax + kRowsPerWave - 1) / kRowsPerWave));
-  hipError_t e = launch_id_batch(ia, waves, st);
+  hipError_t e = launch_id_batch(ia, st);
   int32_t flag = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&flag, status, sizeof flag, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(status);
+  (void)hipFree(samp_pos);
   if (e != hipSuccess) {
     set_error("id_batch: %s", hipGetErrorString(e));
     return IDBF_EHIP;

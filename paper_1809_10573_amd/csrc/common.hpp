@@ -12,9 +12,7 @@ namespace idbf {
 
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kMaxCand = 64;     // candidates per ID: one lane each
-constexpr int kRowsPerWave = 32; // sampled rows held in registers per wave
-constexpr int kMaxWaves = 4;     // waves cooperating on one ID
-constexpr int kMaxSamples = kRowsPerWave * kMaxWaves;
+constexpr int kMaxSamples = 128; // sampled rows per ID
 constexpr int kMaxRank = 32;     // rank rows live in wave 0's registers
 constexpr int kSlot = 1024;      // T entries per ID in slot layout (max k (c - k))
 constexpr double kPivotTie = 1e-8;

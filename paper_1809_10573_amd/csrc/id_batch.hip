@@ -1,26 +1,33 @@
 // Batched linear-scaling interpolative decomposition (Section 2.1, Lemma 2.1,
-// eqs. pivotedQR2, acc, R2) on gfx950, in FP64.
+// eqs. pivotedQR2, acc, R2) on gfx950, in FP64.  Two kernels:
 //
-// One ID per workgroup of W wavefronts.  Lane l owns candidate l (a column of
-// the sampled matrix B = K(samples, cand) for a column ID, or of
-// B = K(cand, samples)^T for a row ID); wave w holds sampled rows
-// [32 w, 32 w + 32) of every column in registers, so the Householder sweep,
-// column norms and dot products are lane-local and only the per-step pivot
-// vector goes through LDS.  Steps of the sweep:
-//   1. Mock-Chebyshev selection of s = min(t c, |allowed|) allowed points
-//      (targets in parallel; a sequential "nearest unused" pass only when two
-//      targets share a nearest point).
-//   2. Entry sampling in FP64 with exact phase reduction.
-//   3. Column-pivoted Householder QR stopped at the eps-rank: before step j,
-//      residual norms are recomputed, M = max; stop when M <= eps |R_00|; the
-//      pivot is the smallest candidate index with norm >= (1 - 1e-8) M.
-//   4. T = R11^{-1} R12 by back-substitution (wave 0; R11 entries read from
-//      the pivot lanes' registers), rows permuted to ascending skeletons.
+// select_kernel -- Mock-Chebyshev sample selection, one wavefront per ID.
+//   Targets are searched in parallel (one lane per target) by an
+//   interpolation-then-bisection search over the sorted allowed coordinates;
+//   the sequential "nearest unused point" rule runs only for IDs where two
+//   targets share a nearest point (otherwise it gives the same picks).
+//
+// id_kernel -- sampling + pivoted QR + interpolation solve, one ID per
+//   workgroup of W wavefronts.  Lane l owns candidate l (a column of the
+//   sampled matrix B = K(samples, cand) for a column ID, or of
+//   B = K(cand, samples)^T for a row ID); wave w holds sampled rows
+//   [16 w, 16 w + 16) of every column in registers, so the Householder sweep,
+//   column norms and dot products are lane-local.  Per step: residual norms
+//   are recomputed; M = max (DPP reduction); stop when M <= eps |R_00|; the
+//   pivot is the smallest candidate index with norm >= (1 - 1e-8) M (ballot);
+//   the pivot column's Householder vector goes through LDS.  Then
+//   T = R11^{-1} R12 by back-substitution in registers, one redundant
+//   candidate per lane, rows permuted to ascending skeletons.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace idbf {
 
 namespace {
+
+constexpr int kRPW = 16;    // sampled rows per wavefront in the QR kernel
+constexpr int kSelIds = 4;  // IDs (wavefronts) per selection workgroup
 
 __device__ double cheb_fraction(int j, int s) {
   if (s == 1) return 0.5;
@@ -33,26 +40,50 @@ __device__ double cheb_fraction(int j, int s) {
   return 0.5 * (1.0 - cos(M_PI * (double)j / (double)n));
 }
 
-// Position of the allowed point nearest to z (smaller position on a tie).
-__device__ int nearest_pos(const double* coord, const int32_t* idx, int n, double z) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (coord[idx[mid]] < z) lo = mid + 1; else hi = mid;
+// Coordinates of an index segment: direct[p] when a coordinate array is
+// given, else base[idx[p]].
+struct Seg {
+  const double* direct;
+  const double* base;
+  const int32_t* idx;
+  __device__ __forceinline__ double operator()(int64_t p) const { return direct ? direct[p] : base[idx[p]]; }
+};
+
+// Position of the point nearest to z in the ascending segment a[0..n), the
+// smaller position on a tie.  Up to four interpolation probes, then bisection.
+__device__ int nearest_pos(const Seg& a, int n, double z) {
+  const double a0 = a(0);
+  if (n == 1 || z <= a0) return 0;
+  const double an = a(n - 1);
+  if (z > an) return n - 1;
+  int lo = 0, hi = n - 1;  // a[lo] < z <= a[hi]
+  double alo = a0, ahi = an;
+  for (int it = 0; hi - lo > 1; ++it) {
+    int g;
+    if (it < 4) {
+      const double f = (z - alo) / (ahi - alo);
+      g = lo + 1 + (int)(f * (double)(hi - lo - 1));
+      g = min(max(g, lo + 1), hi - 1);
+    } else {
+      g = (lo + hi) >> 1;
+    }
+    const double ag = a(g);
+    if (ag < z) {
+      lo = g;
+      alo = ag;
+    } else {
+      hi = g;
+      ahi = ag;
+    }
   }
-  if (lo == 0) return 0;
-  if (lo == n) return n - 1;
-  const double dl = __builtin_fabs(coord[idx[lo - 1]] - z);
-  const double dr = __builtin_fabs(coord[idx[lo]] - z);
-  return (dl <= dr) ? lo - 1 : lo;
+  return (__builtin_fabs(alo - z) <= __builtin_fabs(ahi - z)) ? lo : hi;
 }
 
-// Sequential rule: for targets in order, the nearest unused point.
-__device__ void greedy_select(const double* coord, const int32_t* idx, int n, int s, double lo,
-                              double hi, int* pos) {
+// Sequential rule: for targets in order, the nearest unused point; then sort.
+__device__ void greedy_select(const Seg& a, int n, int s, double lo, double hi, int* pos) {
   for (int j = 0; j < s; ++j) {
     const double z = lo + (hi - lo) * cheb_fraction(j, s);
-    const int p0 = nearest_pos(coord, idx, n, z);
+    const int p0 = nearest_pos(a, n, z);
     auto used = [&](int p) {
       for (int t = 0; t < j; ++t)
         if (pos[t] == p) return true;
@@ -69,14 +100,12 @@ __device__ void greedy_select(const double* coord, const int32_t* idx, int n, in
       } else if (r >= n) {
         pick = l;
       } else {
-        const double dl = __builtin_fabs(coord[idx[l]] - z);
-        const double dr = __builtin_fabs(coord[idx[r]] - z);
-        pick = (dl <= dr) ? l : r;
+        pick = (__builtin_fabs(a(l) - z) <= __builtin_fabs(a(r) - z)) ? l : r;
       }
     }
     pos[j] = pick;
   }
-  for (int i = 1; i < s; ++i) {  // ascending order
+  for (int i = 1; i < s; ++i) {
     const int v = pos[i];
     int k = i - 1;
     while (k >= 0 && pos[k] > v) {
@@ -87,17 +116,82 @@ __device__ void greedy_select(const double* coord, const int32_t* idx, int n, in
   }
 }
 
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront per ID; waves never synchronize with each other.
+__global__ __launch_bounds__(64 * kSelIds) void select_kernel(IdArgs A) {
+  __shared__ int s_pos[kSelIds][kMaxSamples];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int64_t q = blockIdx.x * (int64_t)kSelIds + w;
+  if (q >= A.n_ids) return;
+  const int c = A.cand_len[q], na = A.allow_len[q];
+  const int s = min(A.oversample * c, na);
+  if (c < 1 || c > kMaxCand || na < 1 || s > kMaxSamples) return;  // id_kernel reports it
+  int32_t* out = A.samp_pos + q * (int64_t)kMaxSamples;
+  if (s >= na) {
+    for (int j = lane; j < na; j += kWave) out[j] = j;
+    return;
+  }
+  const bool isV = (A.side == IDBF_SIDE_V);
+  const int ab = A.allow_beg[q];
+  const Seg a{A.allow_coord ? A.allow_coord + ab : nullptr, isV ? A.X : A.Om, A.allow_idx + ab};
+  const double lo = a(0), hi = a(na - 1);
+  int coll = 0;
+  int prev_last = -1;
+  for (int j0 = 0; j0 < s; j0 += kWave) {
+    const int j = j0 + lane;
+    int p = -1;
+    if (j < s) p = nearest_pos(a, na, lo + (hi - lo) * cheb_fraction(j, s));
+    const int left = __shfl_up(p, 1, kWave);
+    const int before = (lane == 0) ? prev_last : left;
+    if (j < s && j > 0 && p == before) coll = 1;
+    prev_last = __shfl(p, kWave - 1, kWave);
+    if (j < s) s_pos[w][j] = p;
+  }
+  if (__ballot(coll)) {
+    wave_lds_sync();
+    if (lane == 0) greedy_select(a, na, s, lo, hi, s_pos[w]);
+  }
+  wave_lds_sync();
+  for (int j = lane; j < s; j += kWave) out[j] = s_pos[w][j];
+}
+
+// DPP max over the 64 lanes of a wavefront: row_shr within rows of 16, then
+// row broadcasts; lane 63 ends with the maximum.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false);
+  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(h2, l2);
+}
+__device__ __forceinline__ double wave_max_dpp(double v) {
+  v = fmax(v, dpp_d<0x111, 0xf>(v));  // row_shr:1
+  v = fmax(v, dpp_d<0x112, 0xf>(v));  // row_shr:2
+  v = fmax(v, dpp_d<0x114, 0xf>(v));  // row_shr:4
+  v = fmax(v, dpp_d<0x118, 0xf>(v));  // row_shr:8
+  v = fmax(v, dpp_d<0x142, 0xa>(v));  // row_bcast:15
+  v = fmax(v, dpp_d<0x143, 0xc>(v));  // row_bcast:31
+  return readlane(v, kWave - 1);
+}
+
 template <int W>
 __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
-  constexpr int R = kRowsPerWave;
+  constexpr int R = kRPW;
   constexpr int SMAX = R * W;
+  __shared__ double s_part[W > 1 ? W : 1][kWave];
+  __shared__ double2 s_partc[W > 1 ? W : 1][kWave];
   __shared__ double s_coord[SMAX];
   __shared__ double s_cx[SMAX];
-  __shared__ int s_pos[SMAX];
   __shared__ double2 s_v[SMAX];
-  __shared__ double s_part[W][kWave];
-  __shared__ double2 s_partc[W][kWave];
+  __shared__ double2 s_col[2][kMaxRank];  // back-substitution: a column of R11
+  __shared__ double2 s_t[2][kWave];       // back-substitution: one row of T
   __shared__ int s_piv[kMaxRank];
+  __shared__ int s_srank[kMaxRank];
   __shared__ double2 s_alpha;
   __shared__ double s_tau;
 
@@ -114,42 +208,27 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
   }
   const bool isV = (A.side == IDBF_SIDE_V);
   const bool fio = (A.ph.kind == IDBF_PHASE_FIO);
-  const double* candX = isV ? A.Om : A.X;
-  const double* allowX = isV ? A.X : A.Om;
-  const int32_t* aidx = A.allow_idx + ab;
+  const Seg cs{A.cand_coord ? A.cand_coord + cb : nullptr, isV ? A.Om : A.X, A.cand_idx + cb};
+  const Seg as{A.allow_coord ? A.allow_coord + ab : nullptr, isV ? A.X : A.Om, A.allow_idx + ab};
 
   int gidx = 0;
   double ccoord = 0.0, ccx = 0.0;
   if (lane < c) {
     gidx = A.cand_idx[cb + lane];
-    ccoord = candX[gidx];
+    ccoord = cs(lane);
     if (!isV && fio) ccx = amplitude_shift(A.ph, ccoord);
   }
-
-  // ---- 1. Mock-Chebyshev sample selection
-  if (s >= na) {
-    for (int j = threadIdx.x; j < na; j += nthreads) s_pos[j] = j;
-  } else {
-    const double lo = allowX[aidx[0]], hi = allowX[aidx[na - 1]];
-    for (int j = threadIdx.x; j < s; j += nthreads)
-      s_pos[j] = nearest_pos(allowX, aidx, na, lo + (hi - lo) * cheb_fraction(j, s));
-    __syncthreads();
-    int coll = 0;
-    for (int j = threadIdx.x + 1; j < s; j += nthreads) coll |= (s_pos[j] == s_pos[j - 1]);
-    if (__syncthreads_or(coll)) {
-      if (threadIdx.x == 0) greedy_select(allowX, aidx, na, s, lo, hi, s_pos);
-    }
-  }
-  __syncthreads();
+  const int32_t* sp = A.samp_pos + q * (int64_t)kMaxSamples;
   for (int j = threadIdx.x; j < s; j += nthreads) {
-    const double v = allowX[aidx[s_pos[j]]];
+    const double v = as(sp[j]);
     s_coord[j] = v;
     s_cx[j] = (isV && fio) ? amplitude_shift(A.ph, v) : 0.0;
   }
   __syncthreads();
 
-  // ---- 2. sampled block, rows [R w, R w + R) of column `lane`
+  // sampled block: rows [R w, R w + R) of column `lane`
   const int row0 = w * R;
+  const bool wave_has_rows = row0 < s;
   double2 a[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
@@ -161,7 +240,6 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
     a[i] = v;
   }
 
-  // ---- 3. column-pivoted Householder QR with eps-rank stop
   const int kuser = min(min(s, c), A.kmax > 0 ? A.kmax : (1 << 30));
   bool pivoted = false;
   double r00 = 0.0;
@@ -169,9 +247,11 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
   bool zero_block = false, overflow = false;
   for (int j = 0;; ++j) {
     double part = 0.0;
+    if (wave_has_rows) {
 #pragma unroll
-    for (int i = 0; i < R; ++i)
-      if (row0 + i >= j) part += cabs2(a[i]);
+      for (int i = 0; i < R; ++i)
+        if (row0 + i >= j) part += cabs2(a[i]);
+    }
     double nrm2 = part;
     if constexpr (W > 1) {
       s_part[w][lane] = part;
@@ -182,7 +262,7 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
     }
     const bool eligible = (lane < c) && !pivoted;
     const double nu = eligible ? sqrt(nrm2) : -1.0;
-    const double M = wave_max(nu);
+    const double M = wave_max_dpp(nu);
     if (j == 0) {
       r00 = M;
       if (M == 0.0) {
@@ -197,15 +277,14 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
       overflow = true;
       break;
     }
-    const int p = __builtin_amdgcn_readfirstlane(
-        wave_min((eligible && nu >= (1.0 - kPivotTie) * M) ? lane : kWave));
-    if (p >= kWave) break;  // no finite residual norm left (cannot happen for finite input)
-    // pivot lane publishes the Householder vector v (rows >= j) and alpha, tau
+    const uint64_t near = __ballot(eligible && nu >= (1.0 - kPivotTie) * M);
+    if (near == 0) break;  // no finite residual norm left (cannot happen for finite input)
+    const int p = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)near) - 1);
     if (lane == p) {
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const int row = row0 + i;
-        if (row > j) s_v[row] = a[i];
+        if (row > j && row < s) s_v[row] = a[i];
         if (row == j) {
           const double2 xj = a[i];
           const double axj = sqrt(cabs2(xj));
@@ -223,13 +302,16 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
           s_tau = 1.0 / (nu * (nu + axj));
         }
       }
+      if (w == 0) s_piv[j] = p;
     }
     __syncthreads();
     const double tau = s_tau;
     double2 dot = make_double2(0.0, 0.0);
+    if (wave_has_rows) {
 #pragma unroll
-    for (int i = 0; i < R; ++i)
-      if (row0 + i >= j) dot = cfma_conj(s_v[row0 + i], a[i], dot);
+      for (int i = 0; i < R; ++i)
+        if (row0 + i >= j && row0 + i < s) dot = cfma_conj(s_v[row0 + i], a[i], dot);
+    }
     if constexpr (W > 1) {
       s_partc[w][lane] = dot;
       __syncthreads();
@@ -246,17 +328,16 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
         if (row > j) a[i] = make_double2(0.0, 0.0);
       }
       pivoted = true;
-      if (w == 0) s_piv[j] = p;
-    } else if (eligible) {
-      const double2 sdot = make_double2(tau * dot.x, tau * dot.y);
+    } else if (eligible && wave_has_rows) {
+      const double2 sdot = make_double2(-tau * dot.x, -tau * dot.y);
 #pragma unroll
       for (int i = 0; i < R; ++i)
-        if (row0 + i >= j) a[i] = cfma(make_double2(-s_v[row0 + i].x, -s_v[row0 + i].y), sdot, a[i]);
+        if (row0 + i >= j && row0 + i < s) a[i] = cfma(s_v[row0 + i], sdot, a[i]);
     }
     k = j + 1;
-    __syncthreads();
+    if constexpr (W == 1) __syncthreads();
   }
-  if (k == 0) zero_block = true;  // no pivot was taken: keep the first candidate, T = 0
+  if (k == 0) zero_block = true;  // no pivot taken: keep the first candidate, T = 0
   if (zero_block) {
     k = 1;
     pivoted = (lane == 0);
@@ -264,67 +345,90 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
   }
   if (overflow && threadIdx.x == 0) atomicOr(A.status, kErrRank);
   __syncthreads();
-  if (w != 0) return;
-
   const uint64_t msk = __ballot(pivoted && lane < c);
+  if (threadIdx.x < k) s_srank[threadIdx.x] = __popcll(msk & lanes_below(s_piv[threadIdx.x]));
+  __syncthreads();
+
   const int below = __popcll(msk & lanes_below(lane));
   const int r = c - k;
-
-  // ---- 4. T = R11^{-1} R12 on the redundant lanes, in place in a[0..k)
   const bool redundant = (lane < c) && !pivoted;
-  if (zero_block) {
-#pragma unroll
-    for (int i = 0; i < R; ++i) a[i] = make_double2(0.0, 0.0);
-  } else {
-#pragma unroll
-    for (int ii = R - 1; ii >= 0; --ii) {
-      if (ii < k) {
-        const int pp = __builtin_amdgcn_readfirstlane(s_piv[ii]);
-        const double2 d = readlane(a[ii], pp);
-        const double inv = 1.0 / cabs2(d);
-        const double2 t = cmul(a[ii], make_double2(d.x * inv, -d.y * inv));
-        if (redundant) a[ii] = t;
-#pragma unroll
-        for (int i = 0; i < ii; ++i) {
-          const double2 rr = readlane(a[i], pp);
-          if (redundant) a[i] = cfma(make_double2(-rr.x, -rr.y), t, a[i]);
-        }
-      }
+  if (w == 0) {
+    if (lane == 0) {
+      A.rank[q] = k;
+      A.mask[q] = msk;
     }
+    if (pivoted && lane < c) A.skel_out[q * kMaxCand + below] = gidx;
   }
-
-  // ---- outputs
-  if (lane == 0) {
-    A.rank[q] = k;
-    A.mask[q] = msk;
-  }
-  if (pivoted && lane < c) A.skel_out[q * kMaxCand + below] = gidx;
-  if (redundant) {
-    const int jr = lane - below;
-    const int64_t off = A.T_off ? A.T_off[q] : q * (int64_t)kSlot;
+  // Back-substitution T = R11^{-1} R12, one redundant candidate per lane, rows
+  // from the last up: t_ii = r_ii / R[ii][piv_ii], then r_i -= R[i][piv_ii] t_ii
+  // for i < ii.  Column piv_ii of R11 and the row t_ii go through double-buffered
+  // LDS slots, so each step needs two barriers.
+  const int jr = lane - below;
+  const int64_t off = A.T_off ? A.T_off[q] : q * (int64_t)kSlot;
+  for (int ii = k - 1; ii >= 0; --ii) {
+    const int buf = ii & 1;
+    const int pp = s_piv[ii];
+    if (lane == pp) {
 #pragma unroll
-    for (int ii = 0; ii < R; ++ii) {
-      if (ii < k) {
-        const int pp = s_piv[ii];
-        const int sr = min(__popcll(msk & lanes_below(pp)), k - 1);
-        const int64_t e = off + (isV ? (int64_t)jr * k + sr : (int64_t)sr * r + jr);
-        A.T128[e] = a[ii];
-        if (A.T64) A.T64[e] = make_float2((float)a[ii].x, (float)a[ii].y);
+      for (int i = 0; i < R; ++i)
+        if (row0 + i <= ii) s_col[buf][row0 + i] = a[i];
+    }
+    __syncthreads();
+    if (redundant && row0 <= ii && ii < row0 + R) {
+      double2 t = make_double2(0.0, 0.0);
+      if (!zero_block) {
+        const double2 d = s_col[buf][ii];
+        const double inv = 1.0 / cabs2(d);
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+          if (row0 + i == ii) t = cmul(a[i], make_double2(d.x * inv, -d.y * inv));
       }
+      s_t[buf][lane] = t;
+      const int sr = s_srank[ii];
+      const int64_t e = off + (isV ? (int64_t)jr * k + sr : (int64_t)sr * r + jr);
+      A.T128[e] = t;
+      if (A.T64) A.T64[e] = make_float2((float)t.x, (float)t.y);
+    }
+    __syncthreads();
+    if (redundant && row0 < ii) {
+      const double2 t = s_t[buf][lane];
+      const double2 mt = make_double2(-t.x, -t.y);
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (row0 + i < ii) a[i] = cfma(s_col[buf][row0 + i], mt, a[i]);
     }
   }
 }
 
 }  // namespace
 
-hipError_t launch_id_batch(const IdArgs& a, int waves, hipStream_t st) {
+int id_batch_waves(int s_max) { return std::max(1, std::min(kMaxSamples / kRPW, (s_max + kRPW - 1) / kRPW)); }
+
+hipError_t launch_select(const IdArgs& a, hipStream_t st) {
   if (a.n_ids <= 0) return hipSuccess;
-  dim3 grid((unsigned)a.n_ids);
-  switch (waves) {
+  hipLaunchKernelGGL(select_kernel, dim3((unsigned)((a.n_ids + kSelIds - 1) / kSelIds)), dim3(64 * kSelIds), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_id_batch(const IdArgs& a, hipStream_t st) {
+  hipError_t e = launch_select(a, st);
+  if (e != hipSuccess) return e;
+  return launch_qr(a, st);
+}
+
+hipError_t launch_qr(const IdArgs& a, hipStream_t st) {
+  if (a.n_ids <= 0) return hipSuccess;
+  const dim3 grid((unsigned)a.n_ids);
+  switch (id_batch_waves(a.s_max)) {
     case 1: hipLaunchKernelGGL(id_kernel<1>, grid, dim3(64), 0, st, a); break;
     case 2: hipLaunchKernelGGL(id_kernel<2>, grid, dim3(128), 0, st, a); break;
     case 3: hipLaunchKernelGGL(id_kernel<3>, grid, dim3(192), 0, st, a); break;
-    default: hipLaunchKernelGGL(id_kernel<4>, grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL(id_kernel<4>, grid, dim3(256), 0, st, a); break;
+    case 5: hipLaunchKernelGGL(id_kernel<5>, grid, dim3(320), 0, st, a); break;
+    case 6: hipLaunchKernelGGL(id_kernel<6>, grid, dim3(384), 0, st, a); break;
+    case 7: hipLaunchKernelGGL(id_kernel<7>, grid, dim3(448), 0, st, a); break;
+    default: hipLaunchKernelGGL(id_kernel<8>, grid, dim3(512), 0, st, a); break;
   }
   return hipGetLastError();
 }

@@ -18,12 +18,16 @@ struct IdArgs {
   const int32_t* cand_idx;
   const int32_t* cand_beg;
   const int32_t* cand_len;
+  const double* cand_coord;   // coordinate of cand_idx[p] at [p], or null (then looked up)
   const int32_t* allow_idx;
   const int32_t* allow_beg;
   const int32_t* allow_len;
+  const double* allow_coord;  // same for the allowed points
   double tol;
   int kmax;
   int oversample;
+  int s_max;                  // largest sample count of the batch (sizes the launch)
+  int32_t* samp_pos;          // kMaxSamples sample positions per ID (scratch)
   int32_t* rank;
   uint64_t* mask;
   int32_t* skel_out;     // kMaxCand entries per ID
@@ -32,8 +36,17 @@ struct IdArgs {
   const int64_t* T_off;  // null: ID q writes at q * kSlot
   int32_t* status;
 };
-// waves: 1..4 cooperating waves per ID (s <= 32 * waves)
-hipError_t launch_id_batch(const IdArgs& a, int waves, hipStream_t st);
+// Selection (one wavefront per ID), then sampling + QR + solve with
+// ceil(s_max / 16) wavefronts per ID; launch_id_batch runs both.
+hipError_t launch_select(const IdArgs& a, hipStream_t st);
+hipError_t launch_qr(const IdArgs& a, hipStream_t st);
+hipError_t launch_id_batch(const IdArgs& a, hipStream_t st);
+int id_batch_waves(int s_max);
+
+// Work of a finished level: out[0] += sum 16 sum_{j<k}(s-j)(c-j) + 4 k^2 (c-k)
+// (FP64 flops), out[1] += sum k (c - k) (T entries), out[2] += sum s c (samples).
+hipError_t launch_id_work(const int32_t* rank, const int32_t* cand_len, const int32_t* samples, int64_t n,
+                          unsigned long long* out, hipStream_t st);
 
 // ------------------------------------------------------------- level plumbing
 struct DescArgs {
@@ -60,8 +73,10 @@ hipError_t launch_scan_i32(const int32_t* v, int64_t n, int32_t* off, const int3
                            int64_t* stats, hipStream_t st);
 
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t st);
+// packed skeleton lists and their coordinates (base[index])
 hipError_t launch_compact_skel(const int32_t* scratch, const int32_t* rank, const int32_t* off,
-                               int64_t n_ids, int32_t* out, hipStream_t st);
+                               int64_t n_ids, const double* base, int32_t* out, double* out_coord,
+                               hipStream_t st);
 
 // Middle factor: per block b rows skel_r[rbeg .. +rlen), cols skel_c[cbeg .. +clen).
 struct MiddleDescArgs {
@@ -73,7 +88,8 @@ struct MiddleDescArgs {
   int32_t* rlen;
   int32_t* cbeg;
   int32_t* clen;
-  int64_t* size;
+  int64_t* size;               // entries reserved per block (rounded up to even)
+  unsigned long long* nnz;     // += sum of rlen * clen (entries in use)
 };
 hipError_t launch_middle_desc(const MiddleDescArgs& a, hipStream_t st);
 struct SampleBlocksArgs {
@@ -113,7 +129,10 @@ struct StageArgs {
   const void* T;           // double2 or float2 entries
   const void* in;
   void* out;
+  int pmax;                // largest factor block (entries) of the stage: LDS per ID
   // middle stage
+  bool dense;              // H = 0: one N x N block
+  int64_t rlen_host;       // its row count
   int nsub;                // blocks per output: 2^(d-H) (1 when H = 0)
   const int32_t* rbeg;
   const int32_t* rlen;

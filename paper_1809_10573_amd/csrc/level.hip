@@ -10,6 +10,8 @@
 //    the right depth, with the partner the tree algebra fixes) are one
 //    contiguous segment of the other side's list,
 // so every ID reads two contiguous index segments.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace idbf {
@@ -59,7 +61,8 @@ __global__ void desc_kernel(DescArgs A) {
   if (A.kmax > 0) kcap = min(kcap, (int64_t)A.kmax);
   kcap = min(kcap, (int64_t)kMaxRank);
   const int64_t half = cl / 2;
-  A.t_bound[q] = (kcap >= half) ? half * (cl - half) : kcap * (cl - kcap);
+  const int64_t bound = (kcap >= half) ? half * (cl - half) : kcap * (cl - kcap);
+  A.t_bound[q] = (bound + 1) & ~int64_t(1);  // even: every T block starts 16-byte aligned
   A.samples[q] = (int32_t)s;
 }
 
@@ -121,16 +124,18 @@ __global__ void iota_kernel(int32_t* p, int64_t n) {
 }
 
 __global__ void compact_kernel(const int32_t* scratch, const int32_t* rank, const int32_t* off,
-                               int64_t n_ids, int32_t* out) {
+                               int64_t n_ids, const double* base, int32_t* out, double* out_coord) {
   const int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave;
   const int lane = threadIdx.x & (kWave - 1);
   if (q >= n_ids) return;
-  if (lane < rank[q]) out[off[q] + lane] = scratch[q * kMaxCand + lane];
+  if (lane < rank[q]) {
+    const int32_t g = scratch[q * kMaxCand + lane];
+    out[off[q] + lane] = g;
+    out_coord[off[q] + lane] = base[g];
+  }
 }
 
-__global__ void middle_desc_kernel(MiddleDescArgs A) {
-  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (b >= A.n_blocks) return;
+__device__ unsigned long long middle_desc_one(const MiddleDescArgs& A, int64_t b) {
   const int H = A.H, d = A.L - A.H + 1, sh = d - H;
   const int64_t nsub = 1ll << sh;
   const int64_t qu = b / nsub, j = b % nsub;
@@ -143,7 +148,16 @@ __global__ void middle_desc_kernel(MiddleDescArgs A) {
   A.rlen[b] = rl;
   A.cbeg[b] = cb;
   A.clen[b] = cl;
-  A.size[b] = (int64_t)rl * cl;
+  A.size[b] = ((int64_t)rl * cl + 1) & ~int64_t(1);  // even: blocks start 16-byte aligned
+  return (unsigned long long)rl * cl;
+}
+
+__global__ __launch_bounds__(256) void middle_desc_kernel(MiddleDescArgs A) {
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  unsigned long long used = 0;
+  if (b < A.n_blocks) used = middle_desc_one(A, b);
+  for (int off = 32; off > 0; off >>= 1) used += __shfl_xor(used, off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0 && used) atomicAdd(A.nnz, used);
 }
 
 // One workgroup per block; lanes over rows, loop over columns.
@@ -174,6 +188,30 @@ __global__ void sample_dense_kernel(PhaseDev ph, const double* X, const double* 
   out[e] = kernel_entry(ph, x, cx, Om[cols[j]]);
 }
 
+__global__ __launch_bounds__(256) void id_work_kernel(const int32_t* rank, const int32_t* cand_len,
+                                                      const int32_t* samples, int64_t n, unsigned long long* out) {
+  __shared__ unsigned long long s_w[3][256];
+  unsigned long long fl = 0, te = 0, se = 0;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = rank[q], c = cand_len[q], sq = samples[q];
+    unsigned long long h = 0;
+    for (int64_t j = 0; j < k; ++j) h += (unsigned long long)((sq - j) * (c - j));
+    fl += 16 * h + 4 * (unsigned long long)(k * k * (c - k));
+    te += (unsigned long long)(k * (c - k));
+    se += (unsigned long long)(sq * c);
+  }
+  s_w[0][threadIdx.x] = fl;
+  s_w[1][threadIdx.x] = te;
+  s_w[2][threadIdx.x] = se;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if ((int)threadIdx.x < d)
+      for (int m = 0; m < 3; ++m) s_w[m][threadIdx.x] += s_w[m][threadIdx.x + d];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) atomicAdd(out + threadIdx.x, s_w[threadIdx.x][0]);
+}
+
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -202,10 +240,18 @@ hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t st) {
 }
 
 hipError_t launch_compact_skel(const int32_t* scratch, const int32_t* rank, const int32_t* off, int64_t n_ids,
-                               int32_t* out, hipStream_t st) {
+                               const double* base, int32_t* out, double* out_coord, hipStream_t st) {
   if (n_ids <= 0) return hipSuccess;
   hipLaunchKernelGGL(compact_kernel, dim3(blocks_for(n_ids, 4)), dim3(256), 0, st, scratch, rank, off, n_ids,
-                     out);
+                     base, out, out_coord);
+  return hipGetLastError();
+}
+
+hipError_t launch_id_work(const int32_t* rank, const int32_t* cand_len, const int32_t* samples, int64_t n,
+                          unsigned long long* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(id_work_kernel, dim3(std::min<unsigned>(blocks_for(n, 256), 1024u)), dim3(256), 0, st, rank,
+                     cand_len, samples, n, out);
   return hipGetLastError();
 }
 
