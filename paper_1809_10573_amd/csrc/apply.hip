@@ -83,32 +83,32 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // V stage: z(ID) = u[skel] + T u[red]; T column-major (entry j*k + i).
-// Dynamic LDS: kIdsPerBlock * pmax products.
+// One wavefront per ID; the ID's packed record is read with a wave-uniform
+// index (scalar loads).  Dynamic LDS: kIdsPerBlock * pmax products.
 template <typename C>
 __global__ __launch_bounds__(256) void apply_v1(StageArgs A) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   __shared__ C s_u[kIdsPerBlock][kWave];
-  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   const int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + w;
   if (q >= A.n) return;
   C* s_p = reinterpret_cast<C*>(s_dyn) + (size_t)w * A.pmax;
   const C* in = static_cast<const C*>(A.in);
   C* out = static_cast<C*>(A.out);
-  const int c = A.cand_len[q], k = A.rank[q], cb = A.cand_beg[q];
-  const uint64_t msk = A.mask[q];
-  const int r = c - k;
+  const ApplyMeta m = A.meta[q];
+  const int c = m.c, k = m.k, r = c - k;
   C u = czero(C{});
-  if (lane < c) u = in[cb + lane];
-  const int below = __popcll(msk & lanes_below(lane));
-  const bool sk = (msk >> lane) & 1ull;
+  if (lane < c) u = in[m.cand_beg + lane];
+  const int below = __popcll(m.mask & lanes_below(lane));
+  const bool sk = (m.mask >> lane) & 1ull;
   if (lane < c && !sk) s_u[w][lane - below] = u;
   wave_sync_lds();
-  stream_products<C, nv_for<C>()>(static_cast<const C*>(A.T) + A.T_off[q], k * r, k, s_u[w], s_p, lane);
+  stream_products<C, nv_for<C>()>(static_cast<const C*>(A.T) + m.t_off, k * r, k, s_u[w], s_p, lane);
   wave_sync_lds();
   if (lane < c && sk) {
     C acc = u;
     for (int j = 0; j < r; ++j) acc = cadd(acc, s_p[j * k + below]);
-    out[A.skel_off[q] + below] = acc;
+    out[m.skel_off + below] = acc;
   }
 }
 
@@ -119,7 +119,7 @@ template <typename C>
 __global__ __launch_bounds__(256) void apply_u1(StageArgs A) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   __shared__ C s_w[kIdsPerBlock][2][kMaxRank];
-  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   const int64_t unit = blockIdx.x * (int64_t)(blockDim.x / kWave) + w;
   if (unit >= A.n) return;
   C* s_p = reinterpret_cast<C*>(s_dyn) + (size_t)w * 2 * A.pmax;
@@ -127,37 +127,34 @@ __global__ __launch_bounds__(256) void apply_u1(StageArgs A) {
   C* out = static_cast<C*>(A.out);
   const C* T = static_cast<const C*>(A.T);
   const int64_t P = unit / A.nn, node = unit % A.nn;
-  const int64_t qid[2] = {2 * P * A.nn + node, 2 * P * A.nn + node + A.nn};
-  const int c = A.cand_len[qid[0]], cb = A.cand_beg[qid[0]];
-  int kk[2];
-  uint64_t mk[2];
+  ApplyMeta m[2];
+  m[0] = A.meta[2 * P * A.nn + node];
+  m[1] = A.meta[2 * P * A.nn + node + A.nn];
+  const int c = m[0].c;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    kk[h] = A.rank[qid[h]];
-    mk[h] = A.mask[qid[h]];
-    if (lane < kk[h]) s_w[w][h][lane] = in[A.skel_off[qid[h]] + lane];
-  }
+  for (int h = 0; h < 2; ++h)
+    if (lane < m[h].k) s_w[w][h][lane] = in[m[h].skel_off + lane];
   wave_sync_lds();
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int r = c - kk[h];
-    stream_products<C, nv_for<C>()>(T + A.T_off[qid[h]], kk[h] * r, r, s_w[w][h], s_p + h * A.pmax, lane);
+    const int r = c - m[h].k;
+    stream_products<C, nv_for<C>()>(T + m[h].t_off, m[h].k * r, r, s_w[w][h], s_p + h * A.pmax, lane);
   }
   wave_sync_lds();
   if (lane < c) {
     C acc = czero(C{});
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const int below = __popcll(mk[h] & lanes_below(lane));
-      if ((mk[h] >> lane) & 1ull) {
+      const int below = __popcll(m[h].mask & lanes_below(lane));
+      if ((m[h].mask >> lane) & 1ull) {
         acc = cadd(acc, s_w[w][h][below]);
       } else {
-        const int r = c - kk[h], jr = lane - below;
-        const C* p = s_p + h * A.pmax + jr;
-        for (int i = 0; i < kk[h]; ++i) acc = cadd(acc, p[i * r]);
+        const int r = c - m[h].k;
+        const C* p = s_p + h * A.pmax + (lane - below);
+        for (int i = 0; i < m[h].k; ++i) acc = cadd(acc, p[i * r]);
       }
     }
-    out[cb + lane] = acc;
+    out[m[0].cand_beg + lane] = acc;
   }
 }
 
@@ -236,90 +233,135 @@ __global__ __launch_bounds__(256) void apply_dense(StageArgs A) {
 }
 
 // ---------------------------------------------------------------- many RHS
-constexpr int kRhsChunk = 64;
+// One thread per right-hand side, a workgroup per (ID or unit, 256 RHS).  The
+// ID's factor block is staged in LDS once; each thread keeps its outputs (or,
+// for U stages, its inputs) in registers, indexed statically up to the rank
+// bound, and every global load and store is coalesced across right-hand sides.
+constexpr int kRhsTile = 256;
+
+template <typename C>
+__device__ __forceinline__ void stage_block(const C* src, int n, C* dst) {
+  for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+}
 
 template <typename C>
 __global__ __launch_bounds__(256) void apply_vn(StageArgs A) {
+  __shared__ C s_T[kSlot];
   __shared__ int s_skel[kMaxCand];
   __shared__ int s_red[kMaxCand];
   const int64_t q = blockIdx.x;
-  const int64_t rhs = blockIdx.y * (int64_t)kRhsChunk + (threadIdx.x & (kRhsChunk - 1));
-  const int g = threadIdx.x / kRhsChunk;
-  const int c = A.cand_len[q], k = A.rank[q], cb = A.cand_beg[q];
+  const int64_t n = blockIdx.y * (int64_t)kRhsTile + threadIdx.x;
+  const int c = A.cand_len[q], k = A.rank[q], cb = A.cand_beg[q], so = A.skel_off[q];
+  const int r = c - k;
   const uint64_t msk = A.mask[q];
   if (threadIdx.x < c) {
     const int l = threadIdx.x;
     const int below = __popcll(msk & lanes_below(l));
     if ((msk >> l) & 1ull) s_skel[below] = l; else s_red[l - below] = l;
   }
+  stage_block(static_cast<const C*>(A.T) + A.T_off[q], k * r, s_T);
   __syncthreads();
-  if (rhs >= A.nrhs) return;
-  const C* in = static_cast<const C*>(A.in);
-  C* out = static_cast<C*>(A.out);
-  const C* Tq = static_cast<const C*>(A.T) + A.T_off[q];
+  if (n >= A.nrhs) return;
+  const C* in = static_cast<const C*>(A.in) + n;
+  C* out = static_cast<C*>(A.out) + n;
   const int64_t nr = A.nrhs;
-  const int r = c - k;
-  for (int i = g; i < k; i += 256 / kRhsChunk) {
-    C acc = in[(int64_t)(cb + s_skel[i]) * nr + rhs];
-    for (int j = 0; j < r; ++j) acc = cfma(Tq[(int64_t)j * k + i], in[(int64_t)(cb + s_red[j]) * nr + rhs], acc);
-    out[(int64_t)(A.skel_off[q] + i) * nr + rhs] = acc;
+  C acc[kMaxRank];
+#pragma unroll
+  for (int i = 0; i < kMaxRank; ++i) acc[i] = czero(C{});
+  for (int j = 0; j < r; ++j) {
+    const C uj = in[(int64_t)(cb + s_red[j]) * nr];
+    const C* t = s_T + j * k;
+#pragma unroll
+    for (int i = 0; i < kMaxRank; ++i)
+      if (i < k) acc[i] = cfma(t[i], uj, acc[i]);
   }
+#pragma unroll
+  for (int i = 0; i < kMaxRank; ++i)
+    if (i < k) out[(int64_t)(so + i) * nr] = cadd(acc[i], in[(int64_t)(cb + s_skel[i]) * nr]);
 }
 
 template <typename C>
 __global__ __launch_bounds__(256) void apply_un(StageArgs A) {
+  __shared__ C s_T[2][kSlot];
   const int64_t unit = blockIdx.x;
-  const int64_t rhs = blockIdx.y * (int64_t)kRhsChunk + (threadIdx.x & (kRhsChunk - 1));
-  const int g = threadIdx.x / kRhsChunk;
-  if (rhs >= A.nrhs) return;
+  const int64_t n = blockIdx.y * (int64_t)kRhsTile + threadIdx.x;
   const int64_t P = unit / A.nn, node = unit % A.nn;
-  const int64_t qid[2] = {2 * P * A.nn + node, 2 * P * A.nn + node + A.nn};
-  const int c = A.cand_len[qid[0]], cb = A.cand_beg[qid[0]];
-  const C* in = static_cast<const C*>(A.in);
-  C* out = static_cast<C*>(A.out);
+  const int64_t qa = 2 * P * A.nn + node, qb = qa + A.nn;
+  const int c = A.cand_len[qa], cb = A.cand_beg[qa];
+  const int ka = A.rank[qa], kb = A.rank[qb];
+  const int soa = A.skel_off[qa], sob = A.skel_off[qb];
+  const uint64_t ma = A.mask[qa], mb = A.mask[qb];
   const C* T = static_cast<const C*>(A.T);
+  stage_block(T + A.T_off[qa], ka * (c - ka), s_T[0]);
+  stage_block(T + A.T_off[qb], kb * (c - kb), s_T[1]);
+  __syncthreads();
+  if (n >= A.nrhs) return;
+  const C* in = static_cast<const C*>(A.in) + n;
+  C* out = static_cast<C*>(A.out) + n;
   const int64_t nr = A.nrhs;
-  for (int l = g; l < c; l += 256 / kRhsChunk) {
-    C acc = czero(C{});
+  C wa[kMaxRank], wb[kMaxRank];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const uint64_t msk = A.mask[qid[h]];
-      const int k = A.rank[qid[h]], so = A.skel_off[qid[h]];
-      const int below = __popcll(msk & lanes_below(l));
-      if ((msk >> l) & 1ull) {
-        acc = cadd(acc, in[(int64_t)(so + below) * nr + rhs]);
-      } else {
-        const int r = c - k, jr = l - below;
-        const C* Tq = T + A.T_off[qid[h]] + jr;
-        for (int i = 0; i < k; ++i) acc = cfma(Tq[(int64_t)i * r], in[(int64_t)(so + i) * nr + rhs], acc);
-      }
+  for (int i = 0; i < kMaxRank; ++i) {
+    wa[i] = (i < ka) ? in[(int64_t)(soa + i) * nr] : czero(C{});
+    wb[i] = (i < kb) ? in[(int64_t)(sob + i) * nr] : czero(C{});
+  }
+  const int ra = c - ka, rb = c - kb;
+  for (int l = 0; l < c; ++l) {
+    C acc = czero(C{});
+    const int ba = __popcll(ma & lanes_below(l)), bb = __popcll(mb & lanes_below(l));
+    if ((ma >> l) & 1ull) {
+      acc = cadd(acc, in[(int64_t)(soa + ba) * nr]);
+    } else {
+      const C* t = s_T[0] + (l - ba);
+#pragma unroll
+      for (int i = 0; i < kMaxRank; ++i)
+        if (i < ka) acc = cfma(t[i * ra], wa[i], acc);
     }
-    out[(int64_t)(cb + l) * nr + rhs] = acc;
+    if ((mb >> l) & 1ull) {
+      acc = cadd(acc, in[(int64_t)(sob + bb) * nr]);
+    } else {
+      const C* t = s_T[1] + (l - bb);
+#pragma unroll
+      for (int i = 0; i < kMaxRank; ++i)
+        if (i < kb) acc = cfma(t[i * rb], wb[i], acc);
+    }
+    out[(int64_t)(cb + l) * nr] = acc;
   }
 }
 
 template <typename C>
 __global__ __launch_bounds__(256) void apply_sn(StageArgs A) {
+  __shared__ C s_S[kSlot];
   const int64_t q = blockIdx.x;
-  const int64_t rhs = blockIdx.y * (int64_t)kRhsChunk + (threadIdx.x & (kRhsChunk - 1));
-  const int g = threadIdx.x / kRhsChunk;
-  if (rhs >= A.nrhs) return;
-  const C* in = static_cast<const C*>(A.in);
-  C* out = static_cast<C*>(A.out);
-  const C* S = static_cast<const C*>(A.T);
-  const int64_t nr = A.nrhs;
+  const int64_t n = blockIdx.y * (int64_t)kRhsTile + threadIdx.x;
   const int64_t b0 = q * A.nsub;
-  const int rl = A.rlen[b0], rb = A.rbeg[b0];
-  for (int i = g; i < rl; i += 256 / kRhsChunk) {
-    C acc = czero(C{});
-    for (int jb = 0; jb < A.nsub; ++jb) {
-      const int64_t b = b0 + jb;
-      const int cl = A.clen[b], cbg = A.cbeg[b];
-      const C* Sb = S + A.T_off[b] + i;
-      for (int col = 0; col < cl; ++col) acc = cfma(Sb[(int64_t)col * rl], in[(int64_t)(cbg + col) * nr + rhs], acc);
+  const int rl = A.rlen[b0], rbg = A.rbeg[b0];
+  const bool live = n < A.nrhs;
+  const C* in = static_cast<const C*>(A.in) + (live ? n : 0);
+  const int64_t nr = A.nrhs;
+  C acc[kMaxRank];
+#pragma unroll
+  for (int i = 0; i < kMaxRank; ++i) acc[i] = czero(C{});
+  for (int jb = 0; jb < A.nsub; ++jb) {
+    const int64_t b = b0 + jb;
+    const int cl = A.clen[b], cbg = A.cbeg[b];
+    __syncthreads();
+    stage_block(static_cast<const C*>(A.T) + A.T_off[b], rl * cl, s_S);
+    __syncthreads();
+    if (!live) continue;
+    for (int col = 0; col < cl; ++col) {
+      const C zc = in[(int64_t)(cbg + col) * nr];
+      const C* sc = s_S + col * rl;
+#pragma unroll
+      for (int i = 0; i < kMaxRank; ++i)
+        if (i < rl) acc[i] = cfma(sc[i], zc, acc[i]);
     }
-    out[(int64_t)(rb + i) * nr + rhs] = acc;
   }
+  if (!live) return;
+  C* out = static_cast<C*>(A.out) + n;
+#pragma unroll
+  for (int i = 0; i < kMaxRank; ++i)
+    if (i < rl) out[(int64_t)(rbg + i) * nr] = acc[i];
 }
 
 inline unsigned grid1(int64_t n, int ipb = kIdsPerBlock) { return (unsigned)((n + ipb - 1) / ipb); }
@@ -329,7 +371,7 @@ inline int ids_per_block(size_t per_id) {
   return (int)std::max<size_t>(1, std::min<size_t>(kIdsPerBlock, kDynLds / std::max<size_t>(per_id, 1)));
 }
 inline dim3 gridn(int64_t n, int64_t nrhs) {
-  return dim3((unsigned)n, (unsigned)((nrhs + kRhsChunk - 1) / kRhsChunk));
+  return dim3((unsigned)n, (unsigned)((nrhs + kRhsTile - 1) / kRhsTile));
 }
 
 }  // namespace

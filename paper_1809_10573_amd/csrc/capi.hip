@@ -93,6 +93,7 @@ struct Batch {
   int32_t *cand_beg = nullptr, *cand_len = nullptr, *allow_beg = nullptr, *allow_len = nullptr;
   int32_t *samples = nullptr, *rank = nullptr, *skel_off = nullptr, *skel_idx = nullptr;
   double* skel_coord = nullptr;  // X (U side) or Omega (V side) of each skeleton index
+  ApplyMeta* meta = nullptr;     // packed per-ID apply records
   int64_t *t_bound = nullptr, *T_off = nullptr;
   uint64_t* mask = nullptr;
   double2* T128 = nullptr;
@@ -205,6 +206,8 @@ struct idbf_handle_s {
   int32_t* iota = nullptr;
   int32_t* scratch = nullptr;  // skeleton lists before compaction (64 per ID)
   int32_t* samp_pos = nullptr; // sample positions of the current level (128 per ID)
+  int32_t* order = nullptr;    // IDs of the current level grouped by QR wavefronts
+  unsigned long long* bucket = nullptr;  // [0..8): bucket counts, [8..16): fill cursors
   int64_t* stats = nullptr;    // 8 int64 read back after each scan
   int32_t* status = nullptr;
   std::vector<Batch> U, V;
@@ -294,7 +297,11 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   TRYHIP(launch_desc(d, h->stream));
   TRYHIP(launch_scan_i64(b.t_bound, n, b.T_off, b.cand_len, h->stats, h->stream));
   TRYHIP(launch_scan_i32(b.samples, n, b.skel_off, nullptr, h->stats + 4, h->stream));
+  TRYHIP(hipMemsetAsync(h->bucket, 0, 8 * sizeof(unsigned long long), h->stream));
+  TRYHIP(launch_bucket_count(b.samples, n, h->bucket, h->stream));
   h->prof.end(pr, h->stream);
+  unsigned long long counts[8];
+  TRYHIP(hipMemcpyAsync(counts, h->bucket, sizeof counts, hipMemcpyDeviceToHost, h->stream));
   int64_t st[8];
   TRY(read_stats(h, st, 8));
   b.n_T = st[0];
@@ -333,6 +340,15 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   ia.oversample = h->oversample;
   ia.s_max = b.s_max;
   ia.samp_pos = h->samp_pos;
+  ia.order = h->order;
+  ia.bucket_off[0] = 0;
+  for (int w = 1; w <= 8; ++w) ia.bucket_off[w] = ia.bucket_off[w - 1] + (int64_t)counts[w - 1];
+  {
+    unsigned long long cursors[8];
+    for (int w = 0; w < 8; ++w) cursors[w] = (unsigned long long)ia.bucket_off[w];
+    TRYHIP(hipMemcpy(h->bucket + 8, cursors, sizeof cursors, hipMemcpyHostToDevice));
+    TRYHIP(launch_bucket_fill(b.samples, n, h->bucket + 8, h->order, h->stream));
+  }
   ia.rank = b.rank;
   ia.mask = b.mask;
   ia.skel_out = h->scratch;
@@ -373,9 +389,11 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   b.rank_min = (int)st[2];
   TRY(A.get(std::max<int64_t>(b.n_skel, 1), &b.skel_idx));
   TRY(A.get(std::max<int64_t>(b.n_skel, 1), &b.skel_coord));
+  TRY(A.get(n, &b.meta));
   pr = h->prof.begin("level_compact", h->stream);
   TRYHIP(launch_compact_skel(h->scratch, b.rank, b.skel_off, n, side == IDBF_SIDE_U ? X : Om, b.skel_idx,
                              b.skel_coord, h->stream));
+  TRYHIP(launch_pack_meta(b.T_off, b.mask, b.cand_beg, b.skel_off, b.cand_len, b.rank, n, b.meta, h->stream));
   h->prof.end(pr, h->stream);
   h->max_skel = std::max(h->max_skel, b.n_skel);
   if (side == IDBF_SIDE_U) h->U.push_back(b); else h->V.push_back(b);
@@ -486,6 +504,8 @@ idbf_status construct_impl(idbf_handle_s* h, const double* X, const double* Om) 
   if (h->H > 0) {
     TRY(A.get((int64_t(2) << h->L) * kMaxCand, &h->scratch));
     TRY(A.get((int64_t(2) << h->L) * kMaxSamples, &h->samp_pos));
+    TRY(A.get(int64_t(2) << h->L, &h->order));
+    TRY(A.get(16, &h->bucket));
   }
   for (int t = 1; t <= h->H; ++t) {
     TRY(run_batch(h, X, Om, IDBF_SIDE_U, t));
@@ -628,6 +648,7 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
   for (int t = 1; t <= h->H; ++t) {
     const Batch& b = h->V[t - 1];
     StageArgs a{};
+    a.meta = b.meta;
     a.n = b.n;
     a.nrhs = nrhs;
     a.cand_beg = b.cand_beg;
@@ -674,6 +695,7 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
   for (int t = h->H; t >= 1; --t) {
     const Batch& b = h->U[t - 1];
     StageArgs a{};
+    a.meta = b.meta;
     a.n = int64_t(1) << h->L;  // units: one per (node, parent partner)
     a.nn = 1 << (h->L - t + 1);
     a.nrhs = nrhs;

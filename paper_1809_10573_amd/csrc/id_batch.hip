@@ -26,7 +26,7 @@ namespace idbf {
 
 namespace {
 
-constexpr int kRPW = 16;    // sampled rows per wavefront in the QR kernel
+constexpr int kRPW = kRowsPerWaveQR;
 constexpr int kSelIds = 4;  // IDs (wavefronts) per selection workgroup
 
 __device__ double cheb_fraction(int j, int s) {
@@ -79,31 +79,44 @@ __device__ int nearest_pos(const Seg& a, int n, double z) {
   return (__builtin_fabs(alo - z) <= __builtin_fabs(ahi - z)) ? lo : hi;
 }
 
-// Sequential rule: for targets in order, the nearest unused point; then sort.
-__device__ void greedy_select(const Seg& a, int n, int s, double lo, double hi, int* pos) {
+// Sequential rule, given each target z[j] and its nearest point p0[j]: for
+// targets in order, the nearest unused point (smaller position on a tie); then
+// ascending order.  Used positions are a bitmap when the set is small enough,
+// else a scan of the picks at or below the largest pick so far (later
+// nearest points above it are free).
+constexpr int kSelBitmapWords = 256;  // positions covered by the bitmap: 8192
+
+__device__ void greedy_select(const Seg& a, int n, int s, const double* z, const int* p0, int* pos,
+                              uint32_t* bits) {
+  const bool use_bits = n <= kSelBitmapWords * 32;
+  int maxpick = -1;
+  auto used = [&](int p) -> bool {
+    if (use_bits) return (bits[p >> 5] >> (p & 31)) & 1u;
+    if (p > maxpick) return false;
+    for (int t = 0; t < s; ++t)
+      if (pos[t] == p) return true;
+    return false;
+  };
+  for (int j = 0; j < s; ++j) pos[j] = -1;
   for (int j = 0; j < s; ++j) {
-    const double z = lo + (hi - lo) * cheb_fraction(j, s);
-    const int p0 = nearest_pos(a, n, z);
-    auto used = [&](int p) {
-      for (int t = 0; t < j; ++t)
-        if (pos[t] == p) return true;
-      return false;
-    };
-    int pick = p0;
-    if (used(p0)) {
-      int l = p0 - 1;
+    const int q0 = p0[j];
+    int pick = q0;
+    if (used(q0)) {
+      int l = q0 - 1;
       while (l >= 0 && used(l)) --l;
-      int r = p0 + 1;
+      int r = q0 + 1;
       while (r < n && used(r)) ++r;
       if (l < 0) {
         pick = r;
       } else if (r >= n) {
         pick = l;
       } else {
-        pick = (__builtin_fabs(a(l) - z) <= __builtin_fabs(a(r) - z)) ? l : r;
+        pick = (__builtin_fabs(a(l) - z[j]) <= __builtin_fabs(a(r) - z[j])) ? l : r;
       }
     }
     pos[j] = pick;
+    maxpick = max(maxpick, pick);
+    if (use_bits) bits[pick >> 5] |= 1u << (pick & 31);
   }
   for (int i = 1; i < s; ++i) {
     const int v = pos[i];
@@ -125,6 +138,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // One wavefront per ID; waves never synchronize with each other.
 __global__ __launch_bounds__(64 * kSelIds) void select_kernel(IdArgs A) {
   __shared__ int s_pos[kSelIds][kMaxSamples];
+  __shared__ int s_p0[kSelIds][kMaxSamples];
+  __shared__ double s_z[kSelIds][kMaxSamples];
+  __shared__ uint32_t s_bits[kSelIds][kSelBitmapWords];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
   const int64_t q = blockIdx.x * (int64_t)kSelIds + w;
   if (q >= A.n_ids) return;
@@ -145,19 +161,28 @@ __global__ __launch_bounds__(64 * kSelIds) void select_kernel(IdArgs A) {
   for (int j0 = 0; j0 < s; j0 += kWave) {
     const int j = j0 + lane;
     int p = -1;
-    if (j < s) p = nearest_pos(a, na, lo + (hi - lo) * cheb_fraction(j, s));
+    if (j < s) {
+      const double z = lo + (hi - lo) * cheb_fraction(j, s);
+      p = nearest_pos(a, na, z);
+      s_z[w][j] = z;
+      s_p0[w][j] = p;
+    }
     const int left = __shfl_up(p, 1, kWave);
     const int before = (lane == 0) ? prev_last : left;
     if (j < s && j > 0 && p == before) coll = 1;
     prev_last = __shfl(p, kWave - 1, kWave);
-    if (j < s) s_pos[w][j] = p;
   }
   if (__ballot(coll)) {
+    if (na <= kSelBitmapWords * 32)
+      for (int i = lane; i < (na + 31) / 32; i += kWave) s_bits[w][i] = 0u;
     wave_lds_sync();
-    if (lane == 0) greedy_select(a, na, s, lo, hi, s_pos[w]);
+    if (lane == 0) greedy_select(a, na, s, s_z[w], s_p0[w], s_pos[w], s_bits[w]);
+    wave_lds_sync();
+    for (int j = lane; j < s; j += kWave) out[j] = s_pos[w][j];
+  } else {
+    wave_lds_sync();
+    for (int j = lane; j < s; j += kWave) out[j] = s_p0[w][j];
   }
-  wave_lds_sync();
-  for (int j = lane; j < s; j += kWave) out[j] = s_pos[w][j];
 }
 
 // DPP max over the 64 lanes of a wavefront: row_shr within rows of 16, then
@@ -179,23 +204,35 @@ __device__ __forceinline__ double wave_max_dpp(double v) {
   return readlane(v, kWave - 1);
 }
 
+// Rows [row0, row0 + 16) of one wavefront, restricted to rows >= j (the
+// predicate is uniform across the wavefront).
+#define IDBF_ROWS_FROM(j, BODY)                                  \
+  if (row0 + R > (j)) {                                          \
+    _Pragma("unroll") for (int i = 0; i < R; ++i) {              \
+      if (row0 + i >= (j)) { BODY; }                             \
+    }                                                            \
+  }
+
 template <int W>
-__global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) void id_kernel(IdArgs A) {
   constexpr int R = kRPW;
   constexpr int SMAX = R * W;
-  __shared__ double s_part[W > 1 ? W : 1][kWave];
-  __shared__ double2 s_partc[W > 1 ? W : 1][kWave];
+  // partial sums of the QR loop and the R rows of the solve share LDS
+  constexpr size_t kPart = (size_t)W * kWave * (sizeof(double) + sizeof(double2));
+  constexpr size_t kRrows = (size_t)kMaxRank * kWave * sizeof(double2);
+  __shared__ __attribute__((aligned(16))) unsigned char s_raw[kPart > kRrows ? kPart : kRrows];
   __shared__ double s_coord[SMAX];
   __shared__ double s_cx[SMAX];
   __shared__ double2 s_v[SMAX];
-  __shared__ double2 s_col[2][kMaxRank];  // back-substitution: a column of R11
-  __shared__ double2 s_t[2][kWave];       // back-substitution: one row of T
   __shared__ int s_piv[kMaxRank];
   __shared__ int s_srank[kMaxRank];
+  __shared__ double s_axj[2];
   __shared__ double2 s_alpha;
-  __shared__ double s_tau;
+  double* s_part = reinterpret_cast<double*>(s_raw);                                    // [W][64]
+  double2* s_partc = reinterpret_cast<double2*>(s_raw + W * kWave * sizeof(double));   // [W][64]
+  double2* s_R = reinterpret_cast<double2*>(s_raw);                                     // [32][64]
 
-  const int64_t q = blockIdx.x;
+  const int64_t q = A.order ? A.order[blockIdx.x] : (int64_t)blockIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const int nthreads = kWave * W;
@@ -226,9 +263,8 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
   }
   __syncthreads();
 
-  // sampled block: rows [R w, R w + R) of column `lane`
+  // sampled block: rows [R w, R w + R) of column `lane` (rows >= s stay zero)
   const int row0 = w * R;
-  const bool wave_has_rows = row0 < s;
   double2 a[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
@@ -246,19 +282,16 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
   int k = 0;
   bool zero_block = false, overflow = false;
   for (int j = 0;; ++j) {
+    // residual column norms over rows >= j
     double part = 0.0;
-    if (wave_has_rows) {
-#pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (row0 + i >= j) part += cabs2(a[i]);
-    }
+    IDBF_ROWS_FROM(j, part += cabs2(a[i]))
     double nrm2 = part;
     if constexpr (W > 1) {
-      s_part[w][lane] = part;
+      s_part[w * kWave + lane] = part;
       __syncthreads();
       nrm2 = 0.0;
 #pragma unroll
-      for (int ww = 0; ww < W; ++ww) nrm2 += s_part[ww][lane];
+      for (int ww = 0; ww < W; ++ww) nrm2 += s_part[ww * kWave + lane];
     }
     const bool eligible = (lane < c) && !pivoted;
     const double nu = eligible ? sqrt(nrm2) : -1.0;
@@ -280,62 +313,56 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
     const uint64_t near = __ballot(eligible && nu >= (1.0 - kPivotTie) * M);
     if (near == 0) break;  // no finite residual norm left (cannot happen for finite input)
     const int p = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)near) - 1);
+    // Householder vector of the pivot column (rows >= j): lane p of every wave
+    // publishes its own rows to the wave's slice of LDS (no workgroup barrier);
+    // v_i = a_i(p) for i > j and v_j = x_j - alpha, alpha = -(x_j/|x_j|) nu_p,
+    // tau = 2 / |v|^2 = 1 / (nu_p (nu_p + |x_j|)).
+    const double nup = readlane(nu, p);
     if (lane == p) {
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int row = row0 + i;
-        if (row > j && row < s) s_v[row] = a[i];
-        if (row == j) {
+      IDBF_ROWS_FROM(j, {
+        if (row0 + i == j) {
           const double2 xj = a[i];
           const double axj = sqrt(cabs2(xj));
-          double2 alpha, vj;
+          double2 vj;
           if (axj > 0.0) {
-            alpha = make_double2(-xj.x / axj * nu, -xj.y / axj * nu);
-            const double sc = (axj + nu) / axj;
+            s_alpha = make_double2(-xj.x / axj * nup, -xj.y / axj * nup);
+            const double sc = (axj + nup) / axj;
             vj = make_double2(xj.x * sc, xj.y * sc);
           } else {
-            alpha = make_double2(-nu, 0.0);
-            vj = make_double2(nu, 0.0);
+            s_alpha = make_double2(-nup, 0.0);
+            vj = make_double2(nup, 0.0);
           }
-          s_v[row] = vj;
-          s_alpha = alpha;
-          s_tau = 1.0 / (nu * (nu + axj));
+          s_v[row0 + i] = vj;
+          s_axj[j & 1] = axj;
+        } else {
+          s_v[row0 + i] = a[i];
         }
-      }
-      if (w == 0) s_piv[j] = p;
+      })
     }
-    __syncthreads();
-    const double tau = s_tau;
+    wave_lds_sync();
     double2 dot = make_double2(0.0, 0.0);
-    if (wave_has_rows) {
-#pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (row0 + i >= j && row0 + i < s) dot = cfma_conj(s_v[row0 + i], a[i], dot);
-    }
+    IDBF_ROWS_FROM(j, dot = cfma_conj(s_v[row0 + i], a[i], dot))
+    double tau;
     if constexpr (W > 1) {
-      s_partc[w][lane] = dot;
+      s_partc[w * kWave + lane] = dot;
       __syncthreads();
       dot = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int ww = 0; ww < W; ++ww) dot = cadd(dot, s_partc[ww][lane]);
+      for (int ww = 0; ww < W; ++ww) dot = cadd(dot, s_partc[ww * kWave + lane]);
     }
+    tau = 1.0 / (nup * (nup + s_axj[j & 1]));
+    if (eligible && lane != p) {
+      const double2 sdot = make_double2(-tau * dot.x, -tau * dot.y);
+      IDBF_ROWS_FROM(j, a[i] = cfma(s_v[row0 + i], sdot, a[i]))
+    }
+    // the pivot column becomes (alpha, 0, ..., 0) from row j down
     if (lane == p) {
       const double2 alpha = s_alpha;
-#pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const int row = row0 + i;
-        if (row == j) a[i] = alpha;
-        if (row > j) a[i] = make_double2(0.0, 0.0);
-      }
+      IDBF_ROWS_FROM(j, a[i] = (row0 + i == j) ? alpha : make_double2(0.0, 0.0))
       pivoted = true;
-    } else if (eligible && wave_has_rows) {
-      const double2 sdot = make_double2(-tau * dot.x, -tau * dot.y);
-#pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (row0 + i >= j && row0 + i < s) a[i] = cfma(s_v[row0 + i], sdot, a[i]);
     }
+    if (threadIdx.x == 0) s_piv[j] = p;
     k = j + 1;
-    if constexpr (W == 1) __syncthreads();
   }
   if (k == 0) zero_block = true;  // no pivot taken: keep the first candidate, T = 0
   if (zero_block) {
@@ -344,65 +371,56 @@ __global__ __launch_bounds__(64 * W) void id_kernel(IdArgs A) {
     if (threadIdx.x == 0) s_piv[0] = 0;
   }
   if (overflow && threadIdx.x == 0) atomicOr(A.status, kErrRank);
-  __syncthreads();
+  __syncthreads();  // every read of the partial sums is done: s_raw now holds R rows
+
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int row = row0 + i;
+    if (row < k) s_R[row * kWave + lane] = zero_block ? make_double2(0.0, 0.0) : a[i];
+  }
   const uint64_t msk = __ballot(pivoted && lane < c);
   if (threadIdx.x < k) s_srank[threadIdx.x] = __popcll(msk & lanes_below(s_piv[threadIdx.x]));
   __syncthreads();
+  if (w != 0) return;
 
   const int below = __popcll(msk & lanes_below(lane));
   const int r = c - k;
   const bool redundant = (lane < c) && !pivoted;
-  if (w == 0) {
-    if (lane == 0) {
-      A.rank[q] = k;
-      A.mask[q] = msk;
-    }
-    if (pivoted && lane < c) A.skel_out[q * kMaxCand + below] = gidx;
+  if (lane == 0) {
+    A.rank[q] = k;
+    A.mask[q] = msk;
   }
-  // Back-substitution T = R11^{-1} R12, one redundant candidate per lane, rows
-  // from the last up: t_ii = r_ii / R[ii][piv_ii], then r_i -= R[i][piv_ii] t_ii
-  // for i < ii.  Column piv_ii of R11 and the row t_ii go through double-buffered
-  // LDS slots, so each step needs two barriers.
+  if (pivoted && lane < c) A.skel_out[q * kMaxCand + below] = gidx;
+  if (!redundant) return;
+  // back-substitution on this lane's column of R12, t overwriting it in LDS:
+  //   t_ii = (r_ii - sum_{l > ii} R[ii][piv_l] t_l) / R[ii][piv_ii]
   const int jr = lane - below;
   const int64_t off = A.T_off ? A.T_off[q] : q * (int64_t)kSlot;
   for (int ii = k - 1; ii >= 0; --ii) {
-    const int buf = ii & 1;
-    const int pp = s_piv[ii];
-    if (lane == pp) {
-#pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (row0 + i <= ii) s_col[buf][row0 + i] = a[i];
-    }
-    __syncthreads();
-    if (redundant && row0 <= ii && ii < row0 + R) {
-      double2 t = make_double2(0.0, 0.0);
-      if (!zero_block) {
-        const double2 d = s_col[buf][ii];
-        const double inv = 1.0 / cabs2(d);
-#pragma unroll
-        for (int i = 0; i < R; ++i)
-          if (row0 + i == ii) t = cmul(a[i], make_double2(d.x * inv, -d.y * inv));
+    double2 acc = s_R[ii * kWave + lane];
+    if (!zero_block) {
+      for (int l = ii + 1; l < k; ++l) {
+        const double2 rl = s_R[ii * kWave + s_piv[l]];
+        acc = cfma(make_double2(-rl.x, -rl.y), s_R[l * kWave + lane], acc);
       }
-      s_t[buf][lane] = t;
-      const int sr = s_srank[ii];
-      const int64_t e = off + (isV ? (int64_t)jr * k + sr : (int64_t)sr * r + jr);
-      A.T128[e] = t;
-      if (A.T64) A.T64[e] = make_float2((float)t.x, (float)t.y);
+      const double2 d = s_R[ii * kWave + s_piv[ii]];
+      const double inv = 1.0 / cabs2(d);
+      acc = cmul(acc, make_double2(d.x * inv, -d.y * inv));
     }
-    __syncthreads();
-    if (redundant && row0 < ii) {
-      const double2 t = s_t[buf][lane];
-      const double2 mt = make_double2(-t.x, -t.y);
-#pragma unroll
-      for (int i = 0; i < R; ++i)
-        if (row0 + i < ii) a[i] = cfma(s_col[buf][row0 + i], mt, a[i]);
-    }
+    s_R[ii * kWave + lane] = acc;
+    const int sr = s_srank[ii];
+    const int64_t e = off + (isV ? (int64_t)jr * k + sr : (int64_t)sr * r + jr);
+    A.T128[e] = acc;
+    if (A.T64) A.T64[e] = make_float2((float)acc.x, (float)acc.y);
   }
 }
+#undef IDBF_ROWS_FROM
 
 }  // namespace
 
 int id_batch_waves(int s_max) { return std::max(1, std::min(kMaxSamples / kRPW, (s_max + kRPW - 1) / kRPW)); }
+
+hipError_t launch_qr_waves(const IdArgs& a, int64_t n, int waves, hipStream_t st);
 
 hipError_t launch_select(const IdArgs& a, hipStream_t st) {
   if (a.n_ids <= 0) return hipSuccess;
@@ -419,8 +437,22 @@ hipError_t launch_id_batch(const IdArgs& a, hipStream_t st) {
 
 hipError_t launch_qr(const IdArgs& a, hipStream_t st) {
   if (a.n_ids <= 0) return hipSuccess;
-  const dim3 grid((unsigned)a.n_ids);
-  switch (id_batch_waves(a.s_max)) {
+  if (!a.order) return launch_qr_waves(a, a.n_ids, id_batch_waves(a.s_max), st);
+  // one launch per bucket of IDs that need the same number of wavefronts
+  IdArgs b = a;
+  for (int wv = 1; wv <= kMaxSamples / kRPW; ++wv) {
+    const int64_t cnt = a.bucket_off[wv] - a.bucket_off[wv - 1];
+    if (cnt <= 0) continue;
+    b.order = a.order + a.bucket_off[wv - 1];
+    hipError_t e = launch_qr_waves(b, cnt, wv, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_qr_waves(const IdArgs& a, int64_t n, int waves, hipStream_t st) {
+  const dim3 grid((unsigned)n);
+  switch (waves) {
     case 1: hipLaunchKernelGGL(id_kernel<1>, grid, dim3(64), 0, st, a); break;
     case 2: hipLaunchKernelGGL(id_kernel<2>, grid, dim3(128), 0, st, a); break;
     case 3: hipLaunchKernelGGL(id_kernel<3>, grid, dim3(192), 0, st, a); break;

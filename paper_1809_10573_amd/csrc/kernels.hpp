@@ -28,6 +28,8 @@ struct IdArgs {
   int oversample;
   int s_max;                  // largest sample count of the batch (sizes the launch)
   int32_t* samp_pos;          // kMaxSamples sample positions per ID (scratch)
+  const int32_t* order;       // QR launch: IDs grouped by wavefronts needed, or null
+  int64_t bucket_off[9];      // host: order[bucket_off[w-1] .. bucket_off[w]) need w waves
   int32_t* rank;
   uint64_t* mask;
   int32_t* skel_out;     // kMaxCand entries per ID
@@ -42,6 +44,13 @@ hipError_t launch_select(const IdArgs& a, hipStream_t st);
 hipError_t launch_qr(const IdArgs& a, hipStream_t st);
 hipError_t launch_id_batch(const IdArgs& a, hipStream_t st);
 int id_batch_waves(int s_max);
+constexpr int kRowsPerWaveQR = 16;  // sampled rows per wavefront in the QR kernel
+// IDs grouped by ceil(samples / 16): counts[0..7] += bucket sizes (pass 1),
+// then order[] filled from per-bucket cursors (pass 2, cursors pre-set to the
+// bucket offsets).
+hipError_t launch_bucket_count(const int32_t* samples, int64_t n, unsigned long long* counts, hipStream_t st);
+hipError_t launch_bucket_fill(const int32_t* samples, int64_t n, unsigned long long* cursors, int32_t* order,
+                              hipStream_t st);
 
 // Work of a finished level: out[0] += sum 16 sum_{j<k}(s-j)(c-j) + 4 k^2 (c-k)
 // (FP64 flops), out[1] += sum k (c - k) (T entries), out[2] += sum s c (samples).
@@ -116,7 +125,21 @@ hipError_t launch_sample_dense(const PhaseDev& ph, const double* X, const double
                                double2* out, hipStream_t st);
 
 // ------------------------------------------------------------- apply
+// Everything one apply stage needs of an ID, in one 32-byte record.
+struct ApplyMeta {
+  int64_t t_off;     // first T entry (even)
+  uint64_t mask;     // bit l: candidate l is a skeleton
+  int32_t cand_beg;  // input (V) / output (U) segment start
+  int32_t skel_off;  // output (V) / input (U) segment start
+  int32_t c;         // candidates
+  int32_t k;         // rank
+};
+hipError_t launch_pack_meta(const int64_t* t_off, const uint64_t* mask, const int32_t* cand_beg,
+                            const int32_t* skel_off, const int32_t* cand_len, const int32_t* rank, int64_t n,
+                            ApplyMeta* out, hipStream_t st);
+
 struct StageArgs {
+  const ApplyMeta* meta;   // per ID (V, U stages)
   int64_t n;               // IDs (V stage) or units (U stage) or U_H IDs (S stage)
   int nn;                  // U stage: nodes per partner row of the level (2^(L-t+1))
   int64_t nrhs;
