@@ -234,7 +234,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 
   const int64_t q = A.order ? A.order[blockIdx.x] : (int64_t)blockIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform: row tests branch on SGPRs
   const int nthreads = kWave * W;
   const int cb = A.cand_beg[q], c = A.cand_len[q];
   const int ab = A.allow_beg[q], na = A.allow_len[q];
@@ -282,9 +282,18 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   int k = 0;
   bool zero_block = false, overflow = false;
   for (int j = 0;; ++j) {
-    // residual column norms over rows >= j
+    // residual column norms over rows >= j (two independent sums)
+    const bool live = row0 + R > j;  // wave-uniform: this wave holds rows >= j
     double part = 0.0;
-    IDBF_ROWS_FROM(j, part += cabs2(a[i]))
+    if (live) {
+      double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const double t = (row0 + i >= j) ? cabs2(a[i]) : 0.0;
+        if (i & 1) p1 += t; else p0 += t;
+      }
+      part = p0 + p1;
+    }
     double nrm2 = part;
     if constexpr (W > 1) {
       s_part[w * kWave + lane] = part;
@@ -314,34 +323,41 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     if (near == 0) break;  // no finite residual norm left (cannot happen for finite input)
     const int p = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)near) - 1);
     // Householder vector of the pivot column (rows >= j): lane p of every wave
-    // publishes its own rows to the wave's slice of LDS (no workgroup barrier);
-    // v_i = a_i(p) for i > j and v_j = x_j - alpha, alpha = -(x_j/|x_j|) nu_p,
-    // tau = 2 / |v|^2 = 1 / (nu_p (nu_p + |x_j|)).
+    // publishes its own rows to the wave's slice of LDS (no workgroup barrier),
+    // zero above row j, so that rows < j drop out of the dot and the update
+    // exactly; v_i = a_i(p) for i > j and v_j = x_j - alpha,
+    // alpha = -(x_j/|x_j|) nu_p, tau = 2 / |v|^2 = 1 / (nu_p (nu_p + |x_j|)).
     const double nup = readlane(nu, p);
-    if (lane == p) {
-      IDBF_ROWS_FROM(j, {
-        if (row0 + i == j) {
-          const double2 xj = a[i];
-          const double axj = sqrt(cabs2(xj));
-          double2 vj;
-          if (axj > 0.0) {
-            s_alpha = make_double2(-xj.x / axj * nup, -xj.y / axj * nup);
-            const double sc = (axj + nup) / axj;
-            vj = make_double2(xj.x * sc, xj.y * sc);
-          } else {
-            s_alpha = make_double2(-nup, 0.0);
-            vj = make_double2(nup, 0.0);
-          }
-          s_v[row0 + i] = vj;
-          s_axj[j & 1] = axj;
+    if (lane == p && live) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) s_v[row0 + i] = (row0 + i >= j) ? a[i] : make_double2(0.0, 0.0);
+      if (row0 <= j) {  // this wave holds row j: form the head (same-lane LDS accesses are ordered)
+        const double2 xj = s_v[j];
+        const double axj = sqrt(cabs2(xj));
+        double2 vj;
+        if (axj > 0.0) {
+          s_alpha = make_double2(-xj.x / axj * nup, -xj.y / axj * nup);
+          const double sc = (axj + nup) / axj;
+          vj = make_double2(xj.x * sc, xj.y * sc);
         } else {
-          s_v[row0 + i] = a[i];
+          s_alpha = make_double2(-nup, 0.0);
+          vj = make_double2(nup, 0.0);
         }
-      })
+        s_v[j] = vj;
+        s_axj[j & 1] = axj;
+      }
     }
     wave_lds_sync();
     double2 dot = make_double2(0.0, 0.0);
-    IDBF_ROWS_FROM(j, dot = cfma_conj(s_v[row0 + i], a[i], dot))
+    if (live) {
+      double2 d0 = make_double2(0.0, 0.0), d1 = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        if (i & 1) d1 = cfma_conj(s_v[row0 + i], a[i], d1);
+        else d0 = cfma_conj(s_v[row0 + i], a[i], d0);
+      }
+      dot = cadd(d0, d1);
+    }
     double tau;
     if constexpr (W > 1) {
       s_partc[w * kWave + lane] = dot;
@@ -351,16 +367,21 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       for (int ww = 0; ww < W; ++ww) dot = cadd(dot, s_partc[ww * kWave + lane]);
     }
     tau = 1.0 / (nup * (nup + s_axj[j & 1]));
-    if (eligible && lane != p) {
-      const double2 sdot = make_double2(-tau * dot.x, -tau * dot.y);
-      IDBF_ROWS_FROM(j, a[i] = cfma(s_v[row0 + i], sdot, a[i]))
+    if (live) {
+      if (eligible && lane != p) {
+        const double2 sdot = make_double2(-tau * dot.x, -tau * dot.y);
+#pragma unroll
+        for (int i = 0; i < R; ++i) a[i] = cfma(s_v[row0 + i], sdot, a[i]);
+      }
+      // the pivot column becomes (alpha, 0, ..., 0) from row j down
+      if (lane == p) {
+        const double2 alpha = s_alpha;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+          if (row0 + i >= j) a[i] = (row0 + i == j) ? alpha : make_double2(0.0, 0.0);
+      }
     }
-    // the pivot column becomes (alpha, 0, ..., 0) from row j down
-    if (lane == p) {
-      const double2 alpha = s_alpha;
-      IDBF_ROWS_FROM(j, a[i] = (row0 + i == j) ? alpha : make_double2(0.0, 0.0))
-      pivoted = true;
-    }
+    if (lane == p) pivoted = true;
     if (threadIdx.x == 0) s_piv[j] = p;
     k = j + 1;
   }
