@@ -3,8 +3,9 @@
 One step = the whole hot path on the N = 2^20 FIO workload
 (Phi = x xi + c(x)|xi|, c(x) = (2 + sin 2 pi x)/8, leaf 16, tol 1e-6,
 oversampling t = 2): construction (FP64 IDs on the GPU), one 1-RHS apply in
-complex64 and one apply to 1024 right-hand sides in complex64, all inputs
-resident in HBM.  Prints one JSON line.
+complex64, and one apply to 1024 right-hand sides in complex64 on the matrix
+cores in each of the two precisions (FP32 MFMA; BF16 hi/lo split products
+with FP32 accumulation), all inputs resident in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--nrhs 1024] [--no-cpu-baseline]
 
@@ -34,6 +35,7 @@ METRIC = "IDBF apply GB/s+GFLOP/s & construct ms, N=2^20, vs plain FP64 at rel.e
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK = 78.6e12
 FP32_MFMA_PEAK = 157.3e12
+BF16_MFMA_PEAK = 2500e12
 
 WORKLOAD = dict(N=1 << 20, leaf=16, tol=1e-6, oversample=2, a=1.0, freq=1.0, c0=2.0, cdiv=8.0)
 
@@ -118,18 +120,21 @@ def main() -> int:
                           device=dev, stream=stream)
         t_con = (time.perf_counter() - t0) * 1e3
         fac.reserve(nrhs, B.C64)  # apply workspace, allocated outside the timed applies
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
         e[0].record(stream)
         fac.apply(x1, y1, stream=stream)
         e[1].record(stream)
         e[2].record(stream)
         fac.apply(XM, YM, stream=stream)
         e[3].record(stream)
+        e[4].record(stream)
+        fac.apply(XM, YM, dtype=B.C64_BF16X3, stream=stream)
+        e[5].record(stream)
         torch.cuda.synchronize()
         if record is not None:
             record.append(dict(construct_ms=t_con, apply1_ms=e[0].elapsed_time(e[1]),
-                               applyn_ms=e[2].elapsed_time(e[3]), prof=fac.profile(reset=True),
-                               info=fac.info()))
+                               applyn_ms=e[2].elapsed_time(e[3]), applyb_ms=e[4].elapsed_time(e[5]),
+                               prof=fac.profile(reset=True), info=fac.info()))
         return fac
 
     for _ in range(args.warmup):
@@ -149,6 +154,7 @@ def main() -> int:
     bytes1 = (info["nnz_T"] + info["nnz_S"]) * elem + 8 * info["n_ids"] + 2 * N * elem
     apply1_ms = float(np.mean([r["apply1_ms"] for r in recs]))
     applyn_ms = float(np.mean([r["applyn_ms"] for r in recs]))
+    applyb_ms = float(np.mean([r["applyb_ms"] for r in recs]))
     construct_ms = float(np.mean([r["construct_ms"] for r in recs]))
     flops_n = 8.0 * (info["nnz_T"] + info["nnz_S"]) * nrhs
     value = bytes1 / apply1_ms / 1e6
@@ -165,9 +171,10 @@ def main() -> int:
     if dom_name == "id_qr":
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=FP64_VALU_PEAK / 1e12, unit="TFLOP/s")
-    elif dom_name.startswith("applyn"):
+    elif dom_name.startswith("applyn") or dom_name.startswith("applyb"):
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=FP32_MFMA_PEAK / 1e12, unit="TFLOP/s")
+        peak = FP32_MFMA_PEAK if dom_name.startswith("applyn") else BF16_MFMA_PEAK
+        roof = dict(bound="mfma", achieved=achieved, peak=peak / 1e12, unit="TFLOP/s")
     else:
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s")
@@ -179,9 +186,12 @@ def main() -> int:
     # accuracy (outside the timed region): complex64 apply vs the FP64 (complex128)
     # apply of the same factors on 8 probe vectors, and the paper's epsilon^a on 256 rows
     probes = torch.as_tensor(I.gaussian_vectors(N, 8, 5), device=dev)
-    y64 = fac.apply(probes.to(torch.complex64).contiguous()).to(torch.complex128)
+    p64 = probes.to(torch.complex64).contiguous()
+    y64 = fac.apply(p64).to(torch.complex128)
+    ybf = fac.apply(p64, dtype=B.C64_BF16X3).to(torch.complex128)
     y128 = fac.apply(probes)
     rel64 = float(torch.linalg.norm(y64 - y128) / torch.linalg.norm(y128))
+    relbf = float(torch.linalg.norm(ybf - y128) / torch.linalg.norm(y128))
     rows = np.sort(np.random.default_rng(0).choice(N, 256, replace=False))
     ex = torch.zeros(256, dtype=torch.complex128, device=dev)
     cols = torch.arange(N, dtype=torch.int32, device=dev)
@@ -200,8 +210,9 @@ def main() -> int:
                    "nrhs": [1, nrhs]},
         "construct_ms": construct_ms, "apply1_ms": apply1_ms, "applyn_ms": applyn_ms,
         "applyn_gflops": flops_n / applyn_ms / 1e6,
+        "applyb_ms": applyb_ms, "applyb_gflops": flops_n / applyb_ms / 1e6,
         "id_fp64_tflops": agg.get("id_qr", {}).get("flops", 0) / max(agg.get("id_qr", {}).get("ms", 1), 1e-9) / 1e9,
-        "rel_err_c64_vs_c128": rel64, "eps_a_256rows": eps_a,
+        "rel_err_c64_vs_c128": rel64, "rel_err_bf16x3_vs_c128": relbf, "eps_a_256rows": eps_a,
         "nnz": info["nnz_T"] + info["nnz_S"], "rank_max": info["rank_max"],
         "kernels": {k: {"launches_per_step": v["launches"] / len(recs),
                         "ms_per_step": v["ms"] / len(recs)} for k, v in sorted(agg.items())},

@@ -50,7 +50,11 @@ enum { IDBF_PHASE_DFT = 0, IDBF_PHASE_FIO = 1 };
 
 /* Apply precisions: complex128 arithmetic on FP64 factors, or complex64
  * arithmetic on FP32 copies of the same FP64-constructed factors. */
-enum { IDBF_C128 = 0, IDBF_C64 = 1 };
+/* Element types / arithmetic of the apply.  IDBF_C64_BF16X3 keeps complex64
+ * input and output but forms the products of the many-RHS stages from BF16
+ * hi/lo splits (a = a_hi + a_lo; a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi) on
+ * the matrix cores with FP32 accumulation. */
+enum { IDBF_C128 = 0, IDBF_C64 = 1, IDBF_C64_BF16X3 = 2 };
 
 /* The two ID families of a level: U (row IDs) and V (column IDs). */
 enum { IDBF_SIDE_U = 0, IDBF_SIDE_V = 1 };
@@ -106,7 +110,9 @@ idbf_status idbf_construct(const idbf_phase* phase, const double* X, const doubl
  *   y      device, (N, nrhs) complex of the given dtype; fully overwritten;
  *          must not overlap x.
  *   nrhs   >= 0 (0 is a no-op).
- *   dtype  IDBF_C128 (FP64 factors and arithmetic) or IDBF_C64 (FP32).
+ *   dtype  IDBF_C128 (FP64 factors and arithmetic), IDBF_C64 (FP32: VALU
+ *          for nrhs = 1, FP32 MFMA for nrhs > 1) or IDBF_C64_BF16X3 (complex64
+ *          data, BF16 hi/lo split MFMA products, FP32 accumulation).
  * Asynchronous on stream.  Intermediate vectors live in a workspace owned by
  * the handle, grown (hipMalloc, which synchronizes) when nrhs exceeds what
  * was used before; calls on one handle must not overlap in time.

@@ -1,0 +1,278 @@
+// Many-RHS apply of the IDBF factors on the matrix cores, complex64 in/out
+// (eq. finishIDBF read right to left, the same stages as the VALU apply).
+//
+// Every stage unit is a small dense product on a block of right-hand sides:
+//   V stage (the two IDs (C, 2P), (C, 2P + 1) sharing one candidate segment):
+//                       z_h[skel_off_h + i] = u[skel_h,i] + sum_j T_h(i, j) u[red_h,j] (M = k_0 + k_1, K = c)
+//   S stage (U_H ID):   w[rbeg + i]       = sum_b sum_col S_b(i, col) z[cbeg_b + col] (M = k_R, K = sum k_C')
+//   U stage (a unit):   v[cand_beg + l]   = sum_h ( l in skel_h ? w_h[b] : sum_i T_h(i, red(l)) w_h[i] )
+//                                                                          (M = c, K = k_0 + k_1)
+// A (M x K complex: the factor entries and the identity parts) is staged in
+// LDS once per workgroup; every input row is read once per unit.  Rows of the
+// stage vectors are (row, rhs) complex64, right-hand sides fastest.
+//
+// Complex arithmetic on real MFMA: with B' the interleaved (re, im) rows and
+// B~ the same rows with each pair mapped (re, im) -> (-im, re),
+//   C' = A_re B' + A_im B~
+// gives the interleaved complex product.  A lane holds two complex right-hand
+// sides (4 real columns): real column 4 j + t of the wave's block belongs to
+// N-tile t, so B~ is a register shuffle, never a cross-lane move.
+//
+// Precision: FP32 MFMA (v_mfma_f32_32x32x2_f32), or the BF16 hi/lo split
+// a ~= a_hi + a_lo with a b ~= a_hi b_hi + a_hi b_lo + a_lo b_hi on
+// v_mfma_f32_32x32x16_bf16, FP32 accumulation.  Both consume the same K order:
+// lanes 0-31 take K indices kc + e, lanes 32-63 kc + 8 + e (e < 8).
+#include <algorithm>
+
+#include "kernels.hpp"
+
+namespace idbf {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kMaxKg = 128;  // largest K of a unit (S stage: 4 blocks of <= 32)
+constexpr int kMaxMg = 64;   // largest M of a unit (U stage: c <= 64)
+constexpr int kRhsPerWave = 64;
+constexpr int kWavesG = 4;
+
+enum { kModeV = 0, kModeS = 1, kModeU = 2 };
+
+struct Unit {
+  int M, K;
+};
+
+__device__ __forceinline__ int lda_for(int K) { return ((K + 15) & ~15) + 2; }
+
+// Stage the unit's A (M x K complex, zero padded to Mpad x roundup(K, 16))
+// into LDS with the input row of every K index (s_src) and the output row of
+// every M index (s_out).
+//   V unit (C, P): the IDs (C, 2P) and (C, 2P + 1) share the candidate
+//     segment: rows [0, k0) of A are [I T_0] of the first (skeleton columns
+//     carry the identity), rows [k0, k0 + k1) those of the second.
+//   U unit: A = [P_0 P_1], P_h(l, i) = 1 if l is the i-th skeleton of ID h,
+//     T_h(i, j) if l is its j-th redundant candidate.
+//   S (U_H ID): A = [S_1 ... S_nsub].
+template <int MODE>
+__device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_out, int* s_red) {
+  const int64_t q = blockIdx.x;
+  const float2* T = static_cast<const float2*>(A.T);
+  Unit u{};
+  if constexpr (MODE == kModeS) {
+    const int64_t b0 = q * A.nsub;
+    const int rl = A.rlen[b0], rbg = A.rbeg[b0];
+    int K = 0;
+    for (int jb = 0; jb < A.nsub; ++jb) K += A.clen[b0 + jb];
+    u = Unit{rl, K};
+    const int lda = lda_for(K);
+    for (int e = threadIdx.x; e < 32 * lda; e += blockDim.x) s_A[e] = make_float2(0.f, 0.f);
+    for (int i = threadIdx.x; i < rl; i += blockDim.x) s_out[i] = rbg + i;
+    __syncthreads();
+    int off = 0;
+    for (int jb = 0; jb < A.nsub; ++jb) {
+      const int cl = A.clen[b0 + jb], cbg = A.cbeg[b0 + jb];
+      const int64_t so = A.T_off[b0 + jb];
+      for (int col = threadIdx.x; col < cl; col += blockDim.x) s_src[off + col] = cbg + col;
+      for (int e = threadIdx.x; e < rl * cl; e += blockDim.x) s_A[(e % rl) * lda + off + e / rl] = T[so + e];
+      off += cl;
+    }
+  } else {
+    const int64_t P = q / A.nn, node = q % A.nn;
+    const ApplyMeta m0 = A.meta[2 * P * A.nn + node];
+    const ApplyMeta m1 = A.meta[2 * P * A.nn + node + A.nn];
+    const int c = m0.c, k0 = m0.k;
+    const bool isV = (MODE == kModeV);
+    u = isV ? Unit{k0 + m1.k, c} : Unit{c, k0 + m1.k};
+    const int lda = lda_for(u.K);
+    for (int e = threadIdx.x; e < kMaxMg * lda; e += blockDim.x) s_A[e] = make_float2(0.f, 0.f);
+    __syncthreads();  // zero fill before the identity entries
+    for (int e = threadIdx.x; e < 2 * kWave; e += blockDim.x) {  // (ID h, candidate position l)
+      const int h = e >> 6, l = e & (kWave - 1);
+      const ApplyMeta& m = h ? m1 : m0;
+      const int base = h ? k0 : 0;  // first row (V) or column (U) of ID h in A
+      if (l < m.k) {
+        if (isV) s_out[base + l] = m.skel_off + l;
+        else s_src[base + l] = m.skel_off + l;
+      }
+      if (l < c) {
+        if (h == 0) {
+          if (isV) s_src[l] = m.cand_beg + l;
+          else s_out[l] = m.cand_beg + l;
+        }
+        const int below = __popcll(m.mask & lanes_below(l));
+        if ((m.mask >> l) & 1ull) {
+          if (isV) s_A[(base + below) * lda + l] = make_float2(1.f, 0.f);
+          else s_A[l * lda + base + below] = make_float2(1.f, 0.f);
+        } else {
+          s_red[h * kMaxMg + l - below] = l;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const ApplyMeta& m = h ? m1 : m0;
+      const int k = m.k, r = c - k, base = h ? k0 : 0;
+      if (isV) {  // T_h(i, j) at j k + i
+        for (int e = threadIdx.x; e < k * r; e += blockDim.x)
+          s_A[(base + e % k) * lda + s_red[h * kMaxMg + e / k]] = T[m.t_off + e];
+      } else {    // T_h(i, j) at i r + j
+        for (int e = threadIdx.x; e < k * r; e += blockDim.x)
+          s_A[s_red[h * kMaxMg + e % r] * lda + base + e / r] = T[m.t_off + e];
+      }
+    }
+  }
+  __syncthreads();
+  return u;
+}
+
+__device__ __forceinline__ float2 ld2(const float2* p, bool ok) { return ok ? *p : make_float2(0.f, 0.f); }
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+template <int MODE, bool BF16>
+__global__ __launch_bounds__(64 * kWavesG) void apply_gemm(StageArgs A) {
+  extern __shared__ __attribute__((aligned(16))) float2 s_A[];
+  __shared__ int s_src[kMaxKg];
+  __shared__ int s_out[kMaxMg];
+  __shared__ int s_red[2 * kMaxMg];
+  const Unit u = stage_unit<MODE>(A, s_A, s_src, s_out, s_red);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  // V and U units: two wavefronts per block of right-hand sides, one per 32-row M-tile
+  constexpr int kTilesM = (MODE == kModeS) ? 1 : 2;
+  const int mt = w % kTilesM;
+  const int64_t rhs0 = (blockIdx.y * (int64_t)(blockDim.x / kWave / kTilesM) + w / kTilesM) * kRhsPerWave;
+  if (rhs0 >= A.nrhs || mt * 32 >= u.M) return;
+  const int half = lane >> 5, jj = lane & 31;
+  const int64_t nr = A.nrhs;
+  const int64_t n0 = rhs0 + 2 * jj;
+  const bool ok0 = n0 < nr, ok1 = n0 + 1 < nr;
+  const float2* in = static_cast<const float2*>(A.in);
+  const int lda = lda_for(u.K);
+
+  f32x16 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x16{};
+
+  for (int kc = 0; kc < u.K; kc += 16) {
+    float4 b[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int kk = kc + 8 * half + e;
+      const int row = kk < u.K ? s_src[kk] : -1;
+      const float2* p = in + (int64_t)(row < 0 ? 0 : row) * nr + n0;
+      const float2 v0 = ld2(p, row >= 0 && ok0), v1 = ld2(p + 1, row >= 0 && ok1);
+      b[e] = make_float4(v0.x, v0.y, v1.x, v1.y);
+    }
+    {
+      const float2* ap = s_A + (mt * 32 + jj) * lda + kc + 8 * half;
+      float2 a[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a[e] = ap[e];
+      if constexpr (!BF16) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float bt[4] = {b[e].x, b[e].y, b[e].z, b[e].w};
+          const float bs[4] = {-b[e].y, b[e].x, -b[e].w, b[e].z};
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e].x, bt[t], acc[t], 0, 0, 0);
+            acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e].y, bs[t], acc[t], 0, 0, 0);
+          }
+        }
+      } else {
+        bf16x8 arh, arl, aih, ail;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 h, l;
+          split_bf16(a[e].x, h, l);
+          arh[e] = h;
+          arl[e] = l;
+          split_bf16(a[e].y, h, l);
+          aih[e] = h;
+          ail[e] = l;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          bf16x8 bh, bl, sh, sl;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const float bt[4] = {b[e].x, b[e].y, b[e].z, b[e].w};
+            const float bs[4] = {-b[e].y, b[e].x, -b[e].w, b[e].z};
+            __bf16 h, l;
+            split_bf16(bt[t], h, l);
+            bh[e] = h;
+            bl[e] = l;
+            split_bf16(bs[t], h, l);
+            sh[e] = h;
+            sl[e] = l;
+          }
+          f32x16 c = acc[t];
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bh, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bl, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bh, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, sh, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, sl, c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, sh, c, 0, 0, 0);
+          acc[t] = c;
+        }
+      }
+    }
+  }
+
+  // epilogue: C row i = 32 mt + 8 (v / 4) + 4 half + v % 4, real column 4 jj + t
+  float2* out = static_cast<float2*>(A.out);
+  {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = mt * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+      if (i >= u.M) continue;
+      const float2 o0 = make_float2(acc[0][v], acc[1][v]);
+      const float2 o1 = make_float2(acc[2][v], acc[3][v]);
+      float2* p = out + (int64_t)s_out[i] * nr + n0;
+      if (ok0) p[0] = o0;
+      if (ok1) p[1] = o1;
+    }
+  }
+}
+
+}  // namespace
+
+// LDS bytes of A for a stage whose largest unit has K <= kmax_unit
+static size_t gemm_lds(int mode, int kmax_unit) {
+  return (size_t)(mode == kModeS ? 32 : kMaxMg) * (size_t)(((kmax_unit + 15) & ~15) + 2) * sizeof(float2);
+}
+
+hipError_t launch_apply_gemm(const StageArgs& a, int mode, int kmax_unit, bool bf16, hipStream_t st) {
+  if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
+  if (kmax_unit < 1 || kmax_unit > kMaxKg) return hipErrorInvalidValue;
+  const int tiles_m = (mode == kModeS) ? 1 : 2;
+  const int blocks_rhs = (int)std::min<int64_t>(kWavesG / tiles_m, (a.nrhs + kRhsPerWave - 1) / kRhsPerWave);
+  const int waves = blocks_rhs * tiles_m;
+  const int64_t per_block = (int64_t)blocks_rhs * kRhsPerWave;
+  const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
+  const dim3 block(64 * waves);
+  const size_t lds = gemm_lds(mode, kmax_unit);
+#define IDBF_GEMM(M, B) hipLaunchKernelGGL((apply_gemm<M, B>), grid, block, lds, st, a)
+  switch (mode) {
+    case kModeV:
+      if (bf16) IDBF_GEMM(kModeV, true); else IDBF_GEMM(kModeV, false);
+      break;
+    case kModeS:
+      if (bf16) IDBF_GEMM(kModeS, true); else IDBF_GEMM(kModeS, false);
+      break;
+    default:
+      if (bf16) IDBF_GEMM(kModeU, true); else IDBF_GEMM(kModeU, false);
+      break;
+  }
+#undef IDBF_GEMM
+  return hipGetLastError();
+}
+
+}  // namespace idbf

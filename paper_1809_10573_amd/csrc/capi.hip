@@ -628,8 +628,8 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     set_error("handle is NULL");
     return IDBF_EINVAL;
   }
-  if (nrhs < 0 || (dtype != IDBF_C128 && dtype != IDBF_C64)) {
-    set_error("nrhs must be >= 0 and dtype IDBF_C128 or IDBF_C64");
+  if (nrhs < 0 || (dtype != IDBF_C128 && dtype != IDBF_C64 && dtype != IDBF_C64_BF16X3)) {
+    set_error("nrhs must be >= 0 and dtype IDBF_C128, IDBF_C64 or IDBF_C64_BF16X3");
     return IDBF_EINVAL;
   }
   if (nrhs == 0) return IDBF_OK;
@@ -638,6 +638,8 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     return IDBF_EINVAL;
   }
   const bool fp64 = dtype == IDBF_C128;
+  const bool bf16 = dtype == IDBF_C64_BF16X3;
+  const bool mfma = bf16 || (!fp64 && nrhs > 1);  // matrix-core stage kernels
   const size_t elem = fp64 ? 16 : 8;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t half = size_t(h->max_skel) * size_t(nrhs) * elem;
@@ -662,8 +664,15 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     a.in = in;
     a.out = buf[cur];
     const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
-    const int pr = h->prof.begin(nrhs == 1 ? "apply1_v" : "applyn_v", st);
-    IDBF_HIP_CHECK(launch_apply_v(a, fp64, st));
+    const int pr = h->prof.begin(bf16 ? "applyb_v" : nrhs == 1 ? "apply1_v" : "applyn_v", st);
+    if (mfma) {  // units: the ID pairs (C, 2P), (C, 2P + 1) that share a candidate segment
+      StageArgs g = a;
+      g.n = b.n / 2;
+      g.nn = 1 << (h->L - t + 1);
+      IDBF_HIP_CHECK(launch_apply_gemm(g, 0, b.cand_max, bf16, st));
+    } else {
+      IDBF_HIP_CHECK(launch_apply_v(a, fp64, st));
+    }
     h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T) * nrhs);
     in = buf[cur];
     cur ^= 1;
@@ -686,8 +695,9 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     a.out = (h->H == 0) ? y : buf[cur];
     double bytes = double(h->nnz_S) * elem;
     if (h->H == 0) bytes += 2.0 * double(h->N) * nrhs * elem;
-    const int pr = h->prof.begin(nrhs == 1 ? "apply1_s" : "applyn_s", st);
-    IDBF_HIP_CHECK(launch_apply_s(a, fp64, st));
+    const int pr = h->prof.begin(bf16 ? "applyb_s" : nrhs == 1 ? "apply1_s" : "applyn_s", st);
+    if (mfma && !a.dense) IDBF_HIP_CHECK(launch_apply_gemm(a, 1, a.nsub * h->V[h->H - 1].rank_max, bf16, st));
+    else IDBF_HIP_CHECK(launch_apply_s(a, fp64, st));
     h->prof.end(pr, st, bytes, 8.0 * double(h->nnz_S) * nrhs);
     in = a.out;
     cur ^= 1;
@@ -710,8 +720,9 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     a.in = in;
     a.out = (t == 1) ? y : buf[cur];
     const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
-    const int pr = h->prof.begin(nrhs == 1 ? "apply1_u" : "applyn_u", st);
-    IDBF_HIP_CHECK(launch_apply_u(a, fp64, st));
+    const int pr = h->prof.begin(bf16 ? "applyb_u" : nrhs == 1 ? "apply1_u" : "applyn_u", st);
+    if (mfma) IDBF_HIP_CHECK(launch_apply_gemm(a, 2, 2 * b.rank_max, bf16, st));
+    else IDBF_HIP_CHECK(launch_apply_u(a, fp64, st));
     h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T) * nrhs);
     in = a.out;
     cur ^= 1;
@@ -721,7 +732,7 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
 
 idbf_status idbf_reserve(idbf_handle h, int64_t nrhs, int32_t dtype) {
   g_err[0] = 0;
-  if (!h || nrhs < 0 || (dtype != IDBF_C128 && dtype != IDBF_C64)) {
+  if (!h || nrhs < 0 || (dtype != IDBF_C128 && dtype != IDBF_C64 && dtype != IDBF_C64_BF16X3)) {
     set_error("reserve: invalid handle, nrhs or dtype");
     return IDBF_EINVAL;
   }

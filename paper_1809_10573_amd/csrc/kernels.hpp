@@ -165,5 +165,8 @@ struct StageArgs {
 hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st);
 hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st);
 hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st);
+// matrix-core stage kernels (complex64 data): mode 0 V, 1 S, 2 U; kmax_unit
+// bounds the K of every unit of the stage (sizes the LDS of A)
+hipError_t launch_apply_gemm(const StageArgs& a, int mode, int kmax_unit, bool bf16, hipStream_t st);
 
 }  // namespace idbf

@@ -209,6 +209,32 @@ def test_apply_many_rhs_and_repeat():
     assert fac.apply(empty).shape == (N, 0)
 
 
+@pytest.mark.parametrize("N,leaf,kind,tol,os_", [
+    (1024, 8, "dft", 1e-10, 1),     # odd L: the middle stage has 4 blocks per output
+    (16, 8, "dft", 1e-10, 1),       # H = 0: dense
+    (2048, 16, "fio", 1e-6, 2),
+    (256, 2, "fio", 1e-8, 1),
+])
+@pytest.mark.parametrize("nrhs", [2, 65, 300])
+def test_many_rhs_matrix_core_paths(N, leaf, kind, tol, os_, nrhs):
+    """complex64 apply on the matrix cores (FP32 MFMA, and BF16 hi/lo split
+    products with FP32 accumulation) against the oracle's FP64 apply of its
+    own factors (identical skeletons, so the factors agree to 1e-12); ragged
+    right-hand-side counts cover the tails of the 64-column blocks."""
+    ph = I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    F = oracle.build(ph, X, O, leaf, tol, oversample=os_)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=os_, device=DEV)
+    G = I.gaussian_vectors(N, nrhs, seed=nrhs)
+    Y_or = oracle.apply(F, G)
+    x = torch.as_tensor(G, device=DEV).to(torch.complex64)
+    for dtype, bound in ((B.C64, 2e-6), (B.C64_BF16X3, 2e-4)):
+        Y = fac.apply(x, dtype=dtype).cpu().numpy()
+        assert oracle.relative_error(Y, Y_or) < bound
+        col = np.linalg.norm(Y - Y_or, axis=0) / np.linalg.norm(Y_or, axis=0)
+        assert col.max() < 10 * bound       # every column, tails included
+
+
 def test_construct_errors():
     X, O = I.uniform_grid(64)
     with pytest.raises(B.IdbfError) as e:
@@ -246,3 +272,19 @@ def test_full_size_fio_sampled_rows(dtype):
     rows = np.sort(np.random.default_rng(4).choice(N, 48, replace=False))
     ex = oracle.matvec_rows(ph, X, O, g, rows)
     assert oracle.relative_error(y[rows], ex) < 1e-4
+
+
+def test_full_size_many_rhs_precisions():
+    """N = 2^20 workload, 8 probe vectors: complex64 FP32-MFMA apply within
+    1e-6 and BF16-split apply within 1e-3 of the FP64 apply of the same factors."""
+    N, leaf, tol = 1 << 20, 16, 1e-6
+    ph = I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=2, device=DEV)
+    P = torch.as_tensor(I.gaussian_vectors(N, 8, seed=5), device=DEV)
+    y128 = fac.apply(P)
+    p64 = P.to(torch.complex64)
+    for dtype, bound in ((B.C64, 1e-6), (B.C64_BF16X3, 1e-3)):
+        y = fac.apply(p64, dtype=dtype).to(torch.complex128)
+        rel = float(torch.linalg.norm(y - y128) / torch.linalg.norm(y128))
+        assert rel < bound, (dtype, rel)
