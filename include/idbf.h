@@ -120,6 +120,35 @@ idbf_status idbf_construct(const idbf_phase* phase, const double* X, const doubl
 idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype,
                        void* stream);
 
+/*
+ * idbf_construct_batched -- build `count` independent IDBFs (uneven N, phase,
+ * tol and leaf) in one lockstep level sweep: every phase of every level is
+ * issued for all instances, spread over up to 4 device-lifetime streams of
+ * the library, and the host waits once per phase for all of them.
+ *   phases, X, Omega, N, tol, leaf: host arrays of `count` entries, each entry
+ *          as in idbf_construct (X[i], Omega[i] device pointers).
+ *   opts   host, nullable; applies to every instance.  opts->stream is the
+ *          stream the inputs were produced on (waited for) and the stream the
+ *          handles keep.
+ *   out    host array of `count` handles; all NULL on failure.
+ * Same per-instance results (bit for bit) as idbf_construct.  On failure
+ * every instance is freed and idbf_last_error() names the failing instance.
+ */
+idbf_status idbf_construct_batched(int32_t count, const idbf_phase* phases, const double* const* X,
+                                   const double* const* Omega, const int64_t* N, const double* tol,
+                                   const int32_t* leaf, const idbf_opts* opts, idbf_handle* out);
+
+/*
+ * idbf_apply_batched -- y[i] = K~_i x[i] for `count` distinct handles, each as
+ * in idbf_apply with nrhs[i] right-hand sides of one dtype.  The instances run
+ * concurrently on the library's streams, ordered after prior work on `stream`;
+ * `stream` waits for all of them.  Workspaces are grown first (synchronizing
+ * `stream` when one grows); a batch whose workspaces were reserved allocates
+ * nothing.
+ */
+idbf_status idbf_apply_batched(int32_t count, const idbf_handle* hs, const void* const* x, void* const* y,
+                               const int64_t* nrhs, int32_t dtype, void* stream);
+
 /* Grow the handle's apply workspace (hipMalloc) so that idbf_apply with up to
  * nrhs right-hand sides of dtype allocates nothing.  Synchronizes the device
  * if it allocates. */

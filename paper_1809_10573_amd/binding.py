@@ -28,6 +28,7 @@ EXPORTED = [
     "idbf_opts_default", "idbf_construct", "idbf_apply", "idbf_destroy", "idbf_last_error",
     "idbf_get_info", "idbf_batch_sizes", "idbf_batch_export", "idbf_middle_sizes",
     "idbf_middle_export", "idbf_sample", "idbf_id_batch", "idbf_profile_read", "idbf_reserve",
+    "idbf_construct_batched", "idbf_apply_batched",
 ]
 FLAG_PROFILE = 1
 
@@ -92,6 +93,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
                                   VP, VP, VP, VP, VP]
     lib.idbf_profile_read.argtypes = [VP, P(KernelStat_t), I32, P(I32), I32]
     lib.idbf_reserve.argtypes = [VP, I64, I32]
+    lib.idbf_construct_batched.argtypes = [I32, P(Phase_t), P(VP), P(VP), P(I64), P(D), P(I32), P(Opts_t),
+                                           P(VP)]
+    lib.idbf_apply_batched.argtypes = [I32, P(VP), P(VP), P(VP), P(I64), I32, VP]
     for name in EXPORTED:
         if name not in ("idbf_opts_default", "idbf_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -237,6 +241,57 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
     _check(lib.idbf_construct(C.byref(ph), _ptr(Xd), _ptr(Od), Xd.numel(), float(tol), int(leaf),
                               C.byref(opts), C.byref(h)))
     return Factorization(h.value, Xd, Od)
+
+
+def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample: int = 1,
+                      mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
+                      stream=None) -> list:
+    """idbf_construct_batched: one lockstep construction of len(phases) instances."""
+    lib = load()
+    n = len(phases)
+    if not (len(Xs) == len(Omegas) == len(tols) == len(leafs) == n):
+        raise ValueError("per-instance argument lists must have equal lengths")
+    Xd = [_dev_f64(x, device) for x in Xs]
+    Od = [_dev_f64(o, device) for o in Omegas]
+    for x, o in zip(Xd, Od):
+        if x.numel() != o.numel():
+            raise ValueError("X and Omega must have the same length")
+    opts = Opts_t()
+    lib.idbf_opts_default(C.byref(opts))
+    opts.kmax, opts.oversample, opts.mem_cap_bytes = kmax, oversample, mem_cap_bytes
+    opts.flags = FLAG_PROFILE if profile else 0
+    opts.stream = _stream(stream)
+    ph = (Phase_t * n)(*[_phase(p) for p in phases])
+    xp = (C.c_void_p * n)(*[_ptr(x) for x in Xd])
+    op = (C.c_void_p * n)(*[_ptr(o) for o in Od])
+    Ns = (C.c_int64 * n)(*[x.numel() for x in Xd])
+    ts = (C.c_double * n)(*[float(t) for t in tols])
+    ls = (C.c_int32 * n)(*[int(v) for v in leafs])
+    out = (C.c_void_p * n)()
+    _check(lib.idbf_construct_batched(n, ph, xp, op, Ns, ts, ls, C.byref(opts), out))
+    return [Factorization(out[i], Xd[i], Od[i]) for i in range(n)]
+
+
+def apply_batched(facs, xs, ys=None, dtype: int | None = None, stream=None) -> list:
+    """idbf_apply_batched over distinct factorizations; returns the outputs."""
+    import torch
+    n = len(facs)
+    if len(xs) != n:
+        raise ValueError("one input per factorization")
+    if dtype is None:
+        dtype = C128 if xs[0].dtype == torch.complex128 else C64
+    want = torch.complex128 if dtype == C128 else torch.complex64
+    for x in xs:
+        if x.dtype != want or not x.is_contiguous():
+            raise ValueError(f"inputs must be contiguous {want} tensors")
+    if ys is None:
+        ys = [torch.empty_like(x) for x in xs]
+    hs = (C.c_void_p * n)(*[f._h.value for f in facs])
+    xp = (C.c_void_p * n)(*[_ptr(x) for x in xs])
+    yp = (C.c_void_p * n)(*[_ptr(y) for y in ys])
+    nr = (C.c_int64 * n)(*[1 if x.dim() == 1 else x.shape[1] for x in xs])
+    _check(load().idbf_apply_batched(n, hs, xp, yp, nr, int(dtype), _stream(stream)))
+    return ys
 
 
 def sample(phase, X, Omega, rows, cols, device="cuda", stream=None):

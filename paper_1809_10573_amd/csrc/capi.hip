@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -192,6 +193,24 @@ __global__ void check_points_kernel(const double* p, int64_t n, int32_t* bad) {
   if (!ok) atomicAdd(bad, 1);
 }
 
+// Values read back by the host between the phases of a level, staged in
+// pinned memory so that many handles can be driven in lockstep with one
+// synchronization per phase.
+struct HostStage {
+  int64_t st[8];
+  unsigned long long counts[8];
+  unsigned long long cursors[8];
+  int32_t bad[2];
+};
+
+struct LevelJob {
+  Batch b;
+  IdArgs ia;
+  const double* X = nullptr;
+  const double* Om = nullptr;
+  int side = 0, t = 0;
+};
+
 }  // namespace
 }  // namespace idbf
 
@@ -222,20 +241,18 @@ struct idbf_handle_s {
   double construct_ms = 0.0;
   hipStream_t stream = nullptr;
   Profiler prof;
+  HostStage* pin = nullptr;    // pinned: values the schedule reads back between phases
+  LevelJob job;                // the level batch being built
+  int qr_rec = -1;             // profiler record of that batch's QR launches
 
   ~idbf_handle_s() {
+    if (pin) (void)hipHostFree(pin);
     if (ws) (void)hipFree(ws);
     arena.release();
   }
 };
 
 namespace {
-
-idbf_status read_stats(idbf_handle_s* h, int64_t* host, int n) {
-  IDBF_HIP_CHECK(hipMemcpyAsync(host, h->stats, n * sizeof(int64_t), hipMemcpyDeviceToHost, h->stream));
-  IDBF_HIP_CHECK(hipStreamSynchronize(h->stream));
-  return IDBF_OK;
-}
 
 #define TRY(x)                          \
   do {                                  \
@@ -244,8 +261,25 @@ idbf_status read_stats(idbf_handle_s* h, int64_t* host, int n) {
   } while (0)
 #define TRYHIP(x) IDBF_HIP_CHECK(x)
 
-idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int side, int t) {
-  Batch b;
+idbf_status sync(idbf_handle_s* h) {
+  IDBF_HIP_CHECK(hipStreamSynchronize(h->stream));
+  return IDBF_OK;
+}
+
+// Construction of one level batch (U_t or V_t) in three phases; the host
+// reads the pinned staging area between them, after the handle's stream has
+// been synchronized.
+//   level_begin:  descriptors, segment scans, QR bucket counts
+//   level_ids:    sample selection, pivoted-QR IDs, rank scan
+//   level_finish: skeleton compaction, packed per-ID records
+idbf_status level_begin(idbf_handle_s* h, const double* X, const double* Om, int side, int t) {
+  LevelJob& J = h->job;
+  J = LevelJob{};
+  J.X = X;
+  J.Om = Om;
+  J.side = side;
+  J.t = t;
+  Batch& b = J.b;
   b.side = side;
   b.t = t;
   b.n = int64_t(2) << h->L;
@@ -300,10 +334,18 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   TRYHIP(hipMemsetAsync(h->bucket, 0, 8 * sizeof(unsigned long long), h->stream));
   TRYHIP(launch_bucket_count(b.samples, n, h->bucket, h->stream));
   h->prof.end(pr, h->stream);
-  unsigned long long counts[8];
-  TRYHIP(hipMemcpyAsync(counts, h->bucket, sizeof counts, hipMemcpyDeviceToHost, h->stream));
-  int64_t st[8];
-  TRY(read_stats(h, st, 8));
+  TRYHIP(hipMemcpyAsync(h->pin->counts, h->bucket, sizeof h->pin->counts, hipMemcpyDeviceToHost, h->stream));
+  TRYHIP(hipMemcpyAsync(h->pin->st, h->stats, sizeof h->pin->st, hipMemcpyDeviceToHost, h->stream));
+  return IDBF_OK;
+}
+
+idbf_status level_ids(idbf_handle_s* h) {
+  LevelJob& J = h->job;
+  Batch& b = J.b;
+  const int side = J.side, t = J.t;
+  const int64_t n = b.n;
+  Arena& A = h->arena;
+  const int64_t* st = h->pin->st;
   b.n_T = st[0];
   b.tb_max = st[1];
   b.cand_max = (int)st[3];
@@ -321,10 +363,11 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   TRY(A.get(std::max<int64_t>(b.n_T, 1), &b.T128));
   TRY(A.get(std::max<int64_t>(b.n_T, 1), &b.T64));
 
-  IdArgs ia{};
+  IdArgs& ia = J.ia;
+  ia = IdArgs{};
   ia.ph = h->ph;
-  ia.X = X;
-  ia.Om = Om;
+  ia.X = J.X;
+  ia.Om = J.Om;
   ia.side = side;
   ia.n_ids = n;
   ia.cand_idx = b.cand_arr;
@@ -342,13 +385,11 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   ia.samp_pos = h->samp_pos;
   ia.order = h->order;
   ia.bucket_off[0] = 0;
-  for (int w = 1; w <= 8; ++w) ia.bucket_off[w] = ia.bucket_off[w - 1] + (int64_t)counts[w - 1];
-  {
-    unsigned long long cursors[8];
-    for (int w = 0; w < 8; ++w) cursors[w] = (unsigned long long)ia.bucket_off[w];
-    TRYHIP(hipMemcpy(h->bucket + 8, cursors, sizeof cursors, hipMemcpyHostToDevice));
-    TRYHIP(launch_bucket_fill(b.samples, n, h->bucket + 8, h->order, h->stream));
-  }
+  for (int w = 1; w <= 8; ++w) ia.bucket_off[w] = ia.bucket_off[w - 1] + (int64_t)h->pin->counts[w - 1];
+  for (int w = 0; w < 8; ++w) h->pin->cursors[w] = (unsigned long long)ia.bucket_off[w];
+  TRYHIP(hipMemcpyAsync(h->bucket + 8, h->pin->cursors, sizeof h->pin->cursors, hipMemcpyHostToDevice,
+                        h->stream));
+  TRYHIP(launch_bucket_fill(b.samples, n, h->bucket + 8, h->order, h->stream));
   ia.rank = b.rank;
   ia.mask = b.mask;
   ia.skel_out = h->scratch;
@@ -356,7 +397,7 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   ia.T64 = b.T64;
   ia.T_off = b.T_off;
   ia.status = h->status;
-  pr = h->prof.begin("id_select", h->stream);
+  int pr = h->prof.begin("id_select", h->stream);
   TRYHIP(launch_select(ia, h->stream));
   h->prof.end(pr, h->stream);
   const int pq = h->prof.begin("id_qr", h->stream);
@@ -369,11 +410,22 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   TRYHIP(launch_scan_i32(b.rank, n, b.skel_off, nullptr, h->stats, h->stream));
   TRYHIP(hipMemcpyAsync(h->stats + 7, h->status, sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
   h->prof.end(pr, h->stream);
-  TRY(read_stats(h, st, 8));
+  h->qr_rec = pq;  // its flop count is attached once the work counters are back
+  TRYHIP(hipMemcpyAsync(h->pin->st, h->stats, sizeof h->pin->st, hipMemcpyDeviceToHost, h->stream));
+  return IDBF_OK;
+}
+
+idbf_status level_finish(idbf_handle_s* h) {
+  LevelJob& J = h->job;
+  Batch& b = J.b;
+  const int side = J.side, t = J.t;
+  const int64_t n = b.n;
+  Arena& A = h->arena;
+  const int64_t* st = h->pin->st;
   b.flops = (double)(unsigned long long)st[4];
   b.nnz_T = st[5];
   b.sampled = st[6];
-  if (pq >= 0) h->prof.recs[pq].flops = b.flops;
+  if (h->qr_rec >= 0) h->prof.recs[h->qr_rec].flops = b.flops;
   const int32_t status = (int32_t)(st[7] & 0xffffffff);
   if (status & kErrRank) {
     set_error("level %d %c: an ID needs rank > %d at tol %g", t, side == IDBF_SIDE_U ? 'U' : 'V', kMaxRank,
@@ -390,8 +442,8 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   TRY(A.get(std::max<int64_t>(b.n_skel, 1), &b.skel_idx));
   TRY(A.get(std::max<int64_t>(b.n_skel, 1), &b.skel_coord));
   TRY(A.get(n, &b.meta));
-  pr = h->prof.begin("level_compact", h->stream);
-  TRYHIP(launch_compact_skel(h->scratch, b.rank, b.skel_off, n, side == IDBF_SIDE_U ? X : Om, b.skel_idx,
+  const int pr = h->prof.begin("level_compact", h->stream);
+  TRYHIP(launch_compact_skel(h->scratch, b.rank, b.skel_off, n, side == IDBF_SIDE_U ? J.X : J.Om, b.skel_idx,
                              b.skel_coord, h->stream));
   TRYHIP(launch_pack_meta(b.T_off, b.mask, b.cand_beg, b.skel_off, b.cand_len, b.rank, n, b.meta, h->stream));
   h->prof.end(pr, h->stream);
@@ -400,11 +452,10 @@ idbf_status run_batch(idbf_handle_s* h, const double* X, const double* Om, int s
   return IDBF_OK;
 }
 
-idbf_status build_middle(idbf_handle_s* h, const double* X, const double* Om) {
+// Middle factor: block descriptors and sizes (phase 1), then the sampled
+// blocks (phase 2).
+idbf_status middle_begin(idbf_handle_s* h) {
   Arena& A = h->arena;
-  int64_t st[8];
-  const int32_t* row_idx;
-  const int32_t* col_idx;
   if (h->H == 0) {
     h->nblk = 1;
     TRY(A.get(1, &h->s_rbeg));
@@ -422,36 +473,46 @@ idbf_status build_middle(idbf_handle_s* h, const double* X, const double* Om) {
     TRYHIP(hipMemcpyAsync(h->s_rlen, &nn, 4, hipMemcpyHostToDevice, h->stream));
     TRYHIP(hipMemcpyAsync(h->s_clen, &nn, 4, hipMemcpyHostToDevice, h->stream));
     TRYHIP(hipMemcpyAsync(h->S_off, offs, 16, hipMemcpyHostToDevice, h->stream));
-    TRYHIP(hipStreamSynchronize(h->stream));
+    TRY(sync(h));  // the sources above live on this stack frame
+    return IDBF_OK;
+  }
+  const int d = h->L - h->H + 1;
+  h->nblk = int64_t(1) << (2 * d);
+  TRY(A.get(h->nblk, &h->s_rbeg));
+  TRY(A.get(h->nblk, &h->s_rlen));
+  TRY(A.get(h->nblk, &h->s_cbeg));
+  TRY(A.get(h->nblk, &h->s_clen));
+  TRY(A.get(h->nblk, &h->s_size));
+  TRY(A.get(h->nblk + 1, &h->S_off));
+  MiddleDescArgs m{};
+  m.L = h->L;
+  m.H = h->H;
+  m.n_blocks = h->nblk;
+  m.u_off = h->U[h->H - 1].skel_off;
+  m.v_off = h->V[h->H - 1].skel_off;
+  m.rbeg = h->s_rbeg;
+  m.rlen = h->s_rlen;
+  m.cbeg = h->s_cbeg;
+  m.clen = h->s_clen;
+  m.size = h->s_size;
+  m.nnz = reinterpret_cast<unsigned long long*>(h->stats + 4);
+  TRYHIP(hipMemsetAsync(h->stats + 4, 0, sizeof(int64_t), h->stream));
+  TRYHIP(launch_middle_desc(m, h->stream));
+  TRYHIP(launch_scan_i64(h->s_size, h->nblk, h->S_off, nullptr, h->stats, h->stream));
+  TRYHIP(hipMemcpyAsync(h->pin->st, h->stats, sizeof h->pin->st, hipMemcpyDeviceToHost, h->stream));
+  return IDBF_OK;
+}
+
+idbf_status middle_finish(idbf_handle_s* h, const double* X, const double* Om) {
+  Arena& A = h->arena;
+  const int32_t* row_idx;
+  const int32_t* col_idx;
+  if (h->H == 0) {
     row_idx = col_idx = h->iota;
   } else {
-    const int d = h->L - h->H + 1;
-    h->nblk = int64_t(1) << (2 * d);
-    TRY(A.get(h->nblk, &h->s_rbeg));
-    TRY(A.get(h->nblk, &h->s_rlen));
-    TRY(A.get(h->nblk, &h->s_cbeg));
-    TRY(A.get(h->nblk, &h->s_clen));
-    TRY(A.get(h->nblk, &h->s_size));
-    TRY(A.get(h->nblk + 1, &h->S_off));
-    MiddleDescArgs m{};
-    m.L = h->L;
-    m.H = h->H;
-    m.n_blocks = h->nblk;
-    m.u_off = h->U[h->H - 1].skel_off;
-    m.v_off = h->V[h->H - 1].skel_off;
-    m.rbeg = h->s_rbeg;
-    m.rlen = h->s_rlen;
-    m.cbeg = h->s_cbeg;
-    m.clen = h->s_clen;
-    m.size = h->s_size;
-    m.nnz = reinterpret_cast<unsigned long long*>(h->stats + 4);
-    TRYHIP(hipMemsetAsync(h->stats + 4, 0, sizeof(int64_t), h->stream));
-    TRYHIP(launch_middle_desc(m, h->stream));
-    TRYHIP(launch_scan_i64(h->s_size, h->nblk, h->S_off, nullptr, h->stats, h->stream));
-    TRY(read_stats(h, st, 5));
-    h->nnz_S_res = st[0];
-    h->sblk_max = st[1];
-    h->nnz_S = st[4];
+    h->nnz_S_res = h->pin->st[0];
+    h->sblk_max = h->pin->st[1];
+    h->nnz_S = h->pin->st[4];
     row_idx = h->U[h->H - 1].skel_idx;
     col_idx = h->V[h->H - 1].skel_idx;
   }
@@ -477,42 +538,83 @@ idbf_status build_middle(idbf_handle_s* h, const double* X, const double* Om) {
   return IDBF_OK;
 }
 
-idbf_status check_points(idbf_handle_s* h, const double* p, const char* name) {
-  TRYHIP(hipMemsetAsync(h->status, 0, sizeof(int32_t), h->stream));
-  hipLaunchKernelGGL(check_points_kernel, dim3((unsigned)((h->N + 255) / 256)), dim3(256), 0, h->stream, p, h->N,
-                     h->status);
-  TRYHIP(hipGetLastError());
-  int32_t bad = 0;
-  TRYHIP(hipMemcpyAsync(&bad, h->status, sizeof bad, hipMemcpyDeviceToHost, h->stream));
-  TRYHIP(hipStreamSynchronize(h->stream));
-  if (bad) {
-    set_error("%s must be finite and strictly ascending (%d violations)", name, bad);
-    return IDBF_EINVAL;
+// Input checks (finite, strictly ascending X and Omega): launch, then read.
+idbf_status points_begin(idbf_handle_s* h, const double* X, const double* Om) {
+  const double* pts[2] = {X, Om};
+  for (int i = 0; i < 2; ++i) {
+    TRYHIP(hipMemsetAsync(h->status, 0, sizeof(int32_t), h->stream));
+    hipLaunchKernelGGL(check_points_kernel, dim3((unsigned)((h->N + 255) / 256)), dim3(256), 0, h->stream, pts[i],
+                       h->N, h->status);
+    TRYHIP(hipGetLastError());
+    TRYHIP(hipMemcpyAsync(&h->pin->bad[i], h->status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
   }
   return IDBF_OK;
 }
 
-idbf_status construct_impl(idbf_handle_s* h, const double* X, const double* Om) {
+idbf_status points_finish(idbf_handle_s* h) {
+  const char* names[2] = {"X", "Omega"};
+  for (int i = 0; i < 2; ++i)
+    if (h->pin->bad[i]) {
+      set_error("%s must be finite and strictly ascending (%d violations)", names[i], h->pin->bad[i]);
+      return IDBF_EINVAL;
+    }
+  return IDBF_OK;
+}
+
+// Device and pinned memory every construction needs before its first level.
+idbf_status construct_setup(idbf_handle_s* h) {
   Arena& A = h->arena;
+  if (!h->pin) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->pin), sizeof(HostStage), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      h->pin = nullptr;
+      set_error("pinned host allocation failed: %s", hipGetErrorString(e));
+      return IDBF_ENOMEM;
+    }
+    std::memset(h->pin, 0, sizeof(HostStage));
+  }
   TRY(A.get(8, &h->stats));
   TRY(A.get(1, &h->status));
-  TRY(check_points(h, X, "X"));
-  TRY(check_points(h, Om, "Omega"));
-  TRYHIP(hipMemsetAsync(h->status, 0, sizeof(int32_t), h->stream));
   TRY(A.get(h->N, &h->iota));
-  TRYHIP(launch_iota(h->iota, h->N, h->stream));
   if (h->H > 0) {
     TRY(A.get((int64_t(2) << h->L) * kMaxCand, &h->scratch));
     TRY(A.get((int64_t(2) << h->L) * kMaxSamples, &h->samp_pos));
     TRY(A.get(int64_t(2) << h->L, &h->order));
     TRY(A.get(16, &h->bucket));
   }
-  for (int t = 1; t <= h->H; ++t) {
-    TRY(run_batch(h, X, Om, IDBF_SIDE_U, t));
-    TRY(run_batch(h, X, Om, IDBF_SIDE_V, t));
-  }
-  TRY(build_middle(h, X, Om));
-  TRYHIP(hipStreamSynchronize(h->stream));
+  return IDBF_OK;
+}
+
+idbf_status construct_start(idbf_handle_s* h, const double* X, const double* Om) {
+  TRY(points_begin(h, X, Om));
+  return IDBF_OK;
+}
+
+idbf_status construct_levels_ready(idbf_handle_s* h) {
+  TRY(points_finish(h));
+  TRYHIP(hipMemsetAsync(h->status, 0, sizeof(int32_t), h->stream));
+  TRYHIP(launch_iota(h->iota, h->N, h->stream));
+  return IDBF_OK;
+}
+
+idbf_status construct_impl(idbf_handle_s* h, const double* X, const double* Om) {
+  TRY(construct_setup(h));
+  TRY(construct_start(h, X, Om));
+  TRY(sync(h));
+  TRY(construct_levels_ready(h));
+  for (int t = 1; t <= h->H; ++t)
+    for (int side : {IDBF_SIDE_U, IDBF_SIDE_V}) {
+      TRY(level_begin(h, X, Om, side, t));
+      TRY(sync(h));
+      TRY(level_ids(h));
+      TRY(sync(h));
+      TRY(level_finish(h));
+    }
+  TRY(middle_begin(h));
+  TRY(sync(h));
+  TRY(middle_finish(h, X, Om));
+  TRY(sync(h));
   return IDBF_OK;
 }
 
@@ -554,14 +656,13 @@ void idbf_opts_default(idbf_opts* o) {
 
 const char* idbf_last_error(void) { return g_err; }
 
-idbf_status idbf_construct(const idbf_phase* phase, const double* X, const double* Omega, int64_t N, double tol,
-                           int32_t leaf, const idbf_opts* opts, idbf_handle* out) {
-  g_err[0] = 0;
-  if (!out) {
-    set_error("out is NULL");
-    return IDBF_EINVAL;
-  }
-  *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// Argument checks and an empty handle for one construction.
+idbf_status make_handle(const idbf_phase* phase, const double* X, const double* Omega, int64_t N, double tol,
+                        int32_t leaf, const idbf_opts& o, std::unique_ptr<idbf_handle_s>* out) {
   TRY(check_phase(phase));
   if (!X || !Omega) {
     set_error("X and Omega must be device pointers");
@@ -579,14 +680,10 @@ idbf_status idbf_construct(const idbf_phase* phase, const double* X, const doubl
     set_error("tol must satisfy 0 <= tol < 1, got %g", tol);
     return IDBF_EINVAL;
   }
-  idbf_opts o;
-  idbf_opts_default(&o);
-  if (opts) o = *opts;
   if (o.oversample < 1 || o.kmax < 0) {
     set_error("opts: oversample must be >= 1 and kmax >= 0");
     return IDBF_EINVAL;
   }
-  auto t0 = std::chrono::steady_clock::now();
   std::unique_ptr<idbf_handle_s> h(new (std::nothrow) idbf_handle_s());
   if (!h) {
     set_error("host allocation failed");
@@ -605,6 +702,123 @@ idbf_status idbf_construct(const idbf_phase* phase, const double* X, const doubl
   if (o.mem_cap_bytes) h->arena.chunk_min = std::min<size_t>(h->arena.chunk_min, o.mem_cap_bytes);
   h->stream = static_cast<hipStream_t>(o.stream);
   h->prof.on = (o.flags & IDBF_FLAG_PROFILE) != 0;
+  *out = std::move(h);
+  return IDBF_OK;
+}
+
+void prefix_error(int i) {
+  char msg[sizeof g_err];
+  std::snprintf(msg, sizeof msg, "%s", g_err);
+  set_error("instance %d: %s", i, msg);
+}
+
+constexpr int kBatchStreams = 4;  // hardware queues a process gets by default
+
+// Device-lifetime streams for batched applies (default priority).
+idbf_status pool_streams(std::vector<hipStream_t>* out) {
+  static std::mutex mu;
+  static std::vector<std::pair<int, std::vector<hipStream_t>>> pools;
+  int dev = 0;
+  IDBF_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  for (auto& p : pools)
+    if (p.first == dev) {
+      *out = p.second;
+      return IDBF_OK;
+    }
+  std::vector<hipStream_t> s(kBatchStreams, nullptr);
+  for (auto& x : s) IDBF_HIP_CHECK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+  pools.emplace_back(dev, s);
+  *out = s;
+  return IDBF_OK;
+}
+
+// caller stream -> every stream in `to` (fork) ...
+idbf_status fork_streams(hipStream_t from, const std::vector<hipStream_t>& to) {
+  hipEvent_t ev = nullptr;
+  IDBF_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  hipError_t e = hipEventRecord(ev, from);
+  for (size_t i = 0; e == hipSuccess && i < to.size(); ++i) e = hipStreamWaitEvent(to[i], ev, 0);
+  (void)hipEventDestroy(ev);
+  IDBF_HIP_CHECK(e);
+  return IDBF_OK;
+}
+
+// ... and back (join)
+idbf_status join_streams(const std::vector<hipStream_t>& from, hipStream_t to) {
+  for (hipStream_t s : from) {
+    hipEvent_t ev = nullptr;
+    IDBF_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(to, ev, 0);
+    (void)hipEventDestroy(ev);
+    IDBF_HIP_CHECK(e);
+  }
+  return IDBF_OK;
+}
+
+idbf_status sync_streams(const std::vector<hipStream_t>& ss) {
+  for (hipStream_t s : ss) IDBF_HIP_CHECK(hipStreamSynchronize(s));
+  return IDBF_OK;
+}
+
+// Lockstep construction of several handles: every phase of every level is
+// issued for all handles (each on one of `streams`), then the streams are
+// synchronized once and the next phase reads the pinned staging areas.
+idbf_status construct_lockstep(std::vector<std::unique_ptr<idbf_handle_s>>& hs, const double* const* X,
+                               const double* const* Om, const std::vector<hipStream_t>& streams) {
+  const int n = (int)hs.size();
+#define IDBF_EACH(cond, call)                    \
+  for (int i = 0; i < n; ++i) {                  \
+    idbf_handle_s* h = hs[i].get();              \
+    if (!(cond)) continue;                       \
+    idbf_status s_ = (call);                     \
+    if (s_ != IDBF_OK) {                         \
+      prefix_error(i);                           \
+      (void)sync_streams(streams);               \
+      return s_;                                 \
+    }                                            \
+  }
+  IDBF_EACH(true, construct_setup(h));
+  IDBF_EACH(true, construct_start(h, X[i], Om[i]));
+  TRY(sync_streams(streams));
+  IDBF_EACH(true, construct_levels_ready(h));
+  int Hmax = 0;
+  for (auto& h : hs) Hmax = std::max(Hmax, h->H);
+  for (int t = 1; t <= Hmax; ++t)
+    for (int side : {IDBF_SIDE_U, IDBF_SIDE_V}) {
+      IDBF_EACH(h->H >= t, level_begin(h, X[i], Om[i], side, t));
+      TRY(sync_streams(streams));
+      IDBF_EACH(h->H >= t, level_ids(h));
+      TRY(sync_streams(streams));
+      IDBF_EACH(h->H >= t, level_finish(h));
+    }
+  IDBF_EACH(true, middle_begin(h));
+  TRY(sync_streams(streams));
+  IDBF_EACH(true, middle_finish(h, X[i], Om[i]));
+  TRY(sync_streams(streams));
+#undef IDBF_EACH
+  return IDBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+idbf_status idbf_construct(const idbf_phase* phase, const double* X, const double* Omega, int64_t N, double tol,
+                           int32_t leaf, const idbf_opts* opts, idbf_handle* out) {
+  g_err[0] = 0;
+  if (!out) {
+    set_error("out is NULL");
+    return IDBF_EINVAL;
+  }
+  *out = nullptr;
+  idbf_opts o;
+  idbf_opts_default(&o);
+  if (opts) o = *opts;
+  auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<idbf_handle_s> h;
+  TRY(make_handle(phase, X, Omega, N, tol, leaf, o, &h));
   idbf_status s = construct_impl(h.get(), X, Omega);
   if (s != IDBF_OK) {
     (void)hipStreamSynchronize(h->stream);
@@ -612,6 +826,44 @@ idbf_status idbf_construct(const idbf_phase* phase, const double* X, const doubl
   }
   h->construct_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h.release();
+  return IDBF_OK;
+}
+
+idbf_status idbf_construct_batched(int32_t count, const idbf_phase* phases, const double* const* X,
+                                   const double* const* Omega, const int64_t* N, const double* tol,
+                                   const int32_t* leaf, const idbf_opts* opts, idbf_handle* out) {
+  g_err[0] = 0;
+  if (count < 1 || !phases || !X || !Omega || !N || !tol || !leaf || !out) {
+    set_error("construct_batched: count must be >= 1 and every array non-NULL");
+    return IDBF_EINVAL;
+  }
+  for (int i = 0; i < count; ++i) out[i] = nullptr;
+  idbf_opts o;
+  idbf_opts_default(&o);
+  if (opts) o = *opts;
+  auto t0 = std::chrono::steady_clock::now();
+  std::vector<std::unique_ptr<idbf_handle_s>> hs(count);
+  for (int i = 0; i < count; ++i) {
+    idbf_status s = make_handle(&phases[i], X[i], Omega[i], N[i], tol[i], leaf[i], o, &hs[i]);
+    if (s != IDBF_OK) {
+      prefix_error(i);
+      return s;
+    }
+  }
+  std::vector<hipStream_t> streams;
+  TRY(pool_streams(&streams));
+  streams.resize(std::min<size_t>(streams.size(), (size_t)count));
+  hipStream_t caller = static_cast<hipStream_t>(o.stream);
+  TRY(fork_streams(caller, streams));  // X and Omega may come from work on the caller's stream
+  for (int i = 0; i < count; ++i) hs[i]->stream = streams[i % streams.size()];
+  idbf_status s = construct_lockstep(hs, X, Omega, streams);
+  if (s != IDBF_OK) return s;
+  const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  for (int i = 0; i < count; ++i) {
+    hs[i]->stream = caller;
+    hs[i]->construct_ms = ms;
+    out[i] = hs[i].release();
+  }
   return IDBF_OK;
 }
 
@@ -728,6 +980,50 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     cur ^= 1;
   }
   return IDBF_OK;
+}
+
+idbf_status idbf_apply_batched(int32_t count, const idbf_handle* hs, const void* const* x, void* const* y,
+                               const int64_t* nrhs, int32_t dtype, void* stream) {
+  g_err[0] = 0;
+  if (count < 1 || !hs || !x || !y || !nrhs) {
+    set_error("apply_batched: count must be >= 1 and every array non-NULL");
+    return IDBF_EINVAL;
+  }
+  if (dtype != IDBF_C128 && dtype != IDBF_C64 && dtype != IDBF_C64_BF16X3) {
+    set_error("apply_batched: unknown dtype %d", dtype);
+    return IDBF_EINVAL;
+  }
+  std::vector<idbf_handle> sorted(hs, hs + count);
+  std::sort(sorted.begin(), sorted.end());
+  for (int i = 0; i < count; ++i)
+    if (!sorted[i] || (i > 0 && sorted[i] == sorted[i - 1])) {
+      set_error("apply_batched: handles must be non-NULL and distinct");
+      return IDBF_EINVAL;
+    }
+  hipStream_t caller = static_cast<hipStream_t>(stream);
+  const size_t elem = dtype == IDBF_C128 ? 16 : 8;
+  for (int i = 0; i < count; ++i) {  // workspaces first: growing one synchronizes
+    if (nrhs[i] < 0) {
+      set_error("instance %d: nrhs must be >= 0", i);
+      return IDBF_EINVAL;
+    }
+    idbf_status s = grow_workspace(hs[i], 2 * size_t(hs[i]->max_skel) * size_t(nrhs[i]) * elem, caller);
+    if (s != IDBF_OK) {
+      prefix_error(i);
+      return s;
+    }
+  }
+  std::vector<hipStream_t> streams;
+  TRY(pool_streams(&streams));
+  streams.resize(std::min<size_t>(streams.size(), (size_t)count));
+  TRY(fork_streams(caller, streams));
+  idbf_status st = IDBF_OK;
+  for (int i = 0; i < count && st == IDBF_OK; ++i) {
+    st = idbf_apply(hs[i], x[i], y[i], nrhs[i], dtype, streams[i % streams.size()]);
+    if (st != IDBF_OK) prefix_error(i);
+  }
+  idbf_status sj = join_streams(streams, caller);  // joined even after a failure
+  return st != IDBF_OK ? st : sj;
 }
 
 idbf_status idbf_reserve(idbf_handle h, int64_t nrhs, int32_t dtype) {

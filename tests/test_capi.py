@@ -64,3 +64,5 @@ def test_argument_errors_without_gpu():
     assert lib.idbf_sample(C.byref(ph), fake, fake, fake, 0, fake, 3, fake, None) == B.OK
     assert lib.idbf_id_batch(C.byref(ph), fake, fake, 5, 1, fake, fake, fake, fake, fake, fake, 1e-6, 0, 1,
                              fake, fake, fake, fake, None) == B.EINVAL
+    assert lib.idbf_construct_batched(0, None, None, None, None, None, None, None, None) == B.EINVAL
+    assert lib.idbf_apply_batched(0, None, None, None, None, B.C64, None) == B.EINVAL

@@ -1,0 +1,95 @@
+"""Batched construction and apply (idbf_construct_batched / idbf_apply_batched)
+against the same instances built and applied one by one: the lockstep sweep
+runs the same kernels on the same inputs, so factors and outputs must agree
+bit for bit; the small instances are also checked against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1809_10573_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1809_10573_amd import binding as B  # noqa: E402
+
+DEV = "cuda:0"
+
+# uneven N (odd and even L, H = 0), both kernels, different tolerances and leaves
+CASES = [
+    (I.dft_phase(), 1024, 8, 1e-10),
+    (I.fio_phase(0.3, 2.0), 2048, 16, 1e-6),
+    (I.fio_phase(1.0, 1.0), 4096, 16, 1e-6),
+    (I.dft_phase(), 256, 16, 1e-6),
+    (I.fio_phase(0.0, 1.0), 512, 8, 1e-8),
+    (I.dft_phase(), 16, 8, 1e-10),
+    (I.fio_phase(0.7, 1.0), 8192, 16, 1e-6),
+]
+
+
+def _same_factors(a, b):
+    ia, ib = a.info(), b.info()
+    for key in ("L", "H", "nnz_T", "nnz_S", "n_skel", "rank_max", "rank_min"):
+        assert ia[key] == ib[key], key
+    for side in (B.SIDE_U, B.SIDE_V):
+        for t in range(1, ia["H"] + 1):
+            x, y = a.batch(side, t), b.batch(side, t)
+            for f in ("rank", "cand_len", "mask", "skel", "T_off"):
+                assert np.array_equal(getattr(x, f), getattr(y, f)), (side, t, f)
+            # T entries in use (each ID reserves an upper bound; the tail is never written)
+            for q in range(len(x.rank)):
+                n = int(x.rank[q]) * int(x.cand_len[q] - x.rank[q])
+                o = int(x.T_off[q])
+                assert np.array_equal(x.T[o:o + n], y.T[o:o + n]), (side, t, q)
+    Sa, oa = a.middle()
+    Sb, ob = b.middle()
+    assert np.array_equal(oa, ob)
+    ends = np.append(oa[1:], len(Sa))
+    for o, e in zip(oa, ends):  # a block's reservation is rounded up to even: skip its last slot
+        assert np.array_equal(Sa[o:e - 1], Sb[o:e - 1])
+
+
+def test_construct_batched_equals_one_by_one():
+    grids = [I.uniform_grid(N) for _, N, _, _ in CASES]
+    facs = B.construct_batched([c[0] for c in CASES], [g[0] for g in grids], [g[1] for g in grids],
+                               [c[3] for c in CASES], [c[2] for c in CASES], oversample=2, device=DEV)
+    for (ph, N, leaf, tol), (X, O), fb in zip(CASES, grids, facs):
+        f1 = B.construct(ph, X, O, tol, leaf, oversample=2, device=DEV)
+        _same_factors(fb, f1)
+    # the smallest ones against the oracle's apply of its own factors
+    for (ph, N, leaf, tol), (X, O), fb in list(zip(CASES, grids, facs))[3:6]:
+        F = oracle.build(ph, X, O, leaf, tol, oversample=2)
+        g = I.gaussian_vectors(N, None, seed=N)
+        y = fb.apply(torch.as_tensor(g, device=DEV)).cpu().numpy()
+        assert oracle.relative_error(y, oracle.apply(F, g)) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", [B.C128, B.C64, B.C64_BF16X3])
+def test_apply_batched_equals_one_by_one(dtype):
+    grids = [I.uniform_grid(N) for _, N, _, _ in CASES]
+    facs = B.construct_batched([c[0] for c in CASES], [g[0] for g in grids], [g[1] for g in grids],
+                               [c[3] for c in CASES], [c[2] for c in CASES], oversample=2, device=DEV)
+    tdt = torch.complex128 if dtype == B.C128 else torch.complex64
+    nrhs = [1, 16, 64, 1, 16, 64, 3]
+    xs = [torch.as_tensor(I.gaussian_vectors(N, r if r > 1 else None, seed=7 + i), device=DEV).to(tdt)
+          for i, ((_, N, _, _), r) in enumerate(zip(CASES, nrhs))]
+    ys = B.apply_batched(facs, xs, dtype=dtype)
+    torch.cuda.synchronize()
+    for f, x, y in zip(facs, xs, ys):
+        y1 = f.apply(x, dtype=dtype)
+        assert torch.equal(y, y1)
+
+
+def test_batched_errors_name_the_instance():
+    X, O = I.uniform_grid(256)
+    with pytest.raises(B.IdbfError) as e:
+        B.construct_batched([I.dft_phase(), I.dft_phase()], [X, X], [O, O], [1e-6, 1e-6], [16, 3],
+                            device=DEV)
+    assert e.value.status == B.EINVAL and "instance 1" in str(e.value)
+    f = B.construct(I.dft_phase(), X, O, 1e-6, 16, device=DEV)
+    x = torch.zeros(256, dtype=torch.complex128, device=DEV)
+    with pytest.raises(B.IdbfError):
+        B.apply_batched([f, f], [x, x])        # handles must be distinct
