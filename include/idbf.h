@@ -95,9 +95,9 @@ void idbf_opts_default(idbf_opts* o);
  * sample selection, entry sampling, column-pivoted Householder QR stopped at
  * the eps-rank, and the interpolation solve T = R11^{-1} R12 (eq. R2).
  * Levels run U_1, V_1, ..., U_H, V_H with H = floor(L/2), L = log2(N/leaf);
- * then the middle factor's blocks are sampled.  Candidate sets must stay
- * <= 64 points and sample sets <= 128 (else IDBF_EUNSUPPORTED); ranks <= 32
- * (else IDBF_ERANK).  Synchronizes opts->stream.  The handle owns all factor
+ * then the middle factor's blocks are sampled.  Each ID samples
+ * s = min(oversample * |cand|, |allowed|, 128) points.  Candidate sets must
+ * stay <= 128 points (else IDBF_EUNSUPPORTED); ranks <= 64 (else IDBF_ERANK).  Synchronizes opts->stream.  The handle owns all factor
  * memory (FP64 factors and an FP32 copy) until idbf_destroy.
  */
 idbf_status idbf_construct(const idbf_phase* phase, const double* X, const double* Omega,
@@ -206,8 +206,8 @@ idbf_status idbf_profile_read(idbf_handle h, idbf_kernel_stat* out, int32_t max,
  * compresses and partner the node at depth t of the other tree.
  *   idbf_batch_sizes: *n_ids, *n_skel (sum of ranks), *n_T (T entries stored).
  *   idbf_batch_export (all host arrays, sized by idbf_batch_sizes):
- *     rank[n_ids], cand_len[n_ids], mask[n_ids] (bit l set: candidate l is a
- *     skeleton), skel[n_skel] (global indices, ascending within each ID,
+ *     rank[n_ids], cand_len[n_ids], mask[2 * n_ids] (bit l of the 128-bit
+ *     word pair (mask[2q], mask[2q+1]) set: candidate l is a skeleton), skel[n_skel] (global indices, ascending within each ID,
  *     IDs consecutive), T[2 * n_T] (complex128), T_off[n_ids] (entry offset
  *     of each ID's T).  T of an ID with rank k and r = cand_len - k redundant
  *     candidates is k x r, stored from the even offset T_off[q]; V IDs store it
@@ -248,14 +248,15 @@ idbf_status idbf_sample(const idbf_phase* phase, const double* X, const double* 
  * (Section 2.1, Lemma 2.1, eqs. pivotedQR2, acc, R2), the kernel every level
  * of idbf_construct runs.  ID q compresses candidates
  * cand_idx[cand_beg[q] .. cand_beg[q] + cand_len[q]) (ascending global
- * indices, <= 64) against allowed points allow_idx[allow_beg[q] .. + allow_len[q])
+ * indices, <= 128) against allowed points allow_idx[allow_beg[q] .. + allow_len[q])
  * (ascending).  side IDBF_SIDE_V: candidates are columns (Omega) and the ID
  * is a column ID of K(samples, cand); IDBF_SIDE_U: candidates are rows (X)
  * and it is a row ID of K(cand, samples).  s = min(oversample * cand_len,
- * allow_len) <= 128 samples are picked by the Mock-Chebyshev rule.
- * Outputs (device): rank[q]; mask[q]; skel[q * 64 + i] ascending skeleton
- * global indices; T[(q * 1024 + e) * 2 ..] complex128 in the layout of
- * idbf_batch_export.  Asynchronous on stream.
+ * allow_len, 128) samples are picked by the Mock-Chebyshev rule.
+ * Outputs (device): rank[q]; mask[2q], mask[2q+1] (128-bit skeleton mask);
+ * skel[q * 128 + i] ascending skeleton global indices;
+ * T[(q * 4096 + e) * 2 ..] complex128 in the layout of idbf_batch_export.
+ * Ranks above 64 give IDBF_ERANK.  Asynchronous on stream.
  */
 idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double* Omega,
                           int32_t side, int64_t n_ids, const int32_t* cand_idx,

@@ -35,12 +35,12 @@ from .kernel import (PHASE_DFT, PHASE_FIO, amplitude_shift, phase_mod1, entries,
                      relative_error)
 from .interp import PIVOT_TIE_REL, column_id, ColumnID
 from .sampling import chebyshev_fraction, mock_chebyshev
-from .idbf import Factors, build, apply, densify, tree_sizes, factor_matrices
+from .idbf import Factors, build, apply, densify, tree_sizes, factor_matrices, sample_count, SAMPLE_CAP
 
 __all__ = [
     "PHASE_DFT", "PHASE_FIO", "amplitude_shift", "phase_mod1", "entries",
     "matvec_rows", "dense_matvec", "dft_closed_form", "fio_const_closed_form",
     "relative_error", "PIVOT_TIE_REL", "column_id", "ColumnID",
     "chebyshev_fraction", "mock_chebyshev", "Factors", "build", "apply",
-    "densify", "tree_sizes", "factor_matrices",
+    "densify", "tree_sizes", "factor_matrices", "sample_count", "SAMPLE_CAP",
 ]

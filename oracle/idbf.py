@@ -27,7 +27,7 @@ pair from the outside in: t = 1 is U^L / V^L of the paper):
 * S: with d = L-H+1, for every R, C' at depth d the block
     K(skel_r(R, ancestor of C' at depth H), skel_c(C', ancestor of R at depth H)).
 
-Each ID samples s = min(t |cand|, |allowed|) points of its allowed set by the
+Each ID samples s = min(t |cand|, |allowed|, 128) points of its allowed set by the
 Mock-Chebyshev rule (oversampling t = 1, k = min{m, n}; Section 3), or all of
 them with ``sample_all`` (used to pin the assembly: then every ID is exact to
 its tolerance on the whole block).  An rID of A(cand, allowed) is the cID of
@@ -57,6 +57,10 @@ import numpy as np
 from .interp import column_id
 from .kernel import entries
 from .sampling import mock_chebyshev
+
+# Largest sample count of one ID (a reading: the paper gives no cap; with
+# t <= 2 it binds only for candidate sets above 64 points).
+SAMPLE_CAP = 128
 
 
 @dataclass
@@ -110,16 +114,24 @@ def _interp(B, tol, kmax, cand):
                     T=cid.T, nsamples=B.shape[0], rdiag=cid.rdiag)
 
 
-def _samples(coords_of_allowed, allowed, c, oversample, sample_all):
-    s = len(allowed) if sample_all else min(oversample * c, len(allowed))
+def sample_count(c: int, n_allowed: int, oversample: int, smax: int = SAMPLE_CAP) -> int:
+    """s = min(t |cand|, |allowed|, smax): the paper's t k rows (Section 2.1)
+    with k = |cand|, capped at smax (a reading: the paper states no cap)."""
+    s = min(oversample * c, n_allowed)
+    return s if smax <= 0 else min(s, smax)
+
+
+def _samples(coords_of_allowed, allowed, c, oversample, sample_all, smax):
+    s = len(allowed) if sample_all else sample_count(c, len(allowed), oversample, smax)
     return allowed[mock_chebyshev(coords_of_allowed, s)]
 
 
 def build(phase, X, Omega, leaf: int, tol: float, kmax: int = 0, oversample: int = 1,
-          sample_all: bool = False) -> Factors:
+          sample_all: bool = False, smax: int = SAMPLE_CAP) -> Factors:
     """Construct the IDBF of K(X, Omega) level by level (Sections 2.2-2.4).
 
-    oversample is the parameter t of Section 2.1: s = min(t |cand|, |allowed|).
+    oversample is the parameter t of Section 2.1: s = min(t |cand|, |allowed|,
+    smax) samples per ID (smax <= 0: no cap).
     """
     if oversample < 1:
         raise ValueError("oversample must be >= 1")
@@ -150,7 +162,7 @@ def build(phase, X, Omega, leaf: int, tol: float, kmax: int = 0, oversample: int
                     Vp = F.V[t - 1]
                     allowed = np.concatenate([Vp[(cc, r >> sh)].skel
                                               for cc in range(p << sh, (p + 1) << sh)])
-                samp = _samples(Omega[allowed], allowed, len(cand), oversample, sample_all)
+                samp = _samples(Omega[allowed], allowed, len(cand), oversample, sample_all, smax)
                 B = entries(phase, X, Omega, cand, samp).T          # s x c
                 U[(r, p)] = _interp(B, tol, kmax, cand)
         F.U[t] = U
@@ -166,7 +178,7 @@ def build(phase, X, Omega, leaf: int, tol: float, kmax: int = 0, oversample: int
                 sh = L - 2 * t + 1
                 allowed = np.concatenate([U[(rr, cnode >> sh)].skel
                                           for rr in range(p << sh, (p + 1) << sh)])
-                samp = _samples(X[allowed], allowed, len(cand), oversample, sample_all)
+                samp = _samples(X[allowed], allowed, len(cand), oversample, sample_all, smax)
                 B = entries(phase, X, Omega, samp, cand)            # s x c
                 V[(cnode, p)] = _interp(B, tol, kmax, cand)
         F.V[t] = V

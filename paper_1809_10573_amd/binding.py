@@ -31,6 +31,14 @@ EXPORTED = [
     "idbf_construct_batched", "idbf_apply_batched",
 ]
 FLAG_PROFILE = 1
+MAX_CAND, MAX_RANK, MAX_SAMPLES, SLOT = 128, 64, 128, 4096  # limits of include/idbf.h
+
+
+def mask_bits(mask_row, c: int) -> np.ndarray:
+    """Skeleton flags of candidates 0..c-1 from a (lo, hi) 128-bit mask pair."""
+    lo, hi = int(mask_row[0]), int(mask_row[1])
+    word = lo | (hi << 64)
+    return np.array([(word >> l) & 1 for l in range(c)], bool)
 
 
 class IdbfError(RuntimeError):
@@ -195,7 +203,7 @@ class Factorization:
         _check(lib.idbf_batch_sizes(self._h, side, level, C.byref(n), C.byref(ns), C.byref(nt)))
         rank = np.zeros(n.value, np.int32)
         cand = np.zeros(n.value, np.int32)
-        mask = np.zeros(n.value, np.uint64)
+        mask = np.zeros((n.value, 2), np.uint64)
         skel = np.zeros(max(ns.value, 1), np.int32)
         T = np.zeros(max(nt.value, 1), np.complex128)
         toff = np.zeros(n.value, np.int64)
@@ -308,16 +316,16 @@ def sample(phase, X, Omega, rows, cols, device="cuda", stream=None):
 
 def id_batch(phase, X, Omega, side: int, cand_idx, cand_beg, cand_len, allow_idx, allow_beg,
              allow_len, tol: float, kmax: int = 0, oversample: int = 1, device="cuda", stream=None):
-    """idbf_id_batch; returns host arrays (rank, mask, skel (n, 64), T (n, 1024))."""
+    """idbf_id_batch; returns host arrays (rank, mask (n, 2), skel (n, 128), T (n, 4096))."""
     import torch
     Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
     ci, cb, cl = (_dev_i32(a, device) for a in (cand_idx, cand_beg, cand_len))
     ai, abg, al = (_dev_i32(a, device) for a in (allow_idx, allow_beg, allow_len))
     n = cb.numel()
     rank = torch.zeros(n, dtype=torch.int32, device=device)
-    mask = torch.zeros(n, dtype=torch.int64, device=device)
-    skel = torch.full((n, 64), -1, dtype=torch.int32, device=device)
-    T = torch.zeros((n, 1024), dtype=torch.complex128, device=device)
+    mask = torch.zeros((n, 2), dtype=torch.int64, device=device)
+    skel = torch.full((n, MAX_CAND), -1, dtype=torch.int32, device=device)
+    T = torch.zeros((n, SLOT), dtype=torch.complex128, device=device)
     ph = _phase(phase)
     _check(load().idbf_id_batch(C.byref(ph), _ptr(Xd), _ptr(Od), side, n, _ptr(ci), _ptr(cb),
                                 _ptr(cl), _ptr(ai), _ptr(abg), _ptr(al), float(tol), int(kmax),

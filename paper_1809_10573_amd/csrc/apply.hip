@@ -42,39 +42,42 @@ __device__ __forceinline__ float2 vec_entry<float2>(const float4& v, int t) {
 template <>
 __device__ __forceinline__ double2 vec_entry<double2>(const double2& v, int) { return v; }
 
-// Products P[e] = blk[e] * in[e / div] for e < n; NV vector loads per lane
-// cover the largest block (kSlot entries).
+// Products P[e] = blk[e] * in[e / div] for e < n, streamed NV vector loads
+// per lane at a time (all issued before the first use).
 template <typename C, int NV>
 __device__ __forceinline__ void stream_products(const C* blk, int n, int div, const C* in_lds, C* out_lds,
                                                 int lane) {
   using V = typename Vec<C>::type;
   constexpr int EPL = Vec<C>::epl;
   const V* src = reinterpret_cast<const V*>(blk);
-  V buf[NV];
   const int nv = (n + EPL - 1) / EPL;
-#pragma unroll
-  for (int m = 0; m < NV; ++m) {
-    const int v = lane + m * kWave;
-    if (m * kWave < nv && v < nv) buf[m] = src[v];
-  }
   const float rdiv = 1.0f / (float)div;
+  for (int v0 = 0; v0 < nv; v0 += NV * kWave) {
+    V buf[NV];
 #pragma unroll
-  for (int m = 0; m < NV; ++m) {
-    const int v = lane + m * kWave;
-    if (m * kWave < nv && v < nv) {
+    for (int m = 0; m < NV; ++m) {
+      const int v = v0 + lane + m * kWave;
+      if (v0 + m * kWave < nv && v < nv) buf[m] = src[v];
+    }
 #pragma unroll
-      for (int t = 0; t < EPL; ++t) {
-        const int e = v * EPL + t;
-        if (e < n) {
-          const int j = (int)(((float)e + 0.5f) * rdiv);  // e / div, exact for e < 2^16
-          out_lds[e] = cfma(vec_entry<C>(buf[m], t), in_lds[j], czero(C{}));
+    for (int m = 0; m < NV; ++m) {
+      const int v = v0 + lane + m * kWave;
+      if (v0 + m * kWave < nv && v < nv) {
+#pragma unroll
+        for (int t = 0; t < EPL; ++t) {
+          const int e = v * EPL + t;
+          if (e < n) {
+            const int j = (int)(((float)e + 0.5f) * rdiv);  // e / div, exact for e < 2^16
+            out_lds[e] = cfma(vec_entry<C>(buf[m], t), in_lds[j], czero(C{}));
+          }
         }
       }
     }
   }
 }
 
-template <typename C> constexpr int nv_for() { return kSlot * (int)sizeof(C) / (kWave * 16); }
+// vector loads in flight per lane: 1024 entries of a block per round
+template <typename C> constexpr int nv_for() { return 1024 * (int)sizeof(C) / (kWave * 16); }
 
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -82,13 +85,22 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+__device__ __forceinline__ bool mbit(const ApplyMeta& m, int p) {
+  return p < 64 ? ((m.mask >> p) & 1ull) : ((m.mask_hi >> (p - 64)) & 1ull);
+}
+// skeletons among candidate positions < p
+__device__ __forceinline__ int mbelow(const ApplyMeta& m, int p) {
+  return p < 64 ? __popcll(m.mask & lanes_below(p)) : __popcll(m.mask) + __popcll(m.mask_hi & lanes_below(p - 64));
+}
+
 // V stage: z(ID) = u[skel] + T u[red]; T column-major (entry j*k + i).
-// One wavefront per ID; the ID's packed record is read with a wave-uniform
-// index (scalar loads).  Dynamic LDS: kIdsPerBlock * pmax products.
+// One wavefront per ID, candidate positions lane and lane + 64; the ID's
+// packed record is read with a wave-uniform index (scalar loads).
+// Dynamic LDS: kIdsPerBlock * pmax products.
 template <typename C>
 __global__ __launch_bounds__(256) void apply_v1(StageArgs A) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
-  __shared__ C s_u[kIdsPerBlock][kWave];
+  __shared__ C s_u[kIdsPerBlock][kMaxCand];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   const int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + w;
   if (q >= A.n) return;
@@ -97,18 +109,33 @@ __global__ __launch_bounds__(256) void apply_v1(StageArgs A) {
   C* out = static_cast<C*>(A.out);
   const ApplyMeta m = A.meta[q];
   const int c = m.c, k = m.k, r = c - k;
-  C u = czero(C{});
-  if (lane < c) u = in[m.cand_beg + lane];
-  const int below = __popcll(m.mask & lanes_below(lane));
-  const bool sk = (m.mask >> lane) & 1ull;
-  if (lane < c && !sk) s_u[w][lane - below] = u;
+  const int halves = c > kWave ? 2 : 1;  // wave-uniform
+  C u[2];
+  int below[2];
+  bool sk[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int pos = lane + kWave * h;
+    u[h] = czero(C{});
+    below[h] = 0;
+    sk[h] = false;
+    if (h < halves && pos < c) {
+      u[h] = in[m.cand_beg + pos];
+      below[h] = mbelow(m, pos);
+      sk[h] = mbit(m, pos);
+      if (!sk[h]) s_u[w][pos - below[h]] = u[h];
+    }
+  }
   wave_sync_lds();
   stream_products<C, nv_for<C>()>(static_cast<const C*>(A.T) + m.t_off, k * r, k, s_u[w], s_p, lane);
   wave_sync_lds();
-  if (lane < c && sk) {
-    C acc = u;
-    for (int j = 0; j < r; ++j) acc = cadd(acc, s_p[j * k + below]);
-    out[m.skel_off + below] = acc;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (h < halves && lane + kWave * h < c && sk[h]) {
+      C acc = u[h];
+      for (int j = 0; j < r; ++j) acc = cadd(acc, s_p[j * k + below[h]]);
+      out[m.skel_off + below[h]] = acc;
+    }
   }
 }
 
@@ -131,6 +158,7 @@ __global__ __launch_bounds__(256) void apply_u1(StageArgs A) {
   m[0] = A.meta[2 * P * A.nn + node];
   m[1] = A.meta[2 * P * A.nn + node + A.nn];
   const int c = m[0].c;
+  const int halves = c > kWave ? 2 : 1;  // wave-uniform
 #pragma unroll
   for (int h = 0; h < 2; ++h)
     if (lane < m[h].k) s_w[w][h][lane] = in[m[h].skel_off + lane];
@@ -141,20 +169,24 @@ __global__ __launch_bounds__(256) void apply_u1(StageArgs A) {
     stream_products<C, nv_for<C>()>(T + m[h].t_off, m[h].k * r, r, s_w[w][h], s_p + h * A.pmax, lane);
   }
   wave_sync_lds();
-  if (lane < c) {
-    C acc = czero(C{});
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int below = __popcll(m[h].mask & lanes_below(lane));
-      if ((m[h].mask >> lane) & 1ull) {
-        acc = cadd(acc, s_w[w][h][below]);
-      } else {
-        const int r = c - m[h].k;
-        const C* p = s_p + h * A.pmax + (lane - below);
-        for (int i = 0; i < m[h].k; ++i) acc = cadd(acc, p[i * r]);
+  for (int hp = 0; hp < 2; ++hp) {
+    const int pos = lane + kWave * hp;
+    if (hp < halves && pos < c) {
+      C acc = czero(C{});
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int below = mbelow(m[h], pos);
+        if (mbit(m[h], pos)) {
+          acc = cadd(acc, s_w[w][h][below]);
+        } else {
+          const int r = c - m[h].k;
+          const C* p = s_p + h * A.pmax + (pos - below);
+          for (int i = 0; i < m[h].k; ++i) acc = cadd(acc, p[i * r]);
+        }
       }
+      out[m[0].cand_beg + pos] = acc;
     }
-    out[m[0].cand_beg + lane] = acc;
   }
 }
 
@@ -244,124 +276,143 @@ __device__ __forceinline__ void stage_block(const C* src, int n, C* dst) {
   for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
 }
 
+constexpr int kRankChunk = 16;  // outputs (V, S) or inputs (U) held in registers per pass
+
+// V stage: the ID's T (dynamic LDS, k r entries) is applied to one RHS per
+// thread, kRankChunk outputs per pass.
 template <typename C>
 __global__ __launch_bounds__(256) void apply_vn(StageArgs A) {
-  __shared__ C s_T[kSlot];
+  extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
+  C* s_T = reinterpret_cast<C*>(s_dyn);
   __shared__ int s_skel[kMaxCand];
   __shared__ int s_red[kMaxCand];
   const int64_t q = blockIdx.x;
   const int64_t n = blockIdx.y * (int64_t)kRhsTile + threadIdx.x;
-  const int c = A.cand_len[q], k = A.rank[q], cb = A.cand_beg[q], so = A.skel_off[q];
+  const ApplyMeta m = A.meta[q];
+  const int c = m.c, k = m.k, cb = m.cand_beg, so = m.skel_off;
   const int r = c - k;
-  const uint64_t msk = A.mask[q];
-  if (threadIdx.x < c) {
-    const int l = threadIdx.x;
-    const int below = __popcll(msk & lanes_below(l));
-    if ((msk >> l) & 1ull) s_skel[below] = l; else s_red[l - below] = l;
+  for (int l = threadIdx.x; l < c; l += blockDim.x) {
+    const int below = mbelow(m, l);
+    if (mbit(m, l)) s_skel[below] = l; else s_red[l - below] = l;
   }
-  stage_block(static_cast<const C*>(A.T) + A.T_off[q], k * r, s_T);
+  stage_block(static_cast<const C*>(A.T) + m.t_off, k * r, s_T);
   __syncthreads();
   if (n >= A.nrhs) return;
   const C* in = static_cast<const C*>(A.in) + n;
   C* out = static_cast<C*>(A.out) + n;
   const int64_t nr = A.nrhs;
-  C acc[kMaxRank];
+  for (int i0 = 0; i0 < k; i0 += kRankChunk) {
+    C acc[kRankChunk];
 #pragma unroll
-  for (int i = 0; i < kMaxRank; ++i) acc[i] = czero(C{});
-  for (int j = 0; j < r; ++j) {
-    const C uj = in[(int64_t)(cb + s_red[j]) * nr];
-    const C* t = s_T + j * k;
+    for (int i = 0; i < kRankChunk; ++i) acc[i] = czero(C{});
+    for (int j = 0; j < r; ++j) {
+      const C uj = in[(int64_t)(cb + s_red[j]) * nr];
+      const C* t = s_T + j * k + i0;
 #pragma unroll
-    for (int i = 0; i < kMaxRank; ++i)
-      if (i < k) acc[i] = cfma(t[i], uj, acc[i]);
+      for (int i = 0; i < kRankChunk; ++i)
+        if (i0 + i < k) acc[i] = cfma(t[i], uj, acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < kRankChunk; ++i)
+      if (i0 + i < k) out[(int64_t)(so + i0 + i) * nr] = cadd(acc[i], in[(int64_t)(cb + s_skel[i0 + i]) * nr]);
   }
-#pragma unroll
-  for (int i = 0; i < kMaxRank; ++i)
-    if (i < k) out[(int64_t)(so + i) * nr] = cadd(acc[i], in[(int64_t)(cb + s_skel[i]) * nr]);
 }
 
+// U stage: the unit's two T blocks (dynamic LDS, 2 pmax entries); one RHS per
+// thread; each pass takes kRankChunk inputs of one ID and adds their
+// contribution to every candidate position (the first pass writes).
 template <typename C>
 __global__ __launch_bounds__(256) void apply_un(StageArgs A) {
-  __shared__ C s_T[2][kSlot];
+  extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
+  C* s_T = reinterpret_cast<C*>(s_dyn);
   const int64_t unit = blockIdx.x;
   const int64_t n = blockIdx.y * (int64_t)kRhsTile + threadIdx.x;
   const int64_t P = unit / A.nn, node = unit % A.nn;
-  const int64_t qa = 2 * P * A.nn + node, qb = qa + A.nn;
-  const int c = A.cand_len[qa], cb = A.cand_beg[qa];
-  const int ka = A.rank[qa], kb = A.rank[qb];
-  const int soa = A.skel_off[qa], sob = A.skel_off[qb];
-  const uint64_t ma = A.mask[qa], mb = A.mask[qb];
+  ApplyMeta m[2];
+  m[0] = A.meta[2 * P * A.nn + node];
+  m[1] = A.meta[2 * P * A.nn + node + A.nn];
+  const int c = m[0].c, cb = m[0].cand_beg;
   const C* T = static_cast<const C*>(A.T);
-  stage_block(T + A.T_off[qa], ka * (c - ka), s_T[0]);
-  stage_block(T + A.T_off[qb], kb * (c - kb), s_T[1]);
+  stage_block(T + m[0].t_off, m[0].k * (c - m[0].k), s_T);
+  stage_block(T + m[1].t_off, m[1].k * (c - m[1].k), s_T + A.pmax);
   __syncthreads();
   if (n >= A.nrhs) return;
   const C* in = static_cast<const C*>(A.in) + n;
   C* out = static_cast<C*>(A.out) + n;
   const int64_t nr = A.nrhs;
-  C wa[kMaxRank], wb[kMaxRank];
+  bool first = true;
+  for (int h = 0; h < 2; ++h) {
+    const int k = m[h].k, r = c - k, so = m[h].skel_off;
+    const C* Th = s_T + h * A.pmax;
+    for (int i0 = 0; i0 < k; i0 += kRankChunk) {
+      C wv[kRankChunk];
 #pragma unroll
-  for (int i = 0; i < kMaxRank; ++i) {
-    wa[i] = (i < ka) ? in[(int64_t)(soa + i) * nr] : czero(C{});
-    wb[i] = (i < kb) ? in[(int64_t)(sob + i) * nr] : czero(C{});
-  }
-  const int ra = c - ka, rb = c - kb;
-  for (int l = 0; l < c; ++l) {
-    C acc = czero(C{});
-    const int ba = __popcll(ma & lanes_below(l)), bb = __popcll(mb & lanes_below(l));
-    if ((ma >> l) & 1ull) {
-      acc = cadd(acc, in[(int64_t)(soa + ba) * nr]);
-    } else {
-      const C* t = s_T[0] + (l - ba);
+      for (int i = 0; i < kRankChunk; ++i) wv[i] = (i0 + i < k) ? in[(int64_t)(so + i0 + i) * nr] : czero(C{});
+      for (int l = 0; l < c; ++l) {
+        C acc = first ? czero(C{}) : out[(int64_t)(cb + l) * nr];
+        const int below = mbelow(m[h], l);
+        if (mbit(m[h], l)) {
+          if (below >= i0 && below < i0 + kRankChunk) acc = cadd(acc, in[(int64_t)(so + below) * nr]);
+        } else {
+          const C* t = Th + (int64_t)i0 * r + (l - below);
 #pragma unroll
-      for (int i = 0; i < kMaxRank; ++i)
-        if (i < ka) acc = cfma(t[i * ra], wa[i], acc);
+          for (int i = 0; i < kRankChunk; ++i)
+            if (i0 + i < k) acc = cfma(t[i * r], wv[i], acc);
+        }
+        out[(int64_t)(cb + l) * nr] = acc;
+      }
+      first = false;
     }
-    if ((mb >> l) & 1ull) {
-      acc = cadd(acc, in[(int64_t)(sob + bb) * nr]);
-    } else {
-      const C* t = s_T[1] + (l - bb);
-#pragma unroll
-      for (int i = 0; i < kMaxRank; ++i)
-        if (i < kb) acc = cfma(t[i * rb], wb[i], acc);
-    }
-    out[(int64_t)(cb + l) * nr] = acc;
   }
 }
 
+// Middle stage: one U_H ID per workgroup, its blocks staged in dynamic LDS
+// one at a time (pmax entries); kRankChunk outputs per pass.
 template <typename C>
 __global__ __launch_bounds__(256) void apply_sn(StageArgs A) {
-  __shared__ C s_S[kSlot];
+  extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
+  C* s_S = reinterpret_cast<C*>(s_dyn);
   const int64_t q = blockIdx.x;
   const int64_t n = blockIdx.y * (int64_t)kRhsTile + threadIdx.x;
   const int64_t b0 = q * A.nsub;
   const int rl = A.rlen[b0], rbg = A.rbeg[b0];
   const bool live = n < A.nrhs;
   const C* in = static_cast<const C*>(A.in) + (live ? n : 0);
+  C* out = static_cast<C*>(A.out) + (live ? n : 0);
   const int64_t nr = A.nrhs;
-  C acc[kMaxRank];
+  for (int i0 = 0; i0 < rl; i0 += kRankChunk) {
+    C acc[kRankChunk];
 #pragma unroll
-  for (int i = 0; i < kMaxRank; ++i) acc[i] = czero(C{});
-  for (int jb = 0; jb < A.nsub; ++jb) {
-    const int64_t b = b0 + jb;
-    const int cl = A.clen[b], cbg = A.cbeg[b];
-    __syncthreads();
-    stage_block(static_cast<const C*>(A.T) + A.T_off[b], rl * cl, s_S);
-    __syncthreads();
-    if (!live) continue;
-    for (int col = 0; col < cl; ++col) {
-      const C zc = in[(int64_t)(cbg + col) * nr];
-      const C* sc = s_S + col * rl;
+    for (int i = 0; i < kRankChunk; ++i) acc[i] = czero(C{});
+    for (int jb = 0; jb < A.nsub; ++jb) {
+      const int64_t b = b0 + jb;
+      const int cl = A.clen[b], cbg = A.cbeg[b];
+      __syncthreads();
+      stage_block(static_cast<const C*>(A.T) + A.T_off[b], rl * cl, s_S);
+      __syncthreads();
+      if (!live) continue;
+      for (int col = 0; col < cl; ++col) {
+        const C zc = in[(int64_t)(cbg + col) * nr];
+        const C* sc = s_S + col * rl + i0;
 #pragma unroll
-      for (int i = 0; i < kMaxRank; ++i)
-        if (i < rl) acc[i] = cfma(sc[i], zc, acc[i]);
+        for (int i = 0; i < kRankChunk; ++i)
+          if (i0 + i < rl) acc[i] = cfma(sc[i], zc, acc[i]);
+      }
     }
-  }
-  if (!live) return;
-  C* out = static_cast<C*>(A.out) + n;
+    if (!live) continue;
 #pragma unroll
-  for (int i = 0; i < kMaxRank; ++i)
-    if (i < rl) out[(int64_t)(rbg + i) * nr] = acc[i];
+    for (int i = 0; i < kRankChunk; ++i)
+      if (i0 + i < rl) out[(int64_t)(rbg + i0 + i) * nr] = acc[i];
+  }
+}
+
+// Raise a kernel's dynamic LDS limit once when a launch needs more than the
+// default (gfx950 workgroups may use up to 160 KB).
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= (size_t(64) << 10)) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
 }
 
 inline unsigned grid1(int64_t n, int ipb = kIdsPerBlock) { return (unsigned)((n + ipb - 1) / ipb); }
@@ -381,11 +432,15 @@ hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st) {
   if (a.nrhs == 1) {
     const size_t per = (size_t)a.pmax * (fp64 ? 16 : 8);
     const int ipb = ids_per_block(per);
+    hipError_t e = fp64 ? allow_lds(apply_v1<double2>, ipb * per) : allow_lds(apply_v1<float2>, ipb * per);
+    if (e != hipSuccess) return e;
     if (fp64) hipLaunchKernelGGL(apply_v1<double2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
     else hipLaunchKernelGGL(apply_v1<float2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
   } else {
-    if (fp64) hipLaunchKernelGGL(apply_vn<double2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(apply_vn<float2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);
+    if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
+    const size_t lds = (size_t)a.pmax * sizeof(double2);
+    if (hipError_t e = allow_lds(apply_vn<double2>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL(apply_vn<double2>, gridn(a.n, a.nrhs), dim3(256), lds, st, a);
   }
   return hipGetLastError();
 }
@@ -395,11 +450,15 @@ hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st) {
   if (a.nrhs == 1) {
     const size_t per = (size_t)2 * a.pmax * (fp64 ? 16 : 8);
     const int ipb = ids_per_block(per);
+    hipError_t e = fp64 ? allow_lds(apply_u1<double2>, ipb * per) : allow_lds(apply_u1<float2>, ipb * per);
+    if (e != hipSuccess) return e;
     if (fp64) hipLaunchKernelGGL(apply_u1<double2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
     else hipLaunchKernelGGL(apply_u1<float2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
   } else {
-    if (fp64) hipLaunchKernelGGL(apply_un<double2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(apply_un<float2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);
+    if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
+    const size_t lds = 2 * (size_t)a.pmax * sizeof(double2);
+    if (hipError_t e = allow_lds(apply_un<double2>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL(apply_un<double2>, gridn(a.n, a.nrhs), dim3(256), lds, st, a);
   }
   return hipGetLastError();
 }
@@ -421,8 +480,10 @@ hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st) {
       else hipLaunchKernelGGL(apply_s1_direct<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
     }
   } else {
-    if (fp64) hipLaunchKernelGGL(apply_sn<double2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(apply_sn<float2>, gridn(a.n, a.nrhs), dim3(256), 0, st, a);
+    if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
+    const size_t lds = (size_t)a.pmax * sizeof(double2);
+    if (hipError_t e = allow_lds(apply_sn<double2>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL(apply_sn<double2>, gridn(a.n, a.nrhs), dim3(256), lds, st, a);
   }
   return hipGetLastError();
 }

@@ -33,8 +33,8 @@ namespace {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kMaxKg = 128;  // largest K of a unit (S stage: 4 blocks of <= 32)
-constexpr int kMaxMg = 64;   // largest M of a unit (U stage: c <= 64)
+constexpr int kMaxKg = 256;  // largest K of a unit (S stage: 4 blocks of <= 64 columns)
+constexpr int kMaxMg = 128;  // largest M of a unit (V: k_0 + k_1, U: c)
 constexpr int kRhsPerWave = 64;
 constexpr int kWavesG = 4;
 
@@ -67,7 +67,7 @@ __device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_o
     for (int jb = 0; jb < A.nsub; ++jb) K += A.clen[b0 + jb];
     u = Unit{rl, K};
     const int lda = lda_for(K);
-    for (int e = threadIdx.x; e < 32 * lda; e += blockDim.x) s_A[e] = make_float2(0.f, 0.f);
+    for (int e = threadIdx.x; e < A.gemm_rows * lda; e += blockDim.x) s_A[e] = make_float2(0.f, 0.f);
     for (int i = threadIdx.x; i < rl; i += blockDim.x) s_out[i] = rbg + i;
     __syncthreads();
     int off = 0;
@@ -86,10 +86,10 @@ __device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_o
     const bool isV = (MODE == kModeV);
     u = isV ? Unit{k0 + m1.k, c} : Unit{c, k0 + m1.k};
     const int lda = lda_for(u.K);
-    for (int e = threadIdx.x; e < kMaxMg * lda; e += blockDim.x) s_A[e] = make_float2(0.f, 0.f);
+    for (int e = threadIdx.x; e < A.gemm_rows * lda; e += blockDim.x) s_A[e] = make_float2(0.f, 0.f);
     __syncthreads();  // zero fill before the identity entries
-    for (int e = threadIdx.x; e < 2 * kWave; e += blockDim.x) {  // (ID h, candidate position l)
-      const int h = e >> 6, l = e & (kWave - 1);
+    for (int e = threadIdx.x; e < 2 * kMaxMg; e += blockDim.x) {  // (ID h, candidate position l)
+      const int h = e / kMaxMg, l = e % kMaxMg;
       const ApplyMeta& m = h ? m1 : m0;
       const int base = h ? k0 : 0;  // first row (V) or column (U) of ID h in A
       if (l < m.k) {
@@ -101,8 +101,9 @@ __device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_o
           if (isV) s_src[l] = m.cand_beg + l;
           else s_out[l] = m.cand_beg + l;
         }
-        const int below = __popcll(m.mask & lanes_below(l));
-        if ((m.mask >> l) & 1ull) {
+        const int below = l < 64 ? __popcll(m.mask & lanes_below(l))
+                                 : __popcll(m.mask) + __popcll(m.mask_hi & lanes_below(l - 64));
+        if (l < 64 ? ((m.mask >> l) & 1ull) : ((m.mask_hi >> (l - 64)) & 1ull)) {
           if (isV) s_A[(base + below) * lda + l] = make_float2(1.f, 0.f);
           else s_A[l * lda + base + below] = make_float2(1.f, 0.f);
         } else {
@@ -144,10 +145,10 @@ __global__ __launch_bounds__(64 * kWavesG) void apply_gemm(StageArgs A) {
   const Unit u = stage_unit<MODE>(A, s_A, s_src, s_out, s_red);
   const int lane = threadIdx.x & (kWave - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  // V and U units: two wavefronts per block of right-hand sides, one per 32-row M-tile
-  constexpr int kTilesM = (MODE == kModeS) ? 1 : 2;
-  const int mt = w % kTilesM;
-  const int64_t rhs0 = (blockIdx.y * (int64_t)(blockDim.x / kWave / kTilesM) + w / kTilesM) * kRhsPerWave;
+  // one wavefront per (32-row M-tile, block of right-hand sides)
+  const int tiles = A.gemm_rows / 32;
+  const int mt = w % tiles;
+  const int64_t rhs0 = (blockIdx.y * (int64_t)(blockDim.x / kWave / tiles) + w / tiles) * kRhsPerWave;
   if (rhs0 >= A.nrhs || mt * 32 >= u.M) return;
   const int half = lane >> 5, jj = lane & 31;
   const int64_t nr = A.nrhs;
@@ -244,22 +245,29 @@ __global__ __launch_bounds__(64 * kWavesG) void apply_gemm(StageArgs A) {
 
 }  // namespace
 
-// LDS bytes of A for a stage whose largest unit has K <= kmax_unit
-static size_t gemm_lds(int mode, int kmax_unit) {
-  return (size_t)(mode == kModeS ? 32 : kMaxMg) * (size_t)(((kmax_unit + 15) & ~15) + 2) * sizeof(float2);
-}
-
-hipError_t launch_apply_gemm(const StageArgs& a, int mode, int kmax_unit, bool bf16, hipStream_t st) {
-  if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
-  if (kmax_unit < 1 || kmax_unit > kMaxKg) return hipErrorInvalidValue;
-  const int tiles_m = (mode == kModeS) ? 1 : 2;
-  const int blocks_rhs = (int)std::min<int64_t>(kWavesG / tiles_m, (a.nrhs + kRhsPerWave - 1) / kRhsPerWave);
+hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int mmax_unit, bool bf16,
+                             hipStream_t st) {
+  if (a0.n <= 0 || a0.nrhs <= 0) return hipSuccess;
+  if (kmax_unit < 1 || kmax_unit > kMaxKg || mmax_unit < 1 || mmax_unit > kMaxMg) return hipErrorInvalidValue;
+  StageArgs a = a0;
+  a.gemm_rows = (mmax_unit + 31) & ~31;
+  const int tiles_m = a.gemm_rows / 32;
+  const int blocks_rhs = (int)std::max<int64_t>(
+      1, std::min<int64_t>(kWavesG / tiles_m, (a.nrhs + kRhsPerWave - 1) / kRhsPerWave));
   const int waves = blocks_rhs * tiles_m;
   const int64_t per_block = (int64_t)blocks_rhs * kRhsPerWave;
   const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
   const dim3 block(64 * waves);
-  const size_t lds = gemm_lds(mode, kmax_unit);
-#define IDBF_GEMM(M, B) hipLaunchKernelGGL((apply_gemm<M, B>), grid, block, lds, st, a)
+  const size_t lds = (size_t)a.gemm_rows * (size_t)(((kmax_unit + 15) & ~15) + 2) * sizeof(float2);
+#define IDBF_GEMM(M, B)                                                                              \
+  do {                                                                                               \
+    if (lds > (size_t(64) << 10)) {                                                                  \
+      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_gemm<M, B>),          \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
+      if (e_ != hipSuccess) return e_;                                                               \
+    }                                                                                                \
+    hipLaunchKernelGGL((apply_gemm<M, B>), grid, block, lds, st, a);                                 \
+  } while (0)
   switch (mode) {
     case kModeV:
       if (bf16) IDBF_GEMM(kModeV, true); else IDBF_GEMM(kModeV, false);

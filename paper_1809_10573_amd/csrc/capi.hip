@@ -198,8 +198,8 @@ __global__ void check_points_kernel(const double* p, int64_t n, int32_t* bad) {
 // synchronization per phase.
 struct HostStage {
   int64_t st[8];
-  unsigned long long counts[8];
-  unsigned long long cursors[8];
+  unsigned long long counts[kQrBuckets];
+  unsigned long long cursors[kQrBuckets];
   int32_t bad[2];
 };
 
@@ -226,7 +226,7 @@ struct idbf_handle_s {
   int32_t* scratch = nullptr;  // skeleton lists before compaction (64 per ID)
   int32_t* samp_pos = nullptr; // sample positions of the current level (128 per ID)
   int32_t* order = nullptr;    // IDs of the current level grouped by QR wavefronts
-  unsigned long long* bucket = nullptr;  // [0..8): bucket counts, [8..16): fill cursors
+  unsigned long long* bucket = nullptr;  // [0, kQrBuckets): bucket counts, then the fill cursors
   int64_t* stats = nullptr;    // 8 int64 read back after each scan
   int32_t* status = nullptr;
   std::vector<Batch> U, V;
@@ -294,7 +294,7 @@ idbf_status level_begin(idbf_handle_s* h, const double* X, const double* Om, int
   TRY(A.get(n + 1, &b.skel_off));
   TRY(A.get(n, &b.t_bound));
   TRY(A.get(n + 1, &b.T_off));
-  TRY(A.get(n, &b.mask));
+  TRY(A.get(2 * n, &b.mask));
 
   const Batch* prev = nullptr;   // same side, level t-1
   const Batch* other = nullptr;  // allowed points' batch
@@ -331,8 +331,8 @@ idbf_status level_begin(idbf_handle_s* h, const double* X, const double* Om, int
   TRYHIP(launch_desc(d, h->stream));
   TRYHIP(launch_scan_i64(b.t_bound, n, b.T_off, b.cand_len, h->stats, h->stream));
   TRYHIP(launch_scan_i32(b.samples, n, b.skel_off, nullptr, h->stats + 4, h->stream));
-  TRYHIP(hipMemsetAsync(h->bucket, 0, 8 * sizeof(unsigned long long), h->stream));
-  TRYHIP(launch_bucket_count(b.samples, n, h->bucket, h->stream));
+  TRYHIP(hipMemsetAsync(h->bucket, 0, kQrBuckets * sizeof(unsigned long long), h->stream));
+  TRYHIP(launch_bucket_count(b.samples, b.cand_len, n, h->bucket, h->stream));
   h->prof.end(pr, h->stream);
   TRYHIP(hipMemcpyAsync(h->pin->counts, h->bucket, sizeof h->pin->counts, hipMemcpyDeviceToHost, h->stream));
   TRYHIP(hipMemcpyAsync(h->pin->st, h->stats, sizeof h->pin->st, hipMemcpyDeviceToHost, h->stream));
@@ -353,11 +353,6 @@ idbf_status level_ids(idbf_handle_s* h) {
   if (b.cand_max > kMaxCand) {
     set_error("level %d %c: a candidate set has %d points (max %d); ranks grew past %d", t,
               side == IDBF_SIDE_U ? 'U' : 'V', b.cand_max, kMaxCand, kMaxCand / 2);
-    return IDBF_EUNSUPPORTED;
-  }
-  if (b.s_max > kMaxSamples) {
-    set_error("level %d %c: %d samples requested (max %d); lower the oversampling", t,
-              side == IDBF_SIDE_U ? 'U' : 'V', b.s_max, kMaxSamples);
     return IDBF_EUNSUPPORTED;
   }
   TRY(A.get(std::max<int64_t>(b.n_T, 1), &b.T128));
@@ -382,14 +377,15 @@ idbf_status level_ids(idbf_handle_s* h) {
   ia.kmax = h->kmax;
   ia.oversample = h->oversample;
   ia.s_max = b.s_max;
+  ia.c_max = b.cand_max;
   ia.samp_pos = h->samp_pos;
   ia.order = h->order;
   ia.bucket_off[0] = 0;
-  for (int w = 1; w <= 8; ++w) ia.bucket_off[w] = ia.bucket_off[w - 1] + (int64_t)h->pin->counts[w - 1];
-  for (int w = 0; w < 8; ++w) h->pin->cursors[w] = (unsigned long long)ia.bucket_off[w];
-  TRYHIP(hipMemcpyAsync(h->bucket + 8, h->pin->cursors, sizeof h->pin->cursors, hipMemcpyHostToDevice,
+  for (int w = 0; w < kQrBuckets; ++w) ia.bucket_off[w + 1] = ia.bucket_off[w] + (int64_t)h->pin->counts[w];
+  for (int w = 0; w < kQrBuckets; ++w) h->pin->cursors[w] = (unsigned long long)ia.bucket_off[w];
+  TRYHIP(hipMemcpyAsync(h->bucket + kQrBuckets, h->pin->cursors, sizeof h->pin->cursors, hipMemcpyHostToDevice,
                         h->stream));
-  TRYHIP(launch_bucket_fill(b.samples, n, h->bucket + 8, h->order, h->stream));
+  TRYHIP(launch_bucket_fill(b.samples, b.cand_len, n, h->bucket + kQrBuckets, h->order, h->stream));
   ia.rank = b.rank;
   ia.mask = b.mask;
   ia.skel_out = h->scratch;
@@ -581,7 +577,7 @@ idbf_status construct_setup(idbf_handle_s* h) {
     TRY(A.get((int64_t(2) << h->L) * kMaxCand, &h->scratch));
     TRY(A.get((int64_t(2) << h->L) * kMaxSamples, &h->samp_pos));
     TRY(A.get(int64_t(2) << h->L, &h->order));
-    TRY(A.get(16, &h->bucket));
+    TRY(A.get(2 * kQrBuckets, &h->bucket));
   }
   return IDBF_OK;
 }
@@ -921,7 +917,7 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
       StageArgs g = a;
       g.n = b.n / 2;
       g.nn = 1 << (h->L - t + 1);
-      IDBF_HIP_CHECK(launch_apply_gemm(g, 0, b.cand_max, bf16, st));
+      IDBF_HIP_CHECK(launch_apply_gemm(g, 0, b.cand_max, 2 * b.rank_max, bf16, st));
     } else {
       IDBF_HIP_CHECK(launch_apply_v(a, fp64, st));
     }
@@ -948,7 +944,8 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     double bytes = double(h->nnz_S) * elem;
     if (h->H == 0) bytes += 2.0 * double(h->N) * nrhs * elem;
     const int pr = h->prof.begin(bf16 ? "applyb_s" : nrhs == 1 ? "apply1_s" : "applyn_s", st);
-    if (mfma && !a.dense) IDBF_HIP_CHECK(launch_apply_gemm(a, 1, a.nsub * h->V[h->H - 1].rank_max, bf16, st));
+    if (mfma && !a.dense)
+      IDBF_HIP_CHECK(launch_apply_gemm(a, 1, a.nsub * h->V[h->H - 1].rank_max, h->U[h->H - 1].rank_max, bf16, st));
     else IDBF_HIP_CHECK(launch_apply_s(a, fp64, st));
     h->prof.end(pr, st, bytes, 8.0 * double(h->nnz_S) * nrhs);
     in = a.out;
@@ -973,7 +970,7 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     a.out = (t == 1) ? y : buf[cur];
     const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
     const int pr = h->prof.begin(bf16 ? "applyb_u" : nrhs == 1 ? "apply1_u" : "applyn_u", st);
-    if (mfma) IDBF_HIP_CHECK(launch_apply_gemm(a, 2, 2 * b.rank_max, bf16, st));
+    if (mfma) IDBF_HIP_CHECK(launch_apply_gemm(a, 2, 2 * b.rank_max, b.cand_max, bf16, st));
     else IDBF_HIP_CHECK(launch_apply_u(a, fp64, st));
     h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T) * nrhs);
     in = a.out;
@@ -1134,7 +1131,7 @@ idbf_status idbf_batch_export(idbf_handle h, int32_t side, int32_t level, int32_
   IDBF_HIP_CHECK(hipDeviceSynchronize());
   if (rank) IDBF_HIP_CHECK(hipMemcpy(rank, b->rank, b->n * 4, hipMemcpyDeviceToHost));
   if (cand_len) IDBF_HIP_CHECK(hipMemcpy(cand_len, b->cand_len, b->n * 4, hipMemcpyDeviceToHost));
-  if (mask) IDBF_HIP_CHECK(hipMemcpy(mask, b->mask, b->n * 8, hipMemcpyDeviceToHost));
+  if (mask) IDBF_HIP_CHECK(hipMemcpy(mask, b->mask, b->n * 16, hipMemcpyDeviceToHost));
   if (skel) IDBF_HIP_CHECK(hipMemcpy(skel, b->skel_idx, b->n_skel * 4, hipMemcpyDeviceToHost));
   if (T) IDBF_HIP_CHECK(hipMemcpy(T, b->T128, b->n_T * 16, hipMemcpyDeviceToHost));
   if (T_off) IDBF_HIP_CHECK(hipMemcpy(T_off, b->T_off, b->n * 8, hipMemcpyDeviceToHost));
@@ -1206,18 +1203,16 @@ idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double
   IDBF_HIP_CHECK(hipMemcpyAsync(cl.data(), cand_len, n_ids * 4, hipMemcpyDeviceToHost, st));
   IDBF_HIP_CHECK(hipMemcpyAsync(al.data(), allow_len, n_ids * 4, hipMemcpyDeviceToHost, st));
   IDBF_HIP_CHECK(hipStreamSynchronize(st));
-  int smax = 0;
+  int smax = 0, cmax = 0;
   for (int64_t q = 0; q < n_ids; ++q) {
     if (cl[q] < 1 || cl[q] > kMaxCand || al[q] < 1) {
       set_error("ID %lld: candidate count %d must be in [1, %d] and allowed count %d >= 1", (long long)q, cl[q],
                 kMaxCand, al[q]);
       return IDBF_EINVAL;
     }
-    smax = std::max<int>(smax, (int)std::min<int64_t>((int64_t)oversample * cl[q], al[q]));
-  }
-  if (smax > kMaxSamples) {
-    set_error("%d samples requested (max %d)", smax, kMaxSamples);
-    return IDBF_EUNSUPPORTED;
+    smax = std::max<int>(smax, (int)std::min<int64_t>(std::min<int64_t>((int64_t)oversample * cl[q], al[q]),
+                                                      kMaxSamples));
+    cmax = std::max(cmax, cl[q]);
   }
   int32_t* status = nullptr;
   int32_t* samp_pos = nullptr;
@@ -1245,6 +1240,7 @@ idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double
   ia.kmax = kmax;
   ia.oversample = oversample;
   ia.s_max = smax;
+  ia.c_max = cmax;
   ia.samp_pos = samp_pos;
   ia.rank = rank;
   ia.mask = mask;

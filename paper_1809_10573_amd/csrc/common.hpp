@@ -11,10 +11,10 @@
 namespace idbf {
 
 constexpr int kWave = 64;        // CDNA wavefront width
-constexpr int kMaxCand = 64;     // candidates per ID: one lane each
-constexpr int kMaxSamples = 128; // sampled rows per ID
-constexpr int kMaxRank = 32;     // rank rows live in wave 0's registers
-constexpr int kSlot = 1024;      // T entries per ID in slot layout (max k (c - k))
+constexpr int kMaxCand = 128;    // candidates per ID (two lanes' worth above 64)
+constexpr int kMaxSamples = 128; // sampled rows per ID: s = min(t c, |allowed|, 128)
+constexpr int kMaxRank = 64;     // rank of an ID
+constexpr int kSlot = 4096;      // T entries per ID in slot layout (max k (c - k))
 constexpr double kPivotTie = 1e-8;
 
 struct PhaseDev {

@@ -26,7 +26,6 @@ namespace idbf {
 
 namespace {
 
-constexpr int kRPW = kRowsPerWaveQR;
 constexpr int kSelIds = 4;  // IDs (wavefronts) per selection workgroup
 
 __device__ double cheb_fraction(int j, int s) {
@@ -145,8 +144,8 @@ __global__ __launch_bounds__(64 * kSelIds) void select_kernel(IdArgs A) {
   const int64_t q = blockIdx.x * (int64_t)kSelIds + w;
   if (q >= A.n_ids) return;
   const int c = A.cand_len[q], na = A.allow_len[q];
-  const int s = min(A.oversample * c, na);
-  if (c < 1 || c > kMaxCand || na < 1 || s > kMaxSamples) return;  // id_kernel reports it
+  const int s = min(min(A.oversample * c, na), kMaxSamples);
+  if (c < 1 || c > kMaxCand || na < 1) return;  // id_kernel reports it
   int32_t* out = A.samp_pos + q * (int64_t)kMaxSamples;
   if (s >= na) {
     for (int j = lane; j < na; j += kWave) out[j] = j;
@@ -204,22 +203,27 @@ __device__ __forceinline__ double wave_max_dpp(double v) {
   return readlane(v, kWave - 1);
 }
 
-// Rows [row0, row0 + 16) of one wavefront, restricted to rows >= j (the
-// predicate is uniform across the wavefront).
-#define IDBF_ROWS_FROM(j, BODY)                                  \
-  if (row0 + R > (j)) {                                          \
-    _Pragma("unroll") for (int i = 0; i < R; ++i) {              \
-      if (row0 + i >= (j)) { BODY; }                             \
-    }                                                            \
-  }
+__device__ __forceinline__ bool skel_bit(uint64_t lo, uint64_t hi, int p) {
+  return p < 64 ? ((lo >> p) & 1ull) : ((hi >> (p - 64)) & 1ull);
+}
 
-template <int W>
+// Number of skeletons among candidate positions < p (128-bit mask lo | hi).
+__device__ __forceinline__ int skel_below(uint64_t lo, uint64_t hi, int p) {
+  return p < 64 ? __popcll(lo & lanes_below(p)) : __popcll(lo) + __popcll(hi & lanes_below(p - 64));
+}
+
+// One ID per workgroup of W wavefronts.  Lane l owns candidate columns
+// l + 64 cs (cs < CPL); wavefront w holds sampled rows [R w, R w + R).
+//   CPL = 1, R = 16: up to 64 candidates (W <= 8);
+//   CPL = 2, R = 8:  up to 128 candidates (W <= 16), same registers per lane.
+template <int W, int CPL, int R>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) void id_kernel(IdArgs A) {
-  constexpr int R = kRPW;
   constexpr int SMAX = R * W;
+  constexpr int NC = kWave * CPL;     // candidate columns covered
+  constexpr int kChunk = 32;          // R rows staged in LDS per back-substitution chunk
   // partial sums of the QR loop and the R rows of the solve share LDS
-  constexpr size_t kPart = (size_t)W * kWave * (sizeof(double) + sizeof(double2));
-  constexpr size_t kRrows = (size_t)kMaxRank * kWave * sizeof(double2);
+  constexpr size_t kPart = (size_t)W * CPL * kWave * (sizeof(double) + sizeof(double2));
+  constexpr size_t kRrows = (size_t)kChunk * NC * sizeof(double2);
   __shared__ __attribute__((aligned(16))) unsigned char s_raw[kPart > kRrows ? kPart : kRrows];
   __shared__ double s_coord[SMAX];
   __shared__ double s_cx[SMAX];
@@ -228,9 +232,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   __shared__ int s_srank[kMaxRank];
   __shared__ double s_axj[2];
   __shared__ double2 s_alpha;
-  double* s_part = reinterpret_cast<double*>(s_raw);                                    // [W][64]
-  double2* s_partc = reinterpret_cast<double2*>(s_raw + W * kWave * sizeof(double));   // [W][64]
-  double2* s_R = reinterpret_cast<double2*>(s_raw);                                     // [32][64]
+  double* s_part = reinterpret_cast<double*>(s_raw);                                         // [W][CPL][64]
+  double2* s_partc = reinterpret_cast<double2*>(s_raw + W * CPL * kWave * sizeof(double));  // [W][CPL][64]
+  double2* s_R = reinterpret_cast<double2*>(s_raw);                                          // [kChunk][NC]
 
   const int64_t q = A.order ? A.order[blockIdx.x] : (int64_t)blockIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
@@ -238,22 +242,29 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   const int nthreads = kWave * W;
   const int cb = A.cand_beg[q], c = A.cand_len[q];
   const int ab = A.allow_beg[q], na = A.allow_len[q];
-  const int s = min(A.oversample * c, na);
-  if (c < 1 || c > kMaxCand || na < 1 || s > SMAX) {
+  const int s = min(min(A.oversample * c, na), kMaxSamples);
+  if (c < 1 || c > NC || na < 1 || s > SMAX) {
     if (threadIdx.x == 0) atomicOr(A.status, kErrSize);
     return;
   }
   const bool isV = (A.side == IDBF_SIDE_V);
   const bool fio = (A.ph.kind == IDBF_PHASE_FIO);
-  const Seg cs{A.cand_coord ? A.cand_coord + cb : nullptr, isV ? A.Om : A.X, A.cand_idx + cb};
+  const Seg cs_{A.cand_coord ? A.cand_coord + cb : nullptr, isV ? A.Om : A.X, A.cand_idx + cb};
   const Seg as{A.allow_coord ? A.allow_coord + ab : nullptr, isV ? A.X : A.Om, A.allow_idx + ab};
 
-  int gidx = 0;
-  double ccoord = 0.0, ccx = 0.0;
-  if (lane < c) {
-    gidx = A.cand_idx[cb + lane];
-    ccoord = cs(lane);
-    if (!isV && fio) ccx = amplitude_shift(A.ph, ccoord);
+  int gidx[CPL];
+  double ccoord[CPL], ccx[CPL];
+#pragma unroll
+  for (int cs = 0; cs < CPL; ++cs) {
+    const int col = lane + kWave * cs;
+    gidx[cs] = 0;
+    ccoord[cs] = 0.0;
+    ccx[cs] = 0.0;
+    if (col < c) {
+      gidx[cs] = A.cand_idx[cb + col];
+      ccoord[cs] = cs_(col);
+      if (!isV && fio) ccx[cs] = amplitude_shift(A.ph, ccoord[cs]);
+    }
   }
   const int32_t* sp = A.samp_pos + q * (int64_t)kMaxSamples;
   for (int j = threadIdx.x; j < s; j += nthreads) {
@@ -263,48 +274,69 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   }
   __syncthreads();
 
-  // sampled block: rows [R w, R w + R) of column `lane` (rows >= s stay zero)
+  // sampled block: rows [R w, R w + R) of columns lane + 64 cs (rows >= s stay zero)
   const int row0 = w * R;
-  double2 a[R];
+  double2 a[CPL][R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const int row = row0 + i;
-    double2 v = make_double2(0.0, 0.0);
-    if (lane < c && row < s)
-      v = isV ? kernel_entry(A.ph, s_coord[row], s_cx[row], ccoord)
-              : kernel_entry(A.ph, ccoord, ccx, s_coord[row]);
-    a[i] = v;
-  }
+  for (int cs = 0; cs < CPL; ++cs)
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int row = row0 + i;
+      double2 v = make_double2(0.0, 0.0);
+      if (lane + kWave * cs < c && row < s)
+        v = isV ? kernel_entry(A.ph, s_coord[row], s_cx[row], ccoord[cs])
+                : kernel_entry(A.ph, ccoord[cs], ccx[cs], s_coord[row]);
+      a[cs][i] = v;
+    }
 
   const int kuser = min(min(s, c), A.kmax > 0 ? A.kmax : (1 << 30));
-  bool pivoted = false;
+  bool pivoted[CPL];
+#pragma unroll
+  for (int cs = 0; cs < CPL; ++cs) pivoted[cs] = false;
   double r00 = 0.0;
   int k = 0;
   bool zero_block = false, overflow = false;
   for (int j = 0;; ++j) {
-    // residual column norms over rows >= j (two independent sums)
+    // residual column norms over rows >= j (two independent sums per column)
     const bool live = row0 + R > j;  // wave-uniform: this wave holds rows >= j
-    double part = 0.0;
-    if (live) {
-      double p0 = 0.0, p1 = 0.0;
+    double part[CPL];
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const double t = (row0 + i >= j) ? cabs2(a[i]) : 0.0;
-        if (i & 1) p1 += t; else p0 += t;
+    for (int cs = 0; cs < CPL; ++cs) {
+      part[cs] = 0.0;
+      if (live) {
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const double t = (row0 + i >= j) ? cabs2(a[cs][i]) : 0.0;
+          if (i & 1) p1 += t; else p0 += t;
+        }
+        part[cs] = p0 + p1;
       }
-      part = p0 + p1;
     }
-    double nrm2 = part;
-    if constexpr (W > 1) {
-      s_part[w * kWave + lane] = part;
-      __syncthreads();
-      nrm2 = 0.0;
+    double nrm2[CPL];
 #pragma unroll
-      for (int ww = 0; ww < W; ++ww) nrm2 += s_part[ww * kWave + lane];
+    for (int cs = 0; cs < CPL; ++cs) nrm2[cs] = part[cs];
+    if constexpr (W > 1) {
+#pragma unroll
+      for (int cs = 0; cs < CPL; ++cs) s_part[(w * CPL + cs) * kWave + lane] = part[cs];
+      __syncthreads();
+#pragma unroll
+      for (int cs = 0; cs < CPL; ++cs) {
+        nrm2[cs] = 0.0;
+#pragma unroll(CPL == 1 ? W : 4)
+        for (int ww = 0; ww < W; ++ww) nrm2[cs] += s_part[(ww * CPL + cs) * kWave + lane];
+      }
     }
-    const bool eligible = (lane < c) && !pivoted;
-    const double nu = eligible ? sqrt(nrm2) : -1.0;
-    const double M = wave_max_dpp(nu);
+    bool eligible[CPL];
+    double nu[CPL];
+    double numax = -1.0;
+#pragma unroll
+    for (int cs = 0; cs < CPL; ++cs) {
+      eligible[cs] = (lane + kWave * cs < c) && !pivoted[cs];
+      nu[cs] = eligible[cs] ? sqrt(nrm2[cs]) : -1.0;
+      numax = fmax(numax, nu[cs]);
+    }
+    const double M = wave_max_dpp(numax);
     if (j == 0) {
       r00 = M;
       if (M == 0.0) {
@@ -319,18 +351,26 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       overflow = true;
       break;
     }
-    const uint64_t near = __ballot(eligible && nu >= (1.0 - kPivotTie) * M);
-    if (near == 0) break;  // no finite residual norm left (cannot happen for finite input)
-    const int p = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)near) - 1);
-    // Householder vector of the pivot column (rows >= j): lane p of every wave
+    const double thr = (1.0 - kPivotTie) * M;
+    const uint64_t near0 = __ballot(eligible[0] && nu[0] >= thr);
+    uint64_t near1 = 0;
+    if constexpr (CPL > 1) near1 = __ballot(eligible[CPL - 1] && nu[CPL - 1] >= thr);
+    if (near0 == 0 && near1 == 0) break;  // no finite residual norm left (cannot happen for finite input)
+    const int p = __builtin_amdgcn_readfirstlane(
+        near0 ? __ffsll((unsigned long long)near0) - 1 : kWave + __ffsll((unsigned long long)near1) - 1);
+    const int pl = p & (kWave - 1), pc = p / kWave;  // pivot lane and column slot (uniform)
+    // Householder vector of the pivot column (rows >= j): lane pl of every wave
     // publishes its own rows to the wave's slice of LDS (no workgroup barrier),
     // zero above row j, so that rows < j drop out of the dot and the update
     // exactly; v_i = a_i(p) for i > j and v_j = x_j - alpha,
     // alpha = -(x_j/|x_j|) nu_p, tau = 2 / |v|^2 = 1 / (nu_p (nu_p + |x_j|)).
-    const double nup = readlane(nu, p);
-    if (lane == p && live) {
+    const double nup = readlane(pc == 0 ? nu[0] : nu[CPL - 1], pl);
+    if (lane == pl && live) {
 #pragma unroll
-      for (int i = 0; i < R; ++i) s_v[row0 + i] = (row0 + i >= j) ? a[i] : make_double2(0.0, 0.0);
+      for (int i = 0; i < R; ++i) {
+        const double2 ai = (pc == 0) ? a[0][i] : a[CPL - 1][i];
+        s_v[row0 + i] = (row0 + i >= j) ? ai : make_double2(0.0, 0.0);
+      }
       if (row0 <= j) {  // this wave holds row j: form the head (same-lane LDS accesses are ordered)
         const double2 xj = s_v[j];
         const double axj = sqrt(cabs2(xj));
@@ -348,100 +388,139 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       }
     }
     wave_lds_sync();
-    double2 dot = make_double2(0.0, 0.0);
-    if (live) {
-      double2 d0 = make_double2(0.0, 0.0), d1 = make_double2(0.0, 0.0);
+    double2 dot[CPL];
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        if (i & 1) d1 = cfma_conj(s_v[row0 + i], a[i], d1);
-        else d0 = cfma_conj(s_v[row0 + i], a[i], d0);
+    for (int cs = 0; cs < CPL; ++cs) {
+      dot[cs] = make_double2(0.0, 0.0);
+      if (live) {
+        double2 d0 = make_double2(0.0, 0.0), d1 = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          if (i & 1) d1 = cfma_conj(s_v[row0 + i], a[cs][i], d1);
+          else d0 = cfma_conj(s_v[row0 + i], a[cs][i], d0);
+        }
+        dot[cs] = cadd(d0, d1);
       }
-      dot = cadd(d0, d1);
     }
-    double tau;
     if constexpr (W > 1) {
-      s_partc[w * kWave + lane] = dot;
+#pragma unroll
+      for (int cs = 0; cs < CPL; ++cs) s_partc[(w * CPL + cs) * kWave + lane] = dot[cs];
       __syncthreads();
-      dot = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int ww = 0; ww < W; ++ww) dot = cadd(dot, s_partc[ww * kWave + lane]);
+      for (int cs = 0; cs < CPL; ++cs) {
+        dot[cs] = make_double2(0.0, 0.0);
+#pragma unroll(CPL == 1 ? W : 4)
+        for (int ww = 0; ww < W; ++ww) dot[cs] = cadd(dot[cs], s_partc[(ww * CPL + cs) * kWave + lane]);
+      }
     }
-    tau = 1.0 / (nup * (nup + s_axj[j & 1]));
+    const double tau = 1.0 / (nup * (nup + s_axj[j & 1]));
     if (live) {
-      if (eligible && lane != p) {
-        const double2 sdot = make_double2(-tau * dot.x, -tau * dot.y);
 #pragma unroll
-        for (int i = 0; i < R; ++i) a[i] = cfma(s_v[row0 + i], sdot, a[i]);
+      for (int cs = 0; cs < CPL; ++cs) {
+        if (eligible[cs] && !(lane == pl && cs == pc)) {
+          const double2 sdot = make_double2(-tau * dot[cs].x, -tau * dot[cs].y);
+#pragma unroll
+          for (int i = 0; i < R; ++i) a[cs][i] = cfma(s_v[row0 + i], sdot, a[cs][i]);
+        }
       }
       // the pivot column becomes (alpha, 0, ..., 0) from row j down
-      if (lane == p) {
+      if (lane == pl) {
         const double2 alpha = s_alpha;
 #pragma unroll
-        for (int i = 0; i < R; ++i)
-          if (row0 + i >= j) a[i] = (row0 + i == j) ? alpha : make_double2(0.0, 0.0);
+        for (int cs = 0; cs < CPL; ++cs)
+          if (cs == pc)
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+              if (row0 + i >= j) a[cs][i] = (row0 + i == j) ? alpha : make_double2(0.0, 0.0);
       }
     }
-    if (lane == p) pivoted = true;
+    if (lane == pl) {
+#pragma unroll
+      for (int cs = 0; cs < CPL; ++cs)
+        if (cs == pc) pivoted[cs] = true;
+    }
     if (threadIdx.x == 0) s_piv[j] = p;
     k = j + 1;
   }
   if (k == 0) zero_block = true;  // no pivot taken: keep the first candidate, T = 0
   if (zero_block) {
     k = 1;
-    pivoted = (lane == 0);
+#pragma unroll
+    for (int cs = 0; cs < CPL; ++cs) pivoted[cs] = (cs == 0 && lane == 0);
     if (threadIdx.x == 0) s_piv[0] = 0;
   }
   if (overflow && threadIdx.x == 0) atomicOr(A.status, kErrRank);
-  __syncthreads();  // every read of the partial sums is done: s_raw now holds R rows
+  __syncthreads();  // s_piv complete; every read of the partial sums is done
 
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const int row = row0 + i;
-    if (row < k) s_R[row * kWave + lane] = zero_block ? make_double2(0.0, 0.0) : a[i];
-  }
-  const uint64_t msk = __ballot(pivoted && lane < c);
-  if (threadIdx.x < k) s_srank[threadIdx.x] = __popcll(msk & lanes_below(s_piv[threadIdx.x]));
-  __syncthreads();
-  if (w != 0) return;
-
-  const int below = __popcll(msk & lanes_below(lane));
-  const int r = c - k;
-  const bool redundant = (lane < c) && !pivoted;
-  if (lane == 0) {
-    A.rank[q] = k;
-    A.mask[q] = msk;
-  }
-  if (pivoted && lane < c) A.skel_out[q * kMaxCand + below] = gidx;
-  if (!redundant) return;
-  // back-substitution on this lane's column of R12, t overwriting it in LDS:
-  //   t_ii = (r_ii - sum_{l > ii} R[ii][piv_l] t_l) / R[ii][piv_ii]
-  const int jr = lane - below;
-  const int64_t off = A.T_off ? A.T_off[q] : q * (int64_t)kSlot;
-  for (int ii = k - 1; ii >= 0; --ii) {
-    double2 acc = s_R[ii * kWave + lane];
-    if (!zero_block) {
-      for (int l = ii + 1; l < k; ++l) {
-        const double2 rl = s_R[ii * kWave + s_piv[l]];
-        acc = cfma(make_double2(-rl.x, -rl.y), s_R[l * kWave + lane], acc);
-      }
-      const double2 d = s_R[ii * kWave + s_piv[ii]];
-      const double inv = 1.0 / cabs2(d);
-      acc = cmul(acc, make_double2(d.x * inv, -d.y * inv));
+  // skeleton masks (identical in every wave: pivot decisions are)
+  const uint64_t msk0 = __ballot(pivoted[0] && lane < c);
+  uint64_t msk1 = 0;
+  if constexpr (CPL > 1) msk1 = __ballot(pivoted[CPL - 1] && lane + kWave < c);
+  for (int i = threadIdx.x; i < k; i += nthreads) s_srank[i] = skel_below(msk0, msk1, s_piv[i]);
+  if (w == 0) {
+    if (lane == 0) {
+      A.rank[q] = k;
+      A.mask[2 * q] = msk0;
+      A.mask[2 * q + 1] = msk1;
     }
-    s_R[ii * kWave + lane] = acc;
-    const int sr = s_srank[ii];
-    const int64_t e = off + (isV ? (int64_t)jr * k + sr : (int64_t)sr * r + jr);
-    A.T128[e] = acc;
-    if (A.T64) A.T64[e] = make_float2((float)acc.x, (float)acc.y);
+#pragma unroll
+    for (int cs = 0; cs < CPL; ++cs) {
+      const int col = lane + kWave * cs;
+      if (pivoted[cs] && col < c) A.skel_out[q * kMaxCand + skel_below(msk0, msk1, col)] = gidx[cs];
+    }
+  }
+  // Back-substitution T = R11^{-1} R12 in chunks of kChunk R rows staged in
+  // LDS, last chunk first; waves 0..CPL-1 own the columns (one per thread):
+  //   t_ii = (r_ii - sum_{l > ii} R[ii][piv_l] t_l) / R[ii][piv_ii],
+  // t_l of earlier (higher) chunks read back from this thread's T entries.
+  const int r = c - k;
+  const int64_t off = A.T_off ? A.T_off[q] : q * (int64_t)kSlot;
+  const int col = (w < CPL) ? w * kWave + lane : 0;
+  const bool solver = (w < CPL) && col < c && !skel_bit(msk0, msk1, col);
+  const int jr = solver ? col - skel_below(msk0, msk1, col) : 0;
+  auto t_index = [&](int l) -> int64_t {  // T entry of (skeleton of pivot row l, this column)
+    const int sr = s_srank[l];
+    return off + (isV ? (int64_t)jr * k + sr : (int64_t)sr * r + jr);
+  };
+  for (int cb0 = ((k - 1) / kChunk) * kChunk; cb0 >= 0; cb0 -= kChunk) {
+    const int ce = min(k, cb0 + kChunk);
+    __syncthreads();  // the previous chunk's LDS reads are done
+#pragma unroll
+    for (int cs = 0; cs < CPL; ++cs)
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int row = row0 + i;
+        if (row >= cb0 && row < ce) s_R[(row - cb0) * NC + lane + kWave * cs] = zero_block ? make_double2(0.0, 0.0) : a[cs][i];
+      }
+    __syncthreads();
+    if (!solver) continue;
+    for (int ii = ce - 1; ii >= cb0; --ii) {
+      const double2* Ri = s_R + (ii - cb0) * NC;
+      double2 acc = Ri[col];
+      if (!zero_block) {
+        for (int l = ii + 1; l < ce; ++l) {
+          const double2 rl = Ri[s_piv[l]];
+          acc = cfma(make_double2(-rl.x, -rl.y), s_R[(l - cb0) * NC + col], acc);
+        }
+        for (int l = ce; l < k; ++l) {
+          const double2 rl = Ri[s_piv[l]];
+          acc = cfma(make_double2(-rl.x, -rl.y), A.T128[t_index(l)], acc);
+        }
+        const double2 d = Ri[s_piv[ii]];
+        const double inv = 1.0 / cabs2(d);
+        acc = cmul(acc, make_double2(d.x * inv, -d.y * inv));
+      }
+      s_R[(ii - cb0) * NC + col] = acc;
+      const int64_t e = t_index(ii);
+      A.T128[e] = acc;
+      if (A.T64) A.T64[e] = make_float2((float)acc.x, (float)acc.y);
+    }
   }
 }
-#undef IDBF_ROWS_FROM
 
 }  // namespace
 
-int id_batch_waves(int s_max) { return std::max(1, std::min(kMaxSamples / kRPW, (s_max + kRPW - 1) / kRPW)); }
-
-hipError_t launch_qr_waves(const IdArgs& a, int64_t n, int waves, hipStream_t st);
+hipError_t launch_qr_bucket(const IdArgs& a, int64_t n, int bucket, hipStream_t st);
 
 hipError_t launch_select(const IdArgs& a, hipStream_t st) {
   if (a.n_ids <= 0) return hipSuccess;
@@ -458,32 +537,54 @@ hipError_t launch_id_batch(const IdArgs& a, hipStream_t st) {
 
 hipError_t launch_qr(const IdArgs& a, hipStream_t st) {
   if (a.n_ids <= 0) return hipSuccess;
-  if (!a.order) return launch_qr_waves(a, a.n_ids, id_batch_waves(a.s_max), st);
-  // one launch per bucket of IDs that need the same number of wavefronts
+  if (!a.order) return launch_qr_bucket(a, a.n_ids, qr_bucket(a.c_max, a.s_max), st);
+  // one launch per bucket of IDs that need the same kernel variant
   IdArgs b = a;
-  for (int wv = 1; wv <= kMaxSamples / kRPW; ++wv) {
-    const int64_t cnt = a.bucket_off[wv] - a.bucket_off[wv - 1];
+  for (int bk = 0; bk < kQrBuckets; ++bk) {
+    const int64_t cnt = a.bucket_off[bk + 1] - a.bucket_off[bk];
     if (cnt <= 0) continue;
-    b.order = a.order + a.bucket_off[wv - 1];
-    hipError_t e = launch_qr_waves(b, cnt, wv, st);
+    b.order = a.order + a.bucket_off[bk];
+    hipError_t e = launch_qr_bucket(b, cnt, bk, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t launch_qr_waves(const IdArgs& a, int64_t n, int waves, hipStream_t st) {
-  const dim3 grid((unsigned)n);
-  switch (waves) {
-    case 1: hipLaunchKernelGGL(id_kernel<1>, grid, dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL(id_kernel<2>, grid, dim3(128), 0, st, a); break;
-    case 3: hipLaunchKernelGGL(id_kernel<3>, grid, dim3(192), 0, st, a); break;
-    case 4: hipLaunchKernelGGL(id_kernel<4>, grid, dim3(256), 0, st, a); break;
-    case 5: hipLaunchKernelGGL(id_kernel<5>, grid, dim3(320), 0, st, a); break;
-    case 6: hipLaunchKernelGGL(id_kernel<6>, grid, dim3(384), 0, st, a); break;
-    case 7: hipLaunchKernelGGL(id_kernel<7>, grid, dim3(448), 0, st, a); break;
-    default: hipLaunchKernelGGL(id_kernel<8>, grid, dim3(512), 0, st, a); break;
-  }
+template <int W, int CPL, int R>
+hipError_t launch_one(const IdArgs& a, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((id_kernel<W, CPL, R>), dim3((unsigned)n), dim3(64 * W), 0, st, a);
   return hipGetLastError();
+}
+
+hipError_t launch_qr_bucket(const IdArgs& a, int64_t n, int bucket, hipStream_t st) {
+  switch (bucket) {
+    // up to 64 candidates: 16 rows per wavefront
+    case 0: return launch_one<1, 1, 16>(a, n, st);
+    case 1: return launch_one<2, 1, 16>(a, n, st);
+    case 2: return launch_one<3, 1, 16>(a, n, st);
+    case 3: return launch_one<4, 1, 16>(a, n, st);
+    case 4: return launch_one<5, 1, 16>(a, n, st);
+    case 5: return launch_one<6, 1, 16>(a, n, st);
+    case 6: return launch_one<7, 1, 16>(a, n, st);
+    case 7: return launch_one<8, 1, 16>(a, n, st);
+    // 65..128 candidates: two per lane, 8 rows per wavefront
+    case 8: return launch_one<1, 2, 8>(a, n, st);
+    case 9: return launch_one<2, 2, 8>(a, n, st);
+    case 10: return launch_one<3, 2, 8>(a, n, st);
+    case 11: return launch_one<4, 2, 8>(a, n, st);
+    case 12: return launch_one<5, 2, 8>(a, n, st);
+    case 13: return launch_one<6, 2, 8>(a, n, st);
+    case 14: return launch_one<7, 2, 8>(a, n, st);
+    case 15: return launch_one<8, 2, 8>(a, n, st);
+    case 16: return launch_one<9, 2, 8>(a, n, st);
+    case 17: return launch_one<10, 2, 8>(a, n, st);
+    case 18: return launch_one<11, 2, 8>(a, n, st);
+    case 19: return launch_one<12, 2, 8>(a, n, st);
+    case 20: return launch_one<13, 2, 8>(a, n, st);
+    case 21: return launch_one<14, 2, 8>(a, n, st);
+    case 22: return launch_one<15, 2, 8>(a, n, st);
+    default: return launch_one<16, 2, 8>(a, n, st);
+  }
 }
 
 }  // namespace idbf

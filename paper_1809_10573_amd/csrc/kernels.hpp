@@ -8,6 +8,20 @@ namespace idbf {
 // Error bits a kernel may raise in its status word.
 enum : int32_t { kErrRank = 1, kErrSize = 2 };
 
+// QR kernel variant of an ID with c candidates and s samples: buckets 0..7
+// take up to 64 candidates with ceil(s / 16) wavefronts, buckets 8..23 up to
+// 128 candidates (two per lane) with ceil(s / 8) wavefronts.
+constexpr int kQrBuckets = 24;
+__host__ __device__ inline int qr_bucket(int c, int s) {
+  s = s < 1 ? 1 : s;
+  if (c <= kWave) {
+    const int w = (s + 15) / 16;
+    return (w > 8 ? 8 : w) - 1;
+  }
+  const int w = (s + 7) / 8;
+  return 8 + (w > 16 ? 16 : w) - 1;
+}
+
 // ------------------------------------------------------------- batched ID
 struct IdArgs {
   PhaseDev ph;
@@ -27,30 +41,30 @@ struct IdArgs {
   int kmax;
   int oversample;
   int s_max;                  // largest sample count of the batch (sizes the launch)
+  int c_max;                  // largest candidate count of the batch (sizes the launch)
   int32_t* samp_pos;          // kMaxSamples sample positions per ID (scratch)
-  const int32_t* order;       // QR launch: IDs grouped by wavefronts needed, or null
-  int64_t bucket_off[9];      // host: order[bucket_off[w-1] .. bucket_off[w]) need w waves
+  const int32_t* order;       // QR launch: IDs grouped by kernel variant (qr_bucket), or null
+  int64_t bucket_off[kQrBuckets + 1];  // host: order[bucket_off[b] .. bucket_off[b + 1]) are bucket b
   int32_t* rank;
-  uint64_t* mask;
+  uint64_t* mask;        // two words per ID: bit l of (mask[2q], mask[2q+1]) = candidate l is a skeleton
   int32_t* skel_out;     // kMaxCand entries per ID
   double2* T128;
   float2* T64;           // may be null
   const int64_t* T_off;  // null: ID q writes at q * kSlot
   int32_t* status;
 };
-// Selection (one wavefront per ID), then sampling + QR + solve with
-// ceil(s_max / 16) wavefronts per ID; launch_id_batch runs both.
+// Selection (one wavefront per ID), then sampling + QR + solve (one
+// workgroup per ID, variant by qr_bucket); launch_id_batch runs both.
 hipError_t launch_select(const IdArgs& a, hipStream_t st);
 hipError_t launch_qr(const IdArgs& a, hipStream_t st);
 hipError_t launch_id_batch(const IdArgs& a, hipStream_t st);
-int id_batch_waves(int s_max);
-constexpr int kRowsPerWaveQR = 16;  // sampled rows per wavefront in the QR kernel
-// IDs grouped by ceil(samples / 16): counts[0..7] += bucket sizes (pass 1),
+// IDs grouped by qr_bucket: counts[0..kQrBuckets) += bucket sizes (pass 1),
 // then order[] filled from per-bucket cursors (pass 2, cursors pre-set to the
 // bucket offsets).
-hipError_t launch_bucket_count(const int32_t* samples, int64_t n, unsigned long long* counts, hipStream_t st);
-hipError_t launch_bucket_fill(const int32_t* samples, int64_t n, unsigned long long* cursors, int32_t* order,
-                              hipStream_t st);
+hipError_t launch_bucket_count(const int32_t* samples, const int32_t* cand_len, int64_t n,
+                               unsigned long long* counts, hipStream_t st);
+hipError_t launch_bucket_fill(const int32_t* samples, const int32_t* cand_len, int64_t n,
+                              unsigned long long* cursors, int32_t* order, hipStream_t st);
 
 // Work of a finished level: out[0] += sum 16 sum_{j<k}(s-j)(c-j) + 4 k^2 (c-k)
 // (FP64 flops), out[1] += sum k (c - k) (T entries), out[2] += sum s c (samples).
@@ -125,10 +139,11 @@ hipError_t launch_sample_dense(const PhaseDev& ph, const double* X, const double
                                double2* out, hipStream_t st);
 
 // ------------------------------------------------------------- apply
-// Everything one apply stage needs of an ID, in one 32-byte record.
+// Everything one apply stage needs of an ID, in one 40-byte record.
 struct ApplyMeta {
   int64_t t_off;     // first T entry (even)
-  uint64_t mask;     // bit l: candidate l is a skeleton
+  uint64_t mask;     // bit l: candidate l is a skeleton (l < 64)
+  uint64_t mask_hi;  // bit l - 64: candidate l is a skeleton (64 <= l < 128)
   int32_t cand_beg;  // input (V) / output (U) segment start
   int32_t skel_off;  // output (V) / input (U) segment start
   int32_t c;         // candidates
@@ -153,6 +168,7 @@ struct StageArgs {
   const void* in;
   void* out;
   int pmax;                // largest factor block (entries) of the stage: LDS per ID
+  int gemm_rows;           // matrix-core stage: rows of A staged per unit (multiple of 32)
   // middle stage
   bool dense;              // H = 0: one N x N block
   int64_t rlen_host;       // its row count
@@ -166,7 +182,8 @@ hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st);
 hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st);
 hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st);
 // matrix-core stage kernels (complex64 data): mode 0 V, 1 S, 2 U; kmax_unit
-// bounds the K of every unit of the stage (sizes the LDS of A)
-hipError_t launch_apply_gemm(const StageArgs& a, int mode, int kmax_unit, bool bf16, hipStream_t st);
+// and mmax_unit bound the K and M of every unit of the stage (size the LDS of A)
+hipError_t launch_apply_gemm(const StageArgs& a, int mode, int kmax_unit, int mmax_unit, bool bf16,
+                             hipStream_t st);
 
 }  // namespace idbf

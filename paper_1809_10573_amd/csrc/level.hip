@@ -56,7 +56,7 @@ __global__ void desc_kernel(DescArgs A) {
   A.cand_len[q] = cl;
   A.allow_beg[q] = ab;
   A.allow_len[q] = al;
-  const int64_t s = min((int64_t)A.oversample * cl, (int64_t)al);
+  const int64_t s = min(min((int64_t)A.oversample * cl, (int64_t)al), (int64_t)kMaxSamples);
   int64_t kcap = min((int64_t)cl, s);
   if (A.kmax > 0) kcap = min(kcap, (int64_t)A.kmax);
   kcap = min(kcap, (int64_t)kMaxRank);
@@ -212,38 +212,35 @@ __global__ __launch_bounds__(256) void id_work_kernel(const int32_t* rank, const
   if (threadIdx.x < 3) atomicAdd(out + threadIdx.x, s_w[threadIdx.x][0]);
 }
 
-__device__ __forceinline__ int waves_for(int32_t s) {
-  return max(1, min(8, (s + kRowsPerWaveQR - 1) / kRowsPerWaveQR));
-}
-
-__global__ __launch_bounds__(256) void bucket_count_kernel(const int32_t* samples, int64_t n,
-                                                           unsigned long long* counts) {
-  __shared__ unsigned int s_c[8];
-  if (threadIdx.x < 8) s_c[threadIdx.x] = 0;
+__global__ __launch_bounds__(256) void bucket_count_kernel(const int32_t* samples, const int32_t* cand_len,
+                                                           int64_t n, unsigned long long* counts) {
+  __shared__ unsigned int s_c[kQrBuckets];
+  if (threadIdx.x < kQrBuckets) s_c[threadIdx.x] = 0;
   __syncthreads();
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&s_c[waves_for(samples[q]) - 1], 1u);
+    atomicAdd(&s_c[qr_bucket(cand_len[q], samples[q])], 1u);
   __syncthreads();
-  if (threadIdx.x < 8 && s_c[threadIdx.x]) atomicAdd(counts + threadIdx.x, (unsigned long long)s_c[threadIdx.x]);
+  if (threadIdx.x < kQrBuckets && s_c[threadIdx.x])
+    atomicAdd(counts + threadIdx.x, (unsigned long long)s_c[threadIdx.x]);
 }
 
 // Slots are reserved per workgroup (one global atomic per bucket and
 // workgroup), then handed out inside the workgroup with LDS atomics.
-__global__ __launch_bounds__(256) void bucket_fill_kernel(const int32_t* samples, int64_t n,
-                                                          unsigned long long* cursors, int32_t* order) {
-  __shared__ unsigned int s_cnt[8];
-  __shared__ unsigned long long s_base[8];
-  if (threadIdx.x < 8) s_cnt[threadIdx.x] = 0;
+__global__ __launch_bounds__(256) void bucket_fill_kernel(const int32_t* samples, const int32_t* cand_len,
+                                                          int64_t n, unsigned long long* cursors, int32_t* order) {
+  __shared__ unsigned int s_cnt[kQrBuckets];
+  __shared__ unsigned long long s_base[kQrBuckets];
+  if (threadIdx.x < kQrBuckets) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int b = 0;
   unsigned int local = 0;
   if (q < n) {
-    b = waves_for(samples[q]) - 1;
+    b = qr_bucket(cand_len[q], samples[q]);
     local = atomicAdd(&s_cnt[b], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < 8 && s_cnt[threadIdx.x])
+  if (threadIdx.x < kQrBuckets && s_cnt[threadIdx.x])
     s_base[threadIdx.x] = atomicAdd(cursors + threadIdx.x, (unsigned long long)s_cnt[threadIdx.x]);
   __syncthreads();
   if (q < n) order[s_base[b] + local] = (int32_t)q;
@@ -254,7 +251,7 @@ __global__ void pack_meta_kernel(const int64_t* t_off, const uint64_t* mask, con
                                  ApplyMeta* out) {
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (q >= n) return;
-  out[q] = ApplyMeta{t_off[q], mask[q], cand_beg[q], skel_off[q], cand_len[q], rank[q]};
+  out[q] = ApplyMeta{t_off[q], mask[2 * q], mask[2 * q + 1], cand_beg[q], skel_off[q], cand_len[q], rank[q]};
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -300,17 +297,19 @@ hipError_t launch_id_work(const int32_t* rank, const int32_t* cand_len, const in
   return hipGetLastError();
 }
 
-hipError_t launch_bucket_count(const int32_t* samples, int64_t n, unsigned long long* counts, hipStream_t st) {
+hipError_t launch_bucket_count(const int32_t* samples, const int32_t* cand_len, int64_t n,
+                               unsigned long long* counts, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(bucket_count_kernel, dim3(std::min<unsigned>(blocks_for(n, 256), 1024u)), dim3(256), 0, st,
-                     samples, n, counts);
+                     samples, cand_len, n, counts);
   return hipGetLastError();
 }
 
-hipError_t launch_bucket_fill(const int32_t* samples, int64_t n, unsigned long long* cursors, int32_t* order,
-                              hipStream_t st) {
+hipError_t launch_bucket_fill(const int32_t* samples, const int32_t* cand_len, int64_t n,
+                              unsigned long long* cursors, int32_t* order, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bucket_fill_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, samples, n, cursors, order);
+  hipLaunchKernelGGL(bucket_fill_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, samples, cand_len, n, cursors,
+                     order);
   return hipGetLastError();
 }
 

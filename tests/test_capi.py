@@ -46,7 +46,7 @@ def test_argument_errors_without_gpu():
     assert b"power of two" in lib.idbf_last_error()
     assert h.value is None
     assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1e-6, 3, None, C.byref(h)) == B.EINVAL
-    assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1e-6, 128, None, C.byref(h)) == B.EINVAL
+    assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1e-6, 256, None, C.byref(h)) == B.EINVAL
     assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1.5, 8, None, C.byref(h)) == B.EINVAL
     assert lib.idbf_construct(C.byref(ph), None, fake, 1024, 1e-6, 8, None, C.byref(h)) == B.EINVAL
     bad = B.Phase_t(7, 0, 0.0, 0.0, 0.0, 1.0)

@@ -71,23 +71,30 @@ def _run_ids(ph, X, O, side, problems, tol, kmax, oversample):
                       oversample, device=DEV)
 
 
+NARROW_SHAPES = [(8, 8, 5, 5), (16, 16, 16, 16), (16, 16, 700, 2048), (24, 32, 30, 40),
+                 (33, 40, 700, 800), (52, 64, 60, 64), (64, 128, 64, 100), (5, 5, 1, 1),
+                 (40, 48, 128, 300), (17, 20, 1500, 1600), (1, 1, 50, 60), (12, 12, 12, 12),
+                 (28, 28, 2000, 2048), (60, 64, 90, 90)]
+# more than 64 candidates (two per lane, 8 rows per wavefront); a batch holding
+# any of them runs every ID on that kernel variant
+WIDE_SHAPES = [(96, 120, 150, 400), (70, 80, 60, 64), (128, 128, 200, 256), (65, 300, 90, 120),
+               (100, 110, 1000, 1100), (16, 16, 700, 2048), (40, 48, 128, 300), (3, 3, 8, 8)]
+
+
 @pytest.mark.parametrize("side", [B.SIDE_U, B.SIDE_V])
 @pytest.mark.parametrize("oversample,kmax", [(1, 0), (2, 0), (2, 7)])
-def test_id_batch_matches_oracle(side, oversample, kmax):
+@pytest.mark.parametrize("wide", [False, True])
+def test_id_batch_matches_oracle(side, oversample, kmax, wide):
     N = 4096
     ph = I.fio_phase(1.0, 1.0)
     X, O = I.uniform_grid(N)
-    rng = np.random.default_rng(10 * side + oversample + kmax)
-    shapes = [(8, 8, 5, 5), (16, 16, 16, 16), (16, 16, 700, 2048), (24, 32, 30, 40),
-              (33, 40, 700, 800), (52, 64, 60, 64), (64, 128, 64, 100), (5, 5, 1, 1),
-              (40, 48, 128, 300), (17, 20, 1500, 1600), (1, 1, 50, 60), (12, 12, 12, 12),
-              (28, 28, 2000, 2048), (60, 64, 90, 90)]
-    problems = [_id_problem(rng, N, *sh) for sh in shapes]
+    rng = np.random.default_rng(10 * side + oversample + kmax + 100 * wide)
+    problems = [_id_problem(rng, N, *sh) for sh in (WIDE_SHAPES if wide else NARROW_SHAPES)]
     tol = 1e-6
     rank, mask, skel, T = _run_ids(ph, X, O, side, problems, tol, kmax, oversample)
     allow_coord = X if side == B.SIDE_V else O
     for q, (cand, allowed) in enumerate(problems):
-        s = min(oversample * len(cand), len(allowed))
+        s = oracle.sample_count(len(cand), len(allowed), oversample)
         samp = allowed[oracle.mock_chebyshev(allow_coord[allowed], s)]
         Bm = (oracle.entries(ph, X, O, samp, cand) if side == B.SIDE_V
               else oracle.entries(ph, X, O, cand, samp).T)
@@ -95,7 +102,7 @@ def test_id_batch_matches_oracle(side, oversample, kmax):
         k = cid.rank
         assert rank[q] == k, (q, rank[q], k)
         assert np.array_equal(skel[q, :k], cand[cid.skel]), q
-        bits = np.array([(int(mask[q]) >> l) & 1 for l in range(len(cand))], bool)
+        bits = B.mask_bits(mask[q], len(cand))
         assert np.array_equal(np.nonzero(bits)[0], cid.skel)
         r = len(cand) - k
         flat = T[q, :k * r]
@@ -106,12 +113,12 @@ def test_id_batch_matches_oracle(side, oversample, kmax):
 
 
 def test_id_batch_rank_overflow_is_reported():
-    # 64 candidates spread over the whole grid against 64 spread allowed points:
-    # full rank, above the 32 the kernel holds -> IDBF_ERANK, not a wrong answer
+    # 128 candidates spread over the whole grid against 128 spread allowed
+    # points: full rank, above the 64 an ID may have -> IDBF_ERANK, not a wrong answer
     N = 4096
     X, O = I.uniform_grid(N)
     rng = np.random.default_rng(3)
-    prob = (np.sort(rng.choice(N, 64, replace=False)), np.sort(rng.choice(N, 64, replace=False)))
+    prob = (np.sort(rng.choice(N, 128, replace=False)), np.sort(rng.choice(N, 128, replace=False)))
     with pytest.raises(B.IdbfError) as e:
         _run_ids(I.dft_phase(), X, O, B.SIDE_V, [prob], 1e-6, 0, 1)
     assert e.value.status == B.ERANK
@@ -123,8 +130,8 @@ def test_id_batch_rejects_oversized():
     N = 1024
     X, O = I.uniform_grid(N)
     with pytest.raises(B.IdbfError) as e:
-        B.id_batch(I.dft_phase(), X, O, B.SIDE_V, np.arange(65), [0], [65], np.arange(100), [0],
-                   [100], 1e-6, device=DEV)
+        B.id_batch(I.dft_phase(), X, O, B.SIDE_V, np.arange(129), [0], [129], np.arange(200), [0],
+                   [200], 1e-6, device=DEV)
     assert e.value.status == B.EINVAL
 
 
@@ -233,6 +240,32 @@ def test_many_rhs_matrix_core_paths(N, leaf, kind, tol, os_, nrhs):
         assert oracle.relative_error(Y, Y_or) < bound
         col = np.linalg.norm(Y - Y_or, axis=0) / np.linalg.norm(Y_or, axis=0)
         assert col.max() < 10 * bound       # every column, tails included
+
+
+def test_wide_ranks_construct_and_every_apply_path():
+    """c(x) = (2 + sin 8 pi x)/8 at N = 4096 (leaf 16, tol 1e-6, t = 2): ranks
+    reach the 40s and candidate sets exceed 64, so the two-candidates-per-lane
+    QR variant, the chunked back-substitution and the 128-bit skeleton masks
+    all run; every apply path is checked against the oracle."""
+    N, leaf, tol = 4096, 16, 1e-6
+    ph = I.fio_phase(1.0, 4.0)
+    X, O = I.uniform_grid(N)
+    F = oracle.build(ph, X, O, leaf, tol, oversample=2)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=2, device=DEV)
+    info = fac.info()
+    assert info["cand_max"] > 64 and info["rank_max"] > 32
+    assert _compare_construction(F, fac, ph, X, O) == 0
+    G = I.gaussian_vectors(N, 65, seed=11)
+    Y_or = oracle.apply(F, G)
+    x = torch.as_tensor(G, device=DEV)
+    assert oracle.relative_error(fac.apply(x[:, 0].contiguous()).cpu().numpy(), Y_or[:, 0]) < 1e-12
+    assert oracle.relative_error(fac.apply(x).cpu().numpy(), Y_or) < 1e-12
+    x64 = x.to(torch.complex64)
+    assert oracle.relative_error(fac.apply(x64[:, 0].contiguous()).cpu().numpy(), Y_or[:, 0]) < 2e-6
+    assert oracle.relative_error(fac.apply(x64).cpu().numpy(), Y_or) < 2e-6
+    assert oracle.relative_error(fac.apply(x64, dtype=B.C64_BF16X3).cpu().numpy(), Y_or) < 2e-4
+    y_ex = oracle.dense_matvec(ph, X, O, G[:, 0])
+    assert oracle.relative_error(fac.apply(x[:, 0].contiguous()).cpu().numpy(), y_ex) < 100 * tol
 
 
 def test_construct_errors():
