@@ -80,6 +80,64 @@ print(json.dumps(dict(N=N, nnz=nnz, build_s=tb, apply_s=ta, gbs=(nnz * 16 + 2 * 
                        f"{r['build_s']:.1f} s (N=2^20 would take hours)")}
 
 
+def _batched(B, torch, dev, stream) -> dict:
+    """The many-instance workload (64 instances, N = 2^12..2^18, DFT and FIO
+    family members, nrhs in {1, 16, 64}, complex64 apply): one-by-one versus
+    idbf_construct_batched / idbf_apply_batched, measured once."""
+    work = I.batched_workload()
+    Xs, Os = [], []
+    for w in work:
+        X, O = I.uniform_grid(w["N"])
+        Xs.append(torch.as_tensor(X, device=dev))
+        Os.append(torch.as_tensor(O, device=dev))
+    gen = torch.Generator(device=dev).manual_seed(6)
+    xs = [torch.randn(w["N"], w["nrhs"], dtype=torch.complex64, device=dev, generator=gen).squeeze(1)
+          * np.sqrt(2.0) for w in work]
+    xs = [x.contiguous() for x in xs]
+    ys = [torch.empty_like(x) for x in xs]
+    args = ([w["phase"] for w in work], Xs, Os, [w["tol"] for w in work], [w["leaf"] for w in work])
+
+    def timed_apply(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()  # warm-up
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    facs = [B.construct(w["phase"], X, O, w["tol"], w["leaf"], oversample=2, device=dev, stream=stream)
+            for w, X, O in zip(work, Xs, Os)]
+    seq_con = (time.perf_counter() - t0) * 1e3
+    for f, x in zip(facs, xs):
+        f.reserve(1 if x.dim() == 1 else x.shape[1], B.C64)
+    seq_app = timed_apply(lambda: [f.apply(x, y, stream=stream) for f, x, y in zip(facs, xs, ys)])
+    ref = [y.clone() for y in ys[:4]]
+    ranks = [f.info()["rank_max"] for f in facs]
+    for f in facs:
+        f.close()
+    del facs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    facs = B.construct_batched(*args, oversample=2, device=dev, stream=stream)
+    bat_con = (time.perf_counter() - t0) * 1e3
+    for f, x in zip(facs, xs):
+        f.reserve(1 if x.dim() == 1 else x.shape[1], B.C64)
+    bat_app = timed_apply(lambda: B.apply_batched(facs, xs, ys, stream=stream))
+    same = all(torch.equal(a, b) for a, b in zip(ref, ys[:4]))
+    for f in facs:
+        f.close()
+    return {"instances": len(work), "points": int(sum(w["N"] for w in work)),
+            "rank_max_range": [int(min(ranks)), int(max(ranks))],
+            "construct_ms_one_by_one": seq_con, "construct_ms_batched": bat_con,
+            "apply_ms_one_by_one": seq_app, "apply_ms_batched": bat_app,
+            "construct_speedup": seq_con / bat_con, "apply_speedup": seq_app / bat_app,
+            "outputs_identical": bool(same)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +145,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nrhs", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the many-instance measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU layout is described "
@@ -232,6 +291,10 @@ def main() -> int:
                               "unit": "GB/s", "frac": tb / tm / 1e6 / HBM_PEAK_GBS,
                               "kernels": {k: v["ms"] for k, v in p1.items()}}
     del a1
+    del XM, YM
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = _batched(B, torch, dev, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline()
     print(json.dumps(out), flush=True)

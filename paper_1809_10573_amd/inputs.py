@@ -76,6 +76,25 @@ def family_draws(count: int, seed: int) -> list[tuple[float, int]]:
     return [(float(ai), int(mi)) for ai, mi in zip(a, m)]
 
 
+def batched_workload(count: int = 64, seed: int = 3, emin: int = 12, emax: int = 18,
+                     leaf: int = 16, tol: float = 1e-6) -> list[dict]:
+    """Many independent IDBF instances of uneven size and rank: N = 2^e with
+    e ~ U{emin..emax}; the first half DFT kernels, the second half members of
+    the FIO family c(x) = (2 + a sin 2 pi m x)/8 with a ~ U[0, 1), m ~ U{1..4};
+    nrhs ~ U{1, 16, 64} right-hand sides each."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        e = int(rng.integers(emin, emax + 1))
+        a = float(rng.random())
+        m = int(rng.integers(1, 5))
+        nrhs = int(rng.choice([1, 16, 64]))
+        phase = dft_phase() if i < count // 2 else fio_phase(a, float(m))
+        out.append(dict(phase=phase, N=1 << e, leaf=leaf, tol=tol, nrhs=nrhs, a=a, m=m,
+                        kind="dft" if i < count // 2 else "fio"))
+    return out
+
+
 # The measured configurations (sizes, tolerances, leaf sizes).
 CONFIGS = {
     "dft_n1024": dict(phase=dft_phase(), N=1024, leaf=8, tol=1e-10, seed=1),

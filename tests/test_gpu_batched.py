@@ -93,3 +93,33 @@ def test_batched_errors_name_the_instance():
     x = torch.zeros(256, dtype=torch.complex128, device=DEV)
     with pytest.raises(B.IdbfError):
         B.apply_batched([f, f], [x, x])        # handles must be distinct
+
+
+def test_uneven_family_batch():
+    """The many-instance workload at reduced sizes (12 instances, N = 2^12..2^14,
+    DFT and FIO members c(x) = (2 + a sin 2 pi m x)/8 with uneven ranks): the
+    batched construction equals one-by-one construction, the batched apply
+    equals one-by-one applies, and every instance approximates its kernel
+    (exact rows) to the method's tolerance."""
+    work = I.batched_workload(count=12, seed=5, emin=12, emax=14)
+    grids = [I.uniform_grid(w["N"]) for w in work]
+    facs = B.construct_batched([w["phase"] for w in work], [g[0] for g in grids], [g[1] for g in grids],
+                               [w["tol"] for w in work], [w["leaf"] for w in work], oversample=2, device=DEV)
+    ranks = [f.info()["rank_max"] for f in facs]
+    assert max(ranks) > min(ranks)                       # uneven ranks across instances
+    for w, (X, O), fb in zip(work, grids, facs):
+        _same_factors(fb, B.construct(w["phase"], X, O, w["tol"], w["leaf"], oversample=2, device=DEV))
+    xs = [torch.as_tensor(I.gaussian_vectors(w["N"], w["nrhs"] if w["nrhs"] > 1 else None, seed=i),
+                          device=DEV) for i, w in enumerate(work)]
+    ys = B.apply_batched(facs, xs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for w, (X, O), f, x, y in zip(work, grids, facs, xs, ys):
+        assert torch.equal(y, f.apply(x))
+        rows = np.sort(rng.choice(w["N"], 32, replace=False))
+        g = x.cpu().numpy()
+        g0 = g if g.ndim == 1 else g[:, 0]
+        y0 = y.cpu().numpy()
+        y0 = y0 if y0.ndim == 1 else y0[:, 0]
+        ex = oracle.matvec_rows(w["phase"], X, O, g0, rows)
+        assert oracle.relative_error(y0[rows], ex) < 100 * w["tol"], (w["kind"], w["N"], w["a"], w["m"])
