@@ -69,14 +69,24 @@ enum { IDBF_FLAG_PROFILE = 1 }; /* record per-launch device times (idbf_profile_
 
 typedef struct idbf_opts {
   int32_t kmax;        /* rank parameter k of the (eps, k)-ID (Section 2.1); 0: k = min(s, c) */
-  int32_t oversample;  /* oversampling parameter t >= 1: s = min(t |cand|, |allowed|) samples */
+  int32_t oversample;  /* oversampling parameter t >= 1: s = min(t |cand|, |allowed|, 128) samples */
   int32_t flags;       /* IDBF_FLAG_* */
   int32_t reserved1;
   uint64_t mem_cap_bytes; /* cap on device memory a handle may allocate; 0: none */
   void* stream;        /* hipStream_t used by idbf_construct */
+  /* Learned rank proposal (not in the paper), or NULL: every ID first samples
+   * s' = min(s, t (ceil(k^) + proposal_margin)) points, k^ the network's rank
+   * estimate; a randomized residual test on 8 fresh allowed points accepts it
+   * (||A(r,red) - A(r,skel) T||_F <= 10 tol ||A(r,cand)||_F) or the plain ID
+   * of s samples replaces it.  seed drives the test points (SplitMix64). */
+  struct idbf_mlp_s* proposer;
+  int32_t proposal_margin;
+  int32_t reserved2;
+  uint64_t seed;
 } idbf_opts;
 
 typedef struct idbf_handle_s* idbf_handle;
+typedef struct idbf_mlp_s* idbf_mlp;
 
 /* Fill *o with the defaults: kmax 0, oversample 1 (the paper's t = 1),
  * no flags, no memory cap, null stream.  NULL-safe. */
@@ -174,6 +184,8 @@ typedef struct idbf_info {
   double construct_ms;    /* host wall time of idbf_construct */
   double id_flops;        /* FP64 flops of the IDs: sum 16 sum_{j<k} (s-j)(c-j) + 4 k^2 (c-k) */
   int64_t sampled_entries;/* kernel entries sampled by the IDs: sum s c */
+  int64_t proposed;       /* IDs first computed from a proposal (0 without a proposer) */
+  int64_t rejected;       /* proposals the residual test rejected (recomputed plainly) */
 } idbf_info;
 
 /* Summary of a handle (host *info). */
@@ -265,6 +277,39 @@ idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double
                           const int32_t* allow_len, double tol, int32_t kmax,
                           int32_t oversample, int32_t* rank, uint64_t* mask, int32_t* skel,
                           double* T, void* stream);
+
+/*
+ * Rank-proposal network (not in the paper; the learned-proposal extension of
+ * the construction).  A perceptron with IDBF_MLP_INPUTS inputs, two hidden
+ * ReLU layers of `hidden` units (16, 32, 64 or 128) and one output, FP32 on
+ * the GPU.  Parameters are one flat vector: W1 (inputs x hidden, row-major),
+ * b1, W2 (hidden x hidden), b2, W3 (hidden), b3.  Inputs of an ID (level t,
+ * side 0 = U / 1 = V; x_c, xi_c the centres of its row and column nodes
+ * scaled to [0, 1)): t/8, side, x_c, xi_c, a, m/4, 1 for the FIO kernel,
+ * a m |cos 2 pi m x_c| / 4 (a = m = 0 and 0 for the DFT); the target is
+ * rank / 16.
+ *   idbf_mlp_create: params (host, idbf_mlp_param_count floats) are copied.
+ *   idbf_mlp_forward: y[i] = f(X[i * 8 ..]) (device arrays, asynchronous).
+ *   idbf_mlp_loss_grad: grad (device, param-count floats) of
+ *       mean((f(X) - y)^2) / 2 over the n rows; *loss (host) = that mean.
+ *   idbf_mlp_train: `epochs` passes of Adam (lr, betas 0.9 / 0.999) over
+ *       minibatches of `batch` rows in a SplitMix64 order; loss_per_epoch
+ *       (host, nullable) receives each epoch's mean loss.  Synchronizes.
+ *   idbf_mlp_params: copy the parameters to host.
+ *   idbf_rank_samples: training data from a built handle: features[n_ids * 8]
+ *       and targets[n_ids] (device floats) of one level's IDs.
+ */
+#define IDBF_MLP_INPUTS 8
+int32_t idbf_mlp_param_count(int32_t hidden);
+idbf_status idbf_mlp_create(int32_t hidden, const float* params, idbf_mlp* out);
+idbf_status idbf_mlp_destroy(idbf_mlp m);
+idbf_status idbf_mlp_params(idbf_mlp m, float* params);
+idbf_status idbf_mlp_forward(idbf_mlp m, const float* X, int64_t n, float* y, void* stream);
+idbf_status idbf_mlp_loss_grad(idbf_mlp m, const float* X, const float* y, int64_t n, float* grad, float* loss,
+                               void* stream);
+idbf_status idbf_mlp_train(idbf_mlp m, const float* X, const float* y, int64_t n, int32_t epochs, int32_t batch,
+                           float lr, uint64_t seed, float* loss_per_epoch, void* stream);
+idbf_status idbf_rank_samples(idbf_handle h, int32_t side, int32_t level, float* features, float* targets);
 
 #ifdef __cplusplus
 }

@@ -28,8 +28,11 @@ EXPORTED = [
     "idbf_opts_default", "idbf_construct", "idbf_apply", "idbf_destroy", "idbf_last_error",
     "idbf_get_info", "idbf_batch_sizes", "idbf_batch_export", "idbf_middle_sizes",
     "idbf_middle_export", "idbf_sample", "idbf_id_batch", "idbf_profile_read", "idbf_reserve",
-    "idbf_construct_batched", "idbf_apply_batched",
+    "idbf_construct_batched", "idbf_apply_batched", "idbf_mlp_param_count", "idbf_mlp_create",
+    "idbf_mlp_destroy", "idbf_mlp_params", "idbf_mlp_forward", "idbf_mlp_loss_grad", "idbf_mlp_train",
+    "idbf_rank_samples",
 ]
+MLP_INPUTS = 8
 FLAG_PROFILE = 1
 MAX_CAND, MAX_RANK, MAX_SAMPLES, SLOT = 128, 64, 128, 4096  # limits of include/idbf.h
 
@@ -54,7 +57,9 @@ class Phase_t(C.Structure):
 
 class Opts_t(C.Structure):
     _fields_ = [("kmax", C.c_int32), ("oversample", C.c_int32), ("flags", C.c_int32),
-                ("reserved1", C.c_int32), ("mem_cap_bytes", C.c_uint64), ("stream", C.c_void_p)]
+                ("reserved1", C.c_int32), ("mem_cap_bytes", C.c_uint64), ("stream", C.c_void_p),
+                ("proposer", C.c_void_p), ("proposal_margin", C.c_int32), ("reserved2", C.c_int32),
+                ("seed", C.c_uint64)]
 
 
 class Info_t(C.Structure):
@@ -63,7 +68,8 @@ class Info_t(C.Structure):
                 ("nnz_T", C.c_int64), ("nnz_S", C.c_int64), ("n_skel", C.c_int64),
                 ("rank_min", C.c_int32), ("rank_max", C.c_int32), ("cand_max", C.c_int32),
                 ("samples_max", C.c_int32), ("device_bytes", C.c_int64), ("construct_ms", C.c_double),
-                ("id_flops", C.c_double), ("sampled_entries", C.c_int64)]
+                ("id_flops", C.c_double), ("sampled_entries", C.c_int64), ("proposed", C.c_int64),
+                ("rejected", C.c_int64)]
 
 
 class KernelStat_t(C.Structure):
@@ -104,6 +110,15 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_construct_batched.argtypes = [I32, P(Phase_t), P(VP), P(VP), P(I64), P(D), P(I32), P(Opts_t),
                                            P(VP)]
     lib.idbf_apply_batched.argtypes = [I32, P(VP), P(VP), P(VP), P(I64), I32, VP]
+    F32 = C.c_float
+    lib.idbf_mlp_param_count.argtypes = [I32]
+    lib.idbf_mlp_create.argtypes = [I32, VP, P(VP)]
+    lib.idbf_mlp_destroy.argtypes = [VP]
+    lib.idbf_mlp_params.argtypes = [VP, VP]
+    lib.idbf_mlp_forward.argtypes = [VP, VP, I64, VP, VP]
+    lib.idbf_mlp_loss_grad.argtypes = [VP, VP, VP, I64, VP, P(F32), VP]
+    lib.idbf_mlp_train.argtypes = [VP, VP, VP, I64, I32, I32, F32, C.c_uint64, VP, VP]
+    lib.idbf_rank_samples.argtypes = [VP, I32, I32, VP, VP]
     for name in EXPORTED:
         if name not in ("idbf_opts_default", "idbf_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -233,7 +248,7 @@ class Factorization:
 
 def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample: int = 1,
               mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
-              stream=None) -> Factorization:
+              stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0) -> Factorization:
     """idbf_construct on device copies of X and Omega (float64, ascending)."""
     lib = load()
     Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
@@ -244,6 +259,8 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
     opts.kmax, opts.oversample, opts.mem_cap_bytes = kmax, oversample, mem_cap_bytes
     opts.flags = FLAG_PROFILE if profile else 0
     opts.stream = _stream(stream)
+    if proposer is not None:
+        opts.proposer, opts.proposal_margin, opts.seed = proposer._h.value, int(proposal_margin), int(seed)
     ph = _phase(phase)
     h = C.c_void_p()
     _check(lib.idbf_construct(C.byref(ph), _ptr(Xd), _ptr(Od), Xd.numel(), float(tol), int(leaf),
@@ -253,7 +270,7 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
 
 def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample: int = 1,
                       mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
-                      stream=None) -> list:
+                      stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0) -> list:
     """idbf_construct_batched: one lockstep construction of len(phases) instances."""
     lib = load()
     n = len(phases)
@@ -269,6 +286,8 @@ def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample
     opts.kmax, opts.oversample, opts.mem_cap_bytes = kmax, oversample, mem_cap_bytes
     opts.flags = FLAG_PROFILE if profile else 0
     opts.stream = _stream(stream)
+    if proposer is not None:
+        opts.proposer, opts.proposal_margin, opts.seed = proposer._h.value, int(proposal_margin), int(seed)
     ph = (Phase_t * n)(*[_phase(p) for p in phases])
     xp = (C.c_void_p * n)(*[_ptr(x) for x in Xd])
     op = (C.c_void_p * n)(*[_ptr(o) for o in Od])
@@ -300,6 +319,82 @@ def apply_batched(facs, xs, ys=None, dtype: int | None = None, stream=None) -> l
     nr = (C.c_int64 * n)(*[1 if x.dim() == 1 else x.shape[1] for x in xs])
     _check(load().idbf_apply_batched(n, hs, xp, yp, nr, int(dtype), _stream(stream)))
     return ys
+
+
+def mlp_init(hidden: int, seed: int) -> np.ndarray:
+    """He-uniform weights and zero biases in the flat parameter layout (float32)."""
+    rng = np.random.default_rng(seed)
+    n_in = MLP_INPUTS
+    parts = [rng.uniform(-1, 1, (n_in, hidden)) * np.sqrt(6.0 / n_in), np.zeros(hidden),
+             rng.uniform(-1, 1, (hidden, hidden)) * np.sqrt(6.0 / hidden), np.zeros(hidden),
+             rng.uniform(-1, 1, hidden) * np.sqrt(6.0 / hidden), np.zeros(1)]
+    return np.concatenate([x.ravel() for x in parts]).astype(np.float32)
+
+
+class RankProposer:
+    """The rank-proposal network (idbf_mlp): forward, gradient, Adam training."""
+
+    def __init__(self, hidden: int = 128, params=None, seed: int = 0):
+        lib = load()
+        self.hidden = hidden
+        self.n_params = lib.idbf_mlp_param_count(hidden)
+        p = mlp_init(hidden, seed) if params is None else np.ascontiguousarray(params, np.float32)
+        if p.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        self._h = C.c_void_p()
+        _check(lib.idbf_mlp_create(hidden, p.ctypes.data, C.byref(self._h)))
+
+    def close(self) -> None:
+        if self._h:
+            _check(load().idbf_mlp_destroy(self._h))
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(self.n_params, np.float32)
+        _check(load().idbf_mlp_params(self._h, out.ctypes.data))
+        return out
+
+    def forward(self, X, stream=None):
+        import torch
+        X = X.to(torch.float32).contiguous()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _check(load().idbf_mlp_forward(self._h, _ptr(X), X.shape[0], _ptr(y), _stream(stream)))
+        return y
+
+    def loss_grad(self, X, y, stream=None):
+        import torch
+        X, y = X.to(torch.float32).contiguous(), y.to(torch.float32).contiguous()
+        g = torch.empty(self.n_params, dtype=torch.float32, device=X.device)
+        loss = C.c_float()
+        _check(load().idbf_mlp_loss_grad(self._h, _ptr(X), _ptr(y), X.shape[0], _ptr(g), C.byref(loss),
+                                         _stream(stream)))
+        return float(loss.value), g
+
+    def train(self, X, y, epochs: int, batch: int = 512, lr: float = 1e-3, seed: int = 0, stream=None):
+        import torch
+        X, y = X.to(torch.float32).contiguous(), y.to(torch.float32).contiguous()
+        losses = np.zeros(max(epochs, 1), np.float32)
+        _check(load().idbf_mlp_train(self._h, _ptr(X), _ptr(y), X.shape[0], int(epochs), int(batch),
+                                     float(lr), int(seed), losses.ctypes.data, _stream(stream)))
+        return losses[:epochs]
+
+
+def rank_samples(fac: Factorization, side: int, level: int, device="cuda"):
+    """(features (n, 8), targets (n,)) float32 device tensors of one level's IDs."""
+    import torch
+    n = C.c_int64()
+    ns, nt = C.c_int64(), C.c_int64()
+    _check(load().idbf_batch_sizes(fac._h, side, level, C.byref(n), C.byref(ns), C.byref(nt)))
+    F = torch.empty((n.value, MLP_INPUTS), dtype=torch.float32, device=device)
+    t = torch.empty(n.value, dtype=torch.float32, device=device)
+    _check(load().idbf_rank_samples(fac._h, side, level, _ptr(F), _ptr(t)))
+    return F, t
 
 
 def sample(phase, X, Omega, rows, cols, device="cuda", stream=None):

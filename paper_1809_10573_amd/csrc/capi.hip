@@ -109,6 +109,10 @@ struct Batch {
   double flops = 0.0;             // FP64 flops of the batch's IDs
   int64_t sampled = 0;            // kernel entries sampled
   int rank_min = 0, rank_max = 0, cand_max = 0, s_max = 0;
+  // learned proposal
+  int32_t* s_prop = nullptr;   // sample counts the IDs used (proposal, or plain when rejected)
+  int32_t* reject = nullptr;   // 1: proposal rejected by the residual test
+  int64_t rejected = 0;
 };
 
 // HIP events around kernel launches, aggregated by name on request.
@@ -197,7 +201,7 @@ __global__ void check_points_kernel(const double* p, int64_t n, int32_t* bad) {
 // pinned memory so that many handles can be driven in lockstep with one
 // synchronization per phase.
 struct HostStage {
-  int64_t st[8];
+  int64_t st[12];
   unsigned long long counts[kQrBuckets];
   unsigned long long cursors[kQrBuckets];
   int32_t bad[2];
@@ -216,6 +220,20 @@ struct LevelJob {
 
 using namespace idbf;
 
+struct idbf_mlp_s {
+  int hidden = 0;
+  int np = 0;
+  float* P = nullptr;  // parameters (device)
+  float* M = nullptr;  // Adam moments
+  float* V = nullptr;
+  int step = 0;
+  ~idbf_mlp_s() {
+    if (P) (void)hipFree(P);
+    if (M) (void)hipFree(M);
+    if (V) (void)hipFree(V);
+  }
+};
+
 struct idbf_handle_s {
   int64_t N = 0;
   int leaf = 0, L = 0, H = 0, kmax = 0, oversample = 1;
@@ -227,7 +245,7 @@ struct idbf_handle_s {
   int32_t* samp_pos = nullptr; // sample positions of the current level (128 per ID)
   int32_t* order = nullptr;    // IDs of the current level grouped by QR wavefronts
   unsigned long long* bucket = nullptr;  // [0, kQrBuckets): bucket counts, then the fill cursors
-  int64_t* stats = nullptr;    // 8 int64 read back after each scan
+  int64_t* stats = nullptr;    // 12 int64 read back after each scan ([8, 11): work of every ID pass)
   int32_t* status = nullptr;
   std::vector<Batch> U, V;
   int64_t nblk = 0, nnz_S = 0, nnz_S_res = 0, sblk_max = 0;
@@ -244,6 +262,9 @@ struct idbf_handle_s {
   HostStage* pin = nullptr;    // pinned: values the schedule reads back between phases
   LevelJob job;                // the level batch being built
   int qr_rec = -1;             // profiler record of that batch's QR launches
+  idbf_mlp_s* proposer = nullptr;  // rank proposal network (not owned), or null
+  int margin = 0;
+  uint64_t seed = 0;
 
   ~idbf_handle_s() {
     if (pin) (void)hipHostFree(pin);
@@ -331,13 +352,28 @@ idbf_status level_begin(idbf_handle_s* h, const double* X, const double* Om, int
   TRYHIP(launch_desc(d, h->stream));
   TRYHIP(launch_scan_i64(b.t_bound, n, b.T_off, b.cand_len, h->stats, h->stream));
   TRYHIP(launch_scan_i32(b.samples, n, b.skel_off, nullptr, h->stats + 4, h->stream));
+  const int32_t* qr_samples = b.samples;
+  if (h->proposer) {  // proposed sample counts from the network's rank estimates
+    float *F = nullptr, *y = nullptr;
+    TRY(A.get(n * kProposalInputs, &F));
+    TRY(A.get(n, &y));
+    TRY(A.get(n, &b.s_prop));
+    TRY(A.get(n, &b.reject));
+    TRYHIP(launch_features(n, h->L, t, side == IDBF_SIDE_U ? 0 : 1, h->ph, F, h->stream));
+    TRYHIP(launch_mlp_forward(h->proposer->P, kProposalInputs, h->proposer->hidden, F, n, y, nullptr, nullptr,
+                              h->stream));
+    TRYHIP(launch_propose(y, b.samples, n, h->oversample, h->margin, b.s_prop, h->stream));
+    qr_samples = b.s_prop;
+  }
   TRYHIP(hipMemsetAsync(h->bucket, 0, kQrBuckets * sizeof(unsigned long long), h->stream));
-  TRYHIP(launch_bucket_count(b.samples, b.cand_len, n, h->bucket, h->stream));
+  TRYHIP(launch_bucket_count(qr_samples, b.cand_len, nullptr, n, h->bucket, h->stream));
   h->prof.end(pr, h->stream);
   TRYHIP(hipMemcpyAsync(h->pin->counts, h->bucket, sizeof h->pin->counts, hipMemcpyDeviceToHost, h->stream));
   TRYHIP(hipMemcpyAsync(h->pin->st, h->stats, sizeof h->pin->st, hipMemcpyDeviceToHost, h->stream));
   return IDBF_OK;
 }
+
+idbf_status level_scan(idbf_handle_s* h);
 
 idbf_status level_ids(idbf_handle_s* h) {
   LevelJob& J = h->job;
@@ -385,7 +421,9 @@ idbf_status level_ids(idbf_handle_s* h) {
   for (int w = 0; w < kQrBuckets; ++w) h->pin->cursors[w] = (unsigned long long)ia.bucket_off[w];
   TRYHIP(hipMemcpyAsync(h->bucket + kQrBuckets, h->pin->cursors, sizeof h->pin->cursors, hipMemcpyHostToDevice,
                         h->stream));
-  TRYHIP(launch_bucket_fill(b.samples, b.cand_len, n, h->bucket + kQrBuckets, h->order, h->stream));
+  ia.samples = b.s_prop;  // null without a proposer
+  TRYHIP(launch_bucket_fill(b.s_prop ? b.s_prop : b.samples, b.cand_len, nullptr, n, h->bucket + kQrBuckets,
+                            h->order, h->stream));
   ia.rank = b.rank;
   ia.mask = b.mask;
   ia.skel_out = h->scratch;
@@ -399,14 +437,71 @@ idbf_status level_ids(idbf_handle_s* h) {
   const int pq = h->prof.begin("id_qr", h->stream);
   TRYHIP(launch_qr(ia, h->stream));
   h->prof.end(pq, h->stream);
-  pr = h->prof.begin("level_scan", h->stream);
+  h->qr_rec = pq;  // its flop count is attached once the work counters are back
+  if (h->proposer) {  // residual test; rejected IDs are counted per QR bucket for the fallback
+    TRYHIP(hipMemsetAsync(h->stats + 8, 0, 3 * sizeof(int64_t), h->stream));
+    TRYHIP(launch_id_work(b.rank, b.cand_len, b.s_prop, nullptr, n, reinterpret_cast<unsigned long long*>(h->stats + 8),
+                          h->stream));
+    ResidualArgs ra{};
+    ra.id = ia;
+    ra.level = t;
+    ra.seed = h->seed;
+    ra.factor = 10.0;
+    ra.reject = b.reject;
+    ra.s_prop = b.s_prop;
+    ra.samples_plain = b.samples;
+    pr = h->prof.begin("id_residual", h->stream);
+    TRYHIP(launch_residual(ra, h->stream));
+    h->prof.end(pr, h->stream);
+    TRYHIP(hipMemsetAsync(h->bucket, 0, kQrBuckets * sizeof(unsigned long long), h->stream));
+    TRYHIP(launch_bucket_count(b.s_prop, b.cand_len, b.reject, n, h->bucket, h->stream));
+    TRYHIP(hipMemcpyAsync(h->pin->counts, h->bucket, sizeof h->pin->counts, hipMemcpyDeviceToHost, h->stream));
+    return IDBF_OK;
+  }
+  return level_scan(h);
+}
+
+// Recompute the rejected proposals from the plain sample counts.
+idbf_status level_fallback(idbf_handle_s* h) {
+  LevelJob& J = h->job;
+  Batch& b = J.b;
+  IdArgs ia = J.ia;
+  ia.bucket_off[0] = 0;
+  for (int w = 0; w < kQrBuckets; ++w) ia.bucket_off[w + 1] = ia.bucket_off[w] + (int64_t)h->pin->counts[w];
+  b.rejected = ia.bucket_off[kQrBuckets];
+  if (b.rejected > 0) {
+    for (int w = 0; w < kQrBuckets; ++w) h->pin->cursors[w] = (unsigned long long)ia.bucket_off[w];
+    TRYHIP(hipMemcpyAsync(h->bucket + kQrBuckets, h->pin->cursors, sizeof h->pin->cursors, hipMemcpyHostToDevice,
+                          h->stream));
+    TRYHIP(launch_bucket_fill(b.s_prop, b.cand_len, b.reject, b.n, h->bucket + kQrBuckets, h->order, h->stream));
+    ia.samples = b.s_prop;  // plain counts for the rejected IDs
+    ia.sel_list = h->order;
+    ia.sel_n = b.rejected;
+    int pr = h->prof.begin("id_select", h->stream);
+    TRYHIP(launch_select(ia, h->stream));
+    h->prof.end(pr, h->stream);
+    ia.sel_list = nullptr;
+    pr = h->prof.begin("id_qr_fallback", h->stream);
+    TRYHIP(launch_qr(ia, h->stream));
+    h->prof.end(pr, h->stream);
+    TRYHIP(launch_id_work(b.rank, b.cand_len, b.s_prop, b.reject, b.n,
+                          reinterpret_cast<unsigned long long*>(h->stats + 8), h->stream));
+  }
+  return level_scan(h);
+}
+
+// Work counters and the rank scan of a finished batch, read back by level_finish.
+idbf_status level_scan(idbf_handle_s* h) {
+  LevelJob& J = h->job;
+  Batch& b = J.b;
+  const int64_t n = b.n;
+  const int pr = h->prof.begin("level_scan", h->stream);
   TRYHIP(hipMemsetAsync(h->stats + 4, 0, 3 * sizeof(int64_t), h->stream));
-  TRYHIP(launch_id_work(b.rank, b.cand_len, b.samples, n, reinterpret_cast<unsigned long long*>(h->stats + 4),
-                        h->stream));
+  TRYHIP(launch_id_work(b.rank, b.cand_len, b.s_prop ? b.s_prop : b.samples, nullptr, n,
+                        reinterpret_cast<unsigned long long*>(h->stats + 4), h->stream));
   TRYHIP(launch_scan_i32(b.rank, n, b.skel_off, nullptr, h->stats, h->stream));
   TRYHIP(hipMemcpyAsync(h->stats + 7, h->status, sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
   h->prof.end(pr, h->stream);
-  h->qr_rec = pq;  // its flop count is attached once the work counters are back
   TRYHIP(hipMemcpyAsync(h->pin->st, h->stats, sizeof h->pin->st, hipMemcpyDeviceToHost, h->stream));
   return IDBF_OK;
 }
@@ -421,6 +516,10 @@ idbf_status level_finish(idbf_handle_s* h) {
   b.flops = (double)(unsigned long long)st[4];
   b.nnz_T = st[5];
   b.sampled = st[6];
+  if (h->proposer) {  // work of every pass: the proposals, then the recomputed rejections
+    b.flops = (double)(unsigned long long)st[8];
+    b.sampled = st[10];
+  }
   if (h->qr_rec >= 0) h->prof.recs[h->qr_rec].flops = b.flops;
   const int32_t status = (int32_t)(st[7] & 0xffffffff);
   if (status & kErrRank) {
@@ -570,7 +669,7 @@ idbf_status construct_setup(idbf_handle_s* h) {
     }
     std::memset(h->pin, 0, sizeof(HostStage));
   }
-  TRY(A.get(8, &h->stats));
+  TRY(A.get(12, &h->stats));
   TRY(A.get(1, &h->status));
   TRY(A.get(h->N, &h->iota));
   if (h->H > 0) {
@@ -605,6 +704,10 @@ idbf_status construct_impl(idbf_handle_s* h, const double* X, const double* Om) 
       TRY(sync(h));
       TRY(level_ids(h));
       TRY(sync(h));
+      if (h->proposer) {
+        TRY(level_fallback(h));
+        TRY(sync(h));
+      }
       TRY(level_finish(h));
     }
   TRY(middle_begin(h));
@@ -698,6 +801,13 @@ idbf_status make_handle(const idbf_phase* phase, const double* X, const double* 
   if (o.mem_cap_bytes) h->arena.chunk_min = std::min<size_t>(h->arena.chunk_min, o.mem_cap_bytes);
   h->stream = static_cast<hipStream_t>(o.stream);
   h->prof.on = (o.flags & IDBF_FLAG_PROFILE) != 0;
+  h->proposer = o.proposer;
+  h->margin = o.proposal_margin;
+  h->seed = o.seed;
+  if (h->proposer && o.proposal_margin < 0) {
+    set_error("opts: proposal_margin must be >= 0");
+    return IDBF_EINVAL;
+  }
   *out = std::move(h);
   return IDBF_OK;
 }
@@ -787,6 +897,10 @@ idbf_status construct_lockstep(std::vector<std::unique_ptr<idbf_handle_s>>& hs, 
       TRY(sync_streams(streams));
       IDBF_EACH(h->H >= t, level_ids(h));
       TRY(sync_streams(streams));
+      if (hs[0]->proposer) {  // every instance shares the options
+        IDBF_EACH(h->H >= t, level_fallback(h));
+        TRY(sync_streams(streams));
+      }
       IDBF_EACH(h->H >= t, level_finish(h));
     }
   IDBF_EACH(true, middle_begin(h));
@@ -1058,6 +1172,8 @@ idbf_status idbf_get_info(idbf_handle h, idbf_info* info) {
       info->rank_max = std::max(info->rank_max, b.rank_max);
       info->cand_max = std::max(info->cand_max, b.cand_max);
       info->samples_max = std::max(info->samples_max, b.s_max);
+      if (b.s_prop) info->proposed += b.n;
+      info->rejected += b.rejected;
     }
   }
   if (info->n_ids == 0) info->rank_min = 0;
@@ -1267,6 +1383,179 @@ idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double
     set_error("an ID exceeded the kernel's size limits");
     return IDBF_EUNSUPPORTED;
   }
+  return IDBF_OK;
+}
+
+int32_t idbf_mlp_param_count(int32_t hidden) { return mlp_param_count(kProposalInputs, hidden); }
+
+idbf_status idbf_mlp_create(int32_t hidden, const float* params, idbf_mlp* out) {
+  g_err[0] = 0;
+  if (!out || !params || (hidden != 16 && hidden != 32 && hidden != 64 && hidden != 128)) {
+    set_error("mlp_create: hidden must be 16, 32, 64 or 128 and params/out non-NULL");
+    return IDBF_EINVAL;
+  }
+  *out = nullptr;
+  std::unique_ptr<idbf_mlp_s> m(new (std::nothrow) idbf_mlp_s());
+  if (!m) {
+    set_error("host allocation failed");
+    return IDBF_ENOMEM;
+  }
+  m->hidden = hidden;
+  m->np = mlp_param_count(kProposalInputs, hidden);
+  const size_t bytes = size_t(m->np) * sizeof(float);
+  for (float** p : {&m->P, &m->M, &m->V}) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      set_error("mlp_create: hipMalloc failed");
+      return IDBF_ENOMEM;
+    }
+  }
+  IDBF_HIP_CHECK(hipMemcpy(m->P, params, bytes, hipMemcpyHostToDevice));
+  IDBF_HIP_CHECK(hipMemset(m->M, 0, bytes));
+  IDBF_HIP_CHECK(hipMemset(m->V, 0, bytes));
+  *out = m.release();
+  return IDBF_OK;
+}
+
+idbf_status idbf_mlp_destroy(idbf_mlp m) {
+  if (!m) return IDBF_OK;
+  (void)hipDeviceSynchronize();
+  delete m;
+  return IDBF_OK;
+}
+
+idbf_status idbf_mlp_params(idbf_mlp m, float* params) {
+  if (!m || !params) {
+    set_error("mlp_params: NULL argument");
+    return IDBF_EINVAL;
+  }
+  IDBF_HIP_CHECK(hipMemcpy(params, m->P, size_t(m->np) * sizeof(float), hipMemcpyDeviceToHost));
+  return IDBF_OK;
+}
+
+idbf_status idbf_mlp_forward(idbf_mlp m, const float* X, int64_t n, float* y, void* stream) {
+  g_err[0] = 0;
+  if (!m || n < 0 || (n > 0 && (!X || !y))) {
+    set_error("mlp_forward: invalid arguments");
+    return IDBF_EINVAL;
+  }
+  IDBF_HIP_CHECK(launch_mlp_forward(m->P, kProposalInputs, m->hidden, X, n, y, nullptr, nullptr,
+                                    static_cast<hipStream_t>(stream)));
+  return IDBF_OK;
+}
+
+namespace {
+// device scratch for the gradient: (4 hidden + 2) n floats + the loss
+struct MlpScratch {
+  float* ws = nullptr;
+  float* loss = nullptr;
+  ~MlpScratch() {
+    if (ws) (void)hipFree(ws);
+    if (loss) (void)hipFree(loss);
+  }
+  idbf_status alloc(int hidden, int64_t n, int64_t nloss) {
+    if (hipMalloc(&ws, size_t(4 * hidden + 2) * size_t(n) * sizeof(float)) != hipSuccess ||
+        hipMalloc(&loss, size_t(nloss) * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("mlp: scratch allocation failed");
+      return IDBF_ENOMEM;
+    }
+    return IDBF_OK;
+  }
+};
+}  // namespace
+
+idbf_status idbf_mlp_loss_grad(idbf_mlp m, const float* X, const float* y, int64_t n, float* grad, float* loss,
+                               void* stream) {
+  g_err[0] = 0;
+  if (!m || n < 1 || !X || !y || !grad || !loss) {
+    set_error("mlp_loss_grad: invalid arguments");
+    return IDBF_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  MlpScratch sc;
+  TRY(sc.alloc(m->hidden, n, 1));
+  IDBF_HIP_CHECK(launch_mlp_loss_grad(m->P, kProposalInputs, m->hidden, X, y, n, grad, sc.loss, sc.ws, st));
+  float sum = 0.f;
+  IDBF_HIP_CHECK(hipMemcpyAsync(&sum, sc.loss, sizeof sum, hipMemcpyDeviceToHost, st));
+  IDBF_HIP_CHECK(hipStreamSynchronize(st));
+  *loss = 0.5f * sum / (float)n;
+  return IDBF_OK;
+}
+
+idbf_status idbf_mlp_train(idbf_mlp m, const float* X, const float* y, int64_t n, int32_t epochs, int32_t batch,
+                           float lr, uint64_t seed, float* loss_per_epoch, void* stream) {
+  g_err[0] = 0;
+  if (!m || n < 1 || n > INT32_MAX || !X || !y || epochs < 0 || batch < 1 || !(lr > 0.f)) {
+    set_error("mlp_train: invalid arguments");
+    return IDBF_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t nb = (n + batch - 1) / batch;
+  MlpScratch sc;
+  TRY(sc.alloc(m->hidden, batch, nb));
+  float *Xb = nullptr, *yb = nullptr, *G = nullptr;
+  int32_t* idx = nullptr;
+  struct Free {
+    std::vector<void*> p;
+    ~Free() {
+      for (void* q : p) (void)hipFree(q);
+    }
+  } fr;
+  auto dev = [&](void** p, size_t bytes) -> idbf_status {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("mlp_train: allocation failed");
+      return IDBF_ENOMEM;
+    }
+    fr.p.push_back(*p);
+    return IDBF_OK;
+  };
+  TRY(dev(reinterpret_cast<void**>(&Xb), size_t(batch) * kProposalInputs * sizeof(float)));
+  TRY(dev(reinterpret_cast<void**>(&yb), size_t(batch) * sizeof(float)));
+  TRY(dev(reinterpret_cast<void**>(&G), size_t(m->np) * sizeof(float)));
+  TRY(dev(reinterpret_cast<void**>(&idx), size_t(n) * sizeof(int32_t)));
+  std::vector<int32_t> perm(n);
+  std::vector<float> losses(nb);
+  for (int32_t e = 0; e < epochs; ++e) {
+    // Fisher-Yates with SplitMix64 draws (counter: seed, epoch, position)
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+    for (int64_t i = n - 1; i > 0; --i) {
+      uint64_t z = (seed ^ (uint64_t(e) << 40)) + uint64_t(i) + 0x9E3779B97F4A7C15ull;
+      z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+      z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+      z ^= z >> 31;
+      const int64_t j = (int64_t)(((z >> 32) * uint64_t(i + 1)) >> 32);
+      std::swap(perm[i], perm[j]);
+    }
+    IDBF_HIP_CHECK(hipMemcpyAsync(idx, perm.data(), size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    for (int64_t bi = 0; bi < nb; ++bi) {
+      const int64_t b0 = bi * batch, rows = std::min<int64_t>(batch, n - b0);
+      IDBF_HIP_CHECK(launch_gather_rows(X, y, idx + b0, rows, kProposalInputs, Xb, yb, st));
+      IDBF_HIP_CHECK(launch_mlp_loss_grad(m->P, kProposalInputs, m->hidden, Xb, yb, rows, G, sc.loss + bi, sc.ws, st));
+      IDBF_HIP_CHECK(launch_adam(m->P, G, m->M, m->V, m->np, lr, ++m->step, st));
+    }
+    IDBF_HIP_CHECK(hipMemcpyAsync(losses.data(), sc.loss, size_t(nb) * sizeof(float), hipMemcpyDeviceToHost, st));
+    IDBF_HIP_CHECK(hipStreamSynchronize(st));  // also keeps perm alive until its copy is done
+    double sum = 0.0;
+    for (float v : losses) sum += v;
+    if (loss_per_epoch) loss_per_epoch[e] = (float)(0.5 * sum / (double)n);
+  }
+  IDBF_HIP_CHECK(hipStreamSynchronize(st));
+  return IDBF_OK;
+}
+
+idbf_status idbf_rank_samples(idbf_handle h, int32_t side, int32_t level, float* features, float* targets) {
+  g_err[0] = 0;
+  const Batch* b = h ? find_batch(h, side, level) : nullptr;
+  if (!b || !features || !targets) {
+    set_error("rank_samples: invalid handle, side, level or NULL output");
+    return IDBF_EINVAL;
+  }
+  IDBF_HIP_CHECK(launch_features(b->n, h->L, level, side == IDBF_SIDE_U ? 0 : 1, h->ph, features, h->stream));
+  IDBF_HIP_CHECK(launch_rank_targets(b->rank, b->n, targets, h->stream));
+  IDBF_HIP_CHECK(hipStreamSynchronize(h->stream));
   return IDBF_OK;
 }
 

@@ -141,11 +141,12 @@ __global__ __launch_bounds__(64 * kSelIds) void select_kernel(IdArgs A) {
   __shared__ double s_z[kSelIds][kMaxSamples];
   __shared__ uint32_t s_bits[kSelIds][kSelBitmapWords];
   const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t q = blockIdx.x * (int64_t)kSelIds + w;
-  if (q >= A.n_ids) return;
+  const int64_t qi = blockIdx.x * (int64_t)kSelIds + w;
+  if (qi >= (A.sel_list ? A.sel_n : A.n_ids)) return;
+  const int64_t q = A.sel_list ? (int64_t)A.sel_list[qi] : qi;
   const int c = A.cand_len[q], na = A.allow_len[q];
-  const int s = min(min(A.oversample * c, na), kMaxSamples);
-  if (c < 1 || c > kMaxCand || na < 1) return;  // id_kernel reports it
+  const int s = A.samples ? A.samples[q] : min(min(A.oversample * c, na), kMaxSamples);
+  if (c < 1 || c > kMaxCand || na < 1 || s < 1 || s > kMaxSamples) return;  // id_kernel reports it
   int32_t* out = A.samp_pos + q * (int64_t)kMaxSamples;
   if (s >= na) {
     for (int j = lane; j < na; j += kWave) out[j] = j;
@@ -242,8 +243,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   const int nthreads = kWave * W;
   const int cb = A.cand_beg[q], c = A.cand_len[q];
   const int ab = A.allow_beg[q], na = A.allow_len[q];
-  const int s = min(min(A.oversample * c, na), kMaxSamples);
-  if (c < 1 || c > NC || na < 1 || s > SMAX) {
+  const int s = A.samples ? A.samples[q] : min(min(A.oversample * c, na), kMaxSamples);
+  if (c < 1 || c > NC || na < 1 || s < 1 || s > SMAX || s > na) {
     if (threadIdx.x == 0) atomicOr(A.status, kErrSize);
     return;
   }
@@ -523,9 +524,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 hipError_t launch_qr_bucket(const IdArgs& a, int64_t n, int bucket, hipStream_t st);
 
 hipError_t launch_select(const IdArgs& a, hipStream_t st) {
-  if (a.n_ids <= 0) return hipSuccess;
-  hipLaunchKernelGGL(select_kernel, dim3((unsigned)((a.n_ids + kSelIds - 1) / kSelIds)), dim3(64 * kSelIds), 0,
-                     st, a);
+  const int64_t n = a.sel_list ? a.sel_n : a.n_ids;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(select_kernel, dim3((unsigned)((n + kSelIds - 1) / kSelIds)), dim3(64 * kSelIds), 0, st, a);
   return hipGetLastError();
 }
 

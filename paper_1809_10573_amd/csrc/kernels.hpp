@@ -42,6 +42,9 @@ struct IdArgs {
   int oversample;
   int s_max;                  // largest sample count of the batch (sizes the launch)
   int c_max;                  // largest candidate count of the batch (sizes the launch)
+  const int32_t* samples;     // per-ID sample counts, or null: s = min(t c, |allowed|, kMaxSamples)
+  const int32_t* sel_list;    // selection: the IDs to process (sel_n of them), or null: all n_ids
+  int64_t sel_n;
   int32_t* samp_pos;          // kMaxSamples sample positions per ID (scratch)
   const int32_t* order;       // QR launch: IDs grouped by kernel variant (qr_bucket), or null
   int64_t bucket_off[kQrBuckets + 1];  // host: order[bucket_off[b] .. bucket_off[b + 1]) are bucket b
@@ -61,15 +64,50 @@ hipError_t launch_id_batch(const IdArgs& a, hipStream_t st);
 // IDs grouped by qr_bucket: counts[0..kQrBuckets) += bucket sizes (pass 1),
 // then order[] filled from per-bucket cursors (pass 2, cursors pre-set to the
 // bucket offsets).
-hipError_t launch_bucket_count(const int32_t* samples, const int32_t* cand_len, int64_t n,
+// keep (nullable): only IDs with keep[q] != 0 are counted / placed.
+hipError_t launch_bucket_count(const int32_t* samples, const int32_t* cand_len, const int32_t* keep, int64_t n,
                                unsigned long long* counts, hipStream_t st);
-hipError_t launch_bucket_fill(const int32_t* samples, const int32_t* cand_len, int64_t n,
+hipError_t launch_bucket_fill(const int32_t* samples, const int32_t* cand_len, const int32_t* keep, int64_t n,
                               unsigned long long* cursors, int32_t* order, hipStream_t st);
 
-// Work of a finished level: out[0] += sum 16 sum_{j<k}(s-j)(c-j) + 4 k^2 (c-k)
-// (FP64 flops), out[1] += sum k (c - k) (T entries), out[2] += sum s c (samples).
-hipError_t launch_id_work(const int32_t* rank, const int32_t* cand_len, const int32_t* samples, int64_t n,
-                          unsigned long long* out, hipStream_t st);
+// ------------------------------------------------------------- learned proposal
+constexpr int kProposalInputs = 8;       // features per ID
+constexpr float kProposalScale = 16.f;   // network output x 16 = proposed rank
+int mlp_param_count(int n_in, int hidden);
+// y = network(X) for n rows of n_in features; z1, z2 (nullable, n x hidden):
+// pre-activations kept for the backward pass
+hipError_t launch_mlp_forward(const float* P, int n_in, int hidden, const float* X, int64_t n, float* y,
+                              float* z1, float* z2, hipStream_t st);
+// G = d/dP of mean((y - t)^2) / 2 over the n rows, *loss_dev = sum (y - t)^2;
+// ws: (4 hidden + 2) n floats
+hipError_t launch_mlp_loss_grad(const float* P, int n_in, int hidden, const float* X, const float* t, int64_t n,
+                                float* G, float* loss_dev, float* ws, hipStream_t st);
+hipError_t launch_adam(float* P, const float* G, float* M, float* V, int np, float lr, int step, hipStream_t st);
+hipError_t launch_gather_rows(const float* X, const float* t, const int32_t* idx, int64_t n, int n_in, float* Xb,
+                              float* tb, hipStream_t st);
+// features of the n IDs of level t, side (0 U, 1 V): F[q * kProposalInputs + i]
+hipError_t launch_features(int64_t n, int L, int t, int side, const PhaseDev& ph, float* F, hipStream_t st);
+// s_prop[q] = clamp(t (ceil(16 y[q]) + margin), 1, samples[q])
+hipError_t launch_propose(const float* y, const int32_t* samples, int64_t n, int oversample, int margin,
+                          int32_t* s_prop, hipStream_t st);
+struct ResidualArgs {
+  IdArgs id;                    // the level batch, after its IDs are written
+  int level;
+  uint64_t seed;
+  double factor;                // accept when ||E||_F <= factor tol ||A||_F
+  int32_t* reject;              // out: 1 = rejected
+  int32_t* s_prop;              // rejected IDs get samples_plain[q] (the fallback's count)
+  const int32_t* samples_plain;
+};
+hipError_t launch_residual(const ResidualArgs& a, hipStream_t st);
+// out[q] = rank[q] / kProposalScale (training targets)
+hipError_t launch_rank_targets(const int32_t* rank, int64_t n, float* out, hipStream_t st);
+
+// Work of a finished level (IDs with keep[q] != 0, keep nullable):
+// out[0] += sum 16 sum_{j<k}(s-j)(c-j) + 4 k^2 (c-k) (FP64 flops),
+// out[1] += sum k (c - k) (T entries), out[2] += sum s c (samples).
+hipError_t launch_id_work(const int32_t* rank, const int32_t* cand_len, const int32_t* samples, const int32_t* keep,
+                          int64_t n, unsigned long long* out, hipStream_t st);
 
 // ------------------------------------------------------------- level plumbing
 struct DescArgs {

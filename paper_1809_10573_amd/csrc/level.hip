@@ -189,10 +189,12 @@ __global__ void sample_dense_kernel(PhaseDev ph, const double* X, const double* 
 }
 
 __global__ __launch_bounds__(256) void id_work_kernel(const int32_t* rank, const int32_t* cand_len,
-                                                      const int32_t* samples, int64_t n, unsigned long long* out) {
+                                                      const int32_t* samples, const int32_t* keep, int64_t n,
+                                                      unsigned long long* out) {
   __shared__ unsigned long long s_w[3][256];
   unsigned long long fl = 0, te = 0, se = 0;
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    if (keep && !keep[q]) continue;
     const int64_t k = rank[q], c = cand_len[q], sq = samples[q];
     unsigned long long h = 0;
     for (int64_t j = 0; j < k; ++j) h += (unsigned long long)((sq - j) * (c - j));
@@ -213,12 +215,13 @@ __global__ __launch_bounds__(256) void id_work_kernel(const int32_t* rank, const
 }
 
 __global__ __launch_bounds__(256) void bucket_count_kernel(const int32_t* samples, const int32_t* cand_len,
-                                                           int64_t n, unsigned long long* counts) {
+                                                           const int32_t* keep, int64_t n,
+                                                           unsigned long long* counts) {
   __shared__ unsigned int s_c[kQrBuckets];
   if (threadIdx.x < kQrBuckets) s_c[threadIdx.x] = 0;
   __syncthreads();
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&s_c[qr_bucket(cand_len[q], samples[q])], 1u);
+    if (!keep || keep[q]) atomicAdd(&s_c[qr_bucket(cand_len[q], samples[q])], 1u);
   __syncthreads();
   if (threadIdx.x < kQrBuckets && s_c[threadIdx.x])
     atomicAdd(counts + threadIdx.x, (unsigned long long)s_c[threadIdx.x]);
@@ -227,15 +230,17 @@ __global__ __launch_bounds__(256) void bucket_count_kernel(const int32_t* sample
 // Slots are reserved per workgroup (one global atomic per bucket and
 // workgroup), then handed out inside the workgroup with LDS atomics.
 __global__ __launch_bounds__(256) void bucket_fill_kernel(const int32_t* samples, const int32_t* cand_len,
-                                                          int64_t n, unsigned long long* cursors, int32_t* order) {
+                                                          const int32_t* keep, int64_t n,
+                                                          unsigned long long* cursors, int32_t* order) {
   __shared__ unsigned int s_cnt[kQrBuckets];
   __shared__ unsigned long long s_base[kQrBuckets];
   if (threadIdx.x < kQrBuckets) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool in = q < n && (!keep || keep[q]);
   int b = 0;
   unsigned int local = 0;
-  if (q < n) {
+  if (in) {
     b = qr_bucket(cand_len[q], samples[q]);
     local = atomicAdd(&s_cnt[b], 1u);
   }
@@ -243,7 +248,7 @@ __global__ __launch_bounds__(256) void bucket_fill_kernel(const int32_t* samples
   if (threadIdx.x < kQrBuckets && s_cnt[threadIdx.x])
     s_base[threadIdx.x] = atomicAdd(cursors + threadIdx.x, (unsigned long long)s_cnt[threadIdx.x]);
   __syncthreads();
-  if (q < n) order[s_base[b] + local] = (int32_t)q;
+  if (in) order[s_base[b] + local] = (int32_t)q;
 }
 
 __global__ void pack_meta_kernel(const int64_t* t_off, const uint64_t* mask, const int32_t* cand_beg,
@@ -289,27 +294,27 @@ hipError_t launch_compact_skel(const int32_t* scratch, const int32_t* rank, cons
   return hipGetLastError();
 }
 
-hipError_t launch_id_work(const int32_t* rank, const int32_t* cand_len, const int32_t* samples, int64_t n,
+hipError_t launch_id_work(const int32_t* rank, const int32_t* cand_len, const int32_t* samples, const int32_t* keep, int64_t n,
                           unsigned long long* out, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(id_work_kernel, dim3(std::min<unsigned>(blocks_for(n, 256), 1024u)), dim3(256), 0, st, rank,
-                     cand_len, samples, n, out);
+                     cand_len, samples, keep, n, out);
   return hipGetLastError();
 }
 
-hipError_t launch_bucket_count(const int32_t* samples, const int32_t* cand_len, int64_t n,
+hipError_t launch_bucket_count(const int32_t* samples, const int32_t* cand_len, const int32_t* keep, int64_t n,
                                unsigned long long* counts, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(bucket_count_kernel, dim3(std::min<unsigned>(blocks_for(n, 256), 1024u)), dim3(256), 0, st,
-                     samples, cand_len, n, counts);
+                     samples, cand_len, keep, n, counts);
   return hipGetLastError();
 }
 
-hipError_t launch_bucket_fill(const int32_t* samples, const int32_t* cand_len, int64_t n,
+hipError_t launch_bucket_fill(const int32_t* samples, const int32_t* cand_len, const int32_t* keep, int64_t n,
                               unsigned long long* cursors, int32_t* order, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(bucket_fill_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, samples, cand_len, n, cursors,
-                     order);
+  hipLaunchKernelGGL(bucket_fill_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, samples, cand_len, keep, n,
+                     cursors, order);
   return hipGetLastError();
 }
 

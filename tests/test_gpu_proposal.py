@@ -1,0 +1,140 @@
+"""Learned rank proposal (not in the paper): the network's kernels against the
+FP64 oracle (forward, gradient, one Adam step), and the construction with a
+proposer against the plain construction and the exact kernel."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from paper_1809_10573_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1809_10573_amd import binding as B  # noqa: E402
+
+DEV = "cuda:0"
+NI = B.MLP_INPUTS
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0, 1, (n, NI)).astype(np.float32)
+    y = (np.sin(3 * X[:, 0]) + X[:, 2] * X[:, 3] + 0.5 * X[:, 4]).astype(np.float32)
+    return X, y
+
+
+@pytest.mark.parametrize("hidden", [16, 128])
+def test_forward_and_gradient_match_oracle(hidden):
+    p = B.mlp_init(hidden, seed=hidden)
+    p[NI * hidden:NI * hidden + hidden] = 0.05          # nonzero biases exercise every term
+    X, y = _data(300, 1)                                 # 300: several forward tiles, a ragged tail
+    net = B.RankProposer(hidden, params=p)
+    Xd, yd = torch.as_tensor(X, device=DEV), torch.as_tensor(y, device=DEV)
+    out = net.forward(Xd).cpu().numpy()
+    ref = omlp.forward(p.astype(np.float64), X.astype(np.float64), NI, hidden)
+    assert np.max(np.abs(out - ref)) <= 1e-5 * max(1.0, np.abs(ref).max())
+    loss, g = net.loss_grad(Xd, yd)
+    rloss, rg = omlp.loss_and_grad(p.astype(np.float64), X.astype(np.float64), y.astype(np.float64), NI, hidden)
+    assert abs(loss - rloss) <= 1e-5 * rloss
+    assert np.linalg.norm(g.cpu().numpy() - rg) <= 1e-4 * np.linalg.norm(rg)
+
+
+def test_one_adam_step_matches_oracle():
+    hidden = 32
+    p = B.mlp_init(hidden, seed=3)
+    X, y = _data(256, 2)
+    net = B.RankProposer(hidden, params=p)
+    net.train(torch.as_tensor(X, device=DEV), torch.as_tensor(y, device=DEV), epochs=1, batch=256, lr=1e-2)
+    _, rg = omlp.loss_and_grad(p.astype(np.float64), X.astype(np.float64), y.astype(np.float64), NI, hidden)
+    zero = np.zeros_like(rg)
+    rp, _, _ = omlp.adam_step(p.astype(np.float64), rg, zero, zero, step=1, lr=1e-2)
+    got = net.params()
+    # the first Adam step moves every weight by about lr sign(g); compare where |g| is not tiny
+    big = np.abs(rg) > 1e-4 * np.abs(rg).max()
+    assert np.max(np.abs(got - rp)[big]) <= 1e-5
+
+
+def test_training_on_construction_ranks_reduces_the_loss():
+    feats, targ = [], []
+    for (a, m) in I.family_draws(6, seed=9):
+        X, O = I.uniform_grid(4096)
+        fac = B.construct(I.fio_phase(a, float(m)), X, O, 1e-6, 16, oversample=2, device=DEV)
+        for side in (B.SIDE_U, B.SIDE_V):
+            for t in range(1, fac.info()["H"] + 1):
+                F, tg = B.rank_samples(fac, side, t, device=DEV)
+                feats.append(F)
+                targ.append(tg)
+    F, tg = torch.cat(feats), torch.cat(targ)
+    assert torch.all((tg * 16 >= 1) & (tg * 16 <= 64))
+    net = B.RankProposer(64, seed=1)
+    before = net.loss_grad(F, tg)[0]
+    losses = net.train(F, tg, epochs=60, batch=256, lr=3e-3, seed=2)
+    assert losses[-1] < 0.1 * before
+    pred = net.forward(F) * 16
+    print("rank MAE", float(torch.mean(torch.abs(pred - tg * 16))), "losses", before, losses[0], losses[-1])
+    assert float(torch.mean(torch.abs(pred - tg * 16))) < 3.0   # ranks within a few on average
+
+
+def _rows_error(fac, ph, X, O, seed):
+    N = len(X)
+    g = I.gaussian_vectors(N, None, seed)
+    y = fac.apply(torch.as_tensor(g, device=DEV)).cpu().numpy()
+    rows = np.sort(np.random.default_rng(seed).choice(N, 64, replace=False))
+    return oracle.relative_error(y[rows], oracle.matvec_rows(ph, X, O, g, rows))
+
+
+def test_proposal_that_keeps_plain_counts_reproduces_the_plain_construction():
+    ph = I.fio_phase(0.6, 2.0)
+    X, O = I.uniform_grid(4096)
+    plain = B.construct(ph, X, O, 1e-6, 16, oversample=2, device=DEV)
+    p = B.mlp_init(16, seed=4)
+    p[-1] = 4.0                                           # output bias: every proposed rank is large
+    net = B.RankProposer(16, params=p)
+    prop = B.construct(ph, X, O, 1e-6, 16, oversample=2, device=DEV, proposer=net, proposal_margin=64)
+    info = prop.info()
+    assert info["proposed"] == info["n_ids"] and info["rejected"] == 0
+    for side in (B.SIDE_U, B.SIDE_V):
+        for t in range(1, info["H"] + 1):
+            a, b = plain.batch(side, t), prop.batch(side, t)
+            assert np.array_equal(a.rank, b.rank) and np.array_equal(a.skel, b.skel)
+
+
+def test_wrong_proposals_fall_back_and_keep_accuracy():
+    ph = I.fio_phase(1.0, 3.0)
+    X, O = I.uniform_grid(4096)
+    p = B.mlp_init(16, seed=5)
+    p[:] = 0.0                                            # predicts rank 1 everywhere: s' = t (1 + 0)
+    net = B.RankProposer(16, params=p)
+    fac = B.construct(ph, X, O, 1e-6, 16, oversample=2, device=DEV, proposer=net, proposal_margin=0, seed=7)
+    info = fac.info()
+    assert info["rejected"] > 0.5 * info["proposed"]
+    plain = B.construct(ph, X, O, 1e-6, 16, oversample=2, device=DEV)
+    e_prop, e_plain = _rows_error(fac, ph, X, O, 3), _rows_error(plain, ph, X, O, 3)
+    assert e_prop <= max(2 * e_plain, 1e-4)
+
+
+def test_trained_proposer_saves_samples_at_equal_accuracy():
+    feats, targ = [], []
+    for (a, m) in I.family_draws(8, seed=11):
+        X, O = I.uniform_grid(4096)
+        fac = B.construct(I.fio_phase(a, float(m)), X, O, 1e-6, 16, oversample=2, device=DEV)
+        for side in (B.SIDE_U, B.SIDE_V):
+            for t in range(1, fac.info()["H"] + 1):
+                F, tg = B.rank_samples(fac, side, t, device=DEV)
+                feats.append(F)
+                targ.append(tg)
+    net = B.RankProposer(64, seed=3)
+    net.train(torch.cat(feats), torch.cat(targ), epochs=60, batch=256, lr=3e-3, seed=4)
+    for (a, m) in I.family_draws(3, seed=12):             # held-out family members
+        ph = I.fio_phase(a, float(m))
+        X, O = I.uniform_grid(4096)
+        plain = B.construct(ph, X, O, 1e-6, 16, oversample=2, device=DEV)
+        prop = B.construct(ph, X, O, 1e-6, 16, oversample=2, device=DEV, proposer=net, proposal_margin=4,
+                           seed=1)
+        ip, iq = plain.info(), prop.info()
+        assert iq["sampled_entries"] < ip["sampled_entries"]
+        assert _rows_error(prop, ph, X, O, 5) <= max(2 * _rows_error(plain, ph, X, O, 5), 1e-5)
