@@ -138,6 +138,70 @@ def _batched(B, torch, dev, stream) -> dict:
             "outputs_identical": bool(same)}
 
 
+def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6) -> dict:
+    """The learned rank proposal on the FIO family c(x) = (2 + a sin 2 pi m x)/8
+    at N = 2^18 (leaf 16, tol 1e-6, t = 2): the network is trained on the GPU
+    on ranks from n_train plain constructions, then plain and proposed
+    constructions of n_test held-out (a, m) are compared (wall time, sampled
+    entries, rejected proposals, error on 128 exact rows).  Measured once."""
+    N, leaf, tol = 1 << 18, 16, 1e-6
+    Xh, Oh = I.uniform_grid(N)
+    X, O = torch.as_tensor(Xh, device=dev), torch.as_tensor(Oh, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(8)
+    t0 = time.perf_counter()
+    feats, targ = [], []
+    for (a, m) in I.family_draws(n_train, seed=21):
+        fac = B.construct(I.fio_phase(a, float(m)), X, O, tol, leaf, oversample=2, device=dev, stream=stream)
+        for side in (B.SIDE_U, B.SIDE_V):
+            for t in range(1, fac.info()["H"] + 1):
+                F, tg = B.rank_samples(fac, side, t, device=dev)
+                keep = torch.randperm(F.shape[0], generator=gen, device=dev)[: F.shape[0] // 8]
+                feats.append(F[keep])
+                targ.append(tg[keep])
+        fac.close()
+    F, tg = torch.cat(feats), torch.cat(targ)
+    label_s = time.perf_counter() - t0
+    net = B.RankProposer(128, seed=5)
+    t0 = time.perf_counter()
+    losses = net.train(F, tg, epochs=20, batch=512, lr=2e-3, seed=6, stream=stream)
+    train_s = time.perf_counter() - t0
+    rows = torch.as_tensor(np.sort(np.random.default_rng(1).choice(N, 128, replace=False)), dtype=torch.int32,
+                           device=dev)
+    cols = torch.arange(N, dtype=torch.int32, device=dev)
+    g = torch.as_tensor(I.gaussian_vectors(N, None, 9), device=dev)
+    res = {"plain_ms": [], "proposed_ms": [], "plain_sampled": 0, "proposed_sampled": 0, "proposed": 0,
+           "rejected": 0, "err_plain": [], "err_proposed": []}
+    for (a, m) in I.family_draws(n_test, seed=22):
+        ph = I.fio_phase(a, float(m))
+        ex = torch.zeros(128, dtype=torch.complex128, device=dev)
+        for c0 in range(0, N, 1 << 16):
+            ex += B.sample(ph, X, O, rows, cols[c0:c0 + (1 << 16)], device=dev) @ g[c0:c0 + (1 << 16)]
+        for kind in ("plain", "proposed"):
+            kw = dict(proposer=net, proposal_margin=6, seed=3) if kind == "proposed" else {}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fac = B.construct(ph, X, O, tol, leaf, oversample=2, device=dev, stream=stream, **kw)
+            res[kind + "_ms"].append((time.perf_counter() - t0) * 1e3)
+            info = fac.info()
+            res[kind + "_sampled"] += info["sampled_entries"]
+            if kind == "proposed":
+                res["proposed"] += info["proposed"]
+                res["rejected"] += info["rejected"]
+            y = fac.apply(g)
+            res["err_" + kind].append(float(torch.linalg.norm(y[rows.long()] - ex) / torch.linalg.norm(ex)))
+            fac.close()
+    net.close()
+    return {"N": N, "train_constructions": n_train, "train_samples": int(F.shape[0]),
+            "labels_s": label_s, "train_s": train_s, "loss_first_last": [float(losses[0]), float(losses[-1])],
+            "heldout": n_test,
+            "construct_ms_plain": float(np.mean(res["plain_ms"])),
+            "construct_ms_proposed": float(np.mean(res["proposed_ms"])),
+            "speedup": float(np.mean(res["plain_ms"]) / np.mean(res["proposed_ms"])),
+            "sampled_entries_ratio": res["proposed_sampled"] / max(res["plain_sampled"], 1),
+            "rejected_frac": res["rejected"] / max(res["proposed"], 1),
+            "err_rows_plain_max": max(res["err_plain"]), "err_rows_proposed_max": max(res["err_proposed"])}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,6 +210,7 @@ def main() -> int:
     ap.add_argument("--nrhs", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-instance measurement")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU layout is described "
@@ -295,6 +360,8 @@ def main() -> int:
     torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched"] = _batched(B, torch, dev, stream)
+    if not args.no_learned:
+        out["learned"] = _learned(B, torch, dev, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline()
     print(json.dumps(out), flush=True)
