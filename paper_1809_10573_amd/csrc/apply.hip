@@ -76,8 +76,8 @@ __device__ __forceinline__ void stream_products(const C* blk, int n, int div, co
   }
 }
 
-// vector loads in flight per lane: 1024 entries of a block per round
-template <typename C> constexpr int nv_for() { return 1024 * (int)sizeof(C) / (kWave * 16); }
+// vector loads in flight per lane: one product slot (kProdSlot entries) per round
+template <typename C> constexpr int nv_for();
 
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -93,66 +93,75 @@ __device__ __forceinline__ int mbelow(const ApplyMeta& m, int p) {
   return p < 64 ? __popcll(m.mask & lanes_below(p)) : __popcll(m.mask) + __popcll(m.mask_hi & lanes_below(p - 64));
 }
 
+// Every 1-RHS wavefront stages its products in a fixed slot of kProdSlot
+// entries (LDS), whatever the block size: a block is processed in chunks of
+// whole columns (V, S) or rows (U), partial sums kept in registers.
+constexpr int kProdSlot = 512;
+template <typename C> constexpr int nv_for() { return kProdSlot * (int)sizeof(C) / (kWave * 16); }
+
 // V stage: z(ID) = u[skel] + T u[red]; T column-major (entry j*k + i).
 // One wavefront per ID, candidate positions lane and lane + 64; the ID's
 // packed record is read with a wave-uniform index (scalar loads).
-// Dynamic LDS: kIdsPerBlock * pmax products.
 template <typename C>
 __global__ __launch_bounds__(256) void apply_v1(StageArgs A) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
+  __shared__ C s_prod[kIdsPerBlock][kProdSlot];
   __shared__ C s_u[kIdsPerBlock][kMaxCand];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   const int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + w;
   if (q >= A.n) return;
-  C* s_p = reinterpret_cast<C*>(s_dyn) + (size_t)w * A.pmax;
+  C* s_p = s_prod[w];
   const C* in = static_cast<const C*>(A.in);
   C* out = static_cast<C*>(A.out);
   const ApplyMeta m = A.meta[q];
   const int c = m.c, k = m.k, r = c - k;
   const int halves = c > kWave ? 2 : 1;  // wave-uniform
-  C u[2];
+  C acc[2];
   int below[2];
   bool sk[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int pos = lane + kWave * h;
-    u[h] = czero(C{});
+    acc[h] = czero(C{});
     below[h] = 0;
     sk[h] = false;
     if (h < halves && pos < c) {
-      u[h] = in[m.cand_beg + pos];
+      const C u = in[m.cand_beg + pos];
       below[h] = mbelow(m, pos);
       sk[h] = mbit(m, pos);
-      if (!sk[h]) s_u[w][pos - below[h]] = u[h];
+      if (sk[h]) acc[h] = u; else s_u[w][pos - below[h]] = u;
     }
   }
   wave_sync_lds();
-  stream_products<C, nv_for<C>()>(static_cast<const C*>(A.T) + m.t_off, k * r, k, s_u[w], s_p, lane);
-  wave_sync_lds();
+  const C* T = static_cast<const C*>(A.T) + m.t_off;
+  const int cols = max(1, kProdSlot / max(k, 1));  // whole columns per chunk
+  for (int j0 = 0; j0 < r; j0 += cols) {
+    const int nj = min(cols, r - j0);
+    stream_products<C, nv_for<C>()>(T + (int64_t)j0 * k, nj * k, k, s_u[w] + j0, s_p, lane);
+    wave_sync_lds();
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    if (h < halves && lane + kWave * h < c && sk[h]) {
-      C acc = u[h];
-      for (int j = 0; j < r; ++j) acc = cadd(acc, s_p[j * k + below[h]]);
-      out[m.skel_off + below[h]] = acc;
-    }
+    for (int h = 0; h < 2; ++h)
+      if (h < halves && lane + kWave * h < c && sk[h])
+        for (int j = 0; j < nj; ++j) acc[h] = cadd(acc[h], s_p[j * k + below[h]]);
+    wave_sync_lds();
   }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    if (h < halves && lane + kWave * h < c && sk[h]) out[m.skel_off + below[h]] = acc[h];
 }
 
 // U stage: one unit = the two IDs of one node with the two children of one
 // partner; they share the candidate segment, which the unit writes whole.
-// T row-major (entry i*r + j).
+// T row-major (entry i*r + j), processed in chunks of whole rows.
 template <typename C>
 __global__ __launch_bounds__(256) void apply_u1(StageArgs A) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
+  __shared__ C s_prod[kIdsPerBlock][kProdSlot];
   __shared__ C s_w[kIdsPerBlock][2][kMaxRank];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   const int64_t unit = blockIdx.x * (int64_t)(blockDim.x / kWave) + w;
   if (unit >= A.n) return;
-  C* s_p = reinterpret_cast<C*>(s_dyn) + (size_t)w * 2 * A.pmax;
+  C* s_p = s_prod[w];
   const C* in = static_cast<const C*>(A.in);
   C* out = static_cast<C*>(A.out);
-  const C* T = static_cast<const C*>(A.T);
   const int64_t P = unit / A.nn, node = unit % A.nn;
   ApplyMeta m[2];
   m[0] = A.meta[2 * P * A.nn + node];
@@ -163,87 +172,81 @@ __global__ __launch_bounds__(256) void apply_u1(StageArgs A) {
   for (int h = 0; h < 2; ++h)
     if (lane < m[h].k) s_w[w][h][lane] = in[m[h].skel_off + lane];
   wave_sync_lds();
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int r = c - m[h].k;
-    stream_products<C, nv_for<C>()>(T + m[h].t_off, m[h].k * r, r, s_w[w][h], s_p + h * A.pmax, lane);
-  }
-  wave_sync_lds();
+  C acc[2];
+  int below[2][2];
+  bool sk[2][2];
 #pragma unroll
   for (int hp = 0; hp < 2; ++hp) {
     const int pos = lane + kWave * hp;
-    if (hp < halves && pos < c) {
-      C acc = czero(C{});
+    acc[hp] = czero(C{});
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int below = mbelow(m[h], pos);
-        if (mbit(m[h], pos)) {
-          acc = cadd(acc, s_w[w][h][below]);
-        } else {
-          const int r = c - m[h].k;
-          const C* p = s_p + h * A.pmax + (pos - below);
-          for (int i = 0; i < m[h].k; ++i) acc = cadd(acc, p[i * r]);
+    for (int h = 0; h < 2; ++h) {
+      below[hp][h] = mbelow(m[h], pos);
+      sk[hp][h] = mbit(m[h], pos);
+      if (hp < halves && pos < c && sk[hp][h]) acc[hp] = cadd(acc[hp], s_w[w][h][below[hp][h]]);
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = m[h].k, r = c - k;
+    if (r == 0) continue;
+    const C* T = static_cast<const C*>(A.T) + m[h].t_off;
+    const int rows = max(1, kProdSlot / r);  // whole rows per chunk
+    for (int i0 = 0; i0 < k; i0 += rows) {
+      const int ni = min(rows, k - i0);
+      stream_products<C, nv_for<C>()>(T + (int64_t)i0 * r, ni * r, r, s_w[w][h] + i0, s_p, lane);
+      wave_sync_lds();
+#pragma unroll
+      for (int hp = 0; hp < 2; ++hp) {
+        const int pos = lane + kWave * hp;
+        if (hp < halves && pos < c && !sk[hp][h]) {
+          const C* p = s_p + (pos - below[hp][h]);
+          for (int i = 0; i < ni; ++i) acc[hp] = cadd(acc[hp], p[i * r]);
         }
       }
-      out[m[0].cand_beg + pos] = acc;
+      wave_sync_lds();
     }
+  }
+#pragma unroll
+  for (int hp = 0; hp < 2; ++hp) {
+    const int pos = lane + kWave * hp;
+    if (hp < halves && pos < c) out[m[0].cand_beg + pos] = acc[hp];
   }
 }
 
 // Middle factor, one U_H ID per wavefront: the 2^(d-H) blocks S(R, C') are
-// consecutive, column-major, rows of the output.
+// consecutive, column-major, rows of the output; each block is processed in
+// chunks of whole columns.
 template <typename C>
 __global__ __launch_bounds__(256) void apply_s1(StageArgs A) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
-  __shared__ C s_z[kIdsPerBlock][4][kMaxRank];
-  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  __shared__ C s_prod[kIdsPerBlock][kProdSlot];
+  __shared__ C s_z[kIdsPerBlock][kMaxRank];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
   const int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + w;
   if (q >= A.n) return;
-  C* s_p = reinterpret_cast<C*>(s_dyn) + (size_t)w * A.nsub * A.pmax;
+  C* s_p = s_prod[w];
   const C* in = static_cast<const C*>(A.in);
   C* out = static_cast<C*>(A.out);
   const C* S = static_cast<const C*>(A.T);
   const int64_t b0 = q * A.nsub;
   const int rl = A.rlen[b0], rb = A.rbeg[b0];
-  for (int jb = 0; jb < A.nsub; ++jb)
-    if (lane < A.clen[b0 + jb]) s_z[w][jb][lane] = in[A.cbeg[b0 + jb] + lane];
-  wave_sync_lds();
-  for (int jb = 0; jb < A.nsub; ++jb)
-    stream_products<C, nv_for<C>()>(S + A.T_off[b0 + jb], rl * A.clen[b0 + jb], rl, s_z[w][jb],
-                                    s_p + jb * A.pmax, lane);
-  wave_sync_lds();
-  if (lane < rl) {
-    C acc = czero(C{});
-    for (int jb = 0; jb < A.nsub; ++jb) {
-      const C* p = s_p + jb * A.pmax + lane;
-      for (int col = 0, cl = A.clen[b0 + jb]; col < cl; ++col) acc = cadd(acc, p[col * rl]);
-    }
-    out[rb + lane] = acc;
-  }
-}
-
-// Middle factor when its blocks are too large to stage: lanes over output rows,
-// eight independent column loads in flight per lane.
-template <typename C>
-__global__ __launch_bounds__(256) void apply_s1_direct(StageArgs A) {
-  const int w = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + w;
-  if (q >= A.n) return;
-  const C* in = static_cast<const C*>(A.in);
-  C* out = static_cast<C*>(A.out);
-  const C* S = static_cast<const C*>(A.T);
-  const int64_t b0 = q * A.nsub;
-  const int rl = A.rlen[b0], rb = A.rbeg[b0];
-  if (lane >= rl) return;
   C acc = czero(C{});
   for (int jb = 0; jb < A.nsub; ++jb) {
-    const int64_t b = b0 + jb;
-    const int cl = A.clen[b], cbg = A.cbeg[b];
-    const C* Sb = S + A.T_off[b] + lane;
-#pragma unroll 8
-    for (int col = 0; col < cl; ++col) acc = cfma(Sb[(int64_t)col * rl], in[cbg + col], acc);
+    const int cl = A.clen[b0 + jb];
+    if (lane < cl) s_z[w][lane] = in[A.cbeg[b0 + jb] + lane];
+    wave_sync_lds();
+    const C* Sb = S + A.T_off[b0 + jb];
+    const int cols = max(1, kProdSlot / max(rl, 1));
+    for (int c0 = 0; c0 < cl; c0 += cols) {
+      const int nc = min(cols, cl - c0);
+      stream_products<C, nv_for<C>()>(Sb + (int64_t)c0 * rl, nc * rl, rl, s_z[w] + c0, s_p, lane);
+      wave_sync_lds();
+      if (lane < rl)
+        for (int col = 0; col < nc; ++col) acc = cadd(acc, s_p[col * rl + lane]);
+      wave_sync_lds();
+    }
   }
-  out[rb + lane] = acc;
+  if (lane < rl) out[rb + lane] = acc;
 }
 
 // The whole matrix when the tree has no levels (N <= 2 leaf): lanes over rows.
@@ -416,11 +419,6 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 }
 
 inline unsigned grid1(int64_t n, int ipb = kIdsPerBlock) { return (unsigned)((n + ipb - 1) / ipb); }
-constexpr size_t kDynLds = size_t(48) << 10;  // dynamic LDS budget per workgroup
-// wavefronts (IDs) per workgroup so that per_id bytes of LDS each fit the budget
-inline int ids_per_block(size_t per_id) {
-  return (int)std::max<size_t>(1, std::min<size_t>(kIdsPerBlock, kDynLds / std::max<size_t>(per_id, 1)));
-}
 inline dim3 gridn(int64_t n, int64_t nrhs) {
   return dim3((unsigned)n, (unsigned)((nrhs + kRhsTile - 1) / kRhsTile));
 }
@@ -430,12 +428,8 @@ inline dim3 gridn(int64_t n, int64_t nrhs) {
 hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st) {
   if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
   if (a.nrhs == 1) {
-    const size_t per = (size_t)a.pmax * (fp64 ? 16 : 8);
-    const int ipb = ids_per_block(per);
-    hipError_t e = fp64 ? allow_lds(apply_v1<double2>, ipb * per) : allow_lds(apply_v1<float2>, ipb * per);
-    if (e != hipSuccess) return e;
-    if (fp64) hipLaunchKernelGGL(apply_v1<double2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
-    else hipLaunchKernelGGL(apply_v1<float2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
+    if (fp64) hipLaunchKernelGGL(apply_v1<double2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(apply_v1<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
   } else {
     if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
     const size_t lds = (size_t)a.pmax * sizeof(double2);
@@ -448,12 +442,8 @@ hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st) {
 hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st) {
   if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
   if (a.nrhs == 1) {
-    const size_t per = (size_t)2 * a.pmax * (fp64 ? 16 : 8);
-    const int ipb = ids_per_block(per);
-    hipError_t e = fp64 ? allow_lds(apply_u1<double2>, ipb * per) : allow_lds(apply_u1<float2>, ipb * per);
-    if (e != hipSuccess) return e;
-    if (fp64) hipLaunchKernelGGL(apply_u1<double2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
-    else hipLaunchKernelGGL(apply_u1<float2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
+    if (fp64) hipLaunchKernelGGL(apply_u1<double2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(apply_u1<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
   } else {
     if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
     const size_t lds = 2 * (size_t)a.pmax * sizeof(double2);
@@ -470,15 +460,8 @@ hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st) {
     if (fp64) hipLaunchKernelGGL(apply_dense<double2>, dim3(blocks), dim3(256), 0, st, a);
     else hipLaunchKernelGGL(apply_dense<float2>, dim3(blocks), dim3(256), 0, st, a);
   } else if (a.nrhs == 1) {
-    const size_t per = (size_t)a.nsub * a.pmax * (fp64 ? 16 : 8);
-    if (per <= kDynLds && a.nsub <= 4) {
-      const int ipb = ids_per_block(per);
-      if (fp64) hipLaunchKernelGGL(apply_s1<double2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
-      else hipLaunchKernelGGL(apply_s1<float2>, dim3(grid1(a.n, ipb)), dim3(64 * ipb), ipb * per, st, a);
-    } else {
-      if (fp64) hipLaunchKernelGGL(apply_s1_direct<double2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
-      else hipLaunchKernelGGL(apply_s1_direct<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
-    }
+    if (fp64) hipLaunchKernelGGL(apply_s1<double2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(apply_s1<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
   } else {
     if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
     const size_t lds = (size_t)a.pmax * sizeof(double2);
