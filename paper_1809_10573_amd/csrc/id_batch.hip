@@ -297,23 +297,20 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   double r00 = 0.0;
   int k = 0;
   bool zero_block = false, overflow = false;
-  for (int j = 0;; ++j) {
-    // residual column norms over rows >= j (two independent sums per column)
-    const bool live = row0 + R > j;  // wave-uniform: this wave holds rows >= j
-    double part[CPL];
+  // residual column norms of this wave's rows, for step 0; later steps get
+  // them from the update loop of the step before (rows >= j + 1)
+  double part[CPL];
 #pragma unroll
-    for (int cs = 0; cs < CPL; ++cs) {
-      part[cs] = 0.0;
-      if (live) {
-        double p0 = 0.0, p1 = 0.0;
+  for (int cs = 0; cs < CPL; ++cs) {
+    double p0 = 0.0, p1 = 0.0;
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          const double t = (row0 + i >= j) ? cabs2(a[cs][i]) : 0.0;
-          if (i & 1) p1 += t; else p0 += t;
-        }
-        part[cs] = p0 + p1;
-      }
+    for (int i = 0; i < R; ++i) {
+      if (i & 1) p1 += cabs2(a[cs][i]); else p0 += cabs2(a[cs][i]);
     }
+    part[cs] = p0 + p1;
+  }
+  for (int j = 0;; ++j) {
+    const bool live = row0 + R > j;  // wave-uniform: this wave holds rows >= j
     double nrm2[CPL];
 #pragma unroll
     for (int cs = 0; cs < CPL; ++cs) nrm2[cs] = part[cs];
@@ -328,16 +325,19 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         for (int ww = 0; ww < W; ++ww) nrm2[cs] += s_part[(ww * CPL + cs) * kWave + lane];
       }
     }
+    // pivot search on squared norms (sqrt is monotone: the same maximum, and
+    // the tie band below is far wider than a rounding of the square)
     bool eligible[CPL];
-    double nu[CPL];
-    double numax = -1.0;
+    double nq[CPL];
+    double nqmax = -1.0;
 #pragma unroll
     for (int cs = 0; cs < CPL; ++cs) {
       eligible[cs] = (lane + kWave * cs < c) && !pivoted[cs];
-      nu[cs] = eligible[cs] ? sqrt(nrm2[cs]) : -1.0;
-      numax = fmax(numax, nu[cs]);
+      nq[cs] = eligible[cs] ? nrm2[cs] : -1.0;
+      nqmax = fmax(nqmax, nq[cs]);
     }
-    const double M = wave_max_dpp(numax);
+    const double M2 = wave_max_dpp(nqmax);
+    const double M = M2 > 0.0 ? sqrt(M2) : 0.0;
     if (j == 0) {
       r00 = M;
       if (M == 0.0) {
@@ -353,9 +353,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       break;
     }
     const double thr = (1.0 - kPivotTie) * M;
-    const uint64_t near0 = __ballot(eligible[0] && nu[0] >= thr);
+    const double thr2 = thr * thr;
+    const uint64_t near0 = __ballot(eligible[0] && nq[0] >= thr2);
     uint64_t near1 = 0;
-    if constexpr (CPL > 1) near1 = __ballot(eligible[CPL - 1] && nu[CPL - 1] >= thr);
+    if constexpr (CPL > 1) near1 = __ballot(eligible[CPL - 1] && nq[CPL - 1] >= thr2);
     if (near0 == 0 && near1 == 0) break;  // no finite residual norm left (cannot happen for finite input)
     const int p = __builtin_amdgcn_readfirstlane(
         near0 ? __ffsll((unsigned long long)near0) - 1 : kWave + __ffsll((unsigned long long)near1) - 1);
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     // zero above row j, so that rows < j drop out of the dot and the update
     // exactly; v_i = a_i(p) for i > j and v_j = x_j - alpha,
     // alpha = -(x_j/|x_j|) nu_p, tau = 2 / |v|^2 = 1 / (nu_p (nu_p + |x_j|)).
-    const double nup = readlane(pc == 0 ? nu[0] : nu[CPL - 1], pl);
+    const double nup = sqrt(readlane(pc == 0 ? nq[0] : nq[CPL - 1], pl));
     if (lane == pl && live) {
 #pragma unroll
       for (int i = 0; i < R; ++i) {
@@ -377,9 +378,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         const double axj = sqrt(cabs2(xj));
         double2 vj;
         if (axj > 0.0) {
-          s_alpha = make_double2(-xj.x / axj * nup, -xj.y / axj * nup);
-          const double sc = (axj + nup) / axj;
-          vj = make_double2(xj.x * sc, xj.y * sc);
+          const double g = nup / axj;  // alpha = -g x_j, v_j = (1 + g) x_j
+          s_alpha = make_double2(-xj.x * g, -xj.y * g);
+          vj = make_double2(xj.x + xj.x * g, xj.y + xj.y * g);
         } else {
           s_alpha = make_double2(-nup, 0.0);
           vj = make_double2(nup, 0.0);
@@ -418,10 +419,18 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     if (live) {
 #pragma unroll
       for (int cs = 0; cs < CPL; ++cs) {
+        part[cs] = 0.0;
         if (eligible[cs] && !(lane == pl && cs == pc)) {
+          // update, and the residual norm of rows >= j + 1 for the next step
           const double2 sdot = make_double2(-tau * dot[cs].x, -tau * dot[cs].y);
+          double p0 = 0.0, p1 = 0.0;
 #pragma unroll
-          for (int i = 0; i < R; ++i) a[cs][i] = cfma(s_v[row0 + i], sdot, a[cs][i]);
+          for (int i = 0; i < R; ++i) {
+            a[cs][i] = cfma(s_v[row0 + i], sdot, a[cs][i]);
+            const double t = (row0 + i > j) ? cabs2(a[cs][i]) : 0.0;
+            if (i & 1) p1 += t; else p0 += t;
+          }
+          part[cs] = p0 + p1;
         }
       }
       // the pivot column becomes (alpha, 0, ..., 0) from row j down
@@ -434,6 +443,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             for (int i = 0; i < R; ++i)
               if (row0 + i >= j) a[cs][i] = (row0 + i == j) ? alpha : make_double2(0.0, 0.0);
       }
+    } else {
+#pragma unroll
+      for (int cs = 0; cs < CPL; ++cs) part[cs] = 0.0;  // no rows >= j + 1 here
     }
     if (lane == pl) {
 #pragma unroll
