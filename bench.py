@@ -128,12 +128,18 @@ def _batched(B, torch, dev, stream) -> dict:
         f.reserve(1 if x.dim() == 1 else x.shape[1], B.C64)
     bat_app = timed_apply(lambda: B.apply_batched(facs, xs, ys, stream=stream))
     same = all(torch.equal(a, b) for a, b in zip(ref, ys[:4]))
+    graph_app = None
+    if stream.cuda_stream:  # capture needs a created stream
+        plan = B.ApplyPlan(facs, xs, ys, dtype=B.C64, stream=stream)
+        graph_app = timed_apply(lambda: plan.launch(stream))
+        same = same and all(torch.equal(a, b) for a, b in zip(ref, ys[:4]))
+        plan.close()
     for f in facs:
         f.close()
     return {"instances": len(work), "points": int(sum(w["N"] for w in work)),
             "rank_max_range": [int(min(ranks)), int(max(ranks))],
             "construct_ms_one_by_one": seq_con, "construct_ms_batched": bat_con,
-            "apply_ms_one_by_one": seq_app, "apply_ms_batched": bat_app,
+            "apply_ms_one_by_one": seq_app, "apply_ms_batched": bat_app, "apply_ms_graph": graph_app,
             "construct_speedup": seq_con / bat_con, "apply_speedup": seq_app / bat_app,
             "outputs_identical": bool(same)}
 
@@ -359,7 +365,9 @@ def main() -> int:
     del XM, YM
     torch.cuda.empty_cache()
     if not args.no_batched:
-        out["batched"] = _batched(B, torch, dev, stream)
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            out["batched"] = _batched(B, torch, dev, side)
     if not args.no_learned:
         out["learned"] = _learned(B, torch, dev, stream)
     if not args.no_cpu_baseline:

@@ -159,6 +159,21 @@ idbf_status idbf_construct_batched(int32_t count, const idbf_phase* phases, cons
 idbf_status idbf_apply_batched(int32_t count, const idbf_handle* hs, const void* const* x, void* const* y,
                                const int64_t* nrhs, int32_t dtype, void* stream);
 
+/*
+ * Captured batched apply: idbf_apply_batched_plan records the launches of one
+ * idbf_apply_batched call (same arguments; `stream` must be a created,
+ * non-null stream) into a HIP graph instead of running them; idbf_plan_launch
+ * replays that graph on any stream, with no host work per kernel.  The plan
+ * keeps the device pointers it was built with: x, y and every handle must
+ * stay alive and unchanged until idbf_plan_destroy.  Workspaces are grown
+ * before the capture; profiling is suspended while capturing.
+ */
+typedef struct idbf_plan_s* idbf_plan;
+idbf_status idbf_apply_batched_plan(int32_t count, const idbf_handle* hs, const void* const* x, void* const* y,
+                                    const int64_t* nrhs, int32_t dtype, void* stream, idbf_plan* out);
+idbf_status idbf_plan_launch(idbf_plan p, void* stream);
+idbf_status idbf_plan_destroy(idbf_plan p);
+
 /* Grow the handle's apply workspace (hipMalloc) so that idbf_apply with up to
  * nrhs right-hand sides of dtype allocates nothing.  Synchronizes the device
  * if it allocates. */

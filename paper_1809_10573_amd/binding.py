@@ -30,7 +30,7 @@ EXPORTED = [
     "idbf_middle_export", "idbf_sample", "idbf_id_batch", "idbf_profile_read", "idbf_reserve",
     "idbf_construct_batched", "idbf_apply_batched", "idbf_mlp_param_count", "idbf_mlp_create",
     "idbf_mlp_destroy", "idbf_mlp_params", "idbf_mlp_forward", "idbf_mlp_loss_grad", "idbf_mlp_train",
-    "idbf_rank_samples",
+    "idbf_rank_samples", "idbf_apply_batched_plan", "idbf_plan_launch", "idbf_plan_destroy",
 ]
 MLP_INPUTS = 8
 FLAG_PROFILE = 1
@@ -119,6 +119,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_mlp_loss_grad.argtypes = [VP, VP, VP, I64, VP, P(F32), VP]
     lib.idbf_mlp_train.argtypes = [VP, VP, VP, I64, I32, I32, F32, C.c_uint64, VP, VP]
     lib.idbf_rank_samples.argtypes = [VP, I32, I32, VP, VP]
+    lib.idbf_apply_batched_plan.argtypes = [I32, P(VP), P(VP), P(VP), P(I64), I32, VP, P(VP)]
+    lib.idbf_plan_launch.argtypes = [VP, VP]
+    lib.idbf_plan_destroy.argtypes = [VP]
     for name in EXPORTED:
         if name not in ("idbf_opts_default", "idbf_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -319,6 +322,38 @@ def apply_batched(facs, xs, ys=None, dtype: int | None = None, stream=None) -> l
     nr = (C.c_int64 * n)(*[1 if x.dim() == 1 else x.shape[1] for x in xs])
     _check(load().idbf_apply_batched(n, hs, xp, yp, nr, int(dtype), _stream(stream)))
     return ys
+
+
+class ApplyPlan:
+    """A batched apply captured once into a HIP graph (idbf_apply_batched_plan);
+    launch() replays it.  The factorizations and tensors must outlive the plan."""
+
+    def __init__(self, facs, xs, ys, dtype: int | None = None, stream=None):
+        import torch
+        n = len(facs)
+        if dtype is None:
+            dtype = C128 if xs[0].dtype == torch.complex128 else C64
+        self._keep = (list(facs), list(xs), list(ys))
+        hs = (C.c_void_p * n)(*[f._h.value for f in facs])
+        xp = (C.c_void_p * n)(*[_ptr(x) for x in xs])
+        yp = (C.c_void_p * n)(*[_ptr(y) for y in ys])
+        nr = (C.c_int64 * n)(*[1 if x.dim() == 1 else x.shape[1] for x in xs])
+        self._h = C.c_void_p()
+        _check(load().idbf_apply_batched_plan(n, hs, xp, yp, nr, int(dtype), _stream(stream), C.byref(self._h)))
+
+    def launch(self, stream=None) -> None:
+        _check(load().idbf_plan_launch(self._h, _stream(stream)))
+
+    def close(self) -> None:
+        if self._h:
+            _check(load().idbf_plan_destroy(self._h))
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def mlp_init(hidden: int, seed: int) -> np.ndarray:

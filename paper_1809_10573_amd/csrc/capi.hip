@@ -220,6 +220,15 @@ struct LevelJob {
 
 using namespace idbf;
 
+struct idbf_plan_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~idbf_plan_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
 struct idbf_mlp_s {
   int hidden = 0;
   int np = 0;
@@ -1135,6 +1144,98 @@ idbf_status idbf_apply_batched(int32_t count, const idbf_handle* hs, const void*
   }
   idbf_status sj = join_streams(streams, caller);  // joined even after a failure
   return st != IDBF_OK ? st : sj;
+}
+
+idbf_status idbf_apply_batched_plan(int32_t count, const idbf_handle* hs, const void* const* x, void* const* y,
+                                    const int64_t* nrhs, int32_t dtype, void* stream, idbf_plan* out) {
+  g_err[0] = 0;
+  if (!out) {
+    set_error("apply_batched_plan: out is NULL");
+    return IDBF_EINVAL;
+  }
+  *out = nullptr;
+  if (count < 1 || !hs || !x || !y || !nrhs) {
+    set_error("apply_batched_plan: count must be >= 1 and every array non-NULL");
+    return IDBF_EINVAL;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!st) {
+    set_error("apply_batched_plan: a non-null stream is needed for capture");
+    return IDBF_EINVAL;
+  }
+  // workspaces grow outside the capture (allocation is not capturable)
+  const size_t elem = dtype == IDBF_C128 ? 16 : 8;
+  for (int i = 0; i < count; ++i) {
+    if (!hs[i] || nrhs[i] < 0) {
+      set_error("apply_batched_plan: instance %d: NULL handle or negative nrhs", i);
+      return IDBF_EINVAL;
+    }
+    idbf_status s = grow_workspace(hs[i], 2 * size_t(hs[i]->max_skel) * size_t(nrhs[i]) * elem, st);
+    if (s != IDBF_OK) {
+      prefix_error(i);
+      return s;
+    }
+  }
+  std::vector<hipStream_t> pool;
+  TRY(pool_streams(&pool));  // created before the capture begins
+  std::vector<bool> prof(count);
+  for (int i = 0; i < count; ++i) {  // no event records inside the graph
+    prof[i] = hs[i]->prof.on;
+    hs[i]->prof.on = false;
+  }
+  std::unique_ptr<idbf_plan_s> plan(new (std::nothrow) idbf_plan_s());
+  idbf_status s = IDBF_OK;
+  if (!plan) {
+    set_error("host allocation failed");
+    s = IDBF_ENOMEM;
+  }
+  if (s == IDBF_OK) {
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("apply_batched_plan: hipStreamBeginCapture: %s", hipGetErrorString(e));
+      s = IDBF_EHIP;
+    } else {
+      s = idbf_apply_batched(count, hs, x, y, nrhs, dtype, stream);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(st, &g);
+      plan->graph = g;
+      if (s == IDBF_OK && e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("apply_batched_plan: hipStreamEndCapture: %s", hipGetErrorString(e));
+        s = IDBF_EHIP;
+      }
+      if (s == IDBF_OK) {
+        e = hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          set_error("apply_batched_plan: hipGraphInstantiate: %s", hipGetErrorString(e));
+          s = IDBF_EHIP;
+        }
+      }
+    }
+  }
+  for (int i = 0; i < count; ++i) hs[i]->prof.on = prof[i];
+  if (s != IDBF_OK) return s;
+  *out = plan.release();
+  return IDBF_OK;
+}
+
+idbf_status idbf_plan_launch(idbf_plan p, void* stream) {
+  g_err[0] = 0;
+  if (!p || !p->exec) {
+    set_error("plan_launch: invalid plan");
+    return IDBF_EINVAL;
+  }
+  IDBF_HIP_CHECK(hipGraphLaunch(p->exec, static_cast<hipStream_t>(stream)));
+  return IDBF_OK;
+}
+
+idbf_status idbf_plan_destroy(idbf_plan p) {
+  if (!p) return IDBF_OK;
+  (void)hipDeviceSynchronize();
+  delete p;
+  return IDBF_OK;
 }
 
 idbf_status idbf_reserve(idbf_handle h, int64_t nrhs, int32_t dtype) {
