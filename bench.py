@@ -208,6 +208,59 @@ def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6) -> dict:
             "err_rows_plain_max": max(res["err_plain"]), "err_rows_proposed_max": max(res["err_proposed"])}
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "id_qr_fio_n2p20_counters.md")
+QR_SOURCES = [os.path.join(ROOT, "paper_1809_10573_amd", "csrc", f) for f in ("id_batch.hip", "common.hpp",
+                                                                          "kernels.hpp")]
+
+
+def qr_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in QR_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _qr_traffic() -> float | None:
+    """HBM bytes per step of the QR kernels from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    try:
+        lines = open(COUNTERS).read().splitlines()
+    except OSError:
+        return None
+    kv = dict(l.split("=", 1) for l in lines if l.startswith(("traffic_bytes_per_step=", "source_sha256=")))
+    if kv.get("source_sha256", "").strip() != qr_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_step"])
+
+
+def _only(what: str) -> int:
+    """Single pieces of the step for counter runs: the workload's construction
+    (twice), or a plain 1 GiB device copy (three times) for calibration."""
+    import torch
+    from paper_1809_10573_amd import binding as B
+    dev = torch.device("cuda:0")
+    if what == "copy":
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("copy: 3 x 1 GiB", flush=True)
+        return 0
+    W = WORKLOAD
+    ph = I.fio_phase(W["a"], W["freq"], W["c0"], W["cdiv"])
+    Xh, Oh = I.uniform_grid(W["N"])
+    X, O = torch.as_tensor(Xh, device=dev), torch.as_tensor(Oh, device=dev)
+    for i in range(2):
+        fac = B.construct(ph, X, O, W["tol"], W["leaf"], oversample=W["oversample"], device=dev)
+        torch.cuda.synchronize()
+        print(f"construct {i}: id_flops {fac.info()['id_flops']:.6g}", flush=True)
+        fac.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,7 +270,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-instance measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
+    ap.add_argument("--only", choices=["construct", "copy"], help="run one piece for a counter pass")
     args = ap.parse_args()
+    if args.only:
+        return _only(args.only)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only; the multi-GPU layout is described "
               "in DESIGN.md and not run", file=sys.stderr)
@@ -309,7 +365,7 @@ def main() -> int:
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = _qr_traffic() if dom_name == "id_qr" else None
     roof["kernel"] = dom_name
     roof["launches_per_step"] = dom["launches"] / len(recs)
 
