@@ -144,6 +144,41 @@ def _batched(B, torch, dev, stream) -> dict:
             "outputs_identical": bool(same)}
 
 
+def _ablation(B, torch, dev, stream) -> dict:
+    """The paper's own ablations on the FIO kernel at N = 2^16 (leaf 16): the
+    sampler (Mock-Chebyshev vs uniformly random, t = 1 and 2, tol 1e-6) and
+    the fixed truncation rank (tol, k) in {(1e-15, 30), (1e-6, 30)}; epsilon^a
+    on 256 exact rows, construction wall time and stored entries.  Measured once."""
+    N, leaf = 1 << 16, 16
+    ph = I.fio_phase(1.0, 1.0)
+    Xh, Oh = I.uniform_grid(N)
+    X, O = torch.as_tensor(Xh, device=dev), torch.as_tensor(Oh, device=dev)
+    g = torch.as_tensor(I.gaussian_vectors(N, None, 3), device=dev)
+    rows = torch.as_tensor(np.sort(np.random.default_rng(2).choice(N, 256, replace=False)), dtype=torch.int32,
+                           device=dev)
+    ex = B.sample(ph, X, O, rows, torch.arange(N, dtype=torch.int32, device=dev), device=dev) @ g
+    variants = {
+        "mockcheb_t1": dict(tol=1e-6, oversample=1), "mockcheb_t2": dict(tol=1e-6, oversample=2),
+        "random_t1": dict(tol=1e-6, oversample=1, sampler=B.SAMPLER_RANDOM, seed=1),
+        "random_t2": dict(tol=1e-6, oversample=2, sampler=B.SAMPLER_RANDOM, seed=1),
+        "fixed_k30_tol1e-15": dict(tol=1e-15, kmax=30, oversample=1),
+        "fixed_k30_tol1e-6": dict(tol=1e-6, kmax=30, oversample=1),
+    }
+    out = {}
+    for name, kw in variants.items():
+        tol = kw.pop("tol")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac = B.construct(ph, X, O, tol, leaf, device=dev, stream=stream, **kw)
+        ms = (time.perf_counter() - t0) * 1e3
+        y = fac.apply(g)
+        info = fac.info()
+        out[name] = {"eps_a": float(torch.linalg.norm(y[rows.long()] - ex) / torch.linalg.norm(ex)),
+                     "construct_ms": ms, "nnz": int(info["nnz_T"] + info["nnz_S"]), "rank_max": info["rank_max"]}
+        fac.close()
+    return out
+
+
 def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6) -> dict:
     """The learned rank proposal on the FIO family c(x) = (2 + a sin 2 pi m x)/8
     at N = 2^18 (leaf 16, tol 1e-6, t = 2): the network is trained on the GPU
@@ -270,6 +305,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-instance measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the sampler / fixed-rank ablation")
     ap.add_argument("--only", choices=["construct", "copy"], help="run one piece for a counter pass")
     args = ap.parse_args()
     if args.only:
@@ -426,6 +462,8 @@ def main() -> int:
             out["batched"] = _batched(B, torch, dev, side)
     if not args.no_learned:
         out["learned"] = _learned(B, torch, dev, stream)
+    if not args.no_ablation:
+        out["ablation"] = _ablation(B, torch, dev, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline()
     print(json.dumps(out), flush=True)

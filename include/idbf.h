@@ -67,18 +67,23 @@ typedef struct idbf_phase {
 
 enum { IDBF_FLAG_PROFILE = 1 }; /* record per-launch device times (idbf_profile_read) */
 
+enum { IDBF_SAMPLER_MOCKCHEB = 0, IDBF_SAMPLER_RANDOM = 1 };
+
 typedef struct idbf_opts {
   int32_t kmax;        /* rank parameter k of the (eps, k)-ID (Section 2.1); 0: k = min(s, c) */
   int32_t oversample;  /* oversampling parameter t >= 1: s = min(t |cand|, |allowed|, 128) samples */
   int32_t flags;       /* IDBF_FLAG_* */
-  int32_t reserved1;
+  int32_t sampler;     /* IDBF_SAMPLER_MOCKCHEB (Section 2.1, default) or IDBF_SAMPLER_RANDOM:
+                          uniform distinct positions (Floyd's algorithm on SplitMix64 draws from
+                          seed, level, side, ID), the comparison sampler of Section 3 */
   uint64_t mem_cap_bytes; /* cap on device memory a handle may allocate; 0: none */
   void* stream;        /* hipStream_t used by idbf_construct */
   /* Learned rank proposal (not in the paper), or NULL: every ID first samples
    * s' = min(s, t (ceil(k^) + proposal_margin)) points, k^ the network's rank
    * estimate; a randomized residual test on 8 fresh allowed points accepts it
    * (||A(r,red) - A(r,skel) T||_F <= 10 tol ||A(r,cand)||_F) or the plain ID
-   * of s samples replaces it.  seed drives the test points (SplitMix64). */
+   * of s samples replaces it.  seed drives the test points and the random
+   * sampler (SplitMix64). */
   struct idbf_mlp_s* proposer;
   int32_t proposal_margin;
   int32_t reserved2;

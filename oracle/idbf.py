@@ -56,7 +56,7 @@ import numpy as np
 
 from .interp import column_id
 from .kernel import entries
-from .sampling import mock_chebyshev
+from .sampling import mock_chebyshev, random_positions
 
 # Largest sample count of one ID (a reading: the paper gives no cap; with
 # t <= 2 it binds only for candidate sets above 64 points).
@@ -121,18 +121,26 @@ def sample_count(c: int, n_allowed: int, oversample: int, smax: int = SAMPLE_CAP
     return s if smax <= 0 else min(s, smax)
 
 
-def _samples(coords_of_allowed, allowed, c, oversample, sample_all, smax):
+def _samples(coords_of_allowed, allowed, c, oversample, sample_all, smax, sampler="mockcheb", key=None):
     s = len(allowed) if sample_all else sample_count(c, len(allowed), oversample, smax)
+    if sampler == "random":
+        seed, level, side, q = key
+        return allowed[random_positions(seed, level, side, q, len(allowed), s)]
     return allowed[mock_chebyshev(coords_of_allowed, s)]
 
 
 def build(phase, X, Omega, leaf: int, tol: float, kmax: int = 0, oversample: int = 1,
-          sample_all: bool = False, smax: int = SAMPLE_CAP) -> Factors:
+          sample_all: bool = False, smax: int = SAMPLE_CAP, sampler: str = "mockcheb",
+          seed: int = 0) -> Factors:
     """Construct the IDBF of K(X, Omega) level by level (Sections 2.2-2.4).
 
     oversample is the parameter t of Section 2.1: s = min(t |cand|, |allowed|,
-    smax) samples per ID (smax <= 0: no cap).
+    smax) samples per ID (smax <= 0: no cap).  sampler "mockcheb" (default)
+    or "random" (uniform, sampling.random_positions with this seed; the ID of
+    node n and partner p at level t is q = p 2^(L-t+1) + n, side 0 = U, 1 = V).
     """
+    if sampler not in ("mockcheb", "random"):
+        raise ValueError("sampler must be 'mockcheb' or 'random'")
     if oversample < 1:
         raise ValueError("oversample must be >= 1")
     X = np.asarray(X, dtype=np.float64)
@@ -162,7 +170,8 @@ def build(phase, X, Omega, leaf: int, tol: float, kmax: int = 0, oversample: int
                     Vp = F.V[t - 1]
                     allowed = np.concatenate([Vp[(cc, r >> sh)].skel
                                               for cc in range(p << sh, (p + 1) << sh)])
-                samp = _samples(Omega[allowed], allowed, len(cand), oversample, sample_all, smax)
+                samp = _samples(Omega[allowed], allowed, len(cand), oversample, sample_all, smax, sampler,
+                                (seed, t, 0, p * nn + r))
                 B = entries(phase, X, Omega, cand, samp).T          # s x c
                 U[(r, p)] = _interp(B, tol, kmax, cand)
         F.U[t] = U
@@ -178,7 +187,8 @@ def build(phase, X, Omega, leaf: int, tol: float, kmax: int = 0, oversample: int
                 sh = L - 2 * t + 1
                 allowed = np.concatenate([U[(rr, cnode >> sh)].skel
                                           for rr in range(p << sh, (p + 1) << sh)])
-                samp = _samples(X[allowed], allowed, len(cand), oversample, sample_all, smax)
+                samp = _samples(X[allowed], allowed, len(cand), oversample, sample_all, smax, sampler,
+                                (seed, t, 1, p * nn + cnode))
                 B = entries(phase, X, Omega, samp, cand)            # s x c
                 V[(cnode, p)] = _interp(B, tol, kmax, cand)
         F.V[t] = V

@@ -21,12 +21,22 @@ closest to Chebyshev-Lobatto points):
 Parity unpinned: beyond hand-worked cases there is nothing in the paper to
 check this rule against; only the end-to-end error of the factorization
 pins it.
+
+``random_positions`` is the uniformly random alternative the paper compares
+Mock-Chebyshev against (Section 3): s distinct positions of n by Floyd's
+algorithm (for j = n-s .. n-1: draw t uniform in [0, j]; take t, or j when t
+was taken already), each draw from SplitMix64 of a counter built from
+(seed, level, side, ID, draw), returned ascending.
 """
 from __future__ import annotations
 
 import math
 
 import numpy as np
+
+from .mlp import MASK64, splitmix64
+
+SAMPLER_SALT = 0xA0761D6478BD642F  # keeps the sampler's counters apart from other draws
 
 _EXACT = {(0, 1): 0.0, (1, 3): 0.25, (1, 2): 0.5, (2, 3): 0.75, (1, 1): 1.0}
 
@@ -59,3 +69,18 @@ def mock_chebyshev(coords, s: int) -> np.ndarray:
         used[p] = True
         picks.append(p)
     return np.sort(np.array(picks, dtype=np.int64))
+
+
+def random_positions(seed: int, level: int, side: int, q: int, n: int, s: int) -> np.ndarray:
+    """Ascending positions of s uniformly random distinct points among n
+    (Floyd's algorithm, SplitMix64 draws)."""
+    if s >= n:
+        return np.arange(n)
+    base = ((seed & 0xFFFFFFFF) << 32) ^ (level << 24) ^ (side << 23) ^ q
+    chosen = []
+    for i in range(s):
+        j = n - s + i
+        z = splitmix64((((base << 8) | i) ^ SAMPLER_SALT) & MASK64)
+        t = ((z >> 32) * (j + 1)) >> 32          # uniform in [0, j]
+        chosen.append(j if t in chosen else t)
+    return np.sort(np.array(chosen, dtype=np.int64))

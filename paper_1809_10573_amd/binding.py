@@ -34,6 +34,7 @@ EXPORTED = [
 ]
 MLP_INPUTS = 8
 FLAG_PROFILE = 1
+SAMPLER_MOCKCHEB, SAMPLER_RANDOM = 0, 1
 MAX_CAND, MAX_RANK, MAX_SAMPLES, SLOT = 128, 64, 128, 4096  # limits of include/idbf.h
 
 
@@ -57,7 +58,7 @@ class Phase_t(C.Structure):
 
 class Opts_t(C.Structure):
     _fields_ = [("kmax", C.c_int32), ("oversample", C.c_int32), ("flags", C.c_int32),
-                ("reserved1", C.c_int32), ("mem_cap_bytes", C.c_uint64), ("stream", C.c_void_p),
+                ("sampler", C.c_int32), ("mem_cap_bytes", C.c_uint64), ("stream", C.c_void_p),
                 ("proposer", C.c_void_p), ("proposal_margin", C.c_int32), ("reserved2", C.c_int32),
                 ("seed", C.c_uint64)]
 
@@ -251,7 +252,8 @@ class Factorization:
 
 def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample: int = 1,
               mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
-              stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0) -> Factorization:
+              stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0,
+              sampler: int = SAMPLER_MOCKCHEB) -> Factorization:
     """idbf_construct on device copies of X and Omega (float64, ascending)."""
     lib = load()
     Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
@@ -262,8 +264,9 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
     opts.kmax, opts.oversample, opts.mem_cap_bytes = kmax, oversample, mem_cap_bytes
     opts.flags = FLAG_PROFILE if profile else 0
     opts.stream = _stream(stream)
+    opts.sampler, opts.seed = int(sampler), int(seed)
     if proposer is not None:
-        opts.proposer, opts.proposal_margin, opts.seed = proposer._h.value, int(proposal_margin), int(seed)
+        opts.proposer, opts.proposal_margin = proposer._h.value, int(proposal_margin)
     ph = _phase(phase)
     h = C.c_void_p()
     _check(lib.idbf_construct(C.byref(ph), _ptr(Xd), _ptr(Od), Xd.numel(), float(tol), int(leaf),
@@ -273,7 +276,8 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
 
 def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample: int = 1,
                       mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
-                      stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0) -> list:
+                      stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0,
+                      sampler: int = SAMPLER_MOCKCHEB) -> list:
     """idbf_construct_batched: one lockstep construction of len(phases) instances."""
     lib = load()
     n = len(phases)
@@ -289,8 +293,9 @@ def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample
     opts.kmax, opts.oversample, opts.mem_cap_bytes = kmax, oversample, mem_cap_bytes
     opts.flags = FLAG_PROFILE if profile else 0
     opts.stream = _stream(stream)
+    opts.sampler, opts.seed = int(sampler), int(seed)
     if proposer is not None:
-        opts.proposer, opts.proposal_margin, opts.seed = proposer._h.value, int(proposal_margin), int(seed)
+        opts.proposer, opts.proposal_margin = proposer._h.value, int(proposal_margin)
     ph = (Phase_t * n)(*[_phase(p) for p in phases])
     xp = (C.c_void_p * n)(*[_ptr(x) for x in Xd])
     op = (C.c_void_p * n)(*[_ptr(o) for o in Od])

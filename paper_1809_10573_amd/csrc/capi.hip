@@ -272,6 +272,7 @@ struct idbf_handle_s {
   LevelJob job;                // the level batch being built
   int qr_rec = -1;             // profiler record of that batch's QR launches
   idbf_mlp_s* proposer = nullptr;  // rank proposal network (not owned), or null
+  int sampler = IDBF_SAMPLER_MOCKCHEB;
   int margin = 0;
   uint64_t seed = 0;
 
@@ -423,6 +424,9 @@ idbf_status level_ids(idbf_handle_s* h) {
   ia.oversample = h->oversample;
   ia.s_max = b.s_max;
   ia.c_max = b.cand_max;
+  ia.sampler = h->sampler;
+  ia.level = t;
+  ia.seed = h->seed;
   ia.samp_pos = h->samp_pos;
   ia.order = h->order;
   ia.bucket_off[0] = 0;
@@ -813,6 +817,11 @@ idbf_status make_handle(const idbf_phase* phase, const double* X, const double* 
   h->proposer = o.proposer;
   h->margin = o.proposal_margin;
   h->seed = o.seed;
+  if (o.sampler != IDBF_SAMPLER_MOCKCHEB && o.sampler != IDBF_SAMPLER_RANDOM) {
+    set_error("opts: unknown sampler %d", o.sampler);
+    return IDBF_EINVAL;
+  }
+  h->sampler = o.sampler;
   if (h->proposer && o.proposal_margin < 0) {
     set_error("opts: proposal_margin must be >= 0");
     return IDBF_EINVAL;

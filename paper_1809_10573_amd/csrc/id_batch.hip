@@ -27,6 +27,7 @@ namespace idbf {
 namespace {
 
 constexpr int kSelIds = 4;  // IDs (wavefronts) per selection workgroup
+constexpr uint64_t kSamplerSalt = 0xA0761D6478BD642Full;  // keeps sampler counters apart from other draws
 
 __device__ double cheb_fraction(int j, int s) {
   if (s == 1) return 0.5;
@@ -150,6 +151,37 @@ __global__ __launch_bounds__(64 * kSelIds) void select_kernel(IdArgs A) {
   int32_t* out = A.samp_pos + q * (int64_t)kMaxSamples;
   if (s >= na) {
     for (int j = lane; j < na; j += kWave) out[j] = j;
+    return;
+  }
+  if (A.sampler == IDBF_SAMPLER_RANDOM) {
+    // Floyd's algorithm: for j = na-s .. na-1 draw t uniform in [0, j] (SplitMix64
+    // of a counter from seed, level, side, ID, draw); take t, or j if t is taken
+    if (lane == 0) {
+      const uint64_t base = ((A.seed & 0xffffffffull) << 32) ^ ((uint64_t)A.level << 24) ^
+                            ((uint64_t)A.side << 23) ^ (uint64_t)q;
+      for (int i = 0; i < s; ++i) {
+        const int64_t j = (int64_t)na - s + i;
+        uint64_t z = (((base << 8) | (uint64_t)i) ^ kSamplerSalt) + 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        int t = (int)(((z >> 32) * (uint64_t)(j + 1)) >> 32);
+        for (int e = 0; e < i; ++e)
+          if (s_pos[w][e] == t) {
+            t = (int)j;
+            break;
+          }
+        s_pos[w][i] = t;
+      }
+    }
+    wave_lds_sync();
+    // ascending: each chosen position goes to its rank (positions are distinct)
+    for (int e = lane; e < s; e += kWave) {
+      const int v = s_pos[w][e];
+      int rank = 0;
+      for (int f = 0; f < s; ++f) rank += s_pos[w][f] < v;
+      out[rank] = v;
+    }
     return;
   }
   const bool isV = (A.side == IDBF_SIDE_V);

@@ -43,6 +43,9 @@ struct IdArgs {
   int s_max;                  // largest sample count of the batch (sizes the launch)
   int c_max;                  // largest candidate count of the batch (sizes the launch)
   const int32_t* samples;     // per-ID sample counts, or null: s = min(t c, |allowed|, kMaxSamples)
+  int sampler;                // IDBF_SAMPLER_MOCKCHEB or IDBF_SAMPLER_RANDOM
+  int level;                  // level t of the batch (random sampler counters)
+  uint64_t seed;              // random sampler seed
   const int32_t* sel_list;    // selection: the IDs to process (sel_n of them), or null: all n_ids
   int64_t sel_n;
   int32_t* samp_pos;          // kMaxSamples sample positions per ID (scratch)

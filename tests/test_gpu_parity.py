@@ -136,7 +136,7 @@ def test_id_batch_rejects_oversized():
 
 
 # ------------------------------------------------------------------ construction
-def _compare_construction(F, fac, ph, X, O):
+def _compare_construction(F, fac, ph, X, O, t_bound=1e-12):
     """Level-by-level comparison of GPU factors with the oracle's.
 
     Skeletons must agree exactly.  T = R11^{-1} R12 may differ by the sampled
@@ -162,7 +162,8 @@ def _compare_construction(F, fac, ph, X, O):
                 Tg = flat.reshape(r, k).T if side == B.SIDE_V else flat.reshape(k, r)
                 scale = max(1.0, np.abs(rec.T).max(initial=0.0))
                 kappa = rec.rdiag[0] / rec.rdiag[-1]
-                assert np.max(np.abs(Tg - rec.T), initial=0.0) <= 1e-12 * kappa * scale
+                if t_bound is not None:
+                    assert np.max(np.abs(Tg - rec.T), initial=0.0) <= t_bound * kappa * scale
     return mismatched
 
 
@@ -266,6 +267,36 @@ def test_wide_ranks_construct_and_every_apply_path():
     assert oracle.relative_error(fac.apply(x64, dtype=B.C64_BF16X3).cpu().numpy(), Y_or) < 2e-4
     y_ex = oracle.dense_matvec(ph, X, O, G[:, 0])
     assert oracle.relative_error(fac.apply(x[:, 0].contiguous()).cpu().numpy(), y_ex) < 100 * tol
+
+
+@pytest.mark.parametrize("N,leaf,kind,t,seed", [(1024, 16, "fio", 2, 5), (1024, 8, "dft", 1, 9),
+                                                  (2048, 16, "fio", 1, 3)])
+def test_random_sampler_matches_oracle(N, leaf, kind, t, seed):
+    """The uniformly random sampler (Section 3's comparison): the same SplitMix64
+    draws on both sides give identical sample sets.  At t = 2 the skeletons
+    are then identical.  At t = 1 (as many random rows as candidates) R11 is
+    so ill-conditioned that the eps-rank decision of a few IDs sits within
+    rounding of the threshold and may differ (with its knock-on effects one
+    level up), so up to 1% of the IDs may differ and both factorizations are
+    held to the exact product instead.  T is held to the apply's agreement,
+    not to the Mock-Chebyshev entry bound, for the same conditioning reason."""
+    ph = I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    tol = 1e-6
+    F = oracle.build(ph, X, O, leaf, tol, oversample=t, sampler="random", seed=seed)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=t, device=DEV, sampler=B.SAMPLER_RANDOM, seed=seed)
+    mismatched = _compare_construction(F, fac, ph, X, O, t_bound=None)
+    n_ids = fac.info()["n_ids"]
+    g = I.gaussian_vectors(N, None, seed=2)
+    y = fac.apply(torch.as_tensor(g, device=DEV)).cpu().numpy()
+    y_or = oracle.apply(F, g)
+    if t == 2:
+        assert mismatched == 0
+        assert oracle.relative_error(y, y_or) < 1e-6
+    else:
+        assert mismatched <= max(1, n_ids // 100), (mismatched, n_ids)
+        y_ex = oracle.dft_closed_form(g) if kind == "dft" else oracle.dense_matvec(ph, X, O, g)
+        assert oracle.relative_error(y, y_ex) <= 2 * oracle.relative_error(y_or, y_ex) + 1e-12
 
 
 def test_construct_errors():

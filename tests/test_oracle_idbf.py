@@ -143,3 +143,17 @@ def test_bad_sizes_rejected():
         oracle.tree_sizes(64, 3)
     with pytest.raises(ValueError):
         oracle.tree_sizes(8, 16)
+
+
+def test_mock_chebyshev_beats_random_sampling():
+    """Section 3: Mock-Chebyshev samples give a far more accurate factorization
+    than uniformly random ones at the same sample count."""
+    N = 512
+    ph = I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    g = I.gaussian_vectors(N, None, 1)
+    ex = oracle.dense_matvec(ph, X, O, g)
+    err = {s: oracle.relative_error(oracle.apply(oracle.build(ph, X, O, 16, 1e-6, oversample=2, sampler=s,
+                                                              seed=5), g), ex)
+           for s in ("mockcheb", "random")}
+    assert err["random"] > 10 * err["mockcheb"], err

@@ -43,3 +43,23 @@ def test_selection_is_distinct_sorted_and_endpoint_anchored():
         assert np.all(np.diff(p) > 0)
         if 2 <= s < n:
             assert p[0] == 0 and p[-1] == n - 1
+
+
+def test_random_positions_are_distinct_sorted_and_deterministic():
+    from oracle.sampling import random_positions
+    for (n, s) in [(10, 3), (128, 127), (1000, 128), (5, 5), (7, 9)]:
+        p = random_positions(11, 2, 1, 17, n, s)
+        assert len(p) == min(n, s) and len(np.unique(p)) == len(p)
+        assert np.all(np.diff(p) > 0) and p.min() >= 0 and p.max() < n
+        assert np.array_equal(p, random_positions(11, 2, 1, 17, n, s))
+    assert not np.array_equal(random_positions(11, 2, 1, 17, 1000, 10), random_positions(11, 2, 1, 18, 1000, 10))
+
+
+def test_random_positions_are_uniform_subsets():
+    # Floyd's algorithm draws every s-subset with probability 1 / C(n, s): over
+    # 20000 counters the 10 subsets of 2 out of 5 each appear 2000 +- a few %
+    from oracle.sampling import random_positions
+    from collections import Counter
+    cnt = Counter(tuple(random_positions(3, 1, 0, q, 5, 2)) for q in range(20000))
+    assert len(cnt) == 10
+    assert all(abs(v - 2000) < 200 for v in cnt.values()), cnt
