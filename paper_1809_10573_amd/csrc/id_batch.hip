@@ -15,9 +15,10 @@
 //   column norms and dot products are lane-local.  Per step: residual norms
 //   are recomputed; M = max (DPP reduction); stop when M <= eps |R_00|; the
 //   pivot is the smallest candidate index with norm >= (1 - 1e-8) M (ballot);
-//   the pivot column's Householder vector goes through LDS.  Then
-//   T = R11^{-1} R12 by back-substitution in registers, one redundant
-//   candidate per lane, rows permuted to ascending skeletons.
+//   the pivot column's Householder vector goes through LDS, and only the
+//   wavefront that holds row j applies row masks.  Then T = R11^{-1} R12 by
+//   back-substitution over R rows staged in LDS, one redundant candidate per
+//   thread, rows permuted to ascending skeletons.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -253,7 +254,7 @@ template <int W, int CPL, int R>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) void id_kernel(IdArgs A) {
   constexpr int SMAX = R * W;
   constexpr int NC = kWave * CPL;     // candidate columns covered
-  constexpr int kChunk = 32;          // R rows staged in LDS per back-substitution chunk
+  constexpr int kChunk = 16 / CPL;    // R rows staged in LDS per back-substitution chunk (16 KiB)
   // partial sums of the QR loop and the R rows of the solve share LDS
   constexpr size_t kPart = (size_t)W * CPL * kWave * (sizeof(double) + sizeof(double2));
   constexpr size_t kRrows = (size_t)kChunk * NC * sizeof(double2);
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   __shared__ int s_piv[kMaxRank];
   __shared__ int s_srank[kMaxRank];
   __shared__ double s_axj[2];
-  __shared__ double2 s_alpha;
+  __shared__ double2 s_diag[kMaxRank];  // R_jj of each step
   double* s_part = reinterpret_cast<double*>(s_raw);                                         // [W][CPL][64]
   double2* s_partc = reinterpret_cast<double2*>(s_raw + W * CPL * kWave * sizeof(double));  // [W][CPL][64]
   double2* s_R = reinterpret_cast<double2*>(s_raw);                                          // [kChunk][NC]
@@ -337,12 +338,14 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     double p0 = 0.0, p1 = 0.0;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      if (i & 1) p1 += cabs2(a[cs][i]); else p0 += cabs2(a[cs][i]);
+      if (i & 1) p1 = __builtin_fma(a[cs][i].y, a[cs][i].y, __builtin_fma(a[cs][i].x, a[cs][i].x, p1));
+      else p0 = __builtin_fma(a[cs][i].y, a[cs][i].y, __builtin_fma(a[cs][i].x, a[cs][i].x, p0));
     }
     part[cs] = p0 + p1;
   }
   for (int j = 0;; ++j) {
-    const bool live = row0 + R > j;  // wave-uniform: this wave holds rows >= j
+    const bool live = row0 + R > j;   // wave-uniform: this wave holds rows >= j
+    const bool edge = live && row0 <= j;  // ... and row j itself (rows < j must stay as they are)
     double nrm2[CPL];
 #pragma unroll
     for (int cs = 0; cs < CPL; ++cs) nrm2[cs] = part[cs];
@@ -393,28 +396,40 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     const int p = __builtin_amdgcn_readfirstlane(
         near0 ? __ffsll((unsigned long long)near0) - 1 : kWave + __ffsll((unsigned long long)near1) - 1);
     const int pl = p & (kWave - 1), pc = p / kWave;  // pivot lane and column slot (uniform)
-    // Householder vector of the pivot column (rows >= j): lane pl of every wave
-    // publishes its own rows to the wave's slice of LDS (no workgroup barrier),
-    // zero above row j, so that rows < j drop out of the dot and the update
-    // exactly; v_i = a_i(p) for i > j and v_j = x_j - alpha,
-    // alpha = -(x_j/|x_j|) nu_p, tau = 2 / |v|^2 = 1 / (nu_p (nu_p + |x_j|)).
+    // Householder vector of the pivot column (rows >= j): lane pl of every
+    // live wave publishes its own rows to the wave's slice of LDS (no
+    // workgroup barrier); the wave that holds row j zeroes the rows above it,
+    // so that rows < j drop out of the dot and the update exactly, and forms
+    // the head:
+    //   v_i = a_i(p) for i > j, v_j = x_j - alpha,
+    //   alpha = -(x_j/|x_j|) nu_p, tau = 2 / |v|^2 = 1 / (nu_p (nu_p + |x_j|)).
+    // The pivot column's registers are left as they are: below the diagonal
+    // they are never read again, and R_jj = alpha is kept in LDS.
     const double nup = sqrt(readlane(pc == 0 ? nq[0] : nq[CPL - 1], pl));
     if (lane == pl && live) {
+      if (!edge) {
+        if (pc == 0) {
 #pragma unroll
-      for (int i = 0; i < R; ++i) {
-        const double2 ai = (pc == 0) ? a[0][i] : a[CPL - 1][i];
-        s_v[row0 + i] = (row0 + i >= j) ? ai : make_double2(0.0, 0.0);
-      }
-      if (row0 <= j) {  // this wave holds row j: form the head (same-lane LDS accesses are ordered)
-        const double2 xj = s_v[j];
+          for (int i = 0; i < R; ++i) s_v[row0 + i] = a[0][i];
+        } else {
+#pragma unroll
+          for (int i = 0; i < R; ++i) s_v[row0 + i] = a[CPL - 1][i];
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const double2 ai = (pc == 0) ? a[0][i] : a[CPL - 1][i];
+          s_v[row0 + i] = (row0 + i >= j) ? ai : make_double2(0.0, 0.0);
+        }
+        const double2 xj = s_v[j];  // same-lane LDS accesses are ordered
         const double axj = sqrt(cabs2(xj));
         double2 vj;
         if (axj > 0.0) {
           const double g = nup / axj;  // alpha = -g x_j, v_j = (1 + g) x_j
-          s_alpha = make_double2(-xj.x * g, -xj.y * g);
+          s_diag[j] = make_double2(-xj.x * g, -xj.y * g);
           vj = make_double2(xj.x + xj.x * g, xj.y + xj.y * g);
         } else {
-          s_alpha = make_double2(-nup, 0.0);
+          s_diag[j] = make_double2(-nup, 0.0);
           vj = make_double2(nup, 0.0);
         }
         s_v[j] = vj;
@@ -448,36 +463,32 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       }
     }
     const double tau = 1.0 / (nup * (nup + s_axj[j & 1]));
-    if (live) {
 #pragma unroll
-      for (int cs = 0; cs < CPL; ++cs) {
-        part[cs] = 0.0;
-        if (eligible[cs] && !(lane == pl && cs == pc)) {
-          // update, and the residual norm of rows >= j + 1 for the next step
-          const double2 sdot = make_double2(-tau * dot[cs].x, -tau * dot[cs].y);
-          double p0 = 0.0, p1 = 0.0;
+    for (int cs = 0; cs < CPL; ++cs) {
+      // update, and the residual norm of rows >= j + 1 for the next step (the
+      // wave that holds row j recounts its rows below j)
+      part[cs] = 0.0;
+      if (live && eligible[cs] && !(lane == pl && cs == pc)) {
+        const double2 sdot = make_double2(-tau * dot[cs].x, -tau * dot[cs].y);
+        double p0 = 0.0, p1 = 0.0;
 #pragma unroll
-          for (int i = 0; i < R; ++i) {
-            a[cs][i] = cfma(s_v[row0 + i], sdot, a[cs][i]);
-            const double t = (row0 + i > j) ? cabs2(a[cs][i]) : 0.0;
-            if (i & 1) p1 += t; else p0 += t;
-          }
-          part[cs] = p0 + p1;
+        for (int i = 0; i < R; ++i) {
+          a[cs][i] = cfma(s_v[row0 + i], sdot, a[cs][i]);
+          if (i & 1) p1 = __builtin_fma(a[cs][i].y, a[cs][i].y, __builtin_fma(a[cs][i].x, a[cs][i].x, p1));
+          else p0 = __builtin_fma(a[cs][i].y, a[cs][i].y, __builtin_fma(a[cs][i].x, a[cs][i].x, p0));
         }
+        if (edge) {  // rows <= j of this wave are final: recount without them
+          p0 = 0.0;
+          p1 = 0.0;
+#pragma unroll
+          for (int i = 0; i < R; ++i)
+            if (row0 + i > j) {
+              if (i & 1) p1 = __builtin_fma(a[cs][i].y, a[cs][i].y, __builtin_fma(a[cs][i].x, a[cs][i].x, p1));
+              else p0 = __builtin_fma(a[cs][i].y, a[cs][i].y, __builtin_fma(a[cs][i].x, a[cs][i].x, p0));
+            }
+        }
+        part[cs] = p0 + p1;
       }
-      // the pivot column becomes (alpha, 0, ..., 0) from row j down
-      if (lane == pl) {
-        const double2 alpha = s_alpha;
-#pragma unroll
-        for (int cs = 0; cs < CPL; ++cs)
-          if (cs == pc)
-#pragma unroll
-            for (int i = 0; i < R; ++i)
-              if (row0 + i >= j) a[cs][i] = (row0 + i == j) ? alpha : make_double2(0.0, 0.0);
-      }
-    } else {
-#pragma unroll
-      for (int cs = 0; cs < CPL; ++cs) part[cs] = 0.0;  // no rows >= j + 1 here
     }
     if (lane == pl) {
 #pragma unroll
@@ -551,7 +562,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
           const double2 rl = Ri[s_piv[l]];
           acc = cfma(make_double2(-rl.x, -rl.y), A.T128[t_index(l)], acc);
         }
-        const double2 d = Ri[s_piv[ii]];
+        const double2 d = s_diag[ii];
         const double inv = 1.0 / cabs2(d);
         acc = cmul(acc, make_double2(d.x * inv, -d.y * inv));
       }
