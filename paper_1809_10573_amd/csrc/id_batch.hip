@@ -20,6 +20,7 @@
 //   back-substitution over R rows staged in LDS, one redundant candidate per
 //   thread, rows permuted to ascending skeletons.
 #include <algorithm>
+#include <climits>
 
 #include "kernels.hpp"
 
@@ -218,23 +219,33 @@ __global__ __launch_bounds__(64 * kSelIds) void select_kernel(IdArgs A) {
   }
 }
 
-// DPP max over the 64 lanes of a wavefront: row_shr within rows of 16, then
-// row broadcasts; lane 63 ends with the maximum.
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int l2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false);
-  const int h2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false);
-  return __hiloint2double(h2, l2);
+// Maximum over the 64 lanes of a wavefront of values that are either >= 0 or
+// negative placeholders.  Non-negative doubles order like their bit patterns,
+// so the maximum is taken on the high words (signed, so that placeholders sort
+// below every non-negative value), then on the low words of the lanes that
+// share the largest high word.  Each pass is a DPP max: row_shr within rows of
+// 16, then row broadcasts; lane 63 ends with the maximum.
+template <typename T, int CTRL, int ROWMASK>
+__device__ __forceinline__ T dpp_max(T v, T identity) {
+  const T o = (T)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROWMASK, 0xf, false);
+  return v > o ? v : o;
 }
-__device__ __forceinline__ double wave_max_dpp(double v) {
-  v = fmax(v, dpp_d<0x111, 0xf>(v));  // row_shr:1
-  v = fmax(v, dpp_d<0x112, 0xf>(v));  // row_shr:2
-  v = fmax(v, dpp_d<0x114, 0xf>(v));  // row_shr:4
-  v = fmax(v, dpp_d<0x118, 0xf>(v));  // row_shr:8
-  v = fmax(v, dpp_d<0x142, 0xa>(v));  // row_bcast:15
-  v = fmax(v, dpp_d<0x143, 0xc>(v));  // row_bcast:31
-  return readlane(v, kWave - 1);
+template <typename T>
+__device__ __forceinline__ T wave_max32(T v, T identity) {
+  v = dpp_max<T, 0x111, 0xf>(v, identity);  // row_shr:1
+  v = dpp_max<T, 0x112, 0xf>(v, identity);  // row_shr:2
+  v = dpp_max<T, 0x114, 0xf>(v, identity);  // row_shr:4
+  v = dpp_max<T, 0x118, 0xf>(v, identity);  // row_shr:8
+  v = dpp_max<T, 0x142, 0xa>(v, identity);  // row_bcast:15
+  v = dpp_max<T, 0x143, 0xc>(v, identity);  // row_bcast:31
+  return (T)__builtin_amdgcn_readlane((int)v, kWave - 1);
+}
+__device__ __forceinline__ double wave_max_nonneg(double v) {
+  const int hi = __double2hiint(v);
+  const int mh = wave_max32<int>(hi, INT_MIN);
+  const unsigned lo = (hi == mh) ? (unsigned)__double2loint(v) : 0u;
+  const unsigned ml = wave_max32<unsigned>(lo, 0u);
+  return __hiloint2double(mh, (int)ml);
 }
 
 __device__ __forceinline__ bool skel_bit(uint64_t lo, uint64_t hi, int p) {
@@ -254,7 +265,9 @@ template <int W, int CPL, int R>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) void id_kernel(IdArgs A) {
   constexpr int SMAX = R * W;
   constexpr int NC = kWave * CPL;     // candidate columns covered
-  constexpr int kChunk = 16 / CPL;    // R rows staged in LDS per back-substitution chunk (16 KiB)
+  // R rows staged in LDS per back-substitution chunk: 32 KiB where registers
+  // already limit a CU to four workgroups, else 16 KiB
+  constexpr int kChunk = (W >= 4 ? 32 : 16) / CPL;
   // partial sums of the QR loop and the R rows of the solve share LDS
   constexpr size_t kPart = (size_t)W * CPL * kWave * (sizeof(double) + sizeof(double2));
   constexpr size_t kRrows = (size_t)kChunk * NC * sizeof(double2);
@@ -327,7 +340,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   bool pivoted[CPL];
 #pragma unroll
   for (int cs = 0; cs < CPL; ++cs) pivoted[cs] = false;
-  double r00 = 0.0;
+  double stop2 = 0.0;  // (tol |R_00|)^2
   int k = 0;
   bool zero_block = false, overflow = false;
   // residual column norms of this wave's rows, for step 0; later steps get
@@ -371,15 +384,17 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       nq[cs] = eligible[cs] ? nrm2[cs] : -1.0;
       nqmax = fmax(nqmax, nq[cs]);
     }
-    const double M2 = wave_max_dpp(nqmax);
-    const double M = M2 > 0.0 ? sqrt(M2) : 0.0;
+    // squared maximum residual norm; the stopping test M <= tol |R_00| is
+    // taken on squares
+    const double M2 = wave_max_nonneg(nqmax);
     if (j == 0) {
-      r00 = M;
-      if (M == 0.0) {
+      if (!(M2 > 0.0)) {
         zero_block = true;
         break;
       }
-    } else if (M <= A.tol * r00) {
+      const double b = A.tol * sqrt(M2);
+      stop2 = b * b;
+    } else if (M2 <= stop2) {
       break;
     }
     if (j == kuser) break;
@@ -387,8 +402,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       overflow = true;
       break;
     }
-    const double thr = (1.0 - kPivotTie) * M;
-    const double thr2 = thr * thr;
+    constexpr double kTie2 = (1.0 - kPivotTie) * (1.0 - kPivotTie);
+    const double thr2 = kTie2 * M2;
     const uint64_t near0 = __ballot(eligible[0] && nq[0] >= thr2);
     uint64_t near1 = 0;
     if constexpr (CPL > 1) near1 = __ballot(eligible[CPL - 1] && nq[CPL - 1] >= thr2);
@@ -462,7 +477,11 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         for (int ww = 0; ww < W; ++ww) dot[cs] = cadd(dot[cs], s_partc[(ww * CPL + cs) * kWave + lane]);
       }
     }
-    const double tau = 1.0 / (nup * (nup + s_axj[j & 1]));
+    // tau = 1 / (nu_p (nu_p + |x_j|)): hardware reciprocal and two Newton steps
+    const double den = nup * (nup + s_axj[j & 1]);
+    double tau = __builtin_amdgcn_rcp(den);
+    tau = __builtin_fma(tau, __builtin_fma(-den, tau, 1.0), tau);
+    tau = __builtin_fma(tau, __builtin_fma(-den, tau, 1.0), tau);
 #pragma unroll
     for (int cs = 0; cs < CPL; ++cs) {
       // update, and the residual norm of rows >= j + 1 for the next step (the
