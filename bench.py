@@ -179,6 +179,53 @@ def _ablation(B, torch, dev, stream) -> dict:
     return out
 
 
+def _nufft(B, torch, dev, stream) -> dict:
+    """Example 3, the non-uniform Fourier transform, at the workload's size and
+    settings (N = 2^20, leaf 16, tol 1e-6, t = 2): rows at random frequencies
+    in [-N/2, N/2), columns at random points in [0, 1).  Construction wall
+    time and its ID-kernel time, the complex64 1-RHS apply (stored bytes / time,
+    as the main line), and epsilon^a on 256 exact rows.  Measured once."""
+    N = WORKLOAD["N"]
+    ph = I.dft_phase()
+    Wh, Xh = I.nufft_points(N, seed=1)
+    Wd, Xd = torch.as_tensor(Wh, device=dev), torch.as_tensor(Xh, device=dev)
+    g = torch.as_tensor(I.gaussian_vectors(N, None, 7), device=dev)
+    g64 = g.to(torch.complex64)
+    y64 = torch.empty_like(g64)
+    res = {}
+    for it in range(2):  # the first construction warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac = B.construct(ph, Wd, Xd, WORKLOAD["tol"], WORKLOAD["leaf"], oversample=WORKLOAD["oversample"],
+                          profile=True, device=dev, stream=stream)
+        res["construct_ms"] = (time.perf_counter() - t0) * 1e3
+        res["id_qr_ms"] = fac.profile(reset=True).get("id_qr", {}).get("ms", 0.0)
+        if it == 0:
+            fac.close()
+    info = fac.info()
+    fac.apply(g64, y64, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fac.apply(g64, y64, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    bytes1 = (info["nnz_T"] + info["nnz_S"]) * 8 + 8 * info["n_ids"] + 2 * N * 8
+    y = fac.apply(g)
+    rows = torch.as_tensor(np.sort(np.random.default_rng(3).choice(N, 256, replace=False)), dtype=torch.int32,
+                           device=dev)
+    cols = torch.arange(N, dtype=torch.int32, device=dev)
+    ex = torch.zeros(256, dtype=torch.complex128, device=dev)
+    for c0 in range(0, N, 1 << 16):
+        ex += B.sample(ph, Wd, Xd, rows, cols[c0:c0 + (1 << 16)], device=dev) @ g[c0:c0 + (1 << 16)]
+    eps_a = float(torch.linalg.norm(y[rows.long()] - ex) / torch.linalg.norm(ex))
+    fac.close()
+    return {"N": N, "construct_ms": res["construct_ms"], "id_qr_ms": res["id_qr_ms"], "apply1_ms": ms,
+            "apply1_gbs": bytes1 / ms / 1e6, "eps_a_256rows": eps_a, "nnz": info["nnz_T"] + info["nnz_S"],
+            "rank_min": info["rank_min"], "rank_max": info["rank_max"]}
+
+
 def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6) -> dict:
     """The learned rank proposal on the FIO family c(x) = (2 + a sin 2 pi m x)/8
     at N = 2^18 (leaf 16, tol 1e-6, t = 2): the network is trained on the GPU
@@ -306,6 +353,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the many-instance measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--no-ablation", action="store_true", help="skip the sampler / fixed-rank ablation")
+    ap.add_argument("--no-nufft", action="store_true", help="skip the non-uniform Fourier transform line")
     ap.add_argument("--only", choices=["construct", "copy"], help="run one piece for a counter pass")
     args = ap.parse_args()
     if args.only:
@@ -464,6 +512,8 @@ def main() -> int:
         out["learned"] = _learned(B, torch, dev, stream)
     if not args.no_ablation:
         out["ablation"] = _ablation(B, torch, dev, stream)
+    if not args.no_nufft:
+        out["nufft"] = _nufft(B, torch, dev, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -11,6 +11,8 @@ configurations this project measures:
 
 * uniform grids ``x_i = i/N`` in [0, 1) and ``xi_j = j - N/2`` in
   [-N/2, N/2) (0-based form of the paper's discretisation of Example 1);
+* sorted uniform random points for Example 3 (the non-uniform Fourier
+  transform): frequencies in [-N/2, N/2) and points in [0, 1);
 * phase ``Phi(x, xi) = -x*xi`` (the DFT kernel) or
   ``Phi(x, xi) = x*xi + c(x)|xi|`` with ``c(x) = (c0 + a*sin(2*pi*m*x))/cdiv``
   (the FIO kernel; the paper's own member is c0=2, a=0.2, m=1, cdiv=16);
@@ -59,6 +61,26 @@ def uniform_grid(N: int) -> tuple[np.ndarray, np.ndarray]:
     """x_i = i/N and xi_j = j - N/2, i, j = 0..N-1, as float64 (ascending)."""
     i = np.arange(N, dtype=np.float64)
     return i / N, i - N / 2
+
+
+def nufft_points(N: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Points of Example 3, the 1D non-uniform Fourier transform
+    u_k = sum_n exp(-2 pi i x_n w_k) g_n: row frequencies w_k ~ U[-N/2, N/2)
+    and column points x_n ~ U[0, 1), i.i.d. from ``default_rng(seed)``, each
+    sorted ascending.  A value drawn twice is redrawn, so both arrays are
+    strictly increasing.  With the DFT phase Phi(w, x) = -w x the matrix
+    K(w_k, x_n) is the paper's, rows at the frequencies."""
+    rng = np.random.default_rng(seed)
+
+    def draw(lo: float, hi: float) -> np.ndarray:
+        v = np.unique(lo + (hi - lo) * rng.random(N))
+        while len(v) < N:
+            v = np.unique(np.concatenate([v, lo + (hi - lo) * rng.random(N - len(v))]))
+        return v
+
+    w = draw(-N / 2, N / 2)
+    x = draw(0.0, 1.0)
+    return w, x
 
 
 def gaussian_vectors(N: int, nrhs: int | None, seed: int) -> np.ndarray:

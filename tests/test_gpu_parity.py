@@ -136,6 +136,17 @@ def test_id_batch_rejects_oversized():
 
 
 # ------------------------------------------------------------------ construction
+def _workload(kind, N):
+    """Phase and points: the DFT or FIO kernel on the uniform grid, or Example
+    3's non-uniform Fourier transform (DFT phase, rows at random frequencies,
+    columns at random points)."""
+    if kind == "nufft":
+        W, Xp = I.nufft_points(N, seed=N + 1)
+        return I.dft_phase(), W, Xp
+    X, O = I.uniform_grid(N)
+    return (I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 1.0)), X, O
+
+
 def _compare_construction(F, fac, ph, X, O, t_bound=1e-12):
     """Level-by-level comparison of GPU factors with the oracle's.
 
@@ -174,10 +185,11 @@ def _compare_construction(F, fac, ph, X, O, t_bound=1e-12):
     (256, 2, "fio", 1e-8, 1),       # L = 7 with leaf 2
     (2048, 16, "fio", 1e-6, 2),     # the FIO workload's shape at a small N
     (1024, 4, "fio", 1e-4, 1),
+    (2048, 16, "nufft", 1e-6, 2),   # Example 3: random points, the workload's leaf and t
+    (1024, 8, "nufft", 1e-10, 1),
 ])
 def test_construct_and_apply_match_oracle(N, leaf, kind, tol, os_):
-    ph = I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 1.0)
-    X, O = I.uniform_grid(N)
+    ph, X, O = _workload(kind, N)
     F = oracle.build(ph, X, O, leaf, tol, oversample=os_)
     fac = B.construct(ph, X, O, tol, leaf, oversample=os_, device=DEV)
     info = fac.info()
@@ -222,6 +234,7 @@ def test_apply_many_rhs_and_repeat():
     (16, 8, "dft", 1e-10, 1),       # H = 0: dense
     (2048, 16, "fio", 1e-6, 2),
     (256, 2, "fio", 1e-8, 1),
+    (2048, 16, "nufft", 1e-6, 2),
 ])
 @pytest.mark.parametrize("nrhs", [2, 65, 300])
 def test_many_rhs_matrix_core_paths(N, leaf, kind, tol, os_, nrhs):
@@ -229,8 +242,7 @@ def test_many_rhs_matrix_core_paths(N, leaf, kind, tol, os_, nrhs):
     products with FP32 accumulation) against the oracle's FP64 apply of its
     own factors (identical skeletons, so the factors agree to 1e-12); ragged
     right-hand-side counts cover the tails of the 64-column blocks."""
-    ph = I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 1.0)
-    X, O = I.uniform_grid(N)
+    ph, X, O = _workload(kind, N)
     F = oracle.build(ph, X, O, leaf, tol, oversample=os_)
     fac = B.construct(ph, X, O, tol, leaf, oversample=os_, device=DEV)
     G = I.gaussian_vectors(N, nrhs, seed=nrhs)
@@ -335,6 +347,24 @@ def test_full_size_fio_sampled_rows(dtype):
     y = fac.apply(x).cpu().numpy()
     rows = np.sort(np.random.default_rng(4).choice(N, 48, replace=False))
     ex = oracle.matvec_rows(ph, X, O, g, rows)
+    assert oracle.relative_error(y[rows], ex) < 1e-4
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_full_size_nufft_sampled_rows(dtype):
+    """Example 3 at N = 2^20 (leaf 16, tol 1e-6, t = 2): 48 exact rows."""
+    N, leaf, tol = 1 << 20, 16, 1e-6
+    ph, W, Xp = _workload("nufft", N)
+    fac = B.construct(ph, W, Xp, tol, leaf, oversample=2, device=DEV)
+    info = fac.info()
+    assert info["H"] == 8 and info["rank_max"] <= 64
+    g = I.gaussian_vectors(N, None, seed=6)
+    x = torch.as_tensor(g, device=DEV)
+    if dtype == "c64":
+        x = x.to(torch.complex64)
+    y = fac.apply(x).cpu().numpy()
+    rows = np.sort(np.random.default_rng(6).choice(N, 48, replace=False))
+    ex = oracle.matvec_rows(ph, W, Xp, g, rows)
     assert oracle.relative_error(y[rows], ex) < 1e-4
 
 

@@ -11,21 +11,22 @@ from paper_1809_10573_amd import inputs as I
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _K(ph, N):
-    X, O = I.uniform_grid(N)
+def _K(ph, N, X=None, O=None):
+    if X is None:
+        X, O = I.uniform_grid(N)
     return oracle.entries(ph, X, O, np.arange(N), np.arange(N))
 
 
 @pytest.mark.parametrize("N,leaf,kind", [(16, 8, "dft"), (32, 2, "fio"), (64, 4, "fio"),
                                          (128, 4, "fio"), (128, 2, "dft"), (256, 8, "fio"),
-                                         (256, 2, "fio")])
+                                         (256, 2, "fio"), (256, 4, "nufft"), (128, 2, "nufft")])
 def test_full_sampling_reproduces_K(N, leaf, kind):
     # With every allowed point sampled, each ID is accurate to its tolerance on its
     # whole block; at tol = 1e-13 the assembled factorization must equal K.
-    ph = I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 2.0)
-    X, O = I.uniform_grid(N)
+    ph = I.fio_phase(1.0, 2.0) if kind == "fio" else I.dft_phase()
+    X, O = I.nufft_points(N, seed=N) if kind == "nufft" else I.uniform_grid(N)
     F = oracle.build(ph, X, O, leaf, 1e-13, sample_all=True)
-    K = _K(ph, N)
+    K = _K(ph, N, X, O)
     err = np.linalg.norm(oracle.densify(F) - K, 2) / np.linalg.norm(K, 2)
     assert err < 1e-11
 
@@ -40,6 +41,20 @@ def test_approximation_tracks_tolerance(tol):
     err = np.linalg.norm(oracle.densify(F) - K, 2) / np.linalg.norm(K, 2)
     assert err < 100 * tol
     assert F.nnz() < K.size
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+def test_nufft_tracks_tolerance_with_mock_chebyshev_samples(tol):
+    # Example 3 (random points, unequal geometric block sizes at equal counts):
+    # the sampled construction against the dense matrix
+    N, leaf = 1024, 8
+    W, Xp = I.nufft_points(N, seed=7)
+    ph = I.dft_phase()
+    F = oracle.build(ph, W, Xp, leaf, tol, oversample=2)
+    g = I.gaussian_vectors(N, None, seed=3)
+    err = oracle.relative_error(oracle.apply(F, g), oracle.dense_matvec(ph, W, Xp, g))
+    assert err < 100 * tol
+    assert F.nnz() < N * N
 
 
 def test_ranks_bounded_by_block_svd():

@@ -84,6 +84,35 @@ def test_phase_reduction_is_exact_at_large_N(kind):
     assert worst < (5e-15 if kind == "dft" else 2e-14)
 
 
+def test_phase_reduction_on_nonuniform_points():
+    # Example 3's points: w*x has up to 106 significant bits and is rounded to
+    # 64 in extended precision (<= 2^-64 * N/2 ~ 3e-14 turns at N = 2^20)
+    N = 1 << 20
+    W, Xp = I.nufft_points(N, seed=4)
+    rng = np.random.default_rng(6)
+    rows = np.concatenate([rng.integers(0, N, 30), [0, N - 1]])
+    cols = np.concatenate([rng.integers(0, N, 30), [0, N - 1]])
+    th = oracle.phase_mod1(I.dft_phase(), W[rows], Xp[cols])
+    worst = 0.0
+    for a, i in enumerate(rows):
+        for b, j in enumerate(cols):
+            diff = abs(th[a, b] - float(_exact_turns(W[i], Xp[j], I.dft_phase())))
+            worst = max(worst, min(diff, 1 - diff))
+    assert worst < 4e-14
+    K = oracle.entries(I.dft_phase(), W, Xp, rows, cols)
+    ref = np.exp(-2j * np.pi * np.outer(W[rows], Xp[cols]))   # unreduced: loses ~N*eps turns
+    assert np.max(np.abs(K - ref)) < 1e-9
+
+
+def test_nufft_points_shape_and_order():
+    W, Xp = I.nufft_points(4096, seed=2)
+    assert W.shape == Xp.shape == (4096,)
+    assert np.all(np.diff(W) > 0) and np.all(np.diff(Xp) > 0)
+    assert -2048 <= W[0] and W[-1] < 2048 and 0 <= Xp[0] and Xp[-1] < 1
+    W2, X2 = I.nufft_points(4096, seed=2)
+    assert np.array_equal(W, W2) and np.array_equal(Xp, X2)
+
+
 def test_entries_unimodular_and_dft_integer_form():
     N = 128
     X, O = I.uniform_grid(N)
