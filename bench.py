@@ -502,6 +502,30 @@ def main() -> int:
                               "unit": "GB/s", "frac": tb / tm / 1e6 / HBM_PEAK_GBS,
                               "kernels": {k: v["ms"] for k, v in p1.items()}}
     del a1
+    # adjoint apply y = K~^H x on the same factors (measured once): 1 RHS and
+    # the many-RHS matrix-core paths, with the adjoint identity as a check
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    fac.apply_adjoint(x1, y1)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    fac.apply_adjoint(x1, y1, stream=stream)
+    ev[1].record(stream)
+    ev[2].record(stream)
+    fac.apply_adjoint(XM, YM, stream=stream)
+    ev[3].record(stream)
+    ev[4].record(stream)
+    fac.apply_adjoint(XM, YM, dtype=B.C64_BF16X3, stream=stream)
+    ev[5].record(stream)
+    torch.cuda.synchronize()
+    p0 = probes[:, 0].contiguous()
+    p1 = probes[:, 1].contiguous()
+    ident = abs(complex(torch.vdot(p1, fac.apply(p0)) - torch.vdot(fac.apply_adjoint(p1), p0)))
+    ident /= float(torch.linalg.norm(p1) * torch.linalg.norm(fac.apply(p0)))
+    adj1_ms, adjn_ms, adjb_ms = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]), ev[4].elapsed_time(ev[5])
+    out["adjoint"] = {"apply1_ms": adj1_ms, "apply1_gbs": bytes1 / adj1_ms / 1e6,
+                      "applyn_ms": adjn_ms, "applyn_gflops": flops_n / adjn_ms / 1e6,
+                      "applyb_ms": adjb_ms, "applyb_gflops": flops_n / adjb_ms / 1e6,
+                      "identity_rel_err_c128": ident}
     del XM, YM
     torch.cuda.empty_cache()
     if not args.no_batched:

@@ -136,6 +136,18 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
                        void* stream);
 
 /*
+ * idbf_apply_adjoint -- y = K~^H x = (V^L)^H ... (V^h)^H (S^h)^H (U^h)^H ...
+ * (U^L)^H x, the conjugate transpose of the factorization idbf_apply applies
+ * (the same factors, the stages in reverse order, each conjugate transposed;
+ * the Conclusion's use in iterative solvers).  x is indexed like idbf_apply's
+ * y (rows of K, the points X) and y like its x (columns, the points Omega).
+ * Arguments, dtypes, workspace and error behaviour as idbf_apply; profile
+ * records are named adj1_ / adjn_ / adjb_ + v, s, u.
+ */
+idbf_status idbf_apply_adjoint(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype,
+                               void* stream);
+
+/*
  * idbf_construct_batched -- build `count` independent IDBFs (uneven N, phase,
  * tol and leaf) in one lockstep level sweep: every phase of every level is
  * issued for all instances, spread over up to 4 device-lifetime streams of
@@ -212,7 +224,8 @@ typedef struct idbf_info {
 idbf_status idbf_get_info(idbf_handle h, idbf_info* info);
 
 /* Per-kernel device time of a handle built with IDBF_FLAG_PROFILE: HIP events
- * recorded around every launch of idbf_construct and idbf_apply on the stream
+ * recorded around every launch of idbf_construct, idbf_apply and
+ * idbf_apply_adjoint on the stream
  * the kernel runs on.  bytes / flops are the algorithmic work of those
  * launches: factor entries streamed plus the vectors read or written once
  * (apply), FP64 flops of the pivoted QR and solve (IDs). */

@@ -20,7 +20,8 @@ to be checked against the paper by eye:
 * ``sampling`` -- Mock-Chebyshev sample selection (Section 2.1).
 * ``idbf``     -- the level-by-level construction (LRCS, MSCS, recursive MSCS
                   of Sections 2.2-2.4) and the factor-by-factor apply
-                  (eq. finishIDBF), plus ``densify`` for small N.
+                  (eq. finishIDBF) and its adjoint, plus ``densify`` for
+                  small N.
 * ``mlp``      -- not in the paper: the rank-proposal network (forward,
                   backpropagation, Adam), the randomized residual acceptance
                   test and the SplitMix64 counter generator of the check rows.
@@ -38,7 +39,7 @@ from .kernel import (PHASE_DFT, PHASE_FIO, amplitude_shift, phase_mod1, entries,
                      relative_error)
 from .interp import PIVOT_TIE_REL, column_id, ColumnID
 from .sampling import chebyshev_fraction, mock_chebyshev
-from .idbf import Factors, build, apply, densify, tree_sizes, factor_matrices, sample_count, SAMPLE_CAP
+from .idbf import Factors, build, apply, apply_adjoint, densify, tree_sizes, factor_matrices, sample_count, SAMPLE_CAP
 from . import mlp
 
 __all__ = [
@@ -46,5 +47,5 @@ __all__ = [
     "matvec_rows", "dense_matvec", "dft_closed_form", "fio_const_closed_form",
     "relative_error", "PIVOT_TIE_REL", "column_id", "ColumnID",
     "chebyshev_fraction", "mock_chebyshev", "Factors", "build", "apply",
-    "densify", "tree_sizes", "factor_matrices", "sample_count", "SAMPLE_CAP", "mlp",
+    "apply_adjoint", "densify", "tree_sizes", "factor_matrices", "sample_count", "SAMPLE_CAP", "mlp",
 ]

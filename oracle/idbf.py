@@ -247,6 +247,60 @@ def apply(F: Factors, x) -> np.ndarray:
     return y
 
 
+def apply_adjoint(F: Factors, x) -> np.ndarray:
+    """y = K~^H x, the conjugate transpose of apply: the factors of
+    eq. (finishIDBF) in reverse order, each conjugate transposed.  x is indexed
+    by the rows of K (X), y by its columns (Omega); (N,) or (N, nrhs).
+
+    U_t^H: each ID (r, p) reads the candidate segment its forward stage writes
+    and returns v[skel] + conj(T) v[red].  S^H: the V_H ID (C', p) collects
+    S(R, C')^H w(R, C' >> sh) over R >> sh == p.  V_t^H: the IDs (C, 2P) and
+    (C, 2P + 1) both write their shared candidate segment, e[skel] = z and
+    e[red] = T^H z, summed.
+    """
+    x = np.asarray(x, dtype=np.complex128)
+    if x.shape[0] != F.N:
+        raise ValueError("x has the wrong number of rows")
+    if F.dense is not None:
+        return F.dense.conj().T @ x
+    L, H, leaf, d = F.L, F.H, F.leaf, F.d
+    tail = x.shape[1:]
+    w = None
+    for t in range(1, H + 1):
+        wt = {}
+        for (r, p), rec in F.U[t].items():
+            if t == 1:
+                v = x[r * leaf:(r + 1) * leaf]
+            else:
+                v = np.concatenate([w[(2 * r, p >> 1)], w[(2 * r + 1, p >> 1)]])
+            wt[(r, p)] = v[rec.skelpos] + rec.T.conj() @ v[rec.redpos]
+        w = wt
+    sh = d - H
+    z = {}
+    for cc in range(1 << d):
+        for p in range(1 << H):
+            acc = np.zeros((len(F.V[H][(cc, p)].skel),) + tail, dtype=np.complex128)
+            for r in range(p << sh, (p + 1) << sh):
+                acc += F.S[(r, cc)].conj().T @ w[(r, cc >> sh)]
+            z[(cc, p)] = acc
+    y = np.zeros_like(x)
+    for t in range(H, 0, -1):
+        zn = {}
+        for (cnode, p), rec in F.V[t].items():
+            e = np.zeros((len(rec.cand),) + tail, dtype=np.complex128)
+            e[rec.skelpos] = z[(cnode, p)]
+            e[rec.redpos] = rec.T.conj().T @ z[(cnode, p)]
+            if t == 1:
+                y[cnode * leaf:(cnode + 1) * leaf] += e
+            else:
+                k1 = len(F.V[t - 1][(2 * cnode, p >> 1)].skel)
+                for child, part in ((2 * cnode, e[:k1]), (2 * cnode + 1, e[k1:])):
+                    key = (child, p >> 1)
+                    zn[key] = zn[key] + part if key in zn else part.copy()
+        z = zn
+    return y
+
+
 def densify(F: Factors) -> np.ndarray:
     """The N x N matrix the factorization represents (apply to the identity)."""
     return apply(F, np.eye(F.N, dtype=np.complex128))

@@ -31,6 +31,7 @@ EXPORTED = [
     "idbf_construct_batched", "idbf_apply_batched", "idbf_mlp_param_count", "idbf_mlp_create",
     "idbf_mlp_destroy", "idbf_mlp_params", "idbf_mlp_forward", "idbf_mlp_loss_grad", "idbf_mlp_train",
     "idbf_rank_samples", "idbf_apply_batched_plan", "idbf_plan_launch", "idbf_plan_destroy",
+    "idbf_apply_adjoint",
 ]
 MLP_INPUTS = 8
 FLAG_PROFILE = 1
@@ -97,6 +98,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_last_error.restype = C.c_char_p
     lib.idbf_construct.argtypes = [P(Phase_t), VP, VP, I64, D, I32, P(Opts_t), P(VP)]
     lib.idbf_apply.argtypes = [VP, VP, VP, I64, I32, VP]
+    lib.idbf_apply_adjoint.argtypes = [VP, VP, VP, I64, I32, VP]
     lib.idbf_destroy.argtypes = [VP]
     lib.idbf_get_info.argtypes = [VP, P(Info_t)]
     lib.idbf_batch_sizes.argtypes = [VP, I32, I32, P(I64), P(I64), P(I64)]
@@ -200,6 +202,13 @@ class Factorization:
 
     def apply(self, x, y=None, dtype: int | None = None, stream=None):
         """y = K~ x for a (N,) or (N, nrhs) complex128/complex64 device tensor."""
+        return self._apply(load().idbf_apply, x, y, dtype, stream)
+
+    def apply_adjoint(self, x, y=None, dtype: int | None = None, stream=None):
+        """y = K~^H x (idbf_apply_adjoint), same argument rules as apply."""
+        return self._apply(load().idbf_apply_adjoint, x, y, dtype, stream)
+
+    def _apply(self, fn, x, y, dtype, stream):
         import torch
         if dtype is None:
             dtype = C128 if x.dtype == torch.complex128 else C64
@@ -209,7 +218,7 @@ class Factorization:
         nrhs = 1 if x.dim() == 1 else x.shape[1]
         if y is None:
             y = torch.empty_like(x)
-        _check(load().idbf_apply(self._h, _ptr(x), _ptr(y), nrhs, dtype, _stream(stream)))
+        _check(fn(self._h, _ptr(x), _ptr(y), nrhs, dtype, _stream(stream)))
         return y
 
     def reserve(self, nrhs: int, dtype: int = C64) -> None:

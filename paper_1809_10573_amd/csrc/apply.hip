@@ -42,9 +42,13 @@ __device__ __forceinline__ float2 vec_entry<float2>(const float4& v, int t) {
 template <>
 __device__ __forceinline__ double2 vec_entry<double2>(const double2& v, int) { return v; }
 
-// Products P[e] = blk[e] * in[e / div] for e < n, streamed NV vector loads
-// per lane at a time (all issued before the first use).
-template <typename C, int NV>
+__device__ __forceinline__ float2 conj_if(float2 v, bool c) { return c ? make_float2(v.x, -v.y) : v; }
+__device__ __forceinline__ double2 conj_if(double2 v, bool c) { return c ? make_double2(v.x, -v.y) : v; }
+
+// Products P[e] = blk[e] * in[e / div] (ADJ: conj(blk[e]) * in[e % div]) for
+// e < n, streamed NV vector loads per lane at a time (all issued before the
+// first use).
+template <typename C, int NV, bool ADJ = false>
 __device__ __forceinline__ void stream_products(const C* blk, int n, int div, const C* in_lds, C* out_lds,
                                                 int lane) {
   using V = typename Vec<C>::type;
@@ -68,7 +72,8 @@ __device__ __forceinline__ void stream_products(const C* blk, int n, int div, co
           const int e = v * EPL + t;
           if (e < n) {
             const int j = (int)(((float)e + 0.5f) * rdiv);  // e / div, exact for e < 2^16
-            out_lds[e] = cfma(vec_entry<C>(buf[m], t), in_lds[j], czero(C{}));
+            const int jin = ADJ ? e - j * div : j;
+            out_lds[e] = cfma(conj_if(vec_entry<C>(buf[m], t), ADJ), in_lds[jin], czero(C{}));
           }
         }
       }
@@ -102,7 +107,10 @@ template <typename C> constexpr int nv_for() { return kProdSlot * (int)sizeof(C)
 // V stage: z(ID) = u[skel] + T u[red]; T column-major (entry j*k + i).
 // One wavefront per ID, candidate positions lane and lane + 64; the ID's
 // packed record is read with a wave-uniform index (scalar loads).
-template <typename C>
+// ADJ: the adjoint of a U stage, which has the same shape: per U ID,
+// w(ID) = u[skel] + conj(T) u[red] with T row-major (entry i*r + j), taken in
+// chunks of whole rows.
+template <typename C, bool ADJ = false>
 __global__ __launch_bounds__(256) void apply_v1(StageArgs A) {
   __shared__ C s_prod[kIdsPerBlock][kProdSlot];
   __shared__ C s_u[kIdsPerBlock][kMaxCand];
@@ -133,16 +141,32 @@ __global__ __launch_bounds__(256) void apply_v1(StageArgs A) {
   }
   wave_sync_lds();
   const C* T = static_cast<const C*>(A.T) + m.t_off;
-  const int cols = max(1, kProdSlot / max(k, 1));  // whole columns per chunk
-  for (int j0 = 0; j0 < r; j0 += cols) {
-    const int nj = min(cols, r - j0);
-    stream_products<C, nv_for<C>()>(T + (int64_t)j0 * k, nj * k, k, s_u[w] + j0, s_p, lane);
-    wave_sync_lds();
+  if constexpr (!ADJ) {
+    const int cols = max(1, kProdSlot / max(k, 1));  // whole columns per chunk
+    for (int j0 = 0; j0 < r; j0 += cols) {
+      const int nj = min(cols, r - j0);
+      stream_products<C, nv_for<C>()>(T + (int64_t)j0 * k, nj * k, k, s_u[w] + j0, s_p, lane);
+      wave_sync_lds();
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
-      if (h < halves && lane + kWave * h < c && sk[h])
-        for (int j = 0; j < nj; ++j) acc[h] = cadd(acc[h], s_p[j * k + below[h]]);
-    wave_sync_lds();
+      for (int h = 0; h < 2; ++h)
+        if (h < halves && lane + kWave * h < c && sk[h])
+          for (int j = 0; j < nj; ++j) acc[h] = cadd(acc[h], s_p[j * k + below[h]]);
+      wave_sync_lds();
+    }
+  } else if (r > 0) {
+    const int rows = max(1, kProdSlot / r);  // whole rows per chunk
+    for (int i0 = 0; i0 < k; i0 += rows) {
+      const int ni = min(rows, k - i0);
+      stream_products<C, nv_for<C>(), true>(T + (int64_t)i0 * r, ni * r, r, s_u[w], s_p, lane);
+      wave_sync_lds();
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (h < halves && lane + kWave * h < c && sk[h] && below[h] >= i0 && below[h] < i0 + ni) {
+          const C* p = s_p + (below[h] - i0) * r;
+          for (int j = 0; j < r; ++j) acc[h] = cadd(acc[h], p[j]);
+        }
+      wave_sync_lds();
+    }
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -152,7 +176,11 @@ __global__ __launch_bounds__(256) void apply_v1(StageArgs A) {
 // U stage: one unit = the two IDs of one node with the two children of one
 // partner; they share the candidate segment, which the unit writes whole.
 // T row-major (entry i*r + j), processed in chunks of whole rows.
-template <typename C>
+// ADJ: the adjoint of a V stage, which has the same shape: the V IDs (C, 2P)
+// and (C, 2P + 1) share their candidate segment; v[skel] = w,
+// v[red_j] = sum_i conj(T(i, j)) w_i with T column-major (entry j*k + i),
+// taken in chunks of whole columns.
+template <typename C, bool ADJ = false>
 __global__ __launch_bounds__(256) void apply_u1(StageArgs A) {
   __shared__ C s_prod[kIdsPerBlock][kProdSlot];
   __shared__ C s_w[kIdsPerBlock][2][kMaxRank];
@@ -191,20 +219,39 @@ __global__ __launch_bounds__(256) void apply_u1(StageArgs A) {
     const int k = m[h].k, r = c - k;
     if (r == 0) continue;
     const C* T = static_cast<const C*>(A.T) + m[h].t_off;
-    const int rows = max(1, kProdSlot / r);  // whole rows per chunk
-    for (int i0 = 0; i0 < k; i0 += rows) {
-      const int ni = min(rows, k - i0);
-      stream_products<C, nv_for<C>()>(T + (int64_t)i0 * r, ni * r, r, s_w[w][h] + i0, s_p, lane);
-      wave_sync_lds();
+    if constexpr (!ADJ) {
+      const int rows = max(1, kProdSlot / r);  // whole rows per chunk
+      for (int i0 = 0; i0 < k; i0 += rows) {
+        const int ni = min(rows, k - i0);
+        stream_products<C, nv_for<C>()>(T + (int64_t)i0 * r, ni * r, r, s_w[w][h] + i0, s_p, lane);
+        wave_sync_lds();
 #pragma unroll
-      for (int hp = 0; hp < 2; ++hp) {
-        const int pos = lane + kWave * hp;
-        if (hp < halves && pos < c && !sk[hp][h]) {
-          const C* p = s_p + (pos - below[hp][h]);
-          for (int i = 0; i < ni; ++i) acc[hp] = cadd(acc[hp], p[i * r]);
+        for (int hp = 0; hp < 2; ++hp) {
+          const int pos = lane + kWave * hp;
+          if (hp < halves && pos < c && !sk[hp][h]) {
+            const C* p = s_p + (pos - below[hp][h]);
+            for (int i = 0; i < ni; ++i) acc[hp] = cadd(acc[hp], p[i * r]);
+          }
         }
+        wave_sync_lds();
       }
-      wave_sync_lds();
+    } else {
+      const int cols = max(1, kProdSlot / k);  // whole columns per chunk
+      for (int j0 = 0; j0 < r; j0 += cols) {
+        const int nj = min(cols, r - j0);
+        stream_products<C, nv_for<C>(), true>(T + (int64_t)j0 * k, nj * k, k, s_w[w][h], s_p, lane);
+        wave_sync_lds();
+#pragma unroll
+        for (int hp = 0; hp < 2; ++hp) {
+          const int pos = lane + kWave * hp;
+          const int j = pos - below[hp][h];
+          if (hp < halves && pos < c && !sk[hp][h] && j >= j0 && j < j0 + nj) {
+            const C* p = s_p + (j - j0) * k;
+            for (int i = 0; i < k; ++i) acc[hp] = cadd(acc[hp], p[i]);
+          }
+        }
+        wave_sync_lds();
+      }
     }
   }
 #pragma unroll
@@ -217,7 +264,10 @@ __global__ __launch_bounds__(256) void apply_u1(StageArgs A) {
 // Middle factor, one U_H ID per wavefront: the 2^(d-H) blocks S(R, C') are
 // consecutive, column-major, rows of the output; each block is processed in
 // chunks of whole columns.
-template <typename C>
+// ADJ: one V_H ID per wavefront, z(C') = sum over its blocks of S(R, C')^H
+// w(R); columns of each block are the outputs, again in chunks of whole
+// columns.
+template <typename C, bool ADJ = false>
 __global__ __launch_bounds__(256) void apply_s1(StageArgs A) {
   __shared__ C s_prod[kIdsPerBlock][kProdSlot];
   __shared__ C s_z[kIdsPerBlock][kMaxRank];
@@ -228,42 +278,72 @@ __global__ __launch_bounds__(256) void apply_s1(StageArgs A) {
   const C* in = static_cast<const C*>(A.in);
   C* out = static_cast<C*>(A.out);
   const C* S = static_cast<const C*>(A.T);
-  const int64_t b0 = q * A.nsub;
-  const int rl = A.rlen[b0], rb = A.rbeg[b0];
+  const int64_t b0 = middle_block<ADJ>(A, q, 0);
   C acc = czero(C{});
-  for (int jb = 0; jb < A.nsub; ++jb) {
-    const int cl = A.clen[b0 + jb];
-    if (lane < cl) s_z[w][lane] = in[A.cbeg[b0 + jb] + lane];
-    wave_sync_lds();
-    const C* Sb = S + A.T_off[b0 + jb];
-    const int cols = max(1, kProdSlot / max(rl, 1));
-    for (int c0 = 0; c0 < cl; c0 += cols) {
-      const int nc = min(cols, cl - c0);
-      stream_products<C, nv_for<C>()>(Sb + (int64_t)c0 * rl, nc * rl, rl, s_z[w] + c0, s_p, lane);
+  if constexpr (!ADJ) {
+    const int rl = A.rlen[b0], rb = A.rbeg[b0];
+    for (int jb = 0; jb < A.nsub; ++jb) {
+      const int cl = A.clen[b0 + jb];
+      if (lane < cl) s_z[w][lane] = in[A.cbeg[b0 + jb] + lane];
       wave_sync_lds();
-      if (lane < rl)
-        for (int col = 0; col < nc; ++col) acc = cadd(acc, s_p[col * rl + lane]);
-      wave_sync_lds();
+      const C* Sb = S + A.T_off[b0 + jb];
+      const int cols = max(1, kProdSlot / max(rl, 1));
+      for (int c0 = 0; c0 < cl; c0 += cols) {
+        const int nc = min(cols, cl - c0);
+        stream_products<C, nv_for<C>()>(Sb + (int64_t)c0 * rl, nc * rl, rl, s_z[w] + c0, s_p, lane);
+        wave_sync_lds();
+        if (lane < rl)
+          for (int col = 0; col < nc; ++col) acc = cadd(acc, s_p[col * rl + lane]);
+        wave_sync_lds();
+      }
     }
+    if (lane < rl) out[rb + lane] = acc;
+  } else {
+    const int cl = A.clen[b0], cb = A.cbeg[b0];
+    for (int jb = 0; jb < A.nsub; ++jb) {
+      const int64_t b = middle_block<ADJ>(A, q, jb);
+      const int rl = A.rlen[b];
+      if (lane < rl) s_z[w][lane] = in[A.rbeg[b] + lane];
+      wave_sync_lds();
+      if (rl > 0) {
+        const C* Sb = S + A.T_off[b];
+        const int cols = max(1, kProdSlot / rl);
+        for (int c0 = 0; c0 < cl; c0 += cols) {
+          const int nc = min(cols, cl - c0);
+          stream_products<C, nv_for<C>(), true>(Sb + (int64_t)c0 * rl, nc * rl, rl, s_z[w], s_p, lane);
+          wave_sync_lds();
+          if (lane >= c0 && lane < c0 + nc) {
+            const C* pp = s_p + (lane - c0) * rl;
+            for (int i = 0; i < rl; ++i) acc = cadd(acc, pp[i]);
+          }
+          wave_sync_lds();
+        }
+      }
+    }
+    if (lane < cl) out[cb + lane] = acc;
   }
-  if (lane < rl) out[rb + lane] = acc;
 }
 
-// The whole matrix when the tree has no levels (N <= 2 leaf): lanes over rows.
-template <typename C>
+// The whole matrix when the tree has no levels (N <= 2 leaf): lanes over rows
+// (ADJ: over columns, with conjugated entries).
+template <typename C, bool ADJ = false>
 __global__ __launch_bounds__(256) void apply_dense(StageArgs A) {
   const C* in = static_cast<const C*>(A.in);
   C* out = static_cast<C*>(A.out);
   const C* S = static_cast<const C*>(A.T);
   const int rl = A.rlen[0], cl = A.clen[0];
+  const int no = ADJ ? cl : rl, ni = ADJ ? rl : cl;
   const int64_t nr = A.nrhs;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)rl * nr;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)no * nr;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(e / nr);
+    const int o = (int)(e / nr);
     const int64_t rhs = e % nr;
     C acc = czero(C{});
-    for (int col = 0; col < cl; ++col) acc = cfma(S[(int64_t)col * rl + i], in[(int64_t)col * nr + rhs], acc);
-    out[(int64_t)i * nr + rhs] = acc;
+    for (int l = 0; l < ni; ++l) {
+      const C sv = ADJ ? conj_if(S[(int64_t)o * rl + l], true) : S[(int64_t)l * rl + o];
+      acc = cfma(sv, in[(int64_t)l * nr + rhs], acc);
+    }
+    out[(int64_t)o * nr + rhs] = acc;
   }
 }
 
@@ -282,8 +362,9 @@ __device__ __forceinline__ void stage_block(const C* src, int n, C* dst) {
 constexpr int kRankChunk = 16;  // outputs (V, S) or inputs (U) held in registers per pass
 
 // V stage: the ID's T (dynamic LDS, k r entries) is applied to one RHS per
-// thread, kRankChunk outputs per pass.
-template <typename C>
+// thread, kRankChunk outputs per pass.  ADJ: the adjoint of a U stage (per U
+// ID, conj(T) with T row-major).
+template <typename C, bool ADJ = false>
 __global__ __launch_bounds__(256) void apply_vn(StageArgs A) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   C* s_T = reinterpret_cast<C*>(s_dyn);
@@ -310,10 +391,17 @@ __global__ __launch_bounds__(256) void apply_vn(StageArgs A) {
     for (int i = 0; i < kRankChunk; ++i) acc[i] = czero(C{});
     for (int j = 0; j < r; ++j) {
       const C uj = in[(int64_t)(cb + s_red[j]) * nr];
-      const C* t = s_T + j * k + i0;
+      if constexpr (!ADJ) {
+        const C* t = s_T + j * k + i0;
 #pragma unroll
-      for (int i = 0; i < kRankChunk; ++i)
-        if (i0 + i < k) acc[i] = cfma(t[i], uj, acc[i]);
+        for (int i = 0; i < kRankChunk; ++i)
+          if (i0 + i < k) acc[i] = cfma(t[i], uj, acc[i]);
+      } else {
+        const C* t = s_T + i0 * r + j;
+#pragma unroll
+        for (int i = 0; i < kRankChunk; ++i)
+          if (i0 + i < k) acc[i] = cfma(conj_if(t[i * r], true), uj, acc[i]);
+      }
     }
 #pragma unroll
     for (int i = 0; i < kRankChunk; ++i)
@@ -323,8 +411,10 @@ __global__ __launch_bounds__(256) void apply_vn(StageArgs A) {
 
 // U stage: the unit's two T blocks (dynamic LDS, 2 pmax entries); one RHS per
 // thread; each pass takes kRankChunk inputs of one ID and adds their
-// contribution to every candidate position (the first pass writes).
-template <typename C>
+// contribution to every candidate position (the first pass writes).  ADJ:
+// the adjoint of a V stage (the V ID pair of one segment, conj(T) with T
+// column-major).
+template <typename C, bool ADJ = false>
 __global__ __launch_bounds__(256) void apply_un(StageArgs A) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   C* s_T = reinterpret_cast<C*>(s_dyn);
@@ -357,10 +447,17 @@ __global__ __launch_bounds__(256) void apply_un(StageArgs A) {
         if (mbit(m[h], l)) {
           if (below >= i0 && below < i0 + kRankChunk) acc = cadd(acc, in[(int64_t)(so + below) * nr]);
         } else {
-          const C* t = Th + (int64_t)i0 * r + (l - below);
+          if constexpr (!ADJ) {
+            const C* t = Th + (int64_t)i0 * r + (l - below);
 #pragma unroll
-          for (int i = 0; i < kRankChunk; ++i)
-            if (i0 + i < k) acc = cfma(t[i * r], wv[i], acc);
+            for (int i = 0; i < kRankChunk; ++i)
+              if (i0 + i < k) acc = cfma(t[i * r], wv[i], acc);
+          } else {
+            const C* t = Th + (int64_t)(l - below) * k + i0;
+#pragma unroll
+            for (int i = 0; i < kRankChunk; ++i)
+              if (i0 + i < k) acc = cfma(conj_if(t[i], true), wv[i], acc);
+          }
         }
         out[(int64_t)(cb + l) * nr] = acc;
       }
@@ -370,42 +467,52 @@ __global__ __launch_bounds__(256) void apply_un(StageArgs A) {
 }
 
 // Middle stage: one U_H ID per workgroup, its blocks staged in dynamic LDS
-// one at a time (pmax entries); kRankChunk outputs per pass.
-template <typename C>
+// one at a time (pmax entries); kRankChunk outputs per pass.  ADJ: one V_H ID
+// per workgroup, conj(S)^T of each of its blocks.
+template <typename C, bool ADJ = false>
 __global__ __launch_bounds__(256) void apply_sn(StageArgs A) {
   extern __shared__ __attribute__((aligned(16))) unsigned char s_dyn[];
   C* s_S = reinterpret_cast<C*>(s_dyn);
   const int64_t q = blockIdx.x;
   const int64_t n = blockIdx.y * (int64_t)kRhsTile + threadIdx.x;
-  const int64_t b0 = q * A.nsub;
-  const int rl = A.rlen[b0], rbg = A.rbeg[b0];
+  const int64_t b0 = middle_block<ADJ>(A, q, 0);
+  const int ol = ADJ ? A.clen[b0] : A.rlen[b0];   // outputs
+  const int ob = ADJ ? A.cbeg[b0] : A.rbeg[b0];
   const bool live = n < A.nrhs;
   const C* in = static_cast<const C*>(A.in) + (live ? n : 0);
   C* out = static_cast<C*>(A.out) + (live ? n : 0);
   const int64_t nr = A.nrhs;
-  for (int i0 = 0; i0 < rl; i0 += kRankChunk) {
+  for (int i0 = 0; i0 < ol; i0 += kRankChunk) {
     C acc[kRankChunk];
 #pragma unroll
     for (int i = 0; i < kRankChunk; ++i) acc[i] = czero(C{});
     for (int jb = 0; jb < A.nsub; ++jb) {
-      const int64_t b = b0 + jb;
-      const int cl = A.clen[b], cbg = A.cbeg[b];
+      const int64_t b = middle_block<ADJ>(A, q, jb);
+      const int rl = A.rlen[b], cl = A.clen[b];
+      const int il = ADJ ? rl : cl, ib = ADJ ? A.rbeg[b] : A.cbeg[b];  // inputs of this block
       __syncthreads();
       stage_block(static_cast<const C*>(A.T) + A.T_off[b], rl * cl, s_S);
       __syncthreads();
       if (!live) continue;
-      for (int col = 0; col < cl; ++col) {
-        const C zc = in[(int64_t)(cbg + col) * nr];
-        const C* sc = s_S + col * rl + i0;
+      for (int l = 0; l < il; ++l) {
+        const C zc = in[(int64_t)(ib + l) * nr];
+        if constexpr (!ADJ) {
+          const C* sc = s_S + l * rl + i0;
 #pragma unroll
-        for (int i = 0; i < kRankChunk; ++i)
-          if (i0 + i < rl) acc[i] = cfma(sc[i], zc, acc[i]);
+          for (int i = 0; i < kRankChunk; ++i)
+            if (i0 + i < ol) acc[i] = cfma(sc[i], zc, acc[i]);
+        } else {
+          const C* sc = s_S + i0 * rl + l;
+#pragma unroll
+          for (int i = 0; i < kRankChunk; ++i)
+            if (i0 + i < ol) acc[i] = cfma(conj_if(sc[i * rl], true), zc, acc[i]);
+        }
       }
     }
     if (!live) continue;
 #pragma unroll
     for (int i = 0; i < kRankChunk; ++i)
-      if (i0 + i < rl) out[(int64_t)(rbg + i0 + i) * nr] = acc[i];
+      if (i0 + i < ol) out[(int64_t)(ob + i0 + i) * nr] = acc[i];
   }
 }
 
@@ -423,52 +530,67 @@ inline dim3 gridn(int64_t n, int64_t nrhs) {
   return dim3((unsigned)n, (unsigned)((nrhs + kRhsTile - 1) / kRhsTile));
 }
 
-}  // namespace
-
-hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st) {
-  if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
+template <bool ADJ>
+hipError_t launch_v_shaped(const StageArgs& a, bool fp64, hipStream_t st) {
   if (a.nrhs == 1) {
-    if (fp64) hipLaunchKernelGGL(apply_v1<double2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(apply_v1<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
+    if (fp64) hipLaunchKernelGGL((apply_v1<double2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((apply_v1<float2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
   } else {
     if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
     const size_t lds = (size_t)a.pmax * sizeof(double2);
-    if (hipError_t e = allow_lds(apply_vn<double2>, lds); e != hipSuccess) return e;
-    hipLaunchKernelGGL(apply_vn<double2>, gridn(a.n, a.nrhs), dim3(256), lds, st, a);
+    if (hipError_t e = allow_lds(apply_vn<double2, ADJ>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL((apply_vn<double2, ADJ>), gridn(a.n, a.nrhs), dim3(256), lds, st, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st) {
-  if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
+template <bool ADJ>
+hipError_t launch_u_shaped(const StageArgs& a, bool fp64, hipStream_t st) {
   if (a.nrhs == 1) {
-    if (fp64) hipLaunchKernelGGL(apply_u1<double2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(apply_u1<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
+    if (fp64) hipLaunchKernelGGL((apply_u1<double2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((apply_u1<float2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
   } else {
     if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
     const size_t lds = 2 * (size_t)a.pmax * sizeof(double2);
-    if (hipError_t e = allow_lds(apply_un<double2>, lds); e != hipSuccess) return e;
-    hipLaunchKernelGGL(apply_un<double2>, gridn(a.n, a.nrhs), dim3(256), lds, st, a);
+    if (hipError_t e = allow_lds(apply_un<double2, ADJ>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL((apply_un<double2, ADJ>), gridn(a.n, a.nrhs), dim3(256), lds, st, a);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st) {
-  if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
+template <bool ADJ>
+hipError_t launch_s_stage(const StageArgs& a, bool fp64, hipStream_t st) {
   if (a.dense) {
     const unsigned blocks = (unsigned)std::min<int64_t>((a.rlen_host * a.nrhs + 255) / 256, 65535);
-    if (fp64) hipLaunchKernelGGL(apply_dense<double2>, dim3(blocks), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(apply_dense<float2>, dim3(blocks), dim3(256), 0, st, a);
+    if (fp64) hipLaunchKernelGGL((apply_dense<double2, ADJ>), dim3(blocks), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((apply_dense<float2, ADJ>), dim3(blocks), dim3(256), 0, st, a);
   } else if (a.nrhs == 1) {
-    if (fp64) hipLaunchKernelGGL(apply_s1<double2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(apply_s1<float2>, dim3(grid1(a.n)), dim3(256), 0, st, a);
+    if (fp64) hipLaunchKernelGGL((apply_s1<double2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((apply_s1<float2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
   } else {
     if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
     const size_t lds = (size_t)a.pmax * sizeof(double2);
-    if (hipError_t e = allow_lds(apply_sn<double2>, lds); e != hipSuccess) return e;
-    hipLaunchKernelGGL(apply_sn<double2>, gridn(a.n, a.nrhs), dim3(256), lds, st, a);
+    if (hipError_t e = allow_lds(apply_sn<double2, ADJ>, lds); e != hipSuccess) return e;
+    hipLaunchKernelGGL((apply_sn<double2, ADJ>), gridn(a.n, a.nrhs), dim3(256), lds, st, a);
   }
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st, bool adj) {
+  if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
+  return adj ? launch_v_shaped<true>(a, fp64, st) : launch_v_shaped<false>(a, fp64, st);
+}
+
+hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st, bool adj) {
+  if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
+  return adj ? launch_u_shaped<true>(a, fp64, st) : launch_u_shaped<false>(a, fp64, st);
+}
+
+hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st, bool adj) {
+  if (a.n <= 0 || a.nrhs <= 0) return hipSuccess;
+  return adj ? launch_s_stage<true>(a, fp64, st) : launch_s_stage<false>(a, fp64, st);
 }
 
 }  // namespace idbf

@@ -55,28 +55,40 @@ __device__ __forceinline__ int lda_for(int K) { return ((K + 15) & ~15) + 2; }
 //   U unit: A = [P_0 P_1], P_h(l, i) = 1 if l is the i-th skeleton of ID h,
 //     T_h(i, j) if l is its j-th redundant candidate.
 //   S (U_H ID): A = [S_1 ... S_nsub].
-template <int MODE>
+// ADJ (the adjoint, stages in reverse): a V-shaped unit over the U ID pair
+// of one segment, A = [P_0 P_1]^H; a U-shaped unit over the V ID pair of one
+// segment, A = ([I T_0]; [I T_1])^H; S^H per V_H ID, A = [S(R_1, C')^H ...].
+template <int MODE, bool ADJ>
 __device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_out, int* s_red) {
   const int64_t q = blockIdx.x;
   const float2* T = static_cast<const float2*>(A.T);
   Unit u{};
   if constexpr (MODE == kModeS) {
-    const int64_t b0 = q * A.nsub;
-    const int rl = A.rlen[b0], rbg = A.rbeg[b0];
+    const int64_t b0 = middle_block<ADJ>(A, q, 0);
+    const int ol = ADJ ? A.clen[b0] : A.rlen[b0], obg = ADJ ? A.cbeg[b0] : A.rbeg[b0];  // outputs
     int K = 0;
-    for (int jb = 0; jb < A.nsub; ++jb) K += A.clen[b0 + jb];
-    u = Unit{rl, K};
+    for (int jb = 0; jb < A.nsub; ++jb) {
+      const int64_t b = middle_block<ADJ>(A, q, jb);
+      K += ADJ ? A.rlen[b] : A.clen[b];
+    }
+    u = Unit{ol, K};
     const int lda = lda_for(K);
     for (int e = threadIdx.x; e < A.gemm_rows * lda; e += blockDim.x) s_A[e] = make_float2(0.f, 0.f);
-    for (int i = threadIdx.x; i < rl; i += blockDim.x) s_out[i] = rbg + i;
+    for (int i = threadIdx.x; i < ol; i += blockDim.x) s_out[i] = obg + i;
     __syncthreads();
     int off = 0;
     for (int jb = 0; jb < A.nsub; ++jb) {
-      const int cl = A.clen[b0 + jb], cbg = A.cbeg[b0 + jb];
-      const int64_t so = A.T_off[b0 + jb];
-      for (int col = threadIdx.x; col < cl; col += blockDim.x) s_src[off + col] = cbg + col;
-      for (int e = threadIdx.x; e < rl * cl; e += blockDim.x) s_A[(e % rl) * lda + off + e / rl] = T[so + e];
-      off += cl;
+      const int64_t b = middle_block<ADJ>(A, q, jb);
+      const int rl = A.rlen[b], cl = A.clen[b];
+      const int il = ADJ ? rl : cl, ibg = ADJ ? A.rbeg[b] : A.cbeg[b];  // inputs of this block
+      const int64_t so = A.T_off[b];
+      for (int l = threadIdx.x; l < il; l += blockDim.x) s_src[off + l] = ibg + l;
+      for (int e = threadIdx.x; e < rl * cl; e += blockDim.x) {
+        const float2 v = T[so + e];  // S(e % rl, e / rl)
+        if (ADJ) s_A[(e / rl) * lda + off + e % rl] = make_float2(v.x, -v.y);
+        else s_A[(e % rl) * lda + off + e / rl] = v;
+      }
+      off += il;
     }
   } else {
     const int64_t P = q / A.nn, node = q % A.nn;
@@ -112,16 +124,18 @@ __device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_o
       }
     }
     __syncthreads();
+    // T_h(i, j) at j k + i for V factors, at i r + j for U factors
+    constexpr bool colmajor = (MODE == kModeV) != ADJ;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const ApplyMeta& m = h ? m1 : m0;
       const int k = m.k, r = c - k, base = h ? k0 : 0;
-      if (isV) {  // T_h(i, j) at j k + i
-        for (int e = threadIdx.x; e < k * r; e += blockDim.x)
-          s_A[(base + e % k) * lda + s_red[h * kMaxMg + e / k]] = T[m.t_off + e];
-      } else {    // T_h(i, j) at i r + j
-        for (int e = threadIdx.x; e < k * r; e += blockDim.x)
-          s_A[s_red[h * kMaxMg + e % r] * lda + base + e / r] = T[m.t_off + e];
+      for (int e = threadIdx.x; e < k * r; e += blockDim.x) {
+        const int i = colmajor ? e % k : e / r, j = colmajor ? e / k : e % r;
+        float2 v = T[m.t_off + e];
+        if (ADJ) v.y = -v.y;
+        if (isV) s_A[(base + i) * lda + s_red[h * kMaxMg + j]] = v;
+        else s_A[s_red[h * kMaxMg + j] * lda + base + i] = v;
       }
     }
   }
@@ -136,13 +150,13 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-template <int MODE, bool BF16>
+template <int MODE, bool BF16, bool ADJ>
 __global__ __launch_bounds__(64 * kWavesG) void apply_gemm(StageArgs A) {
   extern __shared__ __attribute__((aligned(16))) float2 s_A[];
   __shared__ int s_src[kMaxKg];
   __shared__ int s_out[kMaxMg];
   __shared__ int s_red[2 * kMaxMg];
-  const Unit u = stage_unit<MODE>(A, s_A, s_src, s_out, s_red);
+  const Unit u = stage_unit<MODE, ADJ>(A, s_A, s_src, s_out, s_red);
   const int lane = threadIdx.x & (kWave - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   // one wavefront per (32-row M-tile, block of right-hand sides)
@@ -246,7 +260,7 @@ __global__ __launch_bounds__(64 * kWavesG) void apply_gemm(StageArgs A) {
 }  // namespace
 
 hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int mmax_unit, bool bf16,
-                             hipStream_t st) {
+                             hipStream_t st, bool adj) {
   if (a0.n <= 0 || a0.nrhs <= 0) return hipSuccess;
   if (kmax_unit < 1 || kmax_unit > kMaxKg || mmax_unit < 1 || mmax_unit > kMaxMg) return hipErrorInvalidValue;
   StageArgs a = a0;
@@ -259,26 +273,29 @@ hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int m
   const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
   const dim3 block(64 * waves);
   const size_t lds = (size_t)a.gemm_rows * (size_t)(((kmax_unit + 15) & ~15) + 2) * sizeof(float2);
-#define IDBF_GEMM(M, B)                                                                              \
+#define IDBF_GEMM(M, B, J)                                                                           \
   do {                                                                                               \
     if (lds > (size_t(64) << 10)) {                                                                  \
-      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_gemm<M, B>),          \
+      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_gemm<M, B, J>),       \
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
       if (e_ != hipSuccess) return e_;                                                               \
     }                                                                                                \
-    hipLaunchKernelGGL((apply_gemm<M, B>), grid, block, lds, st, a);                                 \
+    hipLaunchKernelGGL((apply_gemm<M, B, J>), grid, block, lds, st, a);                              \
+  } while (0)
+#define IDBF_GEMM_MODE(M)                                                                            \
+  do {                                                                                               \
+    if (adj) {                                                                                       \
+      if (bf16) IDBF_GEMM(M, true, true); else IDBF_GEMM(M, false, true);                            \
+    } else {                                                                                         \
+      if (bf16) IDBF_GEMM(M, true, false); else IDBF_GEMM(M, false, false);                          \
+    }                                                                                                \
   } while (0)
   switch (mode) {
-    case kModeV:
-      if (bf16) IDBF_GEMM(kModeV, true); else IDBF_GEMM(kModeV, false);
-      break;
-    case kModeS:
-      if (bf16) IDBF_GEMM(kModeS, true); else IDBF_GEMM(kModeS, false);
-      break;
-    default:
-      if (bf16) IDBF_GEMM(kModeU, true); else IDBF_GEMM(kModeU, false);
-      break;
+    case kModeV: IDBF_GEMM_MODE(kModeV); break;
+    case kModeS: IDBF_GEMM_MODE(kModeS); break;
+    default: IDBF_GEMM_MODE(kModeU); break;
   }
+#undef IDBF_GEMM_MODE
 #undef IDBF_GEMM
   return hipGetLastError();
 }

@@ -1002,7 +1002,30 @@ idbf_status idbf_destroy(idbf_handle h) {
   return IDBF_OK;
 }
 
-idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype, void* stream) {
+namespace {
+
+// The stage arguments of level t of one side, shared by the apply and its
+// adjoint.
+StageArgs level_stage(const Batch& b, bool fp64, int64_t nrhs) {
+  StageArgs a{};
+  a.meta = b.meta;
+  a.n = b.n;
+  a.nrhs = nrhs;
+  a.cand_beg = b.cand_beg;
+  a.cand_len = b.cand_len;
+  a.rank = b.rank;
+  a.skel_off = b.skel_off;
+  a.mask = b.mask;
+  a.T_off = b.T_off;
+  a.T = fp64 ? (const void*)b.T128 : (const void*)b.T64;
+  a.pmax = (int)b.tb_max;
+  return a;
+}
+
+// y = K x (adj: y = K^H x, the stages in reverse order, each conjugate
+// transposed).  Stage names of the profile: apply1_/applyn_/applyb_ (forward)
+// or adj1_/adjn_/adjb_ (adjoint) + v, s, u.
+idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype, void* stream, bool adj) {
   g_err[0] = 0;
   if (!h) {
     set_error("handle is NULL");
@@ -1027,31 +1050,28 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
   char* buf[2] = {static_cast<char*>(h->ws), static_cast<char*>(h->ws) + half};
   int cur = 0;
   const void* in = x;
+  // profile record names (the profiler keeps the pointer: literals only)
+  static const char* const kNames[2][3][3] = {
+      {{"apply1_v", "apply1_s", "apply1_u"}, {"applyn_v", "applyn_s", "applyn_u"},
+       {"applyb_v", "applyb_s", "applyb_u"}},
+      {{"adj1_v", "adj1_s", "adj1_u"}, {"adjn_v", "adjn_s", "adjn_u"}, {"adjb_v", "adjb_s", "adjb_u"}}};
+  const int kind = bf16 ? 2 : nrhs == 1 ? 0 : 1;
+  auto name = [&](char stage) { return kNames[adj][kind][stage == 'v' ? 0 : stage == 's' ? 1 : 2]; };
+  // V-shaped stages: V_t forward (t = 1..H), U_t^H in the adjoint (t = 1..H)
   for (int t = 1; t <= h->H; ++t) {
-    const Batch& b = h->V[t - 1];
-    StageArgs a{};
-    a.meta = b.meta;
-    a.n = b.n;
-    a.nrhs = nrhs;
-    a.cand_beg = b.cand_beg;
-    a.cand_len = b.cand_len;
-    a.rank = b.rank;
-    a.skel_off = b.skel_off;
-    a.mask = b.mask;
-    a.T_off = b.T_off;
-    a.T = fp64 ? (const void*)b.T128 : (const void*)b.T64;
-    a.pmax = (int)b.tb_max;
+    const Batch& b = adj ? h->U[t - 1] : h->V[t - 1];
+    StageArgs a = level_stage(b, fp64, nrhs);
     a.in = in;
     a.out = buf[cur];
     const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
-    const int pr = h->prof.begin(bf16 ? "applyb_v" : nrhs == 1 ? "apply1_v" : "applyn_v", st);
+    const int pr = h->prof.begin(name(adj ? 'u' : 'v'), st);
     if (mfma) {  // units: the ID pairs (C, 2P), (C, 2P + 1) that share a candidate segment
       StageArgs g = a;
       g.n = b.n / 2;
       g.nn = 1 << (h->L - t + 1);
-      IDBF_HIP_CHECK(launch_apply_gemm(g, 0, b.cand_max, 2 * b.rank_max, bf16, st));
+      IDBF_HIP_CHECK(launch_apply_gemm(g, 0, b.cand_max, 2 * b.rank_max, bf16, st, adj));
     } else {
-      IDBF_HIP_CHECK(launch_apply_v(a, fp64, st));
+      IDBF_HIP_CHECK(launch_apply_v(a, fp64, st, adj));
     }
     h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T) * nrhs);
     in = buf[cur];
@@ -1059,7 +1079,8 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
   }
   {
     StageArgs a{};
-    a.n = (h->H == 0) ? 1 : h->U[h->H - 1].n;
+    a.n = (h->H == 0) ? 1 : (adj ? h->V[h->H - 1].n : h->U[h->H - 1].n);
+    a.nn = (h->H == 0) ? 1 : (1 << (h->L - h->H + 1));  // 2^d, used by the adjoint grouping
     a.nrhs = nrhs;
     a.nsub = (h->H == 0) ? 1 : (1 << (h->L - 2 * h->H + 1));
     a.rbeg = h->s_rbeg;
@@ -1075,40 +1096,45 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     a.out = (h->H == 0) ? y : buf[cur];
     double bytes = double(h->nnz_S) * elem;
     if (h->H == 0) bytes += 2.0 * double(h->N) * nrhs * elem;
-    const int pr = h->prof.begin(bf16 ? "applyb_s" : nrhs == 1 ? "apply1_s" : "applyn_s", st);
-    if (mfma && !a.dense)
-      IDBF_HIP_CHECK(launch_apply_gemm(a, 1, a.nsub * h->V[h->H - 1].rank_max, h->U[h->H - 1].rank_max, bf16, st));
-    else IDBF_HIP_CHECK(launch_apply_s(a, fp64, st));
+    const int pr = h->prof.begin(name('s'), st);
+    if (mfma && !a.dense) {
+      const int kin = adj ? h->U[h->H - 1].rank_max : h->V[h->H - 1].rank_max;
+      const int mout = adj ? h->V[h->H - 1].rank_max : h->U[h->H - 1].rank_max;
+      IDBF_HIP_CHECK(launch_apply_gemm(a, 1, a.nsub * kin, mout, bf16, st, adj));
+    } else {
+      IDBF_HIP_CHECK(launch_apply_s(a, fp64, st, adj));
+    }
     h->prof.end(pr, st, bytes, 8.0 * double(h->nnz_S) * nrhs);
     in = a.out;
     cur ^= 1;
   }
+  // U-shaped stages: U_t forward (t = H..1), V_t^H in the adjoint (t = H..1)
   for (int t = h->H; t >= 1; --t) {
-    const Batch& b = h->U[t - 1];
-    StageArgs a{};
-    a.meta = b.meta;
+    const Batch& b = adj ? h->V[t - 1] : h->U[t - 1];
+    StageArgs a = level_stage(b, fp64, nrhs);
     a.n = int64_t(1) << h->L;  // units: one per (node, parent partner)
     a.nn = 1 << (h->L - t + 1);
-    a.nrhs = nrhs;
-    a.cand_beg = b.cand_beg;
-    a.cand_len = b.cand_len;
-    a.rank = b.rank;
-    a.skel_off = b.skel_off;
-    a.mask = b.mask;
-    a.T_off = b.T_off;
-    a.T = fp64 ? (const void*)b.T128 : (const void*)b.T64;
-    a.pmax = (int)b.tb_max;
     a.in = in;
     a.out = (t == 1) ? y : buf[cur];
     const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
-    const int pr = h->prof.begin(bf16 ? "applyb_u" : nrhs == 1 ? "apply1_u" : "applyn_u", st);
-    if (mfma) IDBF_HIP_CHECK(launch_apply_gemm(a, 2, 2 * b.rank_max, b.cand_max, bf16, st));
-    else IDBF_HIP_CHECK(launch_apply_u(a, fp64, st));
+    const int pr = h->prof.begin(name(adj ? 'v' : 'u'), st);
+    if (mfma) IDBF_HIP_CHECK(launch_apply_gemm(a, 2, 2 * b.rank_max, b.cand_max, bf16, st, adj));
+    else IDBF_HIP_CHECK(launch_apply_u(a, fp64, st, adj));
     h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T) * nrhs);
     in = a.out;
     cur ^= 1;
   }
   return IDBF_OK;
+}
+
+}  // namespace
+
+idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype, void* stream) {
+  return apply_impl(h, x, y, nrhs, dtype, stream, false);
+}
+
+idbf_status idbf_apply_adjoint(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype, void* stream) {
+  return apply_impl(h, x, y, nrhs, dtype, stream, true);
 }
 
 idbf_status idbf_apply_batched(int32_t count, const idbf_handle* hs, const void* const* x, void* const* y,

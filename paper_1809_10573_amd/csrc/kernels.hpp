@@ -197,7 +197,8 @@ hipError_t launch_pack_meta(const int64_t* t_off, const uint64_t* mask, const in
 struct StageArgs {
   const ApplyMeta* meta;   // per ID (V, U stages)
   int64_t n;               // IDs (V stage) or units (U stage) or U_H IDs (S stage)
-  int nn;                  // U stage: nodes per partner row of the level (2^(L-t+1))
+  int nn;                  // U stage: nodes per partner row of the level (2^(L-t+1));
+                           // adjoint S stage: 2^d
   int64_t nrhs;
   const int32_t* cand_beg;
   const int32_t* cand_len;
@@ -219,12 +220,34 @@ struct StageArgs {
   const int32_t* cbeg;
   const int32_t* clen;
 };
-hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st);
-hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st);
-hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st);
-// matrix-core stage kernels (complex64 data): mode 0 V, 1 S, 2 U; kmax_unit
+// Block jb of the middle-stage group q.  Forward: the U_H ID q owns the
+// consecutive blocks q nsub + jb.  Adjoint: the V_H ID q = p 2^d + C' meets
+// the blocks S(R, C') of the U_H IDs (R, C' >> sh), R = (p << sh) + jb
+// (A.nn = 2^d, A.nsub = 2^sh).
+template <bool ADJ>
+__device__ __forceinline__ int64_t middle_block(const StageArgs& A, int64_t q, int jb) {
+  if constexpr (!ADJ) {
+    return q * A.nsub + jb;
+  } else {
+    const int sh = __builtin_ctz((unsigned)A.nsub);
+    const int64_t p = q / A.nn, cn = q % A.nn;
+    return ((cn >> sh) * A.nn + (p << sh) + jb) * A.nsub + (cn & (A.nsub - 1));
+  }
+}
+
+// Stage launchers, named by the shape of the stage (V: IDs read a candidate
+// segment and write their skeleton rows; U: ID pairs write a shared
+// candidate segment; S: the middle factor).  adj: the adjoint of the other
+// factor of that shape -- V-shaped over U factors (conj(T), T row-major),
+// U-shaped over V factors (conj(T), T column-major), S^H grouped by V_H ID
+// (nn = 2^d).
+hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st, bool adj = false);
+hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st, bool adj = false);
+hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st, bool adj = false);
+// matrix-core stage kernels (complex64 data): mode 0 V, 1 S, 2 U (the shape,
+// as above, with adj selecting the adjoint of the other factor); kmax_unit
 // and mmax_unit bound the K and M of every unit of the stage (size the LDS of A)
 hipError_t launch_apply_gemm(const StageArgs& a, int mode, int kmax_unit, int mmax_unit, bool bf16,
-                             hipStream_t st);
+                             hipStream_t st, bool adj = false);
 
 }  // namespace idbf

@@ -58,6 +58,8 @@ def test_argument_errors_without_gpu():
     o.oversample = 0
     assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1e-6, 8, C.byref(o), C.byref(h)) == B.EINVAL
     assert lib.idbf_apply(None, fake, fake, 1, B.C128, None) == B.EINVAL
+    assert lib.idbf_apply_adjoint(None, fake, fake, 1, B.C128, None) == B.EINVAL
+    assert b"handle is NULL" in lib.idbf_last_error()
     assert lib.idbf_get_info(None, None) == B.EINVAL
     assert lib.idbf_batch_sizes(None, 0, 1, None, None, None) == B.EINVAL
     assert lib.idbf_sample(C.byref(ph), fake, fake, fake, -1, fake, 3, fake, None) == B.EINVAL

@@ -172,3 +172,46 @@ def test_mock_chebyshev_beats_random_sampling():
                                                               seed=5), g), ex)
            for s in ("mockcheb", "random")}
     assert err["random"] > 10 * err["mockcheb"], err
+
+
+# ------------------------------------------------------------------ adjoint
+@pytest.mark.parametrize("N,leaf,kind,tol,os_", [(1024, 8, "dft", 1e-10, 1), (512, 16, "fio", 1e-6, 2),
+                                                 (256, 2, "fio", 1e-8, 1), (512, 8, "nufft", 1e-8, 2),
+                                                 (16, 8, "dft", 1e-10, 1)])
+def test_adjoint_identity(N, leaf, kind, tol, os_):
+    # <K~ x, y> = <x, K~^H y> for the same factors: pins the reversed,
+    # conjugate-transposed stages against the (independently pinned) apply
+    ph = I.fio_phase(1.0, 1.0) if kind == "fio" else I.dft_phase()
+    X, O = I.nufft_points(N, seed=2) if kind == "nufft" else I.uniform_grid(N)
+    F = oracle.build(ph, X, O, leaf, tol, oversample=os_)
+    x = I.gaussian_vectors(N, 3, seed=1)
+    y = I.gaussian_vectors(N, 3, seed=2)
+    lhs = np.einsum("ij,ij->j", y.conj(), oracle.apply(F, x))
+    rhs = np.einsum("ij,ij->j", oracle.apply_adjoint(F, y).conj(), x)
+    scale = np.linalg.norm(x, axis=0) * np.linalg.norm(y, axis=0) * np.linalg.norm(oracle.apply(F, x)) / \
+        np.linalg.norm(x)
+    assert np.max(np.abs(lhs - rhs) / scale) < 1e-13
+
+
+def test_adjoint_is_conjugate_transpose_of_densified_factors():
+    N, leaf = 64, 4
+    ph = I.fio_phase(1.0, 2.0)
+    X, O = I.uniform_grid(N)
+    F = oracle.build(ph, X, O, leaf, 1e-8, oversample=2)
+    A = oracle.apply_adjoint(F, np.eye(N, dtype=np.complex128))
+    assert np.max(np.abs(A - oracle.densify(F).conj().T)) < 1e-13
+    # and the product of the explicit factors, conjugate transposed in reverse
+    Fs = oracle.factor_matrices(F)
+    P = reduce(lambda a, b: a @ b, [f.conj().T for f in Fs[::-1]])
+    assert np.max(np.abs(A - P)) < 1e-12
+
+
+def test_adjoint_with_full_sampling_reproduces_K_H():
+    # tol 1e-13 with every allowed point sampled: K~^H equals K^H
+    N, leaf = 256, 4
+    W, Xp = I.nufft_points(N, seed=3)
+    ph = I.dft_phase()
+    F = oracle.build(ph, W, Xp, leaf, 1e-13, sample_all=True)
+    K = oracle.entries(ph, W, Xp, np.arange(N), np.arange(N))
+    g = I.gaussian_vectors(N, None, seed=4)
+    assert oracle.relative_error(oracle.apply_adjoint(F, g), K.conj().T @ g) < 1e-11
