@@ -179,15 +179,21 @@ def _ablation(B, torch, dev, stream) -> dict:
     return out
 
 
-def _nufft(B, torch, dev, stream) -> dict:
-    """Example 3, the non-uniform Fourier transform, at the workload's size and
-    settings (N = 2^20, leaf 16, tol 1e-6, t = 2): rows at random frequencies
-    in [-N/2, N/2), columns at random points in [0, 1).  Construction wall
-    time and its ID-kernel time, the complex64 1-RHS apply (stored bytes / time,
-    as the main line), and epsilon^a on 256 exact rows.  Measured once."""
+def _example(B, torch, dev, stream, kind: str) -> dict:
+    """Examples 3 and 2 of the paper at the workload's size and settings
+    (N = 2^20, leaf 16, tol 1e-6, t = 2): the non-uniform Fourier transform
+    (rows at random frequencies in [-N/2, N/2), columns at random points in
+    [0, 1)) or the Schloemilch kernel J_0(g w) (g_k = (k-1)/N, w_n = n pi).
+    Construction wall time and its ID-kernel time, the complex64 1-RHS apply
+    (stored bytes / time, as the main line), and epsilon^a on 256 exact rows.
+    Measured once."""
     N = WORKLOAD["N"]
-    ph = I.dft_phase()
-    Wh, Xh = I.nufft_points(N, seed=1)
+    if kind == "nufft":
+        ph = I.dft_phase()
+        Wh, Xh = I.nufft_points(N, seed=1)
+    else:
+        ph = I.j0_kernel()
+        Wh, Xh = I.schlomilch_points(N)
     Wd, Xd = torch.as_tensor(Wh, device=dev), torch.as_tensor(Xh, device=dev)
     g = torch.as_tensor(I.gaussian_vectors(N, None, 7), device=dev)
     g64 = g.to(torch.complex64)
@@ -353,7 +359,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the many-instance measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--no-ablation", action="store_true", help="skip the sampler / fixed-rank ablation")
-    ap.add_argument("--no-nufft", action="store_true", help="skip the non-uniform Fourier transform line")
+    ap.add_argument("--no-examples", action="store_true",
+                    help="skip the non-uniform Fourier transform and Schloemilch lines")
     ap.add_argument("--only", choices=["construct", "copy"], help="run one piece for a counter pass")
     args = ap.parse_args()
     if args.only:
@@ -536,8 +543,9 @@ def main() -> int:
         out["learned"] = _learned(B, torch, dev, stream)
     if not args.no_ablation:
         out["ablation"] = _ablation(B, torch, dev, stream)
-    if not args.no_nufft:
-        out["nufft"] = _nufft(B, torch, dev, stream)
+    if not args.no_examples:
+        out["nufft"] = _example(B, torch, dev, stream, "nufft")
+        out["schlomilch_j0"] = _example(B, torch, dev, stream, "j0")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -38,19 +38,23 @@ typedef enum idbf_status {
   IDBF_EINVAL = 1,        /* invalid argument (sizes, pointers, tolerances) */
   IDBF_ENOMEM = 2,        /* device allocation failed or exceeded opts.mem_cap_bytes */
   IDBF_EHIP = 3,          /* a HIP runtime call failed */
-  IDBF_ERANK = 4,         /* an ID needed a rank above the supported maximum (32) */
-  IDBF_EUNSUPPORTED = 5   /* a candidate set above 64 or a sample set above 128 */
+  IDBF_ERANK = 4,         /* an ID needed a rank above the supported maximum (64) */
+  IDBF_EUNSUPPORTED = 5   /* a candidate set above 128 or a sample set above 128 */
 } idbf_status;
 
-/* Phase functions (Example 1 and the DFT kernel):
+/* Kernels K(x, xi) = exp(2 pi i Phi(x, xi)) (Example 1 and the DFT kernel,
+ * which on random points is Example 3's non-uniform transform):
  *   IDBF_PHASE_DFT: Phi(x, xi) = -x * xi
  *   IDBF_PHASE_FIO: Phi(x, xi) = x * xi + c(x) |xi|,
- *                   c(x) = (c0 + a * sin(2 pi freq x)) / cdiv              */
-enum { IDBF_PHASE_DFT = 0, IDBF_PHASE_FIO = 1 };
+ *                   c(x) = (c0 + a * sin(2 pi freq x)) / cdiv
+ * and the Schloemilch kernel of Example 2 (eq. S, nu = 0):
+ *   IDBF_PHASE_J0:  K(x, xi) = J_0(x xi), real, at the FP64 product x xi
+ *                   (Miller's recurrence below 25, Hankel's expansion above;
+ *                   |x xi| < 2^24 pi/2)                                    */
+enum { IDBF_PHASE_DFT = 0, IDBF_PHASE_FIO = 1, IDBF_PHASE_J0 = 2 };
 
-/* Apply precisions: complex128 arithmetic on FP64 factors, or complex64
- * arithmetic on FP32 copies of the same FP64-constructed factors. */
-/* Element types / arithmetic of the apply.  IDBF_C64_BF16X3 keeps complex64
+/* Element types / arithmetic of the apply: complex128 on the FP64 factors,
+ * complex64 on FP32 copies of the same FP64-constructed factors.  IDBF_C64_BF16X3 keeps complex64
  * input and output but forms the products of the many-RHS stages from BF16
  * hi/lo splits (a = a_hi + a_lo; a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi) on
  * the matrix cores with FP32 accumulation. */
@@ -60,9 +64,9 @@ enum { IDBF_C128 = 0, IDBF_C64 = 1, IDBF_C64_BF16X3 = 2 };
 enum { IDBF_SIDE_U = 0, IDBF_SIDE_V = 1 };
 
 typedef struct idbf_phase {
-  int32_t kind;   /* IDBF_PHASE_DFT or IDBF_PHASE_FIO */
+  int32_t kind;   /* IDBF_PHASE_DFT, IDBF_PHASE_FIO or IDBF_PHASE_J0 */
   int32_t reserved;
-  double c0, a, freq, cdiv;  /* c(x) parameters; ignored for the DFT; cdiv != 0 */
+  double c0, a, freq, cdiv;  /* c(x) parameters (FIO only; cdiv != 0 there) */
 } idbf_phase;
 
 enum { IDBF_FLAG_PROFILE = 1 }; /* record per-launch device times (idbf_profile_read) */

@@ -22,6 +22,8 @@ to be checked against the paper by eye:
                   of Sections 2.2-2.4) and the factor-by-factor apply
                   (eq. finishIDBF) and its adjoint, plus ``densify`` for
                   small N.
+* ``bessel``   -- J_0 for Example 2's Schloemilch kernel (Miller's backward
+                  recurrence below 25, Hankel's expansion above).
 * ``mlp``      -- not in the paper: the rank-proposal network (forward,
                   backpropagation, Adam), the randomized residual acceptance
                   test and the SplitMix64 counter generator of the check rows.
@@ -34,18 +36,18 @@ closed forms, LAPACK, SVD bounds, brute force or exactness identities, except
 the Mock-Chebyshev rule itself (``sampling.mock_chebyshev``), whose parity is
 unpinned beyond hand-worked cases and the end-to-end error it produces.
 """
-from .kernel import (PHASE_DFT, PHASE_FIO, amplitude_shift, phase_mod1, entries,
+from .kernel import (PHASE_DFT, PHASE_FIO, PHASE_J0, amplitude_shift, phase_mod1, entries,
                      matvec_rows, dense_matvec, dft_closed_form, fio_const_closed_form,
                      relative_error)
 from .interp import PIVOT_TIE_REL, column_id, ColumnID
 from .sampling import chebyshev_fraction, mock_chebyshev
 from .idbf import Factors, build, apply, apply_adjoint, densify, tree_sizes, factor_matrices, sample_count, SAMPLE_CAP
-from . import mlp
+from . import bessel, mlp
 
 __all__ = [
-    "PHASE_DFT", "PHASE_FIO", "amplitude_shift", "phase_mod1", "entries",
+    "PHASE_DFT", "PHASE_FIO", "PHASE_J0", "amplitude_shift", "phase_mod1", "entries",
     "matvec_rows", "dense_matvec", "dft_closed_form", "fio_const_closed_form",
     "relative_error", "PIVOT_TIE_REL", "column_id", "ColumnID",
     "chebyshev_fraction", "mock_chebyshev", "Factors", "build", "apply",
-    "apply_adjoint", "densify", "tree_sizes", "factor_matrices", "sample_count", "SAMPLE_CAP", "mlp",
+    "apply_adjoint", "densify", "tree_sizes", "factor_matrices", "sample_count", "SAMPLE_CAP", "bessel", "mlp",
 ]

@@ -7,6 +7,12 @@ form a(x, xi) exp(2 pi i Phi(x, xi)) with a = 1; Example 1, eqs. 1D-FIO-kernal,
 * kind 0 (DFT):  Phi(x, xi) = -x * xi
 * kind 1 (FIO):  Phi(x, xi) = x * xi + c(x) |xi|,  c(x) = (c0 + a sin(2 pi freq x)) / cdiv
 
+and one kernel that is not of that form:
+
+* kind 2 (J0):   K(g, w) = J_0(g w), the Schloemilch expansion of Example 2
+                 (eq. S with nu = 0), real, evaluated at the float64 product
+                 by ``bessel.j0``.
+
 ``phase`` arguments are any object with attributes kind, c0, a, freq, cdiv.
 
 Phase evaluation.  At N = 2^20 the phase reaches ~10^5 turns, so a float64
@@ -22,8 +28,11 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import bessel
+
 PHASE_DFT = 0
 PHASE_FIO = 1
+PHASE_J0 = 2
 
 _LD = np.longdouble
 
@@ -54,9 +63,13 @@ def phase_mod1(phase, x, xi) -> np.ndarray:
 
 
 def entries(phase, X, Omega, rows, cols) -> np.ndarray:
-    """K(rows, cols) as a complex128 matrix: exp(2 pi i Phi(X[rows], Omega[cols]))."""
+    """K(rows, cols) as a complex128 matrix: exp(2 pi i Phi(X[rows], Omega[cols])),
+    or J_0(X[rows] Omega[cols]) for the Schloemilch kernel."""
     X = np.asarray(X, dtype=np.float64)
     Omega = np.asarray(Omega, dtype=np.float64)
+    if phase.kind == PHASE_J0:
+        z = X[np.asarray(rows)][:, None] * Omega[np.asarray(cols)][None, :]
+        return bessel.j0(z).astype(np.complex128)
     th = phase_mod1(phase, X[np.asarray(rows)], Omega[np.asarray(cols)])
     return np.exp(2j * np.pi * th)
 

@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libidbf.so")
 
 OK, EINVAL, ENOMEM, EHIP, ERANK, EUNSUPPORTED = range(6)
-PHASE_DFT, PHASE_FIO = 0, 1
+PHASE_DFT, PHASE_FIO, PHASE_J0 = 0, 1, 2
 C128, C64, C64_BF16X3 = 0, 1, 2
 SIDE_U, SIDE_V = 0, 1
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ERANK", 5: "EUNSUPPORTED"}

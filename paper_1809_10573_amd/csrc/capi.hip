@@ -174,7 +174,7 @@ idbf_status check_phase(const idbf_phase* phase) {
     set_error("phase is NULL");
     return IDBF_EINVAL;
   }
-  if (phase->kind != IDBF_PHASE_DFT && phase->kind != IDBF_PHASE_FIO) {
+  if (phase->kind != IDBF_PHASE_DFT && phase->kind != IDBF_PHASE_FIO && phase->kind != IDBF_PHASE_J0) {
     set_error("unknown phase kind %d", phase->kind);
     return IDBF_EINVAL;
   }

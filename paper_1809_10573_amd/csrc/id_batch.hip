@@ -42,6 +42,16 @@ __device__ double cheb_fraction(int j, int s) {
   return 0.5 * (1.0 - cos(M_PI * (double)j / (double)n));
 }
 
+// Target lo + (hi - lo) f, with the product and the sum rounded separately as
+// the definition is written: a fused multiply-add rounds once and can move a
+// target that sits on the midpoint of two inexact coordinates (points n pi,
+// f = 1/4) to the other side.
+__device__ __forceinline__ double cheb_target(double lo, double hi, double f) {
+#pragma clang fp contract(off)
+  const double span = hi - lo;
+  return lo + span * f;
+}
+
 // Coordinates of an index segment: direct[p] when a coordinate array is
 // given, else base[idx[p]].
 struct Seg {
@@ -196,7 +206,7 @@ __global__ __launch_bounds__(64 * kSelIds) void select_kernel(IdArgs A) {
     const int j = j0 + lane;
     int p = -1;
     if (j < s) {
-      const double z = lo + (hi - lo) * cheb_fraction(j, s);
+      const double z = cheb_target(lo, hi, cheb_fraction(j, s));
       p = nearest_pos(a, na, z);
       s_z[w][j] = z;
       s_p0[w][j] = p;

@@ -13,6 +13,8 @@ configurations this project measures:
   [-N/2, N/2) (0-based form of the paper's discretisation of Example 1);
 * sorted uniform random points for Example 3 (the non-uniform Fourier
   transform): frequencies in [-N/2, N/2) and points in [0, 1);
+* Example 2's Schloemilch points g_k = (k-1)/N and w_n = n pi for the
+  kernel J_0(g w);
 * phase ``Phi(x, xi) = -x*xi`` (the DFT kernel) or
   ``Phi(x, xi) = x*xi + c(x)|xi|`` with ``c(x) = (c0 + a*sin(2*pi*m*x))/cdiv``
   (the FIO kernel; the paper's own member is c0=2, a=0.2, m=1, cdiv=16);
@@ -27,6 +29,7 @@ import numpy as np
 
 PHASE_DFT = 0
 PHASE_FIO = 1
+PHASE_J0 = 2
 
 
 @dataclass(frozen=True)
@@ -35,6 +38,7 @@ class Phase:
 
     kind == PHASE_DFT: Phi = -x*xi.
     kind == PHASE_FIO: Phi = x*xi + c(x)*|xi|, c(x) = (c0 + a*sin(2*pi*freq*x)) / cdiv.
+    kind == PHASE_J0: not a phase: K(g, w) = J_0(g*w) (Example 2); no parameters.
     """
 
     kind: int
@@ -46,6 +50,18 @@ class Phase:
 
 def dft_phase() -> Phase:
     return Phase(PHASE_DFT, 0.0, 0.0, 0.0, 1.0)
+
+
+def j0_kernel() -> Phase:
+    """The Schloemilch kernel K(g, w) = J_0(g w) of Example 2."""
+    return Phase(PHASE_J0, 0.0, 0.0, 0.0, 1.0)
+
+
+def schlomilch_points(N: int) -> tuple[np.ndarray, np.ndarray]:
+    """Example 2's points: g_k = (k-1)/N and w_n = n pi, k, n = 1..N (float64,
+    ascending; w_n is the float64 product n * pi)."""
+    i = np.arange(N, dtype=np.float64)
+    return i / N, (i + 1.0) * np.pi
 
 
 def fio_phase(a: float = 1.0, freq: float = 1.0, c0: float = 2.0, cdiv: float = 8.0) -> Phase:

@@ -22,6 +22,9 @@ def _workload(kind, N):
     if kind == "nufft":
         W, Xp = I.nufft_points(N, seed=N + 1)
         return I.dft_phase(), W, Xp
+    if kind == "j0":
+        g, w = I.schlomilch_points(N)
+        return I.j0_kernel(), g, w
     X, O = I.uniform_grid(N)
     return (I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 1.0)), X, O
 
@@ -33,6 +36,7 @@ def _workload(kind, N):
     (256, 2, "fio", 1e-8, 1),       # leaf 2, L = 7
     (2048, 16, "fio", 1e-6, 2),     # the workload's shape at a small N
     (2048, 16, "nufft", 1e-6, 2),
+    (1024, 8, "j0", 1e-10, 2),      # real kernel: K^H = K^T
 ])
 def test_adjoint_matches_oracle_every_path(N, leaf, kind, tol, os_):
     ph, X, O = _workload(kind, N)
