@@ -288,7 +288,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   __shared__ int s_piv[kMaxRank];
   __shared__ int s_srank[kMaxRank];
   __shared__ double s_axj[2];
-  __shared__ double2 s_diag[kMaxRank];  // R_jj of each step
+  __shared__ double2 s_diag[kMaxRank];  // R_jj of each step (1 / R_jj once the loop ends)
   double* s_part = reinterpret_cast<double*>(s_raw);                                         // [W][CPL][64]
   double2* s_partc = reinterpret_cast<double2*>(s_raw + W * CPL * kWave * sizeof(double));  // [W][CPL][64]
   double2* s_R = reinterpret_cast<double2*>(s_raw);                                          // [kChunk][NC]
@@ -348,8 +348,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 
   const int kuser = min(min(s, c), A.kmax > 0 ? A.kmax : (1 << 30));
   bool pivoted[CPL];
+  int pstep[CPL];  // step at which the column became a pivot
 #pragma unroll
-  for (int cs = 0; cs < CPL; ++cs) pivoted[cs] = false;
+  for (int cs = 0; cs < CPL; ++cs) {
+    pivoted[cs] = false;
+    pstep[cs] = 0;
+  }
   double stop2 = 0.0;  // (tol |R_00|)^2
   int k = 0;
   bool zero_block = false, overflow = false;
@@ -522,7 +526,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     if (lane == pl) {
 #pragma unroll
       for (int cs = 0; cs < CPL; ++cs)
-        if (cs == pc) pivoted[cs] = true;
+        if (cs == pc) {
+          pivoted[cs] = true;
+          pstep[cs] = j;
+        }
     }
     if (threadIdx.x == 0) s_piv[j] = p;
     k = j + 1;
@@ -531,7 +538,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   if (zero_block) {
     k = 1;
 #pragma unroll
-    for (int cs = 0; cs < CPL; ++cs) pivoted[cs] = (cs == 0 && lane == 0);
+    for (int cs = 0; cs < CPL; ++cs) {
+      pivoted[cs] = (cs == 0 && lane == 0);
+      pstep[cs] = 0;
+    }
     if (threadIdx.x == 0) s_piv[0] = 0;
   }
   if (overflow && threadIdx.x == 0) atomicOr(A.status, kErrRank);
@@ -541,7 +551,14 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   const uint64_t msk0 = __ballot(pivoted[0] && lane < c);
   uint64_t msk1 = 0;
   if constexpr (CPL > 1) msk1 = __ballot(pivoted[CPL - 1] && lane + kWave < c);
-  for (int i = threadIdx.x; i < k; i += nthreads) s_srank[i] = skel_below(msk0, msk1, s_piv[i]);
+  for (int i = threadIdx.x; i < k; i += nthreads) {
+    s_srank[i] = skel_below(msk0, msk1, s_piv[i]);
+    if (!zero_block) {  // 1 / R_ii, for the solve
+      const double2 d = s_diag[i];
+      const double inv = 1.0 / cabs2(d);
+      s_diag[i] = make_double2(d.x * inv, -d.y * inv);
+    }
+  }
   if (w == 0) {
     if (lane == 0) {
       A.rank[q] = k;
@@ -555,11 +572,20 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     }
   }
   // Back-substitution T = R11^{-1} R12 in chunks of kChunk R rows staged in
-  // LDS, last chunk first; waves 0..CPL-1 own the columns (one per thread):
-  //   t_ii = (r_ii - sum_{l > ii} R[ii][piv_l] t_l) / R[ii][piv_ii],
-  // t_l of earlier (higher) chunks read back from this thread's T entries.
+  // LDS, last chunk first, with the columns permuted: pivot l at slot l,
+  // redundant candidate jr at slot k + jr, so both operands of
+  //   t_ii = (r_ii - sum_{l > ii} R[ii][piv_l] t_l) / R[ii][piv_ii]
+  // are direct loads.  Waves 0..CPL-1 own the redundant columns (one per
+  // thread); t_l of earlier (higher) chunks are read back from this thread's
+  // T entries.
   const int r = c - k;
   const int64_t off = A.T_off ? A.T_off[q] : q * (int64_t)kSlot;
+  int slot[CPL];
+#pragma unroll
+  for (int cs = 0; cs < CPL; ++cs) {
+    const int cc = lane + kWave * cs;
+    slot[cs] = pivoted[cs] ? pstep[cs] : k + cc - skel_below(msk0, msk1, cc);
+  }
   const int col = (w < CPL) ? w * kWave + lane : 0;
   const bool solver = (w < CPL) && col < c && !skel_bit(msk0, msk1, col);
   const int jr = solver ? col - skel_below(msk0, msk1, col) : 0;
@@ -575,27 +601,38 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 #pragma unroll
       for (int i = 0; i < R; ++i) {
         const int row = row0 + i;
-        if (row >= cb0 && row < ce) s_R[(row - cb0) * NC + lane + kWave * cs] = zero_block ? make_double2(0.0, 0.0) : a[cs][i];
+        if (row >= cb0 && row < ce && lane + kWave * cs < c)
+          s_R[(row - cb0) * NC + slot[cs]] = zero_block ? make_double2(0.0, 0.0) : a[cs][i];
       }
     __syncthreads();
     if (!solver) continue;
     for (int ii = ce - 1; ii >= cb0; --ii) {
       const double2* Ri = s_R + (ii - cb0) * NC;
-      double2 acc = Ri[col];
+      double2 acc = Ri[k + jr];
       if (!zero_block) {
-        for (int l = ii + 1; l < ce; ++l) {
-          const double2 rl = Ri[s_piv[l]];
-          acc = cfma(make_double2(-rl.x, -rl.y), s_R[(l - cb0) * NC + col], acc);
+        double2 acc1 = make_double2(0.0, 0.0), acc2 = acc1, acc3 = acc1;
+        const double2* tcol = s_R + k + jr - cb0 * NC;  // t_l at tcol[l * NC]
+        int l = ii + 1;
+        for (; l + 3 < ce; l += 4) {  // four independent chains
+          const double2 r0 = Ri[l], r1 = Ri[l + 1], r2 = Ri[l + 2], r3 = Ri[l + 3];
+          const double2 t0 = tcol[l * NC], t1 = tcol[(l + 1) * NC], t2 = tcol[(l + 2) * NC], t3 = tcol[(l + 3) * NC];
+          acc = cfma(make_double2(-r0.x, -r0.y), t0, acc);
+          acc1 = cfma(make_double2(-r1.x, -r1.y), t1, acc1);
+          acc2 = cfma(make_double2(-r2.x, -r2.y), t2, acc2);
+          acc3 = cfma(make_double2(-r3.x, -r3.y), t3, acc3);
         }
-        for (int l = ce; l < k; ++l) {
-          const double2 rl = Ri[s_piv[l]];
-          acc = cfma(make_double2(-rl.x, -rl.y), A.T128[t_index(l)], acc);
+        for (; l < ce; ++l) {
+          const double2 r0 = Ri[l];
+          acc = cfma(make_double2(-r0.x, -r0.y), tcol[l * NC], acc);
         }
-        const double2 d = s_diag[ii];
-        const double inv = 1.0 / cabs2(d);
-        acc = cmul(acc, make_double2(d.x * inv, -d.y * inv));
+        for (l = ce; l < k; ++l) {
+          const double2 rl = Ri[l];
+          acc1 = cfma(make_double2(-rl.x, -rl.y), A.T128[t_index(l)], acc1);
+        }
+        acc = cadd(cadd(acc, acc1), cadd(acc2, acc3));
+        acc = cmul(acc, s_diag[ii]);  // 1 / R_ii
       }
-      s_R[(ii - cb0) * NC + col] = acc;
+      s_R[(ii - cb0) * NC + k + jr] = acc;
       const int64_t e = t_index(ii);
       A.T128[e] = acc;
       if (A.T64) A.T64[e] = make_float2((float)acc.x, (float)acc.y);
