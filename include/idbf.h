@@ -3,8 +3,9 @@
  * factorization (IDBF) of Pang, Ho and Yang, arXiv:1809.10573.
  *
  * The library builds K ~= U^L ... U^h S^h V^h ... V^L (Section 2.4, eq. finishIDBF)
- * for K(x, xi) = exp(2 pi i Phi(x, xi)) sampled entry by entry (Introduction),
- * and applies it to blocks of vectors in O(N log N) per vector.
+ * for K(x, xi) = exp(2 pi i Phi(x, xi)) or J_0(x xi) sampled entry by entry
+ * (Introduction; Examples 1-3), and applies it or its adjoint to blocks of
+ * vectors in O(N log N) per vector.
  *
  * Conventions shared by every entry point:
  *  - Pointers documented as "device" are HIP device pointers on the current
@@ -54,10 +55,11 @@ typedef enum idbf_status {
 enum { IDBF_PHASE_DFT = 0, IDBF_PHASE_FIO = 1, IDBF_PHASE_J0 = 2 };
 
 /* Element types / arithmetic of the apply: complex128 on the FP64 factors,
- * complex64 on FP32 copies of the same FP64-constructed factors.  IDBF_C64_BF16X3 keeps complex64
- * input and output but forms the products of the many-RHS stages from BF16
- * hi/lo splits (a = a_hi + a_lo; a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi) on
- * the matrix cores with FP32 accumulation. */
+ * complex64 on FP32 copies of the same FP64-constructed factors.
+ * IDBF_C64_BF16X3 keeps complex64 input and output but forms the products of
+ * the many-RHS stages from BF16 hi/lo splits (a = a_hi + a_lo;
+ * a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi) on the matrix cores with FP32
+ * accumulation. */
 enum { IDBF_C128 = 0, IDBF_C64 = 1, IDBF_C64_BF16X3 = 2 };
 
 /* The two ID families of a level: U (row IDs) and V (column IDs). */
@@ -106,7 +108,7 @@ void idbf_opts_default(idbf_opts* o);
  *   phase  host; the phase function.
  *   X      device, N doubles, ascending: row points x_i.
  *   Omega  device, N doubles, ascending: column points xi_j.
- *   N      power of two >= leaf; leaf power of two in [1, 64].
+ *   N      power of two >= leaf; leaf power of two in [1, 128].
  *   tol    ID tolerance eps of eq. acc, 0 <= tol < 1.
  *   opts   host, nullable (defaults).
  *   out    host; receives the handle (NULL on failure).
@@ -116,7 +118,8 @@ void idbf_opts_default(idbf_opts* o);
  * Levels run U_1, V_1, ..., U_H, V_H with H = floor(L/2), L = log2(N/leaf);
  * then the middle factor's blocks are sampled.  Each ID samples
  * s = min(oversample * |cand|, |allowed|, 128) points.  Candidate sets must
- * stay <= 128 points (else IDBF_EUNSUPPORTED); ranks <= 64 (else IDBF_ERANK).  Synchronizes opts->stream.  The handle owns all factor
+ * stay <= 128 points (else IDBF_EUNSUPPORTED); ranks <= 64 (else
+ * IDBF_ERANK).  Synchronizes opts->stream.  The handle owns all factor
  * memory (FP64 factors and an FP32 copy) until idbf_destroy.
  */
 idbf_status idbf_construct(const idbf_phase* phase, const double* X, const double* Omega,
@@ -286,7 +289,8 @@ idbf_status idbf_middle_export(idbf_handle h, double* S, int64_t* S_off);
  * idbf_sample -- entry sampler: out[i * ncols + j] = K(X[rows[i]], Omega[cols[j]])
  * as complex128 (Introduction: each entry in O(1) operations).  The phase is
  * formed with an error-free product and reduced modulo 1 in FP64 before the
- * exponential.  rows, cols, out: device; X, Omega: device.
+ * exponential; J_0 entries are real (imaginary part 0).  rows, cols, out:
+ * device; X, Omega: device.
  */
 idbf_status idbf_sample(const idbf_phase* phase, const double* X, const double* Omega,
                         const int32_t* rows, int64_t nrows, const int32_t* cols, int64_t ncols,

@@ -9,9 +9,15 @@
 //           unit writes whole: v[skel] = w, v[red] = T^T w, summed over both
 //           IDs (T row-major, entry i*r + j).  No atomics, no zero fill.
 //
+// Adjoint (K~^H, the stages in reverse order, conjugate transposed): U_t^H has
+// a V stage's shape over the U factors (T row-major), V_t^H a U stage's
+// over the V factors (T column-major), and S^H groups the middle blocks by
+// V_H ID; the same kernels take an ADJ template flag.
+//
 // nrhs == 1: one wavefront per ID (unit), lane = candidate position.
-// nrhs > 1:  one workgroup per (ID, 64 right-hand sides); lanes over
-//            right-hand sides, so every load of z / w / x / y is coalesced.
+// nrhs > 1:  one workgroup per (ID or unit, 256 right-hand sides), one
+//            thread per right-hand side, so every load of z / w / x / y is
+//            coalesced (complex128; complex64 runs on the matrix cores).
 #include <algorithm>
 
 #include "kernels.hpp"

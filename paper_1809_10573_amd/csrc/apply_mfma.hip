@@ -7,6 +7,8 @@
 //   S stage (U_H ID):   w[rbeg + i]       = sum_b sum_col S_b(i, col) z[cbeg_b + col] (M = k_R, K = sum k_C')
 //   U stage (a unit):   v[cand_beg + l]   = sum_h ( l in skel_h ? w_h[b] : sum_i T_h(i, red(l)) w_h[i] )
 //                                                                          (M = c, K = k_0 + k_1)
+// The adjoint stages stage A^H of the other factor of the same shape (U_t^H
+// as a V unit, V_t^H as a U unit, S^H per V_H ID); the product is unchanged.
 // A (M x K complex: the factor entries and the identity parts) is staged in
 // LDS once per workgroup; every input row is read once per unit.  Rows of the
 // stage vectors are (row, rhs) complex64, right-hand sides fastest.
