@@ -205,6 +205,7 @@ struct HostStage {
   unsigned long long counts[kQrBuckets];
   unsigned long long cursors[kQrBuckets];
   int32_t bad[2];
+  double ends[2][2];  // first and last point of X and of Omega
 };
 
 struct LevelJob {
@@ -655,6 +656,9 @@ idbf_status points_begin(idbf_handle_s* h, const double* X, const double* Om) {
                        h->N, h->status);
     TRYHIP(hipGetLastError());
     TRYHIP(hipMemcpyAsync(&h->pin->bad[i], h->status, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    TRYHIP(hipMemcpyAsync(&h->pin->ends[i][0], pts[i], sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    TRYHIP(hipMemcpyAsync(&h->pin->ends[i][1], pts[i] + (h->N - 1), sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
   }
   return IDBF_OK;
 }
@@ -666,6 +670,17 @@ idbf_status points_finish(idbf_handle_s* h) {
       set_error("%s must be finite and strictly ascending (%d violations)", names[i], h->pin->bad[i]);
       return IDBF_EINVAL;
     }
+  if (h->ph.kind == IDBF_PHASE_J0) {
+    // J_0's argument reduction is exact for |x xi| < 2^24 C1 (C1: pi/2 to 27 bits);
+    // the points are ascending, so the largest |x| and |xi| sit at the ends
+    const auto amax = [](const double* e) { return std::max(std::fabs(e[0]), std::fabs(e[1])); };
+    const double zmax = amax(h->pin->ends[0]) * amax(h->pin->ends[1]);
+    const double limit = 16777216.0 * 0x1.921fb54p0;
+    if (!(zmax < limit)) {
+      set_error("J0 kernel: max |x xi| = %g is beyond the supported %g", zmax, limit);
+      return IDBF_EINVAL;
+    }
+  }
   return IDBF_OK;
 }
 

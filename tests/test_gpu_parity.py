@@ -355,6 +355,10 @@ def test_construct_errors():
         B.construct(I.fio_phase(1.0, 1.0), *I.uniform_grid(4096), 1e-6, 16, mem_cap_bytes=1 << 16,
                     device=DEV)
     assert e.value.status == B.ENOMEM
+    g, w = I.schlomilch_points(64)
+    with pytest.raises(B.IdbfError) as e:     # J_0 arguments beyond the exact reduction's range
+        B.construct(I.j0_kernel(), g, w * 1e6, 1e-6, 4, device=DEV)
+    assert e.value.status == B.EINVAL and "J0" in str(e.value)
 
 
 # ------------------------------------------------------------------ full size
