@@ -256,6 +256,7 @@ struct idbf_handle_s {
   int32_t* order = nullptr;    // IDs of the current level grouped by QR wavefronts
   unsigned long long* bucket = nullptr;  // [0, kQrBuckets): bucket counts, then the fill cursors
   int64_t* stats = nullptr;    // 12 int64 read back after each scan ([8, 11): work of every ID pass)
+  int64_t* scan_ws = nullptr;  // tile partials of the prefix scans (kScanWs int64)
   int32_t* status = nullptr;
   std::vector<Batch> U, V;
   int64_t nblk = 0, nnz_S = 0, nnz_S_res = 0, sblk_max = 0;
@@ -361,8 +362,8 @@ idbf_status level_begin(idbf_handle_s* h, const double* X, const double* Om, int
   d.samples = b.samples;
   int pr = h->prof.begin("level_desc", h->stream);
   TRYHIP(launch_desc(d, h->stream));
-  TRYHIP(launch_scan_i64(b.t_bound, n, b.T_off, b.cand_len, h->stats, h->stream));
-  TRYHIP(launch_scan_i32(b.samples, n, b.skel_off, nullptr, h->stats + 4, h->stream));
+  TRYHIP(launch_scan_i64(b.t_bound, n, b.T_off, b.cand_len, h->stats, h->scan_ws, h->stream));
+  TRYHIP(launch_scan_i32(b.samples, n, b.skel_off, nullptr, h->stats + 4, h->scan_ws, h->stream));
   const int32_t* qr_samples = b.samples;
   if (h->proposer) {  // proposed sample counts from the network's rank estimates
     float *F = nullptr, *y = nullptr;
@@ -513,7 +514,7 @@ idbf_status level_scan(idbf_handle_s* h) {
   TRYHIP(hipMemsetAsync(h->stats + 4, 0, 3 * sizeof(int64_t), h->stream));
   TRYHIP(launch_id_work(b.rank, b.cand_len, b.s_prop ? b.s_prop : b.samples, nullptr, n,
                         reinterpret_cast<unsigned long long*>(h->stats + 4), h->stream));
-  TRYHIP(launch_scan_i32(b.rank, n, b.skel_off, nullptr, h->stats, h->stream));
+  TRYHIP(launch_scan_i32(b.rank, n, b.skel_off, nullptr, h->stats, h->scan_ws, h->stream));
   TRYHIP(hipMemcpyAsync(h->stats + 7, h->status, sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
   h->prof.end(pr, h->stream);
   TRYHIP(hipMemcpyAsync(h->pin->st, h->stats, sizeof h->pin->st, hipMemcpyDeviceToHost, h->stream));
@@ -607,7 +608,7 @@ idbf_status middle_begin(idbf_handle_s* h) {
   m.nnz = reinterpret_cast<unsigned long long*>(h->stats + 4);
   TRYHIP(hipMemsetAsync(h->stats + 4, 0, sizeof(int64_t), h->stream));
   TRYHIP(launch_middle_desc(m, h->stream));
-  TRYHIP(launch_scan_i64(h->s_size, h->nblk, h->S_off, nullptr, h->stats, h->stream));
+  TRYHIP(launch_scan_i64(h->s_size, h->nblk, h->S_off, nullptr, h->stats, h->scan_ws, h->stream));
   TRYHIP(hipMemcpyAsync(h->pin->st, h->stats, sizeof h->pin->st, hipMemcpyDeviceToHost, h->stream));
   return IDBF_OK;
 }
@@ -698,6 +699,7 @@ idbf_status construct_setup(idbf_handle_s* h) {
     std::memset(h->pin, 0, sizeof(HostStage));
   }
   TRY(A.get(12, &h->stats));
+  TRY(A.get(kScanWs, &h->scan_ws));
   TRY(A.get(1, &h->status));
   TRY(A.get(h->N, &h->iota));
   if (h->H > 0) {

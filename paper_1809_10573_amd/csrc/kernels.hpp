@@ -130,11 +130,13 @@ hipError_t launch_desc(const DescArgs& a, hipStream_t st);
 
 // Exclusive scan of n values into off[0..n] (off[n] = total) plus the sum,
 // max and min of the values and the max of an optional second array, written
-// to stats[0..3].  One workgroup; fine for the <= 2^22 values of a level.
+// to stats[0..3].  ws: kScanWs int64 of device workspace (tile partials).
+constexpr int kScanMaxTiles = 1024;
+constexpr int64_t kScanWs = 5 * kScanMaxTiles;
 hipError_t launch_scan_i64(const int64_t* v, int64_t n, int64_t* off, const int32_t* aux,
-                           int64_t* stats, hipStream_t st);
+                           int64_t* stats, int64_t* ws, hipStream_t st);
 hipError_t launch_scan_i32(const int32_t* v, int64_t n, int32_t* off, const int32_t* aux,
-                           int64_t* stats, hipStream_t st);
+                           int64_t* stats, int64_t* ws, hipStream_t st);
 
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t st);
 // packed skeleton lists and their coordinates (base[index])

@@ -66,55 +66,128 @@ __global__ void desc_kernel(DescArgs A) {
   A.samples[q] = (int32_t)s;
 }
 
-template <typename V, typename O>
-__global__ __launch_bounds__(1024) void scan_kernel(const V* v, int64_t n, O* off, const int32_t* aux,
-                                                    int64_t* stats) {
-  __shared__ int64_t s_sum[1024];
-  __shared__ int64_t s_max[1024];
-  __shared__ int64_t s_min[1024];
-  __shared__ int64_t s_aux[1024];
-  const int tid = threadIdx.x;
-  const int64_t chunk = (n + 1023) / 1024;
-  const int64_t b = tid * chunk, e = min(n, b + chunk);
+// Exclusive prefix sums over a level's values (off[0 .. n], off[n] = total)
+// with their sum, max and min and the max of an optional second array, in
+// three launches: coalesced tile reductions, one workgroup scanning the tile
+// partials (stats and tile offsets), and a rescan of every tile.
+constexpr int kScanThreads = 256;
+
+__device__ __forceinline__ int64_t wave_incl_sum(int64_t x, int lane) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+template <typename V>
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const V* v, int64_t n, const int32_t* aux,
+                                                                  int64_t tile, int64_t* ws) {
+  __shared__ int64_t s_p[4][kScanThreads / kWave];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int64_t beg = blockIdx.x * tile, end = min(n, beg + tile);
   int64_t sum = 0, mx = INT64_MIN, mn = INT64_MAX, ax = INT64_MIN;
-  for (int64_t i = b; i < e; ++i) {
+  for (int64_t i = beg + tid; i < end; i += kScanThreads) {
     const int64_t x = (int64_t)v[i];
     sum += x;
     mx = max(mx, x);
     mn = min(mn, x);
     if (aux) ax = max(ax, (int64_t)aux[i]);
   }
-  s_sum[tid] = sum;
-  s_max[tid] = mx;
-  s_min[tid] = mn;
-  s_aux[tid] = ax;
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    sum += __shfl_xor(sum, d, kWave);
+    mx = max(mx, __shfl_xor(mx, d, kWave));
+    mn = min(mn, __shfl_xor(mn, d, kWave));
+    ax = max(ax, __shfl_xor(ax, d, kWave));
+  }
+  if (lane == 0) {
+    s_p[0][w] = sum;
+    s_p[1][w] = mx;
+    s_p[2][w] = mn;
+    s_p[3][w] = ax;
+  }
   __syncthreads();
-  // inclusive Hillis-Steele scan of the chunk sums
-  for (int d = 1; d < 1024; d <<= 1) {
-    const int64_t add = (tid >= d) ? s_sum[tid - d] : 0;
-    __syncthreads();
-    s_sum[tid] += add;
-    __syncthreads();
-  }
-  int64_t run = (tid == 0) ? 0 : s_sum[tid - 1];
-  for (int64_t i = b; i < e; ++i) {
-    off[i] = (O)run;
-    run += (int64_t)v[i];
-  }
-  if (tid == 1023) off[n] = (O)s_sum[1023];
-  for (int d = 512; d > 0; d >>= 1) {
-    if (tid < d) {
-      s_max[tid] = max(s_max[tid], s_max[tid + d]);
-      s_min[tid] = min(s_min[tid], s_min[tid + d]);
-      s_aux[tid] = max(s_aux[tid], s_aux[tid + d]);
-    }
-    __syncthreads();
-  }
   if (tid == 0) {
-    stats[0] = s_sum[1023];
-    stats[1] = s_max[0];
-    stats[2] = s_min[0];
-    stats[3] = s_aux[0];
+    for (int k = 1; k < kScanThreads / kWave; ++k) {
+      sum += s_p[0][k];
+      mx = max(mx, s_p[1][k]);
+      mn = min(mn, s_p[2][k]);
+      ax = max(ax, s_p[3][k]);
+    }
+    int64_t* o = ws + 4 * blockIdx.x;
+    o[0] = sum;
+    o[1] = mx;
+    o[2] = mn;
+    o[3] = ax;
+  }
+}
+
+// One workgroup: exclusive offsets of the nb <= kScanMaxTiles tile sums (to
+// ws[4 kScanMaxTiles + b]), the totals to stats, and off[n].
+template <typename O>
+__global__ __launch_bounds__(kScanMaxTiles) void scan_partials_kernel(int nb, int64_t n, int64_t* ws,
+                                                                     int64_t* stats, O* off) {
+  __shared__ int64_t s_w[4][kScanMaxTiles / kWave];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const bool on = tid < nb;
+  const int64_t x = on ? ws[4 * tid] : 0;
+  const int64_t incl = wave_incl_sum(x, lane);
+  int64_t mx = on ? ws[4 * tid + 1] : INT64_MIN, mn = on ? ws[4 * tid + 2] : INT64_MAX;
+  int64_t ax = on ? ws[4 * tid + 3] : INT64_MIN;
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    mx = max(mx, __shfl_xor(mx, d, kWave));
+    mn = min(mn, __shfl_xor(mn, d, kWave));
+    ax = max(ax, __shfl_xor(ax, d, kWave));
+  }
+  if (lane == kWave - 1) s_w[0][w] = incl;
+  if (lane == 0) {
+    s_w[1][w] = mx;
+    s_w[2][w] = mn;
+    s_w[3][w] = ax;
+  }
+  __syncthreads();
+  int64_t before = 0;
+  for (int k = 0; k < w; ++k) before += s_w[0][k];
+  if (on) ws[4 * kScanMaxTiles + tid] = before + incl - x;
+  if (tid == 0) {
+    int64_t tot = 0;
+    for (int k = 0; k < kScanMaxTiles / kWave; ++k) {
+      tot += s_w[0][k];
+      mx = max(mx, s_w[1][k]);
+      mn = min(mn, s_w[2][k]);
+      ax = max(ax, s_w[3][k]);
+    }
+    stats[0] = tot;
+    stats[1] = mx;
+    stats[2] = mn;
+    stats[3] = ax;
+    off[n] = (O)tot;
+  }
+}
+
+template <typename V, typename O>
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(const V* v, int64_t n, int64_t tile,
+                                                                 const int64_t* ws, O* off) {
+  __shared__ int64_t s_w[kScanThreads / kWave];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int64_t beg = blockIdx.x * tile, end = min(n, beg + tile);
+  int64_t carry = ws[4 * kScanMaxTiles + blockIdx.x];
+  for (int64_t c0 = beg; c0 < end; c0 += kScanThreads) {
+    const int64_t i = c0 + tid;
+    const int64_t x = i < end ? (int64_t)v[i] : 0;
+    const int64_t incl = wave_incl_sum(x, lane);
+    if (lane == kWave - 1) s_w[w] = incl;
+    __syncthreads();
+    int64_t before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / kWave; ++k) {
+      if (k < w) before += s_w[k];
+      total += s_w[k];
+    }
+    if (i < end) off[i] = (O)(carry + before + incl - x);
+    carry += total;
+    __syncthreads();  // s_w is rewritten by the next chunk
   }
 }
 
@@ -268,16 +341,28 @@ hipError_t launch_desc(const DescArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan_i64(const int64_t* v, int64_t n, int64_t* off, const int32_t* aux, int64_t* stats,
-                           hipStream_t st) {
-  hipLaunchKernelGGL((scan_kernel<int64_t, int64_t>), dim3(1), dim3(1024), 0, st, v, n, off, aux, stats);
+template <typename V, typename O>
+hipError_t launch_scan(const V* v, int64_t n, O* off, const int32_t* aux, int64_t* stats, int64_t* ws,
+                       hipStream_t st) {
+  // tiles: at most kScanMaxTiles, each a whole number of kScanThreads chunks
+  const int64_t chunks = std::max<int64_t>(1, (n + kScanThreads - 1) / kScanThreads);
+  const int64_t per = (chunks + kScanMaxTiles - 1) / kScanMaxTiles;
+  const int64_t tile = per * kScanThreads;
+  const int nb = (int)std::max<int64_t>(1, (n + tile - 1) / tile);
+  hipLaunchKernelGGL((scan_reduce_kernel<V>), dim3(nb), dim3(kScanThreads), 0, st, v, n, aux, tile, ws);
+  hipLaunchKernelGGL((scan_partials_kernel<O>), dim3(1), dim3(kScanMaxTiles), 0, st, nb, n, ws, stats, off);
+  hipLaunchKernelGGL((scan_apply_kernel<V, O>), dim3(nb), dim3(kScanThreads), 0, st, v, n, tile, ws, off);
   return hipGetLastError();
 }
 
+hipError_t launch_scan_i64(const int64_t* v, int64_t n, int64_t* off, const int32_t* aux, int64_t* stats,
+                           int64_t* ws, hipStream_t st) {
+  return launch_scan(v, n, off, aux, stats, ws, st);
+}
+
 hipError_t launch_scan_i32(const int32_t* v, int64_t n, int32_t* off, const int32_t* aux, int64_t* stats,
-                           hipStream_t st) {
-  hipLaunchKernelGGL((scan_kernel<int32_t, int32_t>), dim3(1), dim3(1024), 0, st, v, n, off, aux, stats);
-  return hipGetLastError();
+                           int64_t* ws, hipStream_t st) {
+  return launch_scan(v, n, off, aux, stats, ws, st);
 }
 
 hipError_t launch_iota(int32_t* p, int64_t n, hipStream_t st) {
