@@ -258,6 +258,29 @@ __device__ __forceinline__ double wave_max_nonneg(double v) {
   return __hiloint2double(mh, (int)ml);
 }
 
+// Maximum over each group of 64 / G lanes (G = 2: lanes [32 g, 32 g + 32);
+// G = 4: rows of 16), by the same two 32-bit passes, returned in every lane
+// of the group: row_shr steps leave each row's maximum in its lane 15,
+// row_bcast:15 joins rows 0-1 and 2-3, and the group's last lane is read.
+template <typename T, int G>
+__device__ __forceinline__ T group_max32(T v, T identity, int lane) {
+  v = dpp_max<T, 0x111, 0xf>(v, identity);  // row_shr:1
+  v = dpp_max<T, 0x112, 0xf>(v, identity);  // row_shr:2
+  v = dpp_max<T, 0x114, 0xf>(v, identity);  // row_shr:4
+  v = dpp_max<T, 0x118, 0xf>(v, identity);  // row_shr:8
+  if constexpr (G == 2) v = dpp_max<T, 0x142, 0xa>(v, identity);  // row_bcast:15
+  constexpr int last = kWave / G - 1;
+  return (T)__shfl((int)v, lane | last, kWave);
+}
+template <int G>
+__device__ __forceinline__ double group_max_nonneg(double v, int lane) {
+  const int hi = __double2hiint(v);
+  const int mh = group_max32<int, G>(hi, INT_MIN, lane);
+  const unsigned lo = (hi == mh) ? (unsigned)__double2loint(v) : 0u;
+  const unsigned ml = group_max32<unsigned, G>(lo, 0u, lane);
+  return __hiloint2double(mh, (int)ml);
+}
+
 __device__ __forceinline__ bool skel_bit(uint64_t lo, uint64_t hi, int p) {
   return p < 64 ? ((lo >> p) & 1ull) : ((hi >> (p - 64)) & 1ull);
 }
@@ -640,6 +663,322 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   }
 }
 
+
+// G IDs per workgroup of W wavefronts, for small IDs (G = 2: up to 32
+// candidates and 64 samples; G = 4: up to 16 and 32).  ID g owns lanes
+// [g GL, g GL + GL), GL = 64 / G, one candidate per lane, and wavefront w
+// holds sampled rows [16 w, 16 w + 16) of every ID.  The IDs take their
+// pivot steps together; an ID that has stopped sits out the remaining steps.
+// The arithmetic of each ID is the one-ID kernel's.
+template <int W, int G>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) void id_kernel_g(IdArgs A,
+                                                                                                int64_t n) {
+  constexpr int R = 16, SMAX = R * W, GL = kWave / G;
+  constexpr int kChunk = W >= 3 ? 32 : 16;  // R rows staged per solve chunk
+  constexpr size_t kPart = (size_t)W * kWave * (sizeof(double) + sizeof(double2));
+  constexpr size_t kRrows = (size_t)kChunk * kWave * sizeof(double2);
+  __shared__ __attribute__((aligned(16))) unsigned char s_raw[kPart > kRrows ? kPart : kRrows];
+  __shared__ double s_coord[G][SMAX];
+  __shared__ double s_cx[G][SMAX];
+  __shared__ double2 s_v[G][SMAX];
+  __shared__ int s_piv[G][GL];      // ranks are at most c <= GL
+  __shared__ int s_srank[G][GL];
+  __shared__ double s_axj[G][2];
+  __shared__ double2 s_diag[G][GL];
+  __shared__ int s_k[G];
+  double* s_part = reinterpret_cast<double*>(s_raw);                                   // [W][64]
+  double2* s_partc = reinterpret_cast<double2*>(s_raw + W * kWave * sizeof(double));  // [W][64]
+  double2* s_R = reinterpret_cast<double2*>(s_raw);                                    // [kChunk][64]
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int nthreads = kWave * W;
+  const int gi = lane / GL, gl = lane % GL;  // this lane's ID in the workgroup, and its column
+  const bool isV = (A.side == IDBF_SIDE_V);
+  const bool fio = (A.ph.kind == IDBF_PHASE_FIO);
+  auto id_of = [&](int g) -> int64_t {  // -1 past the end of the bucket
+    const int64_t qi = blockIdx.x * (int64_t)G + g;
+    return qi < n ? (A.order ? (int64_t)A.order[qi] : qi) : -1;
+  };
+  auto samples_of = [&](int64_t q, int c, int na) {
+    return A.samples ? A.samples[q] : min(min(A.oversample * c, na), kMaxSamples);
+  };
+  // this lane's ID; an ID outside the kernel's limits is reported and sits out
+  const int64_t q = id_of(gi);
+  int c = 0, cb = 0, s = 0;
+  if (q >= 0) {
+    c = A.cand_len[q];
+    cb = A.cand_beg[q];
+    const int na = A.allow_len[q];
+    s = samples_of(q, c, na);
+    if (c < 1 || c > GL || na < 1 || s < 1 || s > SMAX || s > na) {
+      if (w == 0 && gl == 0) atomicOr(A.status, kErrSize);
+      c = 0;
+      s = 0;
+    }
+  }
+  const bool member = c > 0;  // this lane's ID takes part
+
+  const int col = gl;
+  int gidx = 0;
+  double ccoord = 0.0, ccx = 0.0;
+  if (col < c) {
+    gidx = A.cand_idx[cb + col];
+    ccoord = A.cand_coord ? A.cand_coord[cb + col] : (isV ? A.Om : A.X)[gidx];
+    if (!isV && fio) ccx = amplitude_shift(A.ph, ccoord);
+  }
+  for (int e = threadIdx.x; e < G * SMAX; e += nthreads) {  // sampled coordinates of every ID
+    const int g = e / SMAX, j = e % SMAX;
+    const int64_t qg = id_of(g);
+    if (qg < 0) continue;
+    const int cg = A.cand_len[qg], nag = A.allow_len[qg];
+    const int sg = samples_of(qg, cg, nag);
+    if (j >= sg || j >= nag) continue;
+    const int ab = A.allow_beg[qg];
+    const int pos = A.samp_pos[qg * (int64_t)kMaxSamples + j];
+    const double v = A.allow_coord ? A.allow_coord[ab + pos] : (isV ? A.X : A.Om)[A.allow_idx[ab + pos]];
+    s_coord[g][j] = v;
+    s_cx[g][j] = (isV && fio) ? amplitude_shift(A.ph, v) : 0.0;
+  }
+  __syncthreads();
+
+  const int row0 = w * R;
+  double2 a[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int row = row0 + i;
+    double2 v = make_double2(0.0, 0.0);
+    if (col < c && row < s)
+      v = isV ? kernel_entry(A.ph, s_coord[gi][row], s_cx[gi][row], ccoord)
+              : kernel_entry(A.ph, ccoord, ccx, s_coord[gi][row]);
+    a[i] = v;
+  }
+
+  const int kuser = min(min(s, c), A.kmax > 0 ? A.kmax : (1 << 30));
+  bool pivoted = false;
+  int pstep = 0;
+  double stop2 = 0.0;
+  int k = 0;
+  bool done = !member, zero_block = false, overflow = false;
+  double part;
+  {
+    double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      if (i & 1) p1 = __builtin_fma(a[i].y, a[i].y, __builtin_fma(a[i].x, a[i].x, p1));
+      else p0 = __builtin_fma(a[i].y, a[i].y, __builtin_fma(a[i].x, a[i].x, p0));
+    }
+    part = p0 + p1;
+  }
+  const uint64_t gmask = (GL == 64) ? ~0ull : ((1ull << GL) - 1ull);
+  for (int j = 0;; ++j) {
+    const bool live = row0 + R > j;
+    const bool edge = live && row0 <= j;
+    double nrm2 = part;
+    if constexpr (W > 1) {
+      s_part[w * kWave + lane] = part;
+      __syncthreads();
+      nrm2 = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < W; ++ww) nrm2 += s_part[ww * kWave + lane];
+    }
+    const bool eligible = !done && col < c && !pivoted;
+    const double nq = eligible ? nrm2 : -1.0;
+    const double M2 = group_max_nonneg<G>(nq, lane);
+    if (!done) {  // this ID's stopping rules, in the one-ID kernel's order
+      if (j == 0) {
+        if (!(M2 > 0.0)) {
+          zero_block = true;
+          done = true;
+        } else {
+          const double b = A.tol * sqrt(M2);
+          stop2 = b * b;
+        }
+      } else if (M2 <= stop2) {
+        done = true;
+      }
+      if (!done && j == kuser) done = true;
+      if (!done && j == kMaxRank) {
+        overflow = true;
+        done = true;
+      }
+    }
+    constexpr double kTie2 = (1.0 - kPivotTie) * (1.0 - kPivotTie);
+    const uint64_t near = __ballot(!done && eligible && nq >= kTie2 * M2);
+    const uint64_t gbits = (near >> (gi * GL)) & gmask;
+    if (!done && gbits == 0) done = true;  // no finite residual norm left (cannot happen for finite input)
+    if (__ballot(!done) == 0) break;      // every ID has stopped (the same in every wavefront)
+    const int p = done ? 0 : __ffsll((unsigned long long)gbits) - 1;  // pivot column of this ID
+    const int pl = gi * GL + p;                                         // its lane
+    const double nup = sqrt(__shfl(nq, pl, kWave));
+    if (!done && lane == pl && live) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) s_v[gi][row0 + i] = (!edge || row0 + i >= j) ? a[i] : make_double2(0.0, 0.0);
+      if (edge) {  // same-lane LDS accesses are ordered
+        const double2 xj = s_v[gi][j];
+        const double axj = sqrt(cabs2(xj));
+        double2 vj;
+        if (axj > 0.0) {
+          const double g = nup / axj;  // alpha = -g x_j, v_j = (1 + g) x_j
+          s_diag[gi][j] = make_double2(-xj.x * g, -xj.y * g);
+          vj = make_double2(xj.x + xj.x * g, xj.y + xj.y * g);
+        } else {
+          s_diag[gi][j] = make_double2(-nup, 0.0);
+          vj = make_double2(nup, 0.0);
+        }
+        s_v[gi][j] = vj;
+        s_axj[gi][j & 1] = axj;
+      }
+    }
+    wave_lds_sync();
+    double2 dot = make_double2(0.0, 0.0);
+    if (live && !done) {
+      double2 d0 = make_double2(0.0, 0.0), d1 = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        if (i & 1) d1 = cfma_conj(s_v[gi][row0 + i], a[i], d1);
+        else d0 = cfma_conj(s_v[gi][row0 + i], a[i], d0);
+      }
+      dot = cadd(d0, d1);
+    }
+    if constexpr (W > 1) {
+      s_partc[w * kWave + lane] = dot;
+      __syncthreads();
+      dot = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int ww = 0; ww < W; ++ww) dot = cadd(dot, s_partc[ww * kWave + lane]);
+    }
+    part = 0.0;
+    if (!done) {
+      const double den = nup * (nup + s_axj[gi][j & 1]);
+      double tau = __builtin_amdgcn_rcp(den);
+      tau = __builtin_fma(tau, __builtin_fma(-den, tau, 1.0), tau);
+      tau = __builtin_fma(tau, __builtin_fma(-den, tau, 1.0), tau);
+      if (live && eligible && lane != pl) {
+        const double2 sdot = make_double2(-tau * dot.x, -tau * dot.y);
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          a[i] = cfma(s_v[gi][row0 + i], sdot, a[i]);
+          if (i & 1) p1 = __builtin_fma(a[i].y, a[i].y, __builtin_fma(a[i].x, a[i].x, p1));
+          else p0 = __builtin_fma(a[i].y, a[i].y, __builtin_fma(a[i].x, a[i].x, p0));
+        }
+        if (edge) {
+          p0 = 0.0;
+          p1 = 0.0;
+#pragma unroll
+          for (int i = 0; i < R; ++i)
+            if (row0 + i > j) {
+              if (i & 1) p1 = __builtin_fma(a[i].y, a[i].y, __builtin_fma(a[i].x, a[i].x, p1));
+              else p0 = __builtin_fma(a[i].y, a[i].y, __builtin_fma(a[i].x, a[i].x, p0));
+            }
+        }
+        part = p0 + p1;
+      }
+      if (lane == pl) {
+        pivoted = true;
+        pstep = j;
+      }
+      if (w == 0 && lane == pl) s_piv[gi][j] = p;
+      k = j + 1;
+    }
+  }
+  if (member && k == 0) zero_block = true;
+  if (zero_block) {
+    k = 1;
+    pivoted = (gl == 0);
+    pstep = 0;
+    if (w == 0 && gl == 0) s_piv[gi][0] = 0;
+  }
+  if (overflow && w == 0 && gl == 0) atomicOr(A.status, kErrRank);
+  if (w == 0 && gl == 0) s_k[gi] = member ? k : 0;
+  __syncthreads();  // s_piv, s_k complete; every read of the partial sums is done
+
+  const uint64_t msk = (__ballot(pivoted && col < c) >> (gi * GL)) & gmask;  // this ID's skeleton mask
+  for (int e = threadIdx.x; e < G * GL; e += nthreads) {
+    const int g = e / GL, i = e % GL;
+    if (i >= s_k[g]) continue;
+    const int pc = s_piv[g][i];
+    // skeleton rank of pivot column pc: the pivots of ID g below pc
+    int below = 0;
+    for (int l = 0; l < s_k[g]; ++l) below += s_piv[g][l] < pc;
+    s_srank[g][i] = below;
+  }
+  if (member && !zero_block) {
+    for (int i = gl + GL * w; i < k; i += GL * W) {  // 1 / R_ii of this ID
+      const double2 d = s_diag[gi][i];
+      const double inv = 1.0 / cabs2(d);
+      s_diag[gi][i] = make_double2(d.x * inv, -d.y * inv);
+    }
+  }
+  if (w == 0 && member) {
+    if (gl == 0) {
+      A.rank[q] = k;
+      A.mask[2 * q] = msk;
+      A.mask[2 * q + 1] = 0;
+    }
+    if (pivoted && col < c) A.skel_out[q * kMaxCand + __popcll(msk & lanes_below(col))] = gidx;
+  }
+  // Back-substitution as in the one-ID kernel: R rows staged with ID g's
+  // pivots at slots g GL + l and its redundant candidates at g GL + k_g + jr;
+  // wavefront 0 solves, one redundant column per lane.
+  int kall = 0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) kall = max(kall, s_k[g]);
+  const int r = c - k;
+  const int64_t off = member ? (A.T_off ? A.T_off[q] : q * (int64_t)kSlot) : 0;
+  const bool skel = (msk >> col) & 1ull;
+  const int below = __popcll(msk & lanes_below(col));
+  const int slot = gi * GL + (pivoted ? pstep : k + col - below);
+  const bool solver = (w == 0) && member && col < c && !skel;
+  const int jr = solver ? col - below : 0;
+  const int gb = gi * GL;
+  auto t_index = [&](int l) -> int64_t {
+    const int sr = s_srank[gi][l];
+    return off + (isV ? (int64_t)jr * k + sr : (int64_t)sr * r + jr);
+  };
+  for (int cb0 = kall > 0 ? ((kall - 1) / kChunk) * kChunk : -1; cb0 >= 0; cb0 -= kChunk) {
+    const int ce = min(kall, cb0 + kChunk);
+    __syncthreads();  // the previous chunk's LDS reads are done
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int row = row0 + i;
+      if (row >= cb0 && row < ce && row < k && col < c)
+        s_R[(row - cb0) * kWave + slot] = zero_block ? make_double2(0.0, 0.0) : a[i];
+    }
+    __syncthreads();
+    if (!solver) continue;
+    const int cek = min(ce, k);
+    for (int ii = cek - 1; ii >= cb0; --ii) {
+      const double2* Ri = s_R + (ii - cb0) * kWave + gb;
+      double2 acc = Ri[k + jr];
+      if (!zero_block) {
+        double2 acc1 = make_double2(0.0, 0.0);
+        const double2* tcol = s_R + gb + k + jr - cb0 * kWave;  // t_l at tcol[l * 64]
+        int l = ii + 1;
+        for (; l + 1 < cek; l += 2) {
+          const double2 r0 = Ri[l], r1 = Ri[l + 1];
+          acc = cfma(make_double2(-r0.x, -r0.y), tcol[l * kWave], acc);
+          acc1 = cfma(make_double2(-r1.x, -r1.y), tcol[(l + 1) * kWave], acc1);
+        }
+        if (l < cek) {
+          const double2 r0 = Ri[l];
+          acc = cfma(make_double2(-r0.x, -r0.y), tcol[l * kWave], acc);
+        }
+        for (l = ce; l < k; ++l) {
+          const double2 rl = Ri[l];
+          acc1 = cfma(make_double2(-rl.x, -rl.y), A.T128[t_index(l)], acc1);
+        }
+        acc = cmul(cadd(acc, acc1), s_diag[gi][ii]);
+      }
+      s_R[(ii - cb0) * kWave + gb + k + jr] = acc;
+      const int64_t e = t_index(ii);
+      A.T128[e] = acc;
+      if (A.T64) A.T64[e] = make_float2((float)acc.x, (float)acc.y);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_qr_bucket(const IdArgs& a, int64_t n, int bucket, hipStream_t st);
@@ -678,6 +1017,12 @@ hipError_t launch_one(const IdArgs& a, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int W, int G>
+hipError_t launch_packed(const IdArgs& a, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((id_kernel_g<W, G>), dim3((unsigned)((n + G - 1) / G)), dim3(64 * W), 0, st, a, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_qr_bucket(const IdArgs& a, int64_t n, int bucket, hipStream_t st) {
   switch (bucket) {
     // up to 64 candidates: 16 rows per wavefront
@@ -705,7 +1050,15 @@ hipError_t launch_qr_bucket(const IdArgs& a, int64_t n, int bucket, hipStream_t 
     case 20: return launch_one<13, 2, 8>(a, n, st);
     case 21: return launch_one<14, 2, 8>(a, n, st);
     case 22: return launch_one<15, 2, 8>(a, n, st);
-    default: return launch_one<16, 2, 8>(a, n, st);
+    case 23: return launch_one<16, 2, 8>(a, n, st);
+    // two IDs per workgroup: up to 32 candidates and 64 samples
+    case 24: return launch_packed<1, 2>(a, n, st);
+    case 25: return launch_packed<2, 2>(a, n, st);
+    case 26: return launch_packed<3, 2>(a, n, st);
+    case 27: return launch_packed<4, 2>(a, n, st);
+    // four IDs per workgroup: up to 16 candidates and 32 samples
+    case 28: return launch_packed<1, 4>(a, n, st);
+    default: return launch_packed<2, 4>(a, n, st);
   }
 }
 

@@ -10,10 +10,13 @@ enum : int32_t { kErrRank = 1, kErrSize = 2 };
 
 // QR kernel variant of an ID with c candidates and s samples: buckets 0..7
 // take up to 64 candidates with ceil(s / 16) wavefronts, buckets 8..23 up to
-// 128 candidates (two per lane) with ceil(s / 8) wavefronts.
-constexpr int kQrBuckets = 24;
+// 128 with ceil(s / 8); buckets 24..27 pack two IDs of up to 32 candidates
+// and 64 samples per workgroup, 28..29 four IDs of up to 16 and 32.
+constexpr int kQrBuckets = 30;
 __host__ __device__ inline int qr_bucket(int c, int s) {
   s = s < 1 ? 1 : s;
+  if (c <= 16 && s <= 32) return 28 + (s + 15) / 16 - 1;  // four IDs per workgroup
+  if (c <= 32 && s <= 64) return 24 + (s + 15) / 16 - 1;  // two IDs per workgroup
   if (c <= kWave) {
     const int w = (s + 15) / 16;
     return (w > 8 ? 8 : w) - 1;

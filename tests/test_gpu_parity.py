@@ -103,15 +103,25 @@ WIDE_SHAPES = [(96, 120, 150, 400), (70, 80, 60, 64), (128, 128, 200, 256), (65,
                (100, 110, 1000, 1100), (16, 16, 700, 2048), (40, 48, 128, 300), (3, 3, 8, 8)]
 
 
+# small IDs run several to a workgroup: up to 16 candidates and 32 samples
+# four per workgroup, up to 32 and 64 two per workgroup; odd counts leave the
+# last workgroup part empty, and the IDs differ in size and rank
+PACKED4_SHAPES = [(16, 16, 700, 2048), (8, 8, 5, 5), (5, 5, 1, 1), (1, 1, 50, 60), (12, 12, 12, 12),
+                  (3, 3, 8, 8), (16, 20, 30, 40)]
+PACKED2_SHAPES = [(24, 32, 30, 40), (28, 28, 2000, 2048), (17, 20, 1500, 1600), (32, 32, 64, 70),
+                  (20, 24, 40, 48)]
+SHAPES = {"narrow": NARROW_SHAPES, "wide": WIDE_SHAPES, "packed4": PACKED4_SHAPES, "packed2": PACKED2_SHAPES}
+
+
 @pytest.mark.parametrize("side", [B.SIDE_U, B.SIDE_V])
 @pytest.mark.parametrize("oversample,kmax", [(1, 0), (2, 0), (2, 7)])
-@pytest.mark.parametrize("wide", [False, True])
-def test_id_batch_matches_oracle(side, oversample, kmax, wide):
+@pytest.mark.parametrize("shapes", ["narrow", "wide", "packed4", "packed2"])
+def test_id_batch_matches_oracle(side, oversample, kmax, shapes):
     N = 4096
     ph = I.fio_phase(1.0, 1.0)
     X, O = I.uniform_grid(N)
-    rng = np.random.default_rng(10 * side + oversample + kmax + 100 * wide)
-    problems = [_id_problem(rng, N, *sh) for sh in (WIDE_SHAPES if wide else NARROW_SHAPES)]
+    rng = np.random.default_rng(10 * side + oversample + kmax + 100 * list(SHAPES).index(shapes))
+    problems = [_id_problem(rng, N, *sh) for sh in SHAPES[shapes]]
     tol = 1e-6
     rank, mask, skel, T = _run_ids(ph, X, O, side, problems, tol, kmax, oversample)
     allow_coord = X if side == B.SIDE_V else O
