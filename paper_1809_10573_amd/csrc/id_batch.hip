@@ -19,6 +19,8 @@
 //   wavefront that holds row j applies row masks.  Then T = R11^{-1} R12 by
 //   back-substitution over R rows staged in LDS, one redundant candidate per
 //   thread, rows permuted to ascending skeletons.
+// id_kernel_g -- the same, with two (up to 32 candidates) or four (up to 16)
+//   IDs per workgroup, each on its own group of lanes.
 #include <algorithm>
 #include <climits>
 
