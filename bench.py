@@ -366,8 +366,8 @@ def main() -> int:
     if args.only:
         return _only(args.only)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only; the multi-GPU layout is described "
-              "in DESIGN.md and not run", file=sys.stderr)
+        print("bench.py: measures one GPU only; sharding the factorization over several GPUs "
+              "is not implemented", file=sys.stderr)
         return 2
 
     import torch
