@@ -20,10 +20,11 @@
 // sides (4 real columns): real column 4 j + t of the wave's block belongs to
 // N-tile t, so B~ is a register shuffle, never a cross-lane move.
 //
-// Precision: FP32 MFMA (v_mfma_f32_32x32x2_f32), or the BF16 hi/lo split
+// Precision: FP32 MFMA (v_mfma_f32_16x16x4_f32, 16-row M tiles, one
+// wavefront over all M tiles of a unit), or the BF16 hi/lo split
 // a ~= a_hi + a_lo with a b ~= a_hi b_hi + a_hi b_lo + a_lo b_hi on
-// v_mfma_f32_32x32x16_bf16, FP32 accumulation.  Both consume the same K order:
-// lanes 0-31 take K indices kc + e, lanes 32-63 kc + 8 + e (e < 8).
+// v_mfma_f32_32x32x16_bf16 (32-row M tiles), FP32 accumulation.  A unit's A
+// is staged once per workgroup and serves up to 1024 right-hand sides.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -152,8 +153,13 @@ __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(x - (float)hi);
 }
 
-template <int MODE, bool BF16, bool ADJ>
-__global__ __launch_bounds__(64 * kWavesG) void apply_gemm(StageArgs A) {
+// BF16 split on v_mfma_f32_32x32x16_bf16: one wavefront per (32-row M tile,
+// block of 64 right-hand sides); the workgroup's wavefronts cover
+// kRhsIterB such blocks in turn, so the staged A serves them all.
+constexpr int kRhsIterB = 8;
+
+template <int MODE, bool ADJ>
+__global__ __launch_bounds__(64 * kWavesG) void apply_gemm_bf16(StageArgs A) {
   extern __shared__ __attribute__((aligned(16))) float2 s_A[];
   __shared__ int s_src[kMaxKg];
   __shared__ int s_out[kMaxMg];
@@ -161,100 +167,158 @@ __global__ __launch_bounds__(64 * kWavesG) void apply_gemm(StageArgs A) {
   const Unit u = stage_unit<MODE, ADJ>(A, s_A, s_src, s_out, s_red);
   const int lane = threadIdx.x & (kWave - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  // one wavefront per (32-row M-tile, block of right-hand sides)
   const int tiles = A.gemm_rows / 32;
   const int mt = w % tiles;
-  const int64_t rhs0 = (blockIdx.y * (int64_t)(blockDim.x / kWave / tiles) + w / tiles) * kRhsPerWave;
-  if (rhs0 >= A.nrhs || mt * 32 >= u.M) return;
+  if (mt * 32 >= u.M) return;
+  const int blocks = blockDim.x / kWave / tiles;  // right-hand-side blocks per pass
   const int half = lane >> 5, jj = lane & 31;
   const int64_t nr = A.nrhs;
-  const int64_t n0 = rhs0 + 2 * jj;
-  const bool ok0 = n0 < nr, ok1 = n0 + 1 < nr;
   const float2* in = static_cast<const float2*>(A.in);
+  float2* out = static_cast<float2*>(A.out);
   const int lda = lda_for(u.K);
-
-  f32x16 acc[4];
+  for (int it = 0; it < kRhsIterB; ++it) {
+    const int64_t rhs0 = ((blockIdx.y * (int64_t)kRhsIterB + it) * blocks + w / tiles) * kRhsPerWave;
+    if (rhs0 >= nr) return;
+    const int64_t n0 = rhs0 + 2 * jj;
+    const bool ok0 = n0 < nr, ok1 = n0 + 1 < nr;
+    f32x16 acc[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = f32x16{};
-
-  for (int kc = 0; kc < u.K; kc += 16) {
-    float4 b[8];
+    for (int t = 0; t < 4; ++t) acc[t] = f32x16{};
+    for (int kc = 0; kc < u.K; kc += 16) {
+      float4 b[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int kk = kc + 8 * half + e;
-      const int row = kk < u.K ? s_src[kk] : -1;
-      const float2* p = in + (int64_t)(row < 0 ? 0 : row) * nr + n0;
-      const float2 v0 = ld2(p, row >= 0 && ok0), v1 = ld2(p + 1, row >= 0 && ok1);
-      b[e] = make_float4(v0.x, v0.y, v1.x, v1.y);
-    }
-    {
+      for (int e = 0; e < 8; ++e) {
+        const int kk = kc + 8 * half + e;
+        const int row = kk < u.K ? s_src[kk] : -1;
+        const float2* p = in + (int64_t)(row < 0 ? 0 : row) * nr + n0;
+        const float2 v0 = ld2(p, row >= 0 && ok0), v1 = ld2(p + 1, row >= 0 && ok1);
+        b[e] = make_float4(v0.x, v0.y, v1.x, v1.y);
+      }
       const float2* ap = s_A + (mt * 32 + jj) * lda + kc + 8 * half;
-      float2 a[8];
+      bf16x8 arh, arl, aih, ail;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) a[e] = ap[e];
-      if constexpr (!BF16) {
+      for (int e = 0; e < 8; ++e) {
+        const float2 av = ap[e];
+        __bf16 h, l;
+        split_bf16(av.x, h, l);
+        arh[e] = h;
+        arl[e] = l;
+        split_bf16(av.y, h, l);
+        aih[e] = h;
+        ail[e] = l;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        bf16x8 bh, bl, sh, sl;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const float bt[4] = {b[e].x, b[e].y, b[e].z, b[e].w};
           const float bs[4] = {-b[e].y, b[e].x, -b[e].w, b[e].z};
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e].x, bt[t], acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e].y, bs[t], acc[t], 0, 0, 0);
-          }
-        }
-      } else {
-        bf16x8 arh, arl, aih, ail;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
           __bf16 h, l;
-          split_bf16(a[e].x, h, l);
-          arh[e] = h;
-          arl[e] = l;
-          split_bf16(a[e].y, h, l);
-          aih[e] = h;
-          ail[e] = l;
+          split_bf16(bt[t], h, l);
+          bh[e] = h;
+          bl[e] = l;
+          split_bf16(bs[t], h, l);
+          sh[e] = h;
+          sl[e] = l;
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          bf16x8 bh, bl, sh, sl;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const float bt[4] = {b[e].x, b[e].y, b[e].z, b[e].w};
-            const float bs[4] = {-b[e].y, b[e].x, -b[e].w, b[e].z};
-            __bf16 h, l;
-            split_bf16(bt[t], h, l);
-            bh[e] = h;
-            bl[e] = l;
-            split_bf16(bs[t], h, l);
-            sh[e] = h;
-            sl[e] = l;
-          }
-          f32x16 c = acc[t];
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bh, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bl, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bh, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, sh, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, sl, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, sh, c, 0, 0, 0);
-          acc[t] = c;
-        }
+        f32x16 c = acc[t];
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, sh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, sl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, sh, c, 0, 0, 0);
+        acc[t] = c;
       }
     }
-  }
-
-  // epilogue: C row i = 32 mt + 8 (v / 4) + 4 half + v % 4, real column 4 jj + t
-  float2* out = static_cast<float2*>(A.out);
-  {
+    // epilogue: C row i = 32 mt + 8 (v / 4) + 4 half + v % 4, real column 4 jj + t
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int i = mt * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
       if (i >= u.M) continue;
-      const float2 o0 = make_float2(acc[0][v], acc[1][v]);
-      const float2 o1 = make_float2(acc[2][v], acc[3][v]);
       float2* p = out + (int64_t)s_out[i] * nr + n0;
-      if (ok0) p[0] = o0;
-      if (ok1) p[1] = o1;
+      if (ok0) p[0] = make_float2(acc[0][v], acc[1][v]);
+      if (ok1) p[1] = make_float2(acc[2][v], acc[3][v]);
+    }
+  }
+}
+
+// FP32 on v_mfma_f32_16x16x4_f32: 16-row M tiles (a unit of M rows pads to
+// a multiple of 16, not 32).  One wavefront per block of 32 right-hand sides
+// covers every M tile of the unit (up to TM), so each input row is loaded
+// once per wavefront.  Lane (kq = lane / 16, c = lane % 16) feeds K index
+// kc + kq: A row 16 mt + c, and the two complex right-hand sides rhs0 + 2c,
+// rhs0 + 2c + 1 as real columns 4c + t of N-tiles t = 0..3; D row 4 kq + v,
+// column c of tile t is the output of row 16 mt + 4 kq + v, real column
+// 4c + t.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kRhsPerWave16 = 32;
+constexpr int kRhsIter16 = 8;  // right-hand-side blocks per wavefront: the staged A serves 2 kWavesG blocks
+
+template <int MODE, bool ADJ, int TM>
+__global__ __launch_bounds__(64 * kWavesG) void apply_gemm16(StageArgs A) {
+  extern __shared__ __attribute__((aligned(16))) float2 s_A[];
+  __shared__ int s_src[kMaxKg];
+  __shared__ int s_out[kMaxMg];
+  __shared__ int s_red[2 * kMaxMg];
+  const Unit u = stage_unit<MODE, ADJ>(A, s_A, s_src, s_out, s_red);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int kq = lane >> 4, c16 = lane & 15;
+  const int tiles = (u.M + 15) / 16;  // <= TM
+  const int lda = lda_for(u.K);
+  const int64_t nr = A.nrhs;
+  const float2* in = static_cast<const float2*>(A.in);
+  float2* out = static_cast<float2*>(A.out);
+  for (int it = 0; it < kRhsIter16; ++it) {
+    const int64_t rhs0 = ((blockIdx.y * (int64_t)kRhsIter16 + it) * kWavesG + w) * kRhsPerWave16;
+    if (rhs0 >= nr) return;
+    const int64_t n0 = rhs0 + 2 * c16;
+    const bool ok0 = n0 < nr, ok1 = n0 + 1 < nr;
+    f32x4 acc[TM][4];
+#pragma unroll
+    for (int mt = 0; mt < TM; ++mt)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{};
+    for (int kc = 0; kc < u.K; kc += 16) {
+      float4 b[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int kk = kc + 4 * e + kq;
+        const int row = kk < u.K ? s_src[kk] : -1;
+        const float2* p = in + (int64_t)(row < 0 ? 0 : row) * nr + n0;
+        const float2 v0 = ld2(p, row >= 0 && ok0), v1 = ld2(p + 1, row >= 0 && ok1);
+        b[e] = make_float4(v0.x, v0.y, v1.x, v1.y);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (kc + 4 * e >= u.K) break;  // K steps of 4 wholly past K add nothing
+        const float bt[4] = {b[e].x, b[e].y, b[e].z, b[e].w};
+        const float bs[4] = {-b[e].y, b[e].x, -b[e].w, b[e].z};
+#pragma unroll
+        for (int mt = 0; mt < TM; ++mt) {
+          if (mt >= tiles) break;
+          const float2 av = s_A[(mt * 16 + c16) * lda + kc + 4 * e + kq];  // zero past K (padded to 16)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bt[t], acc[mt][t], 0, 0, 0);
+            acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bs[t], acc[mt][t], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < TM; ++mt) {
+      if (mt >= tiles) break;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = mt * 16 + 4 * kq + v;
+        if (i >= u.M) continue;
+        float2* p = out + (int64_t)s_out[i] * nr + n0;
+        if (ok0) p[0] = make_float2(acc[mt][0][v], acc[mt][1][v]);
+        if (ok1) p[1] = make_float2(acc[mt][2][v], acc[mt][3][v]);
+      }
     }
   }
 }
@@ -266,38 +330,54 @@ hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int m
   if (a0.n <= 0 || a0.nrhs <= 0) return hipSuccess;
   if (kmax_unit < 1 || kmax_unit > kMaxKg || mmax_unit < 1 || mmax_unit > kMaxMg) return hipErrorInvalidValue;
   StageArgs a = a0;
-  a.gemm_rows = (mmax_unit + 31) & ~31;
-  const int tiles_m = a.gemm_rows / 32;
-  const int blocks_rhs = (int)std::max<int64_t>(
-      1, std::min<int64_t>(kWavesG / tiles_m, (a.nrhs + kRhsPerWave - 1) / kRhsPerWave));
-  const int waves = blocks_rhs * tiles_m;
-  const int64_t per_block = (int64_t)blocks_rhs * kRhsPerWave;
-  const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
-  const dim3 block(64 * waves);
-  const size_t lds = (size_t)a.gemm_rows * (size_t)(((kmax_unit + 15) & ~15) + 2) * sizeof(float2);
-#define IDBF_GEMM(M, B, J)                                                                           \
+  if (!bf16) {  // FP32: 16-row tiles, one wavefront per 32 right-hand sides over all of them
+    a.gemm_rows = (mmax_unit + 15) & ~15;
+    const int64_t per_block = (int64_t)kRhsIter16 * kWavesG * kRhsPerWave16;
+    const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
+    const size_t lds = (size_t)a.gemm_rows * (size_t)(((kmax_unit + 15) & ~15) + 2) * sizeof(float2);
+#define IDBF_GEMM16(M, J, TM)                                                                        \
   do {                                                                                               \
     if (lds > (size_t(64) << 10)) {                                                                  \
-      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_gemm<M, B, J>),       \
+      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_gemm16<M, J, TM>),    \
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
       if (e_ != hipSuccess) return e_;                                                               \
     }                                                                                                \
-    hipLaunchKernelGGL((apply_gemm<M, B, J>), grid, block, lds, st, a);                              \
+    hipLaunchKernelGGL((apply_gemm16<M, J, TM>), grid, dim3(64 * kWavesG), lds, st, a);              \
   } while (0)
-#define IDBF_GEMM_MODE(M)                                                                            \
+#define IDBF_GEMM16_TM(M, J)                                                                         \
   do {                                                                                               \
-    if (adj) {                                                                                       \
-      if (bf16) IDBF_GEMM(M, true, true); else IDBF_GEMM(M, false, true);                            \
-    } else {                                                                                         \
-      if (bf16) IDBF_GEMM(M, true, false); else IDBF_GEMM(M, false, false);                          \
+    if (a.gemm_rows <= 64) IDBF_GEMM16(M, J, 4); else IDBF_GEMM16(M, J, 8);                          \
+  } while (0)
+    switch (mode) {
+      case kModeV: if (adj) IDBF_GEMM16_TM(kModeV, true); else IDBF_GEMM16_TM(kModeV, false); break;
+      case kModeS: if (adj) IDBF_GEMM16_TM(kModeS, true); else IDBF_GEMM16_TM(kModeS, false); break;
+      default: if (adj) IDBF_GEMM16_TM(kModeU, true); else IDBF_GEMM16_TM(kModeU, false); break;
+    }
+#undef IDBF_GEMM16_TM
+#undef IDBF_GEMM16
+    return hipGetLastError();
+  }
+  a.gemm_rows = (mmax_unit + 31) & ~31;  // BF16 split: 32-row tiles
+  const int tiles_m = a.gemm_rows / 32;
+  const int blocks_rhs = std::max(1, kWavesG / tiles_m);
+  const int64_t per_block = (int64_t)blocks_rhs * kRhsPerWave * kRhsIterB;
+  const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
+  const dim3 block(64 * blocks_rhs * tiles_m);
+  const size_t lds = (size_t)a.gemm_rows * (size_t)(((kmax_unit + 15) & ~15) + 2) * sizeof(float2);
+#define IDBF_GEMM(M, J)                                                                              \
+  do {                                                                                               \
+    if (lds > (size_t(64) << 10)) {                                                                  \
+      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_gemm_bf16<M, J>),     \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
+      if (e_ != hipSuccess) return e_;                                                               \
     }                                                                                                \
+    hipLaunchKernelGGL((apply_gemm_bf16<M, J>), grid, block, lds, st, a);                            \
   } while (0)
   switch (mode) {
-    case kModeV: IDBF_GEMM_MODE(kModeV); break;
-    case kModeS: IDBF_GEMM_MODE(kModeS); break;
-    default: IDBF_GEMM_MODE(kModeU); break;
+    case kModeV: if (adj) IDBF_GEMM(kModeV, true); else IDBF_GEMM(kModeV, false); break;
+    case kModeS: if (adj) IDBF_GEMM(kModeS, true); else IDBF_GEMM(kModeS, false); break;
+    default: if (adj) IDBF_GEMM(kModeU, true); else IDBF_GEMM(kModeU, false); break;
   }
-#undef IDBF_GEMM_MODE
 #undef IDBF_GEMM
   return hipGetLastError();
 }
