@@ -198,13 +198,22 @@ idbf_status idbf_apply_batched_plan(int32_t count, const idbf_handle* hs, const 
 idbf_status idbf_plan_launch(idbf_plan p, void* stream);
 idbf_status idbf_plan_destroy(idbf_plan p);
 
-/* Grow the handle's apply workspace (hipMalloc) so that idbf_apply with up to
- * nrhs right-hand sides of dtype allocates nothing.  Synchronizes the device
- * if it allocates. */
+/* Grow the handle's apply workspace (device memory, a kept chunk when one
+ * fits) so that idbf_apply with up to nrhs right-hand sides of dtype
+ * allocates nothing.  Synchronizes the device if it allocates. */
 idbf_status idbf_reserve(idbf_handle h, int64_t nrhs, int32_t dtype);
 
-/* Free a handle and everything it owns.  NULL-safe.  Synchronizes the device. */
+/* Free a handle and everything it owns.  NULL-safe.  Synchronizes the device.
+ * Its device chunks (factor arena, apply workspace) and pinned staging block
+ * are kept by the library for later constructions on the same device, up to
+ * IDBF_CACHE_BYTES bytes (environment, read once; default 32 GiB, 0 keeps
+ * nothing), the oldest freed first. */
 idbf_status idbf_destroy(idbf_handle h);
+
+/* Free the device and pinned memory kept from destroyed handles (see
+ * idbf_destroy).  Live handles are not affected.  Not for callers that can
+ * race it with idbf_construct on another thread. */
+idbf_status idbf_release_cached_memory(void);
 
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* idbf_last_error(void);
@@ -265,7 +274,8 @@ idbf_status idbf_profile_read(idbf_handle h, idbf_kernel_stat* out, int32_t max,
  *     candidates is k x r, stored from the even offset T_off[q]; V IDs store it
  *     column-major (entry j*k + i), U IDs row-major (entry i*r + j); rows
  *     follow ascending skeletons, columns ascending redundant candidates.
- *     n_T counts the reserved entries (per-ID rank bounds, rounded even).
+ *     n_T counts the reserved entries (per-ID rank bounds, rounded even);
+ *     the reserved entries past an ID's k r are unspecified.
  */
 idbf_status idbf_batch_sizes(idbf_handle h, int32_t side, int32_t level, int64_t* n_ids,
                              int64_t* n_skel, int64_t* n_T);

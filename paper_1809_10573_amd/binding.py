@@ -31,7 +31,7 @@ EXPORTED = [
     "idbf_construct_batched", "idbf_apply_batched", "idbf_mlp_param_count", "idbf_mlp_create",
     "idbf_mlp_destroy", "idbf_mlp_params", "idbf_mlp_forward", "idbf_mlp_loss_grad", "idbf_mlp_train",
     "idbf_rank_samples", "idbf_apply_batched_plan", "idbf_plan_launch", "idbf_plan_destroy",
-    "idbf_apply_adjoint",
+    "idbf_apply_adjoint", "idbf_release_cached_memory",
 ]
 MLP_INPUTS = 8
 FLAG_PROFILE = 1
@@ -314,6 +314,12 @@ def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample
     out = (C.c_void_p * n)()
     _check(lib.idbf_construct_batched(n, ph, xp, op, Ns, ts, ls, C.byref(opts), out))
     return [Factorization(out[i], Xd[i], Od[i]) for i in range(n)]
+
+
+def release_cached_memory() -> None:
+    """Free the device and pinned memory kept from destroyed factorizations
+    (idbf_release_cached_memory)."""
+    _check(load().idbf_release_cached_memory())
 
 
 def apply_batched(facs, xs, ys=None, dtype: int | None = None, stream=None) -> list:

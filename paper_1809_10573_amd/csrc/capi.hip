@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -34,12 +35,130 @@ int ilog2(int64_t v) {
   return l;
 }
 
-// Bump allocator over large hipMalloc chunks: the construction's many
-// per-level arrays cost a handful of driver allocations.
+// Device memory of released handles, kept for later ones on the same device.
+// A construction makes several large hipMalloc calls and its handle as many
+// hipFree calls, and on this platform each can take from milliseconds to
+// seconds.  Chunks enter only when the device is idle (release synchronizes
+// it), so a reused chunk has no work in flight.  Bounded by IDBF_CACHE_BYTES
+// (default 32 GiB, 0 disables; the oldest chunks are freed first);
+// idbf_release_cached_memory frees everything held.
+struct ChunkCache {
+  struct Entry {
+    int dev;
+    void* p;
+    size_t size;
+  };
+  std::mutex mu;
+  std::vector<Entry> list;  // oldest first
+  size_t held = 0, cap = 0;
+  std::vector<void*> pinned;  // HostStage-sized pinned blocks
+  size_t pinned_size = 0;
+
+  ChunkCache() {
+    cap = size_t(32) << 30;
+    if (const char* e = std::getenv("IDBF_CACHE_BYTES")) cap = (size_t)std::strtoull(e, nullptr, 10);
+  }
+  // the smallest held chunk of [want, min(4 want, most)] bytes on device dev, or null
+  void* take(int dev, size_t want, size_t most, size_t* got) {
+    std::lock_guard<std::mutex> g(mu);
+    int best = -1;
+    for (size_t i = 0; i < list.size(); ++i) {
+      const Entry& e = list[i];
+      if (e.dev == dev && e.size >= want && e.size <= most && e.size / 4 <= want &&
+          (best < 0 || e.size < list[best].size))
+        best = (int)i;
+    }
+    if (best < 0) return nullptr;
+    const Entry e = list[best];
+    list.erase(list.begin() + best);
+    held -= e.size;
+    *got = e.size;
+    return e.p;
+  }
+  // an idle chunk back; chunks past the bound are freed
+  void put(int dev, void* p, size_t size) {
+    std::vector<Entry> drop;
+    {
+      std::lock_guard<std::mutex> g(mu);
+      if (size > cap) {
+        drop.push_back({dev, p, size});
+      } else {
+        list.push_back({dev, p, size});
+        held += size;
+        while (held > cap) {
+          drop.push_back(list.front());
+          held -= list.front().size;
+          list.erase(list.begin());
+        }
+      }
+    }
+    for (const Entry& e : drop) (void)hipFree(e.p);
+  }
+  void* take_pinned(size_t size) {
+    std::lock_guard<std::mutex> g(mu);
+    if (pinned.empty() || pinned_size != size) return nullptr;
+    void* p = pinned.back();
+    pinned.pop_back();
+    return p;
+  }
+  void put_pinned(void* p, size_t size) {
+    {
+      std::lock_guard<std::mutex> g(mu);
+      if (cap > 0 && pinned.size() < 256 && (pinned.empty() || pinned_size == size)) {
+        pinned_size = size;
+        pinned.push_back(p);
+        return;
+      }
+    }
+    (void)hipHostFree(p);
+  }
+  void clear() {
+    std::vector<Entry> drop;
+    std::vector<void*> pins;
+    {
+      std::lock_guard<std::mutex> g(mu);
+      drop.swap(list);
+      pins.swap(pinned);
+      held = 0;
+    }
+    for (const Entry& e : drop) (void)hipFree(e.p);
+    for (void* p : pins) (void)hipHostFree(p);
+  }
+};
+
+// never destroyed: freeing device memory while the process exits is not safe
+ChunkCache& chunk_cache() {
+  static ChunkCache* c = new ChunkCache;
+  return *c;
+}
+
+int current_device() {
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) {
+    (void)hipGetLastError();
+    d = 0;
+  }
+  return d;
+}
+
+// Device memory of at least `bytes` and at most `most` (a held chunk when one
+// fits), its size in *got.
+hipError_t device_alloc(size_t bytes, size_t most, void** p, size_t* got) {
+  if (void* q = chunk_cache().take(current_device(), bytes, most, got)) {
+    *p = q;
+    return hipSuccess;
+  }
+  *got = bytes;
+  return hipMalloc(p, bytes);
+}
+
+// Bump allocator over large device chunks: the construction's many per-level
+// arrays cost a handful of allocations.
 struct Arena {
   struct Chunk {
     void* base;
     size_t size;
+    int dev;
   };
   std::vector<Chunk> chunks;
   char* cur = nullptr;
@@ -59,17 +178,18 @@ struct Arena {
       return IDBF_ENOMEM;
     }
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sz);
+    size_t got = sz;
+    hipError_t e = device_alloc(sz, limit ? limit - total : SIZE_MAX, &p, &got);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       set_error("hipMalloc(%zu) failed: %s", sz, hipGetErrorString(e));
       return IDBF_ENOMEM;
     }
-    chunks.push_back({p, sz});
-    total += sz;
+    chunks.push_back({p, got, current_device()});
+    total += got;
     cur = static_cast<char*>(p);
     used = bytes;
-    cap = sz;
+    cap = got;
     *out = p;
     return IDBF_OK;
   }
@@ -80,8 +200,10 @@ struct Arena {
     *out = static_cast<T*>(p);
     return s;
   }
+  // chunks back to the cache once the device is idle
   void release() {
-    for (auto& c : chunks) (void)hipFree(c.base);
+    if (!chunks.empty()) (void)hipDeviceSynchronize();
+    for (auto& c : chunks) chunk_cache().put(c.dev, c.base, c.size);
     chunks.clear();
     cur = nullptr;
     used = cap = total = 0;
@@ -279,8 +401,9 @@ struct idbf_handle_s {
   uint64_t seed = 0;
 
   ~idbf_handle_s() {
-    if (pin) (void)hipHostFree(pin);
-    if (ws) (void)hipFree(ws);
+    if (pin || ws) (void)hipDeviceSynchronize();  // nothing in flight uses them once they are held
+    if (pin) chunk_cache().put_pinned(pin, sizeof(HostStage));
+    if (ws) chunk_cache().put(current_device(), ws, ws_bytes);
     arena.release();
   }
 };
@@ -689,12 +812,15 @@ idbf_status points_finish(idbf_handle_s* h) {
 idbf_status construct_setup(idbf_handle_s* h) {
   Arena& A = h->arena;
   if (!h->pin) {
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->pin), sizeof(HostStage), hipHostMallocDefault);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      h->pin = nullptr;
-      set_error("pinned host allocation failed: %s", hipGetErrorString(e));
-      return IDBF_ENOMEM;
+    h->pin = static_cast<HostStage*>(chunk_cache().take_pinned(sizeof(HostStage)));
+    if (!h->pin) {
+      hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->pin), sizeof(HostStage), hipHostMallocDefault);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        h->pin = nullptr;
+        set_error("pinned host allocation failed: %s", hipGetErrorString(e));
+        return IDBF_ENOMEM;
+      }
     }
     std::memset(h->pin, 0, sizeof(HostStage));
   }
@@ -750,19 +876,21 @@ idbf_status construct_impl(idbf_handle_s* h, const double* X, const double* Om) 
 idbf_status grow_workspace(idbf_handle_s* h, size_t bytes, hipStream_t st) {
   if (h->H == 0 || bytes <= h->ws_bytes) return IDBF_OK;
   if (h->ws) {
-    IDBF_HIP_CHECK(hipStreamSynchronize(st));
-    IDBF_HIP_CHECK(hipFree(h->ws));
+    (void)st;
+    IDBF_HIP_CHECK(hipDeviceSynchronize());  // applies on any stream may still read it
+    chunk_cache().put(current_device(), h->ws, h->ws_bytes);
     h->ws = nullptr;
     h->ws_bytes = 0;
   }
-  hipError_t e = hipMalloc(&h->ws, bytes);
+  size_t got = bytes;
+  hipError_t e = device_alloc(bytes, SIZE_MAX, &h->ws, &got);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     h->ws = nullptr;
     set_error("apply workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
     return IDBF_ENOMEM;
   }
-  h->ws_bytes = bytes;
+  h->ws_bytes = got;
   return IDBF_OK;
 }
 
@@ -1016,6 +1144,11 @@ idbf_status idbf_destroy(idbf_handle h) {
   if (!h) return IDBF_OK;
   (void)hipDeviceSynchronize();
   delete h;
+  return IDBF_OK;
+}
+
+idbf_status idbf_release_cached_memory(void) {
+  chunk_cache().clear();
   return IDBF_OK;
 }
 

@@ -1,0 +1,63 @@
+"""Device memory kept from destroyed handles (idbf_destroy,
+idbf_release_cached_memory): a construction on reused chunks, which hold the
+previous handle's data, gives bit for bit the factors (ranks, skeletons and
+every ID's k x r T block) and apply results of one on freshly allocated
+memory, and so does the apply workspace."""
+import numpy as np
+import pytest
+
+from paper_1809_10573_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1809_10573_amd import binding as B  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _build_and_apply(phase, N, leaf, tol):
+    X, O = I.uniform_grid(N)
+    fac = B.construct(phase, X, O, tol, leaf, oversample=2, device=DEV)
+    info = fac.info()
+    levels = []
+    for side in (B.SIDE_U, B.SIDE_V):
+        for t in range(1, info["H"] + 1):
+            b = fac.batch(side, t)
+            r = b.cand_len.astype(np.int64) - b.rank
+            # the k r entries of every ID (the rest of each reserved slot is unspecified)
+            T = np.concatenate([b.T[o:o + k * rr] for o, k, rr in zip(b.T_off, b.rank.astype(np.int64), r)])
+            levels.append((b.rank.copy(), b.mask.copy(), b.skel.copy(), T))
+    gen = torch.Generator(device=DEV).manual_seed(3)
+    x = torch.randn(N, 8, dtype=torch.complex64, device=DEV, generator=gen)
+    y = fac.apply(x).cpu()
+    y1 = fac.apply(x[:, 0].contiguous()).cpu()
+    fac.close()
+    return levels, y, y1
+
+
+def _same(a, b):
+    (la, ya, y1a), (lb, yb, y1b) = a, b
+    assert len(la) == len(lb)
+    for u, v in zip(la, lb):
+        for p, q in zip(u, v):
+            assert np.array_equal(p, q)
+    assert torch.equal(ya, yb) and torch.equal(y1a, y1b)
+
+
+def test_reused_memory_gives_identical_factors():
+    B.release_cached_memory()
+    fresh = _build_and_apply(I.fio_phase(1.0, 1.0), 4096, 16, 1e-6)
+    # dirty the kept chunks with a different, larger factorization
+    X, O = I.uniform_grid(16384)
+    other = B.construct(I.dft_phase(), X, O, 1e-9, 8, oversample=2, device=DEV)
+    other.apply(torch.ones(16384, 64, dtype=torch.complex64, device=DEV))
+    other.close()
+    reused = _build_and_apply(I.fio_phase(1.0, 1.0), 4096, 16, 1e-6)
+    _same(fresh, reused)
+    B.release_cached_memory()
+    again = _build_and_apply(I.fio_phase(1.0, 1.0), 4096, 16, 1e-6)
+    _same(fresh, again)
