@@ -215,7 +215,7 @@ struct StageArgs {
   const void* in;
   void* out;
   int pmax;                // largest factor block (entries) of the stage: LDS per ID
-  int gemm_rows;           // matrix-core stage: rows of A staged per unit (multiple of 32)
+  int gemm_rows;           // matrix-core stage: rows of A staged per unit (multiple of 16 for FP32, 32 for BF16)
   // middle stage
   bool dense;              // H = 0: one N x N block
   int64_t rlen_host;       // its row count
