@@ -330,6 +330,29 @@ def qr_source_hash() -> str:
     return h.hexdigest()
 
 
+APPLY1_COUNTERS = os.path.join(ROOT, "profiles", "apply1_fio_n2p20_counters.md")
+APPLY1_SOURCES = [os.path.join(ROOT, "paper_1809_10573_amd", "csrc", f) for f in ("apply.hip", "common.hpp",
+                                                                              "kernels.hpp")]
+
+
+def _counted_traffic(path: str, sources: list, key: str) -> float | None:
+    """`key` from a committed counter summary, or None when the listed
+    sources changed since the counters were taken."""
+    import hashlib
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for f in sources:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    kv = dict(l.split("=", 1) for l in lines if l.startswith((key + "=", "source_sha256=")))
+    if kv.get("source_sha256", "").strip() != h.hexdigest() or key not in kv:
+        return None
+    return float(kv[key])
+
+
 def _qr_traffic() -> float | None:
     """HBM bytes per step of the QR kernels from the committed counter summary,
     or None when the kernel sources changed since the counters were taken."""
@@ -345,7 +368,8 @@ def _qr_traffic() -> float | None:
 
 def _only(what: str) -> int:
     """Single pieces of the step for counter runs: the workload's construction
-    (twice), or a plain 1 GiB device copy (three times) for calibration."""
+    (twice), its complex64 1-RHS apply (three times, after one construction),
+    or a plain 1 GiB device copy (three times) for calibration."""
     import torch
     from paper_1809_10573_amd import binding as B
     dev = torch.device("cuda:0")
@@ -361,6 +385,17 @@ def _only(what: str) -> int:
     ph = I.fio_phase(W["a"], W["freq"], W["c0"], W["cdiv"])
     Xh, Oh = I.uniform_grid(W["N"])
     X, O = torch.as_tensor(Xh, device=dev), torch.as_tensor(Oh, device=dev)
+    if what == "apply1":
+        fac = B.construct(ph, X, O, W["tol"], W["leaf"], oversample=W["oversample"], device=dev)
+        x = torch.as_tensor(I.gaussian_vectors(W["N"], None, 4), device=dev).to(torch.complex64)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            fac.apply(x, y)
+        torch.cuda.synchronize()
+        info = fac.info()
+        print(f"apply1: 3 applies, nnz {info['nnz_T'] + info['nnz_S']}, n_ids {info['n_ids']}", flush=True)
+        fac.close()
+        return 0
     for i in range(2):
         fac = B.construct(ph, X, O, W["tol"], W["leaf"], oversample=W["oversample"], device=dev)
         torch.cuda.synchronize()
@@ -381,7 +416,7 @@ def main() -> int:
     ap.add_argument("--no-ablation", action="store_true", help="skip the sampler / fixed-rank ablation")
     ap.add_argument("--no-examples", action="store_true",
                     help="skip the non-uniform Fourier transform and Schloemilch lines")
-    ap.add_argument("--only", choices=["construct", "copy"], help="run one piece for a counter pass")
+    ap.add_argument("--only", choices=["construct", "apply1", "copy"], help="run one piece for a counter pass")
     args = ap.parse_args()
     if args.only:
         return _only(args.only)
@@ -527,6 +562,8 @@ def main() -> int:
     tm = sum(v["ms"] for k, v in p1.items() if k.startswith("apply"))
     out["roofline_apply1"] = {"bound": "hbm", "achieved": tb / tm / 1e6, "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": tb / tm / 1e6 / HBM_PEAK_GBS,
+                              "traffic": _counted_traffic(APPLY1_COUNTERS, APPLY1_SOURCES,
+                                                          "traffic_bytes_per_apply"),
                               "kernels": {k: v["ms"] for k, v in p1.items()}}
     del a1
     # adjoint apply y = K~^H x on the same factors (measured once): 1 RHS and
