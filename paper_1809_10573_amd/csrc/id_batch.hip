@@ -111,15 +111,40 @@ __device__ void greedy_select(const Seg& a, int n, int s, const double* z, const
       if (pos[t] == p) return true;
     return false;
   };
+  // nearest unused position <= p (or -1) and >= p (or n); with the bitmap a
+  // word of 32 positions per step (near-full selections collide at almost
+  // every target)
+  auto free_le = [&](int p) -> int {
+    if (!use_bits) {
+      while (p >= 0 && used(p)) --p;
+      return p;
+    }
+    while (p >= 0) {
+      const uint32_t f = ~bits[p >> 5] & (0xffffffffu >> (31 - (p & 31)));  // free bits <= p in its word
+      if (f) return (p & ~31) + 31 - __clz(f);
+      p = (p & ~31) - 1;
+    }
+    return -1;
+  };
+  auto free_ge = [&](int p) -> int {
+    if (!use_bits) {
+      while (p < n && used(p)) ++p;
+      return p;
+    }
+    while (p < n) {
+      const uint32_t f = ~bits[p >> 5] & (0xffffffffu << (p & 31));  // free bits >= p in its word
+      if (f) return min((p & ~31) + __ffs(f) - 1, n);
+      p = (p & ~31) + 32;
+    }
+    return n;
+  };
   for (int j = 0; j < s; ++j) pos[j] = -1;
   for (int j = 0; j < s; ++j) {
     const int q0 = p0[j];
     int pick = q0;
     if (used(q0)) {
-      int l = q0 - 1;
-      while (l >= 0 && used(l)) --l;
-      int r = q0 + 1;
-      while (r < n && used(r)) ++r;
+      const int l = free_le(q0 - 1);
+      const int r = free_ge(q0 + 1);
       if (l < 0) {
         pick = r;
       } else if (r >= n) {
