@@ -254,10 +254,11 @@ __global__ __launch_bounds__(64 * kWavesG) void apply_gemm_bf16(StageArgs A) {
 // 4c + t.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kRhsPerWave16 = 32;
-constexpr int kRhsIter16 = 8;  // right-hand-side blocks per wavefront: the staged A serves 2 kWavesG blocks
+constexpr int kWavesG16 = 4;   // wavefronts per workgroup
+constexpr int kRhsIter16 = 8;  // right-hand-side blocks per wavefront: the staged A serves kRhsIter16 kWavesG16 blocks
 
 template <int MODE, bool ADJ, int TM>
-__global__ __launch_bounds__(64 * kWavesG) void apply_gemm16(StageArgs A) {
+__global__ __launch_bounds__(64 * kWavesG16) void apply_gemm16(StageArgs A) {
   extern __shared__ __attribute__((aligned(16))) float2 s_A[];
   __shared__ int s_src[kMaxKg];
   __shared__ int s_out[kMaxMg];
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(64 * kWavesG) void apply_gemm16(StageArgs A) {
   const float2* in = static_cast<const float2*>(A.in);
   float2* out = static_cast<float2*>(A.out);
   for (int it = 0; it < kRhsIter16; ++it) {
-    const int64_t rhs0 = ((blockIdx.y * (int64_t)kRhsIter16 + it) * kWavesG + w) * kRhsPerWave16;
+    const int64_t rhs0 = ((blockIdx.y * (int64_t)kRhsIter16 + it) * kWavesG16 + w) * kRhsPerWave16;
     if (rhs0 >= nr) return;
     const int64_t n0 = rhs0 + 2 * c16;
     const bool ok0 = n0 < nr, ok1 = n0 + 1 < nr;
@@ -332,7 +333,7 @@ hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int m
   StageArgs a = a0;
   if (!bf16) {  // FP32: 16-row tiles, one wavefront per 32 right-hand sides over all of them
     a.gemm_rows = (mmax_unit + 15) & ~15;
-    const int64_t per_block = (int64_t)kRhsIter16 * kWavesG * kRhsPerWave16;
+    const int64_t per_block = (int64_t)kRhsIter16 * kWavesG16 * kRhsPerWave16;
     const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
     const size_t lds = (size_t)a.gemm_rows * (size_t)(((kmax_unit + 15) & ~15) + 2) * sizeof(float2);
 #define IDBF_GEMM16(M, J, TM)                                                                        \
@@ -342,7 +343,7 @@ hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int m
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
       if (e_ != hipSuccess) return e_;                                                               \
     }                                                                                                \
-    hipLaunchKernelGGL((apply_gemm16<M, J, TM>), grid, dim3(64 * kWavesG), lds, st, a);              \
+    hipLaunchKernelGGL((apply_gemm16<M, J, TM>), grid, dim3(64 * kWavesG16), lds, st, a);            \
   } while (0)
 #define IDBF_GEMM16_TM(M, J)                                                                         \
   do {                                                                                               \
