@@ -211,8 +211,9 @@ idbf_status idbf_reserve(idbf_handle h, int64_t nrhs, int32_t dtype);
 idbf_status idbf_destroy(idbf_handle h);
 
 /* Free the device and pinned memory kept from destroyed handles (see
- * idbf_destroy).  Live handles are not affected.  Not for callers that can
- * race it with idbf_construct on another thread. */
+ * idbf_destroy).  Live handles are not affected.  Thread-safe: a
+ * construction running meanwhile on another thread only finds less memory to
+ * reuse. */
 idbf_status idbf_release_cached_memory(void);
 
 /* Thread-local description of the last failure on this thread ("" if none). */
