@@ -369,7 +369,8 @@ def _qr_traffic() -> float | None:
 def _only(what: str) -> int:
     """Single pieces of the step for counter runs: the workload's construction
     (twice), its complex64 1-RHS apply (three times, after one construction),
-    or a plain 1 GiB device copy (three times) for calibration."""
+    its 1024-RHS applies (FP32 and BF16 split, once each), or a plain 1 GiB
+    device copy (three times) for calibration."""
     import torch
     from paper_1809_10573_amd import binding as B
     dev = torch.device("cuda:0")
@@ -385,6 +386,18 @@ def _only(what: str) -> int:
     ph = I.fio_phase(W["a"], W["freq"], W["c0"], W["cdiv"])
     Xh, Oh = I.uniform_grid(W["N"])
     X, O = torch.as_tensor(Xh, device=dev), torch.as_tensor(Oh, device=dev)
+    if what == "applyn":
+        fac = B.construct(ph, X, O, W["tol"], W["leaf"], oversample=W["oversample"], device=dev)
+        gen = torch.Generator(device=dev).manual_seed(4)
+        XM = torch.randn(W["N"], 1024, dtype=torch.complex64, device=dev, generator=gen)
+        YM = torch.empty_like(XM)
+        fac.reserve(1024, B.C64)
+        fac.apply(XM, YM)
+        fac.apply(XM, YM, dtype=B.C64_BF16X3)
+        torch.cuda.synchronize()
+        print("applyn: one FP32 and one BF16-split apply, 1024 right-hand sides", flush=True)
+        fac.close()
+        return 0
     if what == "apply1":
         fac = B.construct(ph, X, O, W["tol"], W["leaf"], oversample=W["oversample"], device=dev)
         x = torch.as_tensor(I.gaussian_vectors(W["N"], None, 4), device=dev).to(torch.complex64)
@@ -416,7 +429,7 @@ def main() -> int:
     ap.add_argument("--no-ablation", action="store_true", help="skip the sampler / fixed-rank ablation")
     ap.add_argument("--no-examples", action="store_true",
                     help="skip the non-uniform Fourier transform and Schloemilch lines")
-    ap.add_argument("--only", choices=["construct", "apply1", "copy"], help="run one piece for a counter pass")
+    ap.add_argument("--only", choices=["construct", "apply1", "applyn", "copy"], help="run one piece for a counter pass")
     args = ap.parse_args()
     if args.only:
         return _only(args.only)
