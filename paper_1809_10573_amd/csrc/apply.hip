@@ -330,6 +330,141 @@ __global__ __launch_bounds__(256) void apply_s1(StageArgs A) {
   }
 }
 
+// 1-RHS V and U stages whose candidate sets have at most 64 / G points (the
+// lowest levels: 16 at t = 1): G IDs (units) per wavefront, each on its own
+// group of 64 / G lanes (lane = candidate position), all of an ID's products
+// in one slot of kProdSlot / G entries.  Same products and summation order as
+// apply_v1 / apply_u1, so the same results.
+template <typename C, int G>
+__global__ __launch_bounds__(256) void apply_v1g(StageArgs A) {
+  constexpr int GL = kWave / G, SLOT = kProdSlot / G;
+  using V = typename Vec<C>::type;
+  constexpr int EPL = Vec<C>::epl;
+  constexpr int NV = SLOT / EPL / GL;  // vector loads per lane
+  __shared__ C s_prod[kIdsPerBlock][kProdSlot];
+  __shared__ C s_u[kIdsPerBlock][kWave];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+  const int g = lane / GL, l = lane % GL;
+  const int64_t q0 = (blockIdx.x * (int64_t)kIdsPerBlock + w) * G;
+  if (q0 >= A.n) return;
+  const int64_t q = q0 + g;
+  const bool valid = q < A.n;
+  const ApplyMeta m = A.meta[valid ? q : A.n - 1];
+  const int c = m.c, k = m.k, r = c - k;
+  C* s_p = s_prod[w] + g * SLOT;
+  C* s_ug = s_u[w] + g * GL;
+  const C* in = static_cast<const C*>(A.in);
+  C* out = static_cast<C*>(A.out);
+  const bool on = valid && l < c;
+  C acc = czero(C{});
+  int below = 0;
+  bool sk = false;
+  if (on) {
+    const C u = in[m.cand_beg + l];
+    below = mbelow(m, l);
+    sk = mbit(m, l);
+    if (sk) acc = u; else s_ug[l - below] = u;
+  }
+  wave_sync_lds();
+  // P[e] = T[e] u[red_{e / k}], T column-major (entry j*k + i)
+  const int n = k * r, nv = (n + EPL - 1) / EPL;
+  const V* src = reinterpret_cast<const V*>(static_cast<const C*>(A.T) + m.t_off);
+  const float rk = 1.0f / (float)max(k, 1);
+  V buf[NV];
+#pragma unroll
+  for (int mm = 0; mm < NV; ++mm) {
+    const int v = l + GL * mm;
+    if (valid && v < nv) buf[mm] = src[v];
+  }
+#pragma unroll
+  for (int mm = 0; mm < NV; ++mm) {
+    const int v = l + GL * mm;
+    if (valid && v < nv) {
+#pragma unroll
+      for (int t = 0; t < EPL; ++t) {
+        const int e = v * EPL + t;
+        if (e < n) s_p[e] = cfma(vec_entry<C>(buf[mm], t), s_ug[(int)(((float)e + 0.5f) * rk)], czero(C{}));
+      }
+    }
+  }
+  wave_sync_lds();
+  if (on && sk) {
+    for (int j = 0; j < r; ++j) acc = cadd(acc, s_p[j * k + below]);
+    out[m.skel_off + below] = acc;
+  }
+}
+
+template <typename C, int G>
+__global__ __launch_bounds__(256) void apply_u1g(StageArgs A) {
+  constexpr int GL = kWave / G, SLOT = kProdSlot / G;
+  using V = typename Vec<C>::type;
+  constexpr int EPL = Vec<C>::epl;
+  constexpr int NV = SLOT / EPL / GL;
+  __shared__ C s_prod[kIdsPerBlock][kProdSlot];
+  __shared__ C s_w[kIdsPerBlock][2][kWave];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave), lane = threadIdx.x & (kWave - 1);
+  const int g = lane / GL, l = lane % GL;
+  const int64_t u0 = (blockIdx.x * (int64_t)kIdsPerBlock + w) * G;
+  if (u0 >= A.n) return;
+  const int64_t unit = u0 + g;
+  const bool valid = unit < A.n;
+  const int64_t un = valid ? unit : A.n - 1;
+  const int64_t P = un / A.nn, node = un % A.nn;
+  ApplyMeta m[2];
+  m[0] = A.meta[2 * P * A.nn + node];
+  m[1] = A.meta[2 * P * A.nn + node + A.nn];
+  const int c = m[0].c;
+  C* s_p = s_prod[w] + g * SLOT;
+  const C* in = static_cast<const C*>(A.in);
+  C* out = static_cast<C*>(A.out);
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    if (valid && l < m[h].k) s_w[w][h][g * GL + l] = in[m[h].skel_off + l];
+  wave_sync_lds();
+  const bool on = valid && l < c;
+  C acc = czero(C{});
+  int below[2];
+  bool sk[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    below[h] = mbelow(m[h], l);
+    sk[h] = mbit(m[h], l);
+    if (on && sk[h]) acc = cadd(acc, s_w[w][h][g * GL + below[h]]);
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    // P[e] = T_h[e] w_h[e / r], T row-major (entry i*r + j)
+    const int k = m[h].k, r = c - k, n = k * r, nv = (n + EPL - 1) / EPL;
+    const V* src = reinterpret_cast<const V*>(static_cast<const C*>(A.T) + m[h].t_off);
+    const float rr = 1.0f / (float)max(r, 1);
+    V buf[NV];
+#pragma unroll
+    for (int mm = 0; mm < NV; ++mm) {
+      const int v = l + GL * mm;
+      if (valid && v < nv) buf[mm] = src[v];
+    }
+#pragma unroll
+    for (int mm = 0; mm < NV; ++mm) {
+      const int v = l + GL * mm;
+      if (valid && v < nv) {
+#pragma unroll
+        for (int t = 0; t < EPL; ++t) {
+          const int e = v * EPL + t;
+          if (e < n)
+            s_p[e] = cfma(vec_entry<C>(buf[mm], t), s_w[w][h][g * GL + (int)(((float)e + 0.5f) * rr)], czero(C{}));
+        }
+      }
+    }
+    wave_sync_lds();
+    if (on && !sk[h]) {
+      const C* p = s_p + (l - below[h]);
+      for (int i = 0; i < k; ++i) acc = cadd(acc, p[i * r]);
+    }
+    wave_sync_lds();
+  }
+  if (on) out[m[0].cand_beg + l] = acc;
+}
+
 // The whole matrix when the tree has no levels (N <= 2 leaf): lanes over rows
 // (ADJ: over columns, with conjugated entries).
 template <typename C, bool ADJ = false>
@@ -538,7 +673,15 @@ inline dim3 gridn(int64_t n, int64_t nrhs) {
 
 template <bool ADJ>
 hipError_t launch_v_shaped(const StageArgs& a, bool fp64, hipStream_t st) {
-  if (a.nrhs == 1) {
+  if (a.nrhs == 1 && !ADJ && a.cmax > 0 && a.cmax <= kWave / 2) {  // small candidate sets: IDs share wavefronts
+    if (a.cmax <= kWave / 4) {
+      if (fp64) hipLaunchKernelGGL((apply_v1g<double2, 4>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((apply_v1g<float2, 4>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
+    } else {
+      if (fp64) hipLaunchKernelGGL((apply_v1g<double2, 2>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((apply_v1g<float2, 2>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
+    }
+  } else if (a.nrhs == 1) {
     if (fp64) hipLaunchKernelGGL((apply_v1<double2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((apply_v1<float2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
   } else {
@@ -552,7 +695,15 @@ hipError_t launch_v_shaped(const StageArgs& a, bool fp64, hipStream_t st) {
 
 template <bool ADJ>
 hipError_t launch_u_shaped(const StageArgs& a, bool fp64, hipStream_t st) {
-  if (a.nrhs == 1) {
+  if (a.nrhs == 1 && !ADJ && a.cmax > 0 && a.cmax <= kWave / 2) {  // small candidate sets: units share wavefronts
+    if (a.cmax <= kWave / 4) {
+      if (fp64) hipLaunchKernelGGL((apply_u1g<double2, 4>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((apply_u1g<float2, 4>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
+    } else {
+      if (fp64) hipLaunchKernelGGL((apply_u1g<double2, 2>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((apply_u1g<float2, 2>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
+    }
+  } else if (a.nrhs == 1) {
     if (fp64) hipLaunchKernelGGL((apply_u1<double2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((apply_u1<float2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
   } else {

@@ -1169,6 +1169,7 @@ StageArgs level_stage(const Batch& b, bool fp64, int64_t nrhs) {
   a.T_off = b.T_off;
   a.T = fp64 ? (const void*)b.T128 : (const void*)b.T64;
   a.pmax = (int)b.tb_max;
+  a.cmax = b.cand_max;
   return a;
 }
 

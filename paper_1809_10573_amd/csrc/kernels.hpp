@@ -215,6 +215,7 @@ struct StageArgs {
   const void* in;
   void* out;
   int pmax;                // largest factor block (entries) of the stage: LDS per ID
+  int cmax;                // largest candidate set of the stage (1-RHS: IDs per wavefront)
   int gemm_rows;           // matrix-core stage: rows of A staged per unit (multiple of 16 for FP32, 32 for BF16)
   // middle stage
   bool dense;              // H = 0: one N x N block
