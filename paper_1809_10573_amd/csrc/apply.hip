@@ -330,12 +330,12 @@ __global__ __launch_bounds__(256) void apply_s1(StageArgs A) {
   }
 }
 
-// 1-RHS V and U stages whose candidate sets have at most 64 / G points (the
-// lowest levels: 16 at t = 1): G IDs (units) per wavefront, each on its own
-// group of 64 / G lanes (lane = candidate position), all of an ID's products
-// in one slot of kProdSlot / G entries.  Same products and summation order as
-// apply_v1 / apply_u1, so the same results.
-template <typename C, int G>
+// 1-RHS V- and U-shaped stages whose candidate sets have at most 64 / G
+// points (the lowest levels: 16 at t = 1): G IDs (units) per wavefront, each
+// on its own group of 64 / G lanes (lane = candidate position), all of an
+// ID's products in one slot of kProdSlot / G entries.  Same products and
+// summation order as apply_v1 / apply_u1 (ADJ included), so the same results.
+template <typename C, int G, bool ADJ>
 __global__ __launch_bounds__(256) void apply_v1g(StageArgs A) {
   constexpr int GL = kWave / G, SLOT = kProdSlot / G;
   using V = typename Vec<C>::type;
@@ -366,10 +366,12 @@ __global__ __launch_bounds__(256) void apply_v1g(StageArgs A) {
     if (sk) acc = u; else s_ug[l - below] = u;
   }
   wave_sync_lds();
-  // P[e] = T[e] u[red_{e / k}], T column-major (entry j*k + i)
+  // P[e] = T[e] u[red_{e / k}], T column-major (entry j*k + i); ADJ (U_t^H):
+  // P[e] = conj(T[e]) u[red_{e % r}], T row-major (entry i*r + j)
   const int n = k * r, nv = (n + EPL - 1) / EPL;
   const V* src = reinterpret_cast<const V*>(static_cast<const C*>(A.T) + m.t_off);
-  const float rk = 1.0f / (float)max(k, 1);
+  const int div = ADJ ? r : k;
+  const float rk = 1.0f / (float)max(div, 1);
   V buf[NV];
 #pragma unroll
   for (int mm = 0; mm < NV; ++mm) {
@@ -383,18 +385,25 @@ __global__ __launch_bounds__(256) void apply_v1g(StageArgs A) {
 #pragma unroll
       for (int t = 0; t < EPL; ++t) {
         const int e = v * EPL + t;
-        if (e < n) s_p[e] = cfma(vec_entry<C>(buf[mm], t), s_ug[(int)(((float)e + 0.5f) * rk)], czero(C{}));
+        if (e < n) {
+          const int q = (int)(((float)e + 0.5f) * rk);  // e / div
+          s_p[e] = cfma(conj_if(vec_entry<C>(buf[mm], t), ADJ), s_ug[ADJ ? e - q * div : q], czero(C{}));
+        }
       }
     }
   }
   wave_sync_lds();
   if (on && sk) {
-    for (int j = 0; j < r; ++j) acc = cadd(acc, s_p[j * k + below]);
+    if constexpr (!ADJ) {
+      for (int j = 0; j < r; ++j) acc = cadd(acc, s_p[j * k + below]);
+    } else {
+      for (int j = 0; j < r; ++j) acc = cadd(acc, s_p[below * r + j]);
+    }
     out[m.skel_off + below] = acc;
   }
 }
 
-template <typename C, int G>
+template <typename C, int G, bool ADJ>
 __global__ __launch_bounds__(256) void apply_u1g(StageArgs A) {
   constexpr int GL = kWave / G, SLOT = kProdSlot / G;
   using V = typename Vec<C>::type;
@@ -433,10 +442,12 @@ __global__ __launch_bounds__(256) void apply_u1g(StageArgs A) {
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    // P[e] = T_h[e] w_h[e / r], T row-major (entry i*r + j)
+    // P[e] = T_h[e] w_h[e / r], T row-major (entry i*r + j); ADJ (V_t^H):
+    // P[e] = conj(T_h[e]) w_h[e % k], T column-major (entry j*k + i)
     const int k = m[h].k, r = c - k, n = k * r, nv = (n + EPL - 1) / EPL;
     const V* src = reinterpret_cast<const V*>(static_cast<const C*>(A.T) + m[h].t_off);
-    const float rr = 1.0f / (float)max(r, 1);
+    const int div = ADJ ? k : r;
+    const float rr = 1.0f / (float)max(div, 1);
     V buf[NV];
 #pragma unroll
     for (int mm = 0; mm < NV; ++mm) {
@@ -450,15 +461,23 @@ __global__ __launch_bounds__(256) void apply_u1g(StageArgs A) {
 #pragma unroll
         for (int t = 0; t < EPL; ++t) {
           const int e = v * EPL + t;
-          if (e < n)
-            s_p[e] = cfma(vec_entry<C>(buf[mm], t), s_w[w][h][g * GL + (int)(((float)e + 0.5f) * rr)], czero(C{}));
+          if (e < n) {
+            const int q = (int)(((float)e + 0.5f) * rr);  // e / div
+            s_p[e] = cfma(conj_if(vec_entry<C>(buf[mm], t), ADJ), s_w[w][h][g * GL + (ADJ ? e - q * div : q)],
+                          czero(C{}));
+          }
         }
       }
     }
     wave_sync_lds();
     if (on && !sk[h]) {
-      const C* p = s_p + (l - below[h]);
-      for (int i = 0; i < k; ++i) acc = cadd(acc, p[i * r]);
+      if constexpr (!ADJ) {
+        const C* p = s_p + (l - below[h]);
+        for (int i = 0; i < k; ++i) acc = cadd(acc, p[i * r]);
+      } else {
+        const C* p = s_p + (l - below[h]) * k;
+        for (int i = 0; i < k; ++i) acc = cadd(acc, p[i]);
+      }
     }
     wave_sync_lds();
   }
@@ -673,13 +692,13 @@ inline dim3 gridn(int64_t n, int64_t nrhs) {
 
 template <bool ADJ>
 hipError_t launch_v_shaped(const StageArgs& a, bool fp64, hipStream_t st) {
-  if (a.nrhs == 1 && !ADJ && a.cmax > 0 && a.cmax <= kWave / 2) {  // small candidate sets: IDs share wavefronts
+  if (a.nrhs == 1 && a.cmax > 0 && a.cmax <= kWave / 2) {  // small candidate sets: IDs share wavefronts
     if (a.cmax <= kWave / 4) {
-      if (fp64) hipLaunchKernelGGL((apply_v1g<double2, 4>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
-      else hipLaunchKernelGGL((apply_v1g<float2, 4>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
+      if (fp64) hipLaunchKernelGGL((apply_v1g<double2, 4, ADJ>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((apply_v1g<float2, 4, ADJ>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
     } else {
-      if (fp64) hipLaunchKernelGGL((apply_v1g<double2, 2>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
-      else hipLaunchKernelGGL((apply_v1g<float2, 2>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
+      if (fp64) hipLaunchKernelGGL((apply_v1g<double2, 2, ADJ>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((apply_v1g<float2, 2, ADJ>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
     }
   } else if (a.nrhs == 1) {
     if (fp64) hipLaunchKernelGGL((apply_v1<double2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
@@ -695,13 +714,13 @@ hipError_t launch_v_shaped(const StageArgs& a, bool fp64, hipStream_t st) {
 
 template <bool ADJ>
 hipError_t launch_u_shaped(const StageArgs& a, bool fp64, hipStream_t st) {
-  if (a.nrhs == 1 && !ADJ && a.cmax > 0 && a.cmax <= kWave / 2) {  // small candidate sets: units share wavefronts
+  if (a.nrhs == 1 && a.cmax > 0 && a.cmax <= kWave / 2) {  // small candidate sets: units share wavefronts
     if (a.cmax <= kWave / 4) {
-      if (fp64) hipLaunchKernelGGL((apply_u1g<double2, 4>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
-      else hipLaunchKernelGGL((apply_u1g<float2, 4>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
+      if (fp64) hipLaunchKernelGGL((apply_u1g<double2, 4, ADJ>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((apply_u1g<float2, 4, ADJ>), dim3(grid1(a.n, 4 * kIdsPerBlock)), dim3(256), 0, st, a);
     } else {
-      if (fp64) hipLaunchKernelGGL((apply_u1g<double2, 2>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
-      else hipLaunchKernelGGL((apply_u1g<float2, 2>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
+      if (fp64) hipLaunchKernelGGL((apply_u1g<double2, 2, ADJ>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((apply_u1g<float2, 2, ADJ>), dim3(grid1(a.n, 2 * kIdsPerBlock)), dim3(256), 0, st, a);
     }
   } else if (a.nrhs == 1) {
     if (fp64) hipLaunchKernelGGL((apply_u1<double2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
