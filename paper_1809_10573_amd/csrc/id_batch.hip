@@ -11,7 +11,7 @@
 //   workgroup of W wavefronts.  Lane l owns candidate l (a column of the
 //   sampled matrix B = K(samples, cand) for a column ID, or of
 //   B = K(cand, samples)^T for a row ID); wave w holds sampled rows
-//   [16 w, 16 w + 16) of every column in registers, so the Householder sweep,
+//   [R w, R w + R) of every column in registers, so the Householder sweep,
 //   column norms and dot products are lane-local.  Per step: residual norms
 //   are recomputed; M = max (DPP reduction); stop when M <= eps |R_00|; the
 //   pivot is the smallest candidate index with norm >= (1 - 1e-8) M (ballot);
@@ -319,7 +319,10 @@ __device__ __forceinline__ int skel_below(uint64_t lo, uint64_t hi, int p) {
 
 // One ID per workgroup of W wavefronts.  Lane l owns candidate columns
 // l + 64 cs (cs < CPL); wavefront w holds sampled rows [R w, R w + R).
-//   CPL = 1, R = 16: up to 64 candidates (W <= 8);
+//   CPL = 1, R = 16: up to 64 candidates (W <= 8); 81..96 and 97..112
+//                    samples take W = 8 with R = 12 and 14 instead, which
+//                    fills the 16 wavefront slots a CU has at this register
+//                    use (two workgroups of 6 or 7 would leave 4 or 2 empty);
 //   CPL = 2, R = 8:  up to 128 candidates (W <= 16), same registers per lane.
 template <int W, int CPL, int R>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) void id_kernel(IdArgs A) {
@@ -1052,14 +1055,14 @@ hipError_t launch_packed(const IdArgs& a, int64_t n, hipStream_t st) {
 
 hipError_t launch_qr_bucket(const IdArgs& a, int64_t n, int bucket, hipStream_t st) {
   switch (bucket) {
-    // up to 64 candidates: 16 rows per wavefront
+    // up to 64 candidates: 16 rows per wavefront (81..112 samples: 8 wavefronts of 12 or 14)
     case 0: return launch_one<1, 1, 16>(a, n, st);
     case 1: return launch_one<2, 1, 16>(a, n, st);
     case 2: return launch_one<3, 1, 16>(a, n, st);
     case 3: return launch_one<4, 1, 16>(a, n, st);
     case 4: return launch_one<5, 1, 16>(a, n, st);
-    case 5: return launch_one<6, 1, 16>(a, n, st);
-    case 6: return launch_one<7, 1, 16>(a, n, st);
+    case 5: return launch_one<8, 1, 12>(a, n, st);
+    case 6: return launch_one<8, 1, 14>(a, n, st);
     case 7: return launch_one<8, 1, 16>(a, n, st);
     // 65..128 candidates: two per lane, 8 rows per wavefront
     case 8: return launch_one<1, 2, 8>(a, n, st);
