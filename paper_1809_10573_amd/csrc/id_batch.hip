@@ -174,8 +174,9 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One wavefront per ID; waves never synchronize with each other.
-__global__ __launch_bounds__(64 * kSelIds) void select_kernel(IdArgs A) {
+// One wavefront per ID; waves never synchronize with each other.  Six
+// wavefronts per SIMD (80 VGPRs): the searches are latency-bound.
+__global__ __launch_bounds__(64 * kSelIds) __attribute__((amdgpu_waves_per_eu(6, 8))) void select_kernel(IdArgs A) {
   __shared__ int s_pos[kSelIds][kMaxSamples];
   __shared__ int s_p0[kSelIds][kMaxSamples];
   __shared__ double s_z[kSelIds][kMaxSamples];
