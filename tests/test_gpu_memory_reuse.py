@@ -61,3 +61,20 @@ def test_reused_memory_gives_identical_factors():
     B.release_cached_memory()
     again = _build_and_apply(I.fio_phase(1.0, 1.0), 4096, 16, 1e-6)
     _same(fresh, again)
+
+
+def test_release_keeps_live_handles():
+    """idbf_release_cached_memory frees only what destroyed handles left: a
+    handle alive across the release applies as before."""
+    X, O = I.uniform_grid(2048)
+    live = B.construct(I.fio_phase(1.0, 1.0), X, O, 1e-6, 16, oversample=2, device=DEV)
+    gen = torch.Generator(device=DEV).manual_seed(5)
+    x = torch.randn(2048, 4, dtype=torch.complex64, device=DEV, generator=gen)
+    y0 = live.apply(x).cpu()
+    gone = B.construct(I.dft_phase(), X, O, 1e-9, 8, oversample=2, device=DEV)
+    gone.apply(x)
+    gone.close()
+    B.release_cached_memory()
+    B.release_cached_memory()  # nothing left to free: still fine
+    assert torch.equal(live.apply(x).cpu(), y0)
+    live.close()
