@@ -14,7 +14,8 @@
 // over the V factors (T column-major), and S^H groups the middle blocks by
 // V_H ID; the same kernels take an ADJ template flag.
 //
-// nrhs == 1: one wavefront per ID (unit), lane = candidate position.
+// nrhs == 1: one wavefront per ID (unit), lane = candidate position; IDs
+//            with at most 16 (32) candidates four (two) per wavefront.
 // nrhs > 1:  one workgroup per (ID or unit, 256 right-hand sides), one
 //            thread per right-hand side, so every load of z / w / x / y is
 //            coalesced (complex128; complex64 runs on the matrix cores).
