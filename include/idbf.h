@@ -40,7 +40,7 @@ typedef enum idbf_status {
   IDBF_ENOMEM = 2,        /* device allocation failed or exceeded opts.mem_cap_bytes */
   IDBF_EHIP = 3,          /* a HIP runtime call failed */
   IDBF_ERANK = 4,         /* an ID needed a rank above the supported maximum (64) */
-  IDBF_EUNSUPPORTED = 5   /* a candidate set above 128 or a sample set above 128 */
+  IDBF_EUNSUPPORTED = 5   /* a candidate set above 128 or a sample set above 256 */
 } idbf_status;
 
 /* Kernels K(x, xi) = exp(2 pi i Phi(x, xi)) (Example 1 and the DFT kernel,
@@ -71,13 +71,21 @@ typedef struct idbf_phase {
   double c0, a, freq, cdiv;  /* c(x) parameters (FIO only; cdiv != 0 there) */
 } idbf_phase;
 
-enum { IDBF_FLAG_PROFILE = 1 }; /* record per-launch device times (idbf_profile_read) */
+/* opts.flags bits:
+ *   IDBF_FLAG_PROFILE: record per-launch device times (idbf_profile_read).
+ *   IDBF_FLAG_PROPOSER_FORCE_REJECT: the residual test rejects every proposal
+ *     of opts.proposer, so every ID falls back to the plain ID (the factors
+ *     then equal those of a construction without a proposer, bit for bit).
+ *   IDBF_FLAG_ALLOW_TRUNCATE: an ID whose eps-rank exceeds the supported 64
+ *     keeps 64 skeletons (a rank-64 truncated ID) instead of failing with
+ *     IDBF_ERANK. */
+enum { IDBF_FLAG_PROFILE = 1, IDBF_FLAG_PROPOSER_FORCE_REJECT = 2, IDBF_FLAG_ALLOW_TRUNCATE = 4 };
 
 enum { IDBF_SAMPLER_MOCKCHEB = 0, IDBF_SAMPLER_RANDOM = 1 };
 
 typedef struct idbf_opts {
   int32_t kmax;        /* rank parameter k of the (eps, k)-ID (Section 2.1); 0: k = min(s, c) */
-  int32_t oversample;  /* oversampling parameter t >= 1: s = min(t |cand|, |allowed|, 128) samples */
+  int32_t oversample;  /* oversampling parameter t >= 1: s = min(t |cand|, |allowed|) samples (<= 256) */
   int32_t flags;       /* IDBF_FLAG_* */
   int32_t sampler;     /* IDBF_SAMPLER_MOCKCHEB (Section 2.1, default) or IDBF_SAMPLER_RANDOM:
                           uniform distinct positions (Floyd's algorithm on SplitMix64 draws from
@@ -117,8 +125,11 @@ void idbf_opts_default(idbf_opts* o);
  * the eps-rank, and the interpolation solve T = R11^{-1} R12 (eq. R2).
  * Levels run U_1, V_1, ..., U_H, V_H with H = floor(L/2), L = log2(N/leaf);
  * then the middle factor's blocks are sampled.  Each ID samples
- * s = min(oversample * |cand|, |allowed|, 128) points.  Candidate sets must
- * stay <= 128 points (else IDBF_EUNSUPPORTED); ranks <= 64 (else
+ * s = min(oversample * |cand|, |allowed|) points (the t k rows of eq.
+ * pivotedQR2 with k = |cand|).  A sample block of more than 128 rows is first
+ * reduced to its |cand| x |cand| triangular factor by unpivoted Householder QR
+ * (same pivots and T in exact arithmetic).  Candidate sets must stay <= 128
+ * points and sample sets <= 256 (else IDBF_EUNSUPPORTED); ranks <= 64 (else
  * IDBF_ERANK).  Synchronizes opts->stream.  The handle owns all factor
  * memory (FP64 factors and an FP32 copy) until idbf_destroy.
  */
@@ -189,8 +200,13 @@ idbf_status idbf_apply_batched(int32_t count, const idbf_handle* hs, const void*
  * non-null stream) into a HIP graph instead of running them; idbf_plan_launch
  * replays that graph on any stream, with no host work per kernel.  The plan
  * keeps the device pointers it was built with: x, y and every handle must
- * stay alive and unchanged until idbf_plan_destroy.  Workspaces are grown
- * before the capture; profiling is suspended while capturing.
+ * stay alive until idbf_plan_destroy.  Workspaces are grown before the
+ * capture; profiling is suspended while capturing.  The graph writes each
+ * handle's apply workspace, so while a plan lives that workspace stays where
+ * it is: idbf_apply, idbf_apply_adjoint or idbf_reserve on such a handle that
+ * would need a larger workspace fails with IDBF_EINVAL (smaller applies reuse
+ * it and must not overlap a replay in time), and idbf_destroy of the handle
+ * fails with IDBF_EINVAL until every plan that holds it is destroyed.
  */
 typedef struct idbf_plan_s* idbf_plan;
 idbf_status idbf_apply_batched_plan(int32_t count, const idbf_handle* hs, const void* const* x, void* const* y,
@@ -204,6 +220,7 @@ idbf_status idbf_plan_destroy(idbf_plan p);
 idbf_status idbf_reserve(idbf_handle h, int64_t nrhs, int32_t dtype);
 
 /* Free a handle and everything it owns.  NULL-safe.  Synchronizes the device.
+ * IDBF_EINVAL (nothing freed) while a captured plan still holds the handle.
  * Its device chunks (factor arena, apply workspace) and pinned staging block
  * are kept by the library for later constructions on the same device, up to
  * IDBF_CACHE_BYTES bytes (environment, read once; default 32 GiB, 0 keeps
@@ -239,6 +256,45 @@ typedef struct idbf_info {
 
 /* Summary of a handle (host *info). */
 idbf_status idbf_get_info(idbf_handle h, idbf_info* info);
+
+/*
+ * Per-level statistics of a construction (Section 2.4's factors, level by
+ * level): for level t = 1..H and side IDBF_SIDE_U / IDBF_SIDE_V the rank
+ * histogram of its 2^(L+1) IDs and what the level stores and cost.
+ * idbf_stats fills *out (host) for levels 1..min(H, IDBF_STATS_LEVELS);
+ * entries of other levels are zero.  It reads the ranks back from the device
+ * (a small temporary device buffer; synchronizes the handle's stream).
+ */
+#define IDBF_STATS_LEVELS 16
+#define IDBF_STATS_RANKS 65   /* ranks 0..64 */
+typedef struct idbf_level_stats_t {
+  int64_t n_ids;            /* IDs of the level (2^(L+1)) */
+  int64_t rank_hist[IDBF_STATS_RANKS];  /* rank_hist[r]: IDs of rank r */
+  int32_t rank_min, rank_max, cand_max, samples_max;
+  int64_t n_skel;           /* skeleton indices (sum of ranks) */
+  int64_t nnz_T;            /* T entries in use: sum k (c - k) */
+  int64_t sampled_entries;  /* kernel entries the IDs sampled: sum s c */
+  int64_t tall;             /* IDs with more than 128 samples (row-reduced first) */
+  int64_t proposed;         /* IDs first computed from a proposal */
+  int64_t accepted;         /* proposals the residual test accepted */
+  int64_t rejected;         /* proposals recomputed by the plain ID */
+  double id_flops;          /* FP64 flops of the level's IDs (as idbf_info.id_flops) */
+  double wall_ms;           /* host wall time of the level inside idbf_construct (shared by all
+                               instances of a batched construction) */
+} idbf_level_stats_t;
+typedef struct idbf_stats_t {
+  int32_t L, H;
+  int32_t levels;           /* levels filled: min(H, IDBF_STATS_LEVELS) */
+  int32_t reserved;
+  idbf_level_stats_t level[IDBF_STATS_LEVELS][2];  /* [t - 1][side] */
+  int64_t nnz_S;            /* middle-factor entries in use */
+  int64_t n_blocks_S;       /* middle-factor blocks */
+  int64_t apply_bytes_c64;  /* factor bytes one complex64 apply streams: 8 (nnz_T + nnz_S) + 40 per ID record */
+  int64_t apply_bytes_c128; /* the same for complex128: 16 (nnz_T + nnz_S) + 40 per ID record */
+  int64_t device_bytes;     /* device memory held by the handle */
+  double construct_ms;      /* host wall time of idbf_construct */
+} idbf_stats_t;
+idbf_status idbf_stats(idbf_handle h, idbf_stats_t* out);
 
 /* Per-kernel device time of a handle built with IDBF_FLAG_PROFILE: HIP events
  * recorded around every launch of idbf_construct, idbf_apply and
@@ -316,7 +372,8 @@ idbf_status idbf_sample(const idbf_phase* phase, const double* X, const double* 
  * (ascending).  side IDBF_SIDE_V: candidates are columns (Omega) and the ID
  * is a column ID of K(samples, cand); IDBF_SIDE_U: candidates are rows (X)
  * and it is a row ID of K(cand, samples).  s = min(oversample * cand_len,
- * allow_len, 128) samples are picked by the Mock-Chebyshev rule.
+ * allow_len) samples are picked by the Mock-Chebyshev rule (an ID with
+ * s > 256: IDBF_EUNSUPPORTED, nothing computed).
  * Outputs (device): rank[q]; mask[2q], mask[2q+1] (128-bit skeleton mask);
  * skel[q * 128 + i] ascending skeleton global indices;
  * T[(q * 4096 + e) * 2 ..] complex128 in the layout of idbf_batch_export.

@@ -41,7 +41,7 @@ from .kernel import (PHASE_DFT, PHASE_FIO, PHASE_J0, amplitude_shift, phase_mod1
                      relative_error)
 from .interp import PIVOT_TIE_REL, column_id, ColumnID
 from .sampling import chebyshev_fraction, mock_chebyshev
-from .idbf import Factors, build, apply, apply_adjoint, densify, tree_sizes, factor_matrices, sample_count, SAMPLE_CAP
+from .idbf import Factors, build, apply, apply_adjoint, densify, tree_sizes, factor_matrices, sample_count
 from . import bessel, mlp
 
 __all__ = [
@@ -49,5 +49,5 @@ __all__ = [
     "matvec_rows", "dense_matvec", "dft_closed_form", "fio_const_closed_form",
     "relative_error", "PIVOT_TIE_REL", "column_id", "ColumnID",
     "chebyshev_fraction", "mock_chebyshev", "Factors", "build", "apply",
-    "apply_adjoint", "densify", "tree_sizes", "factor_matrices", "sample_count", "SAMPLE_CAP", "bessel", "mlp",
+    "apply_adjoint", "densify", "tree_sizes", "factor_matrices", "sample_count", "bessel", "mlp",
 ]

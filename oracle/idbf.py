@@ -27,9 +27,10 @@ pair from the outside in: t = 1 is U^L / V^L of the paper):
 * S: with d = L-H+1, for every R, C' at depth d the block
     K(skel_r(R, ancestor of C' at depth H), skel_c(C', ancestor of R at depth H)).
 
-Each ID samples s = min(t |cand|, |allowed|, 128) points of its allowed set by the
-Mock-Chebyshev rule (oversampling t = 1, k = min{m, n}; Section 3), or all of
-them with ``sample_all`` (used to pin the assembly: then every ID is exact to
+Each ID samples s = min(t |cand|, |allowed|) points of its allowed set by the
+Mock-Chebyshev rule (the t k rows of eq. pivotedQR2 with k = |cand|, i.e.
+k = min{m, n} of the ID's matrix; the paper's experiments use t = 1,
+Section 3), or all of them with ``sample_all`` (used to pin the assembly: then every ID is exact to
 its tolerance on the whole block).  An rID of A(cand, allowed) is the cID of
 the transpose A(cand, s)^T (plain transpose; U = Lambda [I T]^T).
 
@@ -57,11 +58,6 @@ import numpy as np
 from .interp import column_id
 from .kernel import entries
 from .sampling import mock_chebyshev, random_positions
-
-# Largest sample count of one ID (a reading: the paper gives no cap; with
-# t <= 2 it binds only for candidate sets above 64 points).
-SAMPLE_CAP = 128
-
 
 @dataclass
 class IDRecord:
@@ -114,9 +110,10 @@ def _interp(B, tol, kmax, cand):
                     T=cid.T, nsamples=B.shape[0], rdiag=cid.rdiag)
 
 
-def sample_count(c: int, n_allowed: int, oversample: int, smax: int = SAMPLE_CAP) -> int:
-    """s = min(t |cand|, |allowed|, smax): the paper's t k rows (Section 2.1)
-    with k = |cand|, capped at smax (a reading: the paper states no cap)."""
+def sample_count(c: int, n_allowed: int, oversample: int, smax: int = 0) -> int:
+    """s = min(t |cand|, |allowed|): the t k rows of eq. pivotedQR2 (Section
+    2.1) with k = |cand|.  smax > 0 adds a cap the paper does not have (an
+    explicit option for experiments only; no parity test uses it)."""
     s = min(oversample * c, n_allowed)
     return s if smax <= 0 else min(s, smax)
 
@@ -130,12 +127,13 @@ def _samples(coords_of_allowed, allowed, c, oversample, sample_all, smax, sample
 
 
 def build(phase, X, Omega, leaf: int, tol: float, kmax: int = 0, oversample: int = 1,
-          sample_all: bool = False, smax: int = SAMPLE_CAP, sampler: str = "mockcheb",
+          sample_all: bool = False, smax: int = 0, sampler: str = "mockcheb",
           seed: int = 0) -> Factors:
     """Construct the IDBF of K(X, Omega) level by level (Sections 2.2-2.4).
 
-    oversample is the parameter t of Section 2.1: s = min(t |cand|, |allowed|,
-    smax) samples per ID (smax <= 0: no cap).  sampler "mockcheb" (default)
+    oversample is the parameter t of Section 2.1: s = min(t |cand|, |allowed|)
+    samples per ID (eq. pivotedQR2); smax > 0 caps s, a departure from the
+    paper kept only as an explicit option.  sampler "mockcheb" (default)
     or "random" (uniform, sampling.random_positions with this seed; the ID of
     node n and partner p at level t is q = p 2^(L-t+1) + n, side 0 = U, 1 = V).
     """

@@ -31,12 +31,13 @@ EXPORTED = [
     "idbf_construct_batched", "idbf_apply_batched", "idbf_mlp_param_count", "idbf_mlp_create",
     "idbf_mlp_destroy", "idbf_mlp_params", "idbf_mlp_forward", "idbf_mlp_loss_grad", "idbf_mlp_train",
     "idbf_rank_samples", "idbf_apply_batched_plan", "idbf_plan_launch", "idbf_plan_destroy",
-    "idbf_apply_adjoint", "idbf_release_cached_memory",
+    "idbf_apply_adjoint", "idbf_release_cached_memory", "idbf_stats",
 ]
 MLP_INPUTS = 8
-FLAG_PROFILE = 1
+FLAG_PROFILE, FLAG_PROPOSER_FORCE_REJECT, FLAG_ALLOW_TRUNCATE = 1, 2, 4
+STATS_LEVELS, STATS_RANKS = 16, 65
 SAMPLER_MOCKCHEB, SAMPLER_RANDOM = 0, 1
-MAX_CAND, MAX_RANK, MAX_SAMPLES, SLOT = 128, 64, 128, 4096  # limits of include/idbf.h
+MAX_CAND, MAX_RANK, MAX_SAMPLES, SLOT = 128, 64, 256, 4096  # limits of include/idbf.h
 
 
 def mask_bits(mask_row, c: int) -> np.ndarray:
@@ -74,6 +75,21 @@ class Info_t(C.Structure):
                 ("rejected", C.c_int64)]
 
 
+class LevelStats_t(C.Structure):
+    _fields_ = [("n_ids", C.c_int64), ("rank_hist", C.c_int64 * STATS_RANKS), ("rank_min", C.c_int32),
+                ("rank_max", C.c_int32), ("cand_max", C.c_int32), ("samples_max", C.c_int32),
+                ("n_skel", C.c_int64), ("nnz_T", C.c_int64), ("sampled_entries", C.c_int64), ("tall", C.c_int64),
+                ("proposed", C.c_int64), ("accepted", C.c_int64), ("rejected", C.c_int64),
+                ("id_flops", C.c_double), ("wall_ms", C.c_double)]
+
+
+class Stats_t(C.Structure):
+    _fields_ = [("L", C.c_int32), ("H", C.c_int32), ("levels", C.c_int32), ("reserved", C.c_int32),
+                ("level", (LevelStats_t * 2) * STATS_LEVELS), ("nnz_S", C.c_int64), ("n_blocks_S", C.c_int64),
+                ("apply_bytes_c64", C.c_int64), ("apply_bytes_c128", C.c_int64), ("device_bytes", C.c_int64),
+                ("construct_ms", C.c_double)]
+
+
 class KernelStat_t(C.Structure):
     _fields_ = [("name", C.c_char * 24), ("launches", C.c_int32), ("reserved", C.c_int32),
                 ("ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double)]
@@ -101,6 +117,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_apply_adjoint.argtypes = [VP, VP, VP, I64, I32, VP]
     lib.idbf_destroy.argtypes = [VP]
     lib.idbf_get_info.argtypes = [VP, P(Info_t)]
+    lib.idbf_stats.argtypes = [VP, P(Stats_t)]
     lib.idbf_batch_sizes.argtypes = [VP, I32, I32, P(I64), P(I64), P(I64)]
     lib.idbf_batch_export.argtypes = [VP, I32, I32, VP, VP, VP, VP, VP, VP]
     lib.idbf_middle_sizes.argtypes = [VP, P(I64), P(I64)]
@@ -167,6 +184,33 @@ def _dev_i32(a, device):
     return torch.as_tensor(np.ascontiguousarray(a, dtype=np.int32), device=device)
 
 
+def _check_operand(name, x, N, want, device) -> None:
+    """The C ABI takes no lengths: a vector block must be exactly (N,) or
+    (N, nrhs), contiguous, of the apply's dtype and on the factorization's
+    device, or the stage kernels would read past its end."""
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if x.dtype != want or not x.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {want} tensor")
+    if x.dim() not in (1, 2) or x.shape[0] != N:
+        raise ValueError(f"{name} must have shape ({N},) or ({N}, nrhs), got {tuple(x.shape)}")
+    if x.device != device:
+        raise ValueError(f"{name} is on {x.device}, the factorization on {device}")
+
+
+def _check_output(x, y) -> None:
+    """y must match x in dtype, shape and device, be contiguous and not overlap x."""
+    import torch
+    if not isinstance(y, torch.Tensor) or y.dtype != x.dtype or y.shape != x.shape or not y.is_contiguous():
+        raise ValueError("y must be a contiguous tensor of x's dtype and shape")
+    if y.device != x.device:
+        raise ValueError("y must be on x's device")
+    nb = x.numel() * x.element_size()
+    if nb and y.data_ptr() < x.data_ptr() + nb and x.data_ptr() < y.data_ptr() + nb:
+        raise ValueError("y must not overlap x")
+
+
 @dataclass
 class Batch:
     rank: np.ndarray
@@ -200,6 +244,24 @@ class Factorization:
         _check(load().idbf_get_info(self._h, C.byref(inf)))
         return {name: getattr(inf, name) for name, _ in Info_t._fields_}
 
+    def stats(self) -> dict:
+        """idbf_stats: per level and side ("U"/"V") the rank histogram and what
+        the level stores and cost, plus whole-factorization totals."""
+        st = Stats_t()
+        _check(load().idbf_stats(self._h, C.byref(st)))
+        levels = []
+        for t in range(st.levels):
+            row = {}
+            for side, name in ((SIDE_U, "U"), (SIDE_V, "V")):
+                L = st.level[t][side]
+                d = {f: getattr(L, f) for f, _ in LevelStats_t._fields_ if f != "rank_hist"}
+                d["rank_hist"] = np.array(L.rank_hist[:], dtype=np.int64)
+                row[name] = d
+            levels.append(row)
+        out = {f: getattr(st, f) for f, _ in Stats_t._fields_ if f not in ("level", "reserved")}
+        out["per_level"] = levels
+        return out
+
     def apply(self, x, y=None, dtype: int | None = None, stream=None):
         """y = K~ x for a (N,) or (N, nrhs) complex128/complex64 device tensor."""
         return self._apply(load().idbf_apply, x, y, dtype, stream)
@@ -213,11 +275,12 @@ class Factorization:
         if dtype is None:
             dtype = C128 if x.dtype == torch.complex128 else C64
         want = torch.complex128 if dtype == C128 else torch.complex64
-        if x.dtype != want or not x.is_contiguous():
-            raise ValueError(f"x must be a contiguous {want} tensor")
-        nrhs = 1 if x.dim() == 1 else x.shape[1]
+        _check_operand("x", x, self.X.numel(), want, self.X.device)
         if y is None:
             y = torch.empty_like(x)
+        else:
+            _check_output(x, y)
+        nrhs = 1 if x.dim() == 1 else x.shape[1]
         _check(fn(self._h, _ptr(x), _ptr(y), nrhs, dtype, _stream(stream)))
         return y
 
@@ -259,10 +322,16 @@ class Factorization:
         return S[:ne.value], off
 
 
+def _flags(profile: bool, force_reject: bool, allow_truncate: bool) -> int:
+    return ((FLAG_PROFILE if profile else 0) | (FLAG_PROPOSER_FORCE_REJECT if force_reject else 0)
+            | (FLAG_ALLOW_TRUNCATE if allow_truncate else 0))
+
+
 def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample: int = 1,
               mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
               stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0,
-              sampler: int = SAMPLER_MOCKCHEB) -> Factorization:
+              sampler: int = SAMPLER_MOCKCHEB, force_reject: bool = False,
+              allow_truncate: bool = False) -> Factorization:
     """idbf_construct on device copies of X and Omega (float64, ascending)."""
     lib = load()
     Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
@@ -271,7 +340,7 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
     opts = Opts_t()
     lib.idbf_opts_default(C.byref(opts))
     opts.kmax, opts.oversample, opts.mem_cap_bytes = kmax, oversample, mem_cap_bytes
-    opts.flags = FLAG_PROFILE if profile else 0
+    opts.flags = _flags(profile, force_reject, allow_truncate)
     opts.stream = _stream(stream)
     opts.sampler, opts.seed = int(sampler), int(seed)
     if proposer is not None:
@@ -286,7 +355,8 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
 def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample: int = 1,
                       mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
                       stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0,
-                      sampler: int = SAMPLER_MOCKCHEB) -> list:
+                      sampler: int = SAMPLER_MOCKCHEB, force_reject: bool = False,
+                      allow_truncate: bool = False) -> list:
     """idbf_construct_batched: one lockstep construction of len(phases) instances."""
     lib = load()
     n = len(phases)
@@ -300,7 +370,7 @@ def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample
     opts = Opts_t()
     lib.idbf_opts_default(C.byref(opts))
     opts.kmax, opts.oversample, opts.mem_cap_bytes = kmax, oversample, mem_cap_bytes
-    opts.flags = FLAG_PROFILE if profile else 0
+    opts.flags = _flags(profile, force_reject, allow_truncate)
     opts.stream = _stream(stream)
     opts.sampler, opts.seed = int(sampler), int(seed)
     if proposer is not None:
@@ -331,11 +401,15 @@ def apply_batched(facs, xs, ys=None, dtype: int | None = None, stream=None) -> l
     if dtype is None:
         dtype = C128 if xs[0].dtype == torch.complex128 else C64
     want = torch.complex128 if dtype == C128 else torch.complex64
-    for x in xs:
-        if x.dtype != want or not x.is_contiguous():
-            raise ValueError(f"inputs must be contiguous {want} tensors")
+    for i, (f, x) in enumerate(zip(facs, xs)):
+        _check_operand(f"xs[{i}]", x, f.X.numel(), want, f.X.device)
     if ys is None:
         ys = [torch.empty_like(x) for x in xs]
+    elif len(ys) != n:
+        raise ValueError("one output per factorization")
+    else:
+        for x, y in zip(xs, ys):
+            _check_output(x, y)
     hs = (C.c_void_p * n)(*[f._h.value for f in facs])
     xp = (C.c_void_p * n)(*[_ptr(x) for x in xs])
     yp = (C.c_void_p * n)(*[_ptr(y) for y in ys])
@@ -351,8 +425,14 @@ class ApplyPlan:
     def __init__(self, facs, xs, ys, dtype: int | None = None, stream=None):
         import torch
         n = len(facs)
+        if len(xs) != n or len(ys) != n:
+            raise ValueError("one input and one output per factorization")
         if dtype is None:
             dtype = C128 if xs[0].dtype == torch.complex128 else C64
+        want = torch.complex128 if dtype == C128 else torch.complex64
+        for i, (f, x, y) in enumerate(zip(facs, xs, ys)):
+            _check_operand(f"xs[{i}]", x, f.X.numel(), want, f.X.device)
+            _check_output(x, y)
         self._keep = (list(facs), list(xs), list(ys))
         hs = (C.c_void_p * n)(*[f._h.value for f in facs])
         xp = (C.c_void_p * n)(*[_ptr(x) for x in xs])

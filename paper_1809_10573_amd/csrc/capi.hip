@@ -235,6 +235,9 @@ struct Batch {
   int32_t* s_prop = nullptr;   // sample counts the IDs used (proposal, or plain when rejected)
   int32_t* reject = nullptr;   // 1: proposal rejected by the residual test
   int64_t rejected = 0;
+  int64_t tall = 0;               // IDs row-reduced before their QR (first pass)
+  double wall_ms = 0.0;           // host wall time of the level
+  std::chrono::steady_clock::time_point t0;
 };
 
 // HIP events around kernel launches, aggregated by name on request.
@@ -324,8 +327,8 @@ __global__ void check_points_kernel(const double* p, int64_t n, int32_t* bad) {
 // synchronization per phase.
 struct HostStage {
   int64_t st[12];
-  unsigned long long counts[kQrBuckets];
-  unsigned long long cursors[kQrBuckets];
+  unsigned long long counts[kBucketSlots];
+  unsigned long long cursors[kBucketSlots];
   int32_t bad[2];
   double ends[2][2];  // first and last point of X and of Omega
 };
@@ -346,6 +349,9 @@ using namespace idbf;
 struct idbf_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // handles whose workspaces the graph writes: each counts this plan in
+  // live_plans until idbf_plan_destroy, which keeps their workspaces in place
+  std::vector<struct idbf_handle_s*> handles;
   ~idbf_plan_s() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -374,9 +380,13 @@ struct idbf_handle_s {
   Arena arena;
   int32_t* iota = nullptr;
   int32_t* scratch = nullptr;  // skeleton lists before compaction (64 per ID)
-  int32_t* samp_pos = nullptr; // sample positions of the current level (128 per ID)
   int32_t* order = nullptr;    // IDs of the current level grouped by QR wavefronts
-  unsigned long long* bucket = nullptr;  // [0, kQrBuckets): bucket counts, then the fill cursors
+  int32_t* tall_list = nullptr;  // tall IDs (more than kQrRows samples) of the current level
+  unsigned long long* bucket = nullptr;  // [0, kBucketSlots): bucket counts, then the fill cursors
+  // per-level scratch, grown as levels need it: sample positions, then the
+  // tall IDs' slots, reduced blocks and reduction work space
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
   int64_t* stats = nullptr;    // 12 int64 read back after each scan ([8, 11): work of every ID pass)
   int64_t* scan_ws = nullptr;  // tile partials of the prefix scans (kScanWs int64)
   int32_t* status = nullptr;
@@ -399,11 +409,15 @@ struct idbf_handle_s {
   int sampler = IDBF_SAMPLER_MOCKCHEB;
   int margin = 0;
   uint64_t seed = 0;
+  int live_plans = 0;          // captured plans that hold this handle's workspace pointer
+  bool force_reject = false;   // IDBF_FLAG_PROPOSER_FORCE_REJECT
+  bool truncate = false;       // IDBF_FLAG_ALLOW_TRUNCATE
 
   ~idbf_handle_s() {
-    if (pin || ws) (void)hipDeviceSynchronize();  // nothing in flight uses them once they are held
+    if (pin || ws || tmp) (void)hipDeviceSynchronize();  // nothing in flight uses them once they are held
     if (pin) chunk_cache().put_pinned(pin, sizeof(HostStage));
     if (ws) chunk_cache().put(current_device(), ws, ws_bytes);
+    if (tmp) chunk_cache().put(current_device(), tmp, tmp_bytes);
     arena.release();
   }
 };
@@ -438,6 +452,7 @@ idbf_status level_begin(idbf_handle_s* h, const double* X, const double* Om, int
   Batch& b = J.b;
   b.side = side;
   b.t = t;
+  b.t0 = std::chrono::steady_clock::now();
   b.n = int64_t(2) << h->L;
   const int64_t n = b.n;
   Arena& A = h->arena;
@@ -500,7 +515,7 @@ idbf_status level_begin(idbf_handle_s* h, const double* X, const double* Om, int
     TRYHIP(launch_propose(y, b.samples, n, h->oversample, h->margin, b.s_prop, h->stream));
     qr_samples = b.s_prop;
   }
-  TRYHIP(hipMemsetAsync(h->bucket, 0, kQrBuckets * sizeof(unsigned long long), h->stream));
+  TRYHIP(hipMemsetAsync(h->bucket, 0, kBucketSlots * sizeof(unsigned long long), h->stream));
   TRYHIP(launch_bucket_count(qr_samples, b.cand_len, nullptr, n, h->bucket, h->stream));
   h->prof.end(pr, h->stream);
   TRYHIP(hipMemcpyAsync(h->pin->counts, h->bucket, sizeof h->pin->counts, hipMemcpyDeviceToHost, h->stream));
@@ -509,6 +524,68 @@ idbf_status level_begin(idbf_handle_s* h, const double* X, const double* Om, int
 }
 
 idbf_status level_scan(idbf_handle_s* h);
+
+// Scratch of a level's ID passes in the handle's growable buffer: sample
+// positions (s_max per ID) and, for the n_tall tall IDs, their slots,
+// reduced c x c blocks and the reduction's s x c work blocks (a bounded
+// number of them; the reduction runs in chunks).
+constexpr size_t kTallWorkBytes = size_t(1) << 30;
+
+idbf_status grow_tmp(idbf_handle_s* h, size_t bytes) {
+  if (bytes <= h->tmp_bytes) return IDBF_OK;
+  if (h->tmp) {
+    IDBF_HIP_CHECK(hipStreamSynchronize(h->stream));  // the previous level's passes are done with it
+    chunk_cache().put(current_device(), h->tmp, h->tmp_bytes);
+    h->tmp = nullptr;
+    h->tmp_bytes = 0;
+  }
+  if (h->arena.limit && h->arena.total + bytes > h->arena.limit) {
+    set_error("device memory cap of %zu bytes exceeded (%zu held, %zu requested for level scratch)",
+              (size_t)h->arena.limit, h->arena.total, bytes);
+    return IDBF_ENOMEM;
+  }
+  size_t got = bytes;
+  hipError_t e = device_alloc(bytes, SIZE_MAX, &h->tmp, &got);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    h->tmp = nullptr;
+    set_error("level scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
+    return IDBF_ENOMEM;
+  }
+  h->tmp_bytes = got;
+  return IDBF_OK;
+}
+
+idbf_status level_scratch(idbf_handle_s* h, IdArgs& ia, int64_t n, int s_max, int c_max, int64_t n_tall) {
+  const int64_t ld = std::max(1, s_max);
+  size_t bytes = ((size_t(n) * ld * 4 + 255) & ~size_t(255));
+  size_t chunk = 0, slot_b = 0, R_b = 0;
+  if (n_tall > 0) {
+    const size_t work_ld = size_t(s_max) * c_max;
+    chunk = std::max<size_t>(1, std::min<size_t>(n_tall, kTallWorkBytes / (work_ld * 16)));
+    slot_b = (size_t(n) * 4 + 255) & ~size_t(255);
+    R_b = size_t(n_tall) * c_max * c_max * 16;
+    bytes += slot_b + R_b + chunk * work_ld * 16;
+  }
+  TRY(grow_tmp(h, bytes));
+  char* p = static_cast<char*>(h->tmp);
+  ia.samp_pos = reinterpret_cast<int32_t*>(p);
+  ia.samp_ld = ld;
+  p += (size_t(n) * ld * 4 + 255) & ~size_t(255);
+  ia.n_tall = n_tall;
+  ia.tall_list = h->tall_list;
+  if (n_tall > 0) {
+    ia.tall_slot = reinterpret_cast<int32_t*>(p);
+    p += slot_b;
+    ia.tall_R = reinterpret_cast<double2*>(p);
+    ia.tall_ld2 = int64_t(c_max) * c_max;
+    p += R_b;
+    ia.tall_work = reinterpret_cast<double2*>(p);
+    ia.tall_work_ld = int64_t(s_max) * c_max;
+    ia.tall_chunk = (int64_t)chunk;
+  }
+  return IDBF_OK;
+}
 
 idbf_status level_ids(idbf_handle_s* h) {
   LevelJob& J = h->job;
@@ -524,6 +601,11 @@ idbf_status level_ids(idbf_handle_s* h) {
   if (b.cand_max > kMaxCand) {
     set_error("level %d %c: a candidate set has %d points (max %d); ranks grew past %d", t,
               side == IDBF_SIDE_U ? 'U' : 'V', b.cand_max, kMaxCand, kMaxCand / 2);
+    return IDBF_EUNSUPPORTED;
+  }
+  if (b.s_max > kMaxSamples) {
+    set_error("level %d %c: an ID samples %d points (t |cand|; max %d)", t, side == IDBF_SIDE_U ? 'U' : 'V',
+              b.s_max, kMaxSamples);
     return IDBF_EUNSUPPORTED;
   }
   TRY(A.get(std::max<int64_t>(b.n_T, 1), &b.T128));
@@ -546,22 +628,25 @@ idbf_status level_ids(idbf_handle_s* h) {
   ia.allow_coord = b.allow_coord;
   ia.tol = h->tol;
   ia.kmax = h->kmax;
+  ia.truncate = h->truncate;
   ia.oversample = h->oversample;
   ia.s_max = b.s_max;
   ia.c_max = b.cand_max;
   ia.sampler = h->sampler;
   ia.level = t;
   ia.seed = h->seed;
-  ia.samp_pos = h->samp_pos;
+  b.tall = (int64_t)h->pin->counts[kQrBuckets];
+  TRY(level_scratch(h, ia, n, b.s_max, b.cand_max, b.tall));
   ia.order = h->order;
   ia.bucket_off[0] = 0;
   for (int w = 0; w < kQrBuckets; ++w) ia.bucket_off[w + 1] = ia.bucket_off[w] + (int64_t)h->pin->counts[w];
   for (int w = 0; w < kQrBuckets; ++w) h->pin->cursors[w] = (unsigned long long)ia.bucket_off[w];
-  TRYHIP(hipMemcpyAsync(h->bucket + kQrBuckets, h->pin->cursors, sizeof h->pin->cursors, hipMemcpyHostToDevice,
+  h->pin->cursors[kQrBuckets] = 0;
+  TRYHIP(hipMemcpyAsync(h->bucket + kBucketSlots, h->pin->cursors, sizeof h->pin->cursors, hipMemcpyHostToDevice,
                         h->stream));
   ia.samples = b.s_prop;  // null without a proposer
-  TRYHIP(launch_bucket_fill(b.s_prop ? b.s_prop : b.samples, b.cand_len, nullptr, n, h->bucket + kQrBuckets,
-                            h->order, h->stream));
+  TRYHIP(launch_bucket_fill(b.s_prop ? b.s_prop : b.samples, b.cand_len, nullptr, n, h->bucket + kBucketSlots,
+                            h->order, h->tall_list, h->stream));
   ia.rank = b.rank;
   ia.mask = b.mask;
   ia.skel_out = h->scratch;
@@ -585,13 +670,14 @@ idbf_status level_ids(idbf_handle_s* h) {
     ra.level = t;
     ra.seed = h->seed;
     ra.factor = 10.0;
+    ra.force_reject = h->force_reject;
     ra.reject = b.reject;
     ra.s_prop = b.s_prop;
     ra.samples_plain = b.samples;
     pr = h->prof.begin("id_residual", h->stream);
     TRYHIP(launch_residual(ra, h->stream));
     h->prof.end(pr, h->stream);
-    TRYHIP(hipMemsetAsync(h->bucket, 0, kQrBuckets * sizeof(unsigned long long), h->stream));
+    TRYHIP(hipMemsetAsync(h->bucket, 0, kBucketSlots * sizeof(unsigned long long), h->stream));
     TRYHIP(launch_bucket_count(b.s_prop, b.cand_len, b.reject, n, h->bucket, h->stream));
     TRYHIP(hipMemcpyAsync(h->pin->counts, h->bucket, sizeof h->pin->counts, hipMemcpyDeviceToHost, h->stream));
     return IDBF_OK;
@@ -608,10 +694,14 @@ idbf_status level_fallback(idbf_handle_s* h) {
   for (int w = 0; w < kQrBuckets; ++w) ia.bucket_off[w + 1] = ia.bucket_off[w] + (int64_t)h->pin->counts[w];
   b.rejected = ia.bucket_off[kQrBuckets];
   if (b.rejected > 0) {
+    // scratch of this pass: sample positions and the rejected tall IDs' blocks
+    TRY(level_scratch(h, ia, b.n, b.s_max, b.cand_max, (int64_t)h->pin->counts[kQrBuckets]));
     for (int w = 0; w < kQrBuckets; ++w) h->pin->cursors[w] = (unsigned long long)ia.bucket_off[w];
-    TRYHIP(hipMemcpyAsync(h->bucket + kQrBuckets, h->pin->cursors, sizeof h->pin->cursors, hipMemcpyHostToDevice,
+    h->pin->cursors[kQrBuckets] = 0;
+    TRYHIP(hipMemcpyAsync(h->bucket + kBucketSlots, h->pin->cursors, sizeof h->pin->cursors, hipMemcpyHostToDevice,
                           h->stream));
-    TRYHIP(launch_bucket_fill(b.s_prop, b.cand_len, b.reject, b.n, h->bucket + kQrBuckets, h->order, h->stream));
+    TRYHIP(launch_bucket_fill(b.s_prop, b.cand_len, b.reject, b.n, h->bucket + kBucketSlots, h->order,
+                              h->tall_list, h->stream));
     ia.samples = b.s_prop;  // plain counts for the rejected IDs
     ia.sel_list = h->order;
     ia.sel_n = b.rejected;
@@ -681,6 +771,7 @@ idbf_status level_finish(idbf_handle_s* h) {
   TRYHIP(launch_pack_meta(b.T_off, b.mask, b.cand_beg, b.skel_off, b.cand_len, b.rank, n, b.meta, h->stream));
   h->prof.end(pr, h->stream);
   h->max_skel = std::max(h->max_skel, b.n_skel);
+  b.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - b.t0).count();
   if (side == IDBF_SIDE_U) h->U.push_back(b); else h->V.push_back(b);
   return IDBF_OK;
 }
@@ -830,9 +921,9 @@ idbf_status construct_setup(idbf_handle_s* h) {
   TRY(A.get(h->N, &h->iota));
   if (h->H > 0) {
     TRY(A.get((int64_t(2) << h->L) * kMaxCand, &h->scratch));
-    TRY(A.get((int64_t(2) << h->L) * kMaxSamples, &h->samp_pos));
     TRY(A.get(int64_t(2) << h->L, &h->order));
-    TRY(A.get(2 * kQrBuckets, &h->bucket));
+    TRY(A.get(int64_t(2) << h->L, &h->tall_list));
+    TRY(A.get(2 * kBucketSlots, &h->bucket));
   }
   return IDBF_OK;
 }
@@ -875,6 +966,14 @@ idbf_status construct_impl(idbf_handle_s* h, const double* X, const double* Om) 
 
 idbf_status grow_workspace(idbf_handle_s* h, size_t bytes, hipStream_t st) {
   if (h->H == 0 || bytes <= h->ws_bytes) return IDBF_OK;
+  if (h->live_plans > 0) {
+    // a captured plan writes the current workspace: moving it would leave the
+    // graph pointing at memory another handle may take over
+    set_error("the apply workspace (%zu bytes) is held by %d captured plan(s); destroy them before applying "
+              "with more right-hand sides (%zu bytes needed)",
+              h->ws_bytes, h->live_plans, bytes);
+    return IDBF_EINVAL;
+  }
   if (h->ws) {
     (void)st;
     IDBF_HIP_CHECK(hipDeviceSynchronize());  // applies on any stream may still read it
@@ -958,7 +1057,13 @@ idbf_status make_handle(const idbf_phase* phase, const double* X, const double* 
   h->arena.chunk_min = std::max<size_t>(size_t(64) << 20, size_t(N) * 2048);
   if (o.mem_cap_bytes) h->arena.chunk_min = std::min<size_t>(h->arena.chunk_min, o.mem_cap_bytes);
   h->stream = static_cast<hipStream_t>(o.stream);
+  if (o.flags & ~(IDBF_FLAG_PROFILE | IDBF_FLAG_PROPOSER_FORCE_REJECT | IDBF_FLAG_ALLOW_TRUNCATE)) {
+    set_error("opts: unknown flags 0x%x", (unsigned)o.flags);
+    return IDBF_EINVAL;
+  }
   h->prof.on = (o.flags & IDBF_FLAG_PROFILE) != 0;
+  h->force_reject = (o.flags & IDBF_FLAG_PROPOSER_FORCE_REJECT) != 0;
+  h->truncate = (o.flags & IDBF_FLAG_ALLOW_TRUNCATE) != 0;
   h->proposer = o.proposer;
   h->margin = o.proposal_margin;
   h->seed = o.seed;
@@ -1142,6 +1247,10 @@ idbf_status idbf_construct_batched(int32_t count, const idbf_phase* phases, cons
 
 idbf_status idbf_destroy(idbf_handle h) {
   if (!h) return IDBF_OK;
+  if (h->live_plans > 0) {
+    set_error("destroy: %d captured plan(s) still use this handle; destroy them first", h->live_plans);
+    return IDBF_EINVAL;
+  }
   (void)hipDeviceSynchronize();
   delete h;
   return IDBF_OK;
@@ -1403,6 +1512,8 @@ idbf_status idbf_apply_batched_plan(int32_t count, const idbf_handle* hs, const 
   }
   for (int i = 0; i < count; ++i) hs[i]->prof.on = prof[i];
   if (s != IDBF_OK) return s;
+  plan->handles.assign(hs, hs + count);
+  for (int i = 0; i < count; ++i) ++hs[i]->live_plans;
   *out = plan.release();
   return IDBF_OK;
 }
@@ -1420,6 +1531,7 @@ idbf_status idbf_plan_launch(idbf_plan p, void* stream) {
 idbf_status idbf_plan_destroy(idbf_plan p) {
   if (!p) return IDBF_OK;
   (void)hipDeviceSynchronize();
+  for (idbf_handle_s* h : p->handles) --h->live_plans;
   delete p;
   return IDBF_OK;
 }
@@ -1464,8 +1576,72 @@ idbf_status idbf_get_info(idbf_handle h, idbf_info* info) {
     }
   }
   if (info->n_ids == 0) info->rank_min = 0;
-  info->device_bytes = (int64_t)(h->arena.total + h->ws_bytes);
+  info->device_bytes = (int64_t)(h->arena.total + h->ws_bytes + h->tmp_bytes);
   info->construct_ms = h->construct_ms;
+  return IDBF_OK;
+}
+
+idbf_status idbf_stats(idbf_handle h, idbf_stats_t* out) {
+  g_err[0] = 0;
+  if (!h || !out) {
+    set_error("stats: handle and out must be non-NULL");
+    return IDBF_EINVAL;
+  }
+  std::memset(out, 0, sizeof *out);
+  out->L = h->L;
+  out->H = h->H;
+  out->levels = std::min(h->H, IDBF_STATS_LEVELS);
+  const int nb = 2 * out->levels;
+  unsigned long long* hist = nullptr;
+  std::vector<unsigned long long> hh(size_t(std::max(nb, 1)) * IDBF_STATS_RANKS, 0ull);
+  if (nb > 0) {
+    IDBF_HIP_CHECK(hipMalloc(&hist, hh.size() * sizeof(unsigned long long)));
+    hipError_t e = hipMemsetAsync(hist, 0, hh.size() * sizeof(unsigned long long), h->stream);
+    for (int t = 1; t <= out->levels && e == hipSuccess; ++t)
+      for (int side = 0; side < 2 && e == hipSuccess; ++side) {
+        const Batch& b = side == IDBF_SIDE_U ? h->U[t - 1] : h->V[t - 1];
+        e = launch_rank_hist(b.rank, b.n, hist + size_t(2 * (t - 1) + side) * IDBF_STATS_RANKS, h->stream);
+      }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hh.data(), hist, hh.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    else (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(hist);
+    if (e != hipSuccess) {
+      set_error("stats: %s", hipGetErrorString(e));
+      return IDBF_EHIP;
+    }
+  }
+  int64_t records = 0, nnz_T = 0;
+  for (int t = 1; t <= h->H; ++t)
+    for (int side = 0; side < 2; ++side) {
+      const Batch& b = side == IDBF_SIDE_U ? h->U[t - 1] : h->V[t - 1];
+      records += b.n;
+      nnz_T += b.nnz_T;
+      if (t > out->levels) continue;
+      idbf_level_stats_t& L = out->level[t - 1][side];
+      L.n_ids = b.n;
+      for (int r = 0; r < IDBF_STATS_RANKS; ++r) L.rank_hist[r] = (int64_t)hh[size_t(2 * (t - 1) + side) * IDBF_STATS_RANKS + r];
+      L.rank_min = b.rank_min;
+      L.rank_max = b.rank_max;
+      L.cand_max = b.cand_max;
+      L.samples_max = b.s_max;
+      L.n_skel = b.n_skel;
+      L.nnz_T = b.nnz_T;
+      L.sampled_entries = b.sampled;
+      L.tall = b.tall;
+      L.proposed = b.s_prop ? b.n : 0;
+      L.rejected = b.rejected;
+      L.accepted = L.proposed - L.rejected;
+      L.id_flops = b.flops;
+      L.wall_ms = b.wall_ms;
+    }
+  out->nnz_S = h->nnz_S;
+  out->n_blocks_S = h->nblk;
+  out->apply_bytes_c64 = 8 * (nnz_T + h->nnz_S) + 40 * records;
+  out->apply_bytes_c128 = 16 * (nnz_T + h->nnz_S) + 40 * records;
+  out->device_bytes = (int64_t)(h->arena.total + h->ws_bytes + h->tmp_bytes);
+  out->construct_ms = h->construct_ms;
   return IDBF_OK;
 }
 
@@ -1606,28 +1782,58 @@ idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double
   IDBF_HIP_CHECK(hipMemcpyAsync(cl.data(), cand_len, n_ids * 4, hipMemcpyDeviceToHost, st));
   IDBF_HIP_CHECK(hipMemcpyAsync(al.data(), allow_len, n_ids * 4, hipMemcpyDeviceToHost, st));
   IDBF_HIP_CHECK(hipStreamSynchronize(st));
-  int smax = 0, cmax = 0;
+  int smax = 0, cmax = 0, rows_max = 0;
+  std::vector<int32_t> tall;
   for (int64_t q = 0; q < n_ids; ++q) {
     if (cl[q] < 1 || cl[q] > kMaxCand || al[q] < 1) {
       set_error("ID %lld: candidate count %d must be in [1, %d] and allowed count %d >= 1", (long long)q, cl[q],
                 kMaxCand, al[q]);
       return IDBF_EINVAL;
     }
-    smax = std::max<int>(smax, (int)std::min<int64_t>(std::min<int64_t>((int64_t)oversample * cl[q], al[q]),
-                                                      kMaxSamples));
+    const int64_t sq = std::min<int64_t>((int64_t)oversample * cl[q], al[q]);
+    if (sq > kMaxSamples) {
+      set_error("ID %lld samples %lld points (oversample x candidates; max %d)", (long long)q, (long long)sq,
+                kMaxSamples);
+      return IDBF_EUNSUPPORTED;
+    }
+    smax = std::max<int>(smax, (int)sq);
     cmax = std::max(cmax, cl[q]);
+    rows_max = std::max(rows_max, qr_rows(cl[q], (int)sq));
+    if (is_tall((int)sq)) tall.push_back((int32_t)q);
   }
-  int32_t* status = nullptr;
-  int32_t* samp_pos = nullptr;
-  IDBF_HIP_CHECK(hipMalloc(&status, sizeof(int32_t)));
-  if (hipMalloc(&samp_pos, size_t(n_ids) * kMaxSamples * sizeof(int32_t)) != hipSuccess) {
+  // one device block: status, sample positions, and the tall IDs' list,
+  // slots, reduced blocks and reduction work space
+  const int64_t n_tall = (int64_t)tall.size();
+  const size_t work_ld = size_t(smax) * cmax;
+  const size_t chunk = n_tall ? std::max<size_t>(1, std::min<size_t>(n_tall, kTallWorkBytes / (work_ld * 16))) : 0;
+  auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t b_pos = up(size_t(n_ids) * smax * 4), b_list = up(size_t(n_tall) * 4), b_slot = up(size_t(n_ids) * 4);
+  const size_t b_R = size_t(n_tall) * cmax * cmax * 16, b_work = chunk * work_ld * 16;
+  const size_t total = 256 + b_pos + (n_tall ? b_list + b_slot + b_R + b_work : 0);
+  char* blk = nullptr;
+  if (hipMalloc(reinterpret_cast<void**>(&blk), total) != hipSuccess) {
     (void)hipGetLastError();
-    (void)hipFree(status);
-    set_error("id_batch: no memory for %lld sample lists", (long long)n_ids);
+    set_error("id_batch: no memory for %lld IDs' scratch (%zu bytes)", (long long)n_ids, total);
     return IDBF_ENOMEM;
   }
-  IDBF_HIP_CHECK(hipMemsetAsync(status, 0, sizeof(int32_t), st));
+  int32_t* status = reinterpret_cast<int32_t*>(blk);
   IdArgs ia{};
+  ia.samp_pos = reinterpret_cast<int32_t*>(blk + 256);
+  ia.samp_ld = std::max(1, smax);
+  hipError_t e = hipMemsetAsync(status, 0, sizeof(int32_t), st);
+  if (n_tall) {
+    char* p = blk + 256 + b_pos;
+    int32_t* list = reinterpret_cast<int32_t*>(p);
+    ia.tall_list = list;
+    ia.n_tall = n_tall;
+    ia.tall_slot = reinterpret_cast<int32_t*>(p + b_list);
+    ia.tall_R = reinterpret_cast<double2*>(p + b_list + b_slot);
+    ia.tall_ld2 = int64_t(cmax) * cmax;
+    ia.tall_work = reinterpret_cast<double2*>(p + b_list + b_slot + b_R);
+    ia.tall_work_ld = (int64_t)work_ld;
+    ia.tall_chunk = (int64_t)chunk;
+    if (e == hipSuccess) e = hipMemcpyAsync(list, tall.data(), size_t(n_tall) * 4, hipMemcpyHostToDevice, st);
+  }
   ia.ph = to_dev(*phase);
   ia.X = X;
   ia.Om = Omega;
@@ -1644,7 +1850,7 @@ idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double
   ia.oversample = oversample;
   ia.s_max = smax;
   ia.c_max = cmax;
-  ia.samp_pos = samp_pos;
+  ia.rows_max = rows_max;
   ia.rank = rank;
   ia.mask = mask;
   ia.skel_out = skel;
@@ -1652,12 +1858,12 @@ idbf_status idbf_id_batch(const idbf_phase* phase, const double* X, const double
   ia.T64 = nullptr;
   ia.T_off = nullptr;
   ia.status = status;
-  hipError_t e = launch_id_batch(ia, st);
+  if (e == hipSuccess) e = launch_id_batch(ia, st);
   int32_t flag = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&flag, status, sizeof flag, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(status);
-  (void)hipFree(samp_pos);
+  else (void)hipStreamSynchronize(st);  // nothing may still use the block when it is freed
+  (void)hipFree(blk);
   if (e != hipSuccess) {
     set_error("id_batch: %s", hipGetErrorString(e));
     return IDBF_EHIP;

@@ -12,7 +12,9 @@ namespace idbf {
 
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kMaxCand = 128;    // candidates per ID (two lanes' worth above 64)
-constexpr int kMaxSamples = 128; // sampled rows per ID: s = min(t c, |allowed|, 128)
+constexpr int kMaxSamples = 256; // sampled rows per ID: s = min(t c, |allowed|) <= 256
+constexpr int kQrRows = 128;     // rows the register-resident QR kernels hold; taller sample
+                                 // blocks are first reduced to their c x c triangular factor
 constexpr int kMaxRank = 64;     // rank of an ID
 constexpr int kSlot = 4096;      // T entries per ID in slot layout (max k (c - k))
 constexpr double kPivotTie = 1e-8;

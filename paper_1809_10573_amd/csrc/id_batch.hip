@@ -186,9 +186,9 @@ __global__ __launch_bounds__(64 * kSelIds) __attribute__((amdgpu_waves_per_eu(6,
   if (qi >= (A.sel_list ? A.sel_n : A.n_ids)) return;
   const int64_t q = A.sel_list ? (int64_t)A.sel_list[qi] : qi;
   const int c = A.cand_len[q], na = A.allow_len[q];
-  const int s = A.samples ? A.samples[q] : min(min(A.oversample * c, na), kMaxSamples);
-  if (c < 1 || c > kMaxCand || na < 1 || s < 1 || s > kMaxSamples) return;  // id_kernel reports it
-  int32_t* out = A.samp_pos + q * (int64_t)kMaxSamples;
+  const int s = A.samples ? A.samples[q] : min(A.oversample * c, na);
+  if (c < 1 || c > kMaxCand || na < 1 || s < 1 || s > kMaxSamples || s > A.samp_ld) return;  // the QR reports it
+  int32_t* out = A.samp_pos + q * A.samp_ld;
   if (s >= na) {
     for (int j = lane; j < na; j += kWave) out[j] = j;
     return;
@@ -353,8 +353,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   const int nthreads = kWave * W;
   const int cb = A.cand_beg[q], c = A.cand_len[q];
   const int ab = A.allow_beg[q], na = A.allow_len[q];
-  const int s = A.samples ? A.samples[q] : min(min(A.oversample * c, na), kMaxSamples);
-  if (c < 1 || c > NC || na < 1 || s < 1 || s > SMAX || s > na) {
+  const int s = A.samples ? A.samples[q] : min(A.oversample * c, na);
+  const bool tall = is_tall(s);  // the block is the row reduction's c x c triangular factor
+  const int srows = qr_rows(c, s);
+  const int64_t tslot =
+      (tall && A.tall_slot) ? (int64_t)__builtin_amdgcn_readfirstlane(A.tall_slot[q]) : -1;  // uniform
+  if (c < 1 || c > NC || na < 1 || s < 1 || s > kMaxSamples || s > A.samp_ld || srows > SMAX || s > na ||
+      (tall && (tslot < 0 || tslot >= A.n_tall || (int64_t)c * c > A.tall_ld2))) {
     if (threadIdx.x == 0) atomicOr(A.status, kErrSize);
     return;
   }
@@ -377,30 +382,41 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       if (!isV && fio) ccx[cs] = amplitude_shift(A.ph, ccoord[cs]);
     }
   }
-  const int32_t* sp = A.samp_pos + q * (int64_t)kMaxSamples;
-  for (int j = threadIdx.x; j < s; j += nthreads) {
+  const int32_t* sp = A.samp_pos + q * A.samp_ld;
+  for (int j = threadIdx.x; j < s && !tall; j += nthreads) {
     const double v = as(sp[j]);
     s_coord[j] = v;
     s_cx[j] = (isV && fio) ? amplitude_shift(A.ph, v) : 0.0;
   }
   __syncthreads();
 
-  // sampled block: rows [R w, R w + R) of columns lane + 64 cs (rows >= s stay zero)
+  // sampled block: rows [R w, R w + R) of columns lane + 64 cs (rows >= srows stay zero)
   const int row0 = w * R;
   double2 a[CPL][R];
+  if (tall) {  // upper triangle of the reduced block
+    const double2* Rt = A.tall_R + tslot * A.tall_ld2;
 #pragma unroll
-  for (int cs = 0; cs < CPL; ++cs)
+    for (int cs = 0; cs < CPL; ++cs)
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int row = row0 + i;
-      double2 v = make_double2(0.0, 0.0);
-      if (lane + kWave * cs < c && row < s)
-        v = isV ? kernel_entry(A.ph, s_coord[row], s_cx[row], ccoord[cs])
-                : kernel_entry(A.ph, ccoord[cs], ccx[cs], s_coord[row]);
-      a[cs][i] = v;
-    }
+      for (int i = 0; i < R; ++i) {
+        const int row = row0 + i, col = lane + kWave * cs;
+        a[cs][i] = (col < c && row <= col) ? Rt[col * c + row] : make_double2(0.0, 0.0);
+      }
+  } else {
+#pragma unroll
+    for (int cs = 0; cs < CPL; ++cs)
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int row = row0 + i;
+        double2 v = make_double2(0.0, 0.0);
+        if (lane + kWave * cs < c && row < s)
+          v = isV ? kernel_entry(A.ph, s_coord[row], s_cx[row], ccoord[cs])
+                  : kernel_entry(A.ph, ccoord[cs], ccx[cs], s_coord[row]);
+        a[cs][i] = v;
+      }
+  }
 
-  const int kuser = min(min(s, c), A.kmax > 0 ? A.kmax : (1 << 30));
+  const int kuser = min(min(min(s, c), A.kmax > 0 ? A.kmax : (1 << 30)), A.truncate ? kMaxRank : (1 << 30));
   bool pivoted[CPL];
   int pstep[CPL];  // step at which the column became a pivot
 #pragma unroll
@@ -732,7 +748,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     return qi < n ? (A.order ? (int64_t)A.order[qi] : qi) : -1;
   };
   auto samples_of = [&](int64_t q, int c, int na) {
-    return A.samples ? A.samples[q] : min(min(A.oversample * c, na), kMaxSamples);
+    return A.samples ? A.samples[q] : min(A.oversample * c, na);
   };
   // this lane's ID; an ID outside the kernel's limits is reported and sits out
   const int64_t q = id_of(gi);
@@ -742,7 +758,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     cb = A.cand_beg[q];
     const int na = A.allow_len[q];
     s = samples_of(q, c, na);
-    if (c < 1 || c > GL || na < 1 || s < 1 || s > SMAX || s > na) {
+    // tall IDs (reduced blocks) always run on the one-ID kernels
+    if (c < 1 || c > GL || na < 1 || s < 1 || s > SMAX || s > A.samp_ld || s > na) {
       if (w == 0 && gl == 0) atomicOr(A.status, kErrSize);
       c = 0;
       s = 0;
@@ -764,9 +781,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     if (qg < 0) continue;
     const int cg = A.cand_len[qg], nag = A.allow_len[qg];
     const int sg = samples_of(qg, cg, nag);
-    if (j >= sg || j >= nag) continue;
+    if (j >= sg || j >= nag || sg > SMAX || sg > A.samp_ld) continue;
     const int ab = A.allow_beg[qg];
-    const int pos = A.samp_pos[qg * (int64_t)kMaxSamples + j];
+    const int pos = A.samp_pos[qg * A.samp_ld + j];
     const double v = A.allow_coord ? A.allow_coord[ab + pos] : (isV ? A.X : A.Om)[A.allow_idx[ab + pos]];
     s_coord[g][j] = v;
     s_cx[g][j] = (isV && fio) ? amplitude_shift(A.ph, v) : 0.0;
@@ -785,7 +802,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     a[i] = v;
   }
 
-  const int kuser = min(min(s, c), A.kmax > 0 ? A.kmax : (1 << 30));
+  const int kuser = min(min(min(s, c), A.kmax > 0 ? A.kmax : (1 << 30)), A.truncate ? kMaxRank : (1 << 30));
   bool pivoted = false;
   int pstep = 0;
   double stop2 = 0.0;
@@ -1010,6 +1027,130 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   }
 }
 
+// Row reduction of a tall sampled block (s > kQrRows rows, c <= 128
+// columns): B = Q0 R0 by unpivoted Householder QR in FP64, keeping the c x c
+// upper triangular R0.  Column pivoting picks each pivot by the norms of the
+// columns' components orthogonal to the columns already taken; these depend
+// on B only through B^H B = R0^H R0.  So the pivoted QR of R0 takes the
+// pivots and |R_jj| that the pivoted QR of B takes, its R differs only by row
+// phases, and T = R11^{-1} R12 is the same (in exact arithmetic).
+// One workgroup per tall ID; the s x c block lives in a global scratch slot
+// (column-major, leading dimension s), each wavefront updating whole columns.
+constexpr int kTallThreads = 256;
+
+__device__ __forceinline__ double2 wave_sum(double2 v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off, kWave);
+    v.y += __shfl_xor(v.y, off, kWave);
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(kTallThreads) void tall_reduce_kernel(IdArgs A, int64_t slot0) {
+  constexpr int NW = kTallThreads / kWave;
+  __shared__ double s_coord[kMaxSamples];
+  __shared__ double s_cx[kMaxSamples];
+  __shared__ double s_ccoord[kMaxCand];
+  __shared__ double s_ccx[kMaxCand];
+  __shared__ double2 s_v[kMaxSamples];
+  __shared__ double s_red[NW];
+  __shared__ double s_tau;
+  const int64_t slot = slot0 + blockIdx.x;
+  if (slot >= A.n_tall) return;
+  const int64_t q = A.tall_list[slot];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  const int c = A.cand_len[q], cb = A.cand_beg[q], na = A.allow_len[q], ab = A.allow_beg[q];
+  const int s = A.samples ? A.samples[q] : min(A.oversample * c, na);
+  if (c < 1 || c > kMaxCand || !is_tall(s) || s > kMaxSamples || s > na || s > A.samp_ld ||
+      (int64_t)s * c > A.tall_work_ld || (int64_t)c * c > A.tall_ld2) {
+    if (tid == 0) {
+      A.tall_slot[q] = -1;  // the QR kernel reports it
+      atomicOr(A.status, kErrSize);
+    }
+    return;
+  }
+  const bool isV = (A.side == IDBF_SIDE_V);
+  const bool fio = (A.ph.kind == IDBF_PHASE_FIO);
+  const Seg cs_{A.cand_coord ? A.cand_coord + cb : nullptr, isV ? A.Om : A.X, A.cand_idx + cb};
+  const Seg as{A.allow_coord ? A.allow_coord + ab : nullptr, isV ? A.X : A.Om, A.allow_idx + ab};
+  const int32_t* sp = A.samp_pos + q * A.samp_ld;
+  for (int j = tid; j < s; j += kTallThreads) {
+    const double v = as(sp[j]);
+    s_coord[j] = v;
+    s_cx[j] = (isV && fio) ? amplitude_shift(A.ph, v) : 0.0;
+  }
+  for (int l = tid; l < c; l += kTallThreads) {
+    const double v = cs_(l);
+    s_ccoord[l] = v;
+    s_ccx[l] = (!isV && fio) ? amplitude_shift(A.ph, v) : 0.0;
+  }
+  __syncthreads();
+  double2* W = A.tall_work + (int64_t)blockIdx.x * A.tall_work_ld;
+  for (int e = tid; e < s * c; e += kTallThreads) {
+    const int i = e % s, l = e / s;
+    W[(int64_t)l * s + i] = isV ? kernel_entry(A.ph, s_coord[i], s_cx[i], s_ccoord[l])
+                                : kernel_entry(A.ph, s_ccoord[l], s_ccx[l], s_coord[i]);
+  }
+  __syncthreads();
+  for (int j = 0; j < c; ++j) {
+    // column j below the diagonal, its norm and the Householder vector
+    double p = 0.0;
+    for (int i = j + tid; i < s; i += kTallThreads) {
+      const double2 v = W[(int64_t)j * s + i];
+      s_v[i] = v;
+      p = __builtin_fma(v.y, v.y, __builtin_fma(v.x, v.x, p));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) p += __shfl_xor(p, off, kWave);
+    if (lane == 0) s_red[w] = p;
+    __syncthreads();
+    if (tid == 0) {
+      double nu2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) nu2 += s_red[k];
+      const double nu = sqrt(nu2);
+      double tau = 0.0;
+      if (nu > 0.0) {
+        const double2 xj = s_v[j];
+        const double axj = sqrt(cabs2(xj));
+        double2 alpha, vj;
+        if (axj > 0.0) {
+          const double g = nu / axj;  // alpha = -g x_j, v_j = (1 + g) x_j
+          alpha = make_double2(-xj.x * g, -xj.y * g);
+          vj = make_double2(xj.x + xj.x * g, xj.y + xj.y * g);
+        } else {
+          alpha = make_double2(-nu, 0.0);
+          vj = make_double2(nu, 0.0);
+        }
+        s_v[j] = vj;
+        W[(int64_t)j * s + j] = alpha;
+        tau = 1.0 / (nu * (nu + axj));  // 2 / |v|^2
+      }
+      s_tau = tau;
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    if (tau != 0.0) {
+      for (int l = j + 1 + w; l < c; l += NW) {
+        double2* col = W + (int64_t)l * s;
+        double2 d = make_double2(0.0, 0.0);
+        for (int i = j + lane; i < s; i += kWave) d = cfma_conj(s_v[i], col[i], d);
+        d = wave_sum(d);
+        const double2 f = make_double2(-tau * d.x, -tau * d.y);
+        for (int i = j + lane; i < s; i += kWave) col[i] = cfma(s_v[i], f, col[i]);
+      }
+    }
+    __syncthreads();  // the columns are updated before the next step reads them
+  }
+  double2* Rt = A.tall_R + slot * A.tall_ld2;
+  for (int e = tid; e < c * c; e += kTallThreads) {
+    const int i = e % c, l = e / c;
+    Rt[e] = i <= l ? W[(int64_t)l * s + i] : make_double2(0.0, 0.0);
+  }
+  if (tid == 0) A.tall_slot[q] = (int32_t)slot;
+}
+
 }  // namespace
 
 hipError_t launch_qr_bucket(const IdArgs& a, int64_t n, int bucket, hipStream_t st);
@@ -1029,7 +1170,20 @@ hipError_t launch_id_batch(const IdArgs& a, hipStream_t st) {
 
 hipError_t launch_qr(const IdArgs& a, hipStream_t st) {
   if (a.n_ids <= 0) return hipSuccess;
-  if (!a.order) return launch_qr_bucket(a, a.n_ids, qr_bucket(a.c_max, a.s_max), st);
+  if (a.n_tall > 0) {  // reduced blocks of the tall IDs first, tall_chunk per launch (scratch slots)
+    if (!a.tall_list || !a.tall_slot || !a.tall_R || !a.tall_work || a.tall_chunk < 1) return hipErrorInvalidValue;
+    for (int64_t b0 = 0; b0 < a.n_tall; b0 += a.tall_chunk) {
+      const int64_t n = std::min<int64_t>(a.tall_chunk, a.n_tall - b0);
+      hipLaunchKernelGGL(tall_reduce_kernel, dim3((unsigned)n), dim3(kTallThreads), 0, st, a, b0);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  if (!a.order) {
+    int bk = qr_bucket(a.c_max, a.rows_max);
+    if (a.n_tall > 0 && bk >= kFirstPackedBucket) bk = (a.rows_max + 15) / 16 - 1;  // tall IDs: one-ID kernels
+    return launch_qr_bucket(a, a.n_ids, bk, st);
+  }
   // one launch per bucket of IDs that need the same kernel variant
   IdArgs b = a;
   for (int bk = 0; bk < kQrBuckets; ++bk) {

@@ -11,12 +11,20 @@ enum : int32_t { kErrRank = 1, kErrSize = 2 };
 // QR kernel variant of an ID with c candidates and s samples: buckets 0..7
 // take up to 64 candidates with ceil(s / 16) wavefronts, buckets 8..23 up to
 // 128 with ceil(s / 8); buckets 24..27 pack two IDs of up to 32 candidates
-// and 64 samples per workgroup, 28..29 four IDs of up to 16 and 32.
+// and 64 samples per workgroup, 28..29 four IDs of up to 16 and 32.  A tall
+// ID (s > kQrRows) enters the one-ID kernels with its reduced block of c
+// rows.  Slot kQrBuckets of the bucket counters counts the tall IDs.
 constexpr int kQrBuckets = 30;
+constexpr int kBucketSlots = kQrBuckets + 1;
+constexpr int kFirstPackedBucket = 24;
+__host__ __device__ inline bool is_tall(int s) { return s > kQrRows; }
+__host__ __device__ inline int qr_rows(int c, int s) { return is_tall(s) ? c : s; }
 __host__ __device__ inline int qr_bucket(int c, int s) {
+  const bool tall = is_tall(s);
+  s = qr_rows(c, s);
   s = s < 1 ? 1 : s;
-  if (c <= 16 && s <= 32) return 28 + (s + 15) / 16 - 1;  // four IDs per workgroup
-  if (c <= 32 && s <= 64) return 24 + (s + 15) / 16 - 1;  // two IDs per workgroup
+  if (!tall && c <= 16 && s <= 32) return 28 + (s + 15) / 16 - 1;  // four IDs per workgroup
+  if (!tall && c <= 32 && s <= 64) return 24 + (s + 15) / 16 - 1;  // two IDs per workgroup
   if (c <= kWave) {
     const int w = (s + 15) / 16;
     return (w > 8 ? 8 : w) - 1;
@@ -42,18 +50,32 @@ struct IdArgs {
   const double* allow_coord;  // same for the allowed points
   double tol;
   int kmax;
+  bool truncate;              // ranks above kMaxRank stop at kMaxRank instead of an error
   int oversample;
-  int s_max;                  // largest sample count of the batch (sizes the launch)
+  int s_max;                  // largest sample count of the batch
   int c_max;                  // largest candidate count of the batch (sizes the launch)
-  const int32_t* samples;     // per-ID sample counts, or null: s = min(t c, |allowed|, kMaxSamples)
+  int rows_max;               // largest qr_rows(c, s) of the batch (sizes an unordered launch)
+  const int32_t* samples;     // per-ID sample counts, or null: s = min(t c, |allowed|)
   int sampler;                // IDBF_SAMPLER_MOCKCHEB or IDBF_SAMPLER_RANDOM
   int level;                  // level t of the batch (random sampler counters)
   uint64_t seed;              // random sampler seed
   const int32_t* sel_list;    // selection: the IDs to process (sel_n of them), or null: all n_ids
   int64_t sel_n;
-  int32_t* samp_pos;          // kMaxSamples sample positions per ID (scratch)
+  int32_t* samp_pos;          // sample positions, samp_ld per ID (scratch)
+  int64_t samp_ld;            // >= the largest sample count of the batch
   const int32_t* order;       // QR launch: IDs grouped by kernel variant (qr_bucket), or null
   int64_t bucket_off[kQrBuckets + 1];  // host: order[bucket_off[b] .. bucket_off[b + 1]) are bucket b
+  // tall IDs (s > kQrRows): the row reduction writes each one's c x c
+  // triangular factor to tall_R + tall_slot[q] * tall_ld2 (column-major,
+  // leading dimension c), which the QR kernels read instead of sampling
+  const int32_t* tall_list;   // the tall IDs; slot i is tall_list[i]
+  int64_t n_tall;
+  int32_t* tall_slot;         // per ID: its slot (tall IDs only)
+  double2* tall_R;
+  int64_t tall_ld2;           // entries per slot: >= c_max^2
+  double2* tall_work;         // reduction scratch: tall_chunk blocks of tall_work_ld entries
+  int64_t tall_work_ld;       // >= s_max c_max
+  int64_t tall_chunk;         // tall IDs per reduction launch
   int32_t* rank;
   uint64_t* mask;        // two words per ID: bit l of (mask[2q], mask[2q+1]) = candidate l is a skeleton
   int32_t* skel_out;     // kMaxCand entries per ID
@@ -63,18 +85,21 @@ struct IdArgs {
   int32_t* status;
 };
 // Selection (one wavefront per ID), then sampling + QR + solve (one
-// workgroup per ID, variant by qr_bucket); launch_id_batch runs both.
+// workgroup per ID, variant by qr_bucket); launch_qr first runs the row
+// reduction of the tall IDs (chunks of tall_chunk); launch_id_batch runs
+// selection and QR.
 hipError_t launch_select(const IdArgs& a, hipStream_t st);
 hipError_t launch_qr(const IdArgs& a, hipStream_t st);
 hipError_t launch_id_batch(const IdArgs& a, hipStream_t st);
-// IDs grouped by qr_bucket: counts[0..kQrBuckets) += bucket sizes (pass 1),
-// then order[] filled from per-bucket cursors (pass 2, cursors pre-set to the
-// bucket offsets).
+// IDs grouped by qr_bucket: counts[0..kQrBuckets) += bucket sizes and
+// counts[kQrBuckets] += tall IDs (pass 1), then order[] (and tall[] for the
+// tall IDs) filled from per-slot cursors (pass 2, cursors pre-set to the
+// bucket offsets; cursors[kQrBuckets] to 0).
 // keep (nullable): only IDs with keep[q] != 0 are counted / placed.
 hipError_t launch_bucket_count(const int32_t* samples, const int32_t* cand_len, const int32_t* keep, int64_t n,
                                unsigned long long* counts, hipStream_t st);
 hipError_t launch_bucket_fill(const int32_t* samples, const int32_t* cand_len, const int32_t* keep, int64_t n,
-                              unsigned long long* cursors, int32_t* order, hipStream_t st);
+                              unsigned long long* cursors, int32_t* order, int32_t* tall, hipStream_t st);
 
 // ------------------------------------------------------------- learned proposal
 constexpr int kProposalInputs = 8;       // features per ID
@@ -101,11 +126,14 @@ struct ResidualArgs {
   int level;
   uint64_t seed;
   double factor;                // accept when ||E||_F <= factor tol ||A||_F
+  bool force_reject;            // reject every proposal (the fallback then recomputes all IDs)
   int32_t* reject;              // out: 1 = rejected
   int32_t* s_prop;              // rejected IDs get samples_plain[q] (the fallback's count)
   const int32_t* samples_plain;
 };
 hipError_t launch_residual(const ResidualArgs& a, hipStream_t st);
+// hist[r] += #{q : rank[q] == r} for r <= kMaxRank (hist zeroed by the caller)
+hipError_t launch_rank_hist(const int32_t* rank, int64_t n, unsigned long long* hist, hipStream_t st);
 // out[q] = rank[q] / kProposalScale (training targets)
 hipError_t launch_rank_targets(const int32_t* rank, int64_t n, float* out, hipStream_t st);
 
@@ -127,7 +155,7 @@ struct DescArgs {
   int32_t* allow_beg;
   int32_t* allow_len;
   int64_t* t_bound;               // upper bound of k (c - k) per ID
-  int32_t* samples;               // s = min(t c, |allowed|) per ID
+  int32_t* samples;               // s = min(t c, |allowed|) per ID (Section 2.1: t k rows, k = c)
 };
 hipError_t launch_desc(const DescArgs& a, hipStream_t st);
 

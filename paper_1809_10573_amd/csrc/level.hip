@@ -56,7 +56,9 @@ __global__ void desc_kernel(DescArgs A) {
   A.cand_len[q] = cl;
   A.allow_beg[q] = ab;
   A.allow_len[q] = al;
-  const int64_t s = min(min((int64_t)A.oversample * cl, (int64_t)al), (int64_t)kMaxSamples);
+  // Section 2.1: t k rows with k = |cand|, at most the allowed set (above
+  // kMaxSamples the construction stops with IDBF_EUNSUPPORTED)
+  const int64_t s = min((int64_t)A.oversample * cl, (int64_t)al);
   int64_t kcap = min((int64_t)cl, s);
   if (A.kmax > 0) kcap = min(kcap, (int64_t)A.kmax);
   kcap = min(kcap, (int64_t)kMaxRank);
@@ -290,13 +292,16 @@ __global__ __launch_bounds__(256) void id_work_kernel(const int32_t* rank, const
 __global__ __launch_bounds__(256) void bucket_count_kernel(const int32_t* samples, const int32_t* cand_len,
                                                            const int32_t* keep, int64_t n,
                                                            unsigned long long* counts) {
-  __shared__ unsigned int s_c[kQrBuckets];
-  if (threadIdx.x < kQrBuckets) s_c[threadIdx.x] = 0;
+  __shared__ unsigned int s_c[kBucketSlots];
+  if (threadIdx.x < kBucketSlots) s_c[threadIdx.x] = 0;
   __syncthreads();
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
-    if (!keep || keep[q]) atomicAdd(&s_c[qr_bucket(cand_len[q], samples[q])], 1u);
+    if (!keep || keep[q]) {
+      atomicAdd(&s_c[qr_bucket(cand_len[q], samples[q])], 1u);
+      if (is_tall(samples[q])) atomicAdd(&s_c[kQrBuckets], 1u);
+    }
   __syncthreads();
-  if (threadIdx.x < kQrBuckets && s_c[threadIdx.x])
+  if (threadIdx.x < kBucketSlots && s_c[threadIdx.x])
     atomicAdd(counts + threadIdx.x, (unsigned long long)s_c[threadIdx.x]);
 }
 
@@ -304,24 +309,27 @@ __global__ __launch_bounds__(256) void bucket_count_kernel(const int32_t* sample
 // workgroup), then handed out inside the workgroup with LDS atomics.
 __global__ __launch_bounds__(256) void bucket_fill_kernel(const int32_t* samples, const int32_t* cand_len,
                                                           const int32_t* keep, int64_t n,
-                                                          unsigned long long* cursors, int32_t* order) {
-  __shared__ unsigned int s_cnt[kQrBuckets];
-  __shared__ unsigned long long s_base[kQrBuckets];
-  if (threadIdx.x < kQrBuckets) s_cnt[threadIdx.x] = 0;
+                                                          unsigned long long* cursors, int32_t* order, int32_t* tall) {
+  __shared__ unsigned int s_cnt[kBucketSlots];
+  __shared__ unsigned long long s_base[kBucketSlots];
+  if (threadIdx.x < kBucketSlots) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const bool in = q < n && (!keep || keep[q]);
+  const bool tl = in && is_tall(samples[q]);
   int b = 0;
-  unsigned int local = 0;
+  unsigned int local = 0, local_t = 0;
   if (in) {
     b = qr_bucket(cand_len[q], samples[q]);
     local = atomicAdd(&s_cnt[b], 1u);
+    if (tl) local_t = atomicAdd(&s_cnt[kQrBuckets], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < kQrBuckets && s_cnt[threadIdx.x])
+  if (threadIdx.x < kBucketSlots && s_cnt[threadIdx.x])
     s_base[threadIdx.x] = atomicAdd(cursors + threadIdx.x, (unsigned long long)s_cnt[threadIdx.x]);
   __syncthreads();
   if (in) order[s_base[b] + local] = (int32_t)q;
+  if (tl) tall[s_base[kQrBuckets] + local_t] = (int32_t)q;
 }
 
 __global__ void pack_meta_kernel(const int64_t* t_off, const uint64_t* mask, const int32_t* cand_beg,
@@ -396,10 +404,10 @@ hipError_t launch_bucket_count(const int32_t* samples, const int32_t* cand_len, 
 }
 
 hipError_t launch_bucket_fill(const int32_t* samples, const int32_t* cand_len, const int32_t* keep, int64_t n,
-                              unsigned long long* cursors, int32_t* order, hipStream_t st) {
+                              unsigned long long* cursors, int32_t* order, int32_t* tall, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(bucket_fill_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, samples, cand_len, keep, n,
-                     cursors, order);
+                     cursors, order, tall);
   return hipGetLastError();
 }
 

@@ -6,6 +6,8 @@
 //   || A(r, red) - A(r, skel) T ||_F <= 10 eps || A(r, cand) ||_F,
 // and rejected IDs are recomputed from the plain s samples (a proposal that
 // kept s' = s is the plain ID and is accepted as it is).
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace idbf {
@@ -134,10 +136,23 @@ __global__ __launch_bounds__(64 * kWavesRC) void residual_kernel(ResidualArgs R)
   if (lane == 0) {
     const double bound = R.factor * A.tol;
     // a proposal that kept the plain sample count is the plain ID itself
-    const bool ok = R.s_prop[q] == R.samples_plain[q] || e2 <= bound * bound * na2;
+    const bool ok = !R.force_reject && (R.s_prop[q] == R.samples_plain[q] || e2 <= bound * bound * na2);
     R.reject[q] = ok ? 0 : 1;
     if (!ok) R.s_prop[q] = R.samples_plain[q];  // the fallback samples the plain count
   }
+}
+
+__global__ __launch_bounds__(256) void rank_hist_kernel(const int32_t* rank, int64_t n, unsigned long long* hist) {
+  __shared__ unsigned int s_h[kMaxRank + 1];
+  for (int i = threadIdx.x; i <= kMaxRank; i += blockDim.x) s_h[i] = 0;
+  __syncthreads();
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    const int r = rank[q];
+    if (r >= 0 && r <= kMaxRank) atomicAdd(&s_h[r], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= kMaxRank; i += blockDim.x)
+    if (s_h[i]) atomicAdd(hist + i, (unsigned long long)s_h[i]);
 }
 
 __global__ void targets_kernel(const int32_t* rank, int64_t n, float* out) {
@@ -152,6 +167,12 @@ inline unsigned blocks(int64_t n, int per = 256) { return (unsigned)((n + per - 
 hipError_t launch_rank_targets(const int32_t* rank, int64_t n, float* out, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(targets_kernel, dim3(blocks(n)), dim3(256), 0, st, rank, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_hist(const int32_t* rank, int64_t n, unsigned long long* hist, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rank_hist_kernel, dim3(std::min<unsigned>(blocks(n), 256u)), dim3(256), 0, st, rank, n, hist);
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1809_10573_amd import binding as B
@@ -68,3 +69,26 @@ def test_argument_errors_without_gpu():
                              fake, fake, fake, fake, None) == B.EINVAL
     assert lib.idbf_construct_batched(0, None, None, None, None, None, None, None, None) == B.EINVAL
     assert lib.idbf_apply_batched(0, None, None, None, None, B.C64, None) == B.EINVAL
+
+
+def test_binding_rejects_bad_operands_before_any_launch():
+    # the C ABI takes no lengths, so the binding checks every vector block:
+    # shape (N,) or (N, nrhs), dtype, contiguity, device, and y against x
+    torch = pytest.importorskip("torch")
+    cpu = torch.device("cpu")
+    good = torch.zeros((8, 3), dtype=torch.complex128)
+    B._check_operand("x", good, 8, torch.complex128, cpu)
+    for bad in (torch.zeros((7, 3), dtype=torch.complex128),           # wrong N
+                torch.zeros((8, 3, 1), dtype=torch.complex128),        # 3-D
+                torch.zeros((8, 3), dtype=torch.complex64),            # dtype
+                torch.zeros((3, 8), dtype=torch.complex128).t(),       # not contiguous
+                np.zeros((8, 3), dtype=np.complex128)):                # not a tensor
+        with pytest.raises(ValueError):
+            B._check_operand("x", bad, 8, torch.complex128, cpu)
+    with pytest.raises(ValueError):
+        B._check_operand("x", good, 8, torch.complex128, torch.device("meta"))
+    B._check_output(good, torch.zeros_like(good))
+    for bad in (torch.zeros((8, 2), dtype=torch.complex128), torch.zeros((8, 3), dtype=torch.complex64),
+                torch.zeros((3, 8), dtype=torch.complex128).t(), good, good[1:]):
+        with pytest.raises(ValueError):
+            B._check_output(good, bad)

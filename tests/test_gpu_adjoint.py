@@ -71,8 +71,12 @@ def test_adjoint_deterministic_and_errors():
     x = torch.as_tensor(I.gaussian_vectors(N, 5, seed=1), device=DEV)
     a = fac.apply_adjoint(x)
     assert torch.equal(a, fac.apply_adjoint(x))
-    with pytest.raises(B.IdbfError):
-        fac.apply_adjoint(x, y=x)                 # in place is refused
+    with pytest.raises(ValueError):
+        fac.apply_adjoint(x, y=x)                 # in place is refused by the binding ...
+    lib = B.load()                                # ... and by the C ABI
+    assert lib.idbf_apply_adjoint(fac._h, x.data_ptr(), x.data_ptr(), 5, B.C128, None) == B.EINVAL
+    with pytest.raises(ValueError):
+        fac.apply_adjoint(x[:N - 1])              # short input: refused before any launch
     empty = torch.zeros((N, 0), dtype=torch.complex128, device=DEV)
     assert fac.apply_adjoint(empty).shape == (N, 0)
 

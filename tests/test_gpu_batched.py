@@ -152,3 +152,40 @@ def test_captured_plan_replays_match_eager(dtype):
             for y, r in zip(ys, ref):
                 assert torch.equal(y, r), rep
         plan.close()
+
+
+def test_live_plan_pins_the_workspace():
+    """A captured plan writes its handles' apply workspaces: while it lives, an
+    apply that would need a larger workspace is refused (IDBF_EINVAL) instead
+    of moving it, the handle cannot be destroyed, and replays still give the
+    eager result; once the plan is gone both work again."""
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        facs = [B.construct(ph, *I.uniform_grid(N), tol, leaf, oversample=2, device=DEV)
+                for ph, N, leaf, tol in CASES[:3]]
+        xs = [torch.as_tensor(I.gaussian_vectors(f.X.numel(), None, seed=30 + i), device=DEV)
+              for i, f in enumerate(facs)]
+        ref = B.apply_batched(facs, xs)
+        ys = [torch.zeros_like(x) for x in xs]
+        plan = B.ApplyPlan(facs, xs, ys, stream=stream)
+        big = torch.as_tensor(I.gaussian_vectors(facs[1].X.numel(), 65, seed=3), device=DEV)
+        with pytest.raises(B.IdbfError) as e:
+            facs[1].apply(big, stream=stream)
+        assert e.value.status == B.EINVAL and "plan" in str(e.value)
+        with pytest.raises(B.IdbfError) as e:
+            facs[1].reserve(65, B.C128)
+        assert e.value.status == B.EINVAL
+        lib = B.load()
+        assert lib.idbf_destroy(facs[0]._h) == B.EINVAL        # still held by the plan
+        small = facs[1].apply(xs[1], stream=stream)             # fits the workspace: allowed
+        plan.launch(stream)
+        stream.synchronize()
+        for y, r in zip(ys, ref):
+            assert torch.equal(y, r)
+        assert torch.equal(small, ref[1])
+        plan.close()
+        Y = facs[1].apply(big, stream=stream)                   # grows now
+        stream.synchronize()
+        assert Y.shape == big.shape
+        for f in facs:
+            f.close()

@@ -144,6 +144,62 @@ def test_id_batch_matches_oracle(side, oversample, kmax, shapes):
         assert np.max(np.abs(Tg - cid.T), initial=0.0) <= 1e-12 * kappa * scale, q
 
 
+# tall sample blocks (more than 128 sampled rows): the library first reduces
+# them to their c x c triangular factor; oversampling 3 and 5 make them tall
+# at small candidate counts too, mixed with IDs that are not
+TALL_SHAPES = {3: [(60, 64, 300, 400), (50, 70, 151, 200), (64, 64, 256, 300), (20, 24, 30, 40),
+                   (80, 100, 400, 500), (8, 8, 700, 800)],
+               5: [(30, 32, 700, 800), (16, 16, 40, 48), (8, 8, 5, 5), (27, 30, 140, 200), (32, 32, 160, 160),
+                   (51, 60, 500, 600)]}
+
+
+@pytest.mark.parametrize("side", [B.SIDE_U, B.SIDE_V])
+@pytest.mark.parametrize("oversample,packed", [(3, False), (5, False), (5, True)])
+def test_id_batch_tall_blocks(side, oversample, packed):
+    """s = t |cand| up to 256 rows (eq. pivotedQR2 without a cap): the reduced
+    blocks give the oracle's skeletons and T.  `packed`: only the IDs of at
+    most 32 candidates, so that the batch would otherwise run on the
+    several-IDs-per-workgroup kernels."""
+    N = 4096
+    ph = I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    shapes = [sh for sh in TALL_SHAPES[oversample] if not packed or sh[0] <= 32]
+    rng = np.random.default_rng(7 + side + 10 * oversample + 100 * packed)
+    problems = [_id_problem(rng, N, *sh) for sh in shapes]
+    tol = 1e-6
+    rank, mask, skel, T = _run_ids(ph, X, O, side, problems, tol, 0, oversample)
+    allow_coord = X if side == B.SIDE_V else O
+    tall = 0
+    for q, (cand, allowed) in enumerate(problems):
+        s = oracle.sample_count(len(cand), len(allowed), oversample)
+        tall += s > 128
+        samp = allowed[oracle.mock_chebyshev(allow_coord[allowed], s)]
+        Bm = (oracle.entries(ph, X, O, samp, cand) if side == B.SIDE_V
+              else oracle.entries(ph, X, O, cand, samp).T)
+        cid = oracle.column_id(Bm, tol)
+        k = cid.rank
+        assert rank[q] == k, (q, rank[q], k)
+        assert np.array_equal(skel[q, :k], cand[cid.skel]), q
+        r = len(cand) - k
+        flat = T[q, :k * r]
+        Tg = flat.reshape(r, k).T if side == B.SIDE_V else flat.reshape(k, r)
+        kappa = cid.rdiag[0] / cid.rdiag[-1]
+        scale = max(1.0, np.abs(cid.T).max()) if r else 1.0
+        assert np.max(np.abs(Tg - cid.T), initial=0.0) <= 1e-12 * kappa * scale, q
+    assert tall >= 2
+
+
+def test_id_batch_rejects_more_than_256_samples():
+    # s = 3 * 128 = 384 sampled rows exceeds the supported 256: reported, not capped
+    N = 4096
+    X, O = I.uniform_grid(N)
+    rng = np.random.default_rng(5)
+    prob = _id_problem(rng, N, 128, 130, 500, 600)
+    with pytest.raises(B.IdbfError) as e:
+        _run_ids(I.fio_phase(1.0, 1.0), X, O, B.SIDE_V, [prob], 1e-6, 0, 3)
+    assert e.value.status == B.EUNSUPPORTED
+
+
 def test_id_batch_rank_overflow_is_reported():
     # 128 candidates spread over the whole grid against 128 spread allowed
     # points: full rank, above the 64 an ID may have -> IDBF_ERANK, not a wrong answer
@@ -224,6 +280,8 @@ def _compare_construction(F, fac, ph, X, O, t_bound=1e-12):
     (1024, 8, "nufft", 1e-10, 1),
     (1024, 8, "j0", 1e-10, 2),      # Example 2: the Schloemilch kernel J_0(g w)
     (2048, 16, "j0", 1e-6, 2),
+    (1024, 32, "dft", 1e-10, 5),    # every ID samples more than 128 rows (up to 248)
+    (1024, 64, "dft", 1e-6, 4),     # tall IDs of up to 90 candidates and 256 rows
 ])
 def test_construct_and_apply_match_oracle(N, leaf, kind, tol, os_):
     ph, X, O = _workload(kind, N)

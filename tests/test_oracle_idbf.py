@@ -215,3 +215,46 @@ def test_adjoint_with_full_sampling_reproduces_K_H():
     K = oracle.entries(ph, W, Xp, np.arange(N), np.arange(N))
     g = I.gaussian_vectors(N, None, seed=4)
     assert oracle.relative_error(oracle.apply_adjoint(F, g), K.conj().T @ g) < 1e-11
+
+
+def _full_blocks(F, ph, X, O):
+    """Every ID's whole complementary block (candidates x the allowed set it
+    sees), as the ID's matrix: K(allowed, cand) for V, K(cand, allowed)^T for U."""
+    N, L, H = F.N, F.L, F.H
+    for t in range(1, H + 1):
+        for (r, p), rec in F.U[t].items():
+            if t == 1:
+                allowed = np.arange(p * N // 2, (p + 1) * N // 2)
+            else:
+                sh = L - 2 * t + 2
+                allowed = np.concatenate([F.V[t - 1][(cc, r >> sh)].skel
+                                          for cc in range(p << sh, (p + 1) << sh)])
+            yield rec, oracle.entries(ph, X, O, rec.cand, allowed).T
+        for (cn, p), rec in F.V[t].items():
+            sh = L - 2 * t + 1
+            allowed = np.concatenate([F.U[t][(rr, cn >> sh)].skel for rr in range(p << sh, (p + 1) << sh)])
+            yield rec, oracle.entries(ph, X, O, allowed, rec.cand)
+
+
+@pytest.mark.parametrize("kind,N,leaf,tol", [("fio", 256, 8, 1e-6), ("dft", 256, 8, 1e-10),
+                                             ("fio", 256, 4, 1e-8), ("fio2", 256, 8, 1e-6),
+                                             ("fio", 256, 16, 1e-6)])
+def test_eps_rank_two_sided_against_block_svd(kind, N, leaf, tol):
+    # With every allowed point sampled each ID sees its whole complementary
+    # block B.  Its eps-rank (eq. acc) is compared with the SVD count
+    # r_eps(B) = #{sigma_i > eps sigma_1} from both sides: |k - r| <= 2 on at
+    # least 95% of the blocks of every level and side, and (empirically, with
+    # |R_00| <= sigma_1 <= sqrt(c) |R_00| bracketing the thresholds) at least a
+    # quarter of them agree exactly -- a rule that kept one column too many
+    # would agree on none.
+    ph = I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 1.0 if kind == "fio" else 2.0)
+    X, O = I.uniform_grid(N)
+    F = oracle.build(ph, X, O, leaf, tol, sample_all=True)
+    d = []
+    for rec, B in _full_blocks(F, ph, X, O):
+        sv = np.linalg.svd(B, compute_uv=False)
+        d.append(len(rec.skel) - np.count_nonzero(sv > tol * sv[0]))
+    d = np.array(d)
+    assert len(d) == 2 * F.H * (2 * N // leaf)
+    assert np.mean(np.abs(d) <= 2) >= 0.95
+    assert np.mean(d == 0) >= 0.25

@@ -66,6 +66,28 @@ def test_stopping_rule_bounds(tol):
         assert np.all(cid.rdiag > tol * r00)
 
 
+@pytest.mark.parametrize("perm", [[0, 1, 2, 3, 4], [3, 0, 4, 2, 1], [4, 3, 2, 1, 0]])
+def test_eps_rank_count_on_known_diagonal(perm):
+    # Columns with a single nonzero each: every Householder step is exact, the
+    # pivots follow decreasing norm and |R_jj| are the norms themselves.  With
+    # norms 1, 2^-10, 2^-20, 2^-30, 2^-40 and eps = 2^-20, eq. (acc)'s
+    # stopping index is the first |R_jj| <= eps |R_00|, i.e. the third pivot
+    # (2^-20, equal to the threshold).  The count kept is the entries strictly
+    # above it: 2.  Keeping the stopping column as well (the literal index),
+    # or comparing with >=, would give 3.
+    d = 2.0 ** -np.array([0, 10, 20, 30, 40])
+    B = np.zeros((7, 5), dtype=np.complex128)
+    B[np.arange(5), np.arange(5)] = d * np.exp(1j * np.arange(5))
+    B = B[:, perm]
+    cid = oracle.column_id(B, tol=2.0 ** -20)
+    assert cid.rank == 2
+    assert list(cid.pivots) == [perm.index(0), perm.index(1)]
+    assert np.array_equal(cid.rdiag, d[:2])
+    # eps just above the third norm keeps two, just below it keeps three
+    assert oracle.column_id(B, tol=2.0 ** -20 * (1 + 2.0 ** -40)).rank == 2
+    assert oracle.column_id(B, tol=2.0 ** -20 * (1 - 2.0 ** -40)).rank == 3
+
+
 def test_tie_rule_prefers_smallest_index():
     # every column has the same norm: the first pivot is the first column; a
     # column permutation moves the pivot with it only through the index order
@@ -97,3 +119,21 @@ def test_row_id_by_transpose():
     U[cid.red] = cid.T.T
     assert cid.rank == 6
     assert np.linalg.norm(A - U @ A[cid.skel]) / np.linalg.norm(A) < 1e-12
+
+
+@pytest.mark.parametrize("s,c,r", [(200, 90, 30), (256, 128, 50), (150, 40, 12)])
+def test_row_reduction_keeps_the_id(s, c, r):
+    # Tall sample blocks may be reduced to their triangular factor R0 (B = Q0 R0)
+    # before the pivoted QR: the pivots follow the norms of the columns'
+    # components orthogonal to those already chosen, which depend on B only
+    # through B^H B = R0^H R0, so the ID of R0 has B's skeleton and T.
+    rng = np.random.default_rng(s + c)
+    B = (_cgauss(rng, s, c) * np.logspace(0, -16 * c / r, c)) @ _cgauss(rng, c, c)
+    R0 = sl.qr(B, mode="r")[0][:c]
+    for tol in (1e-6, 1e-10):
+        a, b = oracle.column_id(B, tol), oracle.column_id(R0, tol)
+        assert 0 < a.rank < c
+        assert np.array_equal(a.skel, b.skel)
+        assert np.allclose(a.rdiag, b.rdiag, rtol=1e-10)
+        kappa = a.rdiag[0] / a.rdiag[-1]
+        assert np.max(np.abs(a.T - b.T)) <= 1e-12 * kappa * max(1.0, np.abs(a.T).max())
