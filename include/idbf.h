@@ -148,7 +148,10 @@ idbf_status idbf_construct(const idbf_phase* phase, const double* X, const doubl
  *          data, BF16 hi/lo split MFMA products, FP32 accumulation).
  * Asynchronous on stream.  Intermediate vectors live in a workspace owned by
  * the handle, grown (hipMalloc, which synchronizes) when nrhs exceeds what
- * was used before; calls on one handle must not overlap in time.
+ * was used before; calls on one handle must not overlap in time.  With
+ * IDBF_FLAG_PROFILE the stage launches are recorded as apply1_ (complex64,
+ * 1 RHS), applyn_ (FP32 MFMA), applyb_ (BF16 split), apply1d_ (complex128,
+ * 1 RHS) or applynd_ (complex128, several RHS), + v, s, u.
  */
 idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype,
                        void* stream);
@@ -160,7 +163,7 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
  * the Conclusion's use in iterative solvers).  x is indexed like idbf_apply's
  * y (rows of K, the points X) and y like its x (columns, the points Omega).
  * Arguments, dtypes, workspace and error behaviour as idbf_apply; profile
- * records are named adj1_ / adjn_ / adjb_ + v, s, u.
+ * records are named as idbf_apply's with adj in place of apply.
  */
 idbf_status idbf_apply_adjoint(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype,
                                void* stream);
@@ -336,6 +339,17 @@ idbf_status idbf_profile_read(idbf_handle h, idbf_kernel_stat* out, int32_t max,
  */
 idbf_status idbf_batch_sizes(idbf_handle h, int32_t side, int32_t level, int64_t* n_ids,
                              int64_t* n_skel, int64_t* n_T);
+/*
+ * idbf_batch_proposal -- sample counts of one level's IDs (host arrays of
+ * n_ids, each nullable): proposed[q] the count the proposal network set
+ * before the residual test, used[q] the count the stored ID was computed
+ * from (the proposal, or the plain t |cand| when rejected), rejected[q] 1
+ * when the residual test rejected the proposal.  Without a proposer all
+ * three describe the plain construction (proposed = used, rejected = 0).
+ * Synchronizes the handle's stream.
+ */
+idbf_status idbf_batch_proposal(idbf_handle h, int32_t side, int32_t level, int32_t* proposed,
+                                int32_t* used, int32_t* rejected);
 idbf_status idbf_batch_export(idbf_handle h, int32_t side, int32_t level, int32_t* rank,
                               int32_t* cand_len, uint64_t* mask, int32_t* skel, double* T,
                               int64_t* T_off);

@@ -126,9 +126,47 @@ def _samples(coords_of_allowed, allowed, c, oversample, sample_all, smax, sample
     return allowed[mock_chebyshev(coords_of_allowed, s)]
 
 
+@dataclass
+class _Context:
+    """What every ID of one construction shares (held per worker process)."""
+    phase: object
+    X: np.ndarray
+    Omega: np.ndarray
+    tol: float
+    kmax: int
+    oversample: int
+    sample_all: bool
+    smax: int
+    sampler: str
+
+
+_CTX: _Context | None = None
+
+
+def _set_context(ctx: _Context) -> None:
+    global _CTX
+    _CTX = ctx
+
+
+def _one_id(job) -> IDRecord:
+    """One ID of a level (Section 2.1): samples of the allowed set, the sampled
+    block of the candidates, its column ID.  side 0: a row ID of
+    A(cand, allowed) as the column ID of K(cand, samples)^T; side 1: a column
+    ID of K(samples, cand)."""
+    side, cand, allowed, key = job
+    c = _CTX
+    coords = c.Omega[allowed] if side == 0 else c.X[allowed]
+    samp = _samples(coords, allowed, len(cand), c.oversample, c.sample_all, c.smax, c.sampler, key)
+    if side == 0:
+        B = entries(c.phase, c.X, c.Omega, cand, samp).T            # s x c
+    else:
+        B = entries(c.phase, c.X, c.Omega, samp, cand)              # s x c
+    return _interp(B, c.tol, c.kmax, cand)
+
+
 def build(phase, X, Omega, leaf: int, tol: float, kmax: int = 0, oversample: int = 1,
           sample_all: bool = False, smax: int = 0, sampler: str = "mockcheb",
-          seed: int = 0) -> Factors:
+          seed: int = 0, workers: int = 0) -> Factors:
     """Construct the IDBF of K(X, Omega) level by level (Sections 2.2-2.4).
 
     oversample is the parameter t of Section 2.1: s = min(t |cand|, |allowed|)
@@ -136,6 +174,9 @@ def build(phase, X, Omega, leaf: int, tol: float, kmax: int = 0, oversample: int
     paper kept only as an explicit option.  sampler "mockcheb" (default)
     or "random" (uniform, sampling.random_positions with this seed; the ID of
     node n and partner p at level t is q = p 2^(L-t+1) + n, side 0 = U, 1 = V).
+    workers > 1 computes the independent IDs of each level in that many
+    processes (the same IDs, in any order; used to time the oracle on all
+    host cores).
     """
     if sampler not in ("mockcheb", "random"):
         raise ValueError("sampler must be 'mockcheb' or 'random'")
@@ -152,44 +193,60 @@ def build(phase, X, Omega, leaf: int, tol: float, kmax: int = 0, oversample: int
         idx = np.arange(N)
         F.dense = entries(phase, X, Omega, idx, idx)
         return F
-    for t in range(1, H + 1):
-        nn, npart = 1 << (L - t + 1), 1 << t
-        U, V = {}, {}
-        # U_t: row IDs of (R at depth L-t+1, C at depth t)
-        for r in range(nn):
-            for p in range(npart):
-                if t == 1:
-                    cand = np.arange(r * leaf, (r + 1) * leaf)
-                    allowed = np.arange(p * (N // 2), (p + 1) * (N // 2))
-                else:
-                    Up = F.U[t - 1]
-                    cand = np.concatenate([Up[(2 * r, p >> 1)].skel, Up[(2 * r + 1, p >> 1)].skel])
-                    sh = L - 2 * t + 2
-                    Vp = F.V[t - 1]
-                    allowed = np.concatenate([Vp[(cc, r >> sh)].skel
-                                              for cc in range(p << sh, (p + 1) << sh)])
-                samp = _samples(Omega[allowed], allowed, len(cand), oversample, sample_all, smax, sampler,
-                                (seed, t, 0, p * nn + r))
-                B = entries(phase, X, Omega, cand, samp).T          # s x c
-                U[(r, p)] = _interp(B, tol, kmax, cand)
-        F.U[t] = U
-        # V_t: column IDs of (C at depth L-t+1, R at depth t)
-        for cnode in range(nn):
-            for p in range(npart):
-                if t == 1:
-                    cand = np.arange(cnode * leaf, (cnode + 1) * leaf)
-                else:
-                    Vp = F.V[t - 1]
-                    cand = np.concatenate([Vp[(2 * cnode, p >> 1)].skel,
-                                           Vp[(2 * cnode + 1, p >> 1)].skel])
-                sh = L - 2 * t + 1
-                allowed = np.concatenate([U[(rr, cnode >> sh)].skel
-                                          for rr in range(p << sh, (p + 1) << sh)])
-                samp = _samples(X[allowed], allowed, len(cand), oversample, sample_all, smax, sampler,
-                                (seed, t, 1, p * nn + cnode))
-                B = entries(phase, X, Omega, samp, cand)            # s x c
-                V[(cnode, p)] = _interp(B, tol, kmax, cand)
-        F.V[t] = V
+    ctx = _Context(phase, X, Omega, tol, kmax, oversample, sample_all, smax, sampler)
+    pool = None
+    if workers > 1:
+        import multiprocessing
+        pool = multiprocessing.get_context("fork").Pool(workers, initializer=_set_context, initargs=(ctx,))
+    else:
+        _set_context(ctx)
+
+    def run(jobs):
+        if pool is None:
+            return [_one_id(j) for j in jobs]
+        return pool.map(_one_id, jobs, chunksize=max(1, len(jobs) // (8 * workers)))
+
+    try:
+        for t in range(1, H + 1):
+            nn, npart = 1 << (L - t + 1), 1 << t
+            # U_t: row IDs of (R at depth L-t+1, C at depth t)
+            keys, jobs = [], []
+            for r in range(nn):
+                for p in range(npart):
+                    if t == 1:
+                        cand = np.arange(r * leaf, (r + 1) * leaf)
+                        allowed = np.arange(p * (N // 2), (p + 1) * (N // 2))
+                    else:
+                        Up = F.U[t - 1]
+                        cand = np.concatenate([Up[(2 * r, p >> 1)].skel, Up[(2 * r + 1, p >> 1)].skel])
+                        sh = L - 2 * t + 2
+                        Vp = F.V[t - 1]
+                        allowed = np.concatenate([Vp[(cc, r >> sh)].skel
+                                                  for cc in range(p << sh, (p + 1) << sh)])
+                    keys.append((r, p))
+                    jobs.append((0, cand, allowed, (seed, t, 0, p * nn + r)))
+            U = dict(zip(keys, run(jobs)))
+            F.U[t] = U
+            # V_t: column IDs of (C at depth L-t+1, R at depth t)
+            keys, jobs = [], []
+            for cnode in range(nn):
+                for p in range(npart):
+                    if t == 1:
+                        cand = np.arange(cnode * leaf, (cnode + 1) * leaf)
+                    else:
+                        Vp = F.V[t - 1]
+                        cand = np.concatenate([Vp[(2 * cnode, p >> 1)].skel,
+                                               Vp[(2 * cnode + 1, p >> 1)].skel])
+                    sh = L - 2 * t + 1
+                    allowed = np.concatenate([U[(rr, cnode >> sh)].skel
+                                              for rr in range(p << sh, (p + 1) << sh)])
+                    keys.append((cnode, p))
+                    jobs.append((1, cand, allowed, (seed, t, 1, p * nn + cnode)))
+            F.V[t] = dict(zip(keys, run(jobs)))
+    finally:
+        if pool is not None:
+            pool.close()
+            pool.join()
     d = F.d
     sh = d - H
     for r in range(1 << d):

@@ -31,7 +31,7 @@ EXPORTED = [
     "idbf_construct_batched", "idbf_apply_batched", "idbf_mlp_param_count", "idbf_mlp_create",
     "idbf_mlp_destroy", "idbf_mlp_params", "idbf_mlp_forward", "idbf_mlp_loss_grad", "idbf_mlp_train",
     "idbf_rank_samples", "idbf_apply_batched_plan", "idbf_plan_launch", "idbf_plan_destroy",
-    "idbf_apply_adjoint", "idbf_release_cached_memory", "idbf_stats",
+    "idbf_apply_adjoint", "idbf_release_cached_memory", "idbf_stats", "idbf_batch_proposal",
 ]
 MLP_INPUTS = 8
 FLAG_PROFILE, FLAG_PROPOSER_FORCE_REJECT, FLAG_ALLOW_TRUNCATE = 1, 2, 4
@@ -118,6 +118,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_destroy.argtypes = [VP]
     lib.idbf_get_info.argtypes = [VP, P(Info_t)]
     lib.idbf_stats.argtypes = [VP, P(Stats_t)]
+    lib.idbf_batch_proposal.argtypes = [VP, I32, I32, VP, VP, VP]
     lib.idbf_batch_sizes.argtypes = [VP, I32, I32, P(I64), P(I64), P(I64)]
     lib.idbf_batch_export.argtypes = [VP, I32, I32, VP, VP, VP, VP, VP, VP]
     lib.idbf_middle_sizes.argtypes = [VP, P(I64), P(I64)]
@@ -302,6 +303,15 @@ class Factorization:
                                      mask.ctypes.data, skel.ctypes.data, T.ctypes.data,
                                      toff.ctypes.data))
         return Batch(rank, cand, mask, skel[:ns.value], T[:nt.value], toff)
+
+    def proposal(self, side: int, level: int):
+        """(proposed, used, rejected) sample counts of one level's IDs (idbf_batch_proposal)."""
+        lib = load()
+        n = C.c_int64()
+        _check(lib.idbf_batch_sizes(self._h, side, level, C.byref(n), None, None))
+        out = [np.zeros(n.value, np.int32) for _ in range(3)]
+        _check(lib.idbf_batch_proposal(self._h, side, level, *[a.ctypes.data for a in out]))
+        return tuple(out)
 
     def profile(self, reset: bool = True) -> dict:
         """{kernel name: {launches, ms, bytes, flops}} since the last reset (IDBF_FLAG_PROFILE)."""

@@ -233,6 +233,7 @@ struct Batch {
   int rank_min = 0, rank_max = 0, cand_max = 0, s_max = 0;
   // learned proposal
   int32_t* s_prop = nullptr;   // sample counts the IDs used (proposal, or plain when rejected)
+  int32_t* s_first = nullptr;  // the proposed counts, before the residual test
   int32_t* reject = nullptr;   // 1: proposal rejected by the residual test
   int64_t rejected = 0;
   int64_t tall = 0;               // IDs row-reduced before their QR (first pass)
@@ -508,11 +509,13 @@ idbf_status level_begin(idbf_handle_s* h, const double* X, const double* Om, int
     TRY(A.get(n * kProposalInputs, &F));
     TRY(A.get(n, &y));
     TRY(A.get(n, &b.s_prop));
+    TRY(A.get(n, &b.s_first));
     TRY(A.get(n, &b.reject));
     TRYHIP(launch_features(n, h->L, t, side == IDBF_SIDE_U ? 0 : 1, h->ph, F, h->stream));
     TRYHIP(launch_mlp_forward(h->proposer->P, kProposalInputs, h->proposer->hidden, F, n, y, nullptr, nullptr,
                               h->stream));
     TRYHIP(launch_propose(y, b.samples, n, h->oversample, h->margin, b.s_prop, h->stream));
+    TRYHIP(hipMemcpyAsync(b.s_first, b.s_prop, n * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
     qr_samples = b.s_prop;
   }
   TRYHIP(hipMemsetAsync(h->bucket, 0, kBucketSlots * sizeof(unsigned long long), h->stream));
@@ -1285,7 +1288,10 @@ StageArgs level_stage(const Batch& b, bool fp64, int64_t nrhs) {
 // y = K x (adj: y = K^H x, the stages in reverse order, each conjugate
 // transposed).  Stage names of the profile: apply1_/applyn_/applyb_ (forward)
 // or adj1_/adjn_/adjb_ (adjoint) + v, s, u.
-idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype, void* stream, bool adj) {
+// ws: the caller's workspace of ws_bytes (nothing allocated, nothing
+// profiled), or null: the handle's own, grown as needed.
+idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype, void* stream, bool adj,
+                       void* ws = nullptr, size_t ws_bytes = 0) {
   g_err[0] = 0;
   if (!h) {
     set_error("handle is NULL");
@@ -1306,16 +1312,36 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
   const size_t elem = fp64 ? 16 : 8;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t half = size_t(h->max_skel) * size_t(nrhs) * elem;
-  TRY(grow_workspace(h, 2 * half, st));
-  char* buf[2] = {static_cast<char*>(h->ws), static_cast<char*>(h->ws) + half};
+  const bool external = ws != nullptr;
+  if (external) {
+    if (2 * half > ws_bytes) {
+      set_error("apply needs %zu bytes of workspace, %zu available", 2 * half, ws_bytes);
+      return IDBF_EINVAL;
+    }
+  } else {
+    TRY(grow_workspace(h, 2 * half, st));
+    ws = h->ws;
+  }
+  // the caller's workspace path records no profile events (creating one may allocate)
+  const bool prof_on = h->prof.on;
+  struct ProfGuard {
+    Profiler& p;
+    bool keep;
+    ~ProfGuard() { p.on = keep; }
+  } guard{h->prof, prof_on};
+  if (external) h->prof.on = false;
+  char* buf[2] = {static_cast<char*>(ws), static_cast<char*>(ws) + half};
   int cur = 0;
   const void* in = x;
-  // profile record names (the profiler keeps the pointer: literals only)
-  static const char* const kNames[2][3][3] = {
+  // profile record names (the profiler keeps the pointer: literals only):
+  // complex64 1 RHS, FP32 MFMA, BF16 split, complex128 1 RHS, complex128 many RHS
+  static const char* const kNames[2][5][3] = {
       {{"apply1_v", "apply1_s", "apply1_u"}, {"applyn_v", "applyn_s", "applyn_u"},
-       {"applyb_v", "applyb_s", "applyb_u"}},
-      {{"adj1_v", "adj1_s", "adj1_u"}, {"adjn_v", "adjn_s", "adjn_u"}, {"adjb_v", "adjb_s", "adjb_u"}}};
-  const int kind = bf16 ? 2 : nrhs == 1 ? 0 : 1;
+       {"applyb_v", "applyb_s", "applyb_u"}, {"apply1d_v", "apply1d_s", "apply1d_u"},
+       {"applynd_v", "applynd_s", "applynd_u"}},
+      {{"adj1_v", "adj1_s", "adj1_u"}, {"adjn_v", "adjn_s", "adjn_u"}, {"adjb_v", "adjb_s", "adjb_u"},
+       {"adj1d_v", "adj1d_s", "adj1d_u"}, {"adjnd_v", "adjnd_s", "adjnd_u"}}};
+  const int kind = bf16 ? 2 : fp64 ? (nrhs == 1 ? 3 : 4) : (nrhs == 1 ? 0 : 1);
   auto name = [&](char stage) { return kNames[adj][kind][stage == 'v' ? 0 : stage == 's' ? 1 : 2]; };
   // V-shaped stages: V_t forward (t = 1..H), U_t^H in the adjoint (t = 1..H)
   for (int t = 1; t <= h->H; ++t) {
@@ -1714,6 +1740,27 @@ idbf_status idbf_batch_export(idbf_handle h, int32_t side, int32_t level, int32_
   if (skel) IDBF_HIP_CHECK(hipMemcpy(skel, b->skel_idx, b->n_skel * 4, hipMemcpyDeviceToHost));
   if (T) IDBF_HIP_CHECK(hipMemcpy(T, b->T128, b->n_T * 16, hipMemcpyDeviceToHost));
   if (T_off) IDBF_HIP_CHECK(hipMemcpy(T_off, b->T_off, b->n * 8, hipMemcpyDeviceToHost));
+  return IDBF_OK;
+}
+
+idbf_status idbf_batch_proposal(idbf_handle h, int32_t side, int32_t level, int32_t* proposed, int32_t* used,
+                                int32_t* rejected) {
+  g_err[0] = 0;
+  const Batch* b = h ? find_batch(h, side, level) : nullptr;
+  if (!b) {
+    set_error("batch_proposal: invalid handle, side or level");
+    return IDBF_EINVAL;
+  }
+  IDBF_HIP_CHECK(hipStreamSynchronize(h->stream));
+  const size_t bytes = size_t(b->n) * sizeof(int32_t);
+  const int32_t* first = b->s_first ? b->s_first : b->samples;
+  const int32_t* final_ = b->s_prop ? b->s_prop : b->samples;
+  if (proposed) IDBF_HIP_CHECK(hipMemcpy(proposed, first, bytes, hipMemcpyDeviceToHost));
+  if (used) IDBF_HIP_CHECK(hipMemcpy(used, final_, bytes, hipMemcpyDeviceToHost));
+  if (rejected) {
+    if (b->reject) IDBF_HIP_CHECK(hipMemcpy(rejected, b->reject, bytes, hipMemcpyDeviceToHost));
+    else std::memset(rejected, 0, bytes);
+  }
   return IDBF_OK;
 }
 

@@ -15,6 +15,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU containers
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_1809_10573_amd import binding as B  # noqa: E402
+from gpu_export import same_factors  # noqa: E402
 
 DEV = "cuda:0"
 
@@ -30,35 +31,13 @@ CASES = [
 ]
 
 
-def _same_factors(a, b):
-    ia, ib = a.info(), b.info()
-    for key in ("L", "H", "nnz_T", "nnz_S", "n_skel", "rank_max", "rank_min"):
-        assert ia[key] == ib[key], key
-    for side in (B.SIDE_U, B.SIDE_V):
-        for t in range(1, ia["H"] + 1):
-            x, y = a.batch(side, t), b.batch(side, t)
-            for f in ("rank", "cand_len", "mask", "skel", "T_off"):
-                assert np.array_equal(getattr(x, f), getattr(y, f)), (side, t, f)
-            # T entries in use (each ID reserves an upper bound; the tail is never written)
-            for q in range(len(x.rank)):
-                n = int(x.rank[q]) * int(x.cand_len[q] - x.rank[q])
-                o = int(x.T_off[q])
-                assert np.array_equal(x.T[o:o + n], y.T[o:o + n]), (side, t, q)
-    Sa, oa = a.middle()
-    Sb, ob = b.middle()
-    assert np.array_equal(oa, ob)
-    ends = np.append(oa[1:], len(Sa))
-    for o, e in zip(oa, ends):  # a block's reservation is rounded up to even: skip its last slot
-        assert np.array_equal(Sa[o:e - 1], Sb[o:e - 1])
-
-
 def test_construct_batched_equals_one_by_one():
     grids = [I.uniform_grid(N) for _, N, _, _ in CASES]
     facs = B.construct_batched([c[0] for c in CASES], [g[0] for g in grids], [g[1] for g in grids],
                                [c[3] for c in CASES], [c[2] for c in CASES], oversample=2, device=DEV)
     for (ph, N, leaf, tol), (X, O), fb in zip(CASES, grids, facs):
         f1 = B.construct(ph, X, O, tol, leaf, oversample=2, device=DEV)
-        _same_factors(fb, f1)
+        same_factors(fb, f1)
     # the smallest ones against the oracle's apply of its own factors
     for (ph, N, leaf, tol), (X, O), fb in list(zip(CASES, grids, facs))[3:6]:
         F = oracle.build(ph, X, O, leaf, tol, oversample=2)
@@ -108,7 +87,7 @@ def test_uneven_family_batch():
     ranks = [f.info()["rank_max"] for f in facs]
     assert max(ranks) > min(ranks)                       # uneven ranks across instances
     for w, (X, O), fb in zip(work, grids, facs):
-        _same_factors(fb, B.construct(w["phase"], X, O, w["tol"], w["leaf"], oversample=2, device=DEV))
+        same_factors(fb, B.construct(w["phase"], X, O, w["tol"], w["leaf"], oversample=2, device=DEV))
     xs = [torch.as_tensor(I.gaussian_vectors(w["N"], w["nrhs"] if w["nrhs"] > 1 else None, seed=i),
                           device=DEV) for i, w in enumerate(work)]
     ys = B.apply_batched(facs, xs)

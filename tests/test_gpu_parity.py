@@ -331,7 +331,7 @@ def test_apply_many_rhs_and_repeat():
     (256, 2, "fio", 1e-8, 1),
     (2048, 16, "nufft", 1e-6, 2),
 ])
-@pytest.mark.parametrize("nrhs", [2, 65, 300])
+@pytest.mark.parametrize("nrhs", [2, 65, 300, 1024, 1100])
 def test_many_rhs_matrix_core_paths(N, leaf, kind, tol, os_, nrhs):
     """complex64 apply on the matrix cores (FP32 MFMA, and BF16 hi/lo split
     products with FP32 accumulation) against the oracle's FP64 apply of its
@@ -499,3 +499,51 @@ def test_full_size_many_rhs_precisions():
         y = fac.apply(p64, dtype=dtype).to(torch.complex128)
         rel = float(torch.linalg.norm(y - y128) / torch.linalg.norm(y128))
         assert rel < bound, (dtype, rel)
+
+
+def test_stats_describe_the_levels():
+    """idbf_stats against the exported levels: rank histograms sum to the ID
+    counts and match the ranks, per-level T entries and skeleton counts match,
+    tall IDs are the ones that sampled more than 128 points."""
+    ph, X, O = _workload("dft", 1024)
+    fac = B.construct(ph, X, O, 1e-6, 64, oversample=4, device=DEV)
+    st = fac.stats()
+    info = fac.info()
+    assert st["levels"] == info["H"] == st["H"]
+    total_T, records = 0, 0
+    for t, row in enumerate(st["per_level"], start=1):
+        for side, name in ((B.SIDE_U, "U"), (B.SIDE_V, "V")):
+            L, b = row[name], fac.batch(side, t)
+            assert L["n_ids"] == len(b.rank) == L["rank_hist"].sum()
+            assert np.array_equal(L["rank_hist"], np.bincount(b.rank, minlength=B.STATS_RANKS))
+            assert (L["rank_min"], L["rank_max"]) == (b.rank.min(), b.rank.max())
+            assert L["n_skel"] == b.rank.sum()
+            assert L["nnz_T"] == int(np.sum(b.rank.astype(np.int64) * (b.cand_len - b.rank)))
+            _, used, _ = fac.proposal(side, t)
+            assert L["tall"] == int(np.sum(used > 128))
+            assert L["proposed"] == L["accepted"] == L["rejected"] == 0
+            total_T += L["nnz_T"]
+            records += L["n_ids"]
+    assert sum(row[s]["tall"] for row in st["per_level"] for s in "UV") > 0
+    assert st["nnz_S"] == info["nnz_S"]
+    assert st["apply_bytes_c64"] == 8 * (total_T + st["nnz_S"]) + 40 * records
+    assert st["apply_bytes_c128"] == 16 * (total_T + st["nnz_S"]) + 40 * records
+
+
+def test_allow_truncate_keeps_rank_64():
+    """An eps-rank above the supported 64 (FIO, leaf 64, tol 1e-10) fails with
+    IDBF_ERANK; with IDBF_FLAG_ALLOW_TRUNCATE those IDs keep 64 skeletons,
+    which is the oracle's ID with rank parameter k = 64 (Section 2.1's
+    (eps, k)-ID)."""
+    N, leaf, tol = 2048, 64, 1e-10
+    ph, X, O = _workload("fio", N)
+    with pytest.raises(B.IdbfError) as e:
+        B.construct(ph, X, O, tol, leaf, oversample=2, device=DEV)
+    assert e.value.status == B.ERANK
+    fac = B.construct(ph, X, O, tol, leaf, oversample=2, device=DEV, allow_truncate=True)
+    assert fac.info()["rank_max"] == 64
+    F = oracle.build(ph, X, O, leaf, tol, oversample=2, kmax=64)
+    assert _compare_construction(F, fac, ph, X, O) == 0
+    g = I.gaussian_vectors(N, None, seed=3)
+    y = fac.apply(torch.as_tensor(g, device=DEV)).cpu().numpy()
+    assert oracle.relative_error(y, oracle.apply(F, g)) < 1e-12

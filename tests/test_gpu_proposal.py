@@ -138,3 +138,85 @@ def test_trained_proposer_saves_samples_at_equal_accuracy():
         ip, iq = plain.info(), prop.info()
         assert iq["sampled_entries"] < ip["sampled_entries"]
         assert _rows_error(prop, ph, X, O, 5) <= max(2 * _rows_error(plain, ph, X, O, 5), 1e-5)
+
+
+def test_accepted_proposals_match_the_oracle():
+    """Every ID of a construction with a proposer, judged by the oracle on the
+    GPU's own candidate and allowed sets: an accepted proposal is the oracle's
+    column_id of the proposal's s' Mock-Chebyshev samples (same skeleton, T to
+    the parity bound) and passes oracle.mlp.residual_ok on the same check
+    rows; a rejected one fails that test and is stored as the plain ID.  The
+    network only chooses s' (passed to the oracle as an input)."""
+    ph = I.fio_phase(1.0, 1.0)
+    N, leaf, tol, t_os, seed = 4096, 16, 1e-6, 2, 5
+    X, O = I.uniform_grid(N)
+    counts = {"accepted": 0, "rejected": 0, "kept": 0}
+    # a proposal of rank 12 (+2) that the test mostly accepts, and one of rank 3
+    # that it mostly rejects
+    for k_hat, margin in ((12, 2), (3, 0)):
+        p = np.zeros(B.load().idbf_mlp_param_count(16), np.float32)
+        p[-1] = k_hat / 16.0                              # proposes rank k_hat everywhere
+        net = B.RankProposer(16, params=p)
+        fac = B.construct(ph, X, O, tol, leaf, oversample=t_os, device=DEV, proposer=net,
+                          proposal_margin=margin, seed=seed)
+        _judge_proposals(fac, ph, X, O, tol, t_os, seed, k_hat + margin, counts)
+        print(k_hat, margin, counts, flush=True)
+    assert counts["accepted"] > 0 and counts["rejected"] > 0
+
+
+def _judge_proposals(fac, ph, X, O, tol, t_os, seed, k_prop, counts):
+    from gpu_export import GpuLevels
+    G = GpuLevels(fac)
+    for t in range(1, G.H + 1):
+        for side in (B.SIDE_U, B.SIDE_V):
+            proposed, used, rejected = fac.proposal(side, t)
+            b, offs = G.batches[(side, t)]
+            for q in range(len(b.rank)):
+                cand, allowed = G.sets(side, t, q)
+                coords = X[allowed] if side == B.SIDE_V else O[allowed]
+                s_plain = oracle.sample_count(len(cand), len(allowed), t_os)
+                sp = int(proposed[q])
+                assert sp == min(s_plain, t_os * k_prop), (t, side, q)
+                samp = allowed[oracle.mock_chebyshev(coords, sp)]
+                Bm = (oracle.entries(ph, X, O, samp, cand) if side == B.SIDE_V
+                      else oracle.entries(ph, X, O, cand, samp).T)
+                cid = oracle.column_id(Bm, tol)
+                pos = omlp.check_positions(seed, t, side, q, len(allowed))
+                rows = allowed[pos]
+                A = (oracle.entries(ph, X, O, rows, cand) if side == B.SIDE_V
+                     else oracle.entries(ph, X, O, cand, rows).T)
+                ok = sp == s_plain or omlp.residual_ok(A, cid.skel, cid.red, cid.T, tol)
+                assert bool(rejected[q]) == (not ok), (t, side, q)
+                rec = G.record(side, t, q)
+                if ok:
+                    counts["kept" if sp == s_plain else "accepted"] += 1
+                    assert int(used[q]) == sp
+                else:
+                    counts["rejected"] += 1
+                    assert int(used[q]) == s_plain
+                    samp = allowed[oracle.mock_chebyshev(coords, s_plain)]
+                    Bm = (oracle.entries(ph, X, O, samp, cand) if side == B.SIDE_V
+                          else oracle.entries(ph, X, O, cand, samp).T)
+                    cid = oracle.column_id(Bm, tol)
+                assert np.array_equal(rec.skel, cand[cid.skel]), (t, side, q)
+                kappa = cid.rdiag[0] / cid.rdiag[-1]
+                scale = max(1.0, np.abs(cid.T).max(initial=0.0))
+                assert np.max(np.abs(rec.T - cid.T), initial=0.0) <= 1e-12 * kappa * scale, (t, side, q)
+
+
+def test_force_reject_gives_the_plain_factors_bit_for_bit():
+    """IDBF_FLAG_PROPOSER_FORCE_REJECT: every proposal is rejected and
+    recomputed by the plain ID, so ranks, skeletons, T and S equal those of a
+    construction without a proposer exactly."""
+    ph = I.fio_phase(0.8, 3.0)
+    X, O = I.uniform_grid(4096)
+    plain = B.construct(ph, X, O, 1e-6, 16, oversample=2, device=DEV)
+    p = B.mlp_init(16, seed=4)
+    net = B.RankProposer(16, params=p)
+    forced = B.construct(ph, X, O, 1e-6, 16, oversample=2, device=DEV, proposer=net, proposal_margin=2,
+                         force_reject=True)
+    st = forced.stats()
+    assert sum(L[s]["rejected"] for L in st["per_level"] for s in "UV") == forced.info()["n_ids"]
+    assert sum(L[s]["accepted"] for L in st["per_level"] for s in "UV") == 0
+    from gpu_export import same_factors
+    same_factors(plain, forced)
