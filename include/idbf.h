@@ -217,6 +217,23 @@ idbf_status idbf_apply_batched_plan(int32_t count, const idbf_handle* hs, const 
 idbf_status idbf_plan_launch(idbf_plan p, void* stream);
 idbf_status idbf_plan_destroy(idbf_plan p);
 
+/*
+ * idbf_apply_noalloc -- idbf_apply for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, kernels and results (bit for bit) as
+ * idbf_apply, but the stage vectors live in one fixed device array of the
+ * library (128 MiB per device, held until the process ends) instead of the
+ * handle's workspace; the call allocates nothing and records no profile
+ * events.  The array holds 2 * (largest skeleton count of a level) * nrhs
+ * complex values: nrhs beyond that gives IDBF_EINVAL with the size in the
+ * message (at N = 2^20, leaf 16, tol 1e-6 one complex128 or complex64 vector
+ * fits).  Every call on a device shares that device's array, so calls that
+ * overlap in time on one device race; the array keeps the last call's
+ * contents, which no call reads before writing.
+ */
+idbf_status idbf_apply_noalloc(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype,
+                               void* stream);
+
 /* Grow the handle's apply workspace (device memory, a kept chunk when one
  * fits) so that idbf_apply with up to nrhs right-hand sides of dtype
  * allocates nothing.  Synchronizes the device if it allocates. */

@@ -32,6 +32,7 @@ EXPORTED = [
     "idbf_mlp_destroy", "idbf_mlp_params", "idbf_mlp_forward", "idbf_mlp_loss_grad", "idbf_mlp_train",
     "idbf_rank_samples", "idbf_apply_batched_plan", "idbf_plan_launch", "idbf_plan_destroy",
     "idbf_apply_adjoint", "idbf_release_cached_memory", "idbf_stats", "idbf_batch_proposal",
+    "idbf_apply_noalloc",
 ]
 MLP_INPUTS = 8
 FLAG_PROFILE, FLAG_PROPOSER_FORCE_REJECT, FLAG_ALLOW_TRUNCATE = 1, 2, 4
@@ -115,6 +116,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_construct.argtypes = [P(Phase_t), VP, VP, I64, D, I32, P(Opts_t), P(VP)]
     lib.idbf_apply.argtypes = [VP, VP, VP, I64, I32, VP]
     lib.idbf_apply_adjoint.argtypes = [VP, VP, VP, I64, I32, VP]
+    lib.idbf_apply_noalloc.argtypes = [VP, VP, VP, I64, I32, VP]
     lib.idbf_destroy.argtypes = [VP]
     lib.idbf_get_info.argtypes = [VP, P(Info_t)]
     lib.idbf_stats.argtypes = [VP, P(Stats_t)]
@@ -266,6 +268,13 @@ class Factorization:
     def apply(self, x, y=None, dtype: int | None = None, stream=None):
         """y = K~ x for a (N,) or (N, nrhs) complex128/complex64 device tensor."""
         return self._apply(load().idbf_apply, x, y, dtype, stream)
+
+    def apply_noalloc(self, x, y, dtype: int | None = None, stream=None):
+        """idbf_apply_noalloc: y = K~ x with the library's fixed scratch array
+        (no device allocation in the library; y must be given)."""
+        if y is None:
+            raise ValueError("apply_noalloc needs the output tensor y")
+        return self._apply(load().idbf_apply_noalloc, x, y, dtype, stream)
 
     def apply_adjoint(self, x, y=None, dtype: int | None = None, stream=None):
         """y = K~^H x (idbf_apply_adjoint), same argument rules as apply."""

@@ -1423,6 +1423,73 @@ idbf_status idbf_apply_adjoint(idbf_handle h, const void* x, void* y, int64_t nr
   return apply_impl(h, x, y, nrhs, dtype, stream, true);
 }
 
+}  // extern "C"
+
+// Device memory of idbf_apply_noalloc: one array per device, held until the
+// process ends.  In host code the name is only a stand-in for the device
+// array: its device address comes from hipGetSymbolAddress, once per device,
+// and only that address is ever passed on.
+static constexpr size_t kNoAllocBytes = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+idbf_status noalloc_scratch(void** out) {
+  static std::mutex mu;
+  static int devs[64];
+  static void* ptrs[64];
+  static int n = 0;
+  int dev = 0;
+  IDBF_HIP_CHECK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  for (int i = 0; i < n; ++i)
+    if (devs[i] == dev) {
+      *out = ptrs[i];
+      return IDBF_OK;
+    }
+  if (n == 64) {
+    set_error("apply_noalloc: more than 64 devices");
+    return IDBF_EUNSUPPORTED;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    set_error("apply_noalloc: hipGetSymbolAddress of the scratch array failed on device %d: %s", dev,
+              hipGetErrorString(e));
+    return IDBF_EHIP;
+  }
+  devs[n] = dev;
+  ptrs[n] = ptr;
+  ++n;
+  *out = ptr;
+  return IDBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+idbf_status idbf_apply_noalloc(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype, void* stream) {
+  g_err[0] = 0;
+  if (!h) {
+    set_error("handle is NULL");
+    return IDBF_EINVAL;
+  }
+  if (nrhs > 0 && (dtype == IDBF_C128 || dtype == IDBF_C64 || dtype == IDBF_C64_BF16X3)) {
+    const size_t need = 2 * size_t(h->max_skel) * size_t(nrhs) * (dtype == IDBF_C128 ? 16 : 8);
+    if (h->H > 0 && need > kNoAllocBytes) {
+      set_error("apply_noalloc: %lld right-hand sides need %zu bytes of workspace; the fixed scratch array "
+                "holds %zu (use idbf_apply, or fewer right-hand sides)",
+                (long long)nrhs, need, kNoAllocBytes);
+      return IDBF_EINVAL;
+    }
+  }
+  void* ws = nullptr;
+  TRY(noalloc_scratch(&ws));
+  return apply_impl(h, x, y, nrhs, dtype, stream, false, ws, kNoAllocBytes);
+}
+
 idbf_status idbf_apply_batched(int32_t count, const idbf_handle* hs, const void* const* x, void* const* y,
                                const int64_t* nrhs, int32_t dtype, void* stream) {
   g_err[0] = 0;
