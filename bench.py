@@ -2,18 +2,26 @@
 
 One step = the whole hot path on the N = 2^20 FIO workload
 (Phi = x xi + c(x)|xi|, c(x) = (2 + sin 2 pi x)/8, leaf 16, tol 1e-6,
-oversampling t = 2): construction (FP64 IDs on the GPU), one 1-RHS apply in
-complex64, and one apply to 1024 right-hand sides in complex64 on the matrix
-cores in each of the two precisions (FP32 MFMA; BF16 hi/lo split products
-with FP32 accumulation), all inputs resident in HBM.  Prints one JSON line.
+oversampling t = 2): construction (FP64 IDs on the GPU), then applies of the
+factors with every input resident in HBM:
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--nrhs 1024] [--no-cpu-baseline]
+  complex64   1 RHS (VALU), 256 and 1024 RHS (FP32 MFMA)
+  BF16 split  256 and 1024 RHS (BF16 hi/lo MFMA products, FP32 accumulation)
+  complex128  1, 256 and 1024 RHS (the plain FP64 form, VALU)
 
-value = algorithmic GB/s of the 1-RHS apply (factor entries + skeleton masks +
-x and y once), averaged over the timed steps; construct_ms and the many-RHS
-apply rate are reported beside it.  "roofline" is computed live from HIP events
-the library records around every launch, for the kernel that takes the largest
-share of a step.
+Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] ...
+    python bench.py --only learned      # the learned proposal at full scale
+                                        # (2000 training constructions, 200 held out)
+
+value = algorithmic GB/s of the complex64 1-RHS apply (factor entries + ID
+records + x and y once), averaged over the timed steps; every other apply is
+reported beside it with its rate, its relative error against the complex128
+apply of the same factors on 8 probe vectors, and its speedup over the
+complex128 apply of the same right-hand-side count.  "roofline" is computed
+live from HIP events the library records around every launch, for the kernel
+that takes the largest share of a step.
 """
 from __future__ import annotations
 
@@ -40,28 +48,43 @@ BF16_MFMA_PEAK = 2500e12
 WORKLOAD = dict(N=1 << 20, leaf=16, tol=1e-6, oversample=2, a=1.0, freq=1.0, c0=2.0, cdiv=8.0)
 
 
-def _cpu_baseline(timeout_s: int = 240) -> dict | None:
-    """The oracle, single-threaded, on a bounded sample of the same workload."""
+def _cpu_baseline(timeout_s: int = 400) -> dict | None:
+    """The oracle on the host cores, before anything initializes the GPU, on
+    the N = 2^16 member of the same FIO kernel (leaf 16, tol 1e-6, t = 2):
+    its construction on all host cores (one process per core over the
+    independent IDs of each level), its complex128 apply on one thread, and
+    its construction on one thread at N = 2^13 (the single-thread build at
+    N = 2^16 takes minutes)."""
     code = r"""
 import json, os, sys, time
 sys.path.insert(0, %r)
 import numpy as np
 import oracle
 from paper_1809_10573_amd import inputs as I
-N, leaf, tol, t = 2048, 16, 1e-6, 2
 ph = I.fio_phase(1.0, 1.0)
+cores = max(1, min(16, os.cpu_count() or 1))
+N, leaf, tol, t = 1 << 16, 16, 1e-6, 2
 X, O = I.uniform_grid(N)
 t0 = time.perf_counter()
-F = oracle.build(ph, X, O, leaf, tol, oversample=t)
-tb = time.perf_counter() - t0
+F = oracle.build(ph, X, O, leaf, tol, oversample=t, workers=cores)
+build_all = time.perf_counter() - t0
 g = I.gaussian_vectors(N, None, 4)
-reps = 5
+reps = 3
 t0 = time.perf_counter()
 for _ in range(reps):
     y = oracle.apply(F, g)
-ta = (time.perf_counter() - t0) / reps
+apply_s = (time.perf_counter() - t0) / reps
 nnz = F.nnz()
-print(json.dumps(dict(N=N, nnz=nnz, build_s=tb, apply_s=ta, gbs=(nnz * 16 + 2 * N * 16) / ta / 1e9)))
+n_ids = sum(len(F.U[k]) + len(F.V[k]) for k in F.U)
+Ns = 1 << 13
+Xs, Os = I.uniform_grid(Ns)
+t0 = time.perf_counter()
+Fs = oracle.build(ph, Xs, Os, leaf, tol, oversample=t)
+build_1 = time.perf_counter() - t0
+n_ids_s = sum(len(Fs.U[k]) + len(Fs.V[k]) for k in Fs.U)
+print(json.dumps(dict(N=N, nnz=nnz, n_ids=n_ids, build_all_s=build_all, cores=cores, apply_s=apply_s,
+                      gbs=(nnz * 16 + 8 * n_ids + 2 * N * 16) / apply_s / 1e9, Ns=Ns, build_1_s=build_1,
+                      n_ids_s=n_ids_s, cpu_count=os.cpu_count())))
 """ % ROOT
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     try:
@@ -74,10 +97,14 @@ print(json.dumps(dict(N=N, nnz=nnz, build_s=tb, apply_s=ta, gbs=(nnz * 16 + 2 * 
         return None
     r = json.loads(res.stdout.strip().splitlines()[-1])
     return {"value": r["gbs"], "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": (f"oracle FP64 apply of its own N={r['N']} factorization of the same FIO "
-                       f"kernel (leaf 16, tol 1e-6, t=2; {r['nnz']} stored entries, complex128), "
-                       f"1 thread; apply {r['apply_s'] * 1e3:.1f} ms, construction "
-                       f"{r['build_s']:.1f} s (N=2^20 would take hours)")}
+            "sample": (f"oracle FP64 (complex128) apply of its own N=2^16 factorization of the same FIO "
+                       f"kernel (leaf 16, tol 1e-6, t=2; {r['nnz']} stored entries), 1 thread: "
+                       f"{r['apply_s'] * 1e3:.0f} ms per apply"),
+            "construct_s_all_cores": r["build_all_s"], "construct_cores": r["cores"],
+            "host_cpu_count": r["cpu_count"],
+            "construct_ids_per_s_all_cores": r["n_ids"] / r["build_all_s"],
+            "construct_s_1thread_n2p13": r["build_1_s"],
+            "construct_ids_per_s_1thread": r["n_ids_s"] / r["build_1_s"]}
 
 
 def _batched(B, torch, dev, stream) -> dict:
@@ -254,27 +281,32 @@ def _example(B, torch, dev, stream, kind: str) -> dict:
             "rank_min": info["rank_min"], "rank_max": info["rank_max"]}
 
 
-def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6) -> dict:
+def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6, keep: int = 8,
+             progress: bool = False) -> dict:
     """The learned rank proposal on the FIO family c(x) = (2 + a sin 2 pi m x)/8
     at N = 2^18 (leaf 16, tol 1e-6, t = 2): the network is trained on the GPU
-    on ranks from n_train plain constructions, then plain and proposed
-    constructions of n_test held-out (a, m) are compared (wall time, sampled
-    entries, rejected proposals, error on 128 exact rows).  Measured once."""
+    on ranks from n_train plain constructions (1 in `keep` of their IDs), then
+    plain and proposed constructions of n_test held-out (a, m) are compared
+    (wall time, sampled entries, rejected proposals, error on 128 exact rows).
+    The default is a reduced run (16 / 6); `--only learned` runs the full
+    2000 / 200.  Measured once."""
     N, leaf, tol = 1 << 18, 16, 1e-6
     Xh, Oh = I.uniform_grid(N)
     X, O = torch.as_tensor(Xh, device=dev), torch.as_tensor(Oh, device=dev)
     gen = torch.Generator(device=dev).manual_seed(8)
     t0 = time.perf_counter()
     feats, targ = [], []
-    for (a, m) in I.family_draws(n_train, seed=21):
+    for i, (a, m) in enumerate(I.family_draws(n_train, seed=21)):
         fac = B.construct(I.fio_phase(a, float(m)), X, O, tol, leaf, oversample=2, device=dev, stream=stream)
         for side in (B.SIDE_U, B.SIDE_V):
             for t in range(1, fac.info()["H"] + 1):
                 F, tg = B.rank_samples(fac, side, t, device=dev)
-                keep = torch.randperm(F.shape[0], generator=gen, device=dev)[: F.shape[0] // 8]
-                feats.append(F[keep])
-                targ.append(tg[keep])
+                sel = torch.randperm(F.shape[0], generator=gen, device=dev)[: F.shape[0] // keep]
+                feats.append(F[sel])
+                targ.append(tg[sel])
         fac.close()
+        if progress and (i + 1) % 100 == 0:
+            print(f"learned: {i + 1} training constructions", file=sys.stderr, flush=True)
     F, tg = torch.cat(feats), torch.cat(targ)
     label_s = time.perf_counter() - t0
     net = B.RankProposer(128, seed=5)
@@ -287,7 +319,9 @@ def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6) -> dict:
     g = torch.as_tensor(I.gaussian_vectors(N, None, 9), device=dev)
     res = {"plain_ms": [], "proposed_ms": [], "plain_sampled": 0, "proposed_sampled": 0, "proposed": 0,
            "rejected": 0, "err_plain": [], "err_proposed": []}
-    for (a, m) in I.family_draws(n_test, seed=22):
+    for i, (a, m) in enumerate(I.family_draws(n_test, seed=22)):
+        if progress and i % 20 == 0:
+            print(f"learned: held-out member {i}", file=sys.stderr, flush=True)
         ph = I.fio_phase(a, float(m))
         ex = torch.zeros(128, dtype=torch.complex128, device=dev)
         for c0 in range(0, N, 1 << 16):
@@ -307,7 +341,8 @@ def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6) -> dict:
             res["err_" + kind].append(float(torch.linalg.norm(y[rows.long()] - ex) / torch.linalg.norm(ex)))
             fac.close()
     net.close()
-    return {"N": N, "train_constructions": n_train, "train_samples": int(F.shape[0]),
+    return {"N": N, "scale": "full (2000 / 200)" if n_train >= 2000 else "reduced",
+            "train_constructions": n_train, "train_samples": int(F.shape[0]),
             "labels_s": label_s, "train_s": train_s, "loss_first_last": [float(losses[0]), float(losses[-1])],
             "heldout": n_test,
             "construct_ms_plain": float(np.mean(res["plain_ms"])),
@@ -315,7 +350,83 @@ def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6) -> dict:
             "speedup": float(np.mean(res["plain_ms"]) / np.mean(res["proposed_ms"])),
             "sampled_entries_ratio": res["proposed_sampled"] / max(res["plain_sampled"], 1),
             "rejected_frac": res["rejected"] / max(res["proposed"], 1),
-            "err_rows_plain_max": max(res["err_plain"]), "err_rows_proposed_max": max(res["err_proposed"])}
+            "err_rows_plain_max": max(res["err_plain"]), "err_rows_proposed_max": max(res["err_proposed"]),
+            "err_rows_plain_median": float(np.median(res["err_plain"])),
+            "err_rows_proposed_median": float(np.median(res["err_proposed"])),
+            "construct_ms_plain_samples": [round(v, 2) for v in res["plain_ms"][:10]],
+            "construct_ms_proposed_samples": [round(v, 2) for v in res["proposed_ms"][:10]]}
+
+
+def _config2(B, torch, dev, stream) -> dict:
+    """The N = 2^16 FIO configuration (leaf 16, tol 1e-6, t = 2; FP64
+    construction, complex64 applies to 1 and 256 right-hand sides): the
+    median of three constructions after a warm-up, event-timed applies in
+    every precision, relative errors against the complex128 apply of the same
+    factors on 8 probes, and epsilon^a on 256 exact rows.  Measured once."""
+    N, leaf, tol, t_os = 1 << 16, 16, 1e-6, 2
+    ph = I.fio_phase(1.0, 1.0)
+    Xh, Oh = I.uniform_grid(N)
+    X, O = torch.as_tensor(Xh, device=dev), torch.as_tensor(Oh, device=dev)
+    times, fac = [], None
+    for it in range(4):
+        if fac is not None:
+            fac.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fac = B.construct(ph, X, O, tol, leaf, oversample=t_os, device=dev, stream=stream)
+        times.append((time.perf_counter() - t0) * 1e3)
+    info = fac.info()
+    nnz = info["nnz_T"] + info["nnz_S"]
+    gen = torch.Generator(device=dev).manual_seed(12)
+    out = {"N": N, "construct_ms": float(np.median(times[1:])), "construct_ms_samples": [round(v, 2) for v in times[1:]],
+           "nnz": nnz, "rank_min": info["rank_min"], "rank_max": info["rank_max"]}
+    fac.reserve(256, B.C128)
+    for nrhs in (1, 256):
+        xd = (torch.randn(N, nrhs, dtype=torch.complex128, device=dev, generator=gen) * np.sqrt(2.0)).squeeze(1)
+        xd = xd.contiguous()
+        for name, x, dt in (("c128", xd, B.C128), ("c64", xd.to(torch.complex64), B.C64),
+                            ("bf16x3", xd.to(torch.complex64), B.C64_BF16X3)):
+            if nrhs == 1 and name == "bf16x3":
+                continue
+            y = torch.empty_like(x)
+            ms = _event_ms(torch, stream, lambda: fac.apply(x, y, dtype=dt, stream=stream))
+            rec = {"ms": ms}
+            if nrhs == 1:
+                rec["gbs"] = (nnz * (16 if name == "c128" else 8) + 8 * info["n_ids"] + 2 * N * x.element_size()) / ms / 1e6
+            else:
+                rec["gflops"] = 8.0 * nnz * nrhs / ms / 1e6
+            out[f"{name}_nrhs{nrhs}"] = rec
+        for name in ("c64", "bf16x3"):
+            key = f"{name}_nrhs{nrhs}"
+            if key in out:
+                out[key]["speedup_vs_c128"] = out[f"c128_nrhs{nrhs}"]["ms"] / out[key]["ms"]
+    probes = torch.as_tensor(I.gaussian_vectors(N, 8, 5), device=dev)
+    y128 = fac.apply(probes)
+    p64 = probes.to(torch.complex64)
+    for name, dt in (("c64", B.C64), ("bf16x3", B.C64_BF16X3)):
+        y = fac.apply(p64, dtype=dt).to(torch.complex128)
+        out[f"rel_err_{name}_vs_c128"] = float(torch.linalg.norm(y - y128) / torch.linalg.norm(y128))
+    y1 = fac.apply(probes[:, 0].contiguous().to(torch.complex64)).to(torch.complex128)
+    out["rel_err_c64_1rhs_vs_c128"] = float(torch.linalg.norm(y1 - y128[:, 0]) / torch.linalg.norm(y128[:, 0]))
+    rows = torch.as_tensor(np.sort(np.random.default_rng(0).choice(N, 256, replace=False)), dtype=torch.int32,
+                           device=dev)
+    ex = B.sample(ph, X, O, rows, torch.arange(N, dtype=torch.int32, device=dev), device=dev) @ probes[:, 0]
+    out["eps_a_256rows"] = float(torch.linalg.norm(y128[rows.long(), 0] - ex) / torch.linalg.norm(ex))
+    fac.close()
+    return out
+
+
+def _event_ms(torch, stream, fn, warm: bool = True) -> float:
+    """Device time of fn() on `stream` between two HIP events (after one untimed run)."""
+    if warm:
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "id_qr_fio_n2p20_counters.md")
@@ -372,10 +483,16 @@ def _only(what: str) -> int:
     """Single pieces of the step for counter runs: the workload's construction
     (twice), its complex64 1-RHS apply (three times, after one construction),
     its 1024-RHS applies (FP32 and BF16 split, once each), or a plain 1 GiB
-    device copy (three times) for calibration."""
+    device copy (three times) for calibration; or the learned proposal at full
+    scale (2000 training constructions, 200 held out)."""
     import torch
     from paper_1809_10573_amd import binding as B
     dev = torch.device("cuda:0")
+    if what == "learned":
+        res = _learned(B, torch, dev, torch.cuda.current_stream(), n_train=2000, n_test=200, keep=64,
+                       progress=True)
+        print(json.dumps({"learned": res}), flush=True)
+        return 0
     if what == "copy":
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -419,26 +536,52 @@ def _only(what: str) -> int:
     return 0
 
 
+APPLY_KINDS = [  # (name, dtype, nrhs): every apply of a step, in launch order
+    ("c64_nrhs1", "c64", 1), ("c128_nrhs1", "c128", 1),
+    ("c64_nrhs256", "c64", 256), ("bf16x3_nrhs256", "bf16x3", 256), ("c128_nrhs256", "c128", 256),
+    ("c64_nrhs1024", "c64", 1024), ("bf16x3_nrhs1024", "bf16x3", 1024), ("c128_nrhs1024", "c128", 1024),
+]
+
+
+def _rank_hist(st: dict) -> dict:
+    """Per level and side, {rank: IDs} of the nonzero histogram entries."""
+    out = {}
+    for t, row in enumerate(st["per_level"], start=1):
+        for side in ("U", "V"):
+            h = row[side]["rank_hist"]
+            out[f"{side}{t}"] = {int(r): int(h[r]) for r in np.nonzero(h)[0]}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--nrhs", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the many-instance measurement")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-proposal measurement")
     ap.add_argument("--no-ablation", action="store_true", help="skip the sampler / fixed-rank ablation")
     ap.add_argument("--no-examples", action="store_true",
                     help="skip the non-uniform Fourier transform and Schloemilch lines")
-    ap.add_argument("--only", choices=["construct", "apply1", "applyn", "copy"], help="run one piece for a counter pass")
+    ap.add_argument("--no-config2", action="store_true", help="skip the N = 2^16 configuration")
+    ap.add_argument("--only", choices=["construct", "apply1", "applyn", "copy", "learned"],
+                    help="run one piece (counter passes; the full-scale learned proposal)")
     args = ap.parse_args()
-    if args.only:
-        return _only(args.only)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: measures one GPU only; sharding the factorization over several GPUs "
               "is not implemented", file=sys.stderr)
         return 2
+    # the oracle's baseline runs first, before anything initializes the GPU
+    cpu = None if (args.only or args.no_cpu_baseline) else _cpu_baseline()
+    # A step builds a new handle; the library keeps the device memory of a
+    # destroyed handle for the next one up to IDBF_CACHE_BYTES.  The step's
+    # largest buffers (factors, and the 1024-RHS complex128 apply workspace of
+    # about 56 GB) then stay allocated between steps instead of going through
+    # hipFree / hipMalloc each time.
+    os.environ.setdefault("IDBF_CACHE_BYTES", str(200 << 30))
+    if args.only:
+        return _only(args.only)
 
     import torch
     from paper_1809_10573_amd import binding as B
@@ -451,14 +594,20 @@ def main() -> int:
     Xh, Oh = I.uniform_grid(N)
     X = torch.as_tensor(Xh, device=dev)
     O = torch.as_tensor(Oh, device=dev)
-    x1 = torch.as_tensor(I.gaussian_vectors(N, None, 4), device=dev).to(torch.complex64)
-    y1 = torch.empty_like(x1)
-    nrhs = args.nrhs
-    gen = torch.Generator(device=dev).manual_seed(4)
-    # N(0,1) + i N(0,1) entries (complex randn has variance 1/2 per component)
-    XM = torch.randn(N, nrhs, dtype=torch.complex64, device=dev, generator=gen) * np.sqrt(2.0)
-    YM = torch.empty_like(XM)
     stream = torch.cuda.current_stream()
+    gen = torch.Generator(device=dev).manual_seed(4)
+    # right-hand sides: N(0,1) + i N(0,1) entries (complex randn has variance 1/2 per component)
+    xin, yout = {}, {}
+    x1d = torch.as_tensor(I.gaussian_vectors(N, None, 4), device=dev)
+    xin[("c128", 1)] = x1d
+    xin[("c64", 1)] = x1d.to(torch.complex64)
+    for nrhs in (256, 1024):
+        xd = torch.randn(N, nrhs, dtype=torch.complex128, device=dev, generator=gen) * np.sqrt(2.0)
+        xin[("c128", nrhs)] = xd
+        xin[("c64", nrhs)] = xd.to(torch.complex64)
+    for k, v in xin.items():
+        yout[k] = torch.empty_like(v)
+    dtypes = {"c64": B.C64, "bf16x3": B.C64_BF16X3, "c128": B.C128}
 
     def step(record):
         torch.cuda.synchronize()
@@ -466,45 +615,55 @@ def main() -> int:
         fac = B.construct(ph, X, O, W["tol"], W["leaf"], oversample=W["oversample"], profile=True,
                           device=dev, stream=stream)
         t_con = (time.perf_counter() - t0) * 1e3
-        fac.reserve(nrhs, B.C64)  # apply workspace, allocated outside the timed applies
-        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-        e[0].record(stream)
-        fac.apply(x1, y1, stream=stream)
-        e[1].record(stream)
-        e[2].record(stream)
-        fac.apply(XM, YM, stream=stream)
-        e[3].record(stream)
-        e[4].record(stream)
-        fac.apply(XM, YM, dtype=B.C64_BF16X3, stream=stream)
-        e[5].record(stream)
+        fac.reserve(1024, B.C128)  # the largest apply workspace, before the timed applies
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(APPLY_KINDS))]
+        for i, (name, prec, nrhs) in enumerate(APPLY_KINDS):
+            key = ("c128" if prec == "c128" else "c64", nrhs)
+            ev[2 * i].record(stream)
+            fac.apply(xin[key], yout[key], dtype=dtypes[prec], stream=stream)
+            ev[2 * i + 1].record(stream)
         torch.cuda.synchronize()
         if record is not None:
-            record.append(dict(construct_ms=t_con, apply1_ms=e[0].elapsed_time(e[1]),
-                               applyn_ms=e[2].elapsed_time(e[3]), applyb_ms=e[4].elapsed_time(e[5]),
-                               prof=fac.profile(reset=True), info=fac.info()))
+            r = dict(construct_ms=t_con, prof=fac.profile(reset=True), info=fac.info())
+            for i, (name, _, _) in enumerate(APPLY_KINDS):
+                r[name] = ev[2 * i].elapsed_time(ev[2 * i + 1])
+            record.append(r)
         return fac
 
     for _ in range(args.warmup):
-        step(None)
+        step(None).close()
     recs: list = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     fac = None
     for _ in range(args.steps):
-        del fac
+        if fac is not None:
+            fac.close()
         fac = step(recs)
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3 / args.steps
 
     info = recs[-1]["info"]
-    elem = 8
-    bytes1 = (info["nnz_T"] + info["nnz_S"]) * elem + 8 * info["n_ids"] + 2 * N * elem
-    apply1_ms = float(np.mean([r["apply1_ms"] for r in recs]))
-    applyn_ms = float(np.mean([r["applyn_ms"] for r in recs]))
-    applyb_ms = float(np.mean([r["applyb_ms"] for r in recs]))
+    nnz = info["nnz_T"] + info["nnz_S"]
     construct_ms = float(np.mean([r["construct_ms"] for r in recs]))
-    flops_n = 8.0 * (info["nnz_T"] + info["nnz_S"]) * nrhs
-    value = bytes1 / apply1_ms / 1e6
+    apply = {}
+    for name, prec, nrhs in APPLY_KINDS:
+        ms = float(np.mean([r[name] for r in recs]))
+        rec = {"ms": ms}
+        if nrhs == 1:
+            elem = 16 if prec == "c128" else 8
+            rec["gbs"] = (nnz * elem + 8 * info["n_ids"] + 2 * N * elem) / ms / 1e6
+            rec["frac_hbm_peak"] = rec["gbs"] / HBM_PEAK_GBS
+        else:
+            rec["gflops"] = 8.0 * nnz * nrhs / ms / 1e6
+            peak = {"c64": FP32_MFMA_PEAK, "bf16x3": BF16_MFMA_PEAK, "c128": FP64_VALU_PEAK}[prec]
+            rec["frac_peak"] = rec["gflops"] * 1e9 / peak
+            rec["peak"] = {"c64": "FP32 MFMA", "bf16x3": "BF16 MFMA", "c128": "FP64 VALU"}[prec]
+        apply[name] = rec
+    for name, prec, nrhs in APPLY_KINDS:
+        if prec != "c128":
+            apply[name]["speedup_vs_c128"] = apply[f"c128_nrhs{nrhs}"]["ms"] / apply[name]["ms"]
+    value = apply["c64_nrhs1"]["gbs"]
 
     # per-kernel aggregates over the timed steps
     agg: dict = {}
@@ -515,7 +674,7 @@ def main() -> int:
                 a[k] += st[k]
     dom_name = max(agg, key=lambda k: agg[k]["ms"])
     dom = agg[dom_name]
-    if dom_name == "id_qr":
+    if dom_name == "id_qr" or dom_name.startswith("applynd"):
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=achieved, peak=FP64_VALU_PEAK / 1e12, unit="TFLOP/s")
     elif dom_name.startswith("applyn") or dom_name.startswith("applyb"):
@@ -530,15 +689,21 @@ def main() -> int:
     roof["kernel"] = dom_name
     roof["launches_per_step"] = dom["launches"] / len(recs)
 
-    # accuracy (outside the timed region): complex64 apply vs the FP64 (complex128)
-    # apply of the same factors on 8 probe vectors, and the paper's epsilon^a on 256 rows
+    # accuracy (outside the timed region): every precision against the FP64
+    # (complex128) apply of the same factors on 8 probe vectors, and the
+    # paper's epsilon^a on 256 rows
     probes = torch.as_tensor(I.gaussian_vectors(N, 8, 5), device=dev)
     p64 = probes.to(torch.complex64).contiguous()
-    y64 = fac.apply(p64).to(torch.complex128)
-    ybf = fac.apply(p64, dtype=B.C64_BF16X3).to(torch.complex128)
     y128 = fac.apply(probes)
-    rel64 = float(torch.linalg.norm(y64 - y128) / torch.linalg.norm(y128))
-    relbf = float(torch.linalg.norm(ybf - y128) / torch.linalg.norm(y128))
+    errs = {}
+    for prec in ("c64", "bf16x3"):
+        y = fac.apply(p64, dtype=dtypes[prec]).to(torch.complex128)
+        errs[prec] = float(torch.linalg.norm(y - y128) / torch.linalg.norm(y128))
+    y1 = fac.apply(p64[:, 0].contiguous()).to(torch.complex128)
+    errs["c64_1rhs"] = float(torch.linalg.norm(y1 - y128[:, 0]) / torch.linalg.norm(y128[:, 0]))
+    for name, prec, nrhs in APPLY_KINDS:
+        if prec != "c128":
+            apply[name]["rel_err_vs_c128"] = errs["c64_1rhs" if nrhs == 1 else prec]
     rows = np.sort(np.random.default_rng(0).choice(N, 256, replace=False))
     ex = torch.zeros(256, dtype=torch.complex128, device=dev)
     cols = torch.arange(N, dtype=torch.int32, device=dev)
@@ -547,31 +712,37 @@ def main() -> int:
         K = B.sample(ph, X, O, rows_d, cols[c0:c0 + (1 << 16)], device=dev)
         ex += K @ probes[c0:c0 + (1 << 16), 0]
     eps_a = float(torch.linalg.norm(y128[rows, 0] - ex) / torch.linalg.norm(ex))
+    st = fac.stats()
 
     out = {
         "metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall_ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64 apply / f64 construct", "data": "synthetic",
+        "vs_baseline": None, "dtype": "c64 apply (value) / c128 and bf16x3 applies / f64 construct",
+        "data": "synthetic",
         "config": {"workload": "FIO exp(2 pi i (x xi + (2+sin 2 pi x)/8 |xi|)), uniform grid",
                    "N": N, "leaf": W["leaf"], "tol": W["tol"], "oversample": W["oversample"],
-                   "nrhs": [1, nrhs]},
-        "construct_ms": construct_ms, "apply1_ms": apply1_ms, "applyn_ms": applyn_ms,
-        "applyn_gflops": flops_n / applyn_ms / 1e6,
-        "applyb_ms": applyb_ms, "applyb_gflops": flops_n / applyb_ms / 1e6,
+                   "nrhs": [1, 256, 1024]},
+        "construct_ms": construct_ms, "apply": apply,
+        "apply1_ms": apply["c64_nrhs1"]["ms"], "apply1_c128_ms": apply["c128_nrhs1"]["ms"],
+        "applyn_ms": apply["c64_nrhs1024"]["ms"], "applyn_gflops": apply["c64_nrhs1024"]["gflops"],
+        "applyb_ms": apply["bf16x3_nrhs1024"]["ms"], "applyb_gflops": apply["bf16x3_nrhs1024"]["gflops"],
         "id_fp64_tflops": agg.get("id_qr", {}).get("flops", 0) / max(agg.get("id_qr", {}).get("ms", 1), 1e-9) / 1e9,
-        "rel_err_c64_vs_c128": rel64, "rel_err_bf16x3_vs_c128": relbf, "eps_a_256rows": eps_a,
-        "nnz": info["nnz_T"] + info["nnz_S"], "rank_max": info["rank_max"],
+        "rel_err_c64_vs_c128": errs["c64"], "rel_err_bf16x3_vs_c128": errs["bf16x3"], "eps_a_256rows": eps_a,
+        "nnz": nnz, "rank_max": info["rank_max"],
+        "rank_hist": _rank_hist(st),
+        "tall_ids": int(sum(row[s]["tall"] for row in st["per_level"] for s in "UV")),
         "kernels": {k: {"launches_per_step": v["launches"] / len(recs),
                         "ms_per_step": v["ms"] / len(recs)} for k, v in sorted(agg.items())},
         "roofline": roof,
         "roofline_apply1": None,
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
-    # 1-RHS apply roofline: the three stage kernels of one 1-RHS apply
-    a1 = [fac.apply(x1, y1)]
+    # 1-RHS apply roofline: the three stage kernels of one complex64 1-RHS apply
+    x1, y1b = xin[("c64", 1)], yout[("c64", 1)]
+    fac.apply(x1, y1b)
     torch.cuda.synchronize()
     fac.profile(reset=True)
-    fac.apply(x1, y1)
+    fac.apply(x1, y1b)
     p1 = fac.profile(reset=True)
     tb = sum(v["bytes"] for k, v in p1.items() if k.startswith("apply"))
     tm = sum(v["ms"] for k, v in p1.items() if k.startswith("apply"))
@@ -580,33 +751,25 @@ def main() -> int:
                               "traffic": _counted_traffic(APPLY1_COUNTERS, APPLY1_SOURCES,
                                                           "traffic_bytes_per_apply"),
                               "kernels": {k: v["ms"] for k, v in p1.items()}}
-    del a1
-    # adjoint apply y = K~^H x on the same factors (measured once): 1 RHS and
-    # the many-RHS matrix-core paths, with the adjoint identity as a check
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-    fac.apply_adjoint(x1, y1)
-    torch.cuda.synchronize()
-    ev[0].record(stream)
-    fac.apply_adjoint(x1, y1, stream=stream)
-    ev[1].record(stream)
-    ev[2].record(stream)
-    fac.apply_adjoint(XM, YM, stream=stream)
-    ev[3].record(stream)
-    ev[4].record(stream)
-    fac.apply_adjoint(XM, YM, dtype=B.C64_BF16X3, stream=stream)
-    ev[5].record(stream)
-    torch.cuda.synchronize()
+    # adjoint apply y = K~^H x on the same factors (measured once), with the
+    # adjoint identity as a check
+    adj = {}
+    for name, prec, nrhs in APPLY_KINDS:
+        if nrhs == 256:
+            continue
+        key = ("c128" if prec == "c128" else "c64", nrhs)
+        adj[name] = _event_ms(torch, stream, lambda: fac.apply_adjoint(xin[key], yout[key], dtype=dtypes[prec],
+                                                                       stream=stream))
     p0 = probes[:, 0].contiguous()
-    p1 = probes[:, 1].contiguous()
-    ident = abs(complex(torch.vdot(p1, fac.apply(p0)) - torch.vdot(fac.apply_adjoint(p1), p0)))
-    ident /= float(torch.linalg.norm(p1) * torch.linalg.norm(fac.apply(p0)))
-    adj1_ms, adjn_ms, adjb_ms = ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]), ev[4].elapsed_time(ev[5])
-    out["adjoint"] = {"apply1_ms": adj1_ms, "apply1_gbs": bytes1 / adj1_ms / 1e6,
-                      "applyn_ms": adjn_ms, "applyn_gflops": flops_n / adjn_ms / 1e6,
-                      "applyb_ms": adjb_ms, "applyb_gflops": flops_n / adjb_ms / 1e6,
-                      "identity_rel_err_c128": ident}
-    del XM, YM
+    pb = probes[:, 1].contiguous()
+    ident = abs(complex(torch.vdot(pb, fac.apply(p0)) - torch.vdot(fac.apply_adjoint(pb), p0)))
+    ident /= float(torch.linalg.norm(pb) * torch.linalg.norm(fac.apply(p0)))
+    out["adjoint"] = {"ms": adj, "identity_rel_err_c128": ident}
+    fac.close()
+    del xin, yout
     torch.cuda.empty_cache()
+    if not args.no_config2:
+        out["config2"] = _config2(B, torch, dev, stream)
     if not args.no_batched:
         side = torch.cuda.Stream()
         with torch.cuda.stream(side):
@@ -618,8 +781,6 @@ def main() -> int:
     if not args.no_examples:
         out["nufft"] = _example(B, torch, dev, stream, "nufft")
         out["schlomilch_j0"] = _example(B, torch, dev, stream, "j0")
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = _cpu_baseline()
     print(json.dumps(out), flush=True)
     return 0
 
