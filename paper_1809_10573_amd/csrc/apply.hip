@@ -705,7 +705,7 @@ hipError_t launch_v_shaped(const StageArgs& a, bool fp64, hipStream_t st) {
     if (fp64) hipLaunchKernelGGL((apply_v1<double2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((apply_v1<float2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
   } else {
-    if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
+    if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores (complex128 there too when A fits LDS)
     const size_t lds = (size_t)a.pmax * sizeof(double2);
     if (hipError_t e = allow_lds(apply_vn<double2, ADJ>, lds); e != hipSuccess) return e;
     hipLaunchKernelGGL((apply_vn<double2, ADJ>), gridn(a.n, a.nrhs), dim3(256), lds, st, a);
@@ -727,7 +727,7 @@ hipError_t launch_u_shaped(const StageArgs& a, bool fp64, hipStream_t st) {
     if (fp64) hipLaunchKernelGGL((apply_u1<double2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((apply_u1<float2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
   } else {
-    if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
+    if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores (complex128 there too when A fits LDS)
     const size_t lds = 2 * (size_t)a.pmax * sizeof(double2);
     if (hipError_t e = allow_lds(apply_un<double2, ADJ>, lds); e != hipSuccess) return e;
     hipLaunchKernelGGL((apply_un<double2, ADJ>), gridn(a.n, a.nrhs), dim3(256), lds, st, a);
@@ -745,7 +745,7 @@ hipError_t launch_s_stage(const StageArgs& a, bool fp64, hipStream_t st) {
     if (fp64) hipLaunchKernelGGL((apply_s1<double2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
     else hipLaunchKernelGGL((apply_s1<float2, ADJ>), dim3(grid1(a.n)), dim3(256), 0, st, a);
   } else {
-    if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores
+    if (!fp64) return hipErrorInvalidValue;  // complex64 runs on the matrix cores (complex128 there too when A fits LDS)
     const size_t lds = (size_t)a.pmax * sizeof(double2);
     if (hipError_t e = allow_lds(apply_sn<double2, ADJ>, lds); e != hipSuccess) return e;
     hipLaunchKernelGGL((apply_sn<double2, ADJ>), gridn(a.n, a.nrhs), dim3(256), lds, st, a);

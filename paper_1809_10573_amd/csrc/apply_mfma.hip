@@ -20,8 +20,10 @@
 // sides (4 real columns): real column 4 j + t of the wave's block belongs to
 // N-tile t, so B~ is a register shuffle, never a cross-lane move.
 //
-// Precision: FP32 MFMA (v_mfma_f32_16x16x4_f32, 16-row M tiles, one
-// wavefront over all M tiles of a unit), or the BF16 hi/lo split
+// Precision: FP64 MFMA for complex128 data (v_mfma_f64_16x16x4_f64, the
+// FP32 layout with one complex right-hand side per lane), FP32 MFMA
+// (v_mfma_f32_16x16x4_f32, 16-row M tiles, one wavefront over all M tiles of
+// a unit), or the BF16 hi/lo split
 // a ~= a_hi + a_lo with a b ~= a_hi b_hi + a_hi b_lo + a_lo b_hi on
 // v_mfma_f32_32x32x16_bf16 (32-row M tiles), FP32 accumulation.  A unit's A
 // is staged once per workgroup and serves up to 1024 right-hand sides.
@@ -61,10 +63,14 @@ __device__ __forceinline__ int lda_for(int K) { return ((K + 15) & ~15) + 2; }
 // ADJ (the adjoint, stages in reverse): a V-shaped unit over the U ID pair
 // of one segment, A = [P_0 P_1]^H; a U-shaped unit over the V ID pair of one
 // segment, A = ([I T_0]; [I T_1])^H; S^H per V_H ID, A = [S(R_1, C')^H ...].
-template <int MODE, bool ADJ>
-__device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_out, int* s_red) {
+__device__ __forceinline__ float2 cplx(float2, float re, float im) { return make_float2(re, im); }
+__device__ __forceinline__ double2 cplx(double2, double re, double im) { return make_double2(re, im); }
+
+template <int MODE, bool ADJ, typename C = float2>
+__device__ Unit stage_unit(const StageArgs& A, C* s_A, int* s_src, int* s_out, int* s_red) {
   const int64_t q = blockIdx.x;
-  const float2* T = static_cast<const float2*>(A.T);
+  const C* T = static_cast<const C*>(A.T);
+  const C zero = cplx(C{}, 0.f, 0.f), one = cplx(C{}, 1.f, 0.f);
   Unit u{};
   if constexpr (MODE == kModeS) {
     const int64_t b0 = middle_block<ADJ>(A, q, 0);
@@ -76,7 +82,7 @@ __device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_o
     }
     u = Unit{ol, K};
     const int lda = lda_for(K);
-    for (int e = threadIdx.x; e < A.gemm_rows * lda; e += blockDim.x) s_A[e] = make_float2(0.f, 0.f);
+    for (int e = threadIdx.x; e < A.gemm_rows * lda; e += blockDim.x) s_A[e] = zero;
     for (int i = threadIdx.x; i < ol; i += blockDim.x) s_out[i] = obg + i;
     __syncthreads();
     int off = 0;
@@ -87,8 +93,8 @@ __device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_o
       const int64_t so = A.T_off[b];
       for (int l = threadIdx.x; l < il; l += blockDim.x) s_src[off + l] = ibg + l;
       for (int e = threadIdx.x; e < rl * cl; e += blockDim.x) {
-        const float2 v = T[so + e];  // S(e % rl, e / rl)
-        if (ADJ) s_A[(e / rl) * lda + off + e % rl] = make_float2(v.x, -v.y);
+        const C v = T[so + e];  // S(e % rl, e / rl)
+        if (ADJ) s_A[(e / rl) * lda + off + e % rl] = cplx(C{}, v.x, -v.y);
         else s_A[(e % rl) * lda + off + e / rl] = v;
       }
       off += il;
@@ -101,7 +107,7 @@ __device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_o
     const bool isV = (MODE == kModeV);
     u = isV ? Unit{k0 + m1.k, c} : Unit{c, k0 + m1.k};
     const int lda = lda_for(u.K);
-    for (int e = threadIdx.x; e < A.gemm_rows * lda; e += blockDim.x) s_A[e] = make_float2(0.f, 0.f);
+    for (int e = threadIdx.x; e < A.gemm_rows * lda; e += blockDim.x) s_A[e] = zero;
     __syncthreads();  // zero fill before the identity entries
     for (int e = threadIdx.x; e < 2 * kMaxMg; e += blockDim.x) {  // (ID h, candidate position l)
       const int h = e / kMaxMg, l = e % kMaxMg;
@@ -119,8 +125,8 @@ __device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_o
         const int below = l < 64 ? __popcll(m.mask & lanes_below(l))
                                  : __popcll(m.mask) + __popcll(m.mask_hi & lanes_below(l - 64));
         if (l < 64 ? ((m.mask >> l) & 1ull) : ((m.mask_hi >> (l - 64)) & 1ull)) {
-          if (isV) s_A[(base + below) * lda + l] = make_float2(1.f, 0.f);
-          else s_A[l * lda + base + below] = make_float2(1.f, 0.f);
+          if (isV) s_A[(base + below) * lda + l] = one;
+          else s_A[l * lda + base + below] = one;
         } else {
           s_red[h * kMaxMg + l - below] = l;
         }
@@ -135,7 +141,7 @@ __device__ Unit stage_unit(const StageArgs& A, float2* s_A, int* s_src, int* s_o
       const int k = m.k, r = c - k, base = h ? k0 : 0;
       for (int e = threadIdx.x; e < k * r; e += blockDim.x) {
         const int i = colmajor ? e % k : e / r, j = colmajor ? e / k : e % r;
-        float2 v = T[m.t_off + e];
+        C v = T[m.t_off + e];
         if (ADJ) v.y = -v.y;
         if (isV) s_A[(base + i) * lda + s_red[h * kMaxMg + j]] = v;
         else s_A[s_red[h * kMaxMg + j] * lda + base + i] = v;
@@ -324,13 +330,122 @@ __global__ __launch_bounds__(64 * kWavesG16) void apply_gemm16(StageArgs A) {
   }
 }
 
+// FP64 on v_mfma_f64_16x16x4_f64 (complex128 data): the FP32 kernel's
+// operand layout with one complex right-hand side per lane, so a wavefront
+// covers 16 right-hand sides in two N-tiles (real and imaginary parts); lane
+// (kq, c) feeds K index kc + kq and right-hand side rhs0 + c.  The f64
+// instruction orders D differently from the f32 one: register v of lane
+// (kq, c) holds row 4 v + kq, column c, i.e. output row 16 mt + 4 v + kq,
+// part t of tile t.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kRhsPerWaveD = 16;
+constexpr int kRhsIterD = 16;  // right-hand-side blocks per wavefront: A serves kRhsIterD kWavesG16 blocks
+
+template <int MODE, bool ADJ, int TM>
+__global__ __launch_bounds__(64 * kWavesG16) void apply_gemm16d(StageArgs A) {
+  extern __shared__ __attribute__((aligned(16))) double2 s_Ad[];
+  __shared__ int s_src[kMaxKg];
+  __shared__ int s_out[kMaxMg];
+  __shared__ int s_red[2 * kMaxMg];
+  const Unit u = stage_unit<MODE, ADJ, double2>(A, s_Ad, s_src, s_out, s_red);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int kq = lane >> 4, c16 = lane & 15;
+  const int tiles = (u.M + 15) / 16;  // <= TM
+  const int lda = lda_for(u.K);
+  const int64_t nr = A.nrhs;
+  const double2* in = static_cast<const double2*>(A.in);
+  double2* out = static_cast<double2*>(A.out);
+  for (int it = 0; it < kRhsIterD; ++it) {
+    const int64_t rhs0 = ((blockIdx.y * (int64_t)kRhsIterD + it) * kWavesG16 + w) * kRhsPerWaveD;
+    if (rhs0 >= nr) return;
+    const int64_t n0 = rhs0 + c16;
+    const bool ok = n0 < nr;
+    f64x4 acc[TM][2];
+#pragma unroll
+    for (int mt = 0; mt < TM; ++mt)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[mt][t] = f64x4{};
+    for (int kc = 0; kc < u.K; kc += 16) {
+      double2 b[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int kk = kc + 4 * e + kq;
+        const int row = kk < u.K ? s_src[kk] : -1;
+        b[e] = (row >= 0 && ok) ? in[(int64_t)row * nr + n0] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (kc + 4 * e >= u.K) break;  // K steps of 4 wholly past K add nothing
+        const double bt[2] = {b[e].x, b[e].y};
+        const double bs[2] = {-b[e].y, b[e].x};
+#pragma unroll
+        for (int mt = 0; mt < TM; ++mt) {
+          if (mt >= tiles) break;
+          const double2 av = s_Ad[(mt * 16 + c16) * lda + kc + 4 * e + kq];  // zero past K (padded to 16)
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bt[t], acc[mt][t], 0, 0, 0);
+            acc[mt][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bs[t], acc[mt][t], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int mt = 0; mt < TM; ++mt) {
+      if (mt >= tiles) break;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = mt * 16 + 4 * v + kq;  // the f64 instruction's D: register v holds row 4 v + lane / 16
+        if (i >= u.M || !ok) continue;
+        out[(int64_t)s_out[i] * nr + n0] = make_double2(acc[mt][0][v], acc[mt][1][v]);
+      }
+    }
+  }
+}
+
 }  // namespace
 
-hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int mmax_unit, bool bf16,
+size_t gemm_lds_bytes(int kmax_unit, int mmax_unit, int prec) {
+  const int rows = prec == kGemmBf16 ? ((mmax_unit + 31) & ~31) : ((mmax_unit + 15) & ~15);
+  const size_t elem = prec == kGemmF64 ? sizeof(double2) : sizeof(float2);
+  return (size_t)rows * (size_t)(((kmax_unit + 15) & ~15) + 2) * elem;
+}
+
+hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int mmax_unit, int prec,
                              hipStream_t st, bool adj) {
   if (a0.n <= 0 || a0.nrhs <= 0) return hipSuccess;
   if (kmax_unit < 1 || kmax_unit > kMaxKg || mmax_unit < 1 || mmax_unit > kMaxMg) return hipErrorInvalidValue;
+  if (gemm_lds_bytes(kmax_unit, mmax_unit, prec) > kMaxGemmLds) return hipErrorInvalidValue;
   StageArgs a = a0;
+  const bool bf16 = prec == kGemmBf16;
+  if (prec == kGemmF64) {  // FP64: the FP32 kernel's layout, 16 right-hand sides per wavefront
+    a.gemm_rows = (mmax_unit + 15) & ~15;
+    const int64_t per_block = (int64_t)kRhsIterD * kWavesG16 * kRhsPerWaveD;
+    const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
+    const size_t lds = gemm_lds_bytes(kmax_unit, mmax_unit, prec);
+#define IDBF_GEMM16D(M, J, TM)                                                                       \
+  do {                                                                                               \
+    if (lds > (size_t(64) << 10)) {                                                                  \
+      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_gemm16d<M, J, TM>),   \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
+      if (e_ != hipSuccess) return e_;                                                               \
+    }                                                                                                \
+    hipLaunchKernelGGL((apply_gemm16d<M, J, TM>), grid, dim3(64 * kWavesG16), lds, st, a);           \
+  } while (0)
+#define IDBF_GEMM16D_TM(M, J)                                                                        \
+  do {                                                                                               \
+    if (a.gemm_rows <= 64) IDBF_GEMM16D(M, J, 4); else IDBF_GEMM16D(M, J, 8);                        \
+  } while (0)
+    switch (mode) {
+      case kModeV: if (adj) IDBF_GEMM16D_TM(kModeV, true); else IDBF_GEMM16D_TM(kModeV, false); break;
+      case kModeS: if (adj) IDBF_GEMM16D_TM(kModeS, true); else IDBF_GEMM16D_TM(kModeS, false); break;
+      default: if (adj) IDBF_GEMM16D_TM(kModeU, true); else IDBF_GEMM16D_TM(kModeU, false); break;
+    }
+#undef IDBF_GEMM16D_TM
+#undef IDBF_GEMM16D
+    return hipGetLastError();
+  }
   if (!bf16) {  // FP32: 16-row tiles, one wavefront per 32 right-hand sides over all of them
     a.gemm_rows = (mmax_unit + 15) & ~15;
     const int64_t per_block = (int64_t)kRhsIter16 * kWavesG16 * kRhsPerWave16;

@@ -1308,7 +1308,14 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
   }
   const bool fp64 = dtype == IDBF_C128;
   const bool bf16 = dtype == IDBF_C64_BF16X3;
-  const bool mfma = bf16 || (!fp64 && nrhs > 1);  // matrix-core stage kernels
+  // matrix-core stage kernels for more than one right-hand side (FP64 MFMA on
+  // complex128, FP32 or BF16 split on complex64); a complex128 stage whose A
+  // does not fit LDS runs on the VALU kernels
+  const bool mfma = bf16 || nrhs > 1;
+  const int prec = bf16 ? kGemmBf16 : fp64 ? kGemmF64 : kGemmF32;
+  auto fits = [&](int kmax_unit, int mmax_unit) {
+    return prec != kGemmF64 || gemm_lds_bytes(kmax_unit, mmax_unit, prec) <= kMaxGemmLds;
+  };
   const size_t elem = fp64 ? 16 : 8;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t half = size_t(h->max_skel) * size_t(nrhs) * elem;
@@ -1351,11 +1358,11 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     a.out = buf[cur];
     const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
     const int pr = h->prof.begin(name(adj ? 'u' : 'v'), st);
-    if (mfma) {  // units: the ID pairs (C, 2P), (C, 2P + 1) that share a candidate segment
+    if (mfma && fits(b.cand_max, 2 * b.rank_max)) {  // units: the ID pairs (C, 2P), (C, 2P + 1) sharing a segment
       StageArgs g = a;
       g.n = b.n / 2;
       g.nn = 1 << (h->L - t + 1);
-      IDBF_HIP_CHECK(launch_apply_gemm(g, 0, b.cand_max, 2 * b.rank_max, bf16, st, adj));
+      IDBF_HIP_CHECK(launch_apply_gemm(g, 0, b.cand_max, 2 * b.rank_max, prec, st, adj));
     } else {
       IDBF_HIP_CHECK(launch_apply_v(a, fp64, st, adj));
     }
@@ -1383,10 +1390,10 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     double bytes = double(h->nnz_S) * elem;
     if (h->H == 0) bytes += 2.0 * double(h->N) * nrhs * elem;
     const int pr = h->prof.begin(name('s'), st);
-    if (mfma && !a.dense) {
-      const int kin = adj ? h->U[h->H - 1].rank_max : h->V[h->H - 1].rank_max;
-      const int mout = adj ? h->V[h->H - 1].rank_max : h->U[h->H - 1].rank_max;
-      IDBF_HIP_CHECK(launch_apply_gemm(a, 1, a.nsub * kin, mout, bf16, st, adj));
+    const int kin = h->H == 0 ? 0 : adj ? h->U[h->H - 1].rank_max : h->V[h->H - 1].rank_max;
+    const int mout = h->H == 0 ? 0 : adj ? h->V[h->H - 1].rank_max : h->U[h->H - 1].rank_max;
+    if (mfma && !a.dense && fits(a.nsub * kin, mout)) {
+      IDBF_HIP_CHECK(launch_apply_gemm(a, 1, a.nsub * kin, mout, prec, st, adj));
     } else {
       IDBF_HIP_CHECK(launch_apply_s(a, fp64, st, adj));
     }
@@ -1404,7 +1411,8 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     a.out = (t == 1) ? y : buf[cur];
     const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
     const int pr = h->prof.begin(name(adj ? 'v' : 'u'), st);
-    if (mfma) IDBF_HIP_CHECK(launch_apply_gemm(a, 2, 2 * b.rank_max, b.cand_max, bf16, st, adj));
+    if (mfma && fits(2 * b.rank_max, b.cand_max))
+      IDBF_HIP_CHECK(launch_apply_gemm(a, 2, 2 * b.rank_max, b.cand_max, prec, st, adj));
     else IDBF_HIP_CHECK(launch_apply_u(a, fp64, st, adj));
     h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T) * nrhs);
     in = a.out;

@@ -278,10 +278,16 @@ __device__ __forceinline__ int64_t middle_block(const StageArgs& A, int64_t q, i
 hipError_t launch_apply_v(const StageArgs& a, bool fp64, hipStream_t st, bool adj = false);
 hipError_t launch_apply_u(const StageArgs& a, bool fp64, hipStream_t st, bool adj = false);
 hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st, bool adj = false);
-// matrix-core stage kernels (complex64 data): mode 0 V, 1 S, 2 U (the shape,
-// as above, with adj selecting the adjoint of the other factor); kmax_unit
-// and mmax_unit bound the K and M of every unit of the stage (size the LDS of A)
-hipError_t launch_apply_gemm(const StageArgs& a, int mode, int kmax_unit, int mmax_unit, bool bf16,
+// matrix-core stage kernels: mode 0 V, 1 S, 2 U (the shape, as above, with
+// adj selecting the adjoint of the other factor); kmax_unit and mmax_unit
+// bound the K and M of every unit of the stage (size the LDS of A); prec:
+// FP32 or BF16 split on complex64 data, FP64 on complex128 data.  A stage
+// whose A would need more than kMaxGemmLds bytes of LDS is refused
+// (hipErrorInvalidValue): gemm_lds_bytes tells beforehand.
+enum { kGemmF32 = 0, kGemmBf16 = 1, kGemmF64 = 2 };
+constexpr size_t kMaxGemmLds = size_t(156) << 10;  // 160 KB less the kernels' static arrays
+size_t gemm_lds_bytes(int kmax_unit, int mmax_unit, int prec);
+hipError_t launch_apply_gemm(const StageArgs& a, int mode, int kmax_unit, int mmax_unit, int prec,
                              hipStream_t st, bool adj = false);
 
 }  // namespace idbf
