@@ -102,6 +102,17 @@ typedef struct idbf_opts {
   int32_t proposal_margin;
   int32_t reserved2;
   uint64_t seed;
+  /* Skeleton proposal (not in the paper), or NULL; needs opts.proposer.  A
+   * second network of the same form scores every candidate of every ID
+   * (features: level, side, node centres, a, m, the candidate's position in
+   * its set and its relative coordinate); the k_p = min(c, 64, ceil(k^) +
+   * 2 proposal_margin) best form the ID's proposed set, and the pivot search
+   * of the column-pivoted QR on the s' samples runs over that set only (the
+   * eps-rank threshold still taken against the block's largest column norm;
+   * T = R11^{-1} R12 for every other candidate).  Every such ID goes through
+   * the residual test, and is rejected if no proposed column is above the
+   * threshold; the plain pivoted ID replaces the rejected ones. */
+  struct idbf_mlp_s* skeleton_proposer;
 } idbf_opts;
 
 typedef struct idbf_handle_s* idbf_handle;
@@ -450,6 +461,20 @@ idbf_status idbf_mlp_loss_grad(idbf_mlp m, const float* X, const float* y, int64
 idbf_status idbf_mlp_train(idbf_mlp m, const float* X, const float* y, int64_t n, int32_t epochs, int32_t batch,
                            float lr, uint64_t seed, float* loss_per_epoch, void* stream);
 idbf_status idbf_rank_samples(idbf_handle h, int32_t side, int32_t level, float* features, float* targets);
+/* Training data of the skeleton network from a built handle: *cmax (host)
+ * receives the level's largest candidate count; with features and targets
+ * (device, n_ids * cmax * 8 and n_ids * cmax floats) given, row q * cmax + l
+ * holds the features of candidate l of ID q and target 1 (a skeleton of the
+ * plain construction) or 0, and -1 for l >= cand_len[q] (padding).
+ * Synchronizes the handle's stream. */
+idbf_status idbf_skeleton_samples(idbf_handle h, int32_t side, int32_t level, int32_t* cmax, float* features,
+                                  float* targets);
+/* The proposed skeleton sets of one level (host arrays, nullable): n_prop[q]
+ * proposed columns of ID q, order[q * 64 + j] the j-th of them (candidate
+ * position, best score first, j < n_prop[q]).  IDBF_EINVAL without a
+ * skeleton proposer.  Synchronizes the handle's stream. */
+idbf_status idbf_batch_skeleton_proposal(idbf_handle h, int32_t side, int32_t level, int32_t* n_prop,
+                                        uint8_t* order);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,8 @@ to be checked against the paper by eye:
 * ``interp``   -- the interpolative decomposition by column-pivoted Householder
                   QR of Lemma 2.1 and the epsilon-rank / truncated interpolation
                   solve of Section 2.1 (eqs. pivotedQR2, acc, R2); row IDs as
-                  column IDs of the transpose.
+                  column IDs of the transpose; the ID on a given skeleton
+                  (the learned proposal's accept path).
 * ``sampling`` -- Mock-Chebyshev sample selection (Section 2.1).
 * ``idbf``     -- the level-by-level construction (LRCS, MSCS, recursive MSCS
                   of Sections 2.2-2.4) and the factor-by-factor apply

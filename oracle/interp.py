@@ -53,25 +53,39 @@ class ColumnID:
         return len(self.skel)
 
 
-def column_id(B, tol: float, kmax: int = 0) -> ColumnID:
-    """(tol, kmax)-cID of B by column-pivoted Householder QR (Lemma 2.1, eqs. acc, R2)."""
+def column_id(B, tol: float, kmax: int = 0, among=None) -> ColumnID:
+    """(tol, kmax)-cID of B by column-pivoted Householder QR (Lemma 2.1, eqs. acc, R2).
+
+    ``among`` (positions; the learned skeleton proposal, not in the paper)
+    restricts the pivot search to those columns: the same steps, the
+    eps-rank rule still taken against the largest column norm of all of B
+    (|R_00| of the unrestricted QR), and at most len(among) steps.  If no
+    column of ``among`` is above that threshold the proposal is unusable:
+    None."""
     R = np.array(B, dtype=np.complex128, copy=True)
     s, c = R.shape
     if s == 0 or c == 0:
         raise ValueError("column_id needs a non-empty matrix")
     kcap = min(s, c) if kmax <= 0 else min(s, c, kmax)
+    if among is not None:
+        among = np.asarray(among, dtype=np.int64)
+        if len(among) < 1 or len(np.unique(among)) != len(among) or among.min() < 0 or among.max() >= c:
+            raise ValueError("among must name distinct columns of B")
+        kcap = min(kcap, len(among))
     order = np.arange(c)           # order[p]: original position of the column now at p
     r00 = 0.0
     rdiag = []
     k = 0
     for j in range(kcap):
         nu = np.linalg.norm(R[j:, j:], axis=0)          # residual norms of columns j..c-1
-        M = nu.max()
         if j == 0:
-            r00 = M
-            if M == 0.0:
+            r00 = nu.max()
+            if r00 == 0.0:
                 break
-        elif M <= tol * r00:
+        if among is not None:
+            nu = np.where(np.isin(order[j:], among), nu, -1.0)
+        M = nu.max()
+        if (j > 0 or among is not None) and M <= tol * r00:
             break
         near = np.nonzero(nu >= (1.0 - PIVOT_TIE_REL) * M)[0]
         p = j + near[np.argmin(order[j + near])]
@@ -92,8 +106,10 @@ def column_id(B, tol: float, kmax: int = 0) -> ColumnID:
         R[j + 1:, j] = 0.0
         rdiag.append(abs(alpha))
         k = j + 1
-    if k == 0:                      # all-zero block: keep the first column, T = 0
-        skel = np.array([0])
+    if k == 0:
+        if r00 > 0.0:               # a restriction none of whose columns is kept
+            return None
+        skel = np.array([0])        # all-zero block: keep the first column, T = 0
         red = np.arange(1, c)
         return ColumnID(skel, red, np.zeros((1, c - 1), dtype=np.complex128),
                         np.array([0]), np.array([0.0]))

@@ -32,7 +32,7 @@ EXPORTED = [
     "idbf_mlp_destroy", "idbf_mlp_params", "idbf_mlp_forward", "idbf_mlp_loss_grad", "idbf_mlp_train",
     "idbf_rank_samples", "idbf_apply_batched_plan", "idbf_plan_launch", "idbf_plan_destroy",
     "idbf_apply_adjoint", "idbf_release_cached_memory", "idbf_stats", "idbf_batch_proposal",
-    "idbf_apply_noalloc",
+    "idbf_apply_noalloc", "idbf_skeleton_samples", "idbf_batch_skeleton_proposal",
 ]
 MLP_INPUTS = 8
 FLAG_PROFILE, FLAG_PROPOSER_FORCE_REJECT, FLAG_ALLOW_TRUNCATE = 1, 2, 4
@@ -63,7 +63,7 @@ class Opts_t(C.Structure):
     _fields_ = [("kmax", C.c_int32), ("oversample", C.c_int32), ("flags", C.c_int32),
                 ("sampler", C.c_int32), ("mem_cap_bytes", C.c_uint64), ("stream", C.c_void_p),
                 ("proposer", C.c_void_p), ("proposal_margin", C.c_int32), ("reserved2", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("skeleton_proposer", C.c_void_p)]
 
 
 class Info_t(C.Structure):
@@ -142,6 +142,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_mlp_loss_grad.argtypes = [VP, VP, VP, I64, VP, P(F32), VP]
     lib.idbf_mlp_train.argtypes = [VP, VP, VP, I64, I32, I32, F32, C.c_uint64, VP, VP]
     lib.idbf_rank_samples.argtypes = [VP, I32, I32, VP, VP]
+    lib.idbf_skeleton_samples.argtypes = [VP, I32, I32, P(I32), VP, VP]
+    lib.idbf_batch_skeleton_proposal.argtypes = [VP, I32, I32, VP, VP]
     lib.idbf_apply_batched_plan.argtypes = [I32, P(VP), P(VP), P(VP), P(I64), I32, VP, P(VP)]
     lib.idbf_plan_launch.argtypes = [VP, VP]
     lib.idbf_plan_destroy.argtypes = [VP]
@@ -322,6 +324,16 @@ class Factorization:
         _check(lib.idbf_batch_proposal(self._h, side, level, *[a.ctypes.data for a in out]))
         return tuple(out)
 
+    def skeleton_proposal(self, side: int, level: int):
+        """(n_prop, order (n, 64) uint8): the proposed skeleton sets of one level (idbf_batch_skeleton_proposal)."""
+        lib = load()
+        n = C.c_int64()
+        _check(lib.idbf_batch_sizes(self._h, side, level, C.byref(n), None, None))
+        k = np.zeros(n.value, np.int32)
+        order = np.zeros((n.value, MAX_RANK), np.uint8)
+        _check(lib.idbf_batch_skeleton_proposal(self._h, side, level, k.ctypes.data, order.ctypes.data))
+        return k, order
+
     def profile(self, reset: bool = True) -> dict:
         """{kernel name: {launches, ms, bytes, flops}} since the last reset (IDBF_FLAG_PROFILE)."""
         arr = (KernelStat_t * 64)()
@@ -350,7 +362,7 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
               mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
               stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0,
               sampler: int = SAMPLER_MOCKCHEB, force_reject: bool = False,
-              allow_truncate: bool = False) -> Factorization:
+              allow_truncate: bool = False, skeleton_proposer=None) -> Factorization:
     """idbf_construct on device copies of X and Omega (float64, ascending)."""
     lib = load()
     Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
@@ -364,6 +376,8 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
     opts.sampler, opts.seed = int(sampler), int(seed)
     if proposer is not None:
         opts.proposer, opts.proposal_margin = proposer._h.value, int(proposal_margin)
+    if skeleton_proposer is not None:
+        opts.skeleton_proposer = skeleton_proposer._h.value
     ph = _phase(phase)
     h = C.c_void_p()
     _check(lib.idbf_construct(C.byref(ph), _ptr(Xd), _ptr(Od), Xd.numel(), float(tol), int(leaf),
@@ -375,7 +389,7 @@ def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample
                       mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
                       stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0,
                       sampler: int = SAMPLER_MOCKCHEB, force_reject: bool = False,
-                      allow_truncate: bool = False) -> list:
+                      allow_truncate: bool = False, skeleton_proposer=None) -> list:
     """idbf_construct_batched: one lockstep construction of len(phases) instances."""
     lib = load()
     n = len(phases)
@@ -394,6 +408,8 @@ def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample
     opts.sampler, opts.seed = int(sampler), int(seed)
     if proposer is not None:
         opts.proposer, opts.proposal_margin = proposer._h.value, int(proposal_margin)
+    if skeleton_proposer is not None:
+        opts.skeleton_proposer = skeleton_proposer._h.value
     ph = (Phase_t * n)(*[_phase(p) for p in phases])
     xp = (C.c_void_p * n)(*[_ptr(x) for x in Xd])
     op = (C.c_void_p * n)(*[_ptr(o) for o in Od])
@@ -549,6 +565,23 @@ def rank_samples(fac: Factorization, side: int, level: int, device="cuda"):
     t = torch.empty(n.value, dtype=torch.float32, device=device)
     _check(load().idbf_rank_samples(fac._h, side, level, _ptr(F), _ptr(t)))
     return F, t
+
+
+def skeleton_samples(fac: Factorization, side: int, level: int, device="cuda"):
+    """(features (rows, 8), targets (rows,)) float32 device tensors: one row per
+    (ID, candidate) of one level, target 1 for a skeleton of the plain
+    construction and 0 otherwise (idbf_skeleton_samples, padding removed)."""
+    import torch
+    lib = load()
+    n = C.c_int64()
+    _check(lib.idbf_batch_sizes(fac._h, side, level, C.byref(n), None, None))
+    cmax = C.c_int32()
+    _check(lib.idbf_skeleton_samples(fac._h, side, level, C.byref(cmax), None, None))
+    F = torch.empty((n.value * cmax.value, MLP_INPUTS), dtype=torch.float32, device=device)
+    t = torch.empty(n.value * cmax.value, dtype=torch.float32, device=device)
+    _check(lib.idbf_skeleton_samples(fac._h, side, level, C.byref(cmax), _ptr(F), _ptr(t)))
+    keep = t >= 0
+    return F[keep], t[keep]
 
 
 def sample(phase, X, Omega, rows, cols, device="cuda", stream=None):

@@ -234,6 +234,9 @@ struct Batch {
   // learned proposal
   int32_t* s_prop = nullptr;   // sample counts the IDs used (proposal, or plain when rejected)
   int32_t* s_first = nullptr;  // the proposed counts, before the residual test
+  float* y_rank = nullptr;     // the rank network's outputs (rank / 16)
+  int32_t* prop_k = nullptr;     // skeleton proposal: number of proposed columns ...
+  uint8_t* prop_cols = nullptr;  // ... and their positions, kMaxRank per ID
   int32_t* reject = nullptr;   // 1: proposal rejected by the residual test
   int64_t rejected = 0;
   int64_t tall = 0;               // IDs row-reduced before their QR (first pass)
@@ -407,6 +410,7 @@ struct idbf_handle_s {
   LevelJob job;                // the level batch being built
   int qr_rec = -1;             // profiler record of that batch's QR launches
   idbf_mlp_s* proposer = nullptr;  // rank proposal network (not owned), or null
+  idbf_mlp_s* skel_proposer = nullptr;  // skeleton proposal network (not owned), or null
   int sampler = IDBF_SAMPLER_MOCKCHEB;
   int margin = 0;
   uint64_t seed = 0;
@@ -508,6 +512,7 @@ idbf_status level_begin(idbf_handle_s* h, const double* X, const double* Om, int
     float *F = nullptr, *y = nullptr;
     TRY(A.get(n * kProposalInputs, &F));
     TRY(A.get(n, &y));
+    b.y_rank = y;
     TRY(A.get(n, &b.s_prop));
     TRY(A.get(n, &b.s_first));
     TRY(A.get(n, &b.reject));
@@ -559,9 +564,10 @@ idbf_status grow_tmp(idbf_handle_s* h, size_t bytes) {
   return IDBF_OK;
 }
 
-idbf_status level_scratch(idbf_handle_s* h, IdArgs& ia, int64_t n, int s_max, int c_max, int64_t n_tall) {
+idbf_status level_scratch(idbf_handle_s* h, IdArgs& ia, int64_t n, int s_max, int c_max, int64_t n_tall,
+                          size_t extra = 0, void** extra_ptr = nullptr) {
   const int64_t ld = std::max(1, s_max);
-  size_t bytes = ((size_t(n) * ld * 4 + 255) & ~size_t(255));
+  size_t bytes = ((size_t(n) * ld * 4 + 255) & ~size_t(255)) + ((extra + 255) & ~size_t(255));
   size_t chunk = 0, slot_b = 0, R_b = 0;
   if (n_tall > 0) {
     const size_t work_ld = size_t(s_max) * c_max;
@@ -572,6 +578,8 @@ idbf_status level_scratch(idbf_handle_s* h, IdArgs& ia, int64_t n, int s_max, in
   }
   TRY(grow_tmp(h, bytes));
   char* p = static_cast<char*>(h->tmp);
+  if (extra_ptr) *extra_ptr = p;
+  p += (extra + 255) & ~size_t(255);
   ia.samp_pos = reinterpret_cast<int32_t*>(p);
   ia.samp_ld = ld;
   p += (size_t(n) * ld * 4 + 255) & ~size_t(255);
@@ -639,7 +647,28 @@ idbf_status level_ids(idbf_handle_s* h) {
   ia.level = t;
   ia.seed = h->seed;
   b.tall = (int64_t)h->pin->counts[kQrBuckets];
-  TRY(level_scratch(h, ia, n, b.s_max, b.cand_max, b.tall));
+  // skeleton proposal: candidate features and scores in the level scratch
+  const size_t sk_bytes = h->skel_proposer ? size_t(n) * b.cand_max * (kProposalInputs + 1) * sizeof(float) : 0;
+  void* sk = nullptr;
+  TRY(level_scratch(h, ia, n, b.s_max, b.cand_max, b.tall, sk_bytes, &sk));
+  if (h->skel_proposer) {
+    float* F = static_cast<float*>(sk);
+    float* score = F + size_t(n) * b.cand_max * kProposalInputs;
+    TRY(A.get(n, &b.prop_k));
+    TRY(A.get(n * kMaxRank, &b.prop_cols));
+    const int pr = h->prof.begin("skel_propose", h->stream);
+    TRYHIP(launch_cand_features(n, h->L, t, side == IDBF_SIDE_U ? 0 : 1, h->ph, b.cand_beg, b.cand_len,
+                                b.cand_coord, b.cand_max, F, h->stream));
+    TRYHIP(launch_mlp_forward(h->skel_proposer->P, kProposalInputs, h->skel_proposer->hidden, F,
+                              n * b.cand_max, score, nullptr, nullptr, h->stream));
+    TRYHIP(launch_pick_skeletons(score, b.cand_max, b.y_rank, b.s_prop, b.cand_len, n, h->margin, b.prop_k,
+                                 b.prop_cols, h->stream));
+    h->prof.end(pr, h->stream);
+    ia.prop_k = b.prop_k;
+    ia.prop_cols = b.prop_cols;
+    ia.prop_fail = b.reject;  // read back by the residual test
+    TRYHIP(hipMemsetAsync(b.reject, 0, size_t(n) * sizeof(int32_t), h->stream));
+  }
   ia.order = h->order;
   ia.bucket_off[0] = 0;
   for (int w = 0; w < kQrBuckets; ++w) ia.bucket_off[w + 1] = ia.bucket_off[w] + (int64_t)h->pin->counts[w];
@@ -674,6 +703,7 @@ idbf_status level_ids(idbf_handle_s* h) {
     ra.seed = h->seed;
     ra.factor = 10.0;
     ra.force_reject = h->force_reject;
+    ra.skeletons = h->skel_proposer != nullptr;
     ra.reject = b.reject;
     ra.s_prop = b.s_prop;
     ra.samples_plain = b.samples;
@@ -693,6 +723,9 @@ idbf_status level_fallback(idbf_handle_s* h) {
   LevelJob& J = h->job;
   Batch& b = J.b;
   IdArgs ia = J.ia;
+  ia.prop_k = nullptr;  // the fallback is the plain pivoted ID
+  ia.prop_cols = nullptr;
+  ia.prop_fail = nullptr;
   ia.bucket_off[0] = 0;
   for (int w = 0; w < kQrBuckets; ++w) ia.bucket_off[w + 1] = ia.bucket_off[w] + (int64_t)h->pin->counts[w];
   b.rejected = ia.bucket_off[kQrBuckets];
@@ -1068,6 +1101,11 @@ idbf_status make_handle(const idbf_phase* phase, const double* X, const double* 
   h->force_reject = (o.flags & IDBF_FLAG_PROPOSER_FORCE_REJECT) != 0;
   h->truncate = (o.flags & IDBF_FLAG_ALLOW_TRUNCATE) != 0;
   h->proposer = o.proposer;
+  h->skel_proposer = o.skeleton_proposer;
+  if (h->skel_proposer && !h->proposer) {
+    set_error("opts: a skeleton proposer needs a rank proposer (opts.proposer)");
+    return IDBF_EINVAL;
+  }
   h->margin = o.proposal_margin;
   h->seed = o.seed;
   if (o.sampler != IDBF_SAMPLER_MOCKCHEB && o.sampler != IDBF_SAMPLER_RANDOM) {
@@ -1836,6 +1874,41 @@ idbf_status idbf_batch_proposal(idbf_handle h, int32_t side, int32_t level, int3
     if (b->reject) IDBF_HIP_CHECK(hipMemcpy(rejected, b->reject, bytes, hipMemcpyDeviceToHost));
     else std::memset(rejected, 0, bytes);
   }
+  return IDBF_OK;
+}
+
+idbf_status idbf_batch_skeleton_proposal(idbf_handle h, int32_t side, int32_t level, int32_t* n_prop,
+                                        uint8_t* order) {
+  g_err[0] = 0;
+  const Batch* b = h ? find_batch(h, side, level) : nullptr;
+  if (!b || !b->prop_k) {
+    set_error("batch_skeleton_proposal: invalid handle, side or level, or no skeleton proposer");
+    return IDBF_EINVAL;
+  }
+  IDBF_HIP_CHECK(hipStreamSynchronize(h->stream));
+  if (n_prop) IDBF_HIP_CHECK(hipMemcpy(n_prop, b->prop_k, size_t(b->n) * 4, hipMemcpyDeviceToHost));
+  if (order) IDBF_HIP_CHECK(hipMemcpy(order, b->prop_cols, size_t(b->n) * kMaxRank, hipMemcpyDeviceToHost));
+  return IDBF_OK;
+}
+
+idbf_status idbf_skeleton_samples(idbf_handle h, int32_t side, int32_t level, int32_t* cmax, float* features,
+                                  float* targets) {
+  g_err[0] = 0;
+  const Batch* b = h ? find_batch(h, side, level) : nullptr;
+  if (!b || !cmax) {
+    set_error("skeleton_samples: invalid handle, side or level, or NULL cmax");
+    return IDBF_EINVAL;
+  }
+  *cmax = b->cand_max;
+  if (!features && !targets) return IDBF_OK;
+  if (!features || !targets) {
+    set_error("skeleton_samples: features and targets must both be given");
+    return IDBF_EINVAL;
+  }
+  IDBF_HIP_CHECK(launch_cand_features(b->n, h->L, level, side == IDBF_SIDE_U ? 0 : 1, h->ph, b->cand_beg,
+                                      b->cand_len, b->cand_coord, b->cand_max, features, h->stream));
+  IDBF_HIP_CHECK(launch_skel_targets(b->mask, b->cand_len, b->n, b->cand_max, targets, h->stream));
+  IDBF_HIP_CHECK(hipStreamSynchronize(h->stream));
   return IDBF_OK;
 }
 

@@ -417,6 +417,23 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   }
 
   const int kuser = min(min(min(s, c), A.kmax > 0 ? A.kmax : (1 << 30)), A.truncate ? kMaxRank : (1 << 30));
+  // a skeleton proposal restricts the pivot search to the proposed columns
+  // (a 128-bit mask, the same in every lane)
+  const bool restricted = A.prop_k != nullptr;
+  uint64_t pm0 = ~0ull, pm1 = ~0ull;
+  if (restricted) {
+    pm0 = pm1 = 0;
+    const uint8_t* fpiv = A.prop_cols + q * (int64_t)kMaxRank;
+    const int kf = __builtin_amdgcn_readfirstlane(min(A.prop_k[q], kMaxRank));
+    for (int i = 0; i < kf; ++i) {
+      const int p = __builtin_amdgcn_readfirstlane((int)fpiv[i]);
+      if (p < kWave) pm0 |= 1ull << p;
+      else if (p < 2 * kWave) pm1 |= 1ull << (p - kWave);
+    }
+  }
+  bool proposed[CPL];
+#pragma unroll
+  for (int cs = 0; cs < CPL; ++cs) proposed[cs] = (((cs == 0 ? pm0 : pm1) >> lane) & 1ull) != 0;
   bool pivoted[CPL];
   int pstep[CPL];  // step at which the column became a pivot
 #pragma unroll
@@ -459,12 +476,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     }
     // pivot search on squared norms (sqrt is monotone: the same maximum, and
     // the tie band below is far wider than a rounding of the square)
-    bool eligible[CPL];
+    bool active[CPL], eligible[CPL];  // not yet a pivot (updated) / and proposed (may become one)
     double nq[CPL];
     double nqmax = -1.0;
 #pragma unroll
     for (int cs = 0; cs < CPL; ++cs) {
-      eligible[cs] = (lane + kWave * cs < c) && !pivoted[cs];
+      active[cs] = (lane + kWave * cs < c) && !pivoted[cs];
+      eligible[cs] = active[cs] && proposed[cs];
       nq[cs] = eligible[cs] ? nrm2[cs] : -1.0;
       nqmax = fmax(nqmax, nq[cs]);
     }
@@ -472,28 +490,39 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     // taken on squares
     const double M2 = wave_max_nonneg(nqmax);
     if (j == 0) {
-      if (!(M2 > 0.0)) {
+      // |R_00| of the unrestricted QR: the largest column norm of the block
+      double all = M2;
+      if (restricted) {
+        double m = -1.0;
+#pragma unroll
+        for (int cs = 0; cs < CPL; ++cs)
+          if (lane + kWave * cs < c) m = fmax(m, nrm2[cs]);
+        all = wave_max_nonneg(m);
+      }
+      if (!(all > 0.0)) {
         zero_block = true;
         break;
       }
-      const double b = A.tol * sqrt(M2);
+      const double b = A.tol * sqrt(all);
       stop2 = b * b;
-    } else if (M2 <= stop2) {
-      break;
     }
+    if ((j > 0 || restricted) && M2 <= stop2) break;  // (a proposal may end at step 0)
     if (j == kuser) break;
     if (j == kMaxRank) {
       overflow = true;
       break;
     }
-    constexpr double kTie2 = (1.0 - kPivotTie) * (1.0 - kPivotTie);
-    const double thr2 = kTie2 * M2;
-    const uint64_t near0 = __ballot(eligible[0] && nq[0] >= thr2);
-    uint64_t near1 = 0;
-    if constexpr (CPL > 1) near1 = __ballot(eligible[CPL - 1] && nq[CPL - 1] >= thr2);
-    if (near0 == 0 && near1 == 0) break;  // no finite residual norm left (cannot happen for finite input)
-    const int p = __builtin_amdgcn_readfirstlane(
-        near0 ? __ffsll((unsigned long long)near0) - 1 : kWave + __ffsll((unsigned long long)near1) - 1);
+    int p;
+    {
+      constexpr double kTie2 = (1.0 - kPivotTie) * (1.0 - kPivotTie);
+      const double thr2 = kTie2 * M2;
+      const uint64_t near0 = __ballot(eligible[0] && nq[0] >= thr2);
+      uint64_t near1 = 0;
+      if constexpr (CPL > 1) near1 = __ballot(eligible[CPL - 1] && nq[CPL - 1] >= thr2);
+      if (near0 == 0 && near1 == 0) break;  // no finite residual norm left (cannot happen for finite input)
+      p = __builtin_amdgcn_readfirstlane(
+          near0 ? __ffsll((unsigned long long)near0) - 1 : kWave + __ffsll((unsigned long long)near1) - 1);
+    }
     const int pl = p & (kWave - 1), pc = p / kWave;  // pivot lane and column slot (uniform)
     // Householder vector of the pivot column (rows >= j): lane pl of every
     // live wave publishes its own rows to the wave's slice of LDS (no
@@ -571,7 +600,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       // update, and the residual norm of rows >= j + 1 for the next step (the
       // wave that holds row j recounts its rows below j)
       part[cs] = 0.0;
-      if (live && eligible[cs] && !(lane == pl && cs == pc)) {
+      if (live && active[cs] && !(lane == pl && cs == pc)) {
         const double2 sdot = make_double2(-tau * dot[cs].x, -tau * dot[cs].y);
         double p0 = 0.0, p1 = 0.0;
 #pragma unroll
@@ -604,7 +633,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     if (threadIdx.x == 0) s_piv[j] = p;
     k = j + 1;
   }
-  if (k == 0) zero_block = true;  // no pivot taken: keep the first candidate, T = 0
+  if (k == 0) {  // no pivot taken: keep the first candidate, T = 0
+    if (restricted && !zero_block && threadIdx.x == 0) A.prop_fail[q] = 1;  // no proposed column above eps
+    zero_block = true;
+  }
   if (zero_block) {
     k = 1;
 #pragma unroll
@@ -803,6 +835,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
   }
 
   const int kuser = min(min(min(s, c), A.kmax > 0 ? A.kmax : (1 << 30)), A.truncate ? kMaxRank : (1 << 30));
+  // a skeleton proposal restricts the pivot search to the proposed columns
+  const bool restricted = A.prop_k != nullptr;
+  bool proposed = !restricted;
+  if (restricted && member) {
+    const int kf = min(A.prop_k[q], kMaxRank);
+    for (int i = 0; i < kf; ++i) proposed = proposed || (int)A.prop_cols[q * (int64_t)kMaxRank + i] == col;
+  }
   bool pivoted = false;
   int pstep = 0;
   double stop2 = 0.0;
@@ -830,21 +869,23 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
 #pragma unroll
       for (int ww = 0; ww < W; ++ww) nrm2 += s_part[ww * kWave + lane];
     }
-    const bool eligible = !done && col < c && !pivoted;
+    const bool active = !done && col < c && !pivoted;  // not yet a pivot: updated
+    const bool eligible = active && proposed;          // ... and a pivot candidate
     const double nq = eligible ? nrm2 : -1.0;
     const double M2 = group_max_nonneg<G>(nq, lane);
+    // |R_00| of the unrestricted QR: the largest column norm of the block
+    const double all = (restricted && j == 0) ? group_max_nonneg<G>(!done && col < c ? nrm2 : -1.0, lane) : M2;
     if (!done) {  // this ID's stopping rules, in the one-ID kernel's order
       if (j == 0) {
-        if (!(M2 > 0.0)) {
+        if (!(all > 0.0)) {
           zero_block = true;
           done = true;
         } else {
-          const double b = A.tol * sqrt(M2);
+          const double b = A.tol * sqrt(all);
           stop2 = b * b;
         }
-      } else if (M2 <= stop2) {
-        done = true;
       }
+      if (!done && (j > 0 || restricted) && M2 <= stop2) done = true;  // (a proposal may end at step 0)
       if (!done && j == kuser) done = true;
       if (!done && j == kMaxRank) {
         overflow = true;
@@ -855,7 +896,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     const uint64_t near = __ballot(!done && eligible && nq >= kTie2 * M2);
     const uint64_t gbits = (near >> (gi * GL)) & gmask;
     if (!done && gbits == 0) done = true;  // no finite residual norm left (cannot happen for finite input)
-    if (__ballot(!done) == 0) break;      // every ID has stopped (the same in every wavefront)
+    if (__ballot(!done) == 0) break;       // every ID has stopped (the same in every wavefront)
     const int p = done ? 0 : __ffsll((unsigned long long)gbits) - 1;  // pivot column of this ID
     const int pl = gi * GL + p;                                         // its lane
     const double nup = sqrt(__shfl(nq, pl, kWave));
@@ -902,7 +943,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       double tau = __builtin_amdgcn_rcp(den);
       tau = __builtin_fma(tau, __builtin_fma(-den, tau, 1.0), tau);
       tau = __builtin_fma(tau, __builtin_fma(-den, tau, 1.0), tau);
-      if (live && eligible && lane != pl) {
+      if (live && active && lane != pl) {
         const double2 sdot = make_double2(-tau * dot.x, -tau * dot.y);
         double p0 = 0.0, p1 = 0.0;
 #pragma unroll
@@ -931,7 +972,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       k = j + 1;
     }
   }
-  if (member && k == 0) zero_block = true;
+  if (member && k == 0) {
+    if (restricted && !zero_block && w == 0 && gl == 0) A.prop_fail[q] = 1;  // no proposed column above eps
+    zero_block = true;
+  }
   if (zero_block) {
     k = 1;
     pivoted = (gl == 0);

@@ -76,6 +76,15 @@ struct IdArgs {
   double2* tall_work;         // reduction scratch: tall_chunk blocks of tall_work_ld entries
   int64_t tall_work_ld;       // >= s_max c_max
   int64_t tall_chunk;         // tall IDs per reduction launch
+  // skeleton proposal: the number of proposed columns of each ID and their
+  // candidate positions (kMaxRank per ID, best first); the pivot search of
+  // the QR runs over these columns only, with the eps-rank threshold still
+  // taken against the block's largest column norm.  An ID none of whose
+  // proposed columns is above it gets prop_fail[q] = 1 (the caller clears
+  // the array).  Null: the pivoted QR of Section 2.1 over every column.
+  const int32_t* prop_k;
+  const uint8_t* prop_cols;
+  int32_t* prop_fail;
   int32_t* rank;
   uint64_t* mask;        // two words per ID: bit l of (mask[2q], mask[2q+1]) = candidate l is a skeleton
   int32_t* skel_out;     // kMaxCand entries per ID
@@ -127,11 +136,26 @@ struct ResidualArgs {
   uint64_t seed;
   double factor;                // accept when ||E||_F <= factor tol ||A||_F
   bool force_reject;            // reject every proposal (the fallback then recomputes all IDs)
+  bool skeletons;               // the IDs took proposed skeletons: every one is tested
   int32_t* reject;              // out: 1 = rejected
   int32_t* s_prop;              // rejected IDs get samples_plain[q] (the fallback's count)
   const int32_t* samples_plain;
 };
 hipError_t launch_residual(const ResidualArgs& a, hipStream_t st);
+// Skeleton proposal.  Features of candidate l of ID q (row q * cmax + l;
+// rows l >= c zero): t/8, side, x_c, xi_c, a, m/4, l/c, and the candidate's
+// coordinate relative to the first and last candidates of its ID.
+hipError_t launch_cand_features(int64_t n, int L, int t, int side, const PhaseDev& ph, const int32_t* cand_beg,
+                                const int32_t* cand_len, const double* cand_coord, int cmax, float* F,
+                                hipStream_t st);
+// per ID: k_f = min(c, s_prop[q], kMaxRank, ceil(16 y_rank[q]) + margin) and the k_f candidates of highest
+// score (score[q * cmax + l]), best first
+hipError_t launch_pick_skeletons(const float* score, int cmax, const float* y_rank, const int32_t* s_prop,
+                                 const int32_t* cand_len, int64_t n, int margin, int32_t* prop_k,
+                                 uint8_t* prop_cols, hipStream_t st);
+// training targets: out[q * cmax + l] = 1 (skeleton) / 0 (redundant), -1 for l >= c
+hipError_t launch_skel_targets(const uint64_t* mask, const int32_t* cand_len, int64_t n, int cmax, float* out,
+                               hipStream_t st);
 // hist[r] += #{q : rank[q] == r} for r <= kMaxRank (hist zeroed by the caller)
 hipError_t launch_rank_hist(const int32_t* rank, int64_t n, unsigned long long* hist, hipStream_t st);
 // out[q] = rank[q] / kProposalScale (training targets)

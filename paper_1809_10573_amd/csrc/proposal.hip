@@ -1,11 +1,15 @@
-// Learned rank proposal for the construction (not in the paper).  Per level
-// batch: features of every ID -> the network's rank estimate k^ ->
-// proposed sample counts s' = min(s, t (ceil k^ + margin)); the IDs are
-// computed from s' samples, then a randomized residual test on r = 8 fresh
-// allowed points accepts or rejects each one,
+// Learned proposal for the construction (not in the paper).  Per level
+// batch: features of every ID -> the rank network's estimate k^ ->
+// proposed sample counts s' = min(s, t (ceil k^ + margin)); optionally a
+// second network scores every candidate of every ID and the k_f best become
+// the ID's proposed skeleton, which the QR takes as its pivots in that order
+// (no pivot search, no eps-rank stop).  The IDs are computed from s' samples,
+// then a randomized residual test on r = 8 fresh allowed points accepts or
+// rejects each one,
 //   || A(r, red) - A(r, skel) T ||_F <= 10 eps || A(r, cand) ||_F,
-// and rejected IDs are recomputed from the plain s samples (a proposal that
-// kept s' = s is the plain ID and is accepted as it is).
+// and rejected IDs are recomputed by the plain pivoted ID from the plain s
+// samples (a rank-only proposal that kept s' = s is the plain ID and is
+// accepted as it is).
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -135,11 +139,86 @@ __global__ __launch_bounds__(64 * kWavesRC) void residual_kernel(ResidualArgs R)
   }
   if (lane == 0) {
     const double bound = R.factor * A.tol;
-    // a proposal that kept the plain sample count is the plain ID itself
-    const bool ok = !R.force_reject && (R.s_prop[q] == R.samples_plain[q] || e2 <= bound * bound * na2);
+    // a rank proposal that kept the plain sample count is the plain ID itself
+    // (a skeleton proposal is not: it is always tested)
+    const bool same = !R.skeletons && R.s_prop[q] == R.samples_plain[q];
+    // a skeleton proposal none of whose columns the QR could keep is unusable
+    const bool kept = !R.skeletons || R.reject[q] == 0;
+    const bool ok = !R.force_reject && kept && (same || e2 <= bound * bound * na2);
     R.reject[q] = ok ? 0 : 1;
     if (!ok) R.s_prop[q] = R.samples_plain[q];  // the fallback samples the plain count
   }
+}
+
+// Candidate features, one thread per (ID, candidate position).
+__global__ void cand_features_kernel(int64_t n, int L, int t, int side, PhaseDev ph, const int32_t* cand_beg,
+                                     const int32_t* cand_len, const double* cand_coord, int cmax, float* F) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * cmax) return;
+  const int64_t q = e / cmax;
+  const int l = (int)(e % cmax);
+  float* f = F + e * kProposalInputs;
+  const int c = cand_len[q];
+  if (l >= c) {
+#pragma unroll
+    for (int i = 0; i < kProposalInputs; ++i) f[i] = 0.f;
+    return;
+  }
+  const int64_t nn = 1ll << (L - t + 1);
+  const int64_t node = q % nn, partner = q / nn;
+  const double cn = ((double)node + 0.5) / (double)nn;
+  const double cp = ((double)partner + 0.5) / (double)(1ll << t);
+  const bool fio = ph.kind == IDBF_PHASE_FIO;
+  const double* cc = cand_coord + cand_beg[q];
+  const double lo = cc[0], hi = cc[c - 1];
+  f[0] = (float)t / 8.f;
+  f[1] = (float)side;
+  f[2] = (float)(side == 0 ? cn : cp);
+  f[3] = (float)(side == 0 ? cp : cn);
+  f[4] = fio ? (float)ph.a : 0.f;
+  f[5] = fio ? (float)(ph.freq / 4.0) : 0.f;
+  f[6] = (float)l / (float)c;
+  f[7] = c > 1 && hi > lo ? (float)((cc[l] - lo) / (hi - lo)) : 0.5f;
+}
+
+// One wavefront per ID: each candidate's place in the descending score order
+// (ties to the lower position) by counting; the first k_f are the pivots.
+__global__ __launch_bounds__(256) void pick_skeletons_kernel(const float* score, int cmax, const float* y_rank,
+                                                             const int32_t* s_prop, const int32_t* cand_len,
+                                                             int64_t n, int margin, int32_t* prop_k,
+                                                             uint8_t* prop_cols) {
+  const int64_t q = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (q >= n) return;
+  const int c = cand_len[q];
+  const float kh = fminf(fmaxf(ceilf(y_rank[q] * kProposalScale), 1.f), (float)kMaxRank);
+  // the proposed set: room for the proposed rank and twice the margin (the
+  // restricted pivot search chooses within it)
+  const int kf = max(1, min(c, min(kMaxRank, (int)kh + 2 * margin)));
+  if (lane == 0) prop_k[q] = kf;
+  const float* sc = score + q * cmax;
+  for (int l = lane; l < c; l += kWave) {
+    const float v = sc[l];
+    int place = 0;
+    for (int m = 0; m < c; ++m) {
+      const float w = sc[m];
+      place += (w > v) || (w == v && m < l);
+    }
+    if (place < kf) prop_cols[q * kMaxRank + place] = (uint8_t)l;
+  }
+}
+
+__global__ void skel_targets_kernel(const uint64_t* mask, const int32_t* cand_len, int64_t n, int cmax, float* out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n * cmax) return;
+  const int64_t q = e / cmax;
+  const int l = (int)(e % cmax);
+  if (l >= cand_len[q]) {
+    out[e] = -1.f;
+    return;
+  }
+  const uint64_t w = l < 64 ? mask[2 * q] : mask[2 * q + 1];
+  out[e] = (float)((w >> (l & 63)) & 1ull);
 }
 
 __global__ __launch_bounds__(256) void rank_hist_kernel(const int32_t* rank, int64_t n, unsigned long long* hist) {
@@ -167,6 +246,31 @@ inline unsigned blocks(int64_t n, int per = 256) { return (unsigned)((n + per - 
 hipError_t launch_rank_targets(const int32_t* rank, int64_t n, float* out, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(targets_kernel, dim3(blocks(n)), dim3(256), 0, st, rank, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cand_features(int64_t n, int L, int t, int side, const PhaseDev& ph, const int32_t* cand_beg,
+                                const int32_t* cand_len, const double* cand_coord, int cmax, float* F,
+                                hipStream_t st) {
+  if (n <= 0 || cmax <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cand_features_kernel, dim3(blocks(n * cmax)), dim3(256), 0, st, n, L, t, side, ph, cand_beg,
+                     cand_len, cand_coord, cmax, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_pick_skeletons(const float* score, int cmax, const float* y_rank, const int32_t* s_prop,
+                                 const int32_t* cand_len, int64_t n, int margin, int32_t* prop_k,
+                                 uint8_t* prop_cols, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pick_skeletons_kernel, dim3(blocks(n, 4)), dim3(256), 0, st, score, cmax, y_rank, s_prop,
+                     cand_len, n, margin, prop_k, prop_cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_skel_targets(const uint64_t* mask, const int32_t* cand_len, int64_t n, int cmax, float* out,
+                               hipStream_t st) {
+  if (n <= 0 || cmax <= 0) return hipSuccess;
+  hipLaunchKernelGGL(skel_targets_kernel, dim3(blocks(n * cmax)), dim3(256), 0, st, mask, cand_len, n, cmax, out);
   return hipGetLastError();
 }
 

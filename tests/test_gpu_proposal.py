@@ -220,3 +220,125 @@ def test_force_reject_gives_the_plain_factors_bit_for_bit():
     assert sum(L[s]["accepted"] for L in st["per_level"] for s in "UV") == 0
     from gpu_export import same_factors
     same_factors(plain, forced)
+
+
+def _train_nets(members, N=4096, epochs=40):
+    """Rank and skeleton networks trained on the GPU on plain constructions."""
+    fr, tr, fs, ts = [], [], [], []
+    for (a, m) in members:
+        X, O = I.uniform_grid(N)
+        fac = B.construct(I.fio_phase(a, float(m)), X, O, 1e-6, 16, oversample=2, device=DEV)
+        for side in (B.SIDE_U, B.SIDE_V):
+            for t in range(1, fac.info()["H"] + 1):
+                F, tg = B.rank_samples(fac, side, t, device=DEV)
+                fr.append(F)
+                tr.append(tg)
+                F, tg = B.skeleton_samples(fac, side, t, device=DEV)
+                fs.append(F)
+                ts.append(tg)
+    rank = B.RankProposer(64, seed=3)
+    rank.train(torch.cat(fr), torch.cat(tr), epochs=epochs, batch=256, lr=3e-3, seed=4)
+    skel = B.RankProposer(64, seed=5)
+    losses = skel.train(torch.cat(fs), torch.cat(ts), epochs=epochs // 2, batch=1024, lr=3e-3, seed=6)
+    return rank, skel, losses
+
+
+def test_skeleton_samples_label_the_plain_skeletons():
+    ph = I.fio_phase(0.5, 2.0)
+    X, O = I.uniform_grid(2048)
+    fac = B.construct(ph, X, O, 1e-6, 16, oversample=2, device=DEV)
+    for side in (B.SIDE_U, B.SIDE_V):
+        for t in range(1, fac.info()["H"] + 1):
+            F, tg = B.skeleton_samples(fac, side, t, device=DEV)
+            b = fac.batch(side, t)
+            assert F.shape == (int(b.cand_len.sum()), B.MLP_INPUTS)
+            assert int(tg.sum().item()) == int(b.rank.sum())        # one label per skeleton
+            rel = F[:, 6].cpu().numpy()                               # l / c in [0, 1)
+            assert rel.min() >= 0 and rel.max() < 1
+
+
+def test_skeleton_proposals_match_the_oracle():
+    """A construction with trained rank and skeleton networks, every ID judged
+    by the oracle on the GPU's own sets: an accepted proposal is
+    oracle.column_id on the s' Mock-Chebyshev samples with the pivot search
+    restricted to the proposed set (same skeleton, T to the parity bound) and
+    passes oracle.mlp.residual_ok on the same check rows; a rejected one
+    fails it (or keeps no column) and is stored as the plain pivoted ID."""
+    from gpu_export import GpuLevels
+    rank, skel, _ = _train_nets(I.family_draws(4, seed=31))
+    (a, m), = I.family_draws(1, seed=32)
+    ph = I.fio_phase(a, float(m))
+    N, leaf, tol, t_os, seed, margin = 4096, 16, 1e-6, 2, 9, 3
+    X, O = I.uniform_grid(N)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=t_os, device=DEV, proposer=rank, proposal_margin=margin,
+                      skeleton_proposer=skel, seed=seed)
+    G = GpuLevels(fac)
+    counts = {"accepted": 0, "rejected": 0}
+    for t in range(1, G.H + 1):
+        for side in (B.SIDE_U, B.SIDE_V):
+            proposed, used, rejected = fac.proposal(side, t)
+            n_prop, order = fac.skeleton_proposal(side, t)
+            b, offs = G.batches[(side, t)]
+            for q in range(len(b.rank)):
+                cand, allowed = G.sets(side, t, q)
+                coords = X[allowed] if side == B.SIDE_V else O[allowed]
+                s_plain = oracle.sample_count(len(cand), len(allowed), t_os)
+                sp = int(proposed[q])
+                assert 1 <= n_prop[q] <= min(len(cand), B.MAX_RANK)
+                among = order[q, :n_prop[q]].astype(np.int64)
+                assert len(np.unique(among)) == n_prop[q] and among.max() < len(cand)
+                samp = allowed[oracle.mock_chebyshev(coords, sp)]
+                Bm = (oracle.entries(ph, X, O, samp, cand) if side == B.SIDE_V
+                      else oracle.entries(ph, X, O, cand, samp).T)
+                cid = oracle.column_id(Bm, tol, among=among)
+                ok, ratio = False, np.inf
+                if cid is not None:
+                    pos = omlp.check_positions(seed, t, side, q, len(allowed))
+                    rows = allowed[pos]
+                    A = (oracle.entries(ph, X, O, rows, cand) if side == B.SIDE_V
+                         else oracle.entries(ph, X, O, cand, rows).T)
+                    ok = omlp.residual_ok(A, cid.skel, cid.red, cid.T, tol)
+                    E = A[:, cid.red] - A[:, cid.skel] @ cid.T
+                    ratio = np.linalg.norm(E) / (10 * tol * np.linalg.norm(A))
+                rec = G.record(side, t, q)
+                if bool(rejected[q]) == ok:
+                    print("decision differs: level", t, "side", side, "id", q, "c", len(cand), "s'", sp,
+                          "n_prop", int(n_prop[q]), "ratio", ratio, "oracle rank", None if cid is None else cid.rank,
+                          "gpu rank", len(rec.skel), "among", sorted(among.tolist()),
+                          "oracle skel", None if cid is None else cid.skel.tolist(),
+                          "gpu skel", np.searchsorted(cand, rec.skel).tolist(), flush=True)
+                assert bool(rejected[q]) == (not ok), (t, side, q)
+                if ok:
+                    counts["accepted"] += 1
+                    assert int(used[q]) == sp
+                else:
+                    counts["rejected"] += 1
+                    assert int(used[q]) == s_plain
+                    samp = allowed[oracle.mock_chebyshev(coords, s_plain)]
+                    Bm = (oracle.entries(ph, X, O, samp, cand) if side == B.SIDE_V
+                          else oracle.entries(ph, X, O, cand, samp).T)
+                    cid = oracle.column_id(Bm, tol)
+                assert np.array_equal(rec.skel, cand[cid.skel]), (t, side, q)
+                kappa = cid.rdiag[0] / cid.rdiag[-1]
+                scale = max(1.0, np.abs(cid.T).max(initial=0.0))
+                assert np.max(np.abs(rec.T - cid.T), initial=0.0) <= 1e-12 * kappa * scale, (t, side, q)
+            print(t, side, counts, flush=True)
+    assert counts["accepted"] > 0 and counts["rejected"] > 0
+
+
+def test_trained_skeleton_proposer_keeps_accuracy():
+    rank, skel, losses = _train_nets(I.family_draws(8, seed=41))
+    assert losses[-1] < losses[0]
+    for (a, m) in I.family_draws(3, seed=42):             # held-out family members
+        ph = I.fio_phase(a, float(m))
+        X, O = I.uniform_grid(4096)
+        plain = B.construct(ph, X, O, 1e-6, 16, oversample=2, device=DEV)
+        prop = B.construct(ph, X, O, 1e-6, 16, oversample=2, device=DEV, proposer=rank, proposal_margin=4,
+                           skeleton_proposer=skel, seed=1)
+        ip, iq = plain.info(), prop.info()
+        st = prop.stats()
+        acc = sum(L[s]["accepted"] for L in st["per_level"] for s in "UV")
+        print(a, m, "accepted", acc, "of", iq["n_ids"], "sampled", iq["sampled_entries"], ip["sampled_entries"],
+              flush=True)
+        assert acc > 0
+        assert _rows_error(prop, ph, X, O, 5) <= max(2 * _rows_error(plain, ph, X, O, 5), 1e-5)

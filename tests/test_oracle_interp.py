@@ -137,3 +137,81 @@ def test_row_reduction_keeps_the_id(s, c, r):
         assert np.allclose(a.rdiag, b.rdiag, rtol=1e-10)
         kappa = a.rdiag[0] / a.rdiag[-1]
         assert np.max(np.abs(a.T - b.T)) <= 1e-12 * kappa * max(1.0, np.abs(a.T).max())
+
+
+def test_restricted_id_without_restriction_is_the_plain_id():
+    # among = every column, or exactly the plain ID's own pivots: the pivot
+    # search finds the same column at every step, so the same arithmetic
+    rng = np.random.default_rng(5)
+    B = (_cgauss(rng, 40, 30) * np.logspace(0, -12, 30)) @ _cgauss(rng, 30, 30)
+    a = oracle.column_id(B, 1e-8)
+    for among in (np.arange(30), a.pivots, a.pivots[::-1]):
+        b = oracle.column_id(B, 1e-8, among=among)
+        assert np.array_equal(a.pivots, b.pivots) and np.array_equal(a.skel, b.skel)
+        assert np.array_equal(a.T, b.T) and np.array_equal(a.rdiag, b.rdiag)
+
+
+def test_restricted_id_first_pivot_and_threshold_by_brute_force():
+    # first pivot: the largest column of the proposal; the eps rule is taken
+    # against the largest column of all of B, not of the proposal
+    rng = np.random.default_rng(7)
+    B = _cgauss(rng, 12, 8) * np.array([1.0, 5.0, 0.5, 2.0, 3.0, 0.1, 4.0, 1e-4])
+    among = [0, 2, 3, 7]
+    cid = oracle.column_id(B, 1e-6, among=among)
+    nrm = np.linalg.norm(B, axis=0)
+    assert cid.pivots[0] == among[int(np.argmax(nrm[among]))]
+    assert sorted(cid.pivots) == among and cid.rank == 4
+    # |B_7| ~ 1e-4 stays below 1e-3 max|B_l| (max|B_l| is column 1's, outside
+    # the proposal): column 7 is not kept, the other three are
+    cid = oracle.column_id(B, 1e-3, among=among)
+    assert sorted(cid.pivots) == [0, 2, 3]
+    assert oracle.column_id(B, 1e-2, among=[7]) is None       # nothing kept: unusable
+
+
+@pytest.mark.parametrize("s,c,r", [(30, 20, 7), (40, 33, 12), (16, 16, 5)])
+def test_restricted_id_on_exact_low_rank(s, c, r):
+    # B exactly of rank r: a proposal that spans it (r + 5 generic columns)
+    # keeps exactly r of them, which interpolate the rest exactly with T the
+    # least-squares solution B[:, skel]^+ B[:, red]
+    rng = np.random.default_rng(s + c)
+    B = _cgauss(rng, s, r) @ _cgauss(rng, r, c)
+    among = rng.choice(c, min(c, r + 5), replace=False)
+    cid = oracle.column_id(B, 1e-10, among=among)
+    assert cid.rank == r and set(cid.skel) <= set(among)
+    err = np.linalg.norm(B[:, cid.red] - B[:, cid.skel] @ cid.T) / np.linalg.norm(B)
+    assert err < 1e-12
+    ls = np.linalg.lstsq(B[:, cid.skel], B[:, cid.red], rcond=None)[0]
+    assert np.allclose(cid.T, ls, atol=1e-10 * max(1.0, np.abs(ls).max()))
+    # a proposal that misses a direction keeps what it spans and leaves a
+    # large residual (what the acceptance test then sees)
+    cid = oracle.column_id(B, 1e-10, among=among[:r - 2])
+    assert cid.rank == r - 2
+    assert np.linalg.norm(B[:, cid.red] - B[:, cid.skel] @ cid.T) / np.linalg.norm(B) > 1e-3
+
+
+def test_restricted_id_keeps_the_rank_of_a_dependent_proposal():
+    # three proposed columns spanning two dimensions: two are kept (the
+    # largest first), and the third gets its exact coefficients in T
+    rng = np.random.default_rng(6)
+    B = _cgauss(rng, 20, 10)
+    B[:, 3] = 2.0 * B[:, 1] - 1j * B[:, 7]
+    cid = oracle.column_id(B, 1e-12, among=[1, 7, 3])
+    assert cid.rank == 2 and cid.pivots[0] == 3
+    (dep,) = [l for l in (1, 7) if l in cid.red]
+    t = cid.T[:, list(cid.red).index(dep)]
+    coef = np.linalg.lstsq(B[:, cid.skel], B[:, dep], rcond=None)[0]
+    assert np.allclose(t, coef, rtol=0, atol=1e-12)
+    assert np.linalg.norm(B[:, cid.skel] @ t - B[:, dep]) < 1e-12 * np.linalg.norm(B[:, dep])
+
+
+def test_restricted_id_degenerate_cases():
+    rng = np.random.default_rng(8)
+    B = _cgauss(rng, 12, 6)
+    B[:, 4] = 0.0
+    assert oracle.column_id(B, 1e-12, among=[4]) is None                 # nothing kept: unusable
+    Z = oracle.column_id(np.zeros((5, 4)), 1e-6, among=[2])              # zero block: the plain convention
+    ref = oracle.column_id(np.zeros((5, 4)), 1e-6)
+    assert np.array_equal(Z.skel, ref.skel) and np.array_equal(Z.T, ref.T)
+    for bad in ([1, 1], [6], []):
+        with pytest.raises(ValueError):
+            oracle.column_id(B, 1e-6, among=bad)
