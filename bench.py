@@ -283,11 +283,13 @@ def _example(B, torch, dev, stream, kind: str) -> dict:
 
 def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6, keep: int = 8,
              progress: bool = False) -> dict:
-    """The learned rank proposal on the FIO family c(x) = (2 + a sin 2 pi m x)/8
-    at N = 2^18 (leaf 16, tol 1e-6, t = 2): the network is trained on the GPU
-    on ranks from n_train plain constructions (1 in `keep` of their IDs), then
-    plain and proposed constructions of n_test held-out (a, m) are compared
-    (wall time, sampled entries, rejected proposals, error on 128 exact rows).
+    """The learned proposals on the FIO family c(x) = (2 + a sin 2 pi m x)/8
+    at N = 2^18 (leaf 16, tol 1e-6, t = 2): the rank network is trained on
+    the GPU on ranks from n_train plain constructions (1 in `keep` of their
+    IDs), the skeleton network on their skeleton labels (at most 8M
+    candidate rows in all); then plain, rank-proposed and rank + skeleton
+    proposed constructions of n_test held-out (a, m) are compared (wall
+    time, sampled entries, rejected proposals, error on 128 exact rows).
     The default is a reduced run (16 / 6); `--only learned` runs the full
     2000 / 200.  Measured once."""
     N, leaf, tol = 1 << 18, 16, 1e-6
@@ -295,30 +297,57 @@ def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6, keep: in
     X, O = torch.as_tensor(Xh, device=dev), torch.as_tensor(Oh, device=dev)
     gen = torch.Generator(device=dev).manual_seed(8)
     t0 = time.perf_counter()
-    feats, targ = [], []
+    feats, targ, sfeats, starg = [], [], [], []
     for i, (a, m) in enumerate(I.family_draws(n_train, seed=21)):
         fac = B.construct(I.fio_phase(a, float(m)), X, O, tol, leaf, oversample=2, device=dev, stream=stream)
+        H = fac.info()["H"]
+        per_call = max(1, 8_000_000 // (n_train * 2 * H))  # skeleton rows kept per level and side
         for side in (B.SIDE_U, B.SIDE_V):
-            for t in range(1, fac.info()["H"] + 1):
+            for t in range(1, H + 1):
                 F, tg = B.rank_samples(fac, side, t, device=dev)
                 sel = torch.randperm(F.shape[0], generator=gen, device=dev)[: F.shape[0] // keep]
                 feats.append(F[sel])
                 targ.append(tg[sel])
+                F, tg = B.skeleton_samples(fac, side, t, device=dev)
+                sel = torch.randperm(F.shape[0], generator=gen, device=dev)[:per_call]
+                sfeats.append(F[sel])
+                starg.append(tg[sel])
         fac.close()
         if progress and (i + 1) % 100 == 0:
             print(f"learned: {i + 1} training constructions", file=sys.stderr, flush=True)
     F, tg = torch.cat(feats), torch.cat(targ)
+    SF, st = torch.cat(sfeats), torch.cat(starg)
+    del feats, targ, sfeats, starg
     label_s = time.perf_counter() - t0
+    # one call per epoch (Adam's state lives in the network), with a progress
+    # line each; the full-scale set is 100x larger, so larger batches and
+    # fewer passes
+    full = n_train >= 1000
+    r_epochs, r_batch = (6, 2048) if full else (20, 512)
+
+    def fit(model, Fm, tm, epochs, batch, seed, name):
+        out = []
+        for e in range(epochs):
+            out.append(float(model.train(Fm, tm, epochs=1, batch=batch, lr=2e-3, seed=seed + 7919 * e,
+                                         stream=stream)[0]))
+            if progress:
+                print(f"learned: {name} epoch {e + 1}/{epochs} loss {out[-1]:.4g}", file=sys.stderr, flush=True)
+        return out
+
     net = B.RankProposer(128, seed=5)
     t0 = time.perf_counter()
-    losses = net.train(F, tg, epochs=20, batch=512, lr=2e-3, seed=6, stream=stream)
+    losses = fit(net, F, tg, r_epochs, r_batch, 6, "rank")
     train_s = time.perf_counter() - t0
+    snet = B.RankProposer(128, seed=7)
+    t0 = time.perf_counter()
+    slosses = fit(snet, SF, st, 10, 2048, 8, "skeleton")
+    strain_s = time.perf_counter() - t0
     rows = torch.as_tensor(np.sort(np.random.default_rng(1).choice(N, 128, replace=False)), dtype=torch.int32,
                            device=dev)
     cols = torch.arange(N, dtype=torch.int32, device=dev)
     g = torch.as_tensor(I.gaussian_vectors(N, None, 9), device=dev)
-    res = {"plain_ms": [], "proposed_ms": [], "plain_sampled": 0, "proposed_sampled": 0, "proposed": 0,
-           "rejected": 0, "err_plain": [], "err_proposed": []}
+    kinds = ("plain", "proposed", "skeleton")
+    res = {k: {"ms": [], "sampled": 0, "proposed": 0, "rejected": 0, "err": []} for k in kinds}
     for i, (a, m) in enumerate(I.family_draws(n_test, seed=22)):
         if progress and i % 20 == 0:
             print(f"learned: held-out member {i}", file=sys.stderr, flush=True)
@@ -326,35 +355,42 @@ def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6, keep: in
         ex = torch.zeros(128, dtype=torch.complex128, device=dev)
         for c0 in range(0, N, 1 << 16):
             ex += B.sample(ph, X, O, rows, cols[c0:c0 + (1 << 16)], device=dev) @ g[c0:c0 + (1 << 16)]
-        for kind in ("plain", "proposed"):
-            kw = dict(proposer=net, proposal_margin=6, seed=3) if kind == "proposed" else {}
+        for kind in kinds:
+            kw = {}
+            if kind != "plain":
+                kw = dict(proposer=net, proposal_margin=6, seed=3)
+            if kind == "skeleton":
+                kw["skeleton_proposer"] = snet
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             fac = B.construct(ph, X, O, tol, leaf, oversample=2, device=dev, stream=stream, **kw)
-            res[kind + "_ms"].append((time.perf_counter() - t0) * 1e3)
+            r = res[kind]
+            r["ms"].append((time.perf_counter() - t0) * 1e3)
             info = fac.info()
-            res[kind + "_sampled"] += info["sampled_entries"]
-            if kind == "proposed":
-                res["proposed"] += info["proposed"]
-                res["rejected"] += info["rejected"]
+            r["sampled"] += info["sampled_entries"]
+            r["proposed"] += info.get("proposed", 0)
+            r["rejected"] += info.get("rejected", 0)
             y = fac.apply(g)
-            res["err_" + kind].append(float(torch.linalg.norm(y[rows.long()] - ex) / torch.linalg.norm(ex)))
+            r["err"].append(float(torch.linalg.norm(y[rows.long()] - ex) / torch.linalg.norm(ex)))
             fac.close()
     net.close()
-    return {"N": N, "scale": "full (2000 / 200)" if n_train >= 2000 else "reduced",
-            "train_constructions": n_train, "train_samples": int(F.shape[0]),
-            "labels_s": label_s, "train_s": train_s, "loss_first_last": [float(losses[0]), float(losses[-1])],
-            "heldout": n_test,
-            "construct_ms_plain": float(np.mean(res["plain_ms"])),
-            "construct_ms_proposed": float(np.mean(res["proposed_ms"])),
-            "speedup": float(np.mean(res["plain_ms"]) / np.mean(res["proposed_ms"])),
-            "sampled_entries_ratio": res["proposed_sampled"] / max(res["plain_sampled"], 1),
-            "rejected_frac": res["rejected"] / max(res["proposed"], 1),
-            "err_rows_plain_max": max(res["err_plain"]), "err_rows_proposed_max": max(res["err_proposed"]),
-            "err_rows_plain_median": float(np.median(res["err_plain"])),
-            "err_rows_proposed_median": float(np.median(res["err_proposed"])),
-            "construct_ms_plain_samples": [round(v, 2) for v in res["plain_ms"][:10]],
-            "construct_ms_proposed_samples": [round(v, 2) for v in res["proposed_ms"][:10]]}
+    snet.close()
+    out = {"N": N, "scale": "full (2000 / 200)" if n_train >= 2000 else "reduced",
+           "train_constructions": n_train, "train_samples": int(F.shape[0]), "skeleton_train_samples": int(SF.shape[0]),
+           "labels_s": label_s, "train_s": train_s, "train_epochs_batch": [r_epochs, r_batch],
+           "skeleton_train_s": strain_s,
+           "loss_first_last": [float(losses[0]), float(losses[-1])],
+           "skeleton_loss_first_last": [float(slosses[0]), float(slosses[-1])], "heldout": n_test}
+    base = res["plain"]
+    for kind in kinds:
+        r = res[kind]
+        out[kind] = {"construct_ms": float(np.mean(r["ms"])), "construct_ms_samples": [round(v, 2) for v in r["ms"][:10]],
+                     "err_rows_max": max(r["err"]), "err_rows_median": float(np.median(r["err"]))}
+        if kind != "plain":
+            out[kind].update({"speedup": float(np.mean(base["ms"]) / np.mean(r["ms"])),
+                              "sampled_entries_ratio": r["sampled"] / max(base["sampled"], 1),
+                              "rejected_frac": r["rejected"] / max(r["proposed"], 1)})
+    return out
 
 
 def _config2(B, torch, dev, stream) -> dict:

@@ -83,6 +83,9 @@ enum { IDBF_FLAG_PROFILE = 1, IDBF_FLAG_PROPOSER_FORCE_REJECT = 2, IDBF_FLAG_ALL
 
 enum { IDBF_SAMPLER_MOCKCHEB = 0, IDBF_SAMPLER_RANDOM = 1 };
 
+/* Default acceptance factor of the learned proposal's residual test. */
+#define IDBF_DEFAULT_ACCEPT 1.0f
+
 typedef struct idbf_opts {
   int32_t kmax;        /* rank parameter k of the (eps, k)-ID (Section 2.1); 0: k = min(s, c) */
   int32_t oversample;  /* oversampling parameter t >= 1: s = min(t |cand|, |allowed|) samples (<= 256) */
@@ -95,12 +98,12 @@ typedef struct idbf_opts {
   /* Learned rank proposal (not in the paper), or NULL: every ID first samples
    * s' = min(s, t (ceil(k^) + proposal_margin)) points, k^ the network's rank
    * estimate; a randomized residual test on 8 fresh allowed points accepts it
-   * (||A(r,red) - A(r,skel) T||_F <= 10 tol ||A(r,cand)||_F) or the plain ID
-   * of s samples replaces it.  seed drives the test points and the random
-   * sampler (SplitMix64). */
+   * (||A(r,red) - A(r,skel) T||_F <= f tol ||A(r,cand)||_F, f =
+   * proposal_accept) or the plain ID of s samples replaces it.  seed drives
+   * the test points and the random sampler (SplitMix64). */
   struct idbf_mlp_s* proposer;
   int32_t proposal_margin;
-  int32_t reserved2;
+  float proposal_accept; /* acceptance factor f > 0 of the residual test; 0: IDBF_DEFAULT_ACCEPT */
   uint64_t seed;
   /* Skeleton proposal (not in the paper), or NULL; needs opts.proposer.  A
    * second network of the same form scores every candidate of every ID

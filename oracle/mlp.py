@@ -123,9 +123,10 @@ def check_positions(seed: int, level: int, side: int, q: int, n_allowed: int, r:
     return out
 
 
-def residual_ok(A_rows, skelpos, redpos, T, tol: float, factor: float = 10.0) -> bool:
+def residual_ok(A_rows, skelpos, redpos, T, tol: float, factor: float = 1.0) -> bool:
     """Acceptance of a proposed ID on check rows A_rows (r x c):
-    || A(:, red) - A(:, skel) T ||_F <= factor * tol * || A ||_F."""
+    || A(:, red) - A(:, skel) T ||_F <= factor * tol * || A ||_F
+    (factor 1 by default: the ID's own tolerance on the check rows)."""
     A_rows = np.asarray(A_rows)
     E = A_rows[:, redpos] - A_rows[:, skelpos] @ T
     return bool(np.linalg.norm(E) <= factor * tol * np.linalg.norm(A_rows))

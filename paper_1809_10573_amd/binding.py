@@ -62,7 +62,7 @@ class Phase_t(C.Structure):
 class Opts_t(C.Structure):
     _fields_ = [("kmax", C.c_int32), ("oversample", C.c_int32), ("flags", C.c_int32),
                 ("sampler", C.c_int32), ("mem_cap_bytes", C.c_uint64), ("stream", C.c_void_p),
-                ("proposer", C.c_void_p), ("proposal_margin", C.c_int32), ("reserved2", C.c_int32),
+                ("proposer", C.c_void_p), ("proposal_margin", C.c_int32), ("proposal_accept", C.c_float),
                 ("seed", C.c_uint64), ("skeleton_proposer", C.c_void_p)]
 
 
@@ -362,7 +362,8 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
               mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
               stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0,
               sampler: int = SAMPLER_MOCKCHEB, force_reject: bool = False,
-              allow_truncate: bool = False, skeleton_proposer=None) -> Factorization:
+              allow_truncate: bool = False, skeleton_proposer=None,
+              proposal_accept: float = 0.0) -> Factorization:
     """idbf_construct on device copies of X and Omega (float64, ascending)."""
     lib = load()
     Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
@@ -376,6 +377,7 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
     opts.sampler, opts.seed = int(sampler), int(seed)
     if proposer is not None:
         opts.proposer, opts.proposal_margin = proposer._h.value, int(proposal_margin)
+        opts.proposal_accept = float(proposal_accept)
     if skeleton_proposer is not None:
         opts.skeleton_proposer = skeleton_proposer._h.value
     ph = _phase(phase)
@@ -389,7 +391,8 @@ def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample
                       mem_cap_bytes: int = 0, profile: bool = False, device="cuda",
                       stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0,
                       sampler: int = SAMPLER_MOCKCHEB, force_reject: bool = False,
-                      allow_truncate: bool = False, skeleton_proposer=None) -> list:
+                      allow_truncate: bool = False, skeleton_proposer=None,
+              proposal_accept: float = 0.0) -> list:
     """idbf_construct_batched: one lockstep construction of len(phases) instances."""
     lib = load()
     n = len(phases)
@@ -408,6 +411,7 @@ def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample
     opts.sampler, opts.seed = int(sampler), int(seed)
     if proposer is not None:
         opts.proposer, opts.proposal_margin = proposer._h.value, int(proposal_margin)
+        opts.proposal_accept = float(proposal_accept)
     if skeleton_proposer is not None:
         opts.skeleton_proposer = skeleton_proposer._h.value
     ph = (Phase_t * n)(*[_phase(p) for p in phases])

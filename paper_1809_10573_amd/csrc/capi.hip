@@ -413,6 +413,7 @@ struct idbf_handle_s {
   idbf_mlp_s* skel_proposer = nullptr;  // skeleton proposal network (not owned), or null
   int sampler = IDBF_SAMPLER_MOCKCHEB;
   int margin = 0;
+  double accept = IDBF_DEFAULT_ACCEPT;  // acceptance factor of the residual test
   uint64_t seed = 0;
   int live_plans = 0;          // captured plans that hold this handle's workspace pointer
   bool force_reject = false;   // IDBF_FLAG_PROPOSER_FORCE_REJECT
@@ -701,7 +702,7 @@ idbf_status level_ids(idbf_handle_s* h) {
     ra.id = ia;
     ra.level = t;
     ra.seed = h->seed;
-    ra.factor = 10.0;
+    ra.factor = h->accept;
     ra.force_reject = h->force_reject;
     ra.skeletons = h->skel_proposer != nullptr;
     ra.reject = b.reject;
@@ -1117,6 +1118,11 @@ idbf_status make_handle(const idbf_phase* phase, const double* X, const double* 
     set_error("opts: proposal_margin must be >= 0");
     return IDBF_EINVAL;
   }
+  if (!(o.proposal_accept >= 0.f) || !std::isfinite(o.proposal_accept)) {
+    set_error("opts: proposal_accept must be finite and >= 0");
+    return IDBF_EINVAL;
+  }
+  h->accept = o.proposal_accept > 0.f ? (double)o.proposal_accept : (double)IDBF_DEFAULT_ACCEPT;
   *out = std::move(h);
   return IDBF_OK;
 }
