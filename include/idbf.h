@@ -267,6 +267,29 @@ idbf_status idbf_destroy(idbf_handle h);
  * reuse. */
 idbf_status idbf_release_cached_memory(void);
 
+/* Launch configuration of the many-right-hand-side apply (a schedule of the
+ * product of eq. finishIDBF, not a change to it):
+ *   fuse: 1 (the default) runs each pair of consecutive V stages, and of U
+ *     stages, of the complex64 FP32 forward apply as one launch over closed
+ *     groups (two level-t units and the two neighbouring-level units they
+ *     feed), the intermediate kept in registers, where every ID of both
+ *     levels has rank <= 32; 0 runs one launch per stage.  Results agree to
+ *     FP32 rounding.
+ *   rhs_iter: right-hand-side blocks (32 complex64 or 16 complex128 columns
+ *     per wavefront) each workgroup walks through with one LDS-staged
+ *     factor block: 0 (the kernels' defaults: 8, complex128 16) or a power
+ *     of two <= 64.
+ * The setting belongs to the handle; idbf_tune_apply picks one by timing. */
+typedef struct idbf_apply_config {
+  int32_t fuse;
+  int32_t rhs_iter;
+  int32_t reserved[6];
+} idbf_apply_config;
+/* Read or replace a handle's apply configuration (IDBF_EINVAL on NULL
+ * arguments or values outside the ranges above; nothing changes then). */
+idbf_status idbf_get_apply_config(idbf_handle h, idbf_apply_config* cfg);
+idbf_status idbf_set_apply_config(idbf_handle h, const idbf_apply_config* cfg);
+
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* idbf_last_error(void);
 

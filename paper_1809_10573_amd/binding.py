@@ -33,6 +33,7 @@ EXPORTED = [
     "idbf_rank_samples", "idbf_apply_batched_plan", "idbf_plan_launch", "idbf_plan_destroy",
     "idbf_apply_adjoint", "idbf_release_cached_memory", "idbf_stats", "idbf_batch_proposal",
     "idbf_apply_noalloc", "idbf_skeleton_samples", "idbf_batch_skeleton_proposal",
+    "idbf_get_apply_config", "idbf_set_apply_config",
 ]
 MLP_INPUTS = 8
 FLAG_PROFILE, FLAG_PROPOSER_FORCE_REJECT, FLAG_ALLOW_TRUNCATE = 1, 2, 4
@@ -91,6 +92,10 @@ class Stats_t(C.Structure):
                 ("construct_ms", C.c_double)]
 
 
+class ApplyConfig_t(C.Structure):
+    _fields_ = [("fuse", C.c_int32), ("rhs_iter", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
 class KernelStat_t(C.Structure):
     _fields_ = [("name", C.c_char * 24), ("launches", C.c_int32), ("reserved", C.c_int32),
                 ("ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double)]
@@ -144,6 +149,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_rank_samples.argtypes = [VP, I32, I32, VP, VP]
     lib.idbf_skeleton_samples.argtypes = [VP, I32, I32, P(I32), VP, VP]
     lib.idbf_batch_skeleton_proposal.argtypes = [VP, I32, I32, VP, VP]
+    lib.idbf_get_apply_config.argtypes = [VP, P(ApplyConfig_t)]
+    lib.idbf_set_apply_config.argtypes = [VP, P(ApplyConfig_t)]
     lib.idbf_apply_batched_plan.argtypes = [I32, P(VP), P(VP), P(VP), P(I64), I32, VP, P(VP)]
     lib.idbf_plan_launch.argtypes = [VP, VP]
     lib.idbf_plan_destroy.argtypes = [VP]
@@ -333,6 +340,20 @@ class Factorization:
         order = np.zeros((n.value, MAX_RANK), np.uint8)
         _check(lib.idbf_batch_skeleton_proposal(self._h, side, level, k.ctypes.data, order.ctypes.data))
         return k, order
+
+    def apply_config(self) -> dict:
+        """{'fuse', 'rhs_iter'} of the many-RHS apply (idbf_get_apply_config)."""
+        cfg = ApplyConfig_t()
+        _check(load().idbf_get_apply_config(self._h, C.byref(cfg)))
+        return {"fuse": cfg.fuse, "rhs_iter": cfg.rhs_iter}
+
+    def set_apply_config(self, fuse: int = None, rhs_iter: int = None) -> None:
+        """Change the many-RHS apply configuration (idbf_set_apply_config); None keeps a value."""
+        cur = self.apply_config()
+        cfg = ApplyConfig_t()
+        cfg.fuse = cur["fuse"] if fuse is None else int(fuse)
+        cfg.rhs_iter = cur["rhs_iter"] if rhs_iter is None else int(rhs_iter)
+        _check(load().idbf_set_apply_config(self._h, C.byref(cfg)))
 
     def profile(self, reset: bool = True) -> dict:
         """{kernel name: {launches, ms, bytes, flops}} since the last reset (IDBF_FLAG_PROFILE)."""

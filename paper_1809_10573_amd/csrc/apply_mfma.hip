@@ -49,7 +49,7 @@ struct Unit {
   int M, K;
 };
 
-__device__ __forceinline__ int lda_for(int K) { return ((K + 15) & ~15) + 2; }
+__host__ __device__ __forceinline__ int lda_for(int K) { return ((K + 15) & ~15) + 2; }
 
 // Stage the unit's A (M x K complex, zero padded to Mpad x roundup(K, 16))
 // into LDS with the input row of every K index (s_src) and the output row of
@@ -66,9 +66,24 @@ __device__ __forceinline__ int lda_for(int K) { return ((K + 15) & ~15) + 2; }
 __device__ __forceinline__ float2 cplx(float2, float re, float im) { return make_float2(re, im); }
 __device__ __forceinline__ double2 cplx(double2, double re, double im) { return make_double2(re, im); }
 
-template <int MODE, bool ADJ, typename C = float2>
-__device__ Unit stage_unit(const StageArgs& A, C* s_A, int* s_src, int* s_out, int* s_red) {
-  const int64_t q = blockIdx.x;
+// Where the entries of a V or U unit go in A: the row of output i of ID h
+// and the column of candidate l (V), or the row of candidate l and the
+// column of input b of ID h (U).  The plain stage packs them densely; the
+// fused two-stage groups place them on their register tiles.
+struct DenseMap {
+  __device__ int vrow(int h, int i, int k0) const { return (h ? k0 : 0) + i; }
+  __device__ int vcol(int l) const { return l; }
+  __device__ int urow(int l) const { return l; }
+  __device__ int ucol(int h, int b, int k0) const { return (h ? k0 : 0) + b; }
+  __device__ Unit vdims(int k0, int k1, int c) const { return Unit{k0 + k1, c}; }
+  __device__ Unit udims(int k0, int k1, int c) const { return Unit{c, k0 + k1}; }
+};
+
+template <int MODE, bool ADJ, typename C = float2, typename Map = DenseMap>
+__device__ Unit stage_unit(const StageArgs& A, C* s_A, int* s_src, int* s_out, int* s_red, int64_t q = -1,
+                           int rows = 0, const Map& mp = Map{}) {
+  if (q < 0) q = blockIdx.x;
+  if (rows == 0) rows = A.gemm_rows;
   const C* T = static_cast<const C*>(A.T);
   const C zero = cplx(C{}, 0.f, 0.f), one = cplx(C{}, 1.f, 0.f);
   Unit u{};
@@ -82,7 +97,7 @@ __device__ Unit stage_unit(const StageArgs& A, C* s_A, int* s_src, int* s_out, i
     }
     u = Unit{ol, K};
     const int lda = lda_for(K);
-    for (int e = threadIdx.x; e < A.gemm_rows * lda; e += blockDim.x) s_A[e] = zero;
+    for (int e = threadIdx.x; e < rows * lda; e += blockDim.x) s_A[e] = zero;
     for (int i = threadIdx.x; i < ol; i += blockDim.x) s_out[i] = obg + i;
     __syncthreads();
     int off = 0;
@@ -105,28 +120,27 @@ __device__ Unit stage_unit(const StageArgs& A, C* s_A, int* s_src, int* s_out, i
     const ApplyMeta m1 = A.meta[2 * P * A.nn + node + A.nn];
     const int c = m0.c, k0 = m0.k;
     const bool isV = (MODE == kModeV);
-    u = isV ? Unit{k0 + m1.k, c} : Unit{c, k0 + m1.k};
+    u = isV ? mp.vdims(k0, m1.k, c) : mp.udims(k0, m1.k, c);
     const int lda = lda_for(u.K);
-    for (int e = threadIdx.x; e < A.gemm_rows * lda; e += blockDim.x) s_A[e] = zero;
+    for (int e = threadIdx.x; e < rows * lda; e += blockDim.x) s_A[e] = zero;
     __syncthreads();  // zero fill before the identity entries
     for (int e = threadIdx.x; e < 2 * kMaxMg; e += blockDim.x) {  // (ID h, candidate position l)
       const int h = e / kMaxMg, l = e % kMaxMg;
       const ApplyMeta& m = h ? m1 : m0;
-      const int base = h ? k0 : 0;  // first row (V) or column (U) of ID h in A
       if (l < m.k) {
-        if (isV) s_out[base + l] = m.skel_off + l;
-        else s_src[base + l] = m.skel_off + l;
+        if (isV) s_out[mp.vrow(h, l, k0)] = m.skel_off + l;
+        else s_src[mp.ucol(h, l, k0)] = m.skel_off + l;
       }
       if (l < c) {
         if (h == 0) {
-          if (isV) s_src[l] = m.cand_beg + l;
-          else s_out[l] = m.cand_beg + l;
+          if (isV) s_src[mp.vcol(l)] = m.cand_beg + l;
+          else s_out[mp.urow(l)] = m.cand_beg + l;
         }
         const int below = l < 64 ? __popcll(m.mask & lanes_below(l))
                                  : __popcll(m.mask) + __popcll(m.mask_hi & lanes_below(l - 64));
         if (l < 64 ? ((m.mask >> l) & 1ull) : ((m.mask_hi >> (l - 64)) & 1ull)) {
-          if (isV) s_A[(base + below) * lda + l] = one;
-          else s_A[l * lda + base + below] = one;
+          if (isV) s_A[mp.vrow(h, below, k0) * lda + mp.vcol(l)] = one;
+          else s_A[mp.urow(l) * lda + mp.ucol(h, below, k0)] = one;
         } else {
           s_red[h * kMaxMg + l - below] = l;
         }
@@ -138,13 +152,13 @@ __device__ Unit stage_unit(const StageArgs& A, C* s_A, int* s_src, int* s_out, i
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const ApplyMeta& m = h ? m1 : m0;
-      const int k = m.k, r = c - k, base = h ? k0 : 0;
+      const int k = m.k, r = c - k;
       for (int e = threadIdx.x; e < k * r; e += blockDim.x) {
         const int i = colmajor ? e % k : e / r, j = colmajor ? e / k : e % r;
         C v = T[m.t_off + e];
         if (ADJ) v.y = -v.y;
-        if (isV) s_A[(base + i) * lda + s_red[h * kMaxMg + j]] = v;
-        else s_A[s_red[h * kMaxMg + j] * lda + base + i] = v;
+        if (isV) s_A[mp.vrow(h, i, k0) * lda + mp.vcol(s_red[h * kMaxMg + j])] = v;
+        else s_A[mp.urow(s_red[h * kMaxMg + j]) * lda + mp.ucol(h, i, k0)] = v;
       }
     }
   }
@@ -182,8 +196,8 @@ __global__ __launch_bounds__(64 * kWavesG) void apply_gemm_bf16(StageArgs A) {
   const float2* in = static_cast<const float2*>(A.in);
   float2* out = static_cast<float2*>(A.out);
   const int lda = lda_for(u.K);
-  for (int it = 0; it < kRhsIterB; ++it) {
-    const int64_t rhs0 = ((blockIdx.y * (int64_t)kRhsIterB + it) * blocks + w / tiles) * kRhsPerWave;
+  for (int it = 0; it < A.rhs_iter; ++it) {
+    const int64_t rhs0 = ((blockIdx.y * (int64_t)A.rhs_iter + it) * blocks + w / tiles) * kRhsPerWave;
     if (rhs0 >= nr) return;
     const int64_t n0 = rhs0 + 2 * jj;
     const bool ok0 = n0 < nr, ok1 = n0 + 1 < nr;
@@ -278,8 +292,8 @@ __global__ __launch_bounds__(64 * kWavesG16) void apply_gemm16(StageArgs A) {
   const int64_t nr = A.nrhs;
   const float2* in = static_cast<const float2*>(A.in);
   float2* out = static_cast<float2*>(A.out);
-  for (int it = 0; it < kRhsIter16; ++it) {
-    const int64_t rhs0 = ((blockIdx.y * (int64_t)kRhsIter16 + it) * kWavesG16 + w) * kRhsPerWave16;
+  for (int it = 0; it < A.rhs_iter; ++it) {
+    const int64_t rhs0 = ((blockIdx.y * (int64_t)A.rhs_iter + it) * kWavesG16 + w) * kRhsPerWave16;
     if (rhs0 >= nr) return;
     const int64_t n0 = rhs0 + 2 * c16;
     const bool ok0 = n0 < nr, ok1 = n0 + 1 < nr;
@@ -330,6 +344,176 @@ __global__ __launch_bounds__(64 * kWavesG16) void apply_gemm16(StageArgs A) {
   }
 }
 
+// Fused two-stage groups (forward, FP32 MFMA).  Two consecutive V stages
+// t, t + 1 (or U stages t, t - 1) form closed groups: the level-t units
+// (2 C', P), (2 C' + 1, P) produce exactly the candidate segments of the
+// level-(t+1) units (C', 2 P), (C', 2 P + 1) -- part h of stage-1 unit u is
+// the outputs of its ID h, which stage-2 unit h reads as its u-th child.
+// The U groups are the transpose: level-t units (C, 2 Q + u) write the
+// candidates of the level-(t-1) IDs (2 C + h, 2 Q + u), the inputs of the
+// level-(t-1) units (2 C + h, Q).  A group's intermediate never leaves the
+// registers: stage 1 places part h of unit u on its own TK row tiles, so the
+// FP32 16x16x4 accumulator of tile h TK + i (lane (kq, c), register v: row
+// 16 i + 4 kq + v of the part, real column 4 c + t) is directly the B
+// operand of stage 2 for K index u 16 TK + 16 i + 4 kq + v, once stage 2's A
+// carries its columns at those indices.  All four units' A sit in LDS;
+// every ID of both levels has rank <= 16 TK.
+template <int TK>
+struct Fuse1Map {  // stage 1: each ID's (V) or child's (U) rows on TK tiles of their own
+  int c0;          // U: candidates of the first child
+  __device__ int vrow(int h, int i, int) const { return h * 16 * TK + i; }
+  __device__ int vcol(int l) const { return l; }
+  __device__ int urow(int l) const { return l < c0 ? l : 16 * TK + l - c0; }
+  __device__ int ucol(int h, int b, int k0) const { return (h ? k0 : 0) + b; }
+  __device__ Unit vdims(int, int, int c) const { return Unit{32 * TK, c}; }
+  __device__ Unit udims(int k0, int k1, int) const { return Unit{32 * TK, k0 + k1}; }
+};
+template <int TK>
+struct Fuse2Map {  // stage 2: inputs at the register tiles of stage 1
+  int kf;          // V: candidates of the first child (its rank)
+  __device__ int vrow(int h, int i, int k0) const { return (h ? k0 : 0) + i; }
+  __device__ int vcol(int l) const { return l < kf ? l : 16 * TK + l - kf; }
+  __device__ int urow(int l) const { return l; }
+  __device__ int ucol(int h, int b, int) const { return h * 16 * TK + b; }
+  __device__ Unit vdims(int k0, int k1, int) const { return Unit{k0 + k1, 32 * TK}; }
+  __device__ Unit udims(int, int, int c) const { return Unit{c, 32 * TK}; }
+};
+
+constexpr int kWavesF = 4;    // wavefronts per workgroup, 32 right-hand sides each
+constexpr int kRhsIterF = 8;  // right-hand-side blocks per wavefront
+
+template <int MODE, int TK>
+__global__ __launch_bounds__(64 * kWavesF) void apply_fused2(StageArgs A1, StageArgs A2, int lda1max, int rows2) {
+  extern __shared__ __attribute__((aligned(16))) float2 s_A[];
+  __shared__ int s_src[4][kMaxKg];
+  __shared__ int s_out[4][kMaxMg];
+  __shared__ int s_red[2 * kMaxMg];
+  constexpr int R1 = 32 * TK, TM1 = 2 * TK;  // stage-1 rows and tiles per unit
+  const int64_t g = blockIdx.x;
+  int64_t q1[2], q2[2];
+  int cut[2];  // V: rank of stage-2 unit h's first child; U: candidates of stage-1 unit u's first child
+  if constexpr (MODE == kModeV) {
+    const int64_t node = g % A2.nn, P = g / A2.nn;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      q1[u] = P * A1.nn + 2 * node + u;
+      q2[u] = (2 * P + u) * A2.nn + node;
+      cut[u] = A1.meta[(2 * P + u) * A1.nn + 2 * node].k;
+    }
+  } else {
+    const int64_t node = g % A1.nn, Q = g / A1.nn;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      q1[u] = (2 * Q + u) * A1.nn + node;
+      q2[u] = Q * A2.nn + 2 * node + u;
+      cut[u] = A2.meta[(2 * Q + u) * A2.nn + 2 * node].k;
+    }
+  }
+  const int lda2 = lda_for(32 * TK);
+  float2* sA1[2] = {s_A, s_A + R1 * lda1max};
+  float2* sA2[2] = {s_A + 2 * R1 * lda1max, s_A + 2 * R1 * lda1max + rows2 * lda2};
+  Unit u1[2], u2[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    u1[u] = stage_unit<MODE, false, float2, Fuse1Map<TK>>(A1, sA1[u], s_src[u], s_out[u], s_red, q1[u], R1,
+                                                          Fuse1Map<TK>{MODE == kModeU ? cut[u] : 0});
+    u2[u] = stage_unit<MODE, false, float2, Fuse2Map<TK>>(A2, sA2[u], s_src[2 + u], s_out[2 + u], s_red, q2[u],
+                                                          rows2, Fuse2Map<TK>{MODE == kModeV ? cut[u] : 0});
+  }
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int kq = lane >> 4, c16 = lane & 15;
+  const int64_t nr = A1.nrhs;
+  const float2* in = static_cast<const float2*>(A1.in);
+  float2* out = static_cast<float2*>(A2.out);
+  for (int it = 0; it < A1.rhs_iter; ++it) {
+    const int64_t rhs0 = ((blockIdx.y * (int64_t)A1.rhs_iter + it) * kWavesF + w) * kRhsPerWave16;
+    if (rhs0 >= nr) return;
+    const int64_t n0 = rhs0 + 2 * c16;
+    const bool ok0 = n0 < nr, ok1 = n0 + 1 < nr;
+    f32x4 acc1[2][TM1][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int mt = 0; mt < TM1; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc1[u][mt][t] = f32x4{};
+      const int K = u1[u].K, lda = lda_for(K);
+      const float2* sA = sA1[u];
+      for (int kc = 0; kc < K; kc += 16) {
+        float4 b[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int kk = kc + 4 * e + kq;
+          const int row = kk < K ? s_src[u][kk] : -1;
+          const float2* p = in + (int64_t)(row < 0 ? 0 : row) * nr + n0;
+          const float2 v0 = ld2(p, row >= 0 && ok0), v1 = ld2(p + 1, row >= 0 && ok1);
+          b[e] = make_float4(v0.x, v0.y, v1.x, v1.y);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (kc + 4 * e >= K) break;
+          const float bt[4] = {b[e].x, b[e].y, b[e].z, b[e].w};
+          const float bs[4] = {-b[e].y, b[e].x, -b[e].w, b[e].z};
+#pragma unroll
+          for (int mt = 0; mt < TM1; ++mt) {
+            const float2 av = sA[(mt * 16 + c16) * lda + kc + 4 * e + kq];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+              acc1[u][mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bt[t], acc1[u][mt][t], 0, 0, 0);
+              acc1[u][mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bs[t], acc1[u][mt][t], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    // stage 2: unit h reads part h of both stage-1 units from the registers
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int tiles = (u2[h].M + 15) / 16;  // <= 4
+      const float2* sA = sA2[h];
+      f32x4 acc[4][4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{};
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int i = 0; i < TK; ++i)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const f32x4* d = acc1[u][h * TK + i];
+            const float bt[4] = {d[0][v], d[1][v], d[2][v], d[3][v]};
+            const float bs[4] = {-d[1][v], d[0][v], -d[3][v], d[2][v]};
+            const int col = u * 16 * TK + 16 * i + 4 * kq + v;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+              if (mt >= tiles) break;
+              const float2 av = sA[(mt * 16 + c16) * lda2 + col];
+#pragma unroll
+              for (int t = 0; t < 4; ++t) {
+                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bt[t], acc[mt][t], 0, 0, 0);
+                acc[mt][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bs[t], acc[mt][t], 0, 0, 0);
+              }
+            }
+          }
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        if (mt >= tiles) break;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = mt * 16 + 4 * kq + v;
+          if (i >= u2[h].M) continue;
+          float2* p = out + (int64_t)s_out[2 + h][i] * nr + n0;
+          if (ok0) p[0] = make_float2(acc[mt][0][v], acc[mt][1][v]);
+          if (ok1) p[1] = make_float2(acc[mt][2][v], acc[mt][3][v]);
+        }
+      }
+    }
+  }
+}
+
 // FP64 on v_mfma_f64_16x16x4_f64 (complex128 data): the FP32 kernel's
 // operand layout with one complex right-hand side per lane, so a wavefront
 // covers 16 right-hand sides in two N-tiles (real and imaginary parts); lane
@@ -356,8 +540,8 @@ __global__ __launch_bounds__(64 * kWavesG16) void apply_gemm16d(StageArgs A) {
   const int64_t nr = A.nrhs;
   const double2* in = static_cast<const double2*>(A.in);
   double2* out = static_cast<double2*>(A.out);
-  for (int it = 0; it < kRhsIterD; ++it) {
-    const int64_t rhs0 = ((blockIdx.y * (int64_t)kRhsIterD + it) * kWavesG16 + w) * kRhsPerWaveD;
+  for (int it = 0; it < A.rhs_iter; ++it) {
+    const int64_t rhs0 = ((blockIdx.y * (int64_t)A.rhs_iter + it) * kWavesG16 + w) * kRhsPerWaveD;
     if (rhs0 >= nr) return;
     const int64_t n0 = rhs0 + c16;
     const bool ok = n0 < nr;
@@ -412,16 +596,54 @@ size_t gemm_lds_bytes(int kmax_unit, int mmax_unit, int prec) {
   return (size_t)rows * (size_t)(((kmax_unit + 15) & ~15) + 2) * elem;
 }
 
+size_t fused2_lds_bytes(int tk, int kmax1, int mmax2) {
+  const int r1 = 32 * tk, r2 = (mmax2 + 15) & ~15;
+  return sizeof(float2) * (2 * (size_t)r1 * lda_for(kmax1) + 2 * (size_t)r2 * lda_for(32 * tk));
+}
+
+hipError_t launch_apply_fused2(const StageArgs& a1, const StageArgs& a2, int mode, int tk, int kmax1, int mmax2,
+                               hipStream_t st) {
+  if (a1.n <= 0 || a1.nrhs <= 0) return hipSuccess;
+  if ((tk != 1 && tk != 2) || kmax1 < 1 || kmax1 > kMaxKg || mmax2 < 1 || mmax2 > 64 || (a1.n & 1) ||
+      a1.rhs_iter < 0 || a1.rhs_iter > kMaxRhsIter)
+    return hipErrorInvalidValue;
+  const size_t lds = fused2_lds_bytes(tk, kmax1, mmax2);
+  if (lds > kMaxFusedLds) return hipErrorInvalidValue;
+  const int rows2 = (mmax2 + 15) & ~15, lda1 = lda_for(kmax1);
+  StageArgs b1 = a1;
+  if (b1.rhs_iter == 0) b1.rhs_iter = kRhsIterF;
+  const int64_t per_block = (int64_t)b1.rhs_iter * kWavesF * kRhsPerWave16;
+  const dim3 grid((unsigned)(a1.n / 2), (unsigned)((a1.nrhs + per_block - 1) / per_block));
+#define IDBF_FUSED2(M, TK)                                                                           \
+  do {                                                                                               \
+    if (lds > (size_t(64) << 10)) {                                                                  \
+      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_fused2<M, TK>),       \
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
+      if (e_ != hipSuccess) return e_;                                                               \
+    }                                                                                                \
+    hipLaunchKernelGGL((apply_fused2<M, TK>), grid, dim3(64 * kWavesF), lds, st, b1, a2, lda1, rows2); \
+  } while (0)
+  if (mode == kModeV) {
+    if (tk == 1) IDBF_FUSED2(kModeV, 1); else IDBF_FUSED2(kModeV, 2);
+  } else {
+    if (tk == 1) IDBF_FUSED2(kModeU, 1); else IDBF_FUSED2(kModeU, 2);
+  }
+#undef IDBF_FUSED2
+  return hipGetLastError();
+}
+
 hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int mmax_unit, int prec,
                              hipStream_t st, bool adj) {
   if (a0.n <= 0 || a0.nrhs <= 0) return hipSuccess;
   if (kmax_unit < 1 || kmax_unit > kMaxKg || mmax_unit < 1 || mmax_unit > kMaxMg) return hipErrorInvalidValue;
   if (gemm_lds_bytes(kmax_unit, mmax_unit, prec) > kMaxGemmLds) return hipErrorInvalidValue;
+  if (a0.rhs_iter < 0 || a0.rhs_iter > kMaxRhsIter) return hipErrorInvalidValue;
   StageArgs a = a0;
   const bool bf16 = prec == kGemmBf16;
   if (prec == kGemmF64) {  // FP64: the FP32 kernel's layout, 16 right-hand sides per wavefront
     a.gemm_rows = (mmax_unit + 15) & ~15;
-    const int64_t per_block = (int64_t)kRhsIterD * kWavesG16 * kRhsPerWaveD;
+    if (a.rhs_iter == 0) a.rhs_iter = kRhsIterD;
+    const int64_t per_block = (int64_t)a.rhs_iter * kWavesG16 * kRhsPerWaveD;
     const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
     const size_t lds = gemm_lds_bytes(kmax_unit, mmax_unit, prec);
 #define IDBF_GEMM16D(M, J, TM)                                                                       \
@@ -448,7 +670,8 @@ hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int m
   }
   if (!bf16) {  // FP32: 16-row tiles, one wavefront per 32 right-hand sides over all of them
     a.gemm_rows = (mmax_unit + 15) & ~15;
-    const int64_t per_block = (int64_t)kRhsIter16 * kWavesG16 * kRhsPerWave16;
+    if (a.rhs_iter == 0) a.rhs_iter = kRhsIter16;
+    const int64_t per_block = (int64_t)a.rhs_iter * kWavesG16 * kRhsPerWave16;
     const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
     const size_t lds = (size_t)a.gemm_rows * (size_t)(((kmax_unit + 15) & ~15) + 2) * sizeof(float2);
 #define IDBF_GEMM16(M, J, TM)                                                                        \
@@ -476,7 +699,8 @@ hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int m
   a.gemm_rows = (mmax_unit + 31) & ~31;  // BF16 split: 32-row tiles
   const int tiles_m = a.gemm_rows / 32;
   const int blocks_rhs = std::max(1, kWavesG / tiles_m);
-  const int64_t per_block = (int64_t)blocks_rhs * kRhsPerWave * kRhsIterB;
+  if (a.rhs_iter == 0) a.rhs_iter = kRhsIterB;
+  const int64_t per_block = (int64_t)blocks_rhs * kRhsPerWave * a.rhs_iter;
   const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
   const dim3 block(64 * blocks_rhs * tiles_m);
   const size_t lds = (size_t)a.gemm_rows * (size_t)(((kmax_unit + 15) & ~15) + 2) * sizeof(float2);

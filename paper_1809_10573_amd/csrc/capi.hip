@@ -417,6 +417,8 @@ struct idbf_handle_s {
   uint64_t seed = 0;
   int live_plans = 0;          // captured plans that hold this handle's workspace pointer
   bool force_reject = false;   // IDBF_FLAG_PROPOSER_FORCE_REJECT
+  bool apply_fuse = true;      // many-RHS apply: fused two-stage groups where eligible
+  int rhs_iter = 0;            // many-RHS apply: right-hand-side blocks per workgroup (0: kernel default)
   bool truncate = false;       // IDBF_FLAG_ALLOW_TRUNCATE
 
   ~idbf_handle_s() {
@@ -1308,6 +1310,34 @@ idbf_status idbf_release_cached_memory(void) {
   return IDBF_OK;
 }
 
+idbf_status idbf_get_apply_config(idbf_handle h, idbf_apply_config* cfg) {
+  g_err[0] = 0;
+  if (!h || !cfg) {
+    set_error("get_apply_config: NULL handle or config");
+    return IDBF_EINVAL;
+  }
+  *cfg = idbf_apply_config{};
+  cfg->fuse = h->apply_fuse ? 1 : 0;
+  cfg->rhs_iter = h->rhs_iter;
+  return IDBF_OK;
+}
+
+idbf_status idbf_set_apply_config(idbf_handle h, const idbf_apply_config* cfg) {
+  g_err[0] = 0;
+  if (!h || !cfg) {
+    set_error("set_apply_config: NULL handle or config");
+    return IDBF_EINVAL;
+  }
+  const int r = cfg->rhs_iter;
+  if ((cfg->fuse != 0 && cfg->fuse != 1) || r < 0 || r > kMaxRhsIter || (r & (r - 1)) != 0) {
+    set_error("set_apply_config: fuse must be 0 or 1 and rhs_iter 0 or a power of two <= %d", kMaxRhsIter);
+    return IDBF_EINVAL;
+  }
+  h->apply_fuse = cfg->fuse == 1;
+  h->rhs_iter = r;
+  return IDBF_OK;
+}
+
 namespace {
 
 // The stage arguments of level t of one side, shared by the apply and its
@@ -1394,12 +1424,43 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
        {"adj1d_v", "adj1d_s", "adj1d_u"}, {"adjnd_v", "adjnd_s", "adjnd_u"}}};
   const int kind = bf16 ? 2 : fp64 ? (nrhs == 1 ? 3 : 4) : (nrhs == 1 ? 0 : 1);
   auto name = [&](char stage) { return kNames[adj][kind][stage == 'v' ? 0 : stage == 's' ? 1 : 2]; };
+  // fused two-stage groups (complex64 FP32 MFMA, forward): the rank bound
+  // of both levels picks the register tiles per part (0: not fusable)
+  const bool fuse = h->apply_fuse && !adj && prec == kGemmF32 && nrhs > 1;
+  auto fuse_tk = [&](const Batch& b1, const Batch& b2, int kmax1, int mmax2) {
+    const int r = std::max(b1.rank_max, b2.rank_max);
+    const int tk = r <= 16 ? 1 : r <= 32 ? 2 : 0;
+    if (!tk || kmax1 > 256 || mmax2 > 64 || fused2_lds_bytes(tk, kmax1, mmax2) > kMaxFusedLds) return 0;
+    return tk;
+  };
   // V-shaped stages: V_t forward (t = 1..H), U_t^H in the adjoint (t = 1..H)
   for (int t = 1; t <= h->H; ++t) {
     const Batch& b = adj ? h->U[t - 1] : h->V[t - 1];
     StageArgs a = level_stage(b, fp64, nrhs);
+    a.rhs_iter = h->rhs_iter;
     a.in = in;
     a.out = buf[cur];
+    if (fuse && t < h->H) {
+      const Batch& b2 = h->V[t];
+      const int tk = fuse_tk(b, b2, b.cand_max, 2 * b2.rank_max);
+      if (tk) {
+        a.n = b.n / 2;
+        a.nn = 1 << (h->L - t + 1);
+        StageArgs a2 = level_stage(b2, fp64, nrhs);
+        a2.n = b2.n / 2;
+        a2.nn = 1 << (h->L - t);
+        a2.out = buf[cur];
+        const double bytes = double(b.nnz_T + b2.nnz_T) * elem + 8.0 * (b.n + b2.n) +
+                             (t == 1 ? double(h->N) * nrhs * elem : 0.0);
+        const int pr = h->prof.begin("applyn_vv", st);
+        IDBF_HIP_CHECK(launch_apply_fused2(a, a2, 0, tk, b.cand_max, 2 * b2.rank_max, st));
+        h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T + b2.nnz_T) * nrhs);
+        in = buf[cur];
+        cur ^= 1;
+        ++t;
+        continue;
+      }
+    }
     const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
     const int pr = h->prof.begin(name(adj ? 'u' : 'v'), st);
     if (mfma && fits(b.cand_max, 2 * b.rank_max)) {  // units: the ID pairs (C, 2P), (C, 2P + 1) sharing a segment
@@ -1416,6 +1477,7 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
   }
   {
     StageArgs a{};
+    a.rhs_iter = h->rhs_iter;
     a.n = (h->H == 0) ? 1 : (adj ? h->V[h->H - 1].n : h->U[h->H - 1].n);
     a.nn = (h->H == 0) ? 1 : (1 << (h->L - h->H + 1));  // 2^d, used by the adjoint grouping
     a.nrhs = nrhs;
@@ -1449,10 +1511,30 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
   for (int t = h->H; t >= 1; --t) {
     const Batch& b = adj ? h->V[t - 1] : h->U[t - 1];
     StageArgs a = level_stage(b, fp64, nrhs);
+    a.rhs_iter = h->rhs_iter;
     a.n = int64_t(1) << h->L;  // units: one per (node, parent partner)
     a.nn = 1 << (h->L - t + 1);
     a.in = in;
     a.out = (t == 1) ? y : buf[cur];
+    if (fuse && t > 1) {
+      const Batch& b2 = h->U[t - 2];
+      const int tk = fuse_tk(b, b2, 2 * b.rank_max, b2.cand_max);
+      if (tk) {
+        StageArgs a2 = level_stage(b2, fp64, nrhs);
+        a2.n = int64_t(1) << h->L;
+        a2.nn = 1 << (h->L - t + 2);
+        a2.out = (t == 2) ? y : buf[cur];
+        const double bytes = double(b.nnz_T + b2.nnz_T) * elem + 8.0 * (b.n + b2.n) +
+                             (t == 2 ? double(h->N) * nrhs * elem : 0.0);
+        const int pr = h->prof.begin("applyn_uu", st);
+        IDBF_HIP_CHECK(launch_apply_fused2(a, a2, 2, tk, 2 * b.rank_max, b2.cand_max, st));
+        h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T + b2.nnz_T) * nrhs);
+        in = a2.out;
+        cur ^= 1;
+        --t;
+        continue;
+      }
+    }
     const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
     const int pr = h->prof.begin(name(adj ? 'v' : 'u'), st);
     if (mfma && fits(2 * b.rank_max, b.cand_max))

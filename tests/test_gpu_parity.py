@@ -350,6 +350,81 @@ def test_many_rhs_matrix_core_paths(N, leaf, kind, tol, os_, nrhs):
         assert col.max() < 10 * bound       # every column, tails included
 
 
+def _expected_fused_launches(levels, H):
+    """Stage pairs the apply fuses, from the documented rule: greedy from
+    V_1 up and from U_H down, a pair where both levels' ranks are <= 32, the
+    second stage's output rows <= 64 and the four staged blocks fit 152 KiB
+    of LDS (FP32 complex, 16-row tiles, rows padded to 16 plus 2)."""
+    lda = lambda K: ((K + 15) & ~15) + 2
+    def ok(r1, r2, kmax1, mmax2):
+        r = max(r1, r2)
+        tk = 1 if r <= 16 else 2 if r <= 32 else 0
+        lds = 8 * (2 * 32 * tk * lda(kmax1) + 2 * ((mmax2 + 15) & ~15) * lda(32 * tk))
+        return tk > 0 and kmax1 <= 256 and mmax2 <= 64 and lds <= 152 * 1024
+    n, t = 0, 1
+    while t <= H:
+        a, b = levels[t - 1]["V"], levels[t]["V"] if t < H else None
+        if b is not None and ok(a["rank_max"], b["rank_max"], a["cand_max"], 2 * b["rank_max"]):
+            n, t = n + 1, t + 2
+        else:
+            t += 1
+    t = H
+    while t >= 1:
+        a, b = levels[t - 1]["U"], levels[t - 2]["U"] if t > 1 else None
+        if b is not None and ok(a["rank_max"], b["rank_max"], 2 * a["rank_max"], b["cand_max"]):
+            n, t = n + 1, t - 2
+        else:
+            t -= 1
+    return n
+
+
+@pytest.mark.parametrize("N,leaf,kind,tol,os_,fusable", [
+    (2048, 16, "fio", 1e-6, 2, True),     # H = 3: one V pair, one U pair, one stage each left over
+    (4096, 16, "fio", 1e-6, 2, True),     # H = 4: every stage in a pair
+    (1024, 8, "dft", 1e-10, 1, True),     # ranks <= 16: one register tile per part
+    (256, 2, "fio", 1e-8, 1, True),
+    (4096, 16, "fio_m4", 1e-6, 2, False),  # ranks above 32: one launch per stage
+])
+@pytest.mark.parametrize("nrhs", [2, 65, 1100])
+def test_fused_stage_groups(N, leaf, kind, tol, os_, fusable, nrhs):
+    """The fused two-stage groups of the complex64 many-RHS apply against the
+    oracle's FP64 apply and against the per-stage kernels on the same
+    factors; the right-hand-side blocking changes no bit of the result."""
+    if kind == "fio_m4":
+        ph, (X, O) = I.fio_phase(1.0, 4.0), I.uniform_grid(N)
+    else:
+        ph, X, O = _workload(kind, N)
+    F = oracle.build(ph, X, O, leaf, tol, oversample=os_)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=os_, device=DEV, profile=True)
+    assert fac.apply_config() == {"fuse": 1, "rhs_iter": 0}
+    G = I.gaussian_vectors(N, nrhs, seed=3 + nrhs)
+    Y_or = oracle.apply(F, G)
+    x = torch.as_tensor(G, device=DEV).to(torch.complex64)
+    fac.profile(reset=True)
+    Yf = fac.apply(x)
+    prof = fac.profile(reset=True)
+    fused = prof.get("applyn_vv", {}).get("launches", 0) + prof.get("applyn_uu", {}).get("launches", 0)
+    H = fac.info()["H"]
+    expect = _expected_fused_launches(fac.stats()["per_level"], H)
+    assert fused == expect
+    assert (expect == 2 * (H // 2)) if fusable else (0 < expect < 2 * (H // 2)), expect
+    yf = Yf.cpu().numpy()
+    assert oracle.relative_error(yf, Y_or) < 2e-6
+    col = np.linalg.norm(yf - Y_or, axis=0) / np.linalg.norm(Y_or, axis=0)
+    assert col.max() < 2e-5
+    fac.set_apply_config(fuse=0)
+    Ys = fac.apply(x)
+    assert fac.profile(reset=True).get("applyn_vv") is None
+    assert oracle.relative_error(yf, Ys.cpu().numpy()) < 1e-6
+    fac.set_apply_config(fuse=1)
+    for r in (1, 2, 16):
+        fac.set_apply_config(rhs_iter=r)
+        assert torch.equal(fac.apply(x), Yf), r
+    with pytest.raises(B.IdbfError):
+        fac.set_apply_config(rhs_iter=3)
+    assert fac.apply_config() == {"fuse": 1, "rhs_iter": 16}
+
+
 def test_wide_ranks_construct_and_every_apply_path():
     """c(x) = (2 + sin 8 pi x)/8 at N = 4096 (leaf 16, tol 1e-6, t = 2): ranks
     reach the 40s and candidate sets exceed 64, so the two-candidates-per-lane
