@@ -283,12 +283,30 @@ idbf_status idbf_release_cached_memory(void);
 typedef struct idbf_apply_config {
   int32_t fuse;
   int32_t rhs_iter;
-  int32_t reserved[6];
+  int32_t from_cache; /* idbf_tune_apply's answer: 1 if read from its cache file */
+  float ms;           /* idbf_tune_apply's answer: the chosen configuration's time per apply */
+  int32_t reserved[4];
 } idbf_apply_config;
 /* Read or replace a handle's apply configuration (IDBF_EINVAL on NULL
  * arguments or values outside the ranges above; nothing changes then). */
 idbf_status idbf_get_apply_config(idbf_handle h, idbf_apply_config* cfg);
 idbf_status idbf_set_apply_config(idbf_handle h, const idbf_apply_config* cfg);
+
+/* Autotuner of the many-RHS apply (not in the paper): times every
+ * configuration (fuse 1 and 0 for complex64; rhs_iter 1, 2, 4, ... up to 16
+ * or the number of right-hand-side blocks) on this handle's factors for
+ * (nrhs, dtype) -- one warm-up and three forward applies each, HIP events on
+ * `stream` -- and sets the fastest on the handle (*chosen, nullable, gets it
+ * with its time).  cache_path (nullable): a text file, one line per tuned
+ * problem, "<key>\t<fuse> <rhs_iter> <ms>", the key naming the device's
+ * architecture, N, L, H, nrhs, dtype and every level's rank and candidate
+ * bounds; a problem found there is set without timing (from_cache = 1), and
+ * a newly tuned one is appended.  The library allocates two N x nrhs
+ * operands for the timing (IDBF_ENOMEM if it cannot) and frees them before
+ * returning.  Synchronizes `stream`.  The handle's configuration is
+ * unchanged if an error is returned. */
+idbf_status idbf_tune_apply(idbf_handle h, int64_t nrhs, int32_t dtype, const char* cache_path, void* stream,
+                            idbf_apply_config* chosen);
 
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* idbf_last_error(void);

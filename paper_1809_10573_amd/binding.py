@@ -33,7 +33,7 @@ EXPORTED = [
     "idbf_rank_samples", "idbf_apply_batched_plan", "idbf_plan_launch", "idbf_plan_destroy",
     "idbf_apply_adjoint", "idbf_release_cached_memory", "idbf_stats", "idbf_batch_proposal",
     "idbf_apply_noalloc", "idbf_skeleton_samples", "idbf_batch_skeleton_proposal",
-    "idbf_get_apply_config", "idbf_set_apply_config",
+    "idbf_get_apply_config", "idbf_set_apply_config", "idbf_tune_apply",
 ]
 MLP_INPUTS = 8
 FLAG_PROFILE, FLAG_PROPOSER_FORCE_REJECT, FLAG_ALLOW_TRUNCATE = 1, 2, 4
@@ -93,7 +93,8 @@ class Stats_t(C.Structure):
 
 
 class ApplyConfig_t(C.Structure):
-    _fields_ = [("fuse", C.c_int32), ("rhs_iter", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("fuse", C.c_int32), ("rhs_iter", C.c_int32), ("from_cache", C.c_int32), ("ms", C.c_float),
+                ("reserved", C.c_int32 * 4)]
 
 
 class KernelStat_t(C.Structure):
@@ -151,6 +152,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_batch_skeleton_proposal.argtypes = [VP, I32, I32, VP, VP]
     lib.idbf_get_apply_config.argtypes = [VP, P(ApplyConfig_t)]
     lib.idbf_set_apply_config.argtypes = [VP, P(ApplyConfig_t)]
+    lib.idbf_tune_apply.argtypes = [VP, I64, I32, C.c_char_p, VP, P(ApplyConfig_t)]
     lib.idbf_apply_batched_plan.argtypes = [I32, P(VP), P(VP), P(VP), P(I64), I32, VP, P(VP)]
     lib.idbf_plan_launch.argtypes = [VP, VP]
     lib.idbf_plan_destroy.argtypes = [VP]
@@ -354,6 +356,13 @@ class Factorization:
         cfg.fuse = cur["fuse"] if fuse is None else int(fuse)
         cfg.rhs_iter = cur["rhs_iter"] if rhs_iter is None else int(rhs_iter)
         _check(load().idbf_set_apply_config(self._h, C.byref(cfg)))
+
+    def tune_apply(self, nrhs: int, dtype: int = C64, cache_path: str | None = None, stream=None) -> dict:
+        """idbf_tune_apply: time the apply configurations for (nrhs, dtype), keep the fastest."""
+        cfg = ApplyConfig_t()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(load().idbf_tune_apply(self._h, int(nrhs), int(dtype), path, _stream(stream), C.byref(cfg)))
+        return {"fuse": cfg.fuse, "rhs_iter": cfg.rhs_iter, "from_cache": bool(cfg.from_cache), "ms": cfg.ms}
 
     def profile(self, reset: bool = True) -> dict:
         """{kernel name: {launches, ms, bytes, flops}} since the last reset (IDBF_FLAG_PROFILE)."""

@@ -379,7 +379,7 @@ struct Fuse2Map {  // stage 2: inputs at the register tiles of stage 1
   __device__ Unit udims(int, int, int c) const { return Unit{c, 32 * TK}; }
 };
 
-constexpr int kWavesF = 4;    // wavefronts per workgroup, 32 right-hand sides each
+constexpr int kWavesF = 8;    // wavefronts per workgroup, 32 right-hand sides each
 constexpr int kRhsIterF = 8;  // right-hand-side blocks per wavefront
 
 template <int MODE, int TK>
@@ -440,8 +440,8 @@ __global__ __launch_bounds__(64 * kWavesF) void apply_fused2(StageArgs A1, Stage
         for (int t = 0; t < 4; ++t) acc1[u][mt][t] = f32x4{};
       const int K = u1[u].K, lda = lda_for(K);
       const float2* sA = sA1[u];
-      for (int kc = 0; kc < K; kc += 16) {
-        float4 b[4];
+      // the rows of K block kc, four per lane (zero past K)
+      auto load = [&](float4* b, int kc) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int kk = kc + 4 * e + kq;
@@ -450,6 +450,11 @@ __global__ __launch_bounds__(64 * kWavesF) void apply_fused2(StageArgs A1, Stage
           const float2 v0 = ld2(p, row >= 0 && ok0), v1 = ld2(p + 1, row >= 0 && ok1);
           b[e] = make_float4(v0.x, v0.y, v1.x, v1.y);
         }
+      };
+      float4 b[4], bn[4];
+      load(b, 0);
+      for (int kc = 0; kc < K; kc += 16) {
+        if (kc + 16 < K) load(bn, kc + 16);  // next block in flight during this one's products
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           if (kc + 4 * e >= K) break;
@@ -465,6 +470,8 @@ __global__ __launch_bounds__(64 * kWavesF) void apply_fused2(StageArgs A1, Stage
             }
           }
         }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) b[e] = bn[e];
       }
     }
     // stage 2: unit h reads part h of both stage-1 units from the registers

@@ -11,6 +11,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "kernels.hpp"
@@ -1555,6 +1556,158 @@ idbf_status idbf_apply(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
 
 idbf_status idbf_apply_adjoint(idbf_handle h, const void* x, void* y, int64_t nrhs, int32_t dtype, void* stream) {
   return apply_impl(h, x, y, nrhs, dtype, stream, true);
+}
+
+}  // extern "C"
+
+namespace {
+
+// The tuner's cache key: device, shape, the per-level rank and candidate
+// bounds that decide every launch's tiles, right-hand sides and data type.
+std::string tune_key(const idbf_handle_s* h, int64_t nrhs, int32_t dtype) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    std::snprintf(prop.gcnArchName, sizeof prop.gcnArchName, "unknown");
+  }
+  std::string key = std::string(prop.gcnArchName) + " N=" + std::to_string(h->N) + " L=" + std::to_string(h->L) +
+                    " H=" + std::to_string(h->H) + " nrhs=" + std::to_string(nrhs) + " dtype=" + std::to_string(dtype) +
+                    " ranks=";
+  for (int t = 0; t < h->H; ++t)
+    key += std::to_string(h->V[t].rank_max) + "/" + std::to_string(h->V[t].cand_max) + "," +
+           std::to_string(h->U[t].rank_max) + "/" + std::to_string(h->U[t].cand_max) + ";";
+  for (char& ch : key)
+    if (ch == '\t' || ch == '\n') ch = ' ';
+  return key;
+}
+
+std::mutex& tune_file_mutex() {
+  static std::mutex m;
+  return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+idbf_status idbf_tune_apply(idbf_handle h, int64_t nrhs, int32_t dtype, const char* cache_path, void* stream,
+                            idbf_apply_config* chosen) {
+  g_err[0] = 0;
+  if (!h || nrhs < 1 || (dtype != IDBF_C128 && dtype != IDBF_C64 && dtype != IDBF_C64_BF16X3)) {
+    set_error("tune_apply: NULL handle, nrhs < 1 or unknown dtype");
+    return IDBF_EINVAL;
+  }
+  const std::string key = tune_key(h, nrhs, dtype);
+  auto finish = [&](int fuse, int rhs_iter, float ms, bool cached) {
+    h->apply_fuse = fuse == 1;
+    h->rhs_iter = rhs_iter;
+    if (chosen) {
+      *chosen = idbf_apply_config{};
+      chosen->fuse = fuse;
+      chosen->rhs_iter = rhs_iter;
+      chosen->from_cache = cached ? 1 : 0;
+      chosen->ms = ms;
+    }
+    return IDBF_OK;
+  };
+  if (cache_path) {  // "<key>\t<fuse> <rhs_iter> <ms>" per line; the last line for a key wins
+    std::lock_guard<std::mutex> lock(tune_file_mutex());
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      std::vector<char> line(8192);
+      int fuse = -1, rhs_iter = 0;
+      float ms = 0.f;
+      while (std::fgets(line.data(), (int)line.size(), f)) {
+        char* tab = std::strchr(line.data(), '\t');
+        if (!tab || std::string(line.data(), tab) != key) continue;
+        int fz = 0, ri = 0;
+        float m = 0.f;
+        if (std::sscanf(tab + 1, "%d %d %f", &fz, &ri, &m) == 3 && (fz == 0 || fz == 1) && ri >= 0 &&
+            ri <= kMaxRhsIter && (ri & (ri - 1)) == 0) {
+          fuse = fz;
+          rhs_iter = ri;
+          ms = m;
+        }
+      }
+      std::fclose(f);
+      if (fuse >= 0) return finish(fuse, rhs_iter, ms, true);
+    }
+  }
+  // time every candidate on scratch operands (an arbitrary finite pattern:
+  // the kernels' timing does not depend on the values)
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t elem = dtype == IDBF_C128 ? 16 : 8;
+  const size_t bytes = size_t(h->N) * size_t(nrhs) * elem;
+  void *x = nullptr, *y = nullptr;
+  if (hipMalloc(&x, bytes) != hipSuccess || hipMalloc(&y, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    if (x) (void)hipFree(x);
+    set_error("tune_apply: cannot allocate %zu bytes of operands", 2 * bytes);
+    return IDBF_ENOMEM;
+  }
+  struct Free {
+    void *a, *b;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Free() {
+      (void)hipFree(a);
+      (void)hipFree(b);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } fr{x, y};
+  IDBF_HIP_CHECK(hipMemsetAsync(x, 0x3c, bytes, st));
+  IDBF_HIP_CHECK(hipEventCreate(&fr.e0));
+  IDBF_HIP_CHECK(hipEventCreate(&fr.e1));
+  const bool keep_fuse = h->apply_fuse;
+  const int keep_iter = h->rhs_iter;
+  const bool prof = h->prof.on;
+  h->prof.on = false;
+  const bool fusable = dtype == IDBF_C64 && nrhs > 1;
+  const int64_t per_wave = dtype == IDBF_C128 ? 16 : dtype == IDBF_C64_BF16X3 ? 64 : 32;
+  const int64_t blocks = (nrhs + 4 * per_wave - 1) / (4 * per_wave);  // right-hand-side blocks of 4 wavefronts
+  int best_fuse = keep_fuse ? 1 : 0, best_iter = keep_iter;
+  float best = -1.f;
+  idbf_status s = IDBF_OK;
+  const std::vector<int> fuses = fusable ? std::vector<int>{1, 0} : std::vector<int>{keep_fuse ? 1 : 0};
+  for (const int fuse : fuses) {
+    if (s != IDBF_OK) break;
+    for (int r = 1; r <= 16 && s == IDBF_OK; r *= 2) {
+      if (r > 1 && (r / 2) >= blocks) break;  // more blocks per workgroup than there are
+      h->apply_fuse = fuse == 1;
+      h->rhs_iter = r;
+      s = apply_impl(h, x, y, nrhs, dtype, stream, false);  // warm-up (and workspace growth)
+      if (s != IDBF_OK) break;
+      if (hipEventRecord(fr.e0, st) != hipSuccess) s = IDBF_EHIP;
+      for (int rep = 0; rep < 3 && s == IDBF_OK; ++rep) s = apply_impl(h, x, y, nrhs, dtype, stream, false);
+      float ms = 0.f;
+      if (s == IDBF_OK && (hipEventRecord(fr.e1, st) != hipSuccess || hipEventSynchronize(fr.e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, fr.e0, fr.e1) != hipSuccess)) {
+        set_error("tune_apply: event timing failed");
+        s = IDBF_EHIP;
+      }
+      if (s != IDBF_OK) break;
+      ms /= 3.f;
+      if (best < 0.f || ms < best) {
+        best = ms;
+        best_fuse = fuse;
+        best_iter = r;
+      }
+    }
+  }
+  h->prof.on = prof;
+  if (s != IDBF_OK) {
+    h->apply_fuse = keep_fuse;
+    h->rhs_iter = keep_iter;
+    return s;
+  }
+  if (cache_path) {
+    std::lock_guard<std::mutex> lock(tune_file_mutex());
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "%s\t%d %d %.4f\n", key.c_str(), best_fuse, best_iter, best);
+      std::fclose(f);
+    }
+  }
+  return finish(best_fuse, best_iter, best, false);
 }
 
 }  // extern "C"

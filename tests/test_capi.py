@@ -69,6 +69,11 @@ def test_argument_errors_without_gpu():
                              fake, fake, fake, fake, None) == B.EINVAL
     assert lib.idbf_construct_batched(0, None, None, None, None, None, None, None, None) == B.EINVAL
     assert lib.idbf_apply_batched(0, None, None, None, None, B.C64, None) == B.EINVAL
+    cfg = B.ApplyConfig_t()
+    assert lib.idbf_get_apply_config(None, C.byref(cfg)) == B.EINVAL
+    assert lib.idbf_set_apply_config(None, C.byref(cfg)) == B.EINVAL
+    assert lib.idbf_tune_apply(None, 16, B.C64, None, None, C.byref(cfg)) == B.EINVAL
+    assert C.sizeof(B.ApplyConfig_t) == 32
 
 
 def test_binding_rejects_bad_operands_before_any_launch():
