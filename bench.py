@@ -520,9 +520,12 @@ def _qr_traffic() -> float | None:
 def _only(what: str) -> int:
     """Single pieces of the step for counter runs: the workload's construction
     (twice), its complex64 1-RHS apply (three times, after one construction),
-    its 1024-RHS applies (FP32 and BF16 split, once each), or a plain 1 GiB
-    device copy (three times) for calibration; or the learned proposal at full
-    scale (2000 training constructions, 200 held out)."""
+    its 1024-RHS applies (FP32 and BF16 split, once each), one whole step
+    (the construction and every apply of the step once, in the step's order,
+    with the library's per-launch event times printed for comparison with a
+    trace of the same run), or a plain 1 GiB device copy (three times) for
+    calibration; or the learned proposal at full scale (2000 training
+    constructions, 200 held out)."""
     import torch
     from paper_1809_10573_amd import binding as B
     dev = torch.device("cuda:0")
@@ -553,6 +556,25 @@ def _only(what: str) -> int:
         fac.apply(XM, YM, dtype=B.C64_BF16X3)
         torch.cuda.synchronize()
         print("applyn: one FP32 and one BF16-split apply, 1024 right-hand sides", flush=True)
+        fac.close()
+        return 0
+    if what == "step":
+        fac = B.construct(ph, X, O, W["tol"], W["leaf"], oversample=W["oversample"], device=dev, profile=True)
+        fac.reserve(1024, B.C128)
+        gen = torch.Generator(device=dev).manual_seed(4)
+        dt = {"c64": B.C64, "bf16x3": B.C64_BF16X3, "c128": B.C128}
+        for name, prec, nrhs in APPLY_KINDS:
+            x = torch.randn(W["N"], nrhs, dtype=torch.complex64 if prec != "c128" else torch.complex128,
+                            device=dev, generator=gen).squeeze(1).contiguous()
+            y = torch.empty_like(x)
+            fac.apply(x, y, dtype=dt[prec])
+            torch.cuda.synchronize()
+            del x, y
+            print(f"step: {name} done", file=sys.stderr, flush=True)
+        prof = fac.profile(reset=True)
+        print(json.dumps({"kernels": {k: {"launches": v["launches"], "ms_per_launch": v["ms"] / v["launches"],
+                                          "bytes": v["bytes"], "flops": v["flops"]}
+                                      for k, v in sorted(prof.items()) if v["launches"]}}), flush=True)
         fac.close()
         return 0
     if what == "apply1":
@@ -603,7 +625,7 @@ def main() -> int:
     ap.add_argument("--no-examples", action="store_true",
                     help="skip the non-uniform Fourier transform and Schloemilch lines")
     ap.add_argument("--no-config2", action="store_true", help="skip the N = 2^16 configuration")
-    ap.add_argument("--only", choices=["construct", "apply1", "applyn", "copy", "learned"],
+    ap.add_argument("--only", choices=["construct", "apply1", "applyn", "step", "copy", "learned"],
                     help="run one piece (counter passes; the full-scale learned proposal)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
