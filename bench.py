@@ -467,24 +467,11 @@ def _event_ms(torch, stream, fn, warm: bool = True) -> float:
     return e0.elapsed_time(e1)
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "id_qr_fio_n2p20_counters.md")
-QR_SOURCES = [os.path.join(ROOT, "paper_1809_10573_amd", "csrc", f) for f in ("id_batch.hip", "common.hpp",
-                                                                          "kernels.hpp")]
-
-
-def qr_source_hash() -> str:
-    import hashlib
-    h = hashlib.sha256()
-    for f in QR_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
-APPLY1_COUNTERS = os.path.join(ROOT, "profiles", "apply1_fio_n2p20_counters.md")
-APPLY1_SOURCES = [os.path.join(ROOT, "paper_1809_10573_amd", "csrc", f) for f in ("apply.hip", "common.hpp",
-                                                                              "kernels.hpp")]
-
+# per-launch HBM traffic of the step's kernels (FETCH_SIZE / WRITE_SIZE passes
+# over `bench.py --only step`), keyed "traffic_bytes_per_launch.<record>="
+STEP_COUNTERS = os.path.join(ROOT, "profiles", "step_fio_n2p20_counters.md")
+STEP_SOURCES = [os.path.join(ROOT, "paper_1809_10573_amd", "csrc", f)
+                for f in ("apply.hip", "apply_mfma.hip", "id_batch.hip", "common.hpp", "kernels.hpp")]
 
 def _counted_traffic(path: str, sources: list, key: str) -> float | None:
     """`key` from a committed counter summary, or None when the listed
@@ -502,19 +489,6 @@ def _counted_traffic(path: str, sources: list, key: str) -> float | None:
     if kv.get("source_sha256", "").strip() != h.hexdigest() or key not in kv:
         return None
     return float(kv[key])
-
-
-def _qr_traffic() -> float | None:
-    """HBM bytes per step of the QR kernels from the committed counter summary,
-    or None when the kernel sources changed since the counters were taken."""
-    try:
-        lines = open(COUNTERS).read().splitlines()
-    except OSError:
-        return None
-    kv = dict(l.split("=", 1) for l in lines if l.startswith(("traffic_bytes_per_step=", "source_sha256=")))
-    if kv.get("source_sha256", "").strip() != qr_source_hash():
-        return None
-    return float(kv["traffic_bytes_per_step"])
 
 
 def _only(what: str) -> int:
@@ -763,7 +737,7 @@ def main() -> int:
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = _qr_traffic() if dom_name == "id_qr" else None
+    roof["traffic"] = _counted_traffic(STEP_COUNTERS, STEP_SOURCES, "traffic_bytes_per_launch." + dom_name)
     roof["kernel"] = dom_name
     roof["launches_per_step"] = dom["launches"] / len(recs)
 
@@ -826,8 +800,8 @@ def main() -> int:
     tm = sum(v["ms"] for k, v in p1.items() if k.startswith("apply"))
     out["roofline_apply1"] = {"bound": "hbm", "achieved": tb / tm / 1e6, "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": tb / tm / 1e6 / HBM_PEAK_GBS,
-                              "traffic": _counted_traffic(APPLY1_COUNTERS, APPLY1_SOURCES,
-                                                          "traffic_bytes_per_apply"),
+                              "traffic": _counted_traffic(STEP_COUNTERS, STEP_SOURCES,
+                                                          "traffic_bytes_per_apply.c64_nrhs1"),
                               "kernels": {k: v["ms"] for k, v in p1.items()}}
     # adjoint apply y = K~^H x on the same factors (measured once), with the
     # adjoint identity as a check

@@ -269,12 +269,12 @@ idbf_status idbf_release_cached_memory(void);
 
 /* Launch configuration of the many-right-hand-side apply (a schedule of the
  * product of eq. finishIDBF, not a change to it):
- *   fuse: 1 (the default) runs each pair of consecutive V stages, and of U
- *     stages, of the complex64 FP32 forward apply as one launch over closed
- *     groups (two level-t units and the two neighbouring-level units they
- *     feed), the intermediate kept in registers, where every ID of both
- *     levels has rank <= 32; 0 runs one launch per stage.  Results agree to
- *     FP32 rounding.
+ *   fuse: 1 runs each pair of consecutive V stages, and of U stages, of the
+ *     complex64 FP32 forward apply as one launch over closed groups (two
+ *     level-t units and the two neighbouring-level units they feed), the
+ *     intermediate kept in registers, where every ID of both levels has
+ *     rank <= 32; 0 (the default) runs one launch per stage.  Results agree
+ *     to FP32 rounding.
  *   rhs_iter: right-hand-side blocks (32 complex64 or 16 complex128 columns
  *     per wavefront) each workgroup walks through with one LDS-staged
  *     factor block: 0 (the kernels' defaults: 8, complex128 16) or a power

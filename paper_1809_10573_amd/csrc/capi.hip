@@ -418,7 +418,7 @@ struct idbf_handle_s {
   uint64_t seed = 0;
   int live_plans = 0;          // captured plans that hold this handle's workspace pointer
   bool force_reject = false;   // IDBF_FLAG_PROPOSER_FORCE_REJECT
-  bool apply_fuse = true;      // many-RHS apply: fused two-stage groups where eligible
+  bool apply_fuse = false;     // many-RHS apply: fused two-stage groups where eligible
   int rhs_iter = 0;            // many-RHS apply: right-hand-side blocks per workgroup (0: kernel default)
   bool truncate = false;       // IDBF_FLAG_ALLOW_TRUNCATE
 

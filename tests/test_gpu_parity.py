@@ -396,7 +396,8 @@ def test_fused_stage_groups(N, leaf, kind, tol, os_, fusable, nrhs):
         ph, X, O = _workload(kind, N)
     F = oracle.build(ph, X, O, leaf, tol, oversample=os_)
     fac = B.construct(ph, X, O, tol, leaf, oversample=os_, device=DEV, profile=True)
-    assert fac.apply_config() == {"fuse": 1, "rhs_iter": 0}
+    assert fac.apply_config() == {"fuse": 0, "rhs_iter": 0}
+    fac.set_apply_config(fuse=1)
     G = I.gaussian_vectors(N, nrhs, seed=3 + nrhs)
     Y_or = oracle.apply(F, G)
     x = torch.as_tensor(G, device=DEV).to(torch.complex64)

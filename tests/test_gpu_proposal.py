@@ -257,23 +257,15 @@ def test_skeleton_samples_label_the_plain_skeletons():
             assert rel.min() >= 0 and rel.max() < 1
 
 
-def test_skeleton_proposals_match_the_oracle():
-    """A construction with trained rank and skeleton networks, every ID judged
-    by the oracle on the GPU's own sets: an accepted proposal is
+def _judge_skeleton_proposals(fac, ph, X, O, tol, t_os, seed, counts):
+    """Every ID of a construction with rank and skeleton proposers, judged by
+    the oracle on the GPU's own sets: an accepted proposal is
     oracle.column_id on the s' Mock-Chebyshev samples with the pivot search
-    restricted to the proposed set (same skeleton, T to the parity bound) and
-    passes oracle.mlp.residual_ok on the same check rows; a rejected one
+    restricted to the proposed set (same skeleton, T to the parity bound)
+    and passes oracle.mlp.residual_ok on the same check rows; a rejected one
     fails it (or keeps no column) and is stored as the plain pivoted ID."""
     from gpu_export import GpuLevels
-    rank, skel, _ = _train_nets(I.family_draws(4, seed=31))
-    (a, m), = I.family_draws(1, seed=32)
-    ph = I.fio_phase(a, float(m))
-    N, leaf, tol, t_os, seed, margin = 4096, 16, 1e-6, 2, 9, 3
-    X, O = I.uniform_grid(N)
-    fac = B.construct(ph, X, O, tol, leaf, oversample=t_os, device=DEV, proposer=rank, proposal_margin=margin,
-                      skeleton_proposer=skel, seed=seed)
     G = GpuLevels(fac)
-    counts = {"accepted": 0, "rejected": 0}
     for t in range(1, G.H + 1):
         for side in (B.SIDE_U, B.SIDE_V):
             proposed, used, rejected = fac.proposal(side, t)
@@ -291,25 +283,18 @@ def test_skeleton_proposals_match_the_oracle():
                 Bm = (oracle.entries(ph, X, O, samp, cand) if side == B.SIDE_V
                       else oracle.entries(ph, X, O, cand, samp).T)
                 cid = oracle.column_id(Bm, tol, among=among)
-                ok, ratio = False, np.inf
+                ok = False
                 if cid is not None:
                     pos = omlp.check_positions(seed, t, side, q, len(allowed))
                     rows = allowed[pos]
                     A = (oracle.entries(ph, X, O, rows, cand) if side == B.SIDE_V
                          else oracle.entries(ph, X, O, cand, rows).T)
                     ok = omlp.residual_ok(A, cid.skel, cid.red, cid.T, tol)
-                    E = A[:, cid.red] - A[:, cid.skel] @ cid.T
-                    ratio = np.linalg.norm(E) / (10 * tol * np.linalg.norm(A))
-                rec = G.record(side, t, q)
-                if bool(rejected[q]) == ok:
-                    print("decision differs: level", t, "side", side, "id", q, "c", len(cand), "s'", sp,
-                          "n_prop", int(n_prop[q]), "ratio", ratio, "oracle rank", None if cid is None else cid.rank,
-                          "gpu rank", len(rec.skel), "among", sorted(among.tolist()),
-                          "oracle skel", None if cid is None else cid.skel.tolist(),
-                          "gpu skel", np.searchsorted(cand, rec.skel).tolist(), flush=True)
                 assert bool(rejected[q]) == (not ok), (t, side, q)
+                rec = G.record(side, t, q)
                 if ok:
                     counts["accepted"] += 1
+                    counts["tall"] += sp > 128
                     assert int(used[q]) == sp
                 else:
                     counts["rejected"] += 1
@@ -323,7 +308,41 @@ def test_skeleton_proposals_match_the_oracle():
                 scale = max(1.0, np.abs(cid.T).max(initial=0.0))
                 assert np.max(np.abs(rec.T - cid.T), initial=0.0) <= 1e-12 * kappa * scale, (t, side, q)
             print(t, side, counts, flush=True)
+
+
+def test_skeleton_proposals_match_the_oracle():
+    rank, skel, _ = _train_nets(I.family_draws(4, seed=31))
+    (a, m), = I.family_draws(1, seed=32)
+    ph = I.fio_phase(a, float(m))
+    N, leaf, tol, t_os, seed, margin = 4096, 16, 1e-6, 2, 9, 3
+    X, O = I.uniform_grid(N)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=t_os, device=DEV, proposer=rank, proposal_margin=margin,
+                      skeleton_proposer=skel, seed=seed)
+    counts = {"accepted": 0, "rejected": 0, "tall": 0}
+    _judge_skeleton_proposals(fac, ph, X, O, tol, t_os, seed, counts)
     assert counts["accepted"] > 0 and counts["rejected"] > 0
+
+
+def test_skeleton_proposals_on_tall_samples_match_the_oracle():
+    """Proposals of more than 128 sampled rows: the restricted pivot search
+    runs on the tall sample's reduced triangular factor.  Fixed networks: a
+    rank of 24 (+4) everywhere, so s' = 5 * 28 = 140 rows, and equal scores,
+    so the proposed set is the first 32 candidates."""
+    nz = B.load().idbf_mlp_param_count(16)
+    p = np.zeros(nz, np.float32)
+    p[-1] = 24 / 16.0
+    rank = B.RankProposer(16, params=p)
+    q = np.zeros(nz, np.float32)
+    q[-1] = 0.5
+    skel = B.RankProposer(16, params=q)
+    ph = I.dft_phase()
+    N, leaf, tol, t_os, seed = 1024, 32, 1e-10, 5, 4
+    X, O = I.uniform_grid(N)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=t_os, device=DEV, proposer=rank, proposal_margin=4,
+                      skeleton_proposer=skel, seed=seed)
+    counts = {"accepted": 0, "rejected": 0, "tall": 0}
+    _judge_skeleton_proposals(fac, ph, X, O, tol, t_os, seed, counts)
+    assert counts["accepted"] > 0 and counts["rejected"] > 0 and counts["tall"] > 0
 
 
 def test_trained_skeleton_proposer_keeps_accuracy():
