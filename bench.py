@@ -386,10 +386,12 @@ def _learned(B, torch, dev, stream, n_train: int = 16, n_test: int = 6, keep: in
     base = res["plain"]
     for kind in kinds:
         r = res[kind]
-        out[kind] = {"construct_ms": float(np.mean(r["ms"])), "construct_ms_samples": [round(v, 2) for v in r["ms"][:10]],
+        out[kind] = {"construct_ms": float(np.mean(r["ms"])), "construct_ms_median": float(np.median(r["ms"])),
+                     "construct_ms_samples": [round(v, 2) for v in r["ms"][:10]],
                      "err_rows_max": max(r["err"]), "err_rows_median": float(np.median(r["err"]))}
         if kind != "plain":
             out[kind].update({"speedup": float(np.mean(base["ms"]) / np.mean(r["ms"])),
+                              "speedup_median": float(np.median(base["ms"]) / np.median(r["ms"])),
                               "sampled_entries_ratio": r["sampled"] / max(base["sampled"], 1),
                               "rejected_frac": r["rejected"] / max(r["proposed"], 1)})
     return out
