@@ -270,11 +270,11 @@ idbf_status idbf_release_cached_memory(void);
 /* Launch configuration of the many-right-hand-side apply (a schedule of the
  * product of eq. finishIDBF, not a change to it):
  *   fuse: 1 runs each pair of consecutive V stages, and of U stages, of the
- *     complex64 FP32 forward apply as one launch over closed groups (two
- *     level-t units and the two neighbouring-level units they feed), the
- *     intermediate kept in registers, where every ID of both levels has
- *     rank <= 32; 0 (the default) runs one launch per stage.  Results agree
- *     to FP32 rounding.
+ *     complex64 forward apply (FP32 MFMA or BF16 split) as one launch over
+ *     closed groups (two level-t units and the two neighbouring-level units
+ *     they feed), the intermediate kept in registers, where every ID of both
+ *     levels has rank <= 32; 0 (the default) runs one launch per stage.
+ *     Results agree to the precision's rounding.
  *   rhs_iter: right-hand-side blocks (32 complex64 or 16 complex128 columns
  *     per wavefront) each workgroup walks through with one LDS-staged
  *     factor block: 0 (the kernels' defaults: 8, complex128 16) or a power
@@ -293,7 +293,8 @@ idbf_status idbf_get_apply_config(idbf_handle h, idbf_apply_config* cfg);
 idbf_status idbf_set_apply_config(idbf_handle h, const idbf_apply_config* cfg);
 
 /* Autotuner of the many-RHS apply (not in the paper): times every
- * configuration (fuse 1 and 0 for complex64; rhs_iter 1, 2, 4, ... up to 16
+ * configuration (fuse 1 and 0 for complex64 and the BF16 split; rhs_iter 1,
+ * 2, 4, ... up to 16
  * or the number of right-hand-side blocks) on this handle's factors for
  * (nrhs, dtype) -- one warm-up and three forward applies each, HIP events on
  * `stream` -- and sets the fastest on the handle (*chosen, nullable, gets it

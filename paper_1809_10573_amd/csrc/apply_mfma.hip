@@ -382,13 +382,14 @@ struct Fuse2Map {  // stage 2: inputs at the register tiles of stage 1
 constexpr int kWavesF = 8;    // wavefronts per workgroup, 32 right-hand sides each
 constexpr int kRhsIterF = 8;  // right-hand-side blocks per wavefront
 
+// The group of workgroup blockIdx.x: its four units' A staged in LDS (stage
+// 1 at sA1[u], stage 2 at sA2[h]) with their index lists; returns the
+// units' shapes.
 template <int MODE, int TK>
-__global__ __launch_bounds__(64 * kWavesF) void apply_fused2(StageArgs A1, StageArgs A2, int lda1max, int rows2) {
-  extern __shared__ __attribute__((aligned(16))) float2 s_A[];
-  __shared__ int s_src[4][kMaxKg];
-  __shared__ int s_out[4][kMaxMg];
-  __shared__ int s_red[2 * kMaxMg];
-  constexpr int R1 = 32 * TK, TM1 = 2 * TK;  // stage-1 rows and tiles per unit
+__device__ void stage_group(const StageArgs& A1, const StageArgs& A2, int lda1max, int rows2, float2* s_A,
+                            int (*s_src)[kMaxKg], int (*s_out)[kMaxMg], int* s_red, Unit* u1, Unit* u2,
+                            float2** sA1, float2** sA2) {
+  constexpr int R1 = 32 * TK;
   const int64_t g = blockIdx.x;
   int64_t q1[2], q2[2];
   int cut[2];  // V: rank of stage-2 unit h's first child; U: candidates of stage-1 unit u's first child
@@ -410,9 +411,10 @@ __global__ __launch_bounds__(64 * kWavesF) void apply_fused2(StageArgs A1, Stage
     }
   }
   const int lda2 = lda_for(32 * TK);
-  float2* sA1[2] = {s_A, s_A + R1 * lda1max};
-  float2* sA2[2] = {s_A + 2 * R1 * lda1max, s_A + 2 * R1 * lda1max + rows2 * lda2};
-  Unit u1[2], u2[2];
+  sA1[0] = s_A;
+  sA1[1] = s_A + R1 * lda1max;
+  sA2[0] = s_A + 2 * R1 * lda1max;
+  sA2[1] = s_A + 2 * R1 * lda1max + rows2 * lda2;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     u1[u] = stage_unit<MODE, false, float2, Fuse1Map<TK>>(A1, sA1[u], s_src[u], s_out[u], s_red, q1[u], R1,
@@ -420,6 +422,19 @@ __global__ __launch_bounds__(64 * kWavesF) void apply_fused2(StageArgs A1, Stage
     u2[u] = stage_unit<MODE, false, float2, Fuse2Map<TK>>(A2, sA2[u], s_src[2 + u], s_out[2 + u], s_red, q2[u],
                                                           rows2, Fuse2Map<TK>{MODE == kModeV ? cut[u] : 0});
   }
+}
+
+template <int MODE, int TK>
+__global__ __launch_bounds__(64 * kWavesF) void apply_fused2(StageArgs A1, StageArgs A2, int lda1max, int rows2) {
+  extern __shared__ __attribute__((aligned(16))) float2 s_A[];
+  __shared__ int s_src[4][kMaxKg];
+  __shared__ int s_out[4][kMaxMg];
+  __shared__ int s_red[2 * kMaxMg];
+  constexpr int TM1 = 2 * TK;  // stage-1 tiles per unit
+  const int lda2 = lda_for(32 * TK);
+  Unit u1[2], u2[2];
+  float2 *sA1[2], *sA2[2];
+  stage_group<MODE, TK>(A1, A2, lda1max, rows2, s_A, s_src, s_out, s_red, u1, u2, sA1, sA2);
   const int lane = threadIdx.x & (kWave - 1);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int kq = lane >> 4, c16 = lane & 15;
@@ -505,6 +520,179 @@ __global__ __launch_bounds__(64 * kWavesF) void apply_fused2(StageArgs A1, Stage
               }
             }
           }
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        if (mt >= tiles) break;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = mt * 16 + 4 * kq + v;
+          if (i >= u2[h].M) continue;
+          float2* p = out + (int64_t)s_out[2 + h][i] * nr + n0;
+          if (ok0) p[0] = make_float2(acc[mt][0][v], acc[mt][1][v]);
+          if (ok1) p[1] = make_float2(acc[mt][2][v], acc[mt][3][v]);
+        }
+      }
+    }
+  }
+}
+
+// The fused groups with BF16 hi/lo split products on
+// v_mfma_f32_16x16x16_bf16 (FP32 accumulation).  Lane (kq, c) feeds K
+// indices kc + 4 kq .. kc + 4 kq + 3 of A row 16 mt + c and of its two
+// complex right-hand sides; the 16x16 accumulator layout (register v: row
+// 4 kq + v, column c) is then exactly stage 2's B operand for one 16-row
+// tile.  Each complex product is A_re B' + A_im B~ with both factors split,
+// a b ~= a_hi b_hi + a_hi b_lo + a_lo b_hi.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split4(const float* x, s16x4& hi, s16x4& lo) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    const __bf16 l = (__bf16)(x[e] - (float)h);
+    hi[e] = __builtin_bit_cast(short, h);
+    lo[e] = __builtin_bit_cast(short, l);
+  }
+}
+
+// A staged block rewritten in place, four K entries at a time, as the split
+// operands (re hi, re lo, im hi, im lo; four BF16 each): 32 bytes, the size
+// of the four complex FP32 entries they replace.  kcols is a multiple of 16.
+__device__ void presplit(float2* sA, int rows, int lda, int kcols) {
+  const int groups = kcols / 4;
+  for (int e = threadIdx.x; e < rows * groups; e += blockDim.x) {
+    float2* g = sA + (e / groups) * lda + 4 * (e % groups);
+    float re[4], im[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      re[i] = g[i].x;
+      im[i] = g[i].y;
+    }
+    s16x4 part[4];
+    split4(re, part[0], part[1]);
+    split4(im, part[2], part[3]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) reinterpret_cast<s16x4*>(g)[i] = part[i];
+  }
+}
+
+struct BOp {  // the split B operand of one K step: N-tile t, and its (re, im) -> (-im, re) rotation
+  s16x4 h[4], l[4], sh[4], sl[4];
+};
+
+__device__ __forceinline__ BOp make_bop(const float (*b)[4]) {
+  BOp o;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    float bs[4];
+    const int tp = t ^ 1;  // the other part of the same right-hand side
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bs[e] = (t & 1) ? b[tp][e] : -b[tp][e];
+    split4(b[t], o.h[t], o.l[t]);
+    split4(bs, o.sh[t], o.sl[t]);
+  }
+  return o;
+}
+
+// acc[t] += A (4 K of one row, pre-split at ap) times B
+__device__ __forceinline__ void mma_bf16(const float2* ap, const BOp& B, f32x4* acc) {
+  const s16x4* g = reinterpret_cast<const s16x4*>(ap);
+  const s16x4 arh = g[0], arl = g[1], aih = g[2], ail = g[3];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    f32x4 c = acc[t];
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(arh, B.h[t], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(arh, B.l[t], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(arl, B.h[t], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aih, B.sh[t], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aih, B.sl[t], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ail, B.sh[t], c, 0, 0, 0);
+    acc[t] = c;
+  }
+}
+
+template <int MODE, int TK>
+__global__ __launch_bounds__(64 * kWavesF) void apply_fused2b(StageArgs A1, StageArgs A2, int lda1max, int rows2) {
+  extern __shared__ __attribute__((aligned(16))) float2 s_A[];
+  __shared__ int s_src[4][kMaxKg];
+  __shared__ int s_out[4][kMaxMg];
+  __shared__ int s_red[2 * kMaxMg];
+  constexpr int TM1 = 2 * TK;
+  const int lda2 = lda_for(32 * TK);
+  Unit u1[2], u2[2];
+  float2 *sA1[2], *sA2[2];
+  stage_group<MODE, TK>(A1, A2, lda1max, rows2, s_A, s_src, s_out, s_red, u1, u2, sA1, sA2);
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    presplit(sA1[u], 32 * TK, lda_for(u1[u].K), lda_for(u1[u].K) - 2);
+    presplit(sA2[u], rows2, lda2, 32 * TK);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int kq = lane >> 4, c16 = lane & 15;
+  const int64_t nr = A1.nrhs;
+  const float2* in = static_cast<const float2*>(A1.in);
+  float2* out = static_cast<float2*>(A2.out);
+  for (int it = 0; it < A1.rhs_iter; ++it) {
+    const int64_t rhs0 = ((blockIdx.y * (int64_t)A1.rhs_iter + it) * kWavesF + w) * kRhsPerWave16;
+    if (rhs0 >= nr) return;
+    const int64_t n0 = rhs0 + 2 * c16;
+    const bool ok0 = n0 < nr, ok1 = n0 + 1 < nr;
+    f32x4 acc1[2][TM1][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int mt = 0; mt < TM1; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc1[u][mt][t] = f32x4{};
+      const int K = u1[u].K, lda = lda_for(K);
+      const float2* sA = sA1[u];
+      for (int kc = 0; kc < K; kc += 16) {
+        float b[4][4];  // N-tile t (re, im of the two right-hand sides), K index kc + 4 kq + e
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int kk = kc + 4 * kq + e;
+          const int row = kk < K ? s_src[u][kk] : -1;
+          const float2* p = in + (int64_t)(row < 0 ? 0 : row) * nr + n0;
+          const float2 v0 = ld2(p, row >= 0 && ok0), v1 = ld2(p + 1, row >= 0 && ok1);
+          b[0][e] = v0.x;
+          b[1][e] = v0.y;
+          b[2][e] = v1.x;
+          b[3][e] = v1.y;
+        }
+        const BOp B = make_bop(b);
+#pragma unroll
+        for (int mt = 0; mt < TM1; ++mt) mma_bf16(sA + (mt * 16 + c16) * lda + kc + 4 * kq, B, acc1[u][mt]);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int tiles = (u2[h].M + 15) / 16;  // <= 4
+      const float2* sA = sA2[h];
+      f32x4 acc[4][4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[mt][t] = f32x4{};
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int i = 0; i < TK; ++i) {
+          const f32x4* d = acc1[u][h * TK + i];
+          float b[4][4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) b[t][e] = d[t][e];
+          const BOp B = make_bop(b);
+          const int col = u * 16 * TK + 16 * i + 4 * kq;
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) {
+            if (mt >= tiles) break;
+            mma_bf16(sA + (mt * 16 + c16) * lda2 + col, B, acc[mt]);
+          }
+        }
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
         if (mt >= tiles) break;
@@ -609,9 +797,10 @@ size_t fused2_lds_bytes(int tk, int kmax1, int mmax2) {
 }
 
 hipError_t launch_apply_fused2(const StageArgs& a1, const StageArgs& a2, int mode, int tk, int kmax1, int mmax2,
-                               hipStream_t st) {
+                               int prec, hipStream_t st) {
   if (a1.n <= 0 || a1.nrhs <= 0) return hipSuccess;
   if ((tk != 1 && tk != 2) || kmax1 < 1 || kmax1 > kMaxKg || mmax2 < 1 || mmax2 > 64 || (a1.n & 1) ||
+      (prec != kGemmF32 && prec != kGemmBf16) ||
       a1.rhs_iter < 0 || a1.rhs_iter > kMaxRhsIter)
     return hipErrorInvalidValue;
   const size_t lds = fused2_lds_bytes(tk, kmax1, mmax2);
@@ -621,20 +810,26 @@ hipError_t launch_apply_fused2(const StageArgs& a1, const StageArgs& a2, int mod
   if (b1.rhs_iter == 0) b1.rhs_iter = kRhsIterF;
   const int64_t per_block = (int64_t)b1.rhs_iter * kWavesF * kRhsPerWave16;
   const dim3 grid((unsigned)(a1.n / 2), (unsigned)((a1.nrhs + per_block - 1) / per_block));
-#define IDBF_FUSED2(M, TK)                                                                           \
+#define IDBF_FUSED2(KERNEL, M, TK)                                                                   \
   do {                                                                                               \
     if (lds > (size_t(64) << 10)) {                                                                  \
-      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_fused2<M, TK>),       \
+      hipError_t e_ = hipFuncSetAttribute(reinterpret_cast<const void*>(&KERNEL<M, TK>),             \
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
       if (e_ != hipSuccess) return e_;                                                               \
     }                                                                                                \
-    hipLaunchKernelGGL((apply_fused2<M, TK>), grid, dim3(64 * kWavesF), lds, st, b1, a2, lda1, rows2); \
+    hipLaunchKernelGGL((KERNEL<M, TK>), grid, dim3(64 * kWavesF), lds, st, b1, a2, lda1, rows2);     \
   } while (0)
-  if (mode == kModeV) {
-    if (tk == 1) IDBF_FUSED2(kModeV, 1); else IDBF_FUSED2(kModeV, 2);
-  } else {
-    if (tk == 1) IDBF_FUSED2(kModeU, 1); else IDBF_FUSED2(kModeU, 2);
-  }
+#define IDBF_FUSED2_ALL(KERNEL)                                                                      \
+  do {                                                                                               \
+    if (mode == kModeV) {                                                                            \
+      if (tk == 1) IDBF_FUSED2(KERNEL, kModeV, 1); else IDBF_FUSED2(KERNEL, kModeV, 2);              \
+    } else {                                                                                         \
+      if (tk == 1) IDBF_FUSED2(KERNEL, kModeU, 1); else IDBF_FUSED2(KERNEL, kModeU, 2);              \
+    }                                                                                                \
+  } while (0)
+  if (prec == kGemmBf16) IDBF_FUSED2_ALL(apply_fused2b);
+  else IDBF_FUSED2_ALL(apply_fused2);
+#undef IDBF_FUSED2_ALL
 #undef IDBF_FUSED2
   return hipGetLastError();
 }

@@ -1427,7 +1427,7 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
   auto name = [&](char stage) { return kNames[adj][kind][stage == 'v' ? 0 : stage == 's' ? 1 : 2]; };
   // fused two-stage groups (complex64 FP32 MFMA, forward): the rank bound
   // of both levels picks the register tiles per part (0: not fusable)
-  const bool fuse = h->apply_fuse && !adj && prec == kGemmF32 && nrhs > 1;
+  const bool fuse = h->apply_fuse && !adj && (prec == kGemmF32 || prec == kGemmBf16) && nrhs > 1;
   auto fuse_tk = [&](const Batch& b1, const Batch& b2, int kmax1, int mmax2) {
     const int r = std::max(b1.rank_max, b2.rank_max);
     const int tk = r <= 16 ? 1 : r <= 32 ? 2 : 0;
@@ -1453,8 +1453,8 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
         a2.out = buf[cur];
         const double bytes = double(b.nnz_T + b2.nnz_T) * elem + 8.0 * (b.n + b2.n) +
                              (t == 1 ? double(h->N) * nrhs * elem : 0.0);
-        const int pr = h->prof.begin("applyn_vv", st);
-        IDBF_HIP_CHECK(launch_apply_fused2(a, a2, 0, tk, b.cand_max, 2 * b2.rank_max, st));
+        const int pr = h->prof.begin(bf16 ? "applyb_vv" : "applyn_vv", st);
+        IDBF_HIP_CHECK(launch_apply_fused2(a, a2, 0, tk, b.cand_max, 2 * b2.rank_max, prec, st));
         h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T + b2.nnz_T) * nrhs);
         in = buf[cur];
         cur ^= 1;
@@ -1527,8 +1527,8 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
         a2.out = (t == 2) ? y : buf[cur];
         const double bytes = double(b.nnz_T + b2.nnz_T) * elem + 8.0 * (b.n + b2.n) +
                              (t == 2 ? double(h->N) * nrhs * elem : 0.0);
-        const int pr = h->prof.begin("applyn_uu", st);
-        IDBF_HIP_CHECK(launch_apply_fused2(a, a2, 2, tk, 2 * b.rank_max, b2.cand_max, st));
+        const int pr = h->prof.begin(bf16 ? "applyb_uu" : "applyn_uu", st);
+        IDBF_HIP_CHECK(launch_apply_fused2(a, a2, 2, tk, 2 * b.rank_max, b2.cand_max, prec, st));
         h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T + b2.nnz_T) * nrhs);
         in = a2.out;
         cur ^= 1;
@@ -1662,7 +1662,7 @@ idbf_status idbf_tune_apply(idbf_handle h, int64_t nrhs, int32_t dtype, const ch
   const int keep_iter = h->rhs_iter;
   const bool prof = h->prof.on;
   h->prof.on = false;
-  const bool fusable = dtype == IDBF_C64 && nrhs > 1;
+  const bool fusable = (dtype == IDBF_C64 || dtype == IDBF_C64_BF16X3) && nrhs > 1;
   const int64_t per_wave = dtype == IDBF_C128 ? 16 : dtype == IDBF_C64_BF16X3 ? 64 : 32;
   const int64_t blocks = (nrhs + 4 * per_wave - 1) / (4 * per_wave);  // right-hand-side blocks of 4 wavefronts
   int best_fuse = keep_fuse ? 1 : 0, best_iter = keep_iter;

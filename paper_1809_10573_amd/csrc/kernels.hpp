@@ -313,7 +313,8 @@ hipError_t launch_apply_s(const StageArgs& a, bool fp64, hipStream_t st, bool ad
 enum { kGemmF32 = 0, kGemmBf16 = 1, kGemmF64 = 2 };
 constexpr size_t kMaxGemmLds = size_t(156) << 10;  // 160 KB less the kernels' static arrays
 size_t gemm_lds_bytes(int kmax_unit, int mmax_unit, int prec);
-// Fused two-stage groups of the complex64 FP32 many-RHS apply (forward):
+// Fused two-stage groups of the complex64 many-RHS apply (forward; prec
+// kGemmF32 or kGemmBf16):
 // V stages t, t + 1 (mode 0; a1 the level-t units, a2 the level-(t+1) ones)
 // or U stages t, t - 1 (mode 2), every ID of both levels of rank <= 16 tk
 // (tk = 1 or 2), stage-1 units' K <= kmax1, stage-2 units' M <= mmax2 <= 64.
@@ -322,7 +323,7 @@ constexpr size_t kMaxFusedLds = size_t(152) << 10;  // 160 KB less the kernel's 
 constexpr int kMaxRhsIter = 64;                      // largest StageArgs::rhs_iter
 size_t fused2_lds_bytes(int tk, int kmax1, int mmax2);
 hipError_t launch_apply_fused2(const StageArgs& a1, const StageArgs& a2, int mode, int tk, int kmax1, int mmax2,
-                               hipStream_t st);
+                               int prec, hipStream_t st);
 hipError_t launch_apply_gemm(const StageArgs& a, int mode, int kmax_unit, int mmax_unit, int prec,
                              hipStream_t st, bool adj = false);
 

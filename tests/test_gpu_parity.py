@@ -413,14 +413,24 @@ def test_fused_stage_groups(N, leaf, kind, tol, os_, fusable, nrhs):
     assert oracle.relative_error(yf, Y_or) < 2e-6
     col = np.linalg.norm(yf - Y_or, axis=0) / np.linalg.norm(Y_or, axis=0)
     assert col.max() < 2e-5
+    # BF16 hi/lo split products: the same groups on the 16x16x16 BF16 matrix cores
+    Yb = fac.apply(x, dtype=B.C64_BF16X3)
+    prof = fac.profile(reset=True)
+    fused_b = prof.get("applyb_vv", {}).get("launches", 0) + prof.get("applyb_uu", {}).get("launches", 0)
+    assert fused_b == expect
+    yb = Yb.cpu().numpy()
+    assert oracle.relative_error(yb, Y_or) < 2e-4
     fac.set_apply_config(fuse=0)
     Ys = fac.apply(x)
     assert fac.profile(reset=True).get("applyn_vv") is None
     assert oracle.relative_error(yf, Ys.cpu().numpy()) < 1e-6
+    Ysb = fac.apply(x, dtype=B.C64_BF16X3).cpu().numpy()
+    assert oracle.relative_error(yb, Ysb) < 1e-4
     fac.set_apply_config(fuse=1)
     for r in (1, 2, 16):
         fac.set_apply_config(rhs_iter=r)
         assert torch.equal(fac.apply(x), Yf), r
+        assert torch.equal(fac.apply(x, dtype=B.C64_BF16X3), Yb), r
     with pytest.raises(B.IdbfError):
         fac.set_apply_config(rhs_iter=3)
     assert fac.apply_config() == {"fuse": 1, "rhs_iter": 16}

@@ -32,8 +32,8 @@ def test_tune_apply_and_cache(tmp_path):
     other = again.tune_apply(17, B.C128, cache)          # a different problem: timed, appended
     assert not other["from_cache"] and other["fuse"] == got["fuse"]   # complex128 keeps the fusion setting
     assert len(open(cache).read().splitlines()) == 2
-    nocache = again.tune_apply(64, B.C64_BF16X3)          # no file
-    assert not nocache["from_cache"]
+    nocache = again.tune_apply(64, B.C64_BF16X3)          # no file; fusion is timed for the BF16 split too
+    assert not nocache["from_cache"] and nocache["fuse"] in (0, 1)
     F = oracle.build(ph, X, O, leaf, tol, oversample=2)
     G = I.gaussian_vectors(N, 300, seed=4)
     fac.set_apply_config(fuse=got["fuse"], rhs_iter=got["rhs_iter"])
