@@ -116,6 +116,20 @@ typedef struct idbf_opts {
    * the residual test, and is rejected if no proposed column is above the
    * threshold; the plain pivoted ID replaces the rejected ones. */
   struct idbf_mlp_s* skeleton_proposer;
+  /* The handle's device memory (factors, apply workspace, level scratch)
+   * from the caller's allocator, e.g. a framework's caching allocator; both
+   * NULL (the default) for the library's own: hipMalloc, with the chunks of
+   * destroyed handles kept for later constructions (see idbf_destroy).
+   * dev_alloc(bytes, user) returns device memory of at least `bytes` on the
+   * current device, 256-byte aligned, or NULL (the call then fails with
+   * IDBF_ENOMEM); dev_free(ptr, bytes, user) takes back what dev_alloc
+   * returned, once the device has finished with it (the library
+   * synchronizes first).  Both run on the thread of the library call that
+   * needs them: construction, an apply with more right-hand sides than any
+   * before it, destruction.  Give both or neither (IDBF_EINVAL). */
+  void* (*dev_alloc)(size_t bytes, void* user);
+  void (*dev_free)(void* ptr, size_t bytes, void* user);
+  void* alloc_user;
 } idbf_opts;
 
 typedef struct idbf_handle_s* idbf_handle;

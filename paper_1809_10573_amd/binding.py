@@ -64,7 +64,47 @@ class Opts_t(C.Structure):
     _fields_ = [("kmax", C.c_int32), ("oversample", C.c_int32), ("flags", C.c_int32),
                 ("sampler", C.c_int32), ("mem_cap_bytes", C.c_uint64), ("stream", C.c_void_p),
                 ("proposer", C.c_void_p), ("proposal_margin", C.c_int32), ("proposal_accept", C.c_float),
-                ("seed", C.c_uint64), ("skeleton_proposer", C.c_void_p)]
+                ("seed", C.c_uint64), ("skeleton_proposer", C.c_void_p), ("dev_alloc", C.c_void_p),
+                ("dev_free", C.c_void_p), ("alloc_user", C.c_void_p)]
+
+
+DEV_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+class TorchAllocator:
+    """A handle's device memory from torch's caching allocator
+    (opts.dev_alloc / dev_free): blocks are taken on the device's current
+    stream and given back to torch when the library frees them."""
+
+    def __init__(self, device="cuda"):
+        import torch
+        dev = torch.device(device)
+        if dev.index is None:
+            dev = torch.device(dev.type, torch.cuda.current_device())
+        self.device = dev
+        self.live: dict = {}
+        self.calls = 0
+
+        def _alloc(nbytes, user):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device)
+            except RuntimeError:
+                return None
+            self.live[int(p)] = int(nbytes)
+            self.calls += 1
+            return p
+
+        def _free(ptr, nbytes, user):
+            self.live.pop(int(ptr), None)
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._alloc = DEV_ALLOC_FN(_alloc)  # kept alive as long as any handle that uses them
+        self._free = DEV_FREE_FN(_free)
+
+    def set(self, opts) -> None:
+        opts.dev_alloc = C.cast(self._alloc, C.c_void_p).value
+        opts.dev_free = C.cast(self._free, C.c_void_p).value
 
 
 class Info_t(C.Structure):
@@ -238,9 +278,10 @@ class Batch:
 class Factorization:
     """A constructed IDBF living on the GPU (owns the C handle)."""
 
-    def __init__(self, handle: int, X, Omega):
+    def __init__(self, handle: int, X, Omega, allocator=None):
         self._h = C.c_void_p(handle)
         self.X, self.Omega = X, Omega
+        self._allocator = allocator  # its callbacks must outlive the handle
 
     def close(self) -> None:
         if self._h:
@@ -393,7 +434,7 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
               stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0,
               sampler: int = SAMPLER_MOCKCHEB, force_reject: bool = False,
               allow_truncate: bool = False, skeleton_proposer=None,
-              proposal_accept: float = 0.0) -> Factorization:
+              proposal_accept: float = 0.0, allocator: TorchAllocator | None = None) -> Factorization:
     """idbf_construct on device copies of X and Omega (float64, ascending)."""
     lib = load()
     Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
@@ -410,11 +451,13 @@ def construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample:
         opts.proposal_accept = float(proposal_accept)
     if skeleton_proposer is not None:
         opts.skeleton_proposer = skeleton_proposer._h.value
+    if allocator is not None:
+        allocator.set(opts)
     ph = _phase(phase)
     h = C.c_void_p()
     _check(lib.idbf_construct(C.byref(ph), _ptr(Xd), _ptr(Od), Xd.numel(), float(tol), int(leaf),
                               C.byref(opts), C.byref(h)))
-    return Factorization(h.value, Xd, Od)
+    return Factorization(h.value, Xd, Od, allocator)
 
 
 def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample: int = 1,
@@ -422,7 +465,7 @@ def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample
                       stream=None, proposer=None, proposal_margin: int = 4, seed: int = 0,
                       sampler: int = SAMPLER_MOCKCHEB, force_reject: bool = False,
                       allow_truncate: bool = False, skeleton_proposer=None,
-              proposal_accept: float = 0.0) -> list:
+              proposal_accept: float = 0.0, allocator: TorchAllocator | None = None) -> list:
     """idbf_construct_batched: one lockstep construction of len(phases) instances."""
     lib = load()
     n = len(phases)
@@ -444,6 +487,8 @@ def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample
         opts.proposal_accept = float(proposal_accept)
     if skeleton_proposer is not None:
         opts.skeleton_proposer = skeleton_proposer._h.value
+    if allocator is not None:
+        allocator.set(opts)
     ph = (Phase_t * n)(*[_phase(p) for p in phases])
     xp = (C.c_void_p * n)(*[_ptr(x) for x in Xd])
     op = (C.c_void_p * n)(*[_ptr(o) for o in Od])
@@ -452,7 +497,7 @@ def construct_batched(phases, Xs, Omegas, tols, leafs, kmax: int = 0, oversample
     ls = (C.c_int32 * n)(*[int(v) for v in leafs])
     out = (C.c_void_p * n)()
     _check(lib.idbf_construct_batched(n, ph, xp, op, Ns, ts, ls, C.byref(opts), out))
-    return [Factorization(out[i], Xd[i], Od[i]) for i in range(n)]
+    return [Factorization(out[i], Xd[i], Od[i], allocator) for i in range(n)]
 
 
 def release_cached_memory() -> None:

@@ -153,6 +153,28 @@ hipError_t device_alloc(size_t bytes, size_t most, void** p, size_t* got) {
   return hipMalloc(p, bytes);
 }
 
+// A handle's device memory: the caller's allocator (opts.dev_alloc /
+// dev_free) when it gave one, else hipMalloc behind the chunk cache.
+struct Allocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, size_t, void*) = nullptr;
+  void* user = nullptr;
+
+  hipError_t get(size_t bytes, size_t most, void** p, size_t* got) const {
+    if (!alloc) return device_alloc(bytes, most, p, got);
+    void* q = alloc(bytes, user);
+    if (!q) return hipErrorOutOfMemory;
+    *p = q;
+    *got = bytes;
+    return hipSuccess;
+  }
+  // back to the caller, or to the cache; the device must be done with it
+  void put(int dev, void* p, size_t bytes) const {
+    if (free) free(p, bytes, user);
+    else chunk_cache().put(dev, p, bytes);
+  }
+};
+
 // Bump allocator over large device chunks: the construction's many per-level
 // arrays cost a handful of allocations.
 struct Arena {
@@ -164,6 +186,7 @@ struct Arena {
   std::vector<Chunk> chunks;
   char* cur = nullptr;
   size_t used = 0, cap = 0, total = 0, limit = 0, chunk_min = size_t(64) << 20;
+  Allocator al;
 
   idbf_status alloc(size_t bytes, void** out) {
     bytes = std::max<size_t>(256, (bytes + 255) & ~size_t(255));
@@ -180,10 +203,10 @@ struct Arena {
     }
     void* p = nullptr;
     size_t got = sz;
-    hipError_t e = device_alloc(sz, limit ? limit - total : SIZE_MAX, &p, &got);
+    hipError_t e = al.get(sz, limit ? limit - total : SIZE_MAX, &p, &got);
     if (e != hipSuccess) {
       (void)hipGetLastError();
-      set_error("hipMalloc(%zu) failed: %s", sz, hipGetErrorString(e));
+      set_error("device allocation of %zu bytes failed: %s", sz, hipGetErrorString(e));
       return IDBF_ENOMEM;
     }
     chunks.push_back({p, got, current_device()});
@@ -204,7 +227,7 @@ struct Arena {
   // chunks back to the cache once the device is idle
   void release() {
     if (!chunks.empty()) (void)hipDeviceSynchronize();
-    for (auto& c : chunks) chunk_cache().put(c.dev, c.base, c.size);
+    for (auto& c : chunks) al.put(c.dev, c.base, c.size);
     chunks.clear();
     cur = nullptr;
     used = cap = total = 0;
@@ -425,8 +448,8 @@ struct idbf_handle_s {
   ~idbf_handle_s() {
     if (pin || ws || tmp) (void)hipDeviceSynchronize();  // nothing in flight uses them once they are held
     if (pin) chunk_cache().put_pinned(pin, sizeof(HostStage));
-    if (ws) chunk_cache().put(current_device(), ws, ws_bytes);
-    if (tmp) chunk_cache().put(current_device(), tmp, tmp_bytes);
+    if (ws) arena.al.put(current_device(), ws, ws_bytes);
+    if (tmp) arena.al.put(current_device(), tmp, tmp_bytes);
     arena.release();
   }
 };
@@ -547,7 +570,7 @@ idbf_status grow_tmp(idbf_handle_s* h, size_t bytes) {
   if (bytes <= h->tmp_bytes) return IDBF_OK;
   if (h->tmp) {
     IDBF_HIP_CHECK(hipStreamSynchronize(h->stream));  // the previous level's passes are done with it
-    chunk_cache().put(current_device(), h->tmp, h->tmp_bytes);
+    h->arena.al.put(current_device(), h->tmp, h->tmp_bytes);
     h->tmp = nullptr;
     h->tmp_bytes = 0;
   }
@@ -557,7 +580,7 @@ idbf_status grow_tmp(idbf_handle_s* h, size_t bytes) {
     return IDBF_ENOMEM;
   }
   size_t got = bytes;
-  hipError_t e = device_alloc(bytes, SIZE_MAX, &h->tmp, &got);
+  hipError_t e = h->arena.al.get(bytes, SIZE_MAX, &h->tmp, &got);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     h->tmp = nullptr;
@@ -1017,12 +1040,12 @@ idbf_status grow_workspace(idbf_handle_s* h, size_t bytes, hipStream_t st) {
   if (h->ws) {
     (void)st;
     IDBF_HIP_CHECK(hipDeviceSynchronize());  // applies on any stream may still read it
-    chunk_cache().put(current_device(), h->ws, h->ws_bytes);
+    h->arena.al.put(current_device(), h->ws, h->ws_bytes);
     h->ws = nullptr;
     h->ws_bytes = 0;
   }
   size_t got = bytes;
-  hipError_t e = device_alloc(bytes, SIZE_MAX, &h->ws, &got);
+  hipError_t e = h->arena.al.get(bytes, SIZE_MAX, &h->ws, &got);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     h->ws = nullptr;
@@ -1094,6 +1117,13 @@ idbf_status make_handle(const idbf_phase* phase, const double* X, const double* 
   h->oversample = o.oversample;
   h->ph = to_dev(*phase);
   h->arena.limit = o.mem_cap_bytes;
+  if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr)) {
+    set_error("opts: dev_alloc and dev_free must be given together");
+    return IDBF_EINVAL;
+  }
+  h->arena.al.alloc = o.dev_alloc;
+  h->arena.al.free = o.dev_free;
+  h->arena.al.user = o.alloc_user;
   h->arena.chunk_min = std::max<size_t>(size_t(64) << 20, size_t(N) * 2048);
   if (o.mem_cap_bytes) h->arena.chunk_min = std::min<size_t>(h->arena.chunk_min, o.mem_cap_bytes);
   h->stream = static_cast<hipStream_t>(o.stream);

@@ -74,6 +74,13 @@ def test_argument_errors_without_gpu():
     assert lib.idbf_set_apply_config(None, C.byref(cfg)) == B.EINVAL
     assert lib.idbf_tune_apply(None, 16, B.C64, None, None, C.byref(cfg)) == B.EINVAL
     assert C.sizeof(B.ApplyConfig_t) == 32
+    assert C.sizeof(B.Opts_t) == 88
+    o = B.Opts_t()
+    lib.idbf_opts_default(C.byref(o))
+    assert (o.dev_alloc, o.dev_free, o.alloc_user) == (None, None, None)
+    o.dev_alloc = C.cast(B.DEV_ALLOC_FN(lambda n, u: None), C.c_void_p).value  # no dev_free: refused
+    assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1e-6, 8, C.byref(o), C.byref(h)) == B.EINVAL
+    assert b"dev_alloc and dev_free" in lib.idbf_last_error()
 
 
 def test_binding_rejects_bad_operands_before_any_launch():
