@@ -710,7 +710,8 @@ def main() -> int:
             peak = {"c64": FP32_MFMA_PEAK, "bf16x3": BF16_MFMA_PEAK, "c128": FP64_MFMA_PEAK}[prec]
             rec["frac_peak"] = rec["gflops"] * 1e9 / peak
             rec["peak"] = {"c64": "FP32 MFMA", "bf16x3": "BF16 MFMA", "c128": "FP64 MFMA"}[prec]
-            rec["tuned"] = {k: tuned[name][k] for k in ("fuse", "rhs_iter")} if name in tuned else None
+            rec["tuned"] = ({"fuse": tuned[name]["fuse"] if prec != "c128" else None,  # no fused complex128 path
+                             "rhs_iter": tuned[name]["rhs_iter"]} if name in tuned else None)
         apply[name] = rec
     for name, prec, nrhs in APPLY_KINDS:
         if prec != "c128":
