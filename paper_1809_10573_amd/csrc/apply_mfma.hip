@@ -745,14 +745,18 @@ __global__ __launch_bounds__(64 * kWavesG16) void apply_gemm16d(StageArgs A) {
     for (int mt = 0; mt < TM; ++mt)
 #pragma unroll
       for (int t = 0; t < 2; ++t) acc[mt][t] = f64x4{};
-    for (int kc = 0; kc < u.K; kc += 16) {
-      double2 b[4];
+    auto load = [&](double2* b, int kc) {  // the rows of K block kc, four per lane (zero past K)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int kk = kc + 4 * e + kq;
         const int row = kk < u.K ? s_src[kk] : -1;
         b[e] = (row >= 0 && ok) ? in[(int64_t)row * nr + n0] : make_double2(0.0, 0.0);
       }
+    };
+    double2 b[4], bn[4];
+    load(b, 0);
+    for (int kc = 0; kc < u.K; kc += 16) {
+      if (kc + 16 < u.K) load(bn, kc + 16);  // next block in flight during this one's products
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         if (kc + 4 * e >= u.K) break;  // K steps of 4 wholly past K add nothing
@@ -769,6 +773,8 @@ __global__ __launch_bounds__(64 * kWavesG16) void apply_gemm16d(StageArgs A) {
           }
         }
       }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b[e] = bn[e];
     }
 #pragma unroll
     for (int mt = 0; mt < TM; ++mt) {
