@@ -718,10 +718,11 @@ __global__ __launch_bounds__(64 * kWavesF) void apply_fused2b(StageArgs A1, Stag
 // part t of tile t.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int kRhsPerWaveD = 16;
-constexpr int kRhsIterD = 16;  // right-hand-side blocks per wavefront: A serves kRhsIterD kWavesG16 blocks
+constexpr int kWavesD = 8;     // wavefronts per workgroup
+constexpr int kRhsIterD = 8;   // right-hand-side blocks per wavefront: A serves kRhsIterD kWavesD blocks
 
 template <int MODE, bool ADJ, int TM>
-__global__ __launch_bounds__(64 * kWavesG16) void apply_gemm16d(StageArgs A) {
+__global__ __launch_bounds__(64 * kWavesD) void apply_gemm16d(StageArgs A) {
   extern __shared__ __attribute__((aligned(16))) double2 s_Ad[];
   __shared__ int s_src[kMaxKg];
   __shared__ int s_out[kMaxMg];
@@ -736,7 +737,7 @@ __global__ __launch_bounds__(64 * kWavesG16) void apply_gemm16d(StageArgs A) {
   const double2* in = static_cast<const double2*>(A.in);
   double2* out = static_cast<double2*>(A.out);
   for (int it = 0; it < A.rhs_iter; ++it) {
-    const int64_t rhs0 = ((blockIdx.y * (int64_t)A.rhs_iter + it) * kWavesG16 + w) * kRhsPerWaveD;
+    const int64_t rhs0 = ((blockIdx.y * (int64_t)A.rhs_iter + it) * kWavesD + w) * kRhsPerWaveD;
     if (rhs0 >= nr) return;
     const int64_t n0 = rhs0 + c16;
     const bool ok = n0 < nr;
@@ -851,7 +852,7 @@ hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int m
   if (prec == kGemmF64) {  // FP64: the FP32 kernel's layout, 16 right-hand sides per wavefront
     a.gemm_rows = (mmax_unit + 15) & ~15;
     if (a.rhs_iter == 0) a.rhs_iter = kRhsIterD;
-    const int64_t per_block = (int64_t)a.rhs_iter * kWavesG16 * kRhsPerWaveD;
+    const int64_t per_block = (int64_t)a.rhs_iter * kWavesD * kRhsPerWaveD;
     const dim3 grid((unsigned)a.n, (unsigned)((a.nrhs + per_block - 1) / per_block));
     const size_t lds = gemm_lds_bytes(kmax_unit, mmax_unit, prec);
 #define IDBF_GEMM16D(M, J, TM)                                                                       \
@@ -861,7 +862,7 @@ hipError_t launch_apply_gemm(const StageArgs& a0, int mode, int kmax_unit, int m
                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);     \
       if (e_ != hipSuccess) return e_;                                                               \
     }                                                                                                \
-    hipLaunchKernelGGL((apply_gemm16d<M, J, TM>), grid, dim3(64 * kWavesG16), lds, st, a);           \
+    hipLaunchKernelGGL((apply_gemm16d<M, J, TM>), grid, dim3(64 * kWavesD), lds, st, a);             \
   } while (0)
 #define IDBF_GEMM16D_TM(M, J)                                                                        \
   do {                                                                                               \
