@@ -291,8 +291,7 @@ idbf_status idbf_release_cached_memory(void);
  *     Results agree to the precision's rounding.
  *   rhs_iter: right-hand-side blocks (32 complex64 or 16 complex128 columns
  *     per wavefront) each workgroup walks through with one LDS-staged
- *     factor block: 0 (the kernels' defaults: 8, complex128 16) or a power
- *     of two <= 64.
+ *     factor block: 0 (the kernels' default, 8) or a power of two <= 64.
  * The setting belongs to the handle; idbf_tune_apply picks one by timing. */
 typedef struct idbf_apply_config {
   int32_t fuse;
@@ -307,12 +306,12 @@ idbf_status idbf_get_apply_config(idbf_handle h, idbf_apply_config* cfg);
 idbf_status idbf_set_apply_config(idbf_handle h, const idbf_apply_config* cfg);
 
 /* Autotuner of the many-RHS apply (not in the paper): times every
- * configuration (fuse 1 and 0 for complex64 and the BF16 split; rhs_iter 1,
- * 2, 4, ... up to 16
- * or the number of right-hand-side blocks) on this handle's factors for
- * (nrhs, dtype) -- one warm-up and three forward applies each, HIP events on
- * `stream` -- and sets the fastest on the handle (*chosen, nullable, gets it
- * with its time).  cache_path (nullable): a text file, one line per tuned
+ * configuration (fuse 1 and 0 for complex64 and the BF16 split, the
+ * handle's current fuse for complex128, which has no fused path; rhs_iter
+ * 1, 2, 4, ... up to 16 or the number of right-hand-side blocks) on this
+ * handle's factors for (nrhs, dtype) -- one warm-up and three forward
+ * applies each, HIP events on `stream` -- and sets the fastest on the
+ * handle (*chosen, nullable, gets it with its time).  cache_path (nullable): a text file, one line per tuned
  * problem, "<key>\t<fuse> <rhs_iter> <ms>", the key naming the device's
  * architecture, N, L, H, nrhs, dtype and every level's rank and candidate
  * bounds; a problem found there is set without timing (from_cache = 1), and
