@@ -806,6 +806,24 @@ def main() -> int:
                               "traffic": _counted_traffic(STEP_COUNTERS, STEP_SOURCES,
                                                           "traffic_bytes_per_apply.c64_nrhs1"),
                               "kernels": {k: v["ms"] for k, v in p1.items()}}
+    # the 1-RHS applies issued back to back, eagerly and replayed from a
+    # captured HIP graph (a one-instance apply plan): 20 of each between two
+    # events; the graph removes the host launch of each of the 2H + 1 stages
+    reps = 20
+    replay = {}
+    cap = torch.cuda.Stream()  # capture needs a stream of its own (default priority)
+    torch.cuda.synchronize()
+    for name, key in (("c64_nrhs1", ("c64", 1)), ("c128_nrhs1", ("c128", 1))):
+        xk, yk = xin[key], yout[key]
+        plan = B.ApplyPlan([fac], [xk], [yk], stream=cap)
+        eager_ms = _event_ms(torch, cap, lambda: [fac.apply(xk, yk, stream=cap) for _ in range(reps)]) / reps
+        graph_ms = _event_ms(torch, cap, lambda: [plan.launch(cap) for _ in range(reps)]) / reps
+        plan.close()
+        elem = 16 if key[0] == "c128" else 8
+        gb = (nnz * elem + 8 * info["n_ids"] + 2 * N * elem) / 1e9
+        replay[name] = {"eager_ms": eager_ms, "graph_ms": graph_ms, "graph_gbs": gb / graph_ms * 1e3,
+                        "graph_frac_hbm_peak": gb / graph_ms * 1e3 / HBM_PEAK_GBS}
+    out["apply1_replay"] = replay
     # adjoint apply y = K~^H x on the same factors (measured once), with the
     # adjoint identity as a check
     adj = {}
