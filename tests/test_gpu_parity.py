@@ -7,6 +7,8 @@ Tolerances are derived from the arithmetic:
   conditioning of R11, bounded by |R_00| / |R_kk|;
 * apply: products of O(log N) factors in FP64 (c128) or FP32 (c64).
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -235,7 +237,18 @@ def _workload(kind, N):
         g, w = I.schlomilch_points(N)
         return I.j0_kernel(), g, w
     X, O = I.uniform_grid(N)
+    if kind == "fio_m4":
+        return I.fio_phase(1.0, 4.0), X, O
     return (I.dft_phase() if kind == "dft" else I.fio_phase(1.0, 1.0)), X, O
+
+
+@functools.lru_cache(maxsize=8)
+def _oracle_case(kind, N, leaf, tol, os_):
+    """The workload and its oracle factors, built once per configuration:
+    oracle.build is deterministic and oracle.apply only reads the factors,
+    so the right-hand-side parametrizations share one build."""
+    ph, X, O = _workload(kind, N)
+    return ph, X, O, oracle.build(ph, X, O, leaf, tol, oversample=os_)
 
 
 def _compare_construction(F, fac, ph, X, O, t_bound=1e-12):
@@ -337,8 +350,7 @@ def test_many_rhs_matrix_core_paths(N, leaf, kind, tol, os_, nrhs):
     products with FP32 accumulation) against the oracle's FP64 apply of its
     own factors (identical skeletons, so the factors agree to 1e-12); ragged
     right-hand-side counts cover the tails of the 64-column blocks."""
-    ph, X, O = _workload(kind, N)
-    F = oracle.build(ph, X, O, leaf, tol, oversample=os_)
+    ph, X, O, F = _oracle_case(kind, N, leaf, tol, os_)
     fac = B.construct(ph, X, O, tol, leaf, oversample=os_, device=DEV)
     G = I.gaussian_vectors(N, nrhs, seed=nrhs)
     Y_or = oracle.apply(F, G)
@@ -390,11 +402,7 @@ def test_fused_stage_groups(N, leaf, kind, tol, os_, fusable, nrhs):
     """The fused two-stage groups of the complex64 many-RHS apply against the
     oracle's FP64 apply and against the per-stage kernels on the same
     factors; the right-hand-side blocking changes no bit of the result."""
-    if kind == "fio_m4":
-        ph, (X, O) = I.fio_phase(1.0, 4.0), I.uniform_grid(N)
-    else:
-        ph, X, O = _workload(kind, N)
-    F = oracle.build(ph, X, O, leaf, tol, oversample=os_)
+    ph, X, O, F = _oracle_case(kind, N, leaf, tol, os_)
     fac = B.construct(ph, X, O, tol, leaf, oversample=os_, device=DEV, profile=True)
     assert fac.apply_config() == {"fuse": 0, "rhs_iter": 0}
     fac.set_apply_config(fuse=1)
@@ -442,9 +450,7 @@ def test_wide_ranks_construct_and_every_apply_path():
     QR variant, the chunked back-substitution and the 128-bit skeleton masks
     all run; every apply path is checked against the oracle."""
     N, leaf, tol = 4096, 16, 1e-6
-    ph = I.fio_phase(1.0, 4.0)
-    X, O = I.uniform_grid(N)
-    F = oracle.build(ph, X, O, leaf, tol, oversample=2)
+    ph, X, O, F = _oracle_case("fio_m4", N, leaf, tol, 2)
     fac = B.construct(ph, X, O, tol, leaf, oversample=2, device=DEV)
     info = fac.info()
     assert info["cand_max"] > 64 and info["rank_max"] > 32
