@@ -320,13 +320,17 @@ __device__ __forceinline__ int skel_below(uint64_t lo, uint64_t hi, int p) {
 
 // One ID per workgroup of W wavefronts.  Lane l owns candidate columns
 // l + 64 cs (cs < CPL); wavefront w holds sampled rows [R w, R w + R).
-//   CPL = 1, R = 16: up to 64 candidates (W <= 8); 81..96 and 97..112
-//                    samples take W = 8 with R = 12 and 14 instead, which
-//                    fills the 16 wavefront slots a CU has at this register
-//                    use (two workgroups of 6 or 7 would leave 4 or 2 empty);
+//   CPL = 1, R = 16: up to 64 candidates and 64 samples (W <= 4);
+//   CPL = 1, W = 4:  65..80, 81..96 and 97..112 samples with R = 20, 24 and
+//                    28 (three wavefronts per SIMD; 113..128 take W = 8,
+//                    R = 16).  Each pivot step pays two workgroup barriers
+//                    and cross-wave reductions, so at this register budget
+//                    few tall wavefronts beat many short ones: three IDs per
+//                    CU instead of two (W = 8), or the same three with
+//                    four-wave instead of five-wave barriers (W = 5);
 //   CPL = 2, R = 8:  up to 128 candidates (W <= 16), same registers per lane.
 template <int W, int CPL, int R>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) void id_kernel(IdArgs A) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(R > 16 ? 3 : 4, 8))) void id_kernel(IdArgs A) {
   constexpr int SMAX = R * W;
   constexpr int NC = kWave * CPL;     // candidate columns covered
   // R rows staged in LDS per back-substitution chunk: 32 KiB where registers
@@ -409,9 +413,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       for (int i = 0; i < R; ++i) {
         const int row = row0 + i;
         double2 v = make_double2(0.0, 0.0);
-        if (lane + kWave * cs < c && row < s)
-          v = isV ? kernel_entry(A.ph, s_coord[row], s_cx[row], ccoord[cs])
-                  : kernel_entry(A.ph, ccoord[cs], ccx[cs], s_coord[row]);
+        if (lane + kWave * cs < c && row < s) {  // one call site per row: K(sample, cand) or K(cand, sample)
+          const double sc = s_coord[row];
+          v = kernel_entry(A.ph, isV ? sc : ccoord[cs], isV ? s_cx[row] : ccx[cs], isV ? ccoord[cs] : sc);
+        }
         a[cs][i] = v;
       }
   }
@@ -1254,14 +1259,15 @@ hipError_t launch_packed(const IdArgs& a, int64_t n, hipStream_t st) {
 
 hipError_t launch_qr_bucket(const IdArgs& a, int64_t n, int bucket, hipStream_t st) {
   switch (bucket) {
-    // up to 64 candidates: 16 rows per wavefront (81..112 samples: 8 wavefronts of 12 or 14)
+    // up to 64 candidates: 16 rows per wavefront up to 64 samples, then four
+    // wavefronts of 20, 24 or 28 rows up to 112
     case 0: return launch_one<1, 1, 16>(a, n, st);
     case 1: return launch_one<2, 1, 16>(a, n, st);
     case 2: return launch_one<3, 1, 16>(a, n, st);
     case 3: return launch_one<4, 1, 16>(a, n, st);
-    case 4: return launch_one<5, 1, 16>(a, n, st);
-    case 5: return launch_one<8, 1, 12>(a, n, st);
-    case 6: return launch_one<8, 1, 14>(a, n, st);
+    case 4: return launch_one<4, 1, 20>(a, n, st);
+    case 5: return launch_one<4, 1, 24>(a, n, st);
+    case 6: return launch_one<4, 1, 28>(a, n, st);
     case 7: return launch_one<8, 1, 16>(a, n, st);
     // 65..128 candidates: two per lane, 8 rows per wavefront
     case 8: return launch_one<1, 2, 8>(a, n, st);

@@ -9,8 +9,10 @@ namespace idbf {
 enum : int32_t { kErrRank = 1, kErrSize = 2 };
 
 // QR kernel variant of an ID with c candidates and s samples: buckets 0..7
-// take up to 64 candidates with ceil(s / 16) wavefronts, buckets 8..23 up to
-// 128 with ceil(s / 8); buckets 24..27 pack two IDs of up to 32 candidates
+// take up to 64 candidates by ceil(s / 16) (one to four wavefronts of 16
+// rows up to 64 samples, four of 20, 24 or 28 rows up to 112, eight of 16
+// up to 128), buckets 8..23 up to 128 with ceil(s / 8) wavefronts of 8
+// rows; buckets 24..27 pack two IDs of up to 32 candidates
 // and 64 samples per workgroup, 28..29 four IDs of up to 16 and 32.  A tall
 // ID (s > kQrRows) enters the one-ID kernels with its reduced block of c
 // rows.  Slot kQrBuckets of the bucket counters counts the tall IDs.
