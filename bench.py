@@ -659,9 +659,15 @@ def main() -> int:
             key = ("c128" if prec == "c128" else "c64", nrhs)
             if name in tuned:  # a host-side setting of the handle, no device work
                 fac.set_apply_config(fuse=tuned[name]["fuse"], rhs_iter=tuned[name]["rhs_iter"])
+            # the 1-RHS applies run without the library's per-stage event
+            # markers (a few microseconds each, 2H + 2 per apply); their
+            # per-kernel times come from a profiled apply after the steps
+            # (roofline_apply1). Host-side switches, no device work.
+            fac.set_profile(nrhs > 1)
             ev[2 * i].record(stream)
             fac.apply(xin[key], yout[key], dtype=dtypes[prec], stream=stream)
             ev[2 * i + 1].record(stream)
+            fac.set_profile(True)
         torch.cuda.synchronize()
         if record is not None:
             r = dict(construct_ms=t_con, prof=fac.profile(reset=True), info=fac.info())
@@ -812,6 +818,7 @@ def main() -> int:
     reps = 20
     replay = {}
     cap = torch.cuda.Stream()  # capture needs a stream of its own (default priority)
+    fac.set_profile(False)  # no event markers on either side (the graph records none)
     torch.cuda.synchronize()
     for name, key in (("c64_nrhs1", ("c64", 1)), ("c128_nrhs1", ("c128", 1))):
         xk, yk = xin[key], yout[key]

@@ -406,6 +406,15 @@ typedef struct idbf_kernel_stat {
 idbf_status idbf_profile_read(idbf_handle h, idbf_kernel_stat* out, int32_t max, int32_t* n,
                               int32_t reset);
 
+/* Switch the recording of those events on (on != 0) or off for later calls on
+ * h, whatever the construction flags were.  Each record costs the stream a
+ * marker of a few microseconds (a 1-RHS apply records 2H + 2 of them), so a
+ * caller that times the path itself can leave the markers out of the calls it
+ * times.  Records already taken stay until idbf_profile_read(reset != 0)
+ * discards them; idbf_profile_read answers IDBF_EINVAL only while profiling is
+ * off and no records are held.  IDBF_EINVAL for a NULL handle. */
+idbf_status idbf_profile_enable(idbf_handle h, int32_t on);
+
 /*
  * Inspection of one level's IDs, for verification.  side IDBF_SIDE_U or
  * IDBF_SIDE_V, level t in [1, H].  IDs are numbered q = partner * 2^(L-t+1)

@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EHIP", 4: "ERANK", 5: "EU
 EXPORTED = [
     "idbf_opts_default", "idbf_construct", "idbf_apply", "idbf_destroy", "idbf_last_error",
     "idbf_get_info", "idbf_batch_sizes", "idbf_batch_export", "idbf_middle_sizes",
-    "idbf_middle_export", "idbf_sample", "idbf_id_batch", "idbf_profile_read", "idbf_reserve",
+    "idbf_middle_export", "idbf_sample", "idbf_id_batch", "idbf_profile_read", "idbf_profile_enable",
+    "idbf_reserve",
     "idbf_construct_batched", "idbf_apply_batched", "idbf_mlp_param_count", "idbf_mlp_create",
     "idbf_mlp_destroy", "idbf_mlp_params", "idbf_mlp_forward", "idbf_mlp_loss_grad", "idbf_mlp_train",
     "idbf_rank_samples", "idbf_apply_batched_plan", "idbf_plan_launch", "idbf_plan_destroy",
@@ -175,6 +176,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_id_batch.argtypes = [P(Phase_t), VP, VP, I32, I64, VP, VP, VP, VP, VP, VP, D, I32, I32,
                                   VP, VP, VP, VP, VP]
     lib.idbf_profile_read.argtypes = [VP, P(KernelStat_t), I32, P(I32), I32]
+    lib.idbf_profile_enable.argtypes = [VP, I32]
     lib.idbf_reserve.argtypes = [VP, I64, I32]
     lib.idbf_construct_batched.argtypes = [I32, P(Phase_t), P(VP), P(VP), P(I64), P(D), P(I32), P(Opts_t),
                                            P(VP)]
@@ -404,6 +406,10 @@ class Factorization:
         path = None if cache_path is None else os.fsencode(cache_path)
         _check(load().idbf_tune_apply(self._h, int(nrhs), int(dtype), path, _stream(stream), C.byref(cfg)))
         return {"fuse": cfg.fuse, "rhs_iter": cfg.rhs_iter, "from_cache": bool(cfg.from_cache), "ms": cfg.ms}
+
+    def set_profile(self, on: bool) -> None:
+        """Record (or stop recording) per-launch events for later calls (idbf_profile_enable)."""
+        _check(load().idbf_profile_enable(self._h, int(bool(on))))
 
     def profile(self, reset: bool = True) -> dict:
         """{kernel name: {launches, ms, bytes, flops}} since the last reset (IDBF_FLAG_PROFILE)."""

@@ -274,6 +274,7 @@ struct Profiler {
     const char* name;
     hipEvent_t a, b;
     double bytes, flops;
+    bool a_shared;  // a is the end event of the record before (not owned)
   };
   bool on = false;
   std::vector<Rec> recs;
@@ -295,9 +296,21 @@ struct Profiler {
   // returns a record index, or -1 when profiling is off
   int begin(const char* name, hipStream_t st) {
     if (!on) return -1;
-    Rec r{name, event(), event(), 0.0, 0.0};
+    Rec r{name, event(), event(), 0.0, 0.0, false};
     if (!r.a || !r.b) return -1;
     (void)hipEventRecord(r.a, st);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  // A record whose launch follows record prev's on the same stream with
+  // nothing enqueued between them: it starts at prev's end event, so a chain
+  // of n launches records n + 1 events instead of 2n (each record costs the
+  // stream a marker).  prev < 0 starts a chain.
+  int begin_after(int prev, const char* name, hipStream_t st) {
+    if (!on) return -1;
+    if (prev < 0) return begin(name, st);
+    Rec r{name, recs[prev].b, event(), 0.0, 0.0, true};
+    if (!r.b) return -1;
     recs.push_back(r);
     return (int)recs.size() - 1;
   }
@@ -309,7 +322,7 @@ struct Profiler {
   }
   void clear() {
     for (auto& r : recs) {
-      pool.push_back(r.a);
+      if (!r.a_shared) pool.push_back(r.a);
       pool.push_back(r.b);
     }
     recs.clear();
@@ -1455,6 +1468,14 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
        {"adj1d_v", "adj1d_s", "adj1d_u"}, {"adjnd_v", "adjnd_s", "adjnd_u"}}};
   const int kind = bf16 ? 2 : fp64 ? (nrhs == 1 ? 3 : 4) : (nrhs == 1 ? 0 : 1);
   auto name = [&](char stage) { return kNames[adj][kind][stage == 'v' ? 0 : stage == 's' ? 1 : 2]; };
+  // one kernel launch per stage record, back to back on st: consecutive
+  // records share their boundary event
+  int prev = -1;
+  auto rec_begin = [&](const char* nm) { return h->prof.begin_after(prev, nm, st); };
+  auto rec_end = [&](int pr, double bytes, double flops) {
+    h->prof.end(pr, st, bytes, flops);
+    prev = pr;
+  };
   // fused two-stage groups (complex64 FP32 MFMA, forward): the rank bound
   // of both levels picks the register tiles per part (0: not fusable)
   const bool fuse = h->apply_fuse && !adj && (prec == kGemmF32 || prec == kGemmBf16) && nrhs > 1;
@@ -1483,9 +1504,9 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
         a2.out = buf[cur];
         const double bytes = double(b.nnz_T + b2.nnz_T) * elem + 8.0 * (b.n + b2.n) +
                              (t == 1 ? double(h->N) * nrhs * elem : 0.0);
-        const int pr = h->prof.begin(bf16 ? "applyb_vv" : "applyn_vv", st);
+        const int pr = rec_begin(bf16 ? "applyb_vv" : "applyn_vv");
         IDBF_HIP_CHECK(launch_apply_fused2(a, a2, 0, tk, b.cand_max, 2 * b2.rank_max, prec, st));
-        h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T + b2.nnz_T) * nrhs);
+        rec_end(pr, bytes, 8.0 * double(b.nnz_T + b2.nnz_T) * nrhs);
         in = buf[cur];
         cur ^= 1;
         ++t;
@@ -1493,7 +1514,7 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
       }
     }
     const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
-    const int pr = h->prof.begin(name(adj ? 'u' : 'v'), st);
+    const int pr = rec_begin(name(adj ? 'u' : 'v'));
     if (mfma && fits(b.cand_max, 2 * b.rank_max)) {  // units: the ID pairs (C, 2P), (C, 2P + 1) sharing a segment
       StageArgs g = a;
       g.n = b.n / 2;
@@ -1502,7 +1523,7 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     } else {
       IDBF_HIP_CHECK(launch_apply_v(a, fp64, st, adj));
     }
-    h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T) * nrhs);
+    rec_end(pr, bytes, 8.0 * double(b.nnz_T) * nrhs);
     in = buf[cur];
     cur ^= 1;
   }
@@ -1526,7 +1547,7 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     a.out = (h->H == 0) ? y : buf[cur];
     double bytes = double(h->nnz_S) * elem;
     if (h->H == 0) bytes += 2.0 * double(h->N) * nrhs * elem;
-    const int pr = h->prof.begin(name('s'), st);
+    const int pr = rec_begin(name('s'));
     const int kin = h->H == 0 ? 0 : adj ? h->U[h->H - 1].rank_max : h->V[h->H - 1].rank_max;
     const int mout = h->H == 0 ? 0 : adj ? h->V[h->H - 1].rank_max : h->U[h->H - 1].rank_max;
     if (mfma && !a.dense && fits(a.nsub * kin, mout)) {
@@ -1534,7 +1555,7 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
     } else {
       IDBF_HIP_CHECK(launch_apply_s(a, fp64, st, adj));
     }
-    h->prof.end(pr, st, bytes, 8.0 * double(h->nnz_S) * nrhs);
+    rec_end(pr, bytes, 8.0 * double(h->nnz_S) * nrhs);
     in = a.out;
     cur ^= 1;
   }
@@ -1557,9 +1578,9 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
         a2.out = (t == 2) ? y : buf[cur];
         const double bytes = double(b.nnz_T + b2.nnz_T) * elem + 8.0 * (b.n + b2.n) +
                              (t == 2 ? double(h->N) * nrhs * elem : 0.0);
-        const int pr = h->prof.begin(bf16 ? "applyb_uu" : "applyn_uu", st);
+        const int pr = rec_begin(bf16 ? "applyb_uu" : "applyn_uu");
         IDBF_HIP_CHECK(launch_apply_fused2(a, a2, 2, tk, 2 * b.rank_max, b2.cand_max, prec, st));
-        h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T + b2.nnz_T) * nrhs);
+        rec_end(pr, bytes, 8.0 * double(b.nnz_T + b2.nnz_T) * nrhs);
         in = a2.out;
         cur ^= 1;
         --t;
@@ -1567,11 +1588,11 @@ idbf_status apply_impl(idbf_handle h, const void* x, void* y, int64_t nrhs, int3
       }
     }
     const double bytes = double(b.nnz_T) * elem + 8.0 * b.n + (t == 1 ? double(h->N) * nrhs * elem : 0.0);
-    const int pr = h->prof.begin(name(adj ? 'v' : 'u'), st);
+    const int pr = rec_begin(name(adj ? 'v' : 'u'));
     if (mfma && fits(2 * b.rank_max, b.cand_max))
       IDBF_HIP_CHECK(launch_apply_gemm(a, 2, 2 * b.rank_max, b.cand_max, prec, st, adj));
     else IDBF_HIP_CHECK(launch_apply_u(a, fp64, st, adj));
-    h->prof.end(pr, st, bytes, 8.0 * double(b.nnz_T) * nrhs);
+    rec_end(pr, bytes, 8.0 * double(b.nnz_T) * nrhs);
     in = a.out;
     cur ^= 1;
   }
@@ -2055,13 +2076,23 @@ idbf_status idbf_stats(idbf_handle h, idbf_stats_t* out) {
   return IDBF_OK;
 }
 
+idbf_status idbf_profile_enable(idbf_handle h, int32_t on) {
+  g_err[0] = 0;
+  if (!h) {
+    set_error("profile_enable: handle is NULL");
+    return IDBF_EINVAL;
+  }
+  h->prof.on = on != 0;
+  return IDBF_OK;
+}
+
 idbf_status idbf_profile_read(idbf_handle h, idbf_kernel_stat* out, int32_t max, int32_t* n, int32_t reset) {
   if (!h || !n || max < 0 || (max > 0 && !out)) {
     set_error("profile_read: handle, n and out must be valid");
     return IDBF_EINVAL;
   }
-  if (!h->prof.on) {
-    set_error("profiling is off for this handle (construct with IDBF_FLAG_PROFILE)");
+  if (!h->prof.on && h->prof.recs.empty()) {
+    set_error("profiling is off for this handle (construct with IDBF_FLAG_PROFILE or call idbf_profile_enable)");
     return IDBF_EINVAL;
   }
   std::vector<idbf_kernel_stat> agg;

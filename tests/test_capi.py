@@ -59,6 +59,7 @@ def test_argument_errors_without_gpu():
     o.oversample = 0
     assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1e-6, 8, C.byref(o), C.byref(h)) == B.EINVAL
     assert lib.idbf_apply(None, fake, fake, 1, B.C128, None) == B.EINVAL
+    assert lib.idbf_profile_enable(None, 1) == B.EINVAL
     assert lib.idbf_apply_adjoint(None, fake, fake, 1, B.C128, None) == B.EINVAL
     assert b"handle is NULL" in lib.idbf_last_error()
     assert lib.idbf_get_info(None, None) == B.EINVAL

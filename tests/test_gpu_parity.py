@@ -639,3 +639,41 @@ def test_allow_truncate_keeps_rank_64():
     g = I.gaussian_vectors(N, None, seed=3)
     y = fac.apply(torch.as_tensor(g, device=DEV)).cpu().numpy()
     assert oracle.relative_error(y, oracle.apply(F, g)) < 1e-12
+
+
+def test_profile_records_tile_one_apply():
+    """With IDBF_FLAG_PROFILE one apply records each stage once. Consecutive
+    stages share their boundary event (one kernel launch per record, back to
+    back on the stream), so the records tile the apply: their sum is at most
+    the time between two events around the call, and the events go back to
+    the profiler's pool once each (three rounds reuse them)."""
+    N, leaf, tol = 4096, 16, 1e-6
+    ph, X, O = _workload("fio", N)
+    fac = B.construct(ph, X, O, tol, leaf, oversample=2, device=DEV, profile=True)
+    H = fac.info()["H"]
+    stream = torch.cuda.Stream()
+    for dtype, ct, pre in ((B.C64, torch.complex64, "apply1"), (B.C128, torch.complex128, "apply1d")):
+        x = torch.randn(N, dtype=ct, device=DEV)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            fac.profile(reset=True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fac.apply(x, y, dtype=dtype, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            prof = fac.profile(reset=True)
+            assert {k: v["launches"] for k, v in prof.items()} == {f"{pre}_v": H, f"{pre}_s": 1, f"{pre}_u": H}
+            assert all(v["ms"] > 0.0 for v in prof.values())
+            assert sum(v["ms"] for v in prof.values()) <= e0.elapsed_time(e1) + 1e-3
+        # switched off, the apply records nothing; records taken before stay readable
+        fac.apply(x, y, dtype=dtype, stream=stream)
+        fac.set_profile(False)
+        fac.apply(x, y, dtype=dtype, stream=stream)
+        torch.cuda.synchronize()
+        assert {k: v["launches"] for k, v in fac.profile(reset=True).items()} == {f"{pre}_v": H, f"{pre}_s": 1,
+                                                                                  f"{pre}_u": H}
+        with pytest.raises(B.IdbfError):
+            fac.profile(reset=True)  # off and nothing held
+        fac.set_profile(True)
+    fac.close()
