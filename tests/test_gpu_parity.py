@@ -125,6 +125,13 @@ def test_id_batch_matches_oracle(side, oversample, kmax, shapes):
     rng = np.random.default_rng(10 * side + oversample + kmax + 100 * list(SHAPES).index(shapes))
     problems = [_id_problem(rng, N, *sh) for sh in SHAPES[shapes]]
     tol = 1e-6
+    _assert_ids_match_oracle(ph, X, O, side, problems, tol, kmax, oversample)
+
+
+def _assert_ids_match_oracle(ph, X, O, side, problems, tol, kmax, oversample):
+    """One batched launch over the problems against oracle.column_id on the
+    same Mock-Chebyshev samples: ranks, skeletons and masks identical, T
+    within the conditioning bound."""
     rank, mask, skel, T = _run_ids(ph, X, O, side, problems, tol, kmax, oversample)
     allow_coord = X if side == B.SIDE_V else O
     for q, (cand, allowed) in enumerate(problems):
@@ -144,6 +151,26 @@ def test_id_batch_matches_oracle(side, oversample, kmax, shapes):
         kappa = cid.rdiag[0] / cid.rdiag[-1]
         scale = max(1.0, np.abs(cid.T).max()) if r else 1.0
         assert np.max(np.abs(Tg - cid.T), initial=0.0) <= 1e-12 * kappa * scale, q
+
+
+@pytest.mark.parametrize("side", [B.SIDE_U, B.SIDE_V])
+@pytest.mark.parametrize("rows", [65, 80, 81, 96, 97, 112])
+def test_id_batch_four_wave_shapes(side, rows):
+    """65..80, 81..96 and 97..112 sampled rows of up to 64 candidates run as
+    four wavefronts of 20, 24 and 28 rows.  A launch takes the batch's largest
+    block, so the first and last IDs here sit exactly on a bucket edge (80, 96
+    and 112 fill every row of the four wavefronts; 65, 81 and 97 leave all but
+    one row of the last wavefront empty), and the others are ragged below."""
+    N = 4096
+    ph = I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    rng = np.random.default_rng(rows + 1000 * side)
+    # oversampling 2: s = min(2 c, |allowed|)
+    shapes = [(56, 64, rows, rows + 20), (rows // 2, rows // 2 + 4, 400, 600), (33, 40, rows - 1, rows + 5),
+              (9, 9, 300, 400), (64, 64, rows, 2 * rows)]
+    problems = [_id_problem(rng, N, *sh) for sh in shapes]
+    assert max(oracle.sample_count(len(c), len(a), 2) for c, a in problems) == rows
+    _assert_ids_match_oracle(ph, X, O, side, problems, 1e-6, 0, 2)
 
 
 # tall sample blocks (more than 128 sampled rows): the library first reduces
