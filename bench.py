@@ -682,6 +682,12 @@ def main() -> int:
     # every many-RHS apply of the step gets its fastest configuration, and the
     # tuner's cache file records it (a fresh file per run)
     tune_file = os.path.join(tempfile.mkdtemp(prefix="idbf_tune_"), "apply_tune.txt")
+    # the QR-shape tuner first (it sets the process-wide shapes the timed
+    # constructions use), then the apply tuner on factors built with them
+    t0 = time.perf_counter()
+    tuned_qr = B.tune_construct(ph, X, O, W["tol"], W["leaf"], oversample=W["oversample"],
+                                cache_path=tune_file, device=dev, stream=stream)
+    tuned_qr["tuning_s"] = time.perf_counter() - t0
     tfac = step(None)
     t0 = time.perf_counter()
     for name, prec, nrhs in APPLY_KINDS:
@@ -784,6 +790,7 @@ def main() -> int:
                    "N": N, "leaf": W["leaf"], "tol": W["tol"], "oversample": W["oversample"],
                    "nrhs": [1, 256, 1024]},
         "construct_ms": construct_ms, "apply": apply, "apply_tuning_s": tune_s,
+        "qr_shapes": {"mask": tuned_qr["mask"], "id_qr_ms": tuned_qr["ms"], "tuning_s": tuned_qr["tuning_s"]},
         "apply1_ms": apply["c64_nrhs1"]["ms"], "apply1_c128_ms": apply["c128_nrhs1"]["ms"],
         "applyn_ms": apply["c64_nrhs1024"]["ms"], "applyn_gflops": apply["c64_nrhs1024"]["gflops"],
         "applyb_ms": apply["bf16x3_nrhs1024"]["ms"], "applyb_gflops": apply["bf16x3_nrhs1024"]["gflops"],

@@ -322,6 +322,34 @@ idbf_status idbf_set_apply_config(idbf_handle h, const idbf_apply_config* cfg);
 idbf_status idbf_tune_apply(idbf_handle h, int64_t nrhs, int32_t dtype, const char* cache_path, void* stream,
                             idbf_apply_config* chosen);
 
+/* Wave shapes of the batched pivoted QR (Section 2.1, eq. pivotedQR2, on
+ * the sampled block) for IDs of up to 64 candidates with 65..80, 81..96 and
+ * 97..112 sampled rows: bit b of the mask for the b-th range.  A clear bit
+ * (the default) runs four wavefronts of 20, 24 or 28 rows; a set bit runs
+ * five of 16, eight of 12 or eight of 14.  The skeletons do not depend on
+ * the shape; T agrees to the rounding of the sums across wavefronts.  The
+ * setting is process-wide and read at every launch, so it should change only
+ * while no construction runs.  idbf_set_qr_shapes: IDBF_EINVAL for bits
+ * above the three; idbf_get_qr_shapes: IDBF_EINVAL for a NULL mask. */
+idbf_status idbf_set_qr_shapes(uint32_t mask);
+idbf_status idbf_get_qr_shapes(uint32_t* mask);
+
+/* Autotuner of those shapes.  Builds the factorization of (phase, X, Omega,
+ * N, tol, leaf, opts) as idbf_construct does, with IDBF_FLAG_PROFILE added,
+ * and times its ID kernels (the id_qr records; the better of two
+ * constructions after one warm-up) for the current mask and then for each
+ * one-bit change of the best mask so far, keeping a change that is faster.
+ * The chosen mask is then set process-wide (idbf_set_qr_shapes).  With
+ * cache_path, a line "<key>\t<mask> <ms>" (key: GPU architecture, N, phase,
+ * tol, leaf, oversampling, kmax) answers later calls without timing; the
+ * last line for a key wins.  *mask, *ms (the ID kernels of one construction
+ * with the chosen shapes; 0 from the cache if it held no time) and
+ * *from_cache are written when non-NULL.  Errors of idbf_construct are
+ * returned as they are, with the shape mask left as it was. */
+idbf_status idbf_tune_construct(const idbf_phase* phase, const double* X, const double* Omega, int64_t N,
+                                double tol, int32_t leaf, const idbf_opts* opts, const char* cache_path,
+                                uint32_t* mask, float* ms, int32_t* from_cache);
+
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char* idbf_last_error(void);
 

@@ -34,7 +34,8 @@ EXPORTED = [
     "idbf_rank_samples", "idbf_apply_batched_plan", "idbf_plan_launch", "idbf_plan_destroy",
     "idbf_apply_adjoint", "idbf_release_cached_memory", "idbf_stats", "idbf_batch_proposal",
     "idbf_apply_noalloc", "idbf_skeleton_samples", "idbf_batch_skeleton_proposal",
-    "idbf_get_apply_config", "idbf_set_apply_config", "idbf_tune_apply",
+    "idbf_get_apply_config", "idbf_set_apply_config", "idbf_tune_apply", "idbf_set_qr_shapes",
+    "idbf_get_qr_shapes", "idbf_tune_construct",
 ]
 MLP_INPUTS = 8
 FLAG_PROFILE, FLAG_PROPOSER_FORCE_REJECT, FLAG_ALLOW_TRUNCATE = 1, 2, 4
@@ -195,6 +196,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.idbf_get_apply_config.argtypes = [VP, P(ApplyConfig_t)]
     lib.idbf_set_apply_config.argtypes = [VP, P(ApplyConfig_t)]
     lib.idbf_tune_apply.argtypes = [VP, I64, I32, C.c_char_p, VP, P(ApplyConfig_t)]
+    lib.idbf_set_qr_shapes.argtypes = [C.c_uint32]
+    lib.idbf_get_qr_shapes.argtypes = [P(C.c_uint32)]
+    lib.idbf_tune_construct.argtypes = [P(Phase_t), VP, VP, I64, D, I32, P(Opts_t), C.c_char_p, P(C.c_uint32),
+                                        P(C.c_float), P(I32)]
     lib.idbf_apply_batched_plan.argtypes = [I32, P(VP), P(VP), P(VP), P(I64), I32, VP, P(VP)]
     lib.idbf_plan_launch.argtypes = [VP, VP]
     lib.idbf_plan_destroy.argtypes = [VP]
@@ -679,6 +684,40 @@ def sample(phase, X, Omega, rows, cols, device="cuda", stream=None):
     _check(load().idbf_sample(C.byref(ph), _ptr(Xd), _ptr(Od), _ptr(r), r.numel(), _ptr(c),
                               c.numel(), _ptr(out), _stream(stream)))
     return out
+
+
+def set_qr_shapes(mask: int) -> None:
+    """Process-wide wave shapes of the QR kernels for 65..112 sampled rows
+    (idbf_set_qr_shapes; bit b set: short wavefronts for the b-th range)."""
+    _check(load().idbf_set_qr_shapes(int(mask)))
+
+
+def qr_shapes() -> int:
+    """The current QR shape mask (idbf_get_qr_shapes)."""
+    m = C.c_uint32()
+    _check(load().idbf_get_qr_shapes(C.byref(m)))
+    return int(m.value)
+
+
+def tune_construct(phase, X, Omega, tol: float, leaf: int, kmax: int = 0, oversample: int = 1,
+                   cache_path: str | None = None, device="cuda", stream=None) -> dict:
+    """idbf_tune_construct: times the ID kernels of this construction per QR
+    shape mask, sets the fastest process-wide and returns
+    {"mask", "ms", "from_cache"}."""
+    lib = load()
+    Xd, Od = _dev_f64(X, device), _dev_f64(Omega, device)
+    if Xd.numel() != Od.numel():
+        raise ValueError("X and Omega must have the same length")
+    opts = Opts_t()
+    lib.idbf_opts_default(C.byref(opts))
+    opts.kmax, opts.oversample = kmax, oversample
+    opts.stream = _stream(stream)
+    ph = _phase(phase)
+    m, ms, cached = C.c_uint32(), C.c_float(), C.c_int32()
+    _check(lib.idbf_tune_construct(C.byref(ph), _ptr(Xd), _ptr(Od), Xd.numel(), float(tol), int(leaf),
+                                   C.byref(opts), cache_path.encode() if cache_path else None, C.byref(m),
+                                   C.byref(ms), C.byref(cached)))
+    return {"mask": int(m.value), "ms": float(ms.value), "from_cache": bool(cached.value)}
 
 
 def id_batch(phase, X, Omega, side: int, cand_idx, cand_beg, cand_len, allow_idx, allow_beg,

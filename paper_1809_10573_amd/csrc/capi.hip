@@ -1638,6 +1638,25 @@ std::mutex& tune_file_mutex() {
   return m;
 }
 
+// Cache key of the QR-shape tuner: the device's architecture and the
+// problem (phase parameters as exact hexadecimal floats).
+std::string construct_key(const idbf_phase& p, int64_t N, double tol, int leaf, const idbf_opts& o) {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    std::snprintf(prop.gcnArchName, sizeof prop.gcnArchName, "unknown");
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof buf, "%s qr N=%lld phase=%d %a %a %a %a tol=%a leaf=%d t=%d kmax=%d sampler=%d",
+                prop.gcnArchName, (long long)N, p.kind, p.c0, p.a, p.freq, p.cdiv, tol, leaf, o.oversample, o.kmax,
+                o.sampler);
+  std::string key(buf);
+  for (char& ch : key)
+    if (ch == '\t' || ch == '\n') ch = ' ';
+  return key;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1759,6 +1778,116 @@ idbf_status idbf_tune_apply(idbf_handle h, int64_t nrhs, int32_t dtype, const ch
     }
   }
   return finish(best_fuse, best_iter, best, false);
+}
+
+idbf_status idbf_set_qr_shapes(uint32_t mask) {
+  g_err[0] = 0;
+  if (mask & ~kQrShapeBits) {
+    set_error("set_qr_shapes: mask 0x%x has bits above the three QR shape ranges", mask);
+    return IDBF_EINVAL;
+  }
+  set_qr_shape_mask(mask);
+  return IDBF_OK;
+}
+
+idbf_status idbf_get_qr_shapes(uint32_t* mask) {
+  g_err[0] = 0;
+  if (!mask) {
+    set_error("get_qr_shapes: mask is NULL");
+    return IDBF_EINVAL;
+  }
+  *mask = qr_shape_mask();
+  return IDBF_OK;
+}
+
+idbf_status idbf_tune_construct(const idbf_phase* phase, const double* X, const double* Omega, int64_t N,
+                                double tol, int32_t leaf, const idbf_opts* opts, const char* cache_path,
+                                uint32_t* mask, float* ms, int32_t* from_cache) {
+  g_err[0] = 0;
+  TRY(check_phase(phase));
+  if (!X || !Omega || N < 1) {
+    set_error("tune_construct: X and Omega must be device arrays of N >= 1 points");
+    return IDBF_EINVAL;
+  }
+  idbf_opts o;
+  if (opts) o = *opts;
+  else idbf_opts_default(&o);
+  const std::string key = construct_key(*phase, N, tol, leaf, o);
+  auto finish = [&](uint32_t m, float t, bool cached) {
+    set_qr_shape_mask(m);
+    if (mask) *mask = m;
+    if (ms) *ms = t;
+    if (from_cache) *from_cache = cached ? 1 : 0;
+    return IDBF_OK;
+  };
+  if (cache_path) {  // "<key>\t<mask> <ms>" per line; the last line for a key wins
+    std::lock_guard<std::mutex> lock(tune_file_mutex());
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      std::vector<char> line(8192);
+      long long found = -1;
+      float t_found = 0.f;
+      while (std::fgets(line.data(), (int)line.size(), f)) {
+        char* tab = std::strchr(line.data(), '\t');
+        if (!tab || std::string(line.data(), tab) != key) continue;
+        unsigned m = 0;
+        float t = 0.f;
+        const int got = std::sscanf(tab + 1, "%u %f", &m, &t);
+        if (got >= 1 && (m & ~kQrShapeBits) == 0) {
+          found = m;
+          t_found = got == 2 ? t : 0.f;
+        }
+      }
+      std::fclose(f);
+      if (found >= 0) return finish((uint32_t)found, t_found, true);
+    }
+  }
+  o.flags |= IDBF_FLAG_PROFILE;
+  const uint32_t keep = qr_shape_mask();
+  // ID-kernel time of one construction with the shapes m (the better of two)
+  auto time_shapes = [&](uint32_t m, int reps, float* out) -> idbf_status {
+    set_qr_shape_mask(m);
+    float best = -1.f;
+    for (int rep = 0; rep < reps; ++rep) {
+      idbf_handle h = nullptr;
+      idbf_status s = idbf_construct(phase, X, Omega, N, tol, leaf, &o, &h);
+      if (s != IDBF_OK) return s;
+      idbf_kernel_stat st[64];
+      int32_t n = 0;
+      s = idbf_profile_read(h, st, 64, &n, 1);
+      (void)idbf_destroy(h);
+      if (s != IDBF_OK) return s;
+      float t = 0.f;
+      for (int i = 0; i < n; ++i)
+        if (std::strncmp(st[i].name, "id_qr", 5) == 0) t += (float)st[i].ms;
+      if (best < 0.f || t < best) best = t;
+    }
+    *out = best;
+    return IDBF_OK;
+  };
+  float t_best = 0.f, t = 0.f;
+  idbf_status s = time_shapes(keep, 1, &t);  // warm-up
+  if (s == IDBF_OK) s = time_shapes(keep, 2, &t_best);
+  uint32_t best = keep;
+  for (uint32_t b = 0; b < 3 && s == IDBF_OK; ++b) {
+    const uint32_t m = best ^ (1u << b);
+    s = time_shapes(m, 2, &t);
+    if (s == IDBF_OK && t < t_best) {
+      best = m;
+      t_best = t;
+    }
+  }
+  if (s != IDBF_OK) {
+    set_qr_shape_mask(keep);
+    return s;
+  }
+  if (cache_path) {
+    std::lock_guard<std::mutex> lock(tune_file_mutex());
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "%s\t%u %.4f\n", key.c_str(), best, t_best);
+      std::fclose(f);
+    }
+  }
+  return finish(best, t_best, false);
 }
 
 }  // extern "C"

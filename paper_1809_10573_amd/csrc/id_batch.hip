@@ -22,6 +22,7 @@
 // id_kernel_g -- the same, with two (up to 32 candidates) or four (up to 16)
 //   IDs per workgroup, each on its own group of lanes.
 #include <algorithm>
+#include <atomic>
 #include <climits>
 
 #include "kernels.hpp"
@@ -1204,6 +1205,13 @@ __global__ __launch_bounds__(kTallThreads) void tall_reduce_kernel(IdArgs A, int
 
 hipError_t launch_qr_bucket(const IdArgs& a, int64_t n, int bucket, hipStream_t st);
 
+namespace {
+std::atomic<uint32_t> g_qr_shapes{0};  // bit b: bucket 4 + b runs on its short wavefronts
+}
+
+uint32_t qr_shape_mask() { return g_qr_shapes.load(std::memory_order_relaxed); }
+void set_qr_shape_mask(uint32_t mask) { g_qr_shapes.store(mask & kQrShapeBits, std::memory_order_relaxed); }
+
 hipError_t launch_select(const IdArgs& a, hipStream_t st) {
   const int64_t n = a.sel_list ? a.sel_n : a.n_ids;
   if (n <= 0) return hipSuccess;
@@ -1258,16 +1266,18 @@ hipError_t launch_packed(const IdArgs& a, int64_t n, hipStream_t st) {
 }
 
 hipError_t launch_qr_bucket(const IdArgs& a, int64_t n, int bucket, hipStream_t st) {
+  const uint32_t shapes = qr_shape_mask();
   switch (bucket) {
     // up to 64 candidates: 16 rows per wavefront up to 64 samples, then four
-    // wavefronts of 20, 24 or 28 rows up to 112
+    // wavefronts of 20, 24 or 28 rows up to 112 (or, with the bucket's bit of
+    // the shape mask set, five or eight short ones)
     case 0: return launch_one<1, 1, 16>(a, n, st);
     case 1: return launch_one<2, 1, 16>(a, n, st);
     case 2: return launch_one<3, 1, 16>(a, n, st);
     case 3: return launch_one<4, 1, 16>(a, n, st);
-    case 4: return launch_one<4, 1, 20>(a, n, st);
-    case 5: return launch_one<4, 1, 24>(a, n, st);
-    case 6: return launch_one<4, 1, 28>(a, n, st);
+    case 4: return (shapes & 1u) ? launch_one<5, 1, 16>(a, n, st) : launch_one<4, 1, 20>(a, n, st);
+    case 5: return (shapes & 2u) ? launch_one<8, 1, 12>(a, n, st) : launch_one<4, 1, 24>(a, n, st);
+    case 6: return (shapes & 4u) ? launch_one<8, 1, 14>(a, n, st) : launch_one<4, 1, 28>(a, n, st);
     case 7: return launch_one<8, 1, 16>(a, n, st);
     // 65..128 candidates: two per lane, 8 rows per wavefront
     case 8: return launch_one<1, 2, 8>(a, n, st);

@@ -102,6 +102,13 @@ struct IdArgs {
 hipError_t launch_select(const IdArgs& a, hipStream_t st);
 hipError_t launch_qr(const IdArgs& a, hipStream_t st);
 hipError_t launch_id_batch(const IdArgs& a, hipStream_t st);
+// Wave shapes of QR buckets 4..6 (65..80, 81..96, 97..112 sampled rows, up to
+// 64 candidates): bit b set runs bucket 4 + b on short wavefronts (five of 16
+// rows, eight of 12, eight of 14) instead of four tall ones (20, 24, 28 rows).
+// Process-wide; read at each launch.
+constexpr uint32_t kQrShapeBits = 7u;
+uint32_t qr_shape_mask();
+void set_qr_shape_mask(uint32_t mask);
 // IDs grouped by qr_bucket: counts[0..kQrBuckets) += bucket sizes and
 // counts[kQrBuckets] += tall IDs (pass 1), then order[] (and tall[] for the
 // tall IDs) filled from per-slot cursors (pass 2, cursors pre-set to the

@@ -60,6 +60,20 @@ def test_argument_errors_without_gpu():
     assert lib.idbf_construct(C.byref(ph), fake, fake, 1024, 1e-6, 8, C.byref(o), C.byref(h)) == B.EINVAL
     assert lib.idbf_apply(None, fake, fake, 1, B.C128, None) == B.EINVAL
     assert lib.idbf_profile_enable(None, 1) == B.EINVAL
+    # the QR shape mask is host state: set, read back, reject bits above the three
+    m = C.c_uint32()
+    assert lib.idbf_get_qr_shapes(C.byref(m)) == B.OK
+    keep = m.value
+    assert lib.idbf_set_qr_shapes(5) == B.OK
+    assert lib.idbf_get_qr_shapes(C.byref(m)) == B.OK and m.value == 5
+    assert lib.idbf_set_qr_shapes(8) == B.EINVAL
+    assert lib.idbf_get_qr_shapes(C.byref(m)) == B.OK and m.value == 5
+    assert lib.idbf_get_qr_shapes(None) == B.EINVAL
+    assert lib.idbf_set_qr_shapes(keep) == B.OK
+    assert lib.idbf_tune_construct(C.byref(bad), fake, fake, 1024, 1e-6, 8, None, None, None, None,
+                                   None) == B.EINVAL
+    assert lib.idbf_tune_construct(C.byref(ph), None, fake, 1024, 1e-6, 8, None, None, None, None,
+                                   None) == B.EINVAL
     assert lib.idbf_apply_adjoint(None, fake, fake, 1, B.C128, None) == B.EINVAL
     assert b"handle is NULL" in lib.idbf_last_error()
     assert lib.idbf_get_info(None, None) == B.EINVAL

@@ -39,3 +39,47 @@ def test_tune_apply_and_cache(tmp_path):
     fac.set_apply_config(fuse=got["fuse"], rhs_iter=got["rhs_iter"])
     y = fac.apply(torch.as_tensor(G, device=DEV).to(torch.complex64)).cpu().numpy()
     assert oracle.relative_error(y, oracle.apply(F, G)) < 2e-6
+
+
+def test_tune_construct_shapes_and_cache(tmp_path):
+    """The QR-shape tuner (idbf_tune_construct) sets the mask it timed fastest
+    and records it; a later call takes it from the cache file.  Both shape
+    families give the same factors: identical ranks, masks and skeletons,
+    and complex128 applies that agree to rounding."""
+    N, leaf, tol = 1 << 14, 16, 1e-6
+    ph = I.fio_phase(1.0, 1.0)
+    X, O = I.uniform_grid(N)
+    keep = B.qr_shapes()
+    try:
+        cache = str(tmp_path / "idbf_qr_tune.txt")
+        got = B.tune_construct(ph, X, O, tol, leaf, oversample=2, cache_path=cache, device=DEV)
+        assert 0 <= got["mask"] <= 7 and not got["from_cache"] and got["ms"] > 0
+        assert B.qr_shapes() == got["mask"]
+        lines = open(cache).read().splitlines()
+        assert len(lines) == 1 and " qr N=16384 " in lines[0].split("\t")[0]
+        B.set_qr_shapes(7 - got["mask"])
+        hit = B.tune_construct(ph, X, O, tol, leaf, oversample=2, cache_path=cache, device=DEV)
+        assert hit["from_cache"] and hit["mask"] == got["mask"] and B.qr_shapes() == got["mask"]
+        with pytest.raises(B.IdbfError):
+            B.set_qr_shapes(8)
+        facs = []
+        for mask in (0, 7):  # every range on the tall, then on the short wavefronts
+            B.set_qr_shapes(mask)
+            facs.append(B.construct(ph, X, O, tol, leaf, oversample=2, device=DEV))
+        a, b = facs
+        s = 0
+        for side in (B.SIDE_U, B.SIDE_V):
+            for t in range(1, a.info()["H"] + 1):
+                x, y = a.batch(side, t), b.batch(side, t)
+                for f in ("rank", "cand_len", "mask", "skel"):
+                    assert np.array_equal(getattr(x, f), getattr(y, f)), (side, t, f)
+                s = max(s, int(oracle.sample_count(int(x.cand_len.max()), N, 2)))
+        assert s > 64  # some IDs ran on the shapes the mask chooses
+        Sa, _ = a.middle()
+        Sb, _ = b.middle()
+        assert np.array_equal(Sa, Sb)
+        v = torch.as_tensor(I.gaussian_vectors(N, 1, 3)[:, 0], device=DEV)
+        ya, yb = a.apply(v).cpu().numpy(), b.apply(v).cpu().numpy()
+        assert np.linalg.norm(ya - yb) <= 1e-12 * np.linalg.norm(ya)
+    finally:
+        B.set_qr_shapes(keep)
