@@ -326,9 +326,11 @@ idbf_status idbf_tune_apply(idbf_handle h, int64_t nrhs, int32_t dtype, const ch
  * the sampled block) for IDs of up to 64 candidates with 65..80, 81..96 and
  * 97..112 sampled rows: bit b of the mask for the b-th range.  A clear bit
  * (the default) runs four wavefronts of 20, 24 or 28 rows; a set bit runs
- * five of 16, eight of 12 or eight of 14.  The skeletons do not depend on
- * the shape; T agrees to the rounding of the sums across wavefronts.  The
- * setting is process-wide and read at every launch, so it should change only
+ * five of 16, eight of 12 or eight of 14.  Both take the same steps; only
+ * the sums across wavefronts round differently, so T agrees to rounding and
+ * a pivot could differ only where two residual norms sit at the edge of the
+ * tie band (the tests find identical skeletons).  The setting is
+ * process-wide and read at every launch, so it should change only
  * while no construction runs.  idbf_set_qr_shapes: IDBF_EINVAL for bits
  * above the three; idbf_get_qr_shapes: IDBF_EINVAL for a NULL mask. */
 idbf_status idbf_set_qr_shapes(uint32_t mask);
