@@ -33,9 +33,12 @@ Readings of the paper where it is silent, ambiguous or garbled are listed in
 the module docstrings where they apply.
 
 Parity status: every function is pinned by ``tests/test_oracle_*.py`` against
-closed forms, LAPACK, SVD bounds, brute force or exactness identities, except
-the Mock-Chebyshev rule itself (``sampling.mock_chebyshev``), whose parity is
-unpinned beyond hand-worked cases and the end-to-end error it produces.
+closed forms, LAPACK, SVD bounds, brute force or exactness identities.  The
+Mock-Chebyshev rule (``sampling.mock_chebyshev``), which the paper cites
+without stating, is pinned by the published definition's closed form on
+equispaced grids (rounded Chebyshev-Lobatto points, from 60-digit cosines),
+the stability of interpolation on its subsets, exact affine invariance and
+hand-worked collision cases.
 """
 from .kernel import (PHASE_DFT, PHASE_FIO, PHASE_J0, amplitude_shift, phase_mod1, entries,
                      matvec_rows, dense_matvec, dft_closed_form, fio_const_closed_form,

@@ -18,9 +18,13 @@ closest to Chebyshev-Lobatto points):
   (smaller position on a tie).
 * The chosen positions are returned in ascending order.
 
-Parity unpinned: beyond hand-worked cases there is nothing in the paper to
-check this rule against; only the end-to-end error of the factorization
-pins it.
+Pins (the paper states no rule to check against): on an equispaced grid,
+wherever the Chebyshev-Lobatto points' nearest grid points are distinct,
+the picks are exactly those points (the published mock-Chebyshev subset,
+computed in the test from 60-digit cosines); interpolation on the subsets
+has a Lebesgue constant near Chebyshev-Lobatto's, far below an equispaced
+subset's; picks are invariant under exact affine maps; hand-worked cases
+fix the collision and tie rules.
 
 ``random_positions`` is the uniformly random alternative the paper compares
 Mock-Chebyshev against (Section 3): s distinct positions of n by Floyd's

@@ -1,4 +1,7 @@
-"""Hand-worked cases of the Mock-Chebyshev rule (the rule itself is parity unpinned)."""
+"""The Mock-Chebyshev rule: hand-worked cases (collisions, ties), the
+closed form of the published mock-Chebyshev subset on equispaced grids,
+exact affine invariance and the stability of interpolation on its subsets;
+and the uniformly random alternative."""
 import numpy as np
 
 import oracle
@@ -63,3 +66,74 @@ def test_random_positions_are_uniform_subsets():
     cnt = Counter(tuple(random_positions(3, 1, 0, q, 5, 2)) for q in range(20000))
     assert len(cnt) == 10
     assert all(abs(v - 2000) < 200 for v in cnt.values()), cnt
+
+
+def _lebesgue_constant(nodes, fine):
+    """max over `fine` of sum_j |l_j(x)| for polynomial interpolation at
+    `nodes` (barycentric weights; nodes distinct)."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    w = np.array([1.0 / np.prod(nodes[j] - np.delete(nodes, j)) for j in range(len(nodes))])
+    lam = 0.0
+    for x in fine:
+        d = x - nodes
+        if np.any(d == 0.0):
+            lam = max(lam, 1.0)
+            continue
+        t = w / d
+        lam = max(lam, np.sum(np.abs(t)) / abs(np.sum(t)))
+    return lam
+
+
+def test_equispaced_grids_give_the_rounded_chebyshev_lobatto_points():
+    """Mock-Chebyshev subsets of an equispaced grid (Boyd and Xu's
+    definition: the grid point nearest each Chebyshev-Lobatto point): where
+    those nearest points are all distinct, the rule must return exactly them.
+    The targets come from 60-digit cosines, the nearest index by rounding
+    with ties to the lower index; no greedy pass is involved."""
+    mp = __import__("pytest").importorskip("mpmath")
+    mp.mp.dps = 60
+    checked = 0
+    for n, s in [(2001, 5), (2001, 17), (2001, 33), (513, 9), (100, 7), (4097, 65), (31, 4), (1001, 21)]:
+        idx = []
+        for j in range(s):
+            z = (n - 1) * (1 - mp.cos(mp.pi * j / (s - 1))) / 2
+            lo = int(mp.floor(z))
+            idx.append(lo if z - lo <= mp.mpf(1) / 2 else lo + 1)  # a tie goes to the lower index
+        if len(set(idx)) < s:
+            continue  # two targets share a nearest point: the greedy rule decides, not this pin
+        for a, h in [(0.0, 1.0), (-3.5, 0.25), (1e3, 2.0 ** -10)]:
+            coords = a + h * np.arange(n, dtype=np.float64)
+            assert list(oracle.mock_chebyshev(coords, s)) == idx, (n, s, a, h)
+        checked += 1
+    assert checked >= 6
+
+
+def test_selection_is_invariant_under_exact_affine_maps():
+    """The rule uses only the ordering of distances to targets placed
+    proportionally over [min, max], so scaling by a power of two and
+    shifting by an integer (both exact on integer-valued coordinates)
+    leave the picks unchanged."""
+    rng = np.random.default_rng(3)
+    for _ in range(40):
+        n = int(rng.integers(3, 300))
+        coords = np.sort(rng.choice(10 ** 6, n, replace=False)).astype(np.float64)
+        s = int(rng.integers(1, n + 1))
+        base = oracle.mock_chebyshev(coords, s)
+        for scale, shift in [(4.0, 1000.0), (0.5, -7.0), (2.0 ** 20, 3.0)]:
+            assert np.array_equal(oracle.mock_chebyshev(scale * coords + shift, s), base)
+
+
+def test_subsets_interpolate_stably():
+    """The reason for mock-Chebyshev subsets: polynomial interpolation on
+    them is as stable as on Chebyshev-Lobatto points (Lebesgue constant
+    2/pi log(s) + 1 up to a small factor), where an equispaced subset of
+    the same size grows like 2^s / (e s log s)."""
+    n = 4001
+    grid = np.linspace(-1.0, 1.0, n)
+    fine = np.linspace(-1.0, 1.0, 20001)
+    for s in (11, 21, 31):
+        mock = grid[oracle.mock_chebyshev(grid, s)]
+        lam = _lebesgue_constant(mock, fine)
+        assert lam < 2.0 * (2.0 / np.pi * np.log(s) + 1.0), (s, lam)
+        equi = grid[np.round(np.linspace(0, n - 1, s)).astype(int)]
+        assert _lebesgue_constant(equi, fine) > 0.5 * 2.0 ** s / (np.e * s * np.log(s)), s
